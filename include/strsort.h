@@ -1,0 +1,233 @@
+/*
+ * strsort -- one GPU's share of the data-parallel hot path of distributed
+ * string sorting, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Scalable Distributed String Sorting" (Kurpicz, Mehnert, Sanders,
+ * Schimek).  The entry points below are the local steps each processing
+ * element runs: sort + LCP array (Section 3, "Initialization"), exact and
+ * approximate distinguishing prefixes (Section 2; Section 4 with Appendix B
+ * and C), bucket computation and LCP compression (Section 3, steps 1-2;
+ * Section 2, "Algorithmic Building Blocks"), and LCP-aware merging of sorted
+ * runs (Section 3, step 3).  The message exchange between processing elements
+ * is replaced by runs already resident in device memory.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - A string array is (bytes, N, offsets, n): string i occupies
+ *   bytes[offsets[i] .. offsets[i+1]), offsets has n+1 non-decreasing entries
+ *   and offsets[n] <= N.  Strings are unsigned byte sequences with explicit
+ *   lengths; a proper prefix sorts before its extensions (the end-of-string
+ *   sentinel of Section 2 sorts below every byte, 0x00 included).
+ * - Order arrays (perm, lcp, front-coded arrays) are indexed by sorted
+ *   position; per-string properties (dist) are indexed by input index.
+ * - Equal strings are ordered by input index (the sort is stable).
+ * - lcp[0] = 0 and lcp[i] = number of equal leading bytes of the strings at
+ *   sorted positions i-1 and i.
+ * - Every pointer is DEVICE memory owned by the caller unless its comment says
+ *   "host".  The library allocates no device memory: scratch comes from the
+ *   caller's workspace `ws` of `ws_bytes` bytes, sized by the matching
+ *   *_workspace() query.  `stream` is a hipStream_t (NULL = default stream).
+ * - Calls are enqueued on `stream`.  Calls that iterate (sort rounds, doubling
+ *   rounds, merge levels) read small counters back to the host and therefore
+ *   synchronise `stream` between iterations; outputs are complete when the call
+ *   returns.  Concurrent calls on different streams with different workspaces
+ *   are independent.
+ * - Return value: SS_OK or a negative SS_ERR_* code; ss_last_error() gives a
+ *   thread-local message.  No call aborts or throws across this boundary.
+ * - Limits: n < 2^32 - 1; every string shorter than 2^32 - 1 bytes.
+ */
+#ifndef STRSORT_H
+#define STRSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SS_OK 0
+#define SS_ERR_INVALID_ARG (-1)  /* null pointer, bad size, bad parameter      */
+#define SS_ERR_WORKSPACE (-2)    /* ws_bytes smaller than the *_workspace query */
+#define SS_ERR_TOO_LARGE (-3)    /* n or a length beyond the 32-bit limits     */
+#define SS_ERR_HIP (-4)          /* a HIP runtime call failed (text in last_error) */
+#define SS_ERR_CAPACITY (-5)     /* an output buffer is smaller than needed    */
+
+/* Thread-local text of the last error (empty if none).  Host string. */
+const char *ss_last_error(void);
+
+/* Library version (major*100 + minor). */
+int ss_version(void);
+
+/* ------------------------------------------------------------------ sort */
+
+/* Workspace bytes for ss_sort / ss_sort_batch on n strings. */
+size_t ss_sort_workspace(uint64_t n);
+
+/* Sort + LCP array (Section 3, "Initialization": sort the local string array;
+ * the LCP array is obtained as a by-product).
+ *   perm[i] (out, n)  input index of the i-th smallest string (stable).
+ *   lcp[i]  (out, n)  LCP array of the sorted order; may be NULL.
+ * Errors: INVALID_ARG (null bytes/offsets/perm with n > 0), TOO_LARGE,
+ * WORKSPACE, HIP. */
+int ss_sort(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+            uint32_t *perm, uint32_t *lcp, void *ws, size_t ws_bytes, void *stream);
+
+/* Many independent sorts in one launch sequence (one sort per set, as each
+ * processing element sorts its own array in Section 3).  set_off (device,
+ * num_sets+1 entries, non-decreasing, set_off[0] = 0, set_off[num_sets] = n)
+ * gives the string-index bounds of each set within one string array.
+ *   perm_local[i] (out, n)  index WITHIN its set of the string at position i
+ *                           of that set's sorted order (positions are global).
+ *   lcp[i] (out, n)         LCP array of each set (0 at each set start); may be NULL.
+ * Uses the ss_sort workspace for n. */
+int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                  const uint64_t *set_off, uint32_t num_sets, uint32_t *perm_local,
+                  uint32_t *lcp, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------- LCP and dist */
+
+/* LCP array of a given order (Section 2): lcp[0] = 0,
+ * lcp[i] = lcp(s_perm[i-1], s_perm[i]).  perm (in, n), lcp (out, n). */
+int ss_lcp(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+           const uint32_t *perm, uint32_t *lcp, void *stream);
+
+/* Exact distinguishing prefix length (Section 2): the characters needed to
+ * rank a string, dist(s) = min(len(s), 1 + max over t != s of lcp(s, t)),
+ * evaluated from the sorted neighbours: for the string at sorted position i,
+ * dist = min(len, 1 + max(lcp[i], lcp[i+1])) with lcp[n] := 0.
+ *   perm, lcp (in, n; a sorted order and its LCP array), dist (out, n, by
+ *   input index). */
+int ss_dist_exact(const uint64_t *offsets, uint64_t n, const uint32_t *perm,
+                  const uint32_t *lcp, uint32_t *dist, void *stream);
+
+/* ----------------------------------------------------- prefix doubling */
+
+/* Workspace bytes for ss_dist_prefix on n strings. */
+size_t ss_dist_prefix_workspace(uint64_t n);
+
+/* Approximate distinguishing prefixes by prefix doubling (Section 4; proof
+ * outline in Appendix C) with exact duplicate detection by sorting (hash,
+ * index) pairs and scanning neighbours (Appendix B).  Round t hashes the
+ * l_t-prefix of every active string, l_t = init_len * 2^t; a string finishes
+ * when its key is unique among the active strings or its length is <= l_t,
+ * with dist_approx = min(l_t, len).  Result: dist_approx >= dist for every
+ * string, whatever the hash.
+ *   init_len   positive multiple of 4 (the paper's l_init; 8 in the workloads).
+ *   hash_bits  keep the low hash_bits bits of each key (8..64; 64 = full key).
+ *              Smaller values force collisions for testing.
+ *   dist_approx (out, n, by input index).
+ *   rounds_host (host, out, nullable): number of doubling rounds run.
+ * Hash: Karp-Rabin modulo 2^61-1 with base 0x0B3C4D5E6F708192 over 4-byte
+ * little-endian limbs of the prefix (last limb zero-padded), followed by the
+ * prefix length as a final digit: key = (C*B + m) mod p.  The paper leaves
+ * the hash open; this one is incremental, so round t reads only bytes
+ * [l_{t-1}, l_t). */
+int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                   uint32_t init_len, uint32_t hash_bits, uint32_t *dist_approx,
+                   uint32_t *rounds_host, void *ws, size_t ws_bytes, void *stream);
+
+/* The prefix-doubling key of each string's first min(m, len) bytes, masked to
+ * hash_bits (same hash as ss_dist_prefix; exposed so that the hash can be
+ * checked on its own).  keys (out, n). */
+int ss_prefix_keys(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                   uint32_t m, uint32_t hash_bits, uint64_t *keys, void *stream);
+
+/* ------------------------------------------- splitters, buckets, coding */
+
+/* One-device form of regular sampling (Section 3.1: f_j = V[j|V|/r - 1]) with
+ * V = the whole sorted array: splitter_ids[j-1] = perm[ceil(j*n/r) - 1] for
+ * j = 1..r-1.  perm (in, n), splitter_ids (out, r-1).  n >= 1, r >= 1. */
+int ss_select_splitters(uint64_t n, const uint32_t *perm, uint32_t r, uint32_t *splitter_ids,
+                        void *stream);
+
+/* Workspace bytes for ss_gather_strings of m strings. */
+size_t ss_gather_workspace(uint64_t m);
+
+/* Copy strings ids[0..m) of a string array into a new string array
+ * (out_offsets: m+1 entries, out_offsets[0] = 0; out_bytes capacity out_cap).
+ * Used to materialise splitter strings.  CAPACITY if out_cap is too small. */
+int ss_gather_strings(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                      const uint32_t *ids, uint64_t m, uint64_t *out_offsets, uint8_t *out_bytes,
+                      uint64_t out_cap, void *ws, size_t ws_bytes, void *stream);
+
+/* Bucket boundaries for r-1 sorted splitters (Section 3, step 1:
+ * B^j = { s : f_j < s <= f_{j+1} }, f_0 = -inf, f_r = +inf):
+ * bounds[0] = 0, bounds[r] = n, bounds[j] = #{ i : s_perm[i] <= f_j }.
+ * Splitters are a string array (spl_bytes, spl_N, spl_offsets, r-1 strings),
+ * non-decreasing.  bounds (out, r+1). */
+int ss_bucket_bounds(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                     const uint32_t *perm, const uint8_t *spl_bytes, uint64_t spl_N,
+                     const uint64_t *spl_offsets, uint32_t r, uint64_t *bounds, void *stream);
+
+/* Workspace bytes for ss_partition_encode on n strings. */
+size_t ss_partition_encode_workspace(uint64_t n);
+
+/* Split a sorted array into r buckets and LCP-compress each bucket (Section 3
+ * steps 1-2 with LCP compression, Section 2; distinguishing prefixes only in
+ * the prefix-doubling variant, Section 4).  Front-coded run format, per
+ * sorted position i in bucket j = [run_off[j], run_off[j+1]):
+ *   fc_lcp[i] = e_i = 0 at the bucket start, else lcp[i];
+ *   fc_len[i] = d_i = dist[perm[i]] if dist != NULL, else the full length;
+ *   fc_id[i]  = perm[i];
+ *   suf[suf_off[i] .. suf_off[i+1]) = bytes s_perm[i][e_i, d_i)
+ * (suf_off has n+1 entries, suf_off[n] = total literal bytes).
+ * Inputs: perm, lcp (a sorted order and its LCP array), dist (by input index,
+ * must satisfy dist >= min(len, lcp+1) as ss_dist_prefix guarantees; NULL =
+ * full strings), splitters as in ss_bucket_bounds.  suf_cap: capacity of suf
+ * (N always suffices).  suf_total_host (host, out, nullable).
+ * Errors: CAPACITY if suf_cap is too small, INVALID_ARG if some e_i > d_i. */
+int ss_partition_encode(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                        const uint32_t *perm, const uint32_t *lcp, const uint32_t *dist,
+                        const uint8_t *spl_bytes, uint64_t spl_N, const uint64_t *spl_offsets,
+                        uint32_t r, uint64_t *run_off, uint32_t *fc_lcp, uint32_t *fc_len,
+                        uint32_t *fc_id, uint64_t *suf_off, uint8_t *suf, uint64_t suf_cap,
+                        uint64_t *suf_total_host, void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes for ss_fc_decode on n strings. */
+size_t ss_fc_decode_workspace(uint64_t n);
+
+/* Decode k front-coded runs (format of ss_partition_encode; run_off has k+1
+ * entries, device) into a string array: string i of run j is the first e_i
+ * bytes of string i-1 of the same run followed by its literal bytes.
+ * out_offsets (out, n+1, out_offsets[0] = 0), out_bytes (out, capacity
+ * out_cap >= sum d_i, else CAPACITY). */
+int ss_fc_decode(uint32_t k, const uint64_t *run_off, const uint32_t *fc_lcp,
+                 const uint32_t *fc_len, const uint64_t *suf_off, const uint8_t *suf, uint64_t n,
+                 uint64_t *out_offsets, uint8_t *out_bytes, uint64_t out_cap, void *ws,
+                 size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------- merge */
+
+/* Workspace bytes for ss_lcp_merge of n strings whose decoded lengths sum to
+ * total_len bytes. */
+size_t ss_lcp_merge_workspace(uint64_t n, uint64_t total_len);
+
+/* LCP-aware k-way merge of k sorted front-coded runs (Section 3, step 3; the
+ * paper uses an LCP loser tree, Section 2).  Input as in ss_fc_decode plus
+ * fc_id.  Output, by merged position i:
+ *   out_src[i] = (run << 32) | position within the run,
+ *   out_id[i]  = fc_id of that element,
+ *   out_lcp[i] = LCP with the previous merged string (0 for i = 0).
+ * Equal strings keep (run, position) order. */
+int ss_lcp_merge(uint32_t k, const uint64_t *run_off, const uint32_t *fc_lcp,
+                 const uint32_t *fc_len, const uint32_t *fc_id, const uint64_t *suf_off,
+                 const uint8_t *suf, uint64_t n, uint64_t *out_src, uint32_t *out_id,
+                 uint32_t *out_lcp, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------- tuning */
+
+/* Tunable launch parameters (chosen by the autotuner; defaults are safe).
+ *   SS_TUNE_SMALL_MAX  segments up to this many strings are sorted in LDS
+ *                      (128, 256, 512 or 1024; default 1024).
+ *   SS_TUNE_TILE       elements per workgroup in radix passes (1024..16384,
+ *                      power of two; default 4096).
+ * Returns the previous value, or SS_ERR_INVALID_ARG. */
+#define SS_TUNE_SMALL_MAX 1
+#define SS_TUNE_TILE 2
+int ss_set_tuning(int param, int value);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STRSORT_H */

@@ -1,0 +1,261 @@
+"""Python binding of libstrsort (the C-ABI in include/strsort.h).
+
+Argument marshalling only: every step runs in the HIP kernels of the shared
+library.  PyTorch supplies device memory (tensors on a ROCm device) and the
+current stream.  32-bit unsigned outputs are returned in ``torch.int32``
+tensors holding the same bits; 64-bit unsigned ones in ``torch.int64``.
+Strings are a ``uint8`` byte tensor plus an ``int64`` offsets tensor of n+1
+entries (string i = bytes[offsets[i]:offsets[i+1]]).
+
+There is no CPU fallback: without the built library or a GPU every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstrsort.so")
+
+SS_TUNE_SMALL_MAX = 1
+SS_TUNE_TILE = 2
+
+
+class StrsortError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """The loaded shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise StrsortError(f"{LIB_PATH} is missing: build it with `python -m paper_2404_16517_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, U32, U64, I32, SZ = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t
+        sig = {
+            "ss_last_error": ([], ctypes.c_char_p),
+            "ss_version": ([], I32),
+            "ss_sort_workspace": ([U64], SZ),
+            "ss_sort": ([P, U64, P, U64, P, P, P, SZ, P], I32),
+            "ss_sort_batch": ([P, U64, P, U64, P, U32, P, P, P, SZ, P], I32),
+            "ss_lcp": ([P, U64, P, U64, P, P, P], I32),
+            "ss_dist_exact": ([P, U64, P, P, P, P], I32),
+            "ss_dist_prefix_workspace": ([U64], SZ),
+            "ss_dist_prefix": ([P, U64, P, U64, U32, U32, P, P, P, SZ, P], I32),
+            "ss_prefix_keys": ([P, U64, P, U64, U32, U32, P, P], I32),
+            "ss_select_splitters": ([U64, P, U32, P, P], I32),
+            "ss_gather_workspace": ([U64], SZ),
+            "ss_gather_strings": ([P, U64, P, U64, P, U64, P, P, U64, P, SZ, P], I32),
+            "ss_bucket_bounds": ([P, U64, P, U64, P, P, U64, P, U32, P, P], I32),
+            "ss_partition_encode_workspace": ([U64], SZ),
+            "ss_partition_encode": ([P, U64, P, U64, P, P, P, P, U64, P, U32, P, P, P, P, P, P, U64, P, P, SZ, P],
+                                    I32),
+            "ss_fc_decode_workspace": ([U64], SZ),
+            "ss_fc_decode": ([U32, P, P, P, P, P, U64, P, P, U64, P, SZ, P], I32),
+            "ss_lcp_merge_workspace": ([U64, U64], SZ),
+            "ss_lcp_merge": ([U32, P, P, P, P, P, P, U64, P, P, P, P, SZ, P], I32),
+            "ss_set_tuning": ([I32, I32], I32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _p(t: torch.Tensor | None):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() else None
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = lib().ss_last_error().decode(errors="replace")
+        raise StrsortError(f"strsort error {rc}: {msg}")
+
+
+def _dev_strings(bytes_: torch.Tensor, offsets: torch.Tensor):
+    if not bytes_.is_cuda or not offsets.is_cuda:
+        raise StrsortError("strings must be on a GPU device")
+    if bytes_.dtype != torch.uint8 or offsets.dtype != torch.int64:
+        raise StrsortError("bytes must be uint8 and offsets int64")
+    if not bytes_.is_contiguous() or not offsets.is_contiguous():
+        raise StrsortError("bytes and offsets must be contiguous")
+    return bytes_, offsets, offsets.numel() - 1
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _u32(n: int, device) -> torch.Tensor:
+    return torch.empty(max(n, 0), dtype=torch.int32, device=device)
+
+
+def set_tuning(param: int, value: int) -> int:
+    old = lib().ss_set_tuning(param, value)
+    if old < 0:
+        _check(old)
+    return old
+
+
+# ---------------------------------------------------------------- sorting
+
+def sort(bytes_, offsets, with_lcp: bool = True, ws: torch.Tensor | None = None):
+    """Stable sort + LCP array.  Returns (perm int32[n], lcp int32[n] or None)."""
+    b, o, n = _dev_strings(bytes_, offsets)
+    dev = b.device
+    perm = _u32(n, dev)
+    lcp = _u32(n, dev) if with_lcp else None
+    need = lib().ss_sort_workspace(n)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, dev)
+    _check(lib().ss_sort(_p(b), b.numel(), _p(o), n, _p(perm), _p(lcp), _p(ws), ws.numel(), _stream(dev)))
+    return perm, lcp
+
+
+def sort_batch(bytes_, offsets, set_off: torch.Tensor, with_lcp: bool = True, ws=None):
+    """Independent sorts of the sets [set_off[j], set_off[j+1]) in one launch sequence.
+    Returns (perm_local int32[n], lcp int32[n] or None)."""
+    b, o, n = _dev_strings(bytes_, offsets)
+    dev = b.device
+    so = set_off.to(device=dev, dtype=torch.int64).contiguous()
+    perm = _u32(n, dev)
+    lcp = _u32(n, dev) if with_lcp else None
+    need = lib().ss_sort_workspace(n)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, dev)
+    _check(lib().ss_sort_batch(_p(b), b.numel(), _p(o), n, _p(so), so.numel() - 1, _p(perm), _p(lcp), _p(ws),
+                               ws.numel(), _stream(dev)))
+    return perm, lcp
+
+
+def lcp(bytes_, offsets, perm):
+    b, o, n = _dev_strings(bytes_, offsets)
+    out = _u32(n, b.device)
+    _check(lib().ss_lcp(_p(b), b.numel(), _p(o), n, _p(perm.contiguous()), _p(out), _stream(b.device)))
+    return out
+
+
+def dist_exact(offsets, perm, lcp_):
+    n = offsets.numel() - 1
+    out = _u32(n, offsets.device)
+    _check(lib().ss_dist_exact(_p(offsets), n, _p(perm.contiguous()), _p(lcp_.contiguous()), _p(out),
+                               _stream(offsets.device)))
+    return out
+
+
+def dist_prefix(bytes_, offsets, init_len: int = 8, hash_bits: int = 64, ws=None):
+    """Prefix doubling.  Returns (dist_approx int32[n] by input index, rounds)."""
+    b, o, n = _dev_strings(bytes_, offsets)
+    dev = b.device
+    out = _u32(n, dev)
+    need = lib().ss_dist_prefix_workspace(n)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, dev)
+    rounds = ctypes.c_uint32(0)
+    _check(lib().ss_dist_prefix(_p(b), b.numel(), _p(o), n, init_len, hash_bits, _p(out), ctypes.byref(rounds),
+                                _p(ws), ws.numel(), _stream(dev)))
+    return out, int(rounds.value)
+
+
+def prefix_keys(bytes_, offsets, m: int, hash_bits: int = 64):
+    b, o, n = _dev_strings(bytes_, offsets)
+    out = torch.empty(max(n, 0), dtype=torch.int64, device=b.device)
+    _check(lib().ss_prefix_keys(_p(b), b.numel(), _p(o), n, m, hash_bits, _p(out), _stream(b.device)))
+    return out
+
+
+# ------------------------------------------------- splitters and coding
+
+def select_splitters(perm: torch.Tensor, r: int):
+    n = perm.numel()
+    ids = _u32(max(r - 1, 0), perm.device)
+    _check(lib().ss_select_splitters(n, _p(perm.contiguous()), r, _p(ids), _stream(perm.device)))
+    return ids
+
+
+def gather_strings(bytes_, offsets, ids: torch.Tensor):
+    b, o, n = _dev_strings(bytes_, offsets)
+    dev = b.device
+    m = ids.numel()
+    out_off = torch.empty(m + 1, dtype=torch.int64, device=dev)
+    lens = (o[1:] - o[:-1])
+    cap = int(lens.max()) * m if (m and n) else 0
+    out = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
+    ws = _ws(lib().ss_gather_workspace(m), dev)
+    _check(lib().ss_gather_strings(_p(b), b.numel(), _p(o), n, _p(ids.contiguous()), m, _p(out_off), _p(out),
+                                   cap, _p(ws), ws.numel(), _stream(dev)))
+    return out[:int(out_off[-1])], out_off
+
+
+def bucket_bounds(bytes_, offsets, perm, spl_bytes, spl_offsets):
+    b, o, n = _dev_strings(bytes_, offsets)
+    r = spl_offsets.numel()  # r-1 splitters
+    out = torch.empty(r + 1, dtype=torch.int64, device=b.device)
+    _check(lib().ss_bucket_bounds(_p(b), b.numel(), _p(o), n, _p(perm.contiguous()), _p(spl_bytes),
+                                  spl_bytes.numel(), _p(spl_offsets), r, _p(out), _stream(b.device)))
+    return out
+
+
+def partition_encode(bytes_, offsets, perm, lcp_, dist, spl_bytes, spl_offsets, suf_cap: int | None = None):
+    """Buckets + front coding.  Returns a dict of device tensors:
+    run_off (r+1), lcp, len, id (n, int32 bits), suf_off (n+1), suf (uint8), total (int)."""
+    b, o, n = _dev_strings(bytes_, offsets)
+    dev = b.device
+    r = spl_offsets.numel()
+    run_off = torch.empty(r + 1, dtype=torch.int64, device=dev)
+    fl, fd, fi = _u32(n, dev), _u32(n, dev), _u32(n, dev)
+    so = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    cap = b.numel() if suf_cap is None else suf_cap
+    suf = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
+    ws = _ws(lib().ss_partition_encode_workspace(n), dev)
+    total = ctypes.c_uint64(0)
+    _check(lib().ss_partition_encode(_p(b), b.numel(), _p(o), n, _p(perm.contiguous()), _p(lcp_.contiguous()),
+                                     _p(dist.contiguous()) if dist is not None else None, _p(spl_bytes),
+                                     spl_bytes.numel(), _p(spl_offsets), r, _p(run_off), _p(fl), _p(fd), _p(fi),
+                                     _p(so), _p(suf), cap, ctypes.byref(total), _p(ws), ws.numel(), _stream(dev)))
+    t = int(total.value)
+    return dict(run_off=run_off, lcp=fl, len=fd, id=fi, suf_off=so, suf=suf[:t], total=t)
+
+
+def fc_decode(run_off, fc_lcp, fc_len, suf_off, suf):
+    """Decode front-coded runs.  Returns (bytes uint8, offsets int64[n+1])."""
+    dev = fc_lcp.device
+    n = fc_lcp.numel()
+    k = run_off.numel() - 1
+    out_off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    total = int(fc_len.to(torch.int64).sum()) if n else 0
+    out = torch.empty(max(total, 1), dtype=torch.uint8, device=dev)
+    ws = _ws(lib().ss_fc_decode_workspace(n), dev)
+    _check(lib().ss_fc_decode(k, _p(run_off), _p(fc_lcp), _p(fc_len), _p(suf_off), _p(suf), n, _p(out_off),
+                              _p(out), total, _p(ws), ws.numel(), _stream(dev)))
+    return out[:total], out_off
+
+
+def lcp_merge(run_off, fc_lcp, fc_len, fc_id, suf_off, suf, ws=None):
+    """LCP-aware k-way merge.  Returns (src int64[n], id int32[n], lcp int32[n])."""
+    dev = fc_lcp.device
+    n = fc_lcp.numel()
+    k = run_off.numel() - 1
+    total = int(fc_len.to(torch.int64).sum()) if n else 0
+    need = lib().ss_lcp_merge_workspace(n, total)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, dev)
+    src = torch.empty(max(n, 0), dtype=torch.int64, device=dev)
+    idv, lc = _u32(n, dev), _u32(n, dev)
+    _check(lib().ss_lcp_merge(k, _p(run_off), _p(fc_lcp), _p(fc_len), _p(fc_id), _p(suf_off), _p(suf), n, _p(src),
+                              _p(idv), _p(lc), _p(ws), ws.numel(), _stream(dev)))
+    return src, idv, lc

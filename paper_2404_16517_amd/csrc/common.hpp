@@ -1,0 +1,204 @@
+// Shared helpers of the strsort HIP library (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/strsort.h"
+
+typedef uint8_t u8;
+typedef uint32_t u32;
+typedef uint64_t u64;
+typedef uint16_t u16;
+
+// ----------------------------------------------------------------- errors
+
+void ss_set_error(const char *fmt, ...);
+void ss_clear_error();
+
+#define SS_HIP(call)                                                            \
+    do {                                                                        \
+        hipError_t e_ = (call);                                                 \
+        if (e_ != hipSuccess) {                                                 \
+            ss_set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),  \
+                         __FILE__, __LINE__);                                   \
+            return SS_ERR_HIP;                                                  \
+        }                                                                       \
+    } while (0)
+
+#define SS_CHECK_LAUNCH()                                                       \
+    do {                                                                        \
+        hipError_t e_ = hipGetLastError();                                      \
+        if (e_ != hipSuccess) {                                                 \
+            ss_set_error("kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), \
+                         __FILE__, __LINE__);                                   \
+            return SS_ERR_HIP;                                                  \
+        }                                                                       \
+    } while (0)
+
+#define SS_TRY(expr)                                                            \
+    do {                                                                        \
+        int rc_ = (expr);                                                       \
+        if (rc_ != SS_OK) return rc_;                                           \
+    } while (0)
+
+static inline u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
+static inline u64 align_up(u64 a, u64 b) { return (a + b - 1) / b * b; }
+
+// Bump allocator over the caller's workspace (256-byte aligned pieces).
+struct WsArena {
+    u8 *base;
+    size_t cap;
+    size_t used;
+    bool overflow;
+    explicit WsArena(void *p, size_t c) : base((u8 *)p), cap(c), used(0), overflow(false) {}
+    template <class T> T *take(u64 count) {
+        size_t bytes = (size_t)align_up(count * sizeof(T) + 1, 256);
+        if (used + bytes > cap) { overflow = true; return nullptr; }
+        T *r = (T *)(base + used);
+        used += bytes;
+        return r;
+    }
+};
+// Same layout computed without memory (for the *_workspace queries).
+struct WsCounter {
+    size_t used = 0;
+    template <class T> void take(u64 count) { used += (size_t)align_up(count * sizeof(T) + 1, 256); }
+};
+
+// Host read-back of small device values (synchronises the stream).
+int ss_read_u32(const u32 *dev, u32 *host, int count, hipStream_t s);
+int ss_read_u64(const u64 *dev, u64 *host, int count, hipStream_t s);
+
+// Tunables (set by ss_set_tuning).
+extern int g_small_max;
+extern int g_tile;
+
+// ------------------------------------------------------ device-wide scans
+
+// Exclusive prefix sum of in[0..n) into out[0..n], out[n] = total.  In-place
+// (in == out) is allowed.  Scratch: ss_scan_scratch_elems(n) elements of T.
+template <class T> u64 ss_scan_scratch_elems(u64 n);
+template <class T> int ss_scan_exclusive(const T *in, T *out, u64 n, T *scratch, hipStream_t s);
+
+// ------------------------------------------------------------ byte loads
+
+// The first `take` (0..8) bytes at bytes[a..] packed big-endian into the top
+// bytes of a 64-bit word (byte a -> bits 63..56), the rest zero.  Reads only
+// inside [bytes, bytes + N): uses two aligned 8-byte loads when they fit and
+// byte loads otherwise.
+__device__ __forceinline__ u64 load_be(const u8 *__restrict__ bytes, u64 N, u64 a, u32 take)
+{
+    if (take == 0) return 0;
+    const uintptr_t p = (uintptr_t)(bytes + a);
+    const uintptr_t base = p & ~(uintptr_t)7;
+    const u32 sh = (u32)(p & 7);
+    const uintptr_t lo = (uintptr_t)bytes, hi = (uintptr_t)(bytes + N);
+    u64 v;
+    if (base >= lo && base + ((sh + take > 8) ? 16 : 8) <= hi) {
+        const u64 *w = (const u64 *)base;
+        u64 w0 = w[0];
+        if (sh == 0) {
+            v = w0;
+        } else if (sh + take <= 8) {
+            v = w0 >> (8 * sh);
+        } else {
+            u64 w1 = w[1];
+            v = (w0 >> (8 * sh)) | (w1 << (64 - 8 * sh));
+        }
+        v = __builtin_bswap64(v);
+    } else {
+        v = 0;
+        for (u32 t = 0; t < take; t++) v |= (u64)bytes[a + t] << (56 - 8 * t);
+    }
+    if (take < 8) v &= ~0ull << (64 - 8 * take);
+    return v;
+}
+
+// Little-endian 8-byte window starting at bytes[a], zero beyond `take` bytes.
+__device__ __forceinline__ u64 load_le(const u8 *__restrict__ bytes, u64 N, u64 a, u32 take)
+{
+    return __builtin_bswap64(load_be(bytes, N, a, take));
+}
+
+// Radix key of a string at byte depth d: the next 7 bytes (zero-padded)
+// big-endian in bits 63..8, and min(len - d, 8) in bits 7..0.  Comparing keys
+// as unsigned integers orders strings by their bytes [d, d+7) with the
+// shorter-is-smaller rule: a count below 8 marks a string ending inside the
+// window, and equal data with count 8 means "equal so far, both continue".
+__device__ __forceinline__ u64 make_key(const u8 *__restrict__ bytes, u64 N, u64 off, u64 len, u64 d)
+{
+    u64 rem = len > d ? len - d : 0;
+    u32 take = rem < 7 ? (u32)rem : 7u;
+    u64 data = load_be(bytes, N, off + d, take);
+    u32 cnt = rem < 8 ? (u32)rem : 8u;
+    return (data & ~0xFFull) | cnt;
+}
+
+// LCP of two strings whose keys at depth d differ (or are equal with count < 8):
+// d + min(equal leading data bytes, count_a, count_b).
+__device__ __forceinline__ u32 key_lcp(u64 ka, u64 kb, u32 d)
+{
+    u64 x = (ka ^ kb) >> 8;
+    u32 eq = x ? (u32)(__clzll(x << 8) >> 3) : 7u;
+    u32 ca = (u32)(ka & 0xFF), cb = (u32)(kb & 0xFF);
+    u32 m = ca < cb ? ca : cb;
+    return d + (eq < m ? eq : m);
+}
+
+// Full LCP of strings a (len la) and b (len lb) starting the comparison at
+// byte `from` (both are known to agree on [0, from)).
+__device__ __forceinline__ u64 str_lcp_from(const u8 *__restrict__ bytes, u64 N, u64 oa, u64 la,
+                                            u64 ob, u64 lb, u64 from)
+{
+    u64 m = la < lb ? la : lb;
+    u64 i = from;
+    while (i < m) {
+        u64 r = m - i;
+        u32 take = r < 8 ? (u32)r : 8u;
+        u64 wa = load_be(bytes, N, oa + i, take);
+        u64 wb = load_be(bytes, N, ob + i, take);
+        if (wa != wb) return i + (__clzll(wa ^ wb) >> 3);
+        i += take;
+    }
+    return m;
+}
+
+// Three-way comparison of string a (bytes pa) against string b (bytes pb),
+// both from possibly different buffers, starting at byte `from`.  Writes the
+// LCP to *lcp_out.  Returns <0, 0, >0.
+__device__ __forceinline__ int str_cmp_from(const u8 *__restrict__ ba, u64 Na, u64 oa, u64 la,
+                                            const u8 *__restrict__ bb, u64 Nb, u64 ob, u64 lb,
+                                            u64 from, u64 *lcp_out)
+{
+    u64 m = la < lb ? la : lb;
+    u64 i = from;
+    while (i < m) {
+        u64 r = m - i;
+        u32 take = r < 8 ? (u32)r : 8u;
+        u64 wa = load_be(ba, Na, oa + i, take);
+        u64 wb = load_be(bb, Nb, ob + i, take);
+        if (wa != wb) {
+            *lcp_out = i + (__clzll(wa ^ wb) >> 3);
+            return wa < wb ? -1 : 1;
+        }
+        i += take;
+    }
+    *lcp_out = m;
+    return la < lb ? -1 : (la > lb ? 1 : 0);
+}
+
+// Binary search: number of entries of the sorted array a[0..n) that are <= x.
+template <class T>
+__device__ __forceinline__ u64 upper_bound_dev(const T *a, u64 n, T x)
+{
+    u64 lo = 0, hi = n;
+    while (lo < hi) {
+        u64 mid = (lo + hi) >> 1;
+        if (a[mid] <= x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ u64 lanemask_lt() { return (1ull << __lane_id()) - 1ull; }

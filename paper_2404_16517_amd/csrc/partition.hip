@@ -1,0 +1,295 @@
+// Splitters, bucket boundaries and LCP compression of buckets (Section 3,
+// steps 1-2; LCP compression from Section 2; distinguishing prefixes only in
+// the prefix-doubling variant of Section 4).
+#include "common.hpp"
+
+// ------------------------------------------------------------- splitters
+
+// f_j = s_perm[ceil(j n / r) - 1], j = 1..r-1 (regular sampling of the whole
+// sorted array, the one-device form of Section 3.1).
+__global__ void k_select(u64 n, const u32 *perm, u32 r, u32 *ids)
+{
+    const u32 j = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (j >= r) return;
+    const u64 c = ((u64)j * n + r - 1) / r;
+    ids[j - 1] = perm[c - 1];
+}
+
+extern "C" int ss_select_splitters(uint64_t n, const uint32_t *perm, uint32_t r, uint32_t *splitter_ids,
+                                   void *stream)
+{
+    ss_clear_error();
+    if (n == 0 || r == 0 || !perm || (r > 1 && !splitter_ids)) {
+        ss_set_error("select_splitters needs n >= 1, r >= 1 and non-null arrays");
+        return SS_ERR_INVALID_ARG;
+    }
+    if (r == 1) return SS_OK;
+    hipStream_t st = (hipStream_t)stream;
+    k_select<<<(unsigned)ceil_div(r - 1, 256), 256, 0, st>>>(n, perm, r, splitter_ids);
+    SS_CHECK_LAUNCH();
+    return SS_OK;
+}
+
+// ---------------------------------------------------------------- gather
+
+__global__ void k_gather_lens(const u64 *off, const u32 *ids, u32 m, u64 *out)
+{
+    const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m) out[j] = off[ids[j] + 1] - off[ids[j]];
+}
+
+// one wave per string, lanes copy consecutive bytes
+__global__ __launch_bounds__(256) void k_gather_copy(const u8 *bytes, const u64 *off, const u32 *ids,
+                                                     u32 m, const u64 *out_off, u8 *out)
+{
+    const u32 j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= m) return;
+    const u32 lane = threadIdx.x & 63;
+    const u64 so = off[ids[j]], len = off[ids[j] + 1] - so, oo = out_off[j];
+    for (u64 q = lane; q < len; q += 64) out[oo + q] = bytes[so + q];
+}
+
+extern "C" size_t ss_gather_workspace(uint64_t m)
+{
+    WsCounter c;
+    c.take<u64>(ss_scan_scratch_elems<u64>(m + 1));
+    return c.used;
+}
+
+extern "C" int ss_gather_strings(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                                 const uint32_t *ids, uint64_t m, uint64_t *out_offsets, uint8_t *out_bytes,
+                                 uint64_t out_cap, void *ws, size_t ws_bytes, void *stream)
+{
+    ss_clear_error();
+    (void)N; (void)n;
+    if (m >= 0xFFFFFFFFull) { ss_set_error("m too large"); return SS_ERR_TOO_LARGE; }
+    if (!out_offsets || (m > 0 && (!offsets || !ids))) { ss_set_error("null pointer"); return SS_ERR_INVALID_ARG; }
+    hipStream_t st = (hipStream_t)stream;
+    WsArena a(ws, ws_bytes);
+    u64 *scratch = a.take<u64>(ss_scan_scratch_elems<u64>(m + 1));
+    if (a.overflow || !ws) {
+        ss_set_error("workspace too small: need %zu bytes", ss_gather_workspace(m));
+        return SS_ERR_WORKSPACE;
+    }
+    if (m > 0) {
+        k_gather_lens<<<(unsigned)ceil_div(m, 256), 256, 0, st>>>(offsets, ids, (u32)m, out_offsets);
+        SS_CHECK_LAUNCH();
+    }
+    SS_TRY(ss_scan_exclusive<u64>(out_offsets, out_offsets, m, scratch, st));
+    u64 total;
+    SS_TRY(ss_read_u64(out_offsets + m, &total, 1, st));
+    if (total > out_cap) {
+        ss_set_error("gather needs %llu bytes, capacity %llu", (unsigned long long)total,
+                     (unsigned long long)out_cap);
+        return SS_ERR_CAPACITY;
+    }
+    if (m > 0 && total > 0) {
+        k_gather_copy<<<(unsigned)ceil_div(m, 4), 256, 0, st>>>(bytes, offsets, ids, (u32)m, out_offsets,
+                                                                out_bytes);
+        SS_CHECK_LAUNCH();
+    }
+    return SS_OK;
+}
+
+// --------------------------------------------------------------- buckets
+
+// bounds[j] = #{ i : s_perm[i] <= f_j }: binary search over the sorted array.
+// All strings between the current bounds share min(lcp_lo, lcp_hi) bytes with
+// f, so each comparison starts there.
+__global__ void k_bounds(const u8 *bytes, u64 N, const u64 *off, u64 n, const u32 *perm, const u8 *sb,
+                         u64 sN, const u64 *soff, u32 r, u64 *bounds)
+{
+    const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0) bounds[0] = 0;
+    if (j == r) bounds[r] = n;
+    if (j == 0 || j >= r) return;
+    const u64 fo = soff[j - 1], fl = soff[j] - fo;
+    u64 lo = 0, hi = n, llo = 0, lhi = 0;
+    while (lo < hi) {
+        const u64 mid = (lo + hi) >> 1;
+        const u32 p = perm[mid];
+        const u64 o = off[p], l = off[p + 1] - o;
+        u64 lc;
+        const u64 from = llo < lhi ? llo : lhi;
+        const int c = str_cmp_from(bytes, N, o, l, sb, sN, fo, fl, from, &lc);
+        if (c <= 0) {  // s <= f
+            lo = mid + 1;
+            llo = lc;
+        } else {
+            hi = mid;
+            lhi = lc;
+        }
+    }
+    bounds[j] = lo;
+}
+
+extern "C" int ss_bucket_bounds(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                                const uint32_t *perm, const uint8_t *spl_bytes, uint64_t spl_N,
+                                const uint64_t *spl_offsets, uint32_t r, uint64_t *bounds, void *stream)
+{
+    ss_clear_error();
+    if (r == 0 || !bounds || (r > 1 && !spl_offsets) || (n > 0 && (!offsets || !perm))) {
+        ss_set_error("bucket_bounds: bad arguments");
+        return SS_ERR_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    k_bounds<<<(unsigned)ceil_div((u64)r + 1, 256), 256, 0, st>>>(bytes, N, offsets, n, perm, spl_bytes,
+                                                                  spl_N, spl_offsets, r, bounds);
+    SS_CHECK_LAUNCH();
+    return SS_OK;
+}
+
+// ---------------------------------------------------------- front coding
+
+// e_i, d_i, id_i and the literal length d_i - e_i of every sorted position.
+__global__ __launch_bounds__(256) void k_fc_meta(const u64 *off, u32 n, const u32 *perm, const u32 *lcp,
+                                                 const u32 *dist, const u64 *run_off, u32 r, u32 *fc_lcp,
+                                                 u32 *fc_len, u32 *fc_id, u64 *sizes, u32 *bad)
+{
+    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // bucket start: the largest run_off[j] <= i
+    u32 lo = 0, hi = r;  // run_off has r+1 entries
+    while (hi - lo > 1) {
+        u32 mid = (lo + hi) >> 1;
+        if (run_off[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    const u32 e = (run_off[lo] == i) ? 0u : lcp[i];
+    const u32 p = perm[i];
+    const u64 len = off[p + 1] - off[p];
+    const u32 d = dist ? dist[p] : (u32)len;
+    fc_lcp[i] = e;
+    fc_len[i] = d;
+    fc_id[i] = p;
+    if (e > d || d > len) {
+        atomicOr(bad, 1u);
+        sizes[i] = 0;
+    } else {
+        sizes[i] = d - e;
+    }
+}
+
+#define CP_NT 256
+#define CP_PER 16
+
+// Output-ordered copy of literal bytes: each thread writes 16 consecutive
+// output bytes; the workgroup first finds the range of strings its 4096 bytes
+// cover, then each thread locates its string inside that range.
+__global__ __launch_bounds__(CP_NT) void k_fc_copy(const u8 *bytes, const u64 *off, u32 n, const u32 *perm,
+                                                   const u32 *fc_lcp, const u64 *suf_off, u64 total, u8 *suf)
+{
+    __shared__ u32 range[2];
+    const u64 c0 = (u64)blockIdx.x * CP_NT * CP_PER;
+    const u64 c1 = (c0 + CP_NT * CP_PER < total) ? c0 + CP_NT * CP_PER : total;
+    if (threadIdx.x < 2) {
+        const u64 q = threadIdx.x == 0 ? c0 : c1 - 1;
+        // largest i with suf_off[i] <= q
+        u32 lo = 0, hi = n;
+        while (hi - lo > 1) {
+            u32 mid = (lo + hi) >> 1;
+            if (suf_off[mid] <= q) lo = mid;
+            else hi = mid;
+        }
+        range[threadIdx.x] = lo;
+    }
+    __syncthreads();
+    const u64 q0 = c0 + (u64)threadIdx.x * CP_PER;
+    if (q0 >= c1) return;
+    u32 lo = range[0], hi = range[1] + 1;
+    while (hi - lo > 1) {
+        u32 mid = (lo + hi) >> 1;
+        if (suf_off[mid] <= q0) lo = mid;
+        else hi = mid;
+    }
+    u32 i = lo;
+    u64 so = suf_off[i], se = suf_off[i + 1];
+    u64 src = off[perm[i]] + fc_lcp[i];
+    u8 buf[CP_PER];
+    const u32 cnt = (u32)((c1 - q0) < CP_PER ? (c1 - q0) : CP_PER);
+#pragma unroll
+    for (u32 t = 0; t < CP_PER; t++) {
+        if (t < cnt) {
+            const u64 q = q0 + t;
+            while (q >= se) {
+                i++;
+                so = se;
+                se = suf_off[i + 1];
+                src = off[perm[i]] + fc_lcp[i];
+            }
+            buf[t] = bytes[src + (q - so)];
+        } else {
+            buf[t] = 0;
+        }
+    }
+    u8 *dst = suf + q0;
+    if (cnt == CP_PER && (((uintptr_t)dst) & 15) == 0) {
+        uint4 v;
+        v.x = buf[0] | (buf[1] << 8) | (buf[2] << 16) | ((u32)buf[3] << 24);
+        v.y = buf[4] | (buf[5] << 8) | (buf[6] << 16) | ((u32)buf[7] << 24);
+        v.z = buf[8] | (buf[9] << 8) | (buf[10] << 16) | ((u32)buf[11] << 24);
+        v.w = buf[12] | (buf[13] << 8) | (buf[14] << 16) | ((u32)buf[15] << 24);
+        *(uint4 *)dst = v;
+    } else {
+        for (u32 t = 0; t < cnt; t++) dst[t] = buf[t];
+    }
+}
+
+extern "C" size_t ss_partition_encode_workspace(uint64_t n)
+{
+    WsCounter c;
+    c.take<u64>(ss_scan_scratch_elems<u64>(n + 1));
+    c.take<u32>(4);
+    return c.used;
+}
+
+extern "C" int ss_partition_encode(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                                   const uint32_t *perm, const uint32_t *lcp, const uint32_t *dist,
+                                   const uint8_t *spl_bytes, uint64_t spl_N, const uint64_t *spl_offsets,
+                                   uint32_t r, uint64_t *run_off, uint32_t *fc_lcp, uint32_t *fc_len,
+                                   uint32_t *fc_id, uint64_t *suf_off, uint8_t *suf, uint64_t suf_cap,
+                                   uint64_t *suf_total_host, void *ws, size_t ws_bytes, void *stream)
+{
+    ss_clear_error();
+    if (n >= 0xFFFFFFFFull) { ss_set_error("n too large"); return SS_ERR_TOO_LARGE; }
+    if (r == 0 || !run_off || !suf_off || (n > 0 && (!offsets || !perm || !lcp || !fc_lcp || !fc_len || !fc_id))) {
+        ss_set_error("partition_encode: bad arguments");
+        return SS_ERR_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    WsArena a(ws, ws_bytes);
+    u64 *scratch = a.take<u64>(ss_scan_scratch_elems<u64>(n + 1));
+    u32 *bad = a.take<u32>(4);
+    if (a.overflow || !ws) {
+        ss_set_error("workspace too small: need %zu bytes", ss_partition_encode_workspace(n));
+        return SS_ERR_WORKSPACE;
+    }
+    SS_TRY(ss_bucket_bounds(bytes, N, offsets, n, perm, spl_bytes, spl_N, spl_offsets, r, run_off, stream));
+    SS_HIP(hipMemsetAsync(bad, 0, sizeof(u32), st));
+    if (n > 0) {
+        k_fc_meta<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(offsets, (u32)n, perm, lcp, dist, run_off, r,
+                                                               fc_lcp, fc_len, fc_id, suf_off, bad);
+        SS_CHECK_LAUNCH();
+    }
+    SS_TRY(ss_scan_exclusive<u64>(suf_off, suf_off, n, scratch, st));
+    u64 total;
+    u32 hbad;
+    SS_TRY(ss_read_u64(suf_off + n, &total, 1, st));
+    SS_TRY(ss_read_u32(bad, &hbad, 1, st));
+    if (hbad) {
+        ss_set_error("front coding needs lcp <= dist <= len at every position");
+        return SS_ERR_INVALID_ARG;
+    }
+    if (total > suf_cap) {
+        ss_set_error("literal bytes %llu exceed capacity %llu", (unsigned long long)total,
+                     (unsigned long long)suf_cap);
+        return SS_ERR_CAPACITY;
+    }
+    if (suf_total_host) *suf_total_host = total;
+    if (total > 0) {
+        k_fc_copy<<<(unsigned)ceil_div(total, CP_NT * CP_PER), CP_NT, 0, st>>>(bytes, offsets, (u32)n, perm,
+                                                                             fc_lcp, suf_off, total, suf);
+        SS_CHECK_LAUNCH();
+    }
+    return SS_OK;
+}

@@ -1,0 +1,759 @@
+// Segmented MSD radix string sort with LCP by-product (gfx950).
+//
+// Sorting the local string array is the first step of the paper's merge sort
+// (Section 3, "Initialization"); the LCP array is its by-product.  This is a
+// GPU-native design, not the paper's CPU algorithm:
+//
+//   * The sorted array is a set of contiguous SEGMENTS whose strings share a
+//     known prefix of `depth` bytes.  Segment boundaries are final.
+//   * Each ROUND takes the unresolved segments and
+//       1. skips their common prefix: every string is compared with the
+//          segment's first string from `depth` on and the minimum LCP is added
+//          to `depth` (deep shared prefixes cost one read of D bytes, not one
+//          radix pass per 7 bytes);
+//       2. loads a 64-bit key per string: the next 7 bytes big-endian plus the
+//          remaining length capped at 8, so that integer order is string order
+//          over that window, end-of-string below every byte;
+//       3. sorts each segment by (key, input index): segments larger than the
+//          LDS cutover go through MSD byte passes (histogram, global scan,
+//          stable scatter), smaller ones are packed into LDS tiles and sorted
+//          by a bitonic network;
+//       4. where neighbours' keys differ the LCP is final and is written; runs
+//          of equal keys whose strings continue become next round's segments
+//          at depth + 7; runs of equal keys whose strings end are equal
+//          strings (LCP = length, order = input index).
+//   * The same machinery, in PLAIN mode, sorts raw 64-bit keys with a 32-bit
+//     payload (duplicate detection of prefix hashes, Appendix B).
+#include <string.h>
+
+#include "common.hpp"
+#include "sort_core.hpp"
+
+#define NT 256
+#define ETILE 2048  // elements per workgroup in element-wise round kernels
+#define LDS_NT 512
+#define LDS_CAP 2048  // elements per LDS tile (2 x the largest cutover)
+
+enum { C_SMALL = 0, C_LARGE = 1, C_NEXT = 2, C_IDENT = 3, C_BND = 4, C_NCTR = 8 };
+
+// ------------------------------------------------------------ wave helpers
+
+// Lanes of this wave holding the same 8-bit digit (restricted to `valid`).
+__device__ __forceinline__ u64 match_digit(u32 digit, bool valid)
+{
+    u64 m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+        u64 bb = __ballot((digit >> b) & 1);
+        m &= ((digit >> b) & 1) ? bb : ~bb;
+    }
+    return m;
+}
+
+// Wave-aggregated append: returns the slot for lanes with pred set.
+__device__ __forceinline__ u32 wave_append(bool pred, u32 *counter)
+{
+    u64 m = __ballot(pred);
+    if (m == 0) return 0;
+    u32 leader = __ffsll((unsigned long long)m) - 1;
+    u32 base = 0;
+    if (__lane_id() == leader) base = atomicAdd(counter, (u32)__popcll(m));
+    base = __shfl(base, leader, 64);
+    return base + (u32)__popcll(m & lanemask_lt());
+}
+
+__device__ __forceinline__ u32 seg_of_tile(const u32 *tstart, u32 nseg, u32 t)
+{
+    // largest s with tstart[s] <= t (tstart has nseg+1 entries, strictly increasing)
+    u32 lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+        u32 mid = (lo + hi) >> 1;
+        if (tstart[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <class T>
+__device__ __forceinline__ T block_min(T v)
+{
+    __shared__ T red[NT / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T y = __shfl_xor(v, o, 64);
+        v = y < v ? y : v;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T r = red[0];
+    for (int w = 1; w < NT / 64; w++) r = red[w] < r ? red[w] : r;
+    __syncthreads();
+    return r;
+}
+
+template <class T>
+__device__ __forceinline__ T block_max(T v)
+{
+    __shared__ T red[NT / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T y = __shfl_xor(v, o, 64);
+        v = y > v ? y : v;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T r = red[0];
+    for (int w = 1; w < NT / 64; w++) r = red[w] > r ? red[w] : r;
+    __syncthreads();
+    return r;
+}
+
+// ------------------------------------------------------------ tile lists
+
+__global__ void k_tile_counts(const Seg *segs, u32 nseg, u32 tile, u32 *out)
+{
+    u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < nseg) out[j] = (segs[j].end - segs[j].begin + tile - 1) / tile;
+}
+
+__global__ void k_sizes(const Seg *segs, u32 nseg, u32 *out)
+{
+    u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < nseg) out[j] = segs[j].end - segs[j].begin;
+}
+
+// ------------------------------------------------------------ round kernels
+
+// Minimum LCP of every member with the segment's first string, from `depth`.
+__global__ __launch_bounds__(NT) void k_skip(const Seg *segs, const u32 *tstart, u32 nseg,
+                                             const u8 *bytes, u64 N, const u64 *off,
+                                             const u32 *perm, u32 *skipv)
+{
+    const u32 t = blockIdx.x;
+    const u32 s = seg_of_tile(tstart, nseg, t);
+    const Seg g = segs[s];
+    if (!(g.aux & SEG_SKIP)) return;
+    const u32 lt = t - tstart[s];
+    const u32 b0 = g.begin + lt * ETILE;
+    const u32 b1 = min(g.end, b0 + ETILE);
+    const u32 f = perm[g.begin];
+    const u64 fo = off[f], fl = off[f + 1] - fo;
+    u32 best = 0xFFFFFFFFu;
+    for (u32 i = b0 + threadIdx.x; i < b1; i += NT) {
+        const u32 p = perm[i];
+        const u64 o = off[p], l = off[p + 1] - o;
+        u64 c = str_lcp_from(bytes, N, o, l, fo, fl, g.depth) - g.depth;
+        best = min(best, (u32)c);
+    }
+    best = block_min(best);
+    if (threadIdx.x == 0) atomicMin(&skipv[s], best);
+}
+
+__global__ __launch_bounds__(NT) void k_keys(const Seg *segs, const u32 *tstart, u32 nseg,
+                                             const u8 *bytes, u64 N, const u64 *off,
+                                             const u32 *perm, const u32 *skipv, u64 *keys)
+{
+    const u32 t = blockIdx.x;
+    const u32 s = seg_of_tile(tstart, nseg, t);
+    const Seg g = segs[s];
+    const u32 lt = t - tstart[s];
+    const u32 b0 = g.begin + lt * ETILE;
+    const u32 b1 = min(g.end, b0 + ETILE);
+    const u64 d = (u64)g.depth + ((g.aux & SEG_SKIP) ? skipv[s] : 0u);
+    for (u32 i = b0 + threadIdx.x; i < b1; i += NT) {
+        const u32 p = perm[i];
+        const u64 o = off[p], l = off[p + 1] - o;
+        keys[i] = make_key(bytes, N, o, l, d);
+    }
+}
+
+// Apply the skip, route each active segment to the LDS list or the radix list.
+__global__ void k_classify(const Seg *act, u32 nact, const u32 *skipv, u32 small_max, Seg *small,
+                           Seg *large, u32 *ctr)
+{
+    u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    bool valid = j < nact;
+    Seg g = {0, 0, 0, 0};
+    if (valid) {
+        g = act[j];
+        if (g.aux & SEG_SKIP) g.depth += skipv[j];
+        g.aux = 0;
+    }
+    bool sm = valid && (g.end - g.begin) <= small_max;
+    bool lg = valid && !sm;
+    u32 a = wave_append(sm, &ctr[C_SMALL]);
+    if (sm) small[a] = g;
+    u32 b = wave_append(lg, &ctr[C_LARGE]);
+    if (lg) large[b] = g;
+}
+
+// ------------------------------------------------------------ radix passes
+
+__device__ __forceinline__ u32 digit_of(u64 k, u32 level) { return (u32)(k >> (56 - 8 * level)) & 0xFFu; }
+
+// Per-tile histogram of the segment's current byte, digit-major per segment:
+// hist[256*tstart[s] + d*T_s + lt].  Also the segment's min and max key.
+__global__ __launch_bounds__(NT) void k_hist(const Seg *segs, const u32 *tstart, u32 nseg, u32 tile,
+                                             const u64 *keys, u32 *hist, u64 *smin, u64 *smax)
+{
+    __shared__ u32 h[256];
+    const u32 t = blockIdx.x;
+    const u32 s = seg_of_tile(tstart, nseg, t);
+    const Seg g = segs[s];
+    const u32 T = tstart[s + 1] - tstart[s];
+    const u32 lt = t - tstart[s];
+    const u32 level = g.aux & 15;
+    const u32 b0 = g.begin + lt * tile;
+    const u32 b1 = min(g.end, b0 + tile);
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    u64 mn = ~0ull, mx = 0;
+    for (u32 c = b0; c < b1; c += NT) {
+        const u32 i = c + threadIdx.x;
+        const bool valid = i < b1;
+        u64 k = valid ? keys[i] : 0;
+        u32 d = digit_of(k, level);
+        u64 peers = match_digit(d, valid);
+        if (valid) {
+            mn = k < mn ? k : mn;
+            mx = k > mx ? k : mx;
+            if ((peers & lanemask_lt()) == 0) atomicAdd(&h[d], (u32)__popcll(peers));
+        }
+    }
+    __syncthreads();
+    hist[256u * tstart[s] + threadIdx.x * T + lt] = h[threadIdx.x];
+    mn = block_min(mn);
+    mx = block_max(mx);
+    if (threadIdx.x == 0) {
+        atomicMin((unsigned long long *)&smin[s], (unsigned long long)mn);
+        atomicMax((unsigned long long *)&smax[s], (unsigned long long)mx);
+    }
+}
+
+struct EmitOut {
+    Seg *small, *large_next, *next, *ident;
+    uint2 *bnd;
+    u32 *ctr;
+    u8 *scat;
+    u32 small_max;
+    int plain;
+};
+
+// A run of strings with equal keys (all 8 key bytes): continue next round, or
+// equal strings.
+__device__ __forceinline__ void emit_exhausted(const EmitOut &o, u32 b, u32 e, u32 depth, u32 cnt)
+{
+    if (o.plain) return;
+    if (cnt == 8) {
+        u32 a = atomicAdd(&o.ctr[C_NEXT], 1u);
+        o.next[a] = Seg{b, e, depth + 7, SEG_SKIP};
+    } else {
+        u32 a = atomicAdd(&o.ctr[C_IDENT], 1u);
+        o.ident[a] = Seg{b, e, depth + cnt, 0};
+    }
+}
+
+// One workgroup per radix segment: digit counts from the scanned histogram,
+// emission of the sub-segments.
+__global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart, u32 nseg,
+                                              const u32 *hist, const u64 *smin, const u64 *smax,
+                                              EmitOut o)
+{
+    const u32 s = blockIdx.x;
+    const u32 d = threadIdx.x;
+    const Seg g = segs[s];
+    const u32 ts = tstart[s];
+    const u32 T = tstart[s + 1] - ts;
+    const u32 level = g.aux & 15;
+    const u64 mn = smin[s], mx = smax[s];
+    if (mn == mx) {
+        if (d == 0) {
+            o.scat[s] = 0;
+            emit_exhausted(o, g.begin, g.end, g.depth, (u32)(mn & 0xFF));
+        }
+        return;
+    }
+    const u32 fb = __clzll(mn ^ mx) >> 3;  // first byte where the keys differ
+    if (fb > level) {
+        // bytes level..fb-1 are common to the whole segment: no scatter needed
+        if (d == 0) {
+            o.scat[s] = 0;
+            u32 a = atomicAdd(&o.ctr[C_LARGE], 1u);
+            o.large_next[a] = Seg{g.begin, g.end, g.depth, fb};
+        }
+        return;
+    }
+    if (d == 0) o.scat[s] = 1;
+    const u32 e = 256u * ts + d * T;
+    const u32 base = hist[256u * ts];
+    const u32 start = hist[e] - base;
+    const u32 cnt = hist[e + T] - hist[e];
+    if (cnt == 0) return;
+    const u32 sb = g.begin + start, se = sb + cnt;
+    if (start > 0 && !o.plain) {
+        u32 a = atomicAdd(&o.ctr[C_BND], 1u);
+        o.bnd[a] = make_uint2(sb, g.depth);
+    }
+    if (cnt == 1) return;
+    if (level == 7) {
+        emit_exhausted(o, sb, se, g.depth, d);
+    } else if (cnt <= o.small_max) {
+        u32 a = atomicAdd(&o.ctr[C_SMALL], 1u);
+        o.small[a] = Seg{sb, se, g.depth, 0};
+    } else {
+        u32 a = atomicAdd(&o.ctr[C_LARGE], 1u);
+        o.large_next[a] = Seg{sb, se, g.depth, level + 1};
+    }
+}
+
+// Stable scatter of (key, payload) by the current byte into the B arrays.
+__global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tstart, u32 nseg, u32 tile,
+                                                const u32 *hist, const u8 *scat, const u64 *keyA,
+                                                const u32 *valA, u64 *keyB, u32 *valB)
+{
+    __shared__ u32 run[256];
+    __shared__ u32 wcnt[NT / 64][256];
+    const u32 t = blockIdx.x;
+    const u32 s = seg_of_tile(tstart, nseg, t);
+    if (!scat[s]) return;
+    const Seg g = segs[s];
+    const u32 ts = tstart[s];
+    const u32 T = tstart[s + 1] - ts;
+    const u32 lt = t - ts;
+    const u32 level = g.aux & 15;
+    const u32 b0 = g.begin + lt * tile;
+    const u32 b1 = min(g.end, b0 + tile);
+    const u32 base = hist[256u * ts];
+    run[threadIdx.x] = g.begin + hist[256u * ts + threadIdx.x * T + lt] - base;
+    const u32 wid = threadIdx.x >> 6;
+    for (u32 c = b0; c < b1; c += NT) {
+        const u32 i = c + threadIdx.x;
+        const bool valid = i < b1;
+        u64 k = 0;
+        u32 v = 0;
+        if (valid) {
+            k = keyA[i];
+            v = valA[i];
+        }
+        const u32 d = digit_of(k, level);
+#pragma unroll
+        for (int w = 0; w < NT / 64; w++) wcnt[w][threadIdx.x] = 0;
+        __syncthreads();
+        const u64 peers = match_digit(d, valid);
+        const u32 rank = (u32)__popcll(peers & lanemask_lt());
+        if (valid && rank == 0) wcnt[wid][d] = (u32)__popcll(peers);
+        __syncthreads();
+        {
+            u32 acc = run[threadIdx.x];
+#pragma unroll
+            for (int w = 0; w < NT / 64; w++) {
+                u32 x = wcnt[w][threadIdx.x];
+                wcnt[w][threadIdx.x] = acc;
+                acc += x;
+            }
+            run[threadIdx.x] = acc;
+        }
+        __syncthreads();
+        if (valid) {
+            const u32 dst = wcnt[wid][d] + rank;
+            keyB[dst] = k;
+            valB[dst] = v;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_copyback(const Seg *segs, const u32 *tstart, u32 nseg, u32 tile,
+                                                 const u8 *scat, const u64 *keyB, const u32 *valB,
+                                                 u64 *keyA, u32 *valA)
+{
+    const u32 t = blockIdx.x;
+    const u32 s = seg_of_tile(tstart, nseg, t);
+    if (!scat[s]) return;
+    const Seg g = segs[s];
+    const u32 lt = t - tstart[s];
+    const u32 b0 = g.begin + lt * tile;
+    const u32 b1 = min(g.end, b0 + tile);
+    for (u32 i = b0 + threadIdx.x; i < b1; i += NT) {
+        keyA[i] = keyB[i];
+        valA[i] = valB[i];
+    }
+}
+
+__global__ void k_boundary(const uint2 *bnd, u32 nb, const u64 *keys, u32 *lcp)
+{
+    u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nb) return;
+    uint2 b = bnd[j];
+    lcp[b.x] = key_lcp(keys[b.x - 1], keys[b.x], b.y);
+}
+
+// Equal strings: LCP = their length for every member after the first.
+__global__ __launch_bounds__(NT) void k_ident(const Seg *segs, const u32 *tstart, u32 nseg, u32 *lcp)
+{
+    const u32 t = blockIdx.x;
+    const u32 s = seg_of_tile(tstart, nseg, t);
+    const Seg g = segs[s];
+    const u32 lt = t - tstart[s];
+    const u32 b0 = g.begin + lt * ETILE;
+    const u32 b1 = min(g.end, b0 + ETILE);
+    for (u32 i = b0 + threadIdx.x; i < b1; i += NT)
+        if (i > g.begin) lcp[i] = g.depth;
+}
+
+// ------------------------------------------------------------- LDS sort
+
+__device__ __forceinline__ bool lds_greater(u16 sa, u64 ka, u32 va, u16 sb, u64 kb, u32 vb)
+{
+    if (sa != sb) return sa > sb;
+    if (ka != kb) return ka > kb;
+    return va > vb;
+}
+
+// Small segments packed into tiles: tile t takes the segments whose start in
+// the concatenated small-segment space lies in [t*H, (t+1)*H); with segment
+// sizes <= H a tile holds < 2H elements.  Sorted by (segment, key, payload)
+// with a bitonic network in LDS.
+__global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32 *pref, u32 nsmall,
+                                                     u32 H, u64 *keys, u32 *vals, u32 *lcp, Seg *next,
+                                                     u32 *ctr, int plain)
+{
+    __shared__ u64 skey[LDS_CAP];
+    __shared__ u32 sval[LDS_CAP];
+    __shared__ u16 sseg[LDS_CAP];
+    __shared__ u32 spref[LDS_CAP / 2 + 1];
+    __shared__ u32 sbeg[LDS_CAP / 2];
+    __shared__ u32 sdep[LDS_CAP / 2];
+    const u32 t = blockIdx.x;
+    const u32 lo = t * H, hi = lo + H;
+    // j0 = first segment with pref >= lo, j1 = first with pref >= hi
+    u32 j0, j1;
+    {
+        u32 a = 0, b = nsmall;
+        while (a < b) { u32 m = (a + b) >> 1; if (pref[m] < lo) a = m + 1; else b = m; }
+        j0 = a;
+        a = j0; b = nsmall;
+        while (a < b) { u32 m = (a + b) >> 1; if (pref[m] < hi) a = m + 1; else b = m; }
+        j1 = a;
+    }
+    if (j0 >= j1) return;
+    const u32 ns = j1 - j0;
+    const u32 base = pref[j0];
+    const u32 cnt = pref[j1] - base;
+    for (u32 k = threadIdx.x; k <= ns; k += LDS_NT) spref[k] = pref[j0 + k] - base;
+    for (u32 k = threadIdx.x; k < ns; k += LDS_NT) {
+        Seg g = small[j0 + k];
+        sbeg[k] = g.begin;
+        sdep[k] = g.depth;
+    }
+    __syncthreads();
+    u32 P = 2;
+    while (P < cnt) P <<= 1;
+    for (u32 e = threadIdx.x; e < P; e += LDS_NT) {
+        if (e < cnt) {
+            u32 a = 0, b = ns;  // largest k with spref[k] <= e
+            while (b - a > 1) { u32 m = (a + b) >> 1; if (spref[m] <= e) a = m; else b = m; }
+            const u32 pos = sbeg[a] + (e - spref[a]);
+            skey[e] = keys[pos];
+            sval[e] = vals[pos];
+            sseg[e] = (u16)a;
+        } else {
+            skey[e] = ~0ull;
+            sval[e] = 0xFFFFFFFFu;
+            sseg[e] = 0xFFFF;
+        }
+    }
+    __syncthreads();
+    for (u32 k = 2; k <= P; k <<= 1) {
+        for (u32 j = k >> 1; j > 0; j >>= 1) {
+            for (u32 i = threadIdx.x; i < P / 2; i += LDS_NT) {
+                const u32 x = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+                const u32 y = x + j;
+                const bool up = (x & k) == 0;
+                const u16 sx = sseg[x], sy = sseg[y];
+                const u64 kx = skey[x], ky = skey[y];
+                const u32 vx = sval[x], vy = sval[y];
+                if (lds_greater(sx, kx, vx, sy, ky, vy) == up) {
+                    sseg[x] = sy; sseg[y] = sx;
+                    skey[x] = ky; skey[y] = kx;
+                    sval[x] = vy; sval[y] = vx;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (u32 e = threadIdx.x; e < cnt; e += LDS_NT) {
+        const u32 a = sseg[e];
+        const u32 first = spref[a];
+        const u32 pos = sbeg[a] + (e - first);
+        const u64 kb = skey[e];
+        vals[pos] = sval[e];
+        keys[pos] = kb;
+        if (plain || e == first) continue;
+        const u64 ka = skey[e - 1];
+        const u32 dep = sdep[a];
+        if (ka != kb) {
+            lcp[pos] = key_lcp(ka, kb, dep);
+            continue;
+        }
+        const u32 c8 = (u32)(kb & 0xFF);
+        if (c8 < 8) {
+            lcp[pos] = dep + c8;
+            continue;
+        }
+        const bool last = (e + 1 == spref[a + 1]) || skey[e + 1] != kb;
+        if (last) {
+            u32 x = first, y = e;  // first index in [first, e] with key == kb
+            while (x < y) { u32 m = (x + y) >> 1; if (skey[m] < kb) x = m + 1; else y = m; }
+            const u32 slot = atomicAdd(&ctr[C_NEXT], 1u);
+            next[slot] = Seg{sbeg[a] + (x - first), pos + 1, dep + 7, SEG_SKIP};
+        }
+    }
+}
+
+// ------------------------------------------------------------ host driver
+
+static int build_tiles(const Seg *segs, u32 nseg, u32 tile, u32 *tstart, void *scan_scratch,
+                       hipStream_t st, u32 *total)
+{
+    k_tile_counts<<<(unsigned)ceil_div(nseg, 256), 256, 0, st>>>(segs, nseg, tile, tstart);
+    SS_CHECK_LAUNCH();
+    SS_TRY(ss_scan_exclusive<u32>(tstart, tstart, nseg, (u32 *)scan_scratch, st));
+    return ss_read_u32(tstart + nseg, total, 1, st);
+}
+
+void sort_ws_layout(u64 n, SortWs *w, WsArena *a, WsCounter *c)
+{
+    // Capacities: segments hold >= 2 strings (<= n/2 of them); radix segments
+    // hold > 128 strings; radix tiles <= n/1024 + radix segments.
+    const u64 nseg = n / 2 + 2;
+    const u64 nlarge = n / 128 + 2;
+    const u64 ntiles = n / 1024 + nlarge + 2;
+    const u64 nscan = (256 * ntiles > nseg + 1 ? 256 * ntiles : nseg + 1) + 1;
+#define TAKE(field, T, cnt)                      \
+    do {                                          \
+        if (a) w->field = a->take<T>(cnt);        \
+        else c->take<T>(cnt);                     \
+    } while (0)
+    TAKE(keyA, u64, n);
+    TAKE(keyB, u64, n);
+    TAKE(valB, u32, n);
+    TAKE(lcp_scratch, u32, n);
+    TAKE(act, Seg, nseg);
+    TAKE(nxt, Seg, nseg);
+    TAKE(small, Seg, nseg);
+    TAKE(ident, Seg, nseg);
+    TAKE(largeA, Seg, nlarge);
+    TAKE(largeB, Seg, nlarge);
+    TAKE(bnd, uint2, n + 1);
+    TAKE(skipv, u32, nseg);
+    TAKE(smin, u64, nlarge);
+    TAKE(smax, u64, nlarge);
+    TAKE(scat, u8, nlarge);
+    TAKE(tstart, u32, nseg + 1);
+    TAKE(spref, u32, nseg + 1);
+    TAKE(hist, u32, nscan);
+    TAKE(scan_scratch, u64, ss_scan_scratch_elems<u64>(nscan));
+    TAKE(ctr, u32, C_NCTR);
+#undef TAKE
+}
+
+// Run rounds until no segment is unresolved.  The caller prepared w.act
+// (nact segments), the payload array `vals`, and in PLAIN mode the keys.
+int sort_rounds(const SortJob &J, SortWs &w, u32 nact)
+{
+    hipStream_t st = J.stream;
+    const u32 SM = (u32)g_small_max;
+    const u32 TL = (u32)g_tile;
+    u32 *lcp = J.lcp;
+    u32 h[C_NCTR];
+    while (nact > 0) {
+        SS_HIP(hipMemsetAsync(w.ctr, 0, sizeof(u32) * C_NCTR, st));
+        if (!J.plain) {
+            u32 ntile;
+            SS_TRY(build_tiles(w.act, nact, ETILE, w.tstart, w.scan_scratch, st, &ntile));
+            SS_HIP(hipMemsetAsync(w.skipv, 0xFF, sizeof(u32) * nact, st));
+            k_skip<<<ntile, NT, 0, st>>>(w.act, w.tstart, nact, J.bytes, J.N, J.off, J.vals, w.skipv);
+            SS_CHECK_LAUNCH();
+            k_keys<<<ntile, NT, 0, st>>>(w.act, w.tstart, nact, J.bytes, J.N, J.off, J.vals, w.skipv,
+                                          w.keyA);
+            SS_CHECK_LAUNCH();
+        }
+        k_classify<<<(unsigned)ceil_div(nact, 256), 256, 0, st>>>(w.act, nact, w.skipv, SM, w.small,
+                                                                   w.largeA, w.ctr);
+        SS_CHECK_LAUNCH();
+        SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, st));
+        u32 nlarge = h[C_LARGE];
+        Seg *LA = w.largeA, *LB = w.largeB;
+        while (nlarge > 0) {
+            u32 ntile;
+            SS_TRY(build_tiles(LA, nlarge, TL, w.tstart, w.scan_scratch, st, &ntile));
+            SS_HIP(hipMemsetAsync(w.smin, 0xFF, sizeof(u64) * nlarge, st));
+            SS_HIP(hipMemsetAsync(w.smax, 0, sizeof(u64) * nlarge, st));
+            k_hist<<<ntile, NT, 0, st>>>(LA, w.tstart, nlarge, TL, w.keyA, w.hist, w.smin, w.smax);
+            SS_CHECK_LAUNCH();
+            SS_TRY(ss_scan_exclusive<u32>(w.hist, w.hist, (u64)ntile * 256, (u32 *)w.scan_scratch, st));
+            SS_HIP(hipMemsetAsync(w.ctr + C_LARGE, 0, sizeof(u32), st));
+            EmitOut eo{w.small, LB, w.nxt, w.ident, w.bnd, w.ctr, w.scat, SM, J.plain};
+            k_emit<<<nlarge, 256, 0, st>>>(LA, w.tstart, nlarge, w.hist, w.smin, w.smax, eo);
+            SS_CHECK_LAUNCH();
+            k_scatter<<<ntile, NT, 0, st>>>(LA, w.tstart, nlarge, TL, w.hist, w.scat, w.keyA, J.vals,
+                                             w.keyB, w.valB);
+            SS_CHECK_LAUNCH();
+            k_copyback<<<ntile, NT, 0, st>>>(LA, w.tstart, nlarge, TL, w.scat, w.keyB, w.valB, w.keyA,
+                                              J.vals);
+            SS_CHECK_LAUNCH();
+            SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, st));
+            nlarge = h[C_LARGE];
+            Seg *tmp = LA; LA = LB; LB = tmp;
+        }
+        const u32 nsmall = h[C_SMALL];
+        if (nsmall > 0) {
+            k_sizes<<<(unsigned)ceil_div(nsmall, 256), 256, 0, st>>>(w.small, nsmall, w.spref);
+            SS_CHECK_LAUNCH();
+            SS_TRY(ss_scan_exclusive<u32>(w.spref, w.spref, nsmall, (u32 *)w.scan_scratch, st));
+            u32 tot;
+            SS_TRY(ss_read_u32(w.spref + nsmall, &tot, 1, st));
+            const u32 ntile = (u32)ceil_div(tot, SM);
+            k_lds_sort<<<ntile, LDS_NT, 0, st>>>(w.small, w.spref, nsmall, SM, w.keyA, J.vals, lcp, w.nxt,
+                                                  w.ctr, J.plain);
+            SS_CHECK_LAUNCH();
+        }
+        SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, st));
+        if (!J.plain) {
+            if (h[C_BND] > 0) {
+                k_boundary<<<(unsigned)ceil_div(h[C_BND], 256), 256, 0, st>>>(w.bnd, h[C_BND], w.keyA, lcp);
+                SS_CHECK_LAUNCH();
+            }
+            if (h[C_IDENT] > 0) {
+                u32 ntile;
+                SS_TRY(build_tiles(w.ident, h[C_IDENT], ETILE, w.tstart, w.scan_scratch, st, &ntile));
+                k_ident<<<ntile, NT, 0, st>>>(w.ident, w.tstart, h[C_IDENT], lcp);
+                SS_CHECK_LAUNCH();
+            }
+        }
+        nact = J.plain ? 0 : h[C_NEXT];
+        Seg *tmp = w.act; w.act = w.nxt; w.nxt = tmp;
+    }
+    return SS_OK;
+}
+
+// ------------------------------------------------------------ entry points
+
+__global__ void k_iota(u32 *p, u32 n)
+{
+    u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = i;
+}
+
+__global__ void k_init_single(Seg *act, u32 n, u32 *lcp)
+{
+    act[0] = Seg{0, n, 0, SEG_SKIP};
+    lcp[0] = 0;
+}
+
+__global__ void k_init_sets(const u64 *set_off, u32 nsets, Seg *act, u32 *ctr, u32 *lcp)
+{
+    u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    bool valid = j < nsets;
+    u32 b = 0, e = 0;
+    if (valid) {
+        b = (u32)set_off[j];
+        e = (u32)set_off[j + 1];
+        if (e > b) lcp[b] = 0;
+    }
+    bool two = valid && e > b + 1;
+    u32 a = wave_append(two, &ctr[0]);
+    if (two) act[a] = Seg{b, e, 0, SEG_SKIP};
+}
+
+__global__ void k_localize(const u64 *set_off, u32 nsets, u32 n, u32 *perm)
+{
+    u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // largest j with set_off[j] <= i
+    u32 lo = 0, hi = nsets;
+    while (hi - lo > 1) {
+        u32 mid = (lo + hi) >> 1;
+        if (set_off[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    perm[i] -= (u32)set_off[lo];
+}
+
+extern "C" size_t ss_sort_workspace(uint64_t n)
+{
+    WsCounter c;
+    SortWs w;
+    sort_ws_layout(n, &w, nullptr, &c);
+    return c.used;
+}
+
+static int sort_common_checks(const uint8_t *bytes, const uint64_t *offsets, uint64_t n, uint32_t *perm)
+{
+    if (n >= 0xFFFFFFFFull) {
+        ss_set_error("n = %llu exceeds the 32-bit index limit", (unsigned long long)n);
+        return SS_ERR_TOO_LARGE;
+    }
+    if (n > 0 && (!offsets || !perm)) {
+        ss_set_error("null offsets or perm");
+        return SS_ERR_INVALID_ARG;
+    }
+    (void)bytes;
+    return SS_OK;
+}
+
+extern "C" int ss_sort(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                       uint32_t *perm, uint32_t *lcp, void *ws, size_t ws_bytes, void *stream)
+{
+    ss_clear_error();
+    SS_TRY(sort_common_checks(bytes, offsets, n, perm));
+    if (n == 0) return SS_OK;
+    hipStream_t st = (hipStream_t)stream;
+    WsArena a(ws, ws_bytes);
+    SortWs w;
+    sort_ws_layout(n, &w, &a, nullptr);
+    if (a.overflow || !ws) {
+        ss_set_error("workspace too small: need %zu bytes", ss_sort_workspace(n));
+        return SS_ERR_WORKSPACE;
+    }
+    SortJob J{bytes, N, offsets, perm, lcp ? lcp : w.lcp_scratch, 0, st};
+    k_iota<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(perm, (u32)n);
+    SS_CHECK_LAUNCH();
+    k_init_single<<<1, 1, 0, st>>>(w.act, (u32)n, J.lcp);
+    SS_CHECK_LAUNCH();
+    return sort_rounds(J, w, n >= 2 ? 1 : 0);
+}
+
+extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                             const uint64_t *set_off, uint32_t num_sets, uint32_t *perm_local,
+                             uint32_t *lcp, void *ws, size_t ws_bytes, void *stream)
+{
+    ss_clear_error();
+    SS_TRY(sort_common_checks(bytes, offsets, n, perm_local));
+    if (num_sets == 0 || !set_off) {
+        ss_set_error("batch needs num_sets >= 1 and set_off");
+        return SS_ERR_INVALID_ARG;
+    }
+    if (n == 0) return SS_OK;
+    hipStream_t st = (hipStream_t)stream;
+    WsArena a(ws, ws_bytes);
+    SortWs w;
+    sort_ws_layout(n, &w, &a, nullptr);
+    if (a.overflow || !ws) {
+        ss_set_error("workspace too small: need %zu bytes", ss_sort_workspace(n));
+        return SS_ERR_WORKSPACE;
+    }
+    SortJob J{bytes, N, offsets, perm_local, lcp ? lcp : w.lcp_scratch, 0, st};
+    k_iota<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(perm_local, (u32)n);
+    SS_CHECK_LAUNCH();
+    SS_HIP(hipMemsetAsync(w.ctr, 0, sizeof(u32) * C_NCTR, st));
+    k_init_sets<<<(unsigned)ceil_div(num_sets, 256), 256, 0, st>>>(set_off, num_sets, w.act, w.ctr, J.lcp);
+    SS_CHECK_LAUNCH();
+    u32 nact;
+    SS_TRY(ss_read_u32(w.ctr, &nact, 1, st));
+    SS_TRY(sort_rounds(J, w, nact));
+    k_localize<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(set_off, num_sets, (u32)n, perm_local);
+    SS_CHECK_LAUNCH();
+    return SS_OK;
+}

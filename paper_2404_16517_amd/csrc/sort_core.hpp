@@ -1,0 +1,38 @@
+// Segmented sort machinery shared by the string sort and the duplicate
+// detection of prefix doubling.
+#pragma once
+#include "common.hpp"
+
+// A contiguous range [begin, end) of sorted positions whose strings share a
+// known prefix of `depth` bytes.  aux: bits 0..3 = current key byte of a radix
+// pass, bit 4 = compute the common-prefix skip first.
+struct Seg {
+    u32 begin, end, depth, aux;
+};
+enum { SEG_SKIP = 16 };
+
+struct SortWs {
+    u64 *keyA, *keyB;
+    u32 *valB, *lcp_scratch;
+    Seg *act, *nxt, *small, *ident, *largeA, *largeB;
+    uint2 *bnd;
+    u32 *skipv;
+    u64 *smin, *smax;
+    u8 *scat;
+    u32 *tstart, *spref, *hist;
+    u64 *scan_scratch;
+    u32 *ctr;
+};
+
+struct SortJob {
+    const u8 *bytes;
+    u64 N;
+    const u64 *off;
+    u32 *vals;  // payload: input indices (string sort) or any 32-bit payload (PLAIN)
+    u32 *lcp;   // LCP output (string sort)
+    int plain;  // 1: sort raw 64-bit keys in keyA, no LCP, single round
+    hipStream_t stream;
+};
+
+void sort_ws_layout(u64 n, SortWs *w, WsArena *a, WsCounter *c);
+int sort_rounds(const SortJob &J, SortWs &w, u32 nact);

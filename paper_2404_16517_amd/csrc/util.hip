@@ -1,0 +1,191 @@
+// Error state, host read-back, tuning and device-wide exclusive scans.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "common.hpp"
+
+static thread_local char g_err[512];
+
+void ss_set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void ss_clear_error() { g_err[0] = 0; }
+
+extern "C" const char *ss_last_error(void) { return g_err; }
+extern "C" int ss_version(void) { return 100; }
+
+int g_small_max = 1024;
+int g_tile = 4096;
+
+extern "C" int ss_set_tuning(int param, int value)
+{
+    if (param == SS_TUNE_SMALL_MAX) {
+        if (value != 128 && value != 256 && value != 512 && value != 1024) {
+            ss_set_error("SS_TUNE_SMALL_MAX must be 128, 256, 512 or 1024");
+            return SS_ERR_INVALID_ARG;
+        }
+        int old = g_small_max;
+        g_small_max = value;
+        return old;
+    }
+    if (param == SS_TUNE_TILE) {
+        if (value < 1024 || value > 16384 || (value & (value - 1))) {
+            ss_set_error("SS_TUNE_TILE must be a power of two in [1024, 16384]");
+            return SS_ERR_INVALID_ARG;
+        }
+        int old = g_tile;
+        g_tile = value;
+        return old;
+    }
+    ss_set_error("unknown tuning parameter %d", param);
+    return SS_ERR_INVALID_ARG;
+}
+
+int ss_read_u32(const u32 *dev, u32 *host, int count, hipStream_t s)
+{
+    SS_HIP(hipMemcpyAsync(host, dev, sizeof(u32) * count, hipMemcpyDeviceToHost, s));
+    SS_HIP(hipStreamSynchronize(s));
+    return SS_OK;
+}
+
+int ss_read_u64(const u64 *dev, u64 *host, int count, hipStream_t s)
+{
+    SS_HIP(hipMemcpyAsync(host, dev, sizeof(u64) * count, hipMemcpyDeviceToHost, s));
+    SS_HIP(hipStreamSynchronize(s));
+    return SS_OK;
+}
+
+// ---------------------------------------------------------------- scans
+//
+// Three phases: per-block sums, one-workgroup scan of the block sums, then a
+// per-block scan that adds the block's offset.  Blocks hold SCAN_ITEMS items.
+
+#define SCAN_NT 256
+#define SCAN_PER 16
+#define SCAN_ITEMS (SCAN_NT * SCAN_PER)
+
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T x)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan of one value per thread over a workgroup of NT threads.
+template <class T, int NT>
+__device__ __forceinline__ T block_excl_scan(T v, T *total)
+{
+    __shared__ T wsum[NT / 64 + 1];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    T x = wave_incl_scan(v);
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T s = 0;
+        for (int w = 0; w < NT / 64; w++) {
+            T t = wsum[w];
+            wsum[w] = s;
+            s += t;
+        }
+        wsum[NT / 64] = s;
+    }
+    __syncthreads();
+    T r = x - v + wsum[wid];
+    *total = wsum[NT / 64];
+    __syncthreads();
+    return r;
+}
+
+template <class T>
+__global__ __launch_bounds__(SCAN_NT) void k_scan_reduce(const T *in, u64 n, T *sums)
+{
+    const u64 b0 = (u64)blockIdx.x * SCAN_ITEMS;
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; k++) {
+        u64 i = b0 + (u64)k * SCAN_NT + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    T tot;
+    block_excl_scan<T, SCAN_NT>(s, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+template <class T>
+__global__ __launch_bounds__(1024) void k_scan_single(T *sums, u64 nb)
+{
+    // each thread owns a contiguous chunk of the block sums
+    const u64 per = (nb + 1023) / 1024;
+    const u64 c0 = threadIdx.x * per, c1 = (c0 + per < nb) ? c0 + per : nb;
+    T s = 0;
+    for (u64 i = c0; i < c1; i++) s += sums[i];
+    T tot;
+    T pre = block_excl_scan<T, 1024>(s, &tot);
+    for (u64 i = c0; i < c1; i++) {
+        T v = sums[i];
+        sums[i] = pre;
+        pre += v;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(SCAN_NT) void k_scan_apply(const T *in, T *out, u64 n, const T *sums)
+{
+    const u64 b0 = (u64)blockIdx.x * SCAN_ITEMS;
+    // thread t owns items b0 + t*SCAN_PER .. (+SCAN_PER): blocked layout
+    T v[SCAN_PER];
+    T s = 0;
+    const u64 i0 = b0 + (u64)threadIdx.x * SCAN_PER;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; k++) {
+        u64 i = i0 + k;
+        v[k] = (i < n) ? in[i] : (T)0;
+        s += v[k];
+    }
+    T tot;
+    T pre = block_excl_scan<T, SCAN_NT>(s, &tot) + sums[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; k++) {
+        u64 i = i0 + k;
+        if (i < n) out[i] = pre;
+        pre += v[k];
+        if (i + 1 == n) out[n] = pre;
+    }
+}
+
+template <class T> __global__ void k_zero_one(T *out) { out[0] = 0; }
+
+template <class T> u64 ss_scan_scratch_elems(u64 n) { return ceil_div(n, SCAN_ITEMS) + 1; }
+
+template <class T> int ss_scan_exclusive(const T *in, T *out, u64 n, T *scratch, hipStream_t s)
+{
+    if (n == 0) {
+        k_zero_one<T><<<1, 1, 0, s>>>(out);
+        SS_CHECK_LAUNCH();
+        return SS_OK;
+    }
+    const u64 nb = ceil_div(n, SCAN_ITEMS);
+    k_scan_reduce<T><<<(unsigned)nb, SCAN_NT, 0, s>>>(in, n, scratch);
+    SS_CHECK_LAUNCH();
+    k_scan_single<T><<<1, 1024, 0, s>>>(scratch, nb);
+    SS_CHECK_LAUNCH();
+    k_scan_apply<T><<<(unsigned)nb, SCAN_NT, 0, s>>>(in, out, n, scratch);
+    SS_CHECK_LAUNCH();
+    return SS_OK;
+}
+
+template u64 ss_scan_scratch_elems<u32>(u64);
+template u64 ss_scan_scratch_elems<u64>(u64);
+template int ss_scan_exclusive<u32>(const u32 *, u32 *, u64, u32 *, hipStream_t);
+template int ss_scan_exclusive<u64>(const u64 *, u64 *, u64, u64 *, hipStream_t);

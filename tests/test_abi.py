@@ -1,0 +1,69 @@
+"""Host-only checks of the C-ABI library: it loads without a GPU, exports every
+entry point declared in include/strsort.h, and its argument checks fail
+cleanly (these calls return before touching a device)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2404_16517_amd as ss
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "strsort.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ss_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 20
+    L = ss.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_version_and_error_text():
+    assert ss.lib().ss_version() >= 100
+    assert isinstance(ss.lib().ss_last_error(), bytes)
+
+
+def test_workspace_queries_grow_with_n():
+    L = ss.lib()
+    for f in ("ss_sort_workspace", "ss_dist_prefix_workspace", "ss_partition_encode_workspace",
+              "ss_fc_decode_workspace", "ss_gather_workspace"):
+        a, b = getattr(L, f)(1000), getattr(L, f)(1_000_000)
+        assert 0 < a < b, f
+    assert L.ss_lcp_merge_workspace(1000, 10**6) > L.ss_lcp_merge_workspace(1000, 0)
+
+
+def test_argument_errors_without_device():
+    L = ss.lib()
+    P = ctypes.c_void_p
+    # n beyond the 32-bit limit
+    assert L.ss_sort(None, 0, None, 1 << 33, None, None, None, 0, None) == -3
+    # null perm with n > 0
+    assert L.ss_sort(None, 0, P(8), 10, None, None, None, 0, None) == -1
+    assert b"null" in L.ss_last_error()
+    # bad init_len / hash_bits
+    assert L.ss_dist_prefix(None, 0, P(8), 10, 6, 64, P(8), None, None, 0, None) == -1
+    assert L.ss_dist_prefix(None, 0, P(8), 10, 8, 4, P(8), None, None, 0, None) == -1
+    # workspace too small is reported before any launch
+    assert L.ss_dist_prefix(None, 0, P(8), 10, 8, 64, P(8), None, P(8), 16, None) == -2
+    assert L.ss_sort(None, 0, P(8), 10, P(8), None, P(8), 16, None) == -2
+    # select_splitters needs r >= 1 and n >= 1
+    assert L.ss_select_splitters(0, P(8), 4, P(8), None) == -1
+    # merge needs 1 <= k <= 65536
+    assert L.ss_lcp_merge(0, P(8), P(8), P(8), P(8), P(8), P(8), 1, P(8), P(8), P(8), None, 0, None) == -1
+
+
+def test_tuning_validation():
+    assert ss.set_tuning(ss.SS_TUNE_SMALL_MAX, 512) == 1024
+    assert ss.set_tuning(ss.SS_TUNE_SMALL_MAX, 1024) == 512
+    with pytest.raises(ss.StrsortError):
+        ss.set_tuning(ss.SS_TUNE_SMALL_MAX, 300)
+    with pytest.raises(ss.StrsortError):
+        ss.set_tuning(ss.SS_TUNE_TILE, 3000)

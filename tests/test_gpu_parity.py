@@ -1,0 +1,311 @@
+"""GPU parity: every entry point of the C-ABI against the CPU oracle, bit-exact.
+
+Inputs are seeded synthetic workloads (synth) and hand-picked edge sets.
+All comparisons are integer and exact (tolerance 0).
+"""
+import os
+import random
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2404_16517_amd as ss
+import synth
+from tests import closed_forms as cf
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+EDGE_SETS = {
+    "n1": [b"HELLO"],
+    "n2_equal": [b"AB", b"AB"],
+    "n2": [b"B", b"A"],
+    "empty_strings": [b"", b"", b"A", b""],
+    "all_equal": [b"SAME" * 5] * 300,
+    "prefix_chain": [b"A" * k for k in range(40, 0, -1)] + [b""],
+    "word_boundaries": [bytes([65 + (i % 3)]) * L for i, L in enumerate([7, 8, 9, 15, 16, 17, 6, 14, 1, 0, 23, 24, 25])],
+    "zero_ff": [b"\x00", b"\x00\x00", b"", b"\xff", b"\xff\x00", b"\x00\xff", b"A\x00", b"A", b"A\x00\x00"],
+    "long_among_short": [b"Q" * 4096 + b"Z"] + [b"Q" * k for k in range(1, 60)] + [b"Q" * 4096 + b"A"],
+    "deep_shared": [b"P" * 300 + bytes([65 + (i * 7) % 26]) + b"X" * (i % 5) for i in range(500)],
+}
+
+
+def _rand_strings(rng, n, alphabet, max_len):
+    return [bytes(rng.choice(alphabet) for _ in range(rng.randint(0, max_len))) for _ in range(n)]
+
+
+def _check_sort(s: synth.StringSet, name=""):
+    _log(f"[sort] {name} n={s.n} N={s.N}")
+    g = s.to(DEV)
+    perm, lcp = ss.sort(g.bytes, g.offsets)
+    torch.cuda.synchronize()
+    b, o = oracle.strings_np(s)
+    p_ref = oracle.sort(b, o)
+    np.testing.assert_array_equal(u32(perm), p_ref)
+    np.testing.assert_array_equal(u32(lcp), oracle.lcp(b, o, p_ref))
+    return g, perm, lcp, b, o, p_ref
+
+
+@pytest.mark.parametrize("name", sorted(EDGE_SETS))
+def test_sort_lcp_dist_edge_sets(name):
+    s = synth.from_list(EDGE_SETS[name])
+    g, perm, lcp, b, o, p_ref = _check_sort(s, name)
+    d = ss.dist_exact(g.offsets, perm, lcp)
+    lcp_ref = oracle.lcp(b, o, p_ref)
+    np.testing.assert_array_equal(u32(d), oracle.dist_exact(o, p_ref, lcp_ref))
+    l2 = ss.lcp(g.bytes, g.offsets, perm)
+    np.testing.assert_array_equal(u32(l2), lcp_ref)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_sort_random_small_alphabets(seed):
+    rng = random.Random(seed)
+    alpha = [(0, 1, 255), (65, 66), tuple(range(256)), (0,)][seed % 4]
+    strs = _rand_strings(rng, rng.choice([5, 100, 3000, 20000]), alpha, rng.choice([3, 12, 40]))
+    _check_sort(synth.from_list(strs), f"random seed={seed}")
+
+
+def test_sort_empty_input():
+    g = synth.from_list([]).to(DEV)
+    perm, lcp = ss.sort(g.bytes, g.offsets)
+    assert perm.numel() == 0
+
+
+@pytest.mark.parametrize("tune", [(128, 1024), (256, 2048), (1024, 4096), (512, 16384)])
+def test_sort_tuning_variants_same_result(tune):
+    sm, tile = tune
+    old_sm = ss.set_tuning(ss.SS_TUNE_SMALL_MAX, sm)
+    old_t = ss.set_tuning(ss.SS_TUNE_TILE, tile)
+    try:
+        s = synth.text_strings(60_000, seed=4, median=12)
+        _check_sort(s, f"tuning {tune}")
+    finally:
+        ss.set_tuning(ss.SS_TUNE_SMALL_MAX, old_sm)
+        ss.set_tuning(ss.SS_TUNE_TILE, old_t)
+
+
+def test_sort_c0_closed_form_and_oracle():
+    """C0: 100,000 x 100 B, D/N 0.5."""
+    s = synth.dn_strings(100_000, 100, 0.5, seed=0)
+    g, perm, lcp, b, o, p_ref = _check_sort(s, "C0")
+    pi = s.meta["pi"].numpy()
+    np.testing.assert_array_equal(u32(perm), cf.dn_perm(pi))
+    np.testing.assert_array_equal(u32(lcp), cf.dn_lcp(s.n, s.meta["k"], s.meta["filler"]))
+    d = ss.dist_exact(g.offsets, perm, lcp)
+    np.testing.assert_array_equal(u32(d)[u32(perm)], cf.dn_dist_sorted(s.n, s.meta["k"], s.meta["filler"], 100))
+
+
+def test_sort_text_with_duplicates():
+    s = synth.text_strings(200_000, seed=1)
+    _check_sort(s, "text 200k")
+
+
+def test_sort_batch_equals_single_sorts():
+    sets, bounds = synth.random_sets(64, 10, 3000, seed=3)
+    _log(f"[batch] n={sets.n}")
+    g = sets.to(DEV)
+    perm, lcp = ss.sort_batch(g.bytes, g.offsets, bounds.to(DEV))
+    torch.cuda.synchronize()
+    P, Lc = u32(perm), u32(lcp)
+    b, o = oracle.strings_np(sets)
+    for j in range(64):
+        a, e = int(bounds[j]), int(bounds[j + 1])
+        sub_o = (o[a:e + 1] - o[a]).astype(np.uint64)
+        sub_b = b[int(o[a]):int(o[e])]
+        pr = oracle.sort(sub_b, sub_o)
+        np.testing.assert_array_equal(P[a:e], pr)
+        np.testing.assert_array_equal(Lc[a:e], oracle.lcp(sub_b, sub_o, pr))
+
+
+def test_sort_batch_with_empty_and_single_sets():
+    strs = [b"C", b"A", b"B", b"Z", b"Y", b"Y"]
+    s = synth.from_list(strs)
+    bounds = torch.tensor([0, 0, 3, 3, 4, 6, 6], dtype=torch.int64)
+    g = s.to(DEV)
+    perm, lcp = ss.sort_batch(g.bytes, g.offsets, bounds.to(DEV))
+    assert list(u32(perm)) == [1, 2, 0, 0, 0, 1]
+    assert list(u32(lcp)) == [0, 0, 0, 0, 0, 1]
+
+
+# ------------------------------------------------------------- prefix doubling
+
+def test_prefix_keys_match_golden_vectors():
+    path = os.path.join(os.path.dirname(__file__), "golden", "kr_vectors.txt")
+    data, keys = [], []
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        h, k = line.split()
+        data.append(bytes.fromhex(h) if h != "-" else b"")
+        keys.append(int(k, 16))
+    g = synth.from_list(data).to(DEV)
+    got = u64(ss.prefix_keys(g.bytes, g.offsets, 0xFFFFFFFF, 64))
+    assert [int(x) for x in got] == keys
+
+
+@pytest.mark.parametrize("m", [0, 1, 4, 7, 8, 9, 16, 33])
+def test_prefix_keys_truncated_match_oracle(m):
+    s = synth.text_strings(500, seed=9, median=20)
+    strs = s.as_list()
+    g = s.to(DEV)
+    got = u64(ss.prefix_keys(g.bytes, g.offsets, m, 64))
+    exp = [oracle.kr_key(x[:m]) for x in strs]
+    assert [int(x) for x in got] == exp
+
+
+@pytest.mark.parametrize("case", ["c0", "text", "text_bits12", "text_bits8", "edge"])
+def test_dist_prefix_matches_oracle(case):
+    if case == "c0":
+        s, bits = synth.dn_strings(100_000, 100, 0.5, seed=0), 64
+    elif case == "edge":
+        s, bits = synth.from_list(EDGE_SETS["prefix_chain"] + EDGE_SETS["zero_ff"] + EDGE_SETS["all_equal"]), 64
+    else:
+        s = synth.text_strings(100_000, seed=2)
+        bits = {"text": 64, "text_bits12": 12, "text_bits8": 8}[case]
+    _log(f"[dist_prefix] {case} n={s.n}")
+    g = s.to(DEV)
+    d, rounds = ss.dist_prefix(g.bytes, g.offsets, 8, bits)
+    b, o = oracle.strings_np(s)
+    ref, r_ref, coll = oracle.dist_prefix(b, o, 8, bits)
+    np.testing.assert_array_equal(u32(d), ref)
+    assert rounds == r_ref
+
+
+# ---------------------------------------------------------- partition / coding
+
+def _partition(s, r, pdms):
+    g = s.to(DEV)
+    perm, lcp = ss.sort(g.bytes, g.offsets)
+    dist = ss.dist_prefix(g.bytes, g.offsets, 8, 64)[0] if pdms else None
+    ids = ss.select_splitters(perm, r)
+    sb, so = ss.gather_strings(g.bytes, g.offsets, ids)
+    fc = ss.partition_encode(g.bytes, g.offsets, perm, lcp, dist, sb, so)
+    torch.cuda.synchronize()
+    return g, perm, lcp, dist, ids, sb, so, fc
+
+
+@pytest.mark.parametrize("pdms", [False, True])
+@pytest.mark.parametrize("r", [1, 2, 16, 300])
+def test_partition_encode_matches_oracle(pdms, r):
+    s = synth.text_strings(30_000, seed=5, median=20)
+    _log(f"[partition] r={r} pdms={pdms}")
+    g, perm, lcp, dist, ids, sb, so, fc = _partition(s, r, pdms)
+    b, o = oracle.strings_np(s)
+    p_ref = oracle.sort(b, o)
+    l_ref = oracle.lcp(b, o, p_ref)
+    d_ref = oracle.dist_prefix(b, o, 8, 64)[0] if pdms else None
+    np.testing.assert_array_equal(u32(ids), oracle.select_splitters(s.n, p_ref, r))
+    strs = s.as_list()
+    spl = synth.from_list([strs[i] for i in oracle.select_splitters(s.n, p_ref, r)])
+    assert bytes(sb.cpu().numpy()) == bytes(spl.bytes.numpy())
+    sbn, son = oracle.strings_np(spl)
+    bounds = oracle.bucket_bounds(b, o, p_ref, sbn, son)
+    np.testing.assert_array_equal(u64(fc["run_off"]), bounds)
+    ref = oracle.fc_encode(b, o, p_ref, l_ref, d_ref, bounds)
+    np.testing.assert_array_equal(u32(fc["lcp"]), ref["lcp"])
+    np.testing.assert_array_equal(u32(fc["len"]), ref["len"])
+    np.testing.assert_array_equal(u32(fc["id"]), ref["id"])
+    np.testing.assert_array_equal(u64(fc["suf_off"]), ref["suf_off"])
+    assert bytes(fc["suf"].cpu().numpy()) == bytes(ref["suf"])
+    # decode on the GPU == oracle decode
+    db, doff = ss.fc_decode(fc["run_off"], fc["lcp"], fc["len"], fc["suf_off"], fc["suf"])
+    rb, roff = oracle.fc_decode(bounds, ref["lcp"], ref["len"], ref["suf_off"], ref["suf"])
+    np.testing.assert_array_equal(u64(doff), roff)
+    assert bytes(db.cpu().numpy()) == bytes(rb)
+
+
+def test_bucket_bounds_with_external_splitters():
+    s = synth.text_strings(20_000, seed=6, median=8)
+    strs = s.as_list()
+    rng = random.Random(6)
+    spl = sorted(rng.sample(strs, 40) + [b"", b"\xff\xff", strs[0], strs[0]])
+    g = s.to(DEV)
+    perm, _ = ss.sort(g.bytes, g.offsets)
+    sp = synth.from_list(spl).to(DEV)
+    got = ss.bucket_bounds(g.bytes, g.offsets, perm, sp.bytes, sp.offsets)
+    b, o = oracle.strings_np(s)
+    sbn, son = oracle.strings_np(synth.from_list(spl))
+    np.testing.assert_array_equal(u64(got), oracle.bucket_bounds(b, o, oracle.sort(b, o), sbn, son))
+
+
+# ----------------------------------------------------------------------- merge
+
+def _runs_from_oracle(s, k, seed, pdms=False):
+    """k sorted front-coded runs built by the oracle from a random split."""
+    rng = np.random.default_rng(seed)
+    b, o = oracle.strings_np(s)
+    strs = s.as_list()
+    assign = rng.integers(0, k, size=s.n)
+    parts = []
+    for j in range(k):
+        idx = np.nonzero(assign == j)[0]
+        sub = synth.from_list([strs[i] for i in idx])
+        sb, so = oracle.strings_np(sub)
+        p = oracle.sort(sb, so)
+        lc = oracle.lcp(sb, so, p)
+        d = oracle.dist_prefix(sb, so, 8, 64)[0] if pdms else None
+        enc = oracle.fc_encode(sb, so, p, lc, d, np.array([0, sub.n], np.uint64))
+        enc["id"] = idx[enc["id"]].astype(np.uint32)
+        parts.append(enc)
+    run_off = np.zeros(k + 1, np.uint64)
+    for j, e in enumerate(parts):
+        run_off[j + 1] = run_off[j] + len(e["lcp"])
+    lcp_ = np.concatenate([e["lcp"] for e in parts])
+    len_ = np.concatenate([e["len"] for e in parts])
+    id_ = np.concatenate([e["id"] for e in parts])
+    suf = np.concatenate([e["suf"] for e in parts]) if parts else np.zeros(0, np.uint8)
+    suf_off = np.zeros(s.n + 1, np.uint64)
+    base, pos = 0, 0
+    for e in parts:
+        m = len(e["lcp"])
+        suf_off[pos:pos + m] = e["suf_off"][:m] + base
+        base += int(e["suf_off"][m])
+        pos += m
+    suf_off[s.n] = base
+    return run_off, lcp_, len_, id_, suf_off, suf
+
+
+@pytest.mark.parametrize("k,seed,pdms", [(1, 0, False), (2, 1, False), (7, 2, False), (64, 3, False),
+                                         (16, 4, True)])
+def test_lcp_merge_matches_oracle(k, seed, pdms):
+    s = synth.text_strings(12_000, seed=20 + seed, median=10)
+    _log(f"[merge] k={k}")
+    ro, lc, ln, idv, so, suf = _runs_from_oracle(s, k, seed, pdms)
+    T = lambda a, dt: torch.from_numpy(a.view(dt).copy()).to(DEV)
+    src, gid, glcp = ss.lcp_merge(T(ro, np.int64), T(lc, np.int32), T(ln, np.int32), T(idv, np.int32),
+                                  T(so, np.int64), torch.from_numpy(suf.copy()).to(DEV))
+    torch.cuda.synchronize()
+    rsrc, rid, rlcp = oracle.merge(ro, lc, ln, idv, so, suf)
+    np.testing.assert_array_equal(u64(src), rsrc)
+    np.testing.assert_array_equal(u32(gid), rid)
+    np.testing.assert_array_equal(u32(glcp), rlcp)
+
+
+def test_lcp_merge_dn_closed_form():
+    """C3b shape scaled down: DN strings of 64 B with D/N 0.3 in 32 runs."""
+    n = 40_000
+    s = synth.dn_strings(n, 64, 0.3, seed=7)
+    ro, lc, ln, idv, so, suf = _runs_from_oracle(s, 32, 7)
+    T = lambda a, dt: torch.from_numpy(a.view(dt).copy()).to(DEV)
+    _, gid, glcp = ss.lcp_merge(T(ro, np.int64), T(lc, np.int32), T(ln, np.int32), T(idv, np.int32),
+                                T(so, np.int64), torch.from_numpy(suf.copy()).to(DEV))
+    pi = s.meta["pi"].numpy()
+    np.testing.assert_array_equal(u32(gid), cf.dn_perm(pi))
+    np.testing.assert_array_equal(u32(glcp), cf.dn_lcp(n, s.meta["k"], s.meta["filler"]))
