@@ -1,14 +1,24 @@
 """Benchmark of the one-GPU string-sorting hot path (prints ONE JSON line).
 
-Workload (default): 16,000,000 strings x 500 bytes over 'A'..'Z' with D/N ratio
-0.5 (the paper's DNData shape; N = 8.0 GB), resident in HBM.
+Workload (default): 16,000,000 strings x 500 bytes over 'A'..'Z' with D/N
+ratio 0.5 (the paper's DNData shape; N = 8.0 GB), resident in HBM.
 
-One step = the whole hot path over that input:
-  sort + LCP array -> exact distinguishing prefixes -> prefix doubling
-  (hash rounds + duplicate detection) -> r = 256 splitters, bucket bounds and
-  front coding of the distinguishing prefixes -> LCP-aware merge of the r
-  front-coded runs back into one sorted order.
-value = N / (seconds per step) in GB/s ("string bytes sorted per second").
+One step = the paper's single-level prefix-doubling merge sort (Section 3 with
+k = 1, prefix doubling of Section 4) executed for p virtual processing elements
+on one GPU; PE i holds the i-th 1/p of the input, and the exchange between
+PEs is replaced by runs that already sit in HBM:
+  1. approximate distinguishing prefixes by prefix doubling (hash rounds +
+     duplicate detection over all strings),
+  2. every PE sorts its array and builds its LCP array (one batched launch),
+  3. regular sampling with sampling factor v = 2: v+1 samples per PE, sorted,
+     splitters f_j = V[j|V|/p - 1],
+  4. every PE splits its array into p buckets and front-codes the
+     distinguishing prefixes of each bucket,
+  5. bucket j merges the p runs it receives with the LCP-aware merge (all p
+     merges in one call),
+  6. exact distinguishing prefixes of the final order (after joining the LCPs
+     across bucket boundaries).
+value = N / (seconds per step), in GB/s ("string bytes sorted per second").
 """
 from __future__ import annotations
 
@@ -21,6 +31,171 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+HBM_PEAK_GBS = 8000.0
+
+
+class Pipeline:
+    def __init__(self, B, O, p, v, ss, torch):
+        self.B, self.O, self.p, self.v, self.ss, self.torch = B, O, p, v, ss, torch
+        dev = B.device
+        n = O.numel() - 1
+        self.n = n
+        self.bounds = [n * i // p for i in range(p + 1)]
+        self.set_off = torch.tensor(self.bounds, dtype=torch.int64, device=dev)
+        # chunk start of every position (to turn PE-local indices into global ones)
+        sizes = torch.tensor([self.bounds[i + 1] - self.bounds[i] for i in range(p)], device=dev)
+        self.pos_base = torch.repeat_interleave(self.set_off[:-1].to(torch.int32), sizes)
+        self.ws_sort = torch.empty(ss.lib().ss_sort_workspace(n), dtype=torch.uint8, device=dev)
+        self.ws_pd = torch.empty(ss.lib().ss_dist_prefix_workspace(n), dtype=torch.uint8, device=dev)
+        self.ws_merge = torch.empty(ss.lib().ss_lcp_merge_workspace(n, n, p * p), dtype=torch.uint8, device=dev)
+        i32 = lambda: torch.empty(n, dtype=torch.int32, device=dev)
+        # shared front-coded arrays: PE i writes positions [bounds[i], bounds[i+1])
+        self.fc = dict(lcp=i32(), len=i32(), id=i32(), suf_off=torch.empty(n + 1, dtype=torch.int64, device=dev),
+                       suf=torch.empty(B.numel() + 16, dtype=torch.uint8, device=dev))
+        self.run_offs = [torch.empty(p + 1, dtype=torch.int64, device=dev) for _ in range(p)]
+        self.group_off = torch.arange(0, p * p + 1, p, dtype=torch.int32, device=dev)
+        self.byte_base = O[torch.tensor(self.bounds, device=dev)].tolist()
+
+    def step(self, marks):
+        ss, torch, B, O, p = self.ss, self.torch, self.B, self.O, self.p
+        ev = marks.mark
+        # 1. prefix doubling over all strings
+        dpx, rounds = ss.dist_prefix(B, O, 8, 64, ws=self.ws_pd)
+        ev("dist_prefix")
+        # 2. every PE sorts its array (+ LCP), one batched launch sequence
+        perm_l, lcp = ss.sort_batch(B, O, self.set_off, ws=self.ws_sort)
+        perm = perm_l + self.pos_base
+        ev("sort_batch+lcp")
+        # 3. regular sampling (v+1 samples per PE) and splitters
+        samp = torch.cat([ss.select_splitters(perm[a:b], self.v + 2)
+                          for a, b in zip(self.bounds[:-1], self.bounds[1:])])
+        sb, so = ss.gather_strings(B, O, samp)
+        sperm, _ = ss.sort(sb, so, with_lcp=False)
+        fid = ss.select_splitters(sperm, p)
+        fb, fo = ss.gather_strings(sb, so, fid)
+        ev("splitters")
+        # 4. buckets + front coding of the distinguishing prefixes, per PE
+        for i in range(p):
+            a, b = self.bounds[i], self.bounds[i + 1]
+            out = dict(run_off=self.run_offs[i], lcp=self.fc["lcp"][a:b], len=self.fc["len"][a:b],
+                       id=self.fc["id"][a:b], suf_off=self.fc["suf_off"][a:b + 1], suf=self.fc["suf"])
+            ss.partition_encode(B, O, perm[a:b], lcp[a:b], dpx, fb, fo, out=out, suf_base=self.byte_base[i], n=b - a)
+        ev("partition_encode")
+        # 5. bucket j merges run (i, j) of every PE i: all p merges in one call
+        ro = torch.stack(self.run_offs) + self.set_off[:-1, None]      # [PE, bucket+1] absolute
+        run_begin = ro[:, :-1].t().reshape(-1)                          # group j = bucket j, run i = PE i
+        run_end = ro[:, 1:].t().reshape(-1)
+        src, order, mlcp = ss.lcp_merge(run_begin, run_end, self.group_off, self.fc["lcp"], self.fc["len"],
+                                        self.fc["id"], self.fc["suf_off"], self.fc["suf"], ws=self.ws_merge)
+        ev("lcp_merge")
+        # 6. LCPs across bucket boundaries, exact distinguishing prefixes
+        sizes = (run_end - run_begin).view(p, p).sum(1)
+        starts = torch.cumsum(sizes, 0)[:-1]
+        starts = starts[(starts > 0) & (starts < self.n)]
+        if starts.numel():
+            pairs = torch.stack([order[starts - 1], order[starts]], 1).reshape(-1).contiguous()
+            pl = ss.lcp(B, O, pairs)
+            mlcp[starts] = pl.view(-1, 2)[:, 1]
+        dist = ss.dist_exact(O, order, mlcp)
+        ev("dist_exact")
+        return order, mlcp, dist, dpx, rounds
+
+
+class Marks:
+    def __init__(self, torch, record):
+        self.torch, self.record, self.ev = torch, record, []
+        if record:
+            self.mark("start")
+
+    def mark(self, name):
+        if self.record:
+            e = self.torch.cuda.Event(enable_timing=True)
+            e.record()
+            self.ev.append((name, e))
+
+    def times(self):
+        return {b: ea.elapsed_time(eb) for (a, ea), (b, eb) in zip(self.ev[:-1], self.ev[1:])}
+
+
+def verify_dn(s, order, mlcp, dist, dpx):
+    """Closed forms of the D/N workload (sorted order, LCP, dist, prefix doubling)."""
+    import numpy as np
+    from tests import closed_forms as cf
+    n, L = s.n, s.meta["length"]
+    k, F = s.meta["k"], s.meta["filler"]
+    pi = s.meta["pi"].numpy()
+    perm_ref = cf.dn_perm(pi)
+    ok = np.array_equal(order.cpu().numpy().view(np.uint32), perm_ref)
+    ok &= np.array_equal(mlcp.cpu().numpy().view(np.uint32), cf.dn_lcp(n, k, F))
+    d_sorted = cf.dn_dist_sorted(n, k, F, L)
+    ok &= np.array_equal(dist.cpu().numpy().view(np.uint32)[perm_ref], d_sorted)
+    d_in = np.empty(n, np.uint32)
+    d_in[perm_ref] = d_sorted
+    ok &= np.array_equal(dpx.cpu().numpy().view(np.uint32), cf.doubling_closed_form(d_in, np.full(n, L), 8))
+    return bool(ok)
+
+
+def cpu_baseline(s_host, p, v, target_s=15.0):
+    """The CPU oracle running the same step on a bounded prefix of the input."""
+    import numpy as np
+    import oracle
+    b_all, o_all = oracle.strings_np(s_host)
+
+    def run(ns):
+        o = o_all[:ns + 1].copy()
+        b = b_all[:int(o[-1])]
+        bounds = [ns * i // p for i in range(p + 1)]
+        t0 = time.perf_counter()
+        dpx, _, _ = oracle.dist_prefix(b, o, 8, 64)
+        perms, lcps = [], []
+        for a, e in zip(bounds[:-1], bounds[1:]):
+            so = o[a:e + 1] - o[a]
+            sb = b[int(o[a]):int(o[e])]
+            pl = oracle.sort(sb, so)
+            perms.append(pl.astype(np.uint32) + np.uint32(a))
+            lcps.append(oracle.lcp(sb, so, pl))
+        samp = np.concatenate([oracle.select_splitters(len(pm), pm, v + 2) for pm in perms])
+        strs = [bytes(b[int(o[i]):int(o[i + 1])]) for i in samp]
+        sl = np.cumsum([0] + [len(x) for x in strs]).astype(np.uint64)
+        sbytes = np.frombuffer(b"".join(strs) or b"\0", np.uint8)
+        sperm = oracle.sort(sbytes, sl)
+        fid = oracle.select_splitters(len(samp), sperm, p)
+        spl = [strs[i] for i in fid]
+        fl = np.cumsum([0] + [len(x) for x in spl]).astype(np.uint64)
+        fbytes = np.frombuffer(b"".join(spl) or b"\0", np.uint8)
+        encs = []
+        for pm, lc in zip(perms, lcps):
+            bb = oracle.bucket_bounds(b, o, pm, fbytes, fl)
+            encs.append((bb, oracle.fc_encode(b, o, pm, lc, dpx, bb)))
+        out_ids = []
+        for j in range(p):
+            ro, LC, LN, ID, SO, SUF, base = [0], [], [], [], [], [], 0
+            for bb, enc in encs:
+                x, y = int(bb[j]), int(bb[j + 1])
+                LC.append(enc["lcp"][x:y]); LN.append(enc["len"][x:y]); ID.append(enc["id"][x:y])
+                SO.append(enc["suf_off"][x:y] - enc["suf_off"][x] + base)
+                SUF.append(enc["suf"][int(enc["suf_off"][x]):int(enc["suf_off"][y])])
+                base += int(enc["suf_off"][y] - enc["suf_off"][x])
+                ro.append(ro[-1] + y - x)
+            if ro[-1]:
+                _, ids, _ = oracle.merge(np.array(ro, np.uint64), np.concatenate(LC), np.concatenate(LN),
+                                         np.concatenate(ID), np.concatenate(SO + [np.array([base], np.uint64)]),
+                                         np.concatenate(SUF))
+                out_ids.append(ids)
+        order = np.concatenate(out_ids)
+        full_lcp = oracle.lcp(b, o, order)
+        oracle.dist_exact(o, order, full_lcp)
+        return time.perf_counter() - t0, int(o[-1])
+
+    ns = 20_000
+    dt, nbytes = run(ns)
+    while dt < target_s / 4 and ns < s_host.n // 2:
+        ns = min(s_host.n, int(ns * min(8.0, max(1.5, target_s / max(dt, 1e-3) * 0.8))))
+        dt, nbytes = run(ns)
+    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {ns} strings ({nbytes} bytes) of the same workload, same step with p={p}, "
+                      f"single-threaded C oracle, {dt:.1f} s"}
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -30,12 +205,14 @@ def main():
     ap.add_argument("--n", type=int, default=16_000_000)
     ap.add_argument("--length", type=int, default=500)
     ap.add_argument("--ratio", type=float, default=0.5)
-    ap.add_argument("--buckets", type=int, default=256)
-    ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
+    ap.add_argument("--pes", type=int, default=16, help="virtual processing elements")
+    ap.add_argument("--sampling", type=int, default=2, help="sampling factor v")
+    ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--stages", action="store_true", help="per-stage times on stderr")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -47,52 +224,31 @@ def main():
     s = synth.dn_strings(args.n, args.length, args.ratio, seed=0, device=dev)
     torch.cuda.synchronize()
     print(f"# generated n={s.n} N={s.N} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    B, O = s.bytes, s.offsets
-    n, N = s.n, s.N
-
-    ws_sort = torch.empty(ss.lib().ss_sort_workspace(n), dtype=torch.uint8, device=dev)
-    ws_pd = torch.empty(ss.lib().ss_dist_prefix_workspace(n), dtype=torch.uint8, device=dev)
-    stages = {}
-
-    def ev():
-        e = torch.cuda.Event(enable_timing=True)
-        e.record()
-        return e
-
-    def step(record):
-        marks = [("start", ev())]
-        perm, lcp = ss.sort(B, O, ws=ws_sort)
-        marks.append(("sort+lcp", ev()))
-        dist = ss.dist_exact(O, perm, lcp)
-        marks.append(("dist_exact", ev()))
-        dpx, rounds = ss.dist_prefix(B, O, 8, 64, ws=ws_pd)
-        marks.append(("dist_prefix", ev()))
-        ids = ss.select_splitters(perm, args.buckets)
-        sb, so = ss.gather_strings(B, O, ids)
-        fc = ss.partition_encode(B, O, perm, lcp, dpx, sb, so)
-        marks.append(("partition_encode", ev()))
-        src, mid, mlcp = ss.lcp_merge(fc["run_off"], fc["lcp"], fc["len"], fc["id"], fc["suf_off"], fc["suf"])
-        marks.append(("lcp_merge", ev()))
-        torch.cuda.synchronize()
-        if record:
-            for (a, ea), (b, eb) in zip(marks[:-1], marks[1:]):
-                stages.setdefault(b, []).append(ea.elapsed_time(eb))
-        return rounds, fc["total"]
+    pipe = Pipeline(s.bytes, s.offsets, args.pes, args.sampling, ss, torch)
 
     for _ in range(args.warmup):
-        step(False)
+        pipe.step(Marks(torch, False))
     torch.cuda.synchronize()
+    stages = {}
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        rounds, lit = step(True)
+        mk = Marks(torch, args.stages)
+        res = pipe.step(mk)
+        if args.stages:
+            torch.cuda.synchronize()
+            for k, v in mk.times().items():
+                stages.setdefault(k, []).append(v)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    if args.stages:
-        for k, v in stages.items():
-            print(f"# stage {k:18s} {sum(v) / len(v):9.3f} ms", file=sys.stderr)
+    order, mlcp, dist, dpx, rounds = res
+    print(f"# step {dt * 1e3:.3f} ms", file=sys.stderr, flush=True)
+    verified = None
+    if not args.no_verify:
+        verified = verify_dn(s, order, mlcp, dist, dpx)
+        print(f"# verified against the closed forms: {verified}", file=sys.stderr, flush=True)
     out = {
         "metric": "string bytes sorted/s",
-        "value": N / dt / 1e9,
+        "value": s.N / dt / 1e9,
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -103,11 +259,19 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": f"dn n={n} len={args.length} D/N={args.ratio}", "n": n, "N": N,
-                   "buckets": args.buckets, "doubling_rounds": rounds, "literal_bytes": lit},
-        "strings_per_s": n / dt,
-        "stages_ms": {k: sum(v) / len(v) for k, v in stages.items()},
+        "config": {"workload": f"D/N-ratio strings n={s.n} len={args.length} D/N={args.ratio}",
+                   "n": s.n, "N": s.N, "virtual_pes": args.pes, "sampling_factor": args.sampling,
+                   "doubling_rounds": rounds},
+        "strings_per_s": s.n / dt,
+        "hbm_frac_of_N_per_step": s.N / dt / 1e9 / HBM_PEAK_GBS,
+        "verified": verified,
     }
+    if args.stages:
+        out["stages_ms"] = {k: sum(v) / len(v) for k, v in stages.items()}
+    if not args.no_cpu:
+        host = synth.StringSet(s.bytes[: int(s.offsets[min(s.n, 2_000_000)])].cpu(),
+                               s.offsets[: min(s.n, 2_000_000) + 1].cpu(), dict(s.meta))
+        out["cpu_baseline"] = cpu_baseline(host, args.pes, args.sampling)
     print(json.dumps(out))
 
 

@@ -88,7 +88,8 @@ int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uin
 /* ------------------------------------------------------- LCP and dist */
 
 /* LCP array of a given order (Section 2): lcp[0] = 0,
- * lcp[i] = lcp(s_perm[i-1], s_perm[i]).  perm (in, n), lcp (out, n). */
+ * lcp[i] = lcp(s_perm[i-1], s_perm[i]).  perm (in, n), lcp (out, n); the
+ * values of perm index the string array (which may hold more than n strings). */
 int ss_lcp(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
            const uint32_t *perm, uint32_t *lcp, void *stream);
 
@@ -96,8 +97,8 @@ int ss_lcp(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n
  * rank a string, dist(s) = min(len(s), 1 + max over t != s of lcp(s, t)),
  * evaluated from the sorted neighbours: for the string at sorted position i,
  * dist = min(len, 1 + max(lcp[i], lcp[i+1])) with lcp[n] := 0.
- *   perm, lcp (in, n; a sorted order and its LCP array), dist (out, n, by
- *   input index). */
+ *   perm, lcp (in, n; a sorted order and its LCP array), dist (out, by input
+ *   index: dist[perm[i]] is written for i < n). */
 int ss_dist_exact(const uint64_t *offsets, uint64_t n, const uint32_t *perm,
                   const uint32_t *lcp, uint32_t *dist, void *stream);
 
@@ -171,18 +172,22 @@ size_t ss_partition_encode_workspace(uint64_t n);
  *   fc_len[i] = d_i = dist[perm[i]] if dist != NULL, else the full length;
  *   fc_id[i]  = perm[i];
  *   suf[suf_off[i] .. suf_off[i+1]) = bytes s_perm[i][e_i, d_i)
- * (suf_off has n+1 entries, suf_off[n] = total literal bytes).
+ * (suf_off has n+1 entries).  Literal bytes start at suf + suf_base and every
+ * suf_off entry includes suf_base, so several arrays can be encoded into one
+ * shared buffer (suf_off[n] = suf_base + total literal bytes).
  * Inputs: perm, lcp (a sorted order and its LCP array), dist (by input index,
  * must satisfy dist >= min(len, lcp+1) as ss_dist_prefix guarantees; NULL =
  * full strings), splitters as in ss_bucket_bounds.  suf_cap: capacity of suf
- * (N always suffices).  suf_total_host (host, out, nullable).
+ * in bytes (suf_base + N always suffices).  suf_total_host (host, out,
+ * nullable): literal bytes written by this call.
  * Errors: CAPACITY if suf_cap is too small, INVALID_ARG if some e_i > d_i. */
 int ss_partition_encode(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
                         const uint32_t *perm, const uint32_t *lcp, const uint32_t *dist,
                         const uint8_t *spl_bytes, uint64_t spl_N, const uint64_t *spl_offsets,
                         uint32_t r, uint64_t *run_off, uint32_t *fc_lcp, uint32_t *fc_len,
-                        uint32_t *fc_id, uint64_t *suf_off, uint8_t *suf, uint64_t suf_cap,
-                        uint64_t *suf_total_host, void *ws, size_t ws_bytes, void *stream);
+                        uint32_t *fc_id, uint64_t *suf_off, uint8_t *suf, uint64_t suf_base,
+                        uint64_t suf_cap, uint64_t *suf_total_host, void *ws, size_t ws_bytes,
+                        void *stream);
 
 /* Workspace bytes for ss_fc_decode on n strings. */
 size_t ss_fc_decode_workspace(uint64_t n);
@@ -199,21 +204,37 @@ int ss_fc_decode(uint32_t k, const uint64_t *run_off, const uint32_t *fc_lcp,
 
 /* ---------------------------------------------------------------- merge */
 
-/* Workspace bytes for ss_lcp_merge of n strings whose decoded lengths sum to
- * total_len bytes. */
-size_t ss_lcp_merge_workspace(uint64_t n, uint64_t total_len);
+/* Workspace bytes for ss_lcp_merge of n_out merged strings drawn from front-
+ * coded arrays of n_fc entries in k runs. */
+size_t ss_lcp_merge_workspace(uint64_t n_out, uint64_t n_fc, uint32_t k);
 
-/* LCP-aware k-way merge of k sorted front-coded runs (Section 3, step 3; the
- * paper uses an LCP loser tree, Section 2).  Input as in ss_fc_decode plus
- * fc_id.  Output, by merged position i:
+/* LCP-aware merging of sorted front-coded runs (Section 3, step 3; the paper
+ * uses an LCP loser tree, Section 2), for several independent groups of runs
+ * in one call (on one device: the runs each bucket receives from every
+ * processing element).
+ *   Front-coded arrays (format of ss_partition_encode), n_fc entries:
+ *     fc_lcp, fc_len, fc_id (n_fc), suf_off (n_fc+1), suf.  The literal of
+ *     entry i is the d_i - e_i bytes at suf + suf_off[i]; suf_off[n_fc] bounds
+ *     the literal buffer (arrays filled by several ss_partition_encode calls
+ *     with different suf_base qualify).
+ *   Runs: run j = front-coded positions [run_begin[j], run_end[j]) (device,
+ *     k entries each); runs must not overlap; every non-empty run starts with
+ *     e = 0 and is sorted.
+ *   Groups: group g merges runs [group_off[g], group_off[g+1]) (device,
+ *     groups+1 entries, group_off[0] = 0, group_off[groups] = k).
+ * Output, n_out = sum of run sizes entries: group g's merged sequence occupies
+ * the positions after all runs of earlier groups, in merged order:
  *   out_src[i] = (run << 32) | position within the run,
  *   out_id[i]  = fc_id of that element,
- *   out_lcp[i] = LCP with the previous merged string (0 for i = 0).
- * Equal strings keep (run, position) order. */
-int ss_lcp_merge(uint32_t k, const uint64_t *run_off, const uint32_t *fc_lcp,
+ *   out_lcp[i] = LCP with the previous string of the same group (0 for the
+ *                group's first).
+ * Equal strings keep (run, position) order.  The runs are read in place; no
+ * decoded copy is made. */
+int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_t *run_end, uint32_t groups,
+                 const uint32_t *group_off, uint64_t n_fc, const uint32_t *fc_lcp,
                  const uint32_t *fc_len, const uint32_t *fc_id, const uint64_t *suf_off,
-                 const uint8_t *suf, uint64_t n, uint64_t *out_src, uint32_t *out_id,
-                 uint32_t *out_lcp, void *ws, size_t ws_bytes, void *stream);
+                 const uint8_t *suf, uint64_t *out_src, uint32_t *out_id, uint32_t *out_lcp,
+                 void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------- tuning */
 

@@ -83,9 +83,10 @@ def sort(bytes_, offsets) -> np.ndarray:
 
 
 def lcp(bytes_, offsets, perm) -> np.ndarray:
+    """LCP array of the order ``perm`` (its values index ``offsets``)."""
     b, o = _host(bytes_, offsets)
-    n = o.size - 1
     perm = np.ascontiguousarray(perm, dtype=np.uint32)
+    n = perm.size
     out = np.empty(max(n, 1), dtype=np.uint32)
     lib().or_lcp(_p(b), _p(o), n, _p(perm), _p(out))
     return out[:n]
@@ -137,7 +138,7 @@ def select_splitters(n, perm, r) -> np.ndarray:
 def bucket_bounds(bytes_, offsets, perm, spl_bytes, spl_offsets) -> np.ndarray:
     b, o = _host(bytes_, offsets)
     sb, so = _host(spl_bytes, spl_offsets)
-    n = o.size - 1
+    n = len(perm)
     r = so.size  # r-1 splitters -> r buckets
     out = np.empty(r + 1, dtype=np.uint64)
     lib().or_bucket_bounds(_p(b), _p(o), n, _p(np.ascontiguousarray(perm, dtype=np.uint32)),
@@ -148,7 +149,7 @@ def bucket_bounds(bytes_, offsets, perm, spl_bytes, spl_offsets) -> np.ndarray:
 def fc_encode(bytes_, offsets, perm, lcp_, dist, bounds):
     """Returns dict(lcp, len, id, suf_off, suf)."""
     b, o = _host(bytes_, offsets)
-    n = o.size - 1
+    n = len(perm)
     r = len(bounds) - 1
     bounds = np.ascontiguousarray(bounds, dtype=np.uint64)
     perm = np.ascontiguousarray(perm, dtype=np.uint32)

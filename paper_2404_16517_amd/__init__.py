@@ -54,12 +54,12 @@ def lib():
             "ss_gather_strings": ([P, U64, P, U64, P, U64, P, P, U64, P, SZ, P], I32),
             "ss_bucket_bounds": ([P, U64, P, U64, P, P, U64, P, U32, P, P], I32),
             "ss_partition_encode_workspace": ([U64], SZ),
-            "ss_partition_encode": ([P, U64, P, U64, P, P, P, P, U64, P, U32, P, P, P, P, P, P, U64, P, P, SZ, P],
-                                    I32),
+            "ss_partition_encode": ([P, U64, P, U64, P, P, P, P, U64, P, U32, P, P, P, P, P, P, U64, U64, P, P, SZ,
+                                     P], I32),
             "ss_fc_decode_workspace": ([U64], SZ),
             "ss_fc_decode": ([U32, P, P, P, P, P, U64, P, P, U64, P, SZ, P], I32),
-            "ss_lcp_merge_workspace": ([U64, U64], SZ),
-            "ss_lcp_merge": ([U32, P, P, P, P, P, P, U64, P, P, P, P, SZ, P], I32),
+            "ss_lcp_merge_workspace": ([U64, U64, U32], SZ),
+            "ss_lcp_merge": ([U32, P, P, U32, P, U64, P, P, P, P, P, P, P, P, P, SZ, P], I32),
             "ss_set_tuning": ([I32, I32], I32),
         }
         for name, (args, res) in sig.items():
@@ -143,15 +143,20 @@ def sort_batch(bytes_, offsets, set_off: torch.Tensor, with_lcp: bool = True, ws
 
 
 def lcp(bytes_, offsets, perm):
-    b, o, n = _dev_strings(bytes_, offsets)
+    """LCP array of the order ``perm`` (perm values index ``offsets``)."""
+    b, o, _ = _dev_strings(bytes_, offsets)
+    n = perm.numel()
     out = _u32(n, b.device)
     _check(lib().ss_lcp(_p(b), b.numel(), _p(o), n, _p(perm.contiguous()), _p(out), _stream(b.device)))
     return out
 
 
 def dist_exact(offsets, perm, lcp_):
-    n = offsets.numel() - 1
-    out = _u32(n, offsets.device)
+    """Exact distinguishing prefixes by input index (sized like ``offsets``)."""
+    n = perm.numel()
+    if lcp_.numel() != n:
+        raise StrsortError("perm and lcp must have the same length")
+    out = torch.zeros(max(offsets.numel() - 1, 0), dtype=torch.int32, device=offsets.device)
     _check(lib().ss_dist_exact(_p(offsets), n, _p(perm.contiguous()), _p(lcp_.contiguous()), _p(out),
                                _stream(offsets.device)))
     return out
@@ -210,25 +215,38 @@ def bucket_bounds(bytes_, offsets, perm, spl_bytes, spl_offsets):
     return out
 
 
-def partition_encode(bytes_, offsets, perm, lcp_, dist, spl_bytes, spl_offsets, suf_cap: int | None = None):
+def partition_encode(bytes_, offsets, perm, lcp_, dist, spl_bytes, spl_offsets, suf_cap: int | None = None,
+                     out: dict | None = None, suf_base: int = 0, n: int | None = None):
     """Buckets + front coding.  Returns a dict of device tensors:
-    run_off (r+1), lcp, len, id (n, int32 bits), suf_off (n+1), suf (uint8), total (int)."""
-    b, o, n = _dev_strings(bytes_, offsets)
+    run_off (r+1), lcp, len, id (n, int32 bits), suf_off (n+1), suf (uint8), total (int).
+
+    ``out`` may supply preallocated output tensors (same keys, ``suf`` being the
+    whole shared literal buffer); literals are then written at ``suf_base``.
+    ``n`` (default: offsets.numel()-1) is the number of sorted positions in
+    ``perm``; perm values index ``offsets``."""
+    b, o, n_all = _dev_strings(bytes_, offsets)
+    n = n_all if n is None else n
     dev = b.device
     r = spl_offsets.numel()
-    run_off = torch.empty(r + 1, dtype=torch.int64, device=dev)
-    fl, fd, fi = _u32(n, dev), _u32(n, dev), _u32(n, dev)
-    so = torch.empty(n + 1, dtype=torch.int64, device=dev)
-    cap = b.numel() if suf_cap is None else suf_cap
-    suf = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
+    if out is None:
+        cap = b.numel() if suf_cap is None else suf_cap
+        out = dict(run_off=torch.empty(r + 1, dtype=torch.int64, device=dev), lcp=_u32(n, dev), len=_u32(n, dev),
+                   id=_u32(n, dev), suf_off=torch.empty(n + 1, dtype=torch.int64, device=dev),
+                   suf=torch.empty(max(cap, 1), dtype=torch.uint8, device=dev))
+    cap = out["suf"].numel()
     ws = _ws(lib().ss_partition_encode_workspace(n), dev)
     total = ctypes.c_uint64(0)
     _check(lib().ss_partition_encode(_p(b), b.numel(), _p(o), n, _p(perm.contiguous()), _p(lcp_.contiguous()),
                                      _p(dist.contiguous()) if dist is not None else None, _p(spl_bytes),
-                                     spl_bytes.numel(), _p(spl_offsets), r, _p(run_off), _p(fl), _p(fd), _p(fi),
-                                     _p(so), _p(suf), cap, ctypes.byref(total), _p(ws), ws.numel(), _stream(dev)))
+                                     spl_bytes.numel(), _p(spl_offsets), r, _p(out["run_off"]), _p(out["lcp"]),
+                                     _p(out["len"]), _p(out["id"]), _p(out["suf_off"]), _p(out["suf"]), suf_base, cap,
+                                     ctypes.byref(total), _p(ws), ws.numel(), _stream(dev)))
     t = int(total.value)
-    return dict(run_off=run_off, lcp=fl, len=fd, id=fi, suf_off=so, suf=suf[:t], total=t)
+    res = dict(out)
+    res["total"] = t
+    if suf_base == 0:
+        res["suf"] = out["suf"][:t]
+    return res
 
 
 def fc_decode(run_off, fc_lcp, fc_len, suf_off, suf):
@@ -245,17 +263,31 @@ def fc_decode(run_off, fc_lcp, fc_len, suf_off, suf):
     return out[:total], out_off
 
 
-def lcp_merge(run_off, fc_lcp, fc_len, fc_id, suf_off, suf, ws=None):
-    """LCP-aware k-way merge.  Returns (src int64[n], id int32[n], lcp int32[n])."""
+def lcp_merge(run_begin, run_end, group_off, fc_lcp, fc_len, fc_id, suf_off, suf, ws=None):
+    """LCP-aware merge of the runs [run_begin[j], run_end[j]) of shared
+    front-coded arrays, one merged sequence per group of runs
+    (group g = runs group_off[g]..group_off[g+1]-1).
+    Returns (src int64[n_out], id int32[n_out], lcp int32[n_out])."""
     dev = fc_lcp.device
-    n = fc_lcp.numel()
-    k = run_off.numel() - 1
-    total = int(fc_len.to(torch.int64).sum()) if n else 0
-    need = lib().ss_lcp_merge_workspace(n, total)
+    n_fc = fc_lcp.numel()
+    rb = run_begin.to(device=dev, dtype=torch.int64).contiguous()
+    re_ = run_end.to(device=dev, dtype=torch.int64).contiguous()
+    go = group_off.to(device=dev, dtype=torch.int32).contiguous()
+    k = rb.numel()
+    n_out = int((re_ - rb).sum()) if k else 0
+    need = lib().ss_lcp_merge_workspace(n_out, n_fc, k)
     if ws is None or ws.numel() < need:
         ws = _ws(need, dev)
-    src = torch.empty(max(n, 0), dtype=torch.int64, device=dev)
-    idv, lc = _u32(n, dev), _u32(n, dev)
-    _check(lib().ss_lcp_merge(k, _p(run_off), _p(fc_lcp), _p(fc_len), _p(fc_id), _p(suf_off), _p(suf), n, _p(src),
-                              _p(idv), _p(lc), _p(ws), ws.numel(), _stream(dev)))
+    src = torch.empty(max(n_out, 0), dtype=torch.int64, device=dev)
+    idv, lc = _u32(n_out, dev), _u32(n_out, dev)
+    _check(lib().ss_lcp_merge(k, _p(rb), _p(re_), go.numel() - 1, _p(go), n_fc, _p(fc_lcp), _p(fc_len), _p(fc_id),
+                              _p(suf_off), _p(suf), _p(src), _p(idv), _p(lc), _p(ws), ws.numel(), _stream(dev)))
     return src, idv, lc
+
+
+def lcp_merge_runs(run_off, fc_lcp, fc_len, fc_id, suf_off, suf, ws=None):
+    """Merge contiguous runs [run_off[j], run_off[j+1]) into one sequence."""
+    ro = run_off.to(dtype=torch.int64)
+    k = ro.numel() - 1
+    go = torch.tensor([0, k], dtype=torch.int32, device=fc_lcp.device)
+    return lcp_merge(ro[:-1], ro[1:], go, fc_lcp, fc_len, fc_id, suf_off, suf, ws=ws)

@@ -54,50 +54,102 @@ __global__ __launch_bounds__(256) void k_prefix_keys(const u8 *bytes, u64 N, con
     keys[i] = kr_finish(kr_extend(bytes, N, o, 0, mm, 0), mm, bits);
 }
 
+struct BPow {
+    u64 p[17];  // B^0 .. B^16 mod p
+};
+
+#define HG 8  // lanes per string in a hash round (64 bytes = 16 limbs per step)
+
 // One doubling round: key of the min(l, len)-prefix of every active string,
 // continuing the Horner state of the previous round (bytes [lprev, l) only).
+// A group of 8 lanes reads 64 consecutive bytes of one string per step; lane
+// j folds its two limbs, and the group combines them as
+// C <- C * B^L + sum_j v_j * B^(limbs after lane j).
 __global__ __launch_bounds__(256) void k_hash_round(const u32 *act, u32 A, const u8 *bytes, u64 N,
                                                     const u64 *off, u64 lprev, u64 l, u32 bits,
-                                                    u64 *state, u64 *keys, u32 *vals)
+                                                    u64 *state, u64 *keys, u32 *vals, BPow bp)
 {
-    const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= A) return;
+    const u32 g = threadIdx.x / HG, lane = threadIdx.x % HG;
+    const u32 j = blockIdx.x * (256 / HG) + g;
+    if (j >= A) return;  // whole group leaves together
     const u32 i = act ? act[j] : j;
     const u64 o = off[i], len = off[i + 1] - o;
     const u64 m = l < len ? l : len;
     u64 C = lprev ? state[i] : 0ull;
-    C = kr_extend(bytes, N, o, lprev, m, C);
-    state[i] = C;
-    keys[j] = kr_finish(C, m, bits);
-    vals[j] = i;
+    for (u64 x = lprev; x < m; x += 8 * HG) {
+        const u64 q = x + 8 * lane;
+        const u32 take = q < m ? (u32)((m - q) < 8 ? (m - q) : 8) : 0u;
+        const u64 w = load_le(bytes, N, o + q, take);
+        // limbs of this lane
+        u32 nl = take == 0 ? 0u : (take > 4 ? 2u : 1u);
+        u64 v = 0;
+        if (nl == 2) v = addmod61(mulmod61(w & 0xFFFFFFFFull, KR_B), w >> 32);
+        else if (nl == 1) v = w & 0xFFFFFFFFull;
+        // limbs in this step and after this lane
+        const u64 rem = m - x;
+        const u32 Lstep = (u32)((rem >= 8 * HG ? 8 * HG : rem) + 3) / 4;
+        const u32 before = 2 * lane < Lstep ? 2 * lane : Lstep;
+        const u32 after = Lstep - before - nl;
+        u64 t = nl ? mulmod61(v, bp.p[after]) : 0ull;
+#pragma unroll
+        for (int s2 = HG / 2; s2 > 0; s2 >>= 1) t = addmod61(t, __shfl_xor(t, s2, HG));
+        C = addmod61(mulmod61(C, bp.p[Lstep]), t);
+    }
+    if (lane == 0) {
+        state[i] = C;
+        keys[j] = kr_finish(C, m, bits);
+        vals[j] = i;
+    }
 }
 
 __device__ __forceinline__ u64 lanemask_lt_h() { return (1ull << __lane_id()) - 1ull; }
 
+#define DD_PER 8
+
 // Finish strings whose key is unique among the active ones or whose length is
-// <= l; the rest form the next active list.
+// <= l; the rest form the next active list (one atomic per workgroup).
 __global__ __launch_bounds__(256) void k_dedup(const u64 *keys, const u32 *vals, u32 A, const u64 *off,
                                                u64 l, u32 *dist, u32 *next, u32 *ctr)
 {
-    const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = j < A;
-    bool keep = false;
-    u32 i = 0;
-    if (valid) {
-        const u64 k = keys[j];
-        const bool dup = (j > 0 && keys[j - 1] == k) || (j + 1 < A && keys[j + 1] == k);
-        i = vals[j];
-        const u64 len = off[i + 1] - off[i];
-        if (!dup || len <= l) dist[i] = (u32)(len < l ? len : l);
-        else keep = true;
+    __shared__ u32 wsum[4];
+    __shared__ u32 base_s;
+    u32 iv[DD_PER];
+    u32 mask = 0;
+#pragma unroll
+    for (int r = 0; r < DD_PER; r++) {
+        iv[r] = 0;
+        const u32 j = blockIdx.x * (256 * DD_PER) + r * 256 + threadIdx.x;
+        if (j < A) {
+            const u64 k = keys[j];
+            const bool dup = (j > 0 && keys[j - 1] == k) || (j + 1 < A && keys[j + 1] == k);
+            const u32 i = vals[j];
+            const u64 len = off[i + 1] - off[i];
+            if (!dup || len <= l) dist[i] = (u32)(len < l ? len : l);
+            else mask |= 1u << r;
+            iv[r] = i;
+        }
     }
-    const u64 m = __ballot(keep);
-    if (m == 0) return;
-    const u32 leader = __ffsll((unsigned long long)m) - 1;
-    u32 base = 0;
-    if (__lane_id() == leader) base = atomicAdd(ctr, (u32)__popcll(m));
-    base = __shfl(base, leader, 64);
-    if (keep) next[base + (u32)__popcll(m & lanemask_lt_h())] = i;
+    const u32 c = (u32)__popc(mask);
+    // block exclusive scan of c
+    u32 x = c;
+    const u32 lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        u32 y = __shfl_up(x, o, 64);
+        if (lane >= (u32)o) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u32 t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        base_s = t ? atomicAdd(ctr, t) : 0u;
+    }
+    __syncthreads();
+    u32 pre = x - c + base_s;
+    for (u32 w = 0; w < wid; w++) pre += wsum[w];
+#pragma unroll
+    for (int r = 0; r < DD_PER; r++)
+        if ((mask >> r) & 1u) next[pre++] = iv[r];
 }
 
 __global__ void k_one_seg(Seg *act, u32 A) { act[0] = Seg{0, A, 0, 0}; }
@@ -171,6 +223,9 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
         ss_set_error("workspace too small: need %zu bytes", ss_dist_prefix_workspace(n));
         return SS_ERR_WORKSPACE;
     }
+    BPow bp;
+    bp.p[0] = 1;
+    for (int t = 1; t <= 16; t++) bp.p[t] = (u64)(((unsigned __int128)bp.p[t - 1] * KR_B) % KR_P);
     u32 A = (u32)n;
     const u32 *act = nullptr;
     u32 *nxt = w.actA;
@@ -178,8 +233,8 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
     u32 rounds = 0;
     while (A > 0) {
         if (++rounds > 64) { ss_set_error("prefix doubling did not terminate"); return SS_ERR_INVALID_ARG; }
-        k_hash_round<<<(unsigned)ceil_div(A, 256), 256, 0, st>>>(act, A, bytes, N, offsets, lprev, l, hash_bits,
-                                                                  w.state, w.sw.keyA, w.vals);
+        k_hash_round<<<(unsigned)ceil_div(A, 256 / HG), 256, 0, st>>>(act, A, bytes, N, offsets, lprev, l,
+                                                                       hash_bits, w.state, w.sw.keyA, w.vals, bp);
         SS_CHECK_LAUNCH();
         if (A >= 2) {
             k_one_seg<<<1, 1, 0, st>>>(w.sw.act, A);
@@ -188,7 +243,7 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
             SS_TRY(sort_rounds(J, w.sw, 1));
         }
         SS_HIP(hipMemsetAsync(w.ctr, 0, sizeof(u32), st));
-        k_dedup<<<(unsigned)ceil_div(A, 256), 256, 0, st>>>(w.sw.keyA, w.vals, A, offsets, l, dist_approx, nxt,
+        k_dedup<<<(unsigned)ceil_div(A, 256 * DD_PER), 256, 0, st>>>(w.sw.keyA, w.vals, A, offsets, l, dist_approx, nxt,
                                                              w.ctr);
         SS_CHECK_LAUNCH();
         SS_TRY(ss_read_u32(w.ctr, &A, 1, st));

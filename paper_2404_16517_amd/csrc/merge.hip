@@ -17,6 +17,7 @@
 // strings compared from h on.
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "common.hpp"
@@ -280,32 +281,138 @@ extern "C" int ss_fc_decode(uint32_t k, const uint64_t *run_off, const uint32_t 
 
 // ----------------------------------------------------------------- merge
 
-#define MG_PER 32  // outputs per thread
-
-struct MergeLevel {
-    const u32 *G, *L;     // input element ids (decoded string index) and lcp
-    u32 *Go, *Lo;         // outputs
-    const u64 *R;         // run bounds of this level (device, nruns+1)
-    const u32 *tstart;    // per pair: first thread (device, npairs+1)
-    u32 npairs;
-    u32 nruns;
-    const u8 *db;         // decoded bytes
-    u64 dN;
-    const u64 *doff;      // decoded offsets
+// Read access to front-coded strings without decoding them: bytes [k, k+take)
+// of string g are gathered piece by piece along its psv chain.
+struct FcView {
+    const u32 *e, *d, *psv;
+    const u64 *suf_off;
+    const u8 *suf;
+    u64 sufN;
 };
 
-__device__ __forceinline__ int cmp_g(const MergeLevel &M, u32 x, u32 y, u64 from, u64 *lcp)
+__device__ __forceinline__ u64 fc_load_be(const FcView &V, u32 g, u64 k, u32 take)
 {
-    const u64 ox = M.doff[x], lx = M.doff[x + 1] - ox;
-    const u64 oy = M.doff[y], ly = M.doff[y + 1] - oy;
-    return str_cmp_from(M.db, M.dN, ox, lx, M.db, M.dN, oy, ly, from, lcp);
+    u64 v = 0;
+    u32 got = 0;
+    while (got < take) {
+        const u64 kk = k + got;
+        u32 j = g;
+        u64 h = V.d[g];
+        u32 ej = V.e[j];
+        while (ej > kk) {
+            h = ej;
+            j = V.psv[j];
+            ej = V.e[j];
+        }
+        const u64 av = h - kk;
+        const u32 part = (u32)(av < (u64)(take - got) ? av : (u64)(take - got));
+        v |= load_be(V.suf, V.sufN, V.suf_off[j] + (kk - ej), part) >> (8 * got);
+        got += part;
+    }
+    return v;
+}
+
+// Three-way comparison of front-coded strings x and y from byte `from`
+// (they agree on [0, from)); *lcp receives their LCP.
+__device__ __forceinline__ int fc_cmp(const FcView &V, u32 x, u32 y, u64 from, u64 *lcp)
+{
+    const u64 lx = V.d[x], ly = V.d[y];
+    const u64 m = lx < ly ? lx : ly;
+    u64 i = from < m ? from : m;
+    while (i < m) {
+        const u64 r = m - i;
+        const u32 take = r < 8 ? (u32)r : 8u;
+        const u64 wa = fc_load_be(V, x, i, take);
+        const u64 wb = fc_load_be(V, y, i, take);
+        if (wa != wb) {
+            *lcp = i + (__clzll(wa ^ wb) >> 3);
+            return wa < wb ? -1 : 1;
+        }
+        i += take;
+    }
+    *lcp = m;
+    return lx < ly ? -1 : (lx > ly ? 1 : 0);
+}
+
+#define MG_PER 64  // outputs per thread
+#define F_FIRST 0xFFFFFFFFu
+
+struct MergeLevel {
+    const u32 *G, *L, *F;  // element ids (FC positions), LCP with predecessor, first-LCP bound
+    u32 *Go, *Lo, *Fo;
+    const u64 *PA0, *PA1, *PB1;  // per pair: run A = [PA0, PA1), run B = [PA1, PB1) in output space
+    const u32 *tstart;           // first thread of each pair (npairs+1)
+    u32 *pc;                     // per pair: lcp of the two runs' first strings
+    u8 *pfirst;                  // per pair: 1 if run A's first string comes first
+    u32 npairs;
+    FcView V;
+};
+
+__device__ __forceinline__ u32 min3u(u32 a, u32 b, u32 c) { return min(a, min(b, c)); }
+
+// Output-space element x of run j: its front-coded position, its LCP with the
+// run predecessor, and a lower bound on its LCP with the run's first string:
+// min(e) over the run up to x, read off the psv chain (the chain's last
+// element before an e = 0 position carries that minimum); chains longer than
+// 64 steps give the trivial bound 0.
+__global__ __launch_bounds__(256) void k_merge_init(const u64 *run_begin, const u64 *P, u32 k, u32 n_out,
+                                                    const u32 *e, const u32 *psv, u32 *G, u32 *L, u32 *F)
+{
+    const u32 x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n_out) return;
+    u32 lo = 0, hi = k;  // largest j with P[j] <= x
+    while (hi - lo > 1) {
+        u32 mid = (lo + hi) >> 1;
+        if (P[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    const u32 start = (u32)run_begin[lo];
+    const u32 g = start + (x - (u32)P[lo]);
+    G[x] = g;
+    if (g == start) {
+        L[x] = 0;
+        F[x] = F_FIRST;
+        return;
+    }
+    L[x] = e[g];
+    u32 z = g, res = 0;
+    if (e[g] > 0) {
+        for (int step = 0; step < 64; step++) {
+            const u32 j = psv[z];
+            if (e[j] == 0) {
+                res = (j == start) ? e[z] : 0u;
+                break;
+            }
+            z = j;
+        }
+    }
+    F[x] = res;
+}
+
+// Per pair of runs: LCP and order of their first strings.
+__global__ void k_pair_info(MergeLevel M)
+{
+    const u32 p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= M.npairs) return;
+    const u64 A0 = M.PA0[p], A1 = M.PA1[p], B1 = M.PB1[p];
+    u32 c = 0;
+    u8 fa = 1;
+    if (A1 > A0 && B1 > A1) {
+        u64 l;
+        const int r = fc_cmp(M.V, M.G[A0], M.G[A1], 0, &l);
+        c = (u32)l;
+        fa = r <= 0 ? 1 : 0;
+    } else if (A1 == A0) {
+        fa = 0;
+    }
+    M.pc[p] = c;
+    M.pfirst[p] = fa;
 }
 
 __global__ __launch_bounds__(256) void k_merge_level(MergeLevel M, u32 nthreads)
 {
     const u32 t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nthreads) return;
-    // pair of this thread: largest p with tstart[p] <= t
     u32 lo = 0, hi = M.npairs;
     while (hi - lo > 1) {
         u32 mid = (lo + hi) >> 1;
@@ -313,42 +420,41 @@ __global__ __launch_bounds__(256) void k_merge_level(MergeLevel M, u32 nthreads)
         else hi = mid;
     }
     const u32 p = lo;
-    const u32 ra = 2 * p, rb = 2 * p + 1;
-    const u64 A0 = M.R[ra], A1 = M.R[ra + 1];
-    const u64 B0 = (rb < M.nruns) ? M.R[rb] : A1;
-    const u64 B1 = (rb < M.nruns) ? M.R[rb + 1] : A1;
+    const u64 A0 = M.PA0[p], A1 = M.PA1[p], B0 = A1, B1 = M.PB1[p];
     const u32 na = (u32)(A1 - A0), nb = (u32)(B1 - B0);
     const u32 dloc = (t - M.tstart[p]) * MG_PER;
     const u32 tot = na + nb;
     if (dloc >= tot) return;
     const u32 cnt = (tot - dloc) < MG_PER ? (tot - dloc) : MG_PER;
-    const u32 *GA = M.G + A0, *LA = M.L + A0, *GB = M.G + B0, *LB = M.L + B0;
+    const u32 *GA = M.G + A0, *LA = M.L + A0, *FA = M.F + A0;
+    const u32 *GB = M.G + B0, *LB = M.L + B0, *FB = M.F + B0;
+    const u32 c = M.pc[p];
+    const bool firstA = M.pfirst[p] != 0;
     u64 tmp;
     // co-rank: x = number of A elements among the first dloc outputs
     u32 xlo = dloc > nb ? dloc - nb : 0, xhi = dloc < na ? dloc : na;
     while (xlo < xhi) {
         const u32 mid = (xlo + xhi) >> 1;
-        // A[mid] <= B[dloc-mid-1] -> A[mid] is among the first dloc outputs
-        if (cmp_g(M, GA[mid], GB[dloc - mid - 1], 0, &tmp) <= 0) xlo = mid + 1;
+        const u32 y = dloc - mid - 1;
+        if (fc_cmp(M.V, GA[mid], GB[y], min3u(FA[mid], c, FB[y]), &tmp) <= 0) xlo = mid + 1;
         else xhi = mid;
     }
     u32 a = xlo, b = dloc - xlo;
-    // LCPs of the next candidates with the previous output
     u32 ha = 0, hb = 0;
     if (dloc > 0) {
         bool lastA;
         if (a == 0) lastA = false;
         else if (b == 0) lastA = true;
-        else lastA = cmp_g(M, GA[a - 1], GB[b - 1], 0, &tmp) > 0;  // A[a-1] > B[b-1] -> A[a-1] was last
+        else lastA = fc_cmp(M.V, GA[a - 1], GB[b - 1], min3u(FA[a - 1], c, FB[b - 1]), &tmp) > 0;
         if (lastA) {
             if (a < na) ha = LA[a];
-            if (b < nb) { cmp_g(M, GA[a - 1], GB[b], 0, &tmp); hb = (u32)tmp; }
+            if (b < nb) { fc_cmp(M.V, GA[a - 1], GB[b], min3u(FA[a - 1], c, FB[b]), &tmp); hb = (u32)tmp; }
         } else {
             if (b < nb) hb = LB[b];
-            if (a < na) { cmp_g(M, GB[b - 1], GA[a], 0, &tmp); ha = (u32)tmp; }
+            if (a < na) { fc_cmp(M.V, GB[b - 1], GA[a], min3u(FB[b - 1], c, FA[a]), &tmp); ha = (u32)tmp; }
         }
     }
-    u32 *Go = M.Go + A0 + dloc, *Lo = M.Lo + A0 + dloc;
+    u32 *Go = M.Go + A0 + dloc, *Lo = M.Lo + A0 + dloc, *Fo = M.Fo + A0 + dloc;
     for (u32 k = 0; k < cnt; k++) {
         bool takeA;
         u32 outl;
@@ -365,9 +471,10 @@ __global__ __launch_bounds__(256) void k_merge_level(MergeLevel M, u32 nthreads)
             takeA = false;
             outl = hb;
         } else {
-            const int c = cmp_g(M, GA[a], GB[b], ha, &tmp);
+            const u32 bound = min3u(FA[a], c, FB[b]);
+            const int r = fc_cmp(M.V, GA[a], GB[b], bound > ha ? bound : ha, &tmp);
             outl = ha;
-            if (c <= 0) {
+            if (r <= 0) {
                 takeA = true;
                 hb = (u32)tmp;
             } else {
@@ -379,147 +486,238 @@ __global__ __launch_bounds__(256) void k_merge_level(MergeLevel M, u32 nthreads)
         if (takeA) {
             Go[k] = GA[a];
             Lo[k] = outl;
+            Fo[k] = firstA ? FA[a] : min(c, FA[a]);
             a++;
             if (a < na) ha = LA[a];
         } else {
             Go[k] = GB[b];
             Lo[k] = outl;
+            Fo[k] = firstA ? min(c, FB[b]) : FB[b];
             b++;
             if (b < nb) hb = LB[b];
         }
     }
 }
 
-__global__ void k_merge_init(const u32 *e, u32 n, u32 *G, u32 *L)
+// Source (run, position) of every output: runs sorted by their front-coded
+// start (sb, sid) locate the run of a front-coded position.
+__global__ void k_merge_out(const u32 *G, const u32 *L, u32 n_out, const u64 *sb, const u32 *sid, u32 k,
+                            const u32 *fc_id, u64 *src, u32 *id, u32 *lcp)
 {
-    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    G[i] = i;
-    L[i] = e[i];
-}
-
-__global__ void k_merge_out(const u32 *G, const u32 *L, u32 n, const u64 *run_off, u32 k, const u32 *fc_id,
-                            u64 *src, u32 *id, u32 *lcp)
-{
-    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const u32 g = G[i];
-    u32 lo = 0, hi = k;  // largest run j with run_off[j] <= g
+    const u32 x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n_out) return;
+    const u32 g = G[x];
+    u32 lo = 0, hi = k;  // largest j with sb[j] <= g
     while (hi - lo > 1) {
         u32 mid = (lo + hi) >> 1;
-        if (run_off[mid] <= g) lo = mid;
+        if (sb[mid] <= g) lo = mid;
         else hi = mid;
     }
-    src[i] = ((u64)lo << 32) | (u64)(g - run_off[lo]);
-    id[i] = fc_id[g];
-    lcp[i] = i == 0 ? 0u : L[i];
+    src[x] = ((u64)sid[lo] << 32) | (u64)(g - sb[lo]);
+    id[x] = fc_id[g];
+    lcp[x] = L[x];
+}
+
+__global__ __launch_bounds__(256) void k_check_merge_runs(const u64 *rb, const u64 *re, u32 k, u64 n_fc,
+                                                          const u32 *e, const u32 *d, u32 *bad)
+{
+    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < k) {
+        if (re[i] < rb[i] || re[i] > n_fc) atomicOr(bad, 1u);
+        else if (re[i] > rb[i] && e[rb[i]] != 0) atomicOr(bad, 2u);
+    }
+    if (i < n_fc) {
+        if (e[i] > d[i]) atomicOr(bad, 4u);
+        if (i > 0 && e[i] > d[i - 1]) atomicOr(bad, 4u);
+    }
 }
 
 struct MergeWs {
     DecWs dec;
-    u64 *doff;
-    u32 *G0, *G1, *L0, *L1;
-    u64 *R;
-    u32 *tstart;
+    u32 *G0, *G1, *L0, *L1, *F0, *F1, *pc, *tstart, *sid;
+    u8 *pfirst;
+    u64 *PA0, *PA1, *PB1, *P, *sb;
 };
-
-// Fixed part of the merge workspace; the decoded bytes take the rest.
-static void merge_layout(u64 n, u64 k, MergeWs *w, WsArena *a, WsCounter *c)
-{
-    dec_layout(n, &w->dec, a, c);
-    if (a) {
-        w->doff = a->take<u64>(n + 1);
-        w->G0 = a->take<u32>(n);
-        w->G1 = a->take<u32>(n);
-        w->L0 = a->take<u32>(n);
-        w->L1 = a->take<u32>(n);
-        w->R = a->take<u64>(k + 2);
-        w->tstart = a->take<u32>(k + 2);
-    } else {
-        c->take<u64>(n + 1);
-        c->take<u32>(n);
-        c->take<u32>(n);
-        c->take<u32>(n);
-        c->take<u32>(n);
-        c->take<u64>(k + 2);
-        c->take<u32>(k + 2);
-    }
-}
 
 #define MERGE_MAX_K 65536
 
-extern "C" size_t ss_lcp_merge_workspace(uint64_t n, uint64_t total_len)
+static void merge_layout(u64 n_out, u64 n_fc, u64 k, MergeWs *w, WsArena *a, WsCounter *c)
+{
+    dec_layout(n_fc, &w->dec, a, c);
+#define MT(field, T, cnt)                       \
+    do {                                         \
+        if (a) w->field = a->take<T>(cnt);       \
+        else c->take<T>(cnt);                    \
+    } while (0)
+    MT(G0, u32, n_out); MT(G1, u32, n_out); MT(L0, u32, n_out); MT(L1, u32, n_out);
+    MT(F0, u32, n_out); MT(F1, u32, n_out);
+    MT(pc, u32, k + 2); MT(tstart, u32, k + 2); MT(sid, u32, k + 2); MT(pfirst, u8, k + 2);
+    MT(PA0, u64, k + 2); MT(PA1, u64, k + 2); MT(PB1, u64, k + 2); MT(P, u64, k + 2); MT(sb, u64, k + 2);
+#undef MT
+}
+
+extern "C" size_t ss_lcp_merge_workspace(uint64_t n_out, uint64_t n_fc, uint32_t k)
 {
     WsCounter c;
     MergeWs w;
-    merge_layout(n, MERGE_MAX_K, &w, nullptr, &c);
-    c.take<u8>(total_len + 16);
+    merge_layout(n_out, n_fc, k, &w, nullptr, &c);
     return c.used;
 }
 
-extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_off, const uint32_t *fc_lcp, const uint32_t *fc_len,
-                            const uint32_t *fc_id, const uint64_t *suf_off, const uint8_t *suf, uint64_t n,
-                            uint64_t *out_src, uint32_t *out_id, uint32_t *out_lcp, void *ws, size_t ws_bytes,
-                            void *stream)
+extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_t *run_end, uint32_t groups,
+                            const uint32_t *group_off, uint64_t n_fc, const uint32_t *fc_lcp, const uint32_t *fc_len,
+                            const uint32_t *fc_id, const uint64_t *suf_off, const uint8_t *suf, uint64_t *out_src,
+                            uint32_t *out_id, uint32_t *out_lcp, void *ws, size_t ws_bytes, void *stream)
 {
     ss_clear_error();
-    if (n >= 0xFFFFFFFFull) { ss_set_error("n too large"); return SS_ERR_TOO_LARGE; }
-    if (k == 0 || k > MERGE_MAX_K || !run_off || (n > 0 && (!fc_lcp || !fc_len || !fc_id || !suf_off || !out_src ||
-                                                             !out_id || !out_lcp))) {
-        ss_set_error("lcp_merge: bad arguments (1 <= k <= %d)", MERGE_MAX_K);
+    if (n_fc >= 0xFFFFFFFFull) { ss_set_error("n_fc too large"); return SS_ERR_TOO_LARGE; }
+    if (k == 0 || k > MERGE_MAX_K || groups == 0 || !run_begin || !run_end || !group_off) {
+        ss_set_error("lcp_merge: bad arguments (1 <= k <= %d, groups >= 1)", MERGE_MAX_K);
         return SS_ERR_INVALID_ARG;
     }
     hipStream_t st = (hipStream_t)stream;
-    std::vector<u64> R(k + 1);
-    SS_HIP(hipMemcpyAsync(R.data(), run_off, sizeof(u64) * (k + 1), hipMemcpyDeviceToHost, st));
+    std::vector<u64> rb(k), re(k);
+    std::vector<u32> go(groups + 1);
+    SS_HIP(hipMemcpyAsync(rb.data(), run_begin, sizeof(u64) * k, hipMemcpyDeviceToHost, st));
+    SS_HIP(hipMemcpyAsync(re.data(), run_end, sizeof(u64) * k, hipMemcpyDeviceToHost, st));
+    SS_HIP(hipMemcpyAsync(go.data(), group_off, sizeof(u32) * (groups + 1), hipMemcpyDeviceToHost, st));
     SS_HIP(hipStreamSynchronize(st));
-    if (R[0] != 0 || R[k] != n) {
-        ss_set_error("run_off must start at 0 and end at n");
+    if (go[0] != 0 || go[groups] != k) {
+        ss_set_error("group_off must start at 0 and end at k");
         return SS_ERR_INVALID_ARG;
     }
+    std::vector<u64> P(k + 1, 0);
+    for (u32 j = 0; j < k; j++) {
+        if (re[j] < rb[j] || re[j] > n_fc) {
+            ss_set_error("run %u = [%llu, %llu) is not inside the %llu front-coded entries", j,
+                         (unsigned long long)rb[j], (unsigned long long)re[j], (unsigned long long)n_fc);
+            return SS_ERR_INVALID_ARG;
+        }
+        P[j + 1] = P[j] + (re[j] - rb[j]);
+    }
+    for (u32 g = 0; g < groups; g++)
+        if (go[g + 1] < go[g]) {
+            ss_set_error("group_off must be non-decreasing");
+            return SS_ERR_INVALID_ARG;
+        }
+    const u64 n_out = P[k];
+    if (n_out == 0) return SS_OK;
+    if (!fc_lcp || !fc_len || !fc_id || !suf_off || !out_src || !out_id || !out_lcp) {
+        ss_set_error("lcp_merge: null array");
+        return SS_ERR_INVALID_ARG;
+    }
+    // non-empty runs sorted by front-coded start, to map positions back to runs
+    std::vector<u32> order;
+    for (u32 j = 0; j < k; j++)
+        if (re[j] > rb[j]) order.push_back(j);
+    std::sort(order.begin(), order.end(), [&](u32 x, u32 y) { return rb[x] < rb[y]; });
+    for (size_t t = 1; t < order.size(); t++)
+        if (re[order[t - 1]] > rb[order[t]]) {
+            ss_set_error("runs overlap");
+            return SS_ERR_INVALID_ARG;
+        }
+    const u32 kne = (u32)order.size();
+    std::vector<u64> sbv(kne);
+    std::vector<u32> sidv(kne);
+    for (u32 t = 0; t < kne; t++) { sbv[t] = rb[order[t]]; sidv[t] = order[t]; }
+
     WsArena a(ws, ws_bytes);
     MergeWs w;
-    merge_layout(n, MERGE_MAX_K, &w, &a, nullptr);
+    merge_layout(n_out, n_fc, k, &w, &a, nullptr);
     if (a.overflow || !ws) {
-        ss_set_error("workspace too small: need %zu bytes plus the decoded bytes", ss_lcp_merge_workspace(n, 0));
+        ss_set_error("workspace too small: need %zu bytes", ss_lcp_merge_workspace(n_out, n_fc, k));
         return SS_ERR_WORKSPACE;
     }
-    u8 *db = a.base + a.used;
-    const u64 budget = ws_bytes - a.used;
-    SS_TRY(decode_impl(k, run_off, fc_lcp, fc_len, suf_off, suf, n, w.doff, db, budget, w.dec, st));
-    if (n == 0) return SS_OK;
-    u64 dN;
-    SS_TRY(ss_read_u64(w.doff + n, &dN, 1, st));
-    k_merge_init<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(fc_lcp, (u32)n, w.G0, w.L0);
+    SS_HIP(hipMemcpyAsync(w.P, P.data(), sizeof(u64) * (k + 1), hipMemcpyHostToDevice, st));
+    SS_HIP(hipMemcpyAsync(w.sb, sbv.data(), sizeof(u64) * kne, hipMemcpyHostToDevice, st));
+    SS_HIP(hipMemcpyAsync(w.sid, sidv.data(), sizeof(u32) * kne, hipMemcpyHostToDevice, st));
+    SS_HIP(hipMemsetAsync(w.dec.bad, 0, sizeof(u32), st));
+    k_check_merge_runs<<<(unsigned)ceil_div((n_fc > k ? n_fc : k) + 1, 256), 256, 0, st>>>(
+        run_begin, run_end, k, n_fc, fc_lcp, fc_len, w.dec.bad);
     SS_CHECK_LAUNCH();
-    u32 *G = w.G0, *L = w.L0, *Go = w.G1, *Lo = w.L1;
-    std::vector<u64> cur(R);
+    u32 bad;
+    u64 sufN;
+    SS_TRY(ss_read_u32(w.dec.bad, &bad, 1, st));
+    SS_TRY(ss_read_u64(suf_off + n_fc, &sufN, 1, st));
+    if (bad) {
+        ss_set_error("malformed front-coded runs (code %u): runs must start with e = 0 and e_i <= d_i, "
+                     "e_i <= d_{i-1}", bad);
+        return SS_ERR_INVALID_ARG;
+    }
+    // psv chains over the whole front-coded array (no decoding of the strings)
+    const u32 nb = (u32)ceil_div(n_fc, DB);
+    k_psv_block<<<nb, DB, 0, st>>>(fc_lcp, (u32)n_fc, w.dec.psv, w.dec.bmin);
+    SS_CHECK_LAUNCH();
+    const u32 per = DSB / DB;
+    const u32 nsb = (u32)ceil_div(nb, per);
+    k_min_reduce<<<(unsigned)ceil_div(nsb, 256), 256, 0, st>>>(w.dec.bmin, nb, per, w.dec.smin);
+    SS_CHECK_LAUNCH();
+    k_psv_far<<<(unsigned)ceil_div(n_fc, 256), 256, 0, st>>>(fc_lcp, (u32)n_fc, w.dec.bmin, w.dec.smin, w.dec.psv);
+    SS_CHECK_LAUNCH();
+    k_merge_init<<<(unsigned)ceil_div(n_out, 256), 256, 0, st>>>(run_begin, w.P, k, (u32)n_out, fc_lcp, w.dec.psv,
+                                                                 w.G0, w.L0, w.F0);
+    SS_CHECK_LAUNCH();
+    const FcView V{fc_lcp, fc_len, w.dec.psv, suf_off, suf, sufN};
+    u32 *G = w.G0, *L = w.L0, *F = w.F0, *Go = w.G1, *Lo = w.L1, *Fo = w.F1;
+    // segments of the output space per group
+    std::vector<std::vector<std::pair<u64, u64>>> segs(groups);
+    for (u32 g = 0; g < groups; g++)
+        for (u32 j = go[g]; j < go[g + 1]; j++) segs[g].push_back({P[j], P[j + 1]});
+    std::vector<u64> pa0, pa1, pb1;
     std::vector<u32> ts;
-    while (cur.size() - 1 > 1) {
-        const u32 nr = (u32)(cur.size() - 1);
-        const u32 np = (nr + 1) / 2;
-        ts.assign(np + 1, 0);
-        for (u32 p = 0; p < np; p++) {
-            const u64 sz = cur[std::min<u64>(2 * p + 2, nr)] - cur[2 * p];
-            ts[p + 1] = ts[p] + (u32)ceil_div(sz ? sz : 1, MG_PER);
+    for (;;) {
+        bool more = false;
+        for (auto &sg : segs) more |= sg.size() > 1;
+        if (!more) break;
+        pa0.clear(); pa1.clear(); pb1.clear(); ts.assign(1, 0);
+        std::vector<std::vector<std::pair<u64, u64>>> nxt(groups);
+        for (u32 g = 0; g < groups; g++) {
+            auto &sg = segs[g];
+            for (size_t m = 0; m < sg.size(); m += 2) {
+                const u64 A0 = sg[m].first, A1 = sg[m].second;
+                const u64 B1 = (m + 1 < sg.size()) ? sg[m + 1].second : A1;
+                nxt[g].push_back({A0, B1});
+                if (sg.size() == 1) continue;  // a lone run of its group is final
+                pa0.push_back(A0); pa1.push_back(A1); pb1.push_back(B1);
+                const u64 sz = B1 - A0;
+                ts.push_back(ts.back() + (u32)ceil_div(sz ? sz : 1, MG_PER));
+            }
         }
-        SS_HIP(hipMemcpyAsync(w.R, cur.data(), sizeof(u64) * (nr + 1), hipMemcpyHostToDevice, st));
-        SS_HIP(hipMemcpyAsync(w.tstart, ts.data(), sizeof(u32) * (np + 1), hipMemcpyHostToDevice, st));
-        MergeLevel M{G, L, Go, Lo, w.R, w.tstart, np, nr, db, dN, w.doff};
-        const u32 nth = ts[np];
-        k_merge_level<<<(unsigned)ceil_div(nth, 256), 256, 0, st>>>(M, nth);
+        const u32 np = (u32)pa0.size();
+        // groups already merged keep their arrays: copy them through as lone pairs
+        for (u32 g = 0; g < groups; g++) {
+            if (segs[g].size() == 1 && segs[g][0].second > segs[g][0].first) {
+                pa0.push_back(segs[g][0].first); pa1.push_back(segs[g][0].second); pb1.push_back(segs[g][0].second);
+                const u64 sz = segs[g][0].second - segs[g][0].first;
+                ts.push_back(ts.back() + (u32)ceil_div(sz, MG_PER));
+            }
+        }
+        const u32 npt = (u32)pa0.size();
+        if (npt > k + 1) {
+            ss_set_error("internal: too many merge pairs");
+            return SS_ERR_INVALID_ARG;
+        }
+        (void)np;
+        SS_HIP(hipMemcpyAsync(w.PA0, pa0.data(), sizeof(u64) * npt, hipMemcpyHostToDevice, st));
+        SS_HIP(hipMemcpyAsync(w.PA1, pa1.data(), sizeof(u64) * npt, hipMemcpyHostToDevice, st));
+        SS_HIP(hipMemcpyAsync(w.PB1, pb1.data(), sizeof(u64) * npt, hipMemcpyHostToDevice, st));
+        SS_HIP(hipMemcpyAsync(w.tstart, ts.data(), sizeof(u32) * (npt + 1), hipMemcpyHostToDevice, st));
+        MergeLevel M{G, L, F, Go, Lo, Fo, w.PA0, w.PA1, w.PB1, w.tstart, w.pc, w.pfirst, npt, V};
+        k_pair_info<<<(unsigned)ceil_div(npt, 64), 64, 0, st>>>(M);
         SS_CHECK_LAUNCH();
-        // the host vectors must stay valid until the copies ran
-        SS_HIP(hipStreamSynchronize(st));
-        std::vector<u64> nxt;
-        for (u32 p = 0; p < np; p++) nxt.push_back(cur[2 * p]);
-        nxt.push_back(cur[nr]);
-        cur.swap(nxt);
+        const u32 nth = ts[npt];
+        if (nth > 0) {
+            k_merge_level<<<(unsigned)ceil_div(nth, 256), 256, 0, st>>>(M, nth);
+            SS_CHECK_LAUNCH();
+        }
+        SS_HIP(hipStreamSynchronize(st));  // keeps the host vectors alive until the copies ran
+        segs.swap(nxt);
         std::swap(G, Go);
         std::swap(L, Lo);
+        std::swap(F, Fo);
     }
-    k_merge_out<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(G, L, (u32)n, run_off, k, fc_id, out_src, out_id,
-                                                            out_lcp);
+    k_merge_out<<<(unsigned)ceil_div(n_out, 256), 256, 0, st>>>(G, L, (u32)n_out, w.sb, w.sid, kne, fc_id,
+                                                                out_src, out_id, out_lcp);
     SS_CHECK_LAUNCH();
     return SS_OK;
 }

@@ -170,6 +170,12 @@ __global__ __launch_bounds__(256) void k_fc_meta(const u64 *off, u32 n, const u3
     }
 }
 
+__global__ void k_add_base(u64 *a, u64 n, u64 base)
+{
+    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] += base;
+}
+
 #define CP_NT 256
 #define CP_PER 16
 
@@ -177,8 +183,15 @@ __global__ __launch_bounds__(256) void k_fc_meta(const u64 *off, u32 n, const u3
 // output bytes; the workgroup first finds the range of strings its 4096 bytes
 // cover, then each thread locates its string inside that range.
 __global__ __launch_bounds__(CP_NT) void k_fc_copy(const u8 *bytes, const u64 *off, u32 n, const u32 *perm,
-                                                   const u32 *fc_lcp, const u64 *suf_off, u64 total, u8 *suf)
+                                                   const u32 *fc_lcp, const u64 *suf_off_abs, u64 base, u64 total,
+                                                   u8 *suf)
 {
+    // suf_off_abs includes `base`; positions below are relative to it
+    struct Rel {
+        const u64 *p; u64 b;
+        __device__ u64 operator[](u64 i) const { return p[i] - b; }
+    } suf_off{suf_off_abs, base};
+    suf += base;
     __shared__ u32 range[2];
     const u64 c0 = (u64)blockIdx.x * CP_NT * CP_PER;
     const u64 c1 = (c0 + CP_NT * CP_PER < total) ? c0 + CP_NT * CP_PER : total;
@@ -247,8 +260,9 @@ extern "C" int ss_partition_encode(const uint8_t *bytes, uint64_t N, const uint6
                                    const uint32_t *perm, const uint32_t *lcp, const uint32_t *dist,
                                    const uint8_t *spl_bytes, uint64_t spl_N, const uint64_t *spl_offsets,
                                    uint32_t r, uint64_t *run_off, uint32_t *fc_lcp, uint32_t *fc_len,
-                                   uint32_t *fc_id, uint64_t *suf_off, uint8_t *suf, uint64_t suf_cap,
-                                   uint64_t *suf_total_host, void *ws, size_t ws_bytes, void *stream)
+                                   uint32_t *fc_id, uint64_t *suf_off, uint8_t *suf, uint64_t suf_base,
+                                   uint64_t suf_cap, uint64_t *suf_total_host, void *ws, size_t ws_bytes,
+                                   void *stream)
 {
     ss_clear_error();
     if (n >= 0xFFFFFFFFull) { ss_set_error("n too large"); return SS_ERR_TOO_LARGE; }
@@ -272,15 +286,20 @@ extern "C" int ss_partition_encode(const uint8_t *bytes, uint64_t N, const uint6
         SS_CHECK_LAUNCH();
     }
     SS_TRY(ss_scan_exclusive<u64>(suf_off, suf_off, n, scratch, st));
+    if (suf_base) {
+        k_add_base<<<(unsigned)ceil_div(n + 1, 256), 256, 0, st>>>(suf_off, n + 1, suf_base);
+        SS_CHECK_LAUNCH();
+    }
     u64 total;
     u32 hbad;
     SS_TRY(ss_read_u64(suf_off + n, &total, 1, st));
+    total -= suf_base;
     SS_TRY(ss_read_u32(bad, &hbad, 1, st));
     if (hbad) {
         ss_set_error("front coding needs lcp <= dist <= len at every position");
         return SS_ERR_INVALID_ARG;
     }
-    if (total > suf_cap) {
+    if (suf_base + total > suf_cap) {
         ss_set_error("literal bytes %llu exceed capacity %llu", (unsigned long long)total,
                      (unsigned long long)suf_cap);
         return SS_ERR_CAPACITY;
@@ -288,7 +307,8 @@ extern "C" int ss_partition_encode(const uint8_t *bytes, uint64_t N, const uint6
     if (suf_total_host) *suf_total_host = total;
     if (total > 0) {
         k_fc_copy<<<(unsigned)ceil_div(total, CP_NT * CP_PER), CP_NT, 0, st>>>(bytes, offsets, (u32)n, perm,
-                                                                             fc_lcp, suf_off, total, suf);
+                                                                             fc_lcp, suf_off, suf_base, total,
+                                                                             suf);
         SS_CHECK_LAUNCH();
     }
     return SS_OK;

@@ -124,7 +124,11 @@ __global__ void k_sizes(const Seg *segs, u32 nseg, u32 *out)
 
 // ------------------------------------------------------------ round kernels
 
+#define SKG 16  // lanes per string in the skip kernel: 128 consecutive bytes per step
+
 // Minimum LCP of every member with the segment's first string, from `depth`.
+// A group of 16 lanes compares 128 consecutive bytes of one member with the
+// first string per step (coalesced reads of both).
 __global__ __launch_bounds__(NT) void k_skip(const Seg *segs, const u32 *tstart, u32 nseg,
                                              const u8 *bytes, u64 N, const u64 *off,
                                              const u32 *perm, u32 *skipv)
@@ -138,15 +142,35 @@ __global__ __launch_bounds__(NT) void k_skip(const Seg *segs, const u32 *tstart,
     const u32 b1 = min(g.end, b0 + ETILE);
     const u32 f = perm[g.begin];
     const u64 fo = off[f], fl = off[f + 1] - fo;
-    u32 best = 0xFFFFFFFFu;
-    for (u32 i = b0 + threadIdx.x; i < b1; i += NT) {
+    const u32 grp = threadIdx.x / SKG, lane = threadIdx.x % SKG;
+    u64 best = ~0ull;
+    for (u32 i = b0 + grp; i < b1; i += NT / SKG) {
         const u32 p = perm[i];
         const u64 o = off[p], l = off[p + 1] - o;
-        u64 c = str_lcp_from(bytes, N, o, l, fo, fl, g.depth) - g.depth;
-        best = min(best, (u32)c);
+        const u64 m = l < fl ? l : fl;
+        u64 res = m;
+        for (u64 x = g.depth; x < m; x += 8 * SKG) {
+            const u64 q = x + 8 * lane;
+            const u32 take = q < m ? (u32)((m - q) < 8 ? (m - q) : 8) : 0u;
+            const u64 wa = load_be(bytes, N, o + q, take);
+            const u64 wb = load_be(bytes, N, fo + q, take);
+            u64 pos = (wa != wb) ? q + (__clzll(wa ^ wb) >> 3) : ~0ull;
+#pragma unroll
+            for (int s2 = SKG / 2; s2 > 0; s2 >>= 1) {
+                const u64 y = __shfl_xor(pos, s2, SKG);
+                pos = y < pos ? y : pos;
+            }
+            if (pos != ~0ull) {
+                res = pos;
+                break;
+            }
+        }
+        const u64 c = res - g.depth;
+        best = c < best ? c : best;
     }
-    best = block_min(best);
-    if (threadIdx.x == 0) atomicMin(&skipv[s], best);
+    const u32 b32 = best > 0xFFFFFFFFull ? 0xFFFFFFFFu : (u32)best;
+    const u32 bm = block_min(b32);
+    if (threadIdx.x == 0) atomicMin(&skipv[s], bm);
 }
 
 __global__ __launch_bounds__(NT) void k_keys(const Seg *segs, const u32 *tstart, u32 nseg,

@@ -37,7 +37,7 @@ def test_workspace_queries_grow_with_n():
               "ss_fc_decode_workspace", "ss_gather_workspace"):
         a, b = getattr(L, f)(1000), getattr(L, f)(1_000_000)
         assert 0 < a < b, f
-    assert L.ss_lcp_merge_workspace(1000, 10**6) > L.ss_lcp_merge_workspace(1000, 0)
+    assert L.ss_lcp_merge_workspace(1000, 10**6, 4) > L.ss_lcp_merge_workspace(1000, 1000, 4)
 
 
 def test_argument_errors_without_device():
@@ -57,7 +57,10 @@ def test_argument_errors_without_device():
     # select_splitters needs r >= 1 and n >= 1
     assert L.ss_select_splitters(0, P(8), 4, P(8), None) == -1
     # merge needs 1 <= k <= 65536
-    assert L.ss_lcp_merge(0, P(8), P(8), P(8), P(8), P(8), P(8), 1, P(8), P(8), P(8), None, 0, None) == -1
+    assert L.ss_lcp_merge(0, P(8), P(8), 1, P(8), 1, P(8), P(8), P(8), P(8), P(8), P(8), P(8), P(8), None, 0,
+                          None) == -1
+    assert L.ss_lcp_merge(4, P(8), P(8), 0, P(8), 1, P(8), P(8), P(8), P(8), P(8), P(8), P(8), P(8), None, 0,
+                          None) == -1
 
 
 def test_tuning_validation():

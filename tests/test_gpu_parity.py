@@ -289,7 +289,7 @@ def test_lcp_merge_matches_oracle(k, seed, pdms):
     _log(f"[merge] k={k}")
     ro, lc, ln, idv, so, suf = _runs_from_oracle(s, k, seed, pdms)
     T = lambda a, dt: torch.from_numpy(a.view(dt).copy()).to(DEV)
-    src, gid, glcp = ss.lcp_merge(T(ro, np.int64), T(lc, np.int32), T(ln, np.int32), T(idv, np.int32),
+    src, gid, glcp = ss.lcp_merge_runs(T(ro, np.int64), T(lc, np.int32), T(ln, np.int32), T(idv, np.int32),
                                   T(so, np.int64), torch.from_numpy(suf.copy()).to(DEV))
     torch.cuda.synchronize()
     rsrc, rid, rlcp = oracle.merge(ro, lc, ln, idv, so, suf)
@@ -304,8 +304,79 @@ def test_lcp_merge_dn_closed_form():
     s = synth.dn_strings(n, 64, 0.3, seed=7)
     ro, lc, ln, idv, so, suf = _runs_from_oracle(s, 32, 7)
     T = lambda a, dt: torch.from_numpy(a.view(dt).copy()).to(DEV)
-    _, gid, glcp = ss.lcp_merge(T(ro, np.int64), T(lc, np.int32), T(ln, np.int32), T(idv, np.int32),
+    _, gid, glcp = ss.lcp_merge_runs(T(ro, np.int64), T(lc, np.int32), T(ln, np.int32), T(idv, np.int32),
                                 T(so, np.int64), torch.from_numpy(suf.copy()).to(DEV))
     pi = s.meta["pi"].numpy()
     np.testing.assert_array_equal(u32(gid), cf.dn_perm(pi))
     np.testing.assert_array_equal(u32(glcp), cf.dn_lcp(n, s.meta["k"], s.meta["filler"]))
+
+
+def test_lcp_merge_groups_runs_in_place():
+    """Several groups merged in one call; runs scattered in shuffled order inside
+    shared front-coded arrays (as the buckets each processing element receives)."""
+    rng = np.random.default_rng(11)
+    groups = []
+    for gi, (n, k) in enumerate([(3000, 4), (1, 1), (5000, 9), (0, 2), (2000, 3)]):
+        s = synth.text_strings(max(n, 1), seed=40 + gi, median=9) if n else synth.from_list([])
+        if n == 1:
+            s = synth.from_list([b"only"])
+        groups.append((s, k) if n else (synth.from_list([]), k))
+    # encode every group's runs with the oracle
+    blocks = []   # (group, run-in-group, dict)
+    for gi, (s, k) in enumerate(groups):
+        ro, lc, ln, idv, so, suf = _runs_from_oracle(s, k, 100 + gi) if s.n else (
+            np.zeros(k + 1, np.uint64), np.zeros(0, np.uint32), np.zeros(0, np.uint32), np.zeros(0, np.uint32),
+            np.zeros(1, np.uint64), np.zeros(0, np.uint8))
+        for j in range(k):
+            a, b = int(ro[j]), int(ro[j + 1])
+            blocks.append((gi, j, dict(lcp=lc[a:b], len=ln[a:b], id=idv[a:b],
+                                       suf=suf[int(so[a]):int(so[b])] if b > a else np.zeros(0, np.uint8),
+                                       so=(so[a:b] - so[a]) if b > a else np.zeros(0, np.uint64))))
+    order = rng.permutation(len(blocks))
+    FL, FD, FI, FS, SUF = [], [], [], [], []
+    pos, sbase, where = 0, 0, {}
+    for bi in order:
+        gi, j, d = blocks[bi]
+        m = len(d["lcp"])
+        where[(gi, j)] = (pos, pos + m)
+        FL.append(d["lcp"]); FD.append(d["len"]); FI.append(d["id"]); FS.append(d["so"] + sbase)
+        SUF.append(d["suf"]); sbase += len(d["suf"]); pos += m
+    fl = np.concatenate(FL); fd = np.concatenate(FD); fi = np.concatenate(FI)
+    so_all = np.concatenate(FS + [np.array([sbase], np.uint64)]); suf_all = np.concatenate(SUF)
+    rb, re_, gofs = [], [], [0]
+    for gi, (s, k) in enumerate(groups):
+        for j in range(k):
+            a, b = where[(gi, j)]
+            rb.append(a); re_.append(b)
+        gofs.append(len(rb))
+    T = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).view(dt).copy()).to(DEV)
+    src, gid, glcp = ss.lcp_merge(torch.tensor(rb, dtype=torch.int64), torch.tensor(re_, dtype=torch.int64),
+                                  torch.tensor(gofs, dtype=torch.int32), T(fl, np.int32), T(fd, np.int32),
+                                  T(fi, np.int32), T(so_all, np.int64), torch.from_numpy(suf_all.copy()).to(DEV))
+    torch.cuda.synchronize()
+    S, I, L = u64(src), u32(gid), u32(glcp)
+    out = 0
+    for gi, (s, k) in enumerate(groups):
+        # oracle: merge this group's runs laid out contiguously
+        ro = [0]; lcs, lns, ids, sos, sufs = [], [], [], [], []
+        base = 0
+        for j in range(k):
+            a, b = where[(gi, j)]
+            lcs.append(fl[a:b]); lns.append(fd[a:b]); ids.append(fi[a:b])
+            if b > a:
+                seg = suf_all[int(so_all[a]):int(so_all[b])]
+                sos.append(so_all[a:b] - so_all[a] + base); sufs.append(seg); base += len(seg)
+            ro.append(ro[-1] + (b - a))
+        m = ro[-1]
+        if m == 0:
+            continue
+        rsrc, rid, rlcp = oracle.merge(np.array(ro, np.uint64), np.concatenate(lcs), np.concatenate(lns),
+                                       np.concatenate(ids), np.concatenate(sos + [np.array([base], np.uint64)]),
+                                       np.concatenate(sufs) if sufs else np.zeros(0, np.uint8))
+        run_base = gofs[gi]
+        exp_src = ((rsrc >> np.uint64(32)) + np.uint64(run_base)) << np.uint64(32) | (rsrc & np.uint64(0xFFFFFFFF))
+        np.testing.assert_array_equal(S[out:out + m], exp_src)
+        np.testing.assert_array_equal(I[out:out + m], rid)
+        np.testing.assert_array_equal(L[out:out + m], rlcp)
+        out += m
+    assert out == len(S)
