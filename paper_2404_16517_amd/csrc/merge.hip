@@ -340,6 +340,10 @@ __device__ __forceinline__ int fc_cmp(const FcView &V, u32 x, u32 y, u64 from, u
 struct MergeLevel {
     const u32 *G, *L, *F;  // element ids (FC positions), LCP with predecessor, first-LCP bound
     u32 *Go, *Lo, *Fo;
+    const u64 *K;          // cached key: 7 bytes at the group depth + remaining length (capped at 8)
+    u64 *Ko;
+    const u32 *pg;         // per pair: group
+    const u32 *Cg;         // per group: common prefix length of all its strings
     const u64 *PA0, *PA1, *PB1;  // per pair: run A = [PA0, PA1), run B = [PA1, PB1) in output space
     const u32 *tstart;           // first thread of each pair (npairs+1)
     u32 *pc;                     // per pair: lcp of the two runs' first strings
@@ -349,6 +353,27 @@ struct MergeLevel {
 };
 
 __device__ __forceinline__ u32 min3u(u32 a, u32 b, u32 c) { return min(a, min(b, c)); }
+
+// Compare two elements of one group whose strings agree on [0, bound): first by
+// their cached keys at the group depth C (bytes [C, C+7) and the remaining
+// length), then, on equal keys of continuing strings, on the strings from C+7.
+__device__ __forceinline__ int cmp_elem(const FcView &V, u32 gx, u64 kx, u32 gy, u64 ky, u32 bound, u32 C,
+                                        u64 *lcp)
+{
+    if (bound < C + 7) {
+        if (kx != ky) {
+            *lcp = key_lcp(kx, ky, C);
+            return kx < ky ? -1 : 1;
+        }
+        const u32 cnt = (u32)(kx & 0xFF);
+        if (cnt < 8) {
+            *lcp = C + cnt;
+            return 0;
+        }
+        bound = C + 7;
+    }
+    return fc_cmp(V, gx, gy, bound, lcp);
+}
 
 // Output-space element x of run j: its front-coded position, its LCP with the
 // run predecessor, and a lower bound on its LCP with the run's first string:
@@ -409,94 +434,213 @@ __global__ void k_pair_info(MergeLevel M)
     M.pfirst[p] = fa;
 }
 
-__global__ __launch_bounds__(256) void k_merge_level(MergeLevel M, u32 nthreads)
+#define MW_NT 256
+#define MW_IPT 8
+#define MW_TILE (MW_NT * MW_IPT)  // outputs per workgroup
+
+// co-rank in global memory: number of A elements among the first d outputs
+__device__ u32 corank_global(const MergeLevel &M, u64 A0, u32 na, u64 B0, u32 nb, u32 d, u32 c, u32 C)
 {
-    const u32 t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nthreads) return;
+    const u32 *GA = M.G + A0, *FA = M.F + A0, *GB = M.G + B0, *FB = M.F + B0;
+    const u64 *KA = M.K + A0, *KB = M.K + B0;
+    u32 xlo = d > nb ? d - nb : 0, xhi = d < na ? d : na;
+    u64 tmp;
+    while (xlo < xhi) {
+        const u32 mid = (xlo + xhi) >> 1;
+        const u32 y = d - mid - 1;
+        if (cmp_elem(M.V, GA[mid], KA[mid], GB[y], KB[y], min3u(FA[mid], c, FB[y]), C, &tmp) <= 0) xlo = mid + 1;
+        else xhi = mid;
+    }
+    return xlo;
+}
+
+// One merge level, merge-path style: each workgroup produces MW_TILE outputs of
+// one pair.  Its A and B windows (plus the element before each) are staged in
+// LDS; every thread co-ranks its 8 outputs inside the window and merges them
+// with the LCP rule; outputs are written back through LDS.
+__global__ __launch_bounds__(MW_NT) void k_merge_level(MergeLevel M, u32 nblocks)
+{
+    __shared__ u32 sG[MW_TILE + 2], sL[MW_TILE + 2], sF[MW_TILE + 2];
+    __shared__ u64 sK[MW_TILE + 2];
+    __shared__ u32 win[4];
+    const u32 blk = blockIdx.x;
+    if (blk >= nblocks) return;
     u32 lo = 0, hi = M.npairs;
     while (hi - lo > 1) {
         u32 mid = (lo + hi) >> 1;
-        if (M.tstart[mid] <= t) lo = mid;
+        if (M.tstart[mid] <= blk) lo = mid;
         else hi = mid;
     }
     const u32 p = lo;
     const u64 A0 = M.PA0[p], A1 = M.PA1[p], B0 = A1, B1 = M.PB1[p];
     const u32 na = (u32)(A1 - A0), nb = (u32)(B1 - B0);
-    const u32 dloc = (t - M.tstart[p]) * MG_PER;
     const u32 tot = na + nb;
-    if (dloc >= tot) return;
-    const u32 cnt = (tot - dloc) < MG_PER ? (tot - dloc) : MG_PER;
-    const u32 *GA = M.G + A0, *LA = M.L + A0, *FA = M.F + A0;
-    const u32 *GB = M.G + B0, *LB = M.L + B0, *FB = M.F + B0;
+    const u32 d0 = (blk - M.tstart[p]) * MW_TILE;
+    if (d0 >= tot) return;
+    const u32 d1 = min(tot, d0 + MW_TILE);
     const u32 c = M.pc[p];
+    const u32 C = M.Cg[M.pg[p]];
     const bool firstA = M.pfirst[p] != 0;
-    u64 tmp;
-    // co-rank: x = number of A elements among the first dloc outputs
-    u32 xlo = dloc > nb ? dloc - nb : 0, xhi = dloc < na ? dloc : na;
-    while (xlo < xhi) {
-        const u32 mid = (xlo + xhi) >> 1;
-        const u32 y = dloc - mid - 1;
-        if (fc_cmp(M.V, GA[mid], GB[y], min3u(FA[mid], c, FB[y]), &tmp) <= 0) xlo = mid + 1;
-        else xhi = mid;
+    if (threadIdx.x == 0) win[0] = corank_global(M, A0, na, B0, nb, d0, c, C);
+    if (threadIdx.x == 64) win[1] = (d1 == tot) ? na : corank_global(M, A0, na, B0, nb, d1, c, C);
+    __syncthreads();
+    const u32 a0 = win[0], a1 = win[1];
+    const u32 b0 = d0 - a0, b1 = d1 - a1;
+    const u32 wa = a1 - a0, wb = b1 - b0;
+    // LDS layout: [pa | A window (wa) | pb | B window (wb)], pa/pb = element before the window
+    const u32 baseA = 1, baseB = wa + 2;
+    for (u32 i = threadIdx.x; i < wa + 1; i += MW_NT) {
+        if (i == 0 && a0 == 0) continue;
+        const u64 gi = A0 + a0 + i - 1;
+        sG[i] = M.G[gi]; sL[i] = M.L[gi]; sF[i] = M.F[gi]; sK[i] = M.K[gi];
     }
-    u32 a = xlo, b = dloc - xlo;
-    u32 ha = 0, hb = 0;
-    if (dloc > 0) {
-        bool lastA;
-        if (a == 0) lastA = false;
-        else if (b == 0) lastA = true;
-        else lastA = fc_cmp(M.V, GA[a - 1], GB[b - 1], min3u(FA[a - 1], c, FB[b - 1]), &tmp) > 0;
-        if (lastA) {
-            if (a < na) ha = LA[a];
-            if (b < nb) { fc_cmp(M.V, GA[a - 1], GB[b], min3u(FA[a - 1], c, FB[b]), &tmp); hb = (u32)tmp; }
-        } else {
-            if (b < nb) hb = LB[b];
-            if (a < na) { fc_cmp(M.V, GB[b - 1], GA[a], min3u(FB[b - 1], c, FA[a]), &tmp); ha = (u32)tmp; }
+    for (u32 i = threadIdx.x; i < wb + 1; i += MW_NT) {
+        if (i == 0 && b0 == 0) continue;
+        const u64 gi = B0 + b0 + i - 1;
+        sG[baseB - 1 + i] = M.G[gi]; sL[baseB - 1 + i] = M.L[gi]; sF[baseB - 1 + i] = M.F[gi];
+        sK[baseB - 1 + i] = M.K[gi];
+    }
+    __syncthreads();
+    const FcView &V = M.V;
+    const u32 dd = threadIdx.x * MW_IPT;  // local diagonal of this thread
+    const u32 dw = d1 - d0;
+    u32 oG[MW_IPT], oL[MW_IPT], oF[MW_IPT];
+    u64 oK[MW_IPT];
+    u32 cnt = 0;
+    if (dd < dw) {
+        cnt = min((u32)MW_IPT, dw - dd);
+        u64 tmp;
+        // co-rank inside the window (indices relative to a0 / b0)
+        u32 xlo = dd > wb ? dd - wb : 0, xhi = dd < wa ? dd : wa;
+        while (xlo < xhi) {
+            const u32 mid = (xlo + xhi) >> 1;
+            const u32 ia = baseA + mid, ib = baseB + (dd - mid - 1);
+            if (cmp_elem(V, sG[ia], sK[ia], sG[ib], sK[ib], min3u(sF[ia], c, sF[ib]), C, &tmp) <= 0) xlo = mid + 1;
+            else xhi = mid;
         }
-    }
-    u32 *Go = M.Go + A0 + dloc, *Lo = M.Lo + A0 + dloc, *Fo = M.Fo + A0 + dloc;
-    for (u32 k = 0; k < cnt; k++) {
-        bool takeA;
-        u32 outl;
-        if (a >= na) {
-            takeA = false;
-            outl = hb;
-        } else if (b >= nb) {
-            takeA = true;
-            outl = ha;
-        } else if (ha > hb) {
-            takeA = true;
-            outl = ha;
-        } else if (ha < hb) {
-            takeA = false;
-            outl = hb;
-        } else {
-            const u32 bound = min3u(FA[a], c, FB[b]);
-            const int r = fc_cmp(M.V, GA[a], GB[b], bound > ha ? bound : ha, &tmp);
-            outl = ha;
-            if (r <= 0) {
-                takeA = true;
-                hb = (u32)tmp;
+        u32 a = xlo, b = dd - xlo;  // relative to the window
+        const u32 ga = a0 + a, gb = b0 + b;  // relative to the runs
+        u32 ha = 0, hb = 0;
+        if (d0 + dd > 0) {
+            // the previous output is A[ga-1] or B[gb-1] (LDS slots baseA+a-1 / baseB+b-1)
+            bool lastA;
+            const u32 pa = baseA + a - 1, pb = baseB + b - 1;
+            if (ga == 0) lastA = false;
+            else if (gb == 0) lastA = true;
+            else lastA = cmp_elem(V, sG[pa], sK[pa], sG[pb], sK[pb], min3u(sF[pa], c, sF[pb]), C, &tmp) > 0;
+            if (lastA) {
+                if (a < wa) ha = sL[baseA + a];
+                if (b < wb) {
+                    cmp_elem(V, sG[pa], sK[pa], sG[baseB + b], sK[baseB + b], min3u(sF[pa], c, sF[baseB + b]), C,
+                             &tmp);
+                    hb = (u32)tmp;
+                }
             } else {
-                takeA = false;
-                ha = (u32)tmp;
+                if (b < wb) hb = sL[baseB + b];
+                if (a < wa) {
+                    cmp_elem(V, sG[pb], sK[pb], sG[baseA + a], sK[baseA + a], min3u(sF[pb], c, sF[baseA + a]), C,
+                             &tmp);
+                    ha = (u32)tmp;
+                }
             }
         }
-        if (dloc + k == 0) outl = 0;
-        if (takeA) {
-            Go[k] = GA[a];
-            Lo[k] = outl;
-            Fo[k] = firstA ? FA[a] : min(c, FA[a]);
-            a++;
-            if (a < na) ha = LA[a];
-        } else {
-            Go[k] = GB[b];
-            Lo[k] = outl;
-            Fo[k] = firstA ? min(c, FB[b]) : FB[b];
-            b++;
-            if (b < nb) hb = LB[b];
+#pragma unroll
+        for (u32 k = 0; k < MW_IPT; k++) {
+            if (k >= cnt) break;
+            bool takeA;
+            u32 outl;
+            const u32 ia = baseA + a, ib = baseB + b;
+            if (a >= wa) {
+                takeA = false;
+                outl = hb;
+            } else if (b >= wb) {
+                takeA = true;
+                outl = ha;
+            } else if (ha > hb) {
+                takeA = true;
+                outl = ha;
+            } else if (ha < hb) {
+                takeA = false;
+                outl = hb;
+            } else {
+                const u32 bound = min3u(sF[ia], c, sF[ib]);
+                const int r = cmp_elem(V, sG[ia], sK[ia], sG[ib], sK[ib], bound > ha ? bound : ha, C, &tmp);
+                outl = ha;
+                if (r <= 0) {
+                    takeA = true;
+                    hb = (u32)tmp;
+                } else {
+                    takeA = false;
+                    ha = (u32)tmp;
+                }
+            }
+            if (d0 + dd + k == 0) outl = 0;
+            if (takeA) {
+                oG[k] = sG[ia]; oL[k] = outl; oF[k] = firstA ? sF[ia] : min(c, sF[ia]); oK[k] = sK[ia];
+                a++;
+                if (a < wa) ha = sL[baseA + a];
+            } else {
+                oG[k] = sG[ib]; oL[k] = outl; oF[k] = firstA ? min(c, sF[ib]) : sF[ib]; oK[k] = sK[ib];
+                b++;
+                if (b < wb) hb = sL[baseB + b];
+            }
         }
     }
+    __syncthreads();
+#pragma unroll
+    for (u32 k = 0; k < MW_IPT; k++) {
+        if (k < cnt) {
+            sG[dd + k] = oG[k]; sL[dd + k] = oL[k]; sF[dd + k] = oF[k]; sK[dd + k] = oK[k];
+        }
+    }
+    __syncthreads();
+    const u64 ob = A0 + d0;
+    for (u32 i = threadIdx.x; i < dw; i += MW_NT) {
+        M.Go[ob + i] = sG[i]; M.Lo[ob + i] = sL[i]; M.Fo[ob + i] = sF[i]; M.Ko[ob + i] = sK[i];
+    }
+}
+
+// Common prefix length of each group: every string of run r shares
+// min(lcp(head of the group's first run, head of r), F[last of r]) bytes with
+// the group's first head, where F[last] = lcp(head of r, last of r).
+__global__ void k_group_depth(const u64 *P, const u32 *run_group, const u32 *rep, u32 k, const u32 *G, const u32 *F,
+                              FcView V, u32 *Cg)
+{
+    const u32 r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= k) return;
+    const u64 a = P[r], b = P[r + 1];
+    if (b == a) return;
+    const u32 g = run_group[r];
+    const u32 r0 = rep[g];
+    u32 v = 0xFFFFFFFFu;
+    if (r0 != r) {
+        u64 l;
+        fc_cmp(V, G[P[r0]], G[a], 0, &l);
+        v = (u32)l;
+    }
+    if (b - a >= 2) v = min(v, F[b - 1]);
+    atomicMin(&Cg[g], v);
+}
+
+__global__ __launch_bounds__(256) void k_merge_keys(const u64 *P, const u32 *run_group, u32 k, u32 n_out,
+                                                    const u32 *G, const u32 *Cg, FcView V, u64 *K)
+{
+    const u32 x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n_out) return;
+    u32 lo = 0, hi = k;
+    while (hi - lo > 1) {
+        u32 mid = (lo + hi) >> 1;
+        if (P[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    const u32 C = Cg[run_group[lo]];
+    const u32 g = G[x];
+    const u64 len = V.d[g];
+    const u64 rem = len > C ? len - C : 0;
+    const u32 take = rem < 7 ? (u32)rem : 7u;
+    const u64 data = fc_load_be(V, g, C, take);
+    const u32 cnt = rem < 8 ? (u32)rem : 8u;
+    K[x] = (data & ~0xFFull) | cnt;
 }
 
 // Source (run, position) of every output: runs sorted by their front-coded
@@ -534,9 +678,9 @@ __global__ __launch_bounds__(256) void k_check_merge_runs(const u64 *rb, const u
 
 struct MergeWs {
     DecWs dec;
-    u32 *G0, *G1, *L0, *L1, *F0, *F1, *pc, *tstart, *sid;
+    u32 *G0, *G1, *L0, *L1, *F0, *F1, *pc, *tstart, *sid, *pg, *Cg, *rgroup, *rep;
     u8 *pfirst;
-    u64 *PA0, *PA1, *PB1, *P, *sb;
+    u64 *PA0, *PA1, *PB1, *P, *sb, *K0, *K1;
 };
 
 #define MERGE_MAX_K 65536
@@ -550,7 +694,8 @@ static void merge_layout(u64 n_out, u64 n_fc, u64 k, MergeWs *w, WsArena *a, WsC
         else c->take<T>(cnt);                    \
     } while (0)
     MT(G0, u32, n_out); MT(G1, u32, n_out); MT(L0, u32, n_out); MT(L1, u32, n_out);
-    MT(F0, u32, n_out); MT(F1, u32, n_out);
+    MT(F0, u32, n_out); MT(F1, u32, n_out); MT(K0, u64, n_out); MT(K1, u64, n_out);
+    MT(pg, u32, k + 2); MT(Cg, u32, k + 2); MT(rgroup, u32, k + 2); MT(rep, u32, k + 2);
     MT(pc, u32, k + 2); MT(tstart, u32, k + 2); MT(sid, u32, k + 2); MT(pfirst, u8, k + 2);
     MT(PA0, u64, k + 2); MT(PA1, u64, k + 2); MT(PB1, u64, k + 2); MT(P, u64, k + 2); MT(sb, u64, k + 2);
 #undef MT
@@ -658,7 +803,29 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
                                                                  w.G0, w.L0, w.F0);
     SS_CHECK_LAUNCH();
     const FcView V{fc_lcp, fc_len, w.dec.psv, suf_off, suf, sufN};
+    {
+        // group of every run, first non-empty run of every group, group depths, keys
+        std::vector<u32> rg(k), rep(groups, 0);
+        for (u32 g = 0; g < groups; g++) {
+            bool found = false;
+            for (u32 j = go[g]; j < go[g + 1]; j++) {
+                rg[j] = g;
+                if (!found && re[j] > rb[j]) { rep[g] = j; found = true; }
+            }
+        }
+        SS_HIP(hipMemcpyAsync(w.rgroup, rg.data(), sizeof(u32) * k, hipMemcpyHostToDevice, st));
+        SS_HIP(hipMemcpyAsync(w.rep, rep.data(), sizeof(u32) * groups, hipMemcpyHostToDevice, st));
+        SS_HIP(hipMemsetAsync(w.Cg, 0xFF, sizeof(u32) * groups, st));
+        k_group_depth<<<(unsigned)ceil_div(k, 64), 64, 0, st>>>(w.P, w.rgroup, w.rep, k, w.G0, w.F0, V, w.Cg);
+        SS_CHECK_LAUNCH();
+        k_merge_keys<<<(unsigned)ceil_div(n_out, 256), 256, 0, st>>>(w.P, w.rgroup, k, (u32)n_out, w.G0, w.Cg, V,
+                                                                     w.K0);
+        SS_CHECK_LAUNCH();
+        SS_HIP(hipStreamSynchronize(st));  // the host vectors above must outlive the copies
+    }
     u32 *G = w.G0, *L = w.L0, *F = w.F0, *Go = w.G1, *Lo = w.L1, *Fo = w.F1;
+    u64 *K = w.K0, *Ko = w.K1;
+    std::vector<u32> pgv;
     // segments of the output space per group
     std::vector<std::vector<std::pair<u64, u64>>> segs(groups);
     for (u32 g = 0; g < groups; g++)
@@ -669,7 +836,7 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
         bool more = false;
         for (auto &sg : segs) more |= sg.size() > 1;
         if (!more) break;
-        pa0.clear(); pa1.clear(); pb1.clear(); ts.assign(1, 0);
+        pa0.clear(); pa1.clear(); pb1.clear(); ts.assign(1, 0); pgv.clear();
         std::vector<std::vector<std::pair<u64, u64>>> nxt(groups);
         for (u32 g = 0; g < groups; g++) {
             auto &sg = segs[g];
@@ -678,9 +845,9 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
                 const u64 B1 = (m + 1 < sg.size()) ? sg[m + 1].second : A1;
                 nxt[g].push_back({A0, B1});
                 if (sg.size() == 1) continue;  // a lone run of its group is final
-                pa0.push_back(A0); pa1.push_back(A1); pb1.push_back(B1);
+                pa0.push_back(A0); pa1.push_back(A1); pb1.push_back(B1); pgv.push_back(g);
                 const u64 sz = B1 - A0;
-                ts.push_back(ts.back() + (u32)ceil_div(sz ? sz : 1, MG_PER));
+                ts.push_back(ts.back() + (u32)ceil_div(sz ? sz : 1, MW_TILE));
             }
         }
         const u32 np = (u32)pa0.size();
@@ -688,8 +855,9 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
         for (u32 g = 0; g < groups; g++) {
             if (segs[g].size() == 1 && segs[g][0].second > segs[g][0].first) {
                 pa0.push_back(segs[g][0].first); pa1.push_back(segs[g][0].second); pb1.push_back(segs[g][0].second);
+                pgv.push_back(g);
                 const u64 sz = segs[g][0].second - segs[g][0].first;
-                ts.push_back(ts.back() + (u32)ceil_div(sz, MG_PER));
+                ts.push_back(ts.back() + (u32)ceil_div(sz, MW_TILE));
             }
         }
         const u32 npt = (u32)pa0.size();
@@ -702,12 +870,13 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
         SS_HIP(hipMemcpyAsync(w.PA1, pa1.data(), sizeof(u64) * npt, hipMemcpyHostToDevice, st));
         SS_HIP(hipMemcpyAsync(w.PB1, pb1.data(), sizeof(u64) * npt, hipMemcpyHostToDevice, st));
         SS_HIP(hipMemcpyAsync(w.tstart, ts.data(), sizeof(u32) * (npt + 1), hipMemcpyHostToDevice, st));
-        MergeLevel M{G, L, F, Go, Lo, Fo, w.PA0, w.PA1, w.PB1, w.tstart, w.pc, w.pfirst, npt, V};
+        SS_HIP(hipMemcpyAsync(w.pg, pgv.data(), sizeof(u32) * npt, hipMemcpyHostToDevice, st));
+        MergeLevel M{G, L, F, Go, Lo, Fo, K, Ko, w.pg, w.Cg, w.PA0, w.PA1, w.PB1, w.tstart, w.pc, w.pfirst, npt, V};
         k_pair_info<<<(unsigned)ceil_div(npt, 64), 64, 0, st>>>(M);
         SS_CHECK_LAUNCH();
-        const u32 nth = ts[npt];
-        if (nth > 0) {
-            k_merge_level<<<(unsigned)ceil_div(nth, 256), 256, 0, st>>>(M, nth);
+        const u32 nblk = ts[npt];
+        if (nblk > 0) {
+            k_merge_level<<<nblk, MW_NT, 0, st>>>(M, nblk);
             SS_CHECK_LAUNCH();
         }
         SS_HIP(hipStreamSynchronize(st));  // keeps the host vectors alive until the copies ran
@@ -715,6 +884,7 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
         std::swap(G, Go);
         std::swap(L, Lo);
         std::swap(F, Fo);
+        std::swap(K, Ko);
     }
     k_merge_out<<<(unsigned)ceil_div(n_out, 256), 256, 0, st>>>(G, L, (u32)n_out, w.sb, w.sid, kne, fc_id,
                                                                 out_src, out_id, out_lcp);

@@ -292,9 +292,10 @@ extern "C" int ss_partition_encode(const uint8_t *bytes, uint64_t N, const uint6
     }
     u64 total;
     u32 hbad;
-    SS_TRY(ss_read_u64(suf_off + n, &total, 1, st));
+    SS_HIP(hipMemcpyAsync(&total, suf_off + n, sizeof(u64), hipMemcpyDeviceToHost, st));
+    SS_HIP(hipMemcpyAsync(&hbad, bad, sizeof(u32), hipMemcpyDeviceToHost, st));
+    SS_HIP(hipStreamSynchronize(st));
     total -= suf_base;
-    SS_TRY(ss_read_u32(bad, &hbad, 1, st));
     if (hbad) {
         ss_set_error("front coding needs lcp <= dist <= len at every position");
         return SS_ERR_INVALID_ARG;
