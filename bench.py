@@ -48,13 +48,8 @@ class Pipeline:
         self.ws_sort = torch.empty(ss.lib().ss_sort_workspace(n), dtype=torch.uint8, device=dev)
         self.ws_pd = torch.empty(ss.lib().ss_dist_prefix_workspace(n), dtype=torch.uint8, device=dev)
         self.ws_merge = torch.empty(ss.lib().ss_lcp_merge_workspace(n, n, p * p), dtype=torch.uint8, device=dev)
-        i32 = lambda: torch.empty(n, dtype=torch.int32, device=dev)
-        # shared front-coded arrays: PE i writes positions [bounds[i], bounds[i+1])
-        self.fc = dict(lcp=i32(), len=i32(), id=i32(), suf_off=torch.empty(n + 1, dtype=torch.int64, device=dev),
-                       suf=torch.empty(B.numel() + 16, dtype=torch.uint8, device=dev))
-        self.run_offs = [torch.empty(p + 1, dtype=torch.int64, device=dev) for _ in range(p)]
+        self.ws_pe = torch.empty(ss.lib().ss_partition_encode_workspace(n), dtype=torch.uint8, device=dev)
         self.group_off = torch.arange(0, p * p + 1, p, dtype=torch.int32, device=dev)
-        self.byte_base = O[torch.tensor(self.bounds, device=dev)].tolist()
 
     def step(self, marks):
         ss, torch, B, O, p = self.ss, self.torch, self.B, self.O, self.p
@@ -74,19 +69,16 @@ class Pipeline:
         fid = ss.select_splitters(sperm, p)
         fb, fo = ss.gather_strings(sb, so, fid)
         ev("splitters")
-        # 4. buckets + front coding of the distinguishing prefixes, per PE
-        for i in range(p):
-            a, b = self.bounds[i], self.bounds[i + 1]
-            out = dict(run_off=self.run_offs[i], lcp=self.fc["lcp"][a:b], len=self.fc["len"][a:b],
-                       id=self.fc["id"][a:b], suf_off=self.fc["suf_off"][a:b + 1], suf=self.fc["suf"])
-            ss.partition_encode(B, O, perm[a:b], lcp[a:b], dpx, fb, fo, out=out, suf_base=self.byte_base[i], n=b - a)
+        # 4. every PE splits its array into p buckets and front-codes the
+        #    distinguishing prefixes (all PEs in one batched call)
+        fc = ss.partition_encode_batch(B, O, self.set_off, perm, lcp, dpx, fb, fo, ws=self.ws_pe)
         ev("partition_encode")
         # 5. bucket j merges run (i, j) of every PE i: all p merges in one call
-        ro = torch.stack(self.run_offs) + self.set_off[:-1, None]      # [PE, bucket+1] absolute
+        ro = fc["run_off"].view(p, p + 1)                              # [PE, bucket bound], absolute
         run_begin = ro[:, :-1].t().reshape(-1)                          # group j = bucket j, run i = PE i
         run_end = ro[:, 1:].t().reshape(-1)
-        src, order, mlcp = ss.lcp_merge(run_begin, run_end, self.group_off, self.fc["lcp"], self.fc["len"],
-                                        self.fc["id"], self.fc["suf_off"], self.fc["suf"], ws=self.ws_merge)
+        src, order, mlcp = ss.lcp_merge(run_begin, run_end, self.group_off, fc["lcp"], fc["len"], fc["id"],
+                                        fc["suf_off"], fc["suf"], ws=self.ws_merge)
         ev("lcp_merge")
         # 6. LCPs across bucket boundaries, exact distinguishing prefixes
         sizes = (run_end - run_begin).view(p, p).sum(1)
@@ -230,6 +222,7 @@ def main():
         pipe.step(Marks(torch, False))
     torch.cuda.synchronize()
     stages = {}
+    ss.profile_enable(True)   # HIP events around the library's kernels during the timed steps
     t0 = time.perf_counter()
     for _ in range(args.steps):
         mk = Marks(torch, args.stages)
@@ -240,6 +233,8 @@ def main():
                 stages.setdefault(k, []).append(v)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    prof = ss.profile_report()
+    ss.profile_enable(False)
     order, mlcp, dist, dpx, rounds = res
     print(f"# step {dt * 1e3:.3f} ms", file=sys.stderr, flush=True)
     verified = None
@@ -266,6 +261,16 @@ def main():
         "hbm_frac_of_N_per_step": s.N / dt / 1e9 / HBM_PEAK_GBS,
         "verified": verified,
     }
+    if prof:
+        name = max(prof, key=lambda k: prof[k][0])
+        ms, by, cnt = prof[name]
+        achieved = by / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": name,
+                           "launches_per_step": cnt / args.steps, "avg_launch_ms": ms / max(cnt, 1),
+                           "algorithmic_bytes_per_launch": by / max(cnt, 1)}
+        out["kernels_ms_per_step"] = {k: v[0] / args.steps for k, v in sorted(prof.items(), key=lambda x: -x[1][0])}
+        out["kernels_gbs"] = {k: (v[1] / (v[0] / 1e3) / 1e9 if v[0] > 0 else None) for k, v in prof.items()}
     if args.stages:
         out["stages_ms"] = {k: sum(v) / len(v) for k, v in stages.items()}
     if not args.no_cpu:

@@ -189,6 +189,24 @@ int ss_partition_encode(const uint8_t *bytes, uint64_t N, const uint64_t *offset
                         uint64_t suf_cap, uint64_t *suf_total_host, void *ws, size_t ws_bytes,
                         void *stream);
 
+/* ss_partition_encode for num_sets sorted arrays at once (each processing
+ * element splits its own array with the same splitters, Section 3 steps 1-2),
+ * in one launch sequence.  Set b is the sorted positions
+ * [set_off[b], set_off[b+1]) of perm/lcp (set_off: device, num_sets+1
+ * entries, non-decreasing, set_off[num_sets] = n); perm values index offsets.
+ * run_off (out, num_sets*(r+1)): the bucket bounds of set b, as absolute
+ * positions, at run_off[b*(r+1) .. b*(r+1)+r].  The front-coded arrays cover
+ * all n positions; e = 0 at every bucket start of every set.  Workspace as for
+ * ss_partition_encode(n). */
+int ss_partition_encode_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets,
+                              uint64_t n, const uint64_t *set_off, uint32_t num_sets,
+                              const uint32_t *perm, const uint32_t *lcp, const uint32_t *dist,
+                              const uint8_t *spl_bytes, uint64_t spl_N,
+                              const uint64_t *spl_offsets, uint32_t r, uint64_t *run_off,
+                              uint32_t *fc_lcp, uint32_t *fc_len, uint32_t *fc_id,
+                              uint64_t *suf_off, uint8_t *suf, uint64_t suf_base, uint64_t suf_cap,
+                              uint64_t *suf_total_host, void *ws, size_t ws_bytes, void *stream);
+
 /* Workspace bytes for ss_fc_decode on n strings. */
 size_t ss_fc_decode_workspace(uint64_t n);
 
@@ -235,6 +253,25 @@ int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_t *run_end,
                  const uint32_t *fc_len, const uint32_t *fc_id, const uint64_t *suf_off,
                  const uint8_t *suf, uint64_t *out_src, uint32_t *out_id, uint32_t *out_lcp,
                  void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------ profiling */
+
+/* Opt-in kernel timing for measurement (not part of the method).  While
+ * enabled, the library records a HIP event pair on the launch stream around
+ * every launch of its main kernels, together with the launch's algorithmic
+ * byte count (the bytes the step must move: inputs read once, outputs written
+ * once; each kernel's figure is stated where it is launched).  Enabling clears
+ * earlier records.  Records are process-wide; use from one thread. */
+void ss_profile_enable(int on);
+
+/* Totals for kernel `name` over the records so far: summed event time (ms),
+ * summed algorithmic bytes and number of launches (synchronises the recorded
+ * events).  Returns SS_OK, or SS_ERR_INVALID_ARG if nothing was recorded. */
+int ss_profile_query(const char *name, double *ms, double *bytes, uint32_t *launches);
+
+/* Comma-separated names of the kernels recorded so far, into a host buffer of
+ * `cap` bytes.  Returns the length needed (excluding the terminator). */
+size_t ss_profile_names(char *buf, size_t cap);
 
 /* ------------------------------------------------------------- tuning */
 

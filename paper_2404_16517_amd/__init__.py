@@ -56,7 +56,12 @@ def lib():
             "ss_partition_encode_workspace": ([U64], SZ),
             "ss_partition_encode": ([P, U64, P, U64, P, P, P, P, U64, P, U32, P, P, P, P, P, P, U64, U64, P, P, SZ,
                                      P], I32),
+            "ss_partition_encode_batch": ([P, U64, P, U64, P, U32, P, P, P, P, U64, P, U32, P, P, P, P, P, P, U64, U64,
+                                           P, P, SZ, P], I32),
             "ss_fc_decode_workspace": ([U64], SZ),
+            "ss_profile_enable": ([I32], None),
+            "ss_profile_query": ([ctypes.c_char_p, P, P, P], I32),
+            "ss_profile_names": ([ctypes.c_char_p, SZ], SZ),
             "ss_fc_decode": ([U32, P, P, P, P, P, U64, P, P, U64, P, SZ, P], I32),
             "ss_lcp_merge_workspace": ([U64, U64, U32], SZ),
             "ss_lcp_merge": ([U32, P, P, U32, P, U64, P, P, P, P, P, P, P, P, P, SZ, P], I32),
@@ -247,6 +252,54 @@ def partition_encode(bytes_, offsets, perm, lcp_, dist, spl_bytes, spl_offsets, 
     if suf_base == 0:
         res["suf"] = out["suf"][:t]
     return res
+
+
+def partition_encode_batch(bytes_, offsets, set_off, perm, lcp_, dist, spl_bytes, spl_offsets, ws=None):
+    """Buckets + front coding of several sorted arrays (sets of positions
+    [set_off[b], set_off[b+1]) of perm/lcp) with common splitters, one call.
+    Returns a dict: run_off (sets*(r+1), absolute), lcp, len, id, suf_off, suf, total."""
+    b, o, _ = _dev_strings(bytes_, offsets)
+    dev = b.device
+    n = perm.numel()
+    so = set_off.to(device=dev, dtype=torch.int64).contiguous()
+    B = so.numel() - 1
+    r = spl_offsets.numel()
+    out = dict(run_off=torch.empty(B * (r + 1), dtype=torch.int64, device=dev), lcp=_u32(n, dev), len=_u32(n, dev),
+               id=_u32(n, dev), suf_off=torch.empty(n + 1, dtype=torch.int64, device=dev),
+               suf=torch.empty(max(b.numel(), 1), dtype=torch.uint8, device=dev))
+    need = lib().ss_partition_encode_workspace(n)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, dev)
+    total = ctypes.c_uint64(0)
+    _check(lib().ss_partition_encode_batch(_p(b), b.numel(), _p(o), n, _p(so), B, _p(perm.contiguous()),
+                                           _p(lcp_.contiguous()), _p(dist.contiguous()) if dist is not None else None,
+                                           _p(spl_bytes), spl_bytes.numel(), _p(spl_offsets), r, _p(out["run_off"]),
+                                           _p(out["lcp"]), _p(out["len"]), _p(out["id"]), _p(out["suf_off"]),
+                                           _p(out["suf"]), 0, out["suf"].numel(), ctypes.byref(total), _p(ws),
+                                           ws.numel(), _stream(dev)))
+    out["total"] = int(total.value)
+    return out
+
+
+# -------------------------------------------------------------- profiling
+
+def profile_enable(on: bool = True):
+    """Record HIP events around the library's main kernels (clears old records)."""
+    lib().ss_profile_enable(1 if on else 0)
+
+
+def profile_report() -> dict:
+    """{kernel: (ms, algorithmic bytes, launches)} for the records so far."""
+    L = lib()
+    need = L.ss_profile_names(None, 0)
+    buf = ctypes.create_string_buffer(need + 1)
+    L.ss_profile_names(buf, need + 1)
+    out = {}
+    for name in filter(None, buf.value.decode().split(",")):
+        ms, by, cnt = ctypes.c_double(), ctypes.c_double(), ctypes.c_uint32()
+        if L.ss_profile_query(name.encode(), ctypes.byref(ms), ctypes.byref(by), ctypes.byref(cnt)) == 0:
+            out[name] = (ms.value, by.value, cnt.value)
+    return out
 
 
 def fc_decode(run_off, fc_lcp, fc_len, suf_off, suf):

@@ -70,6 +70,22 @@ struct WsCounter {
 int ss_read_u32(const u32 *dev, u32 *host, int count, hipStream_t s);
 int ss_read_u64(const u64 *dev, u64 *host, int count, hipStream_t s);
 
+// Opt-in launch timing (ss_profile_enable): a scope records an event pair on
+// the stream around the launch it encloses.
+extern bool g_prof_on;
+struct ProfScope {
+    const char *name;
+    hipStream_t st;
+    double bytes;
+    hipEvent_t a;
+    bool on;
+    ProfScope(const char *n, hipStream_t s, double b);
+    ~ProfScope();
+};
+#define SS_PROF(name, stream, bytes) ProfScope ss_prof_scope_(name, stream, (double)(bytes))
+// add bytes to the latest record of `name` (for counts known only after a read-back)
+void ss_prof_add_bytes(const char *name, double bytes);
+
 // Tunables (set by ss_set_tuning).
 extern int g_small_max;
 extern int g_tile;

@@ -58,13 +58,13 @@ struct BPow {
     u64 p[17];  // B^0 .. B^16 mod p
 };
 
-#define HG 8  // lanes per string in a hash round (64 bytes = 16 limbs per step)
-
 // One doubling round: key of the min(l, len)-prefix of every active string,
 // continuing the Horner state of the previous round (bytes [lprev, l) only).
-// A group of 8 lanes reads 64 consecutive bytes of one string per step; lane
-// j folds its two limbs, and the group combines them as
+// A group of HG lanes (1, 2, 4 or 8, matched to the new bytes of the round)
+// reads 8*HG consecutive bytes of one string per step; lane j folds its two
+// limbs, and the group combines them as
 // C <- C * B^L + sum_j v_j * B^(limbs after lane j).
+template <int HG>
 __global__ __launch_bounds__(256) void k_hash_round(const u32 *act, u32 A, const u8 *bytes, u64 N,
                                                     const u64 *off, u64 lprev, u64 l, u32 bits,
                                                     u64 *state, u64 *keys, u32 *vals, BPow bp)
@@ -80,17 +80,15 @@ __global__ __launch_bounds__(256) void k_hash_round(const u32 *act, u32 A, const
         const u64 q = x + 8 * lane;
         const u32 take = q < m ? (u32)((m - q) < 8 ? (m - q) : 8) : 0u;
         const u64 w = load_le(bytes, N, o + q, take);
-        // limbs of this lane
-        u32 nl = take == 0 ? 0u : (take > 4 ? 2u : 1u);
+        const u32 nl = take == 0 ? 0u : (take > 4 ? 2u : 1u);
         u64 v = 0;
         if (nl == 2) v = addmod61(mulmod61(w & 0xFFFFFFFFull, KR_B), w >> 32);
         else if (nl == 1) v = w & 0xFFFFFFFFull;
-        // limbs in this step and after this lane
         const u64 rem = m - x;
         const u32 Lstep = (u32)((rem >= 8 * HG ? 8 * HG : rem) + 3) / 4;
         const u32 before = 2 * lane < Lstep ? 2 * lane : Lstep;
         const u32 after = Lstep - before - nl;
-        u64 t = nl ? mulmod61(v, bp.p[after]) : 0ull;
+        u64 t = nl ? (after ? mulmod61(v, bp.p[after]) : v) : 0ull;
 #pragma unroll
         for (int s2 = HG / 2; s2 > 0; s2 >>= 1) t = addmod61(t, __shfl_xor(t, s2, HG));
         C = addmod61(mulmod61(C, bp.p[Lstep]), t);
@@ -153,6 +151,13 @@ __global__ __launch_bounds__(256) void k_dedup(const u64 *keys, const u32 *vals,
 }
 
 __global__ void k_one_seg(Seg *act, u32 A) { act[0] = Seg{0, A, 0, 0}; }
+
+// flag = 1 if some key differs from keys[0] (then the keys must be sorted)
+__global__ void k_neq(const u64 *keys, u32 A, u32 *flag)
+{
+    const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < A && keys[j] != keys[0]) *flag = 1u;
+}
 
 struct PdWs {
     SortWs sw;
@@ -233,18 +238,46 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
     u32 rounds = 0;
     while (A > 0) {
         if (++rounds > 64) { ss_set_error("prefix doubling did not terminate"); return SS_ERR_INVALID_ARG; }
-        k_hash_round<<<(unsigned)ceil_div(A, 256 / HG), 256, 0, st>>>(act, A, bytes, N, offsets, lprev, l,
-                                                                       hash_bits, w.state, w.sw.keyA, w.vals, bp);
+        {
+            // new prefix bytes (exact for strings of length >= l), offsets, list entry,
+            // hash state in/out, key and payload out
+            SS_PROF("k_hash_round", st, (double)A * (double)(l - lprev) + (double)A * (act ? 48.0 : 36.0));
+            const u64 nb = l - lprev;
+            if (nb <= 8)
+                k_hash_round<1><<<(unsigned)ceil_div(A, 256), 256, 0, st>>>(act, A, bytes, N, offsets, lprev, l,
+                                                                           hash_bits, w.state, w.sw.keyA, w.vals, bp);
+            else if (nb <= 16)
+                k_hash_round<2><<<(unsigned)ceil_div(A, 128), 256, 0, st>>>(act, A, bytes, N, offsets, lprev, l,
+                                                                           hash_bits, w.state, w.sw.keyA, w.vals, bp);
+            else if (nb <= 32)
+                k_hash_round<4><<<(unsigned)ceil_div(A, 64), 256, 0, st>>>(act, A, bytes, N, offsets, lprev, l,
+                                                                          hash_bits, w.state, w.sw.keyA, w.vals, bp);
+            else
+                k_hash_round<8><<<(unsigned)ceil_div(A, 32), 256, 0, st>>>(act, A, bytes, N, offsets, lprev, l,
+                                                                          hash_bits, w.state, w.sw.keyA, w.vals, bp);
+        }
         SS_CHECK_LAUNCH();
         if (A >= 2) {
-            k_one_seg<<<1, 1, 0, st>>>(w.sw.act, A);
+            // all keys equal (e.g. a prefix shared by every string): every
+            // string is a duplicate and no sort is needed
+            SS_HIP(hipMemsetAsync(w.ctr + 1, 0, sizeof(u32), st));
+            k_neq<<<(unsigned)ceil_div(A, 256), 256, 0, st>>>(w.sw.keyA, A, w.ctr + 1);
             SS_CHECK_LAUNCH();
-            SortJob J{bytes, N, offsets, w.vals, nullptr, 1, st};
-            SS_TRY(sort_rounds(J, w.sw, 1));
+            u32 differ;
+            SS_TRY(ss_read_u32(w.ctr + 1, &differ, 1, st));
+            if (differ) {
+                k_one_seg<<<1, 1, 0, st>>>(w.sw.act, A);
+                SS_CHECK_LAUNCH();
+                SortJob J{bytes, N, offsets, w.vals, nullptr, 1, st, A};
+                SS_TRY(sort_rounds(J, w.sw, 1, (u32)ceil_div(A, 2048)));
+            }
         }
         SS_HIP(hipMemsetAsync(w.ctr, 0, sizeof(u32), st));
-        k_dedup<<<(unsigned)ceil_div(A, 256 * DD_PER), 256, 0, st>>>(w.sw.keyA, w.vals, A, offsets, l, dist_approx, nxt,
-                                                             w.ctr);
+        {
+            SS_PROF("k_dedup", st, (double)A * 32.0);  // key, payload, offsets, one 4-byte write
+            k_dedup<<<(unsigned)ceil_div(A, 256 * DD_PER), 256, 0, st>>>(w.sw.keyA, w.vals, A, offsets, l,
+                                                                         dist_approx, nxt, w.ctr);
+        }
         SS_CHECK_LAUNCH();
         SS_TRY(ss_read_u32(w.ctr, &A, 1, st));
         act = nxt;

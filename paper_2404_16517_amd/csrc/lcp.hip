@@ -52,7 +52,10 @@ extern "C" int ss_dist_exact(const uint64_t *offsets, uint64_t n, const uint32_t
     if (n == 0) return SS_OK;
     if (!offsets || !perm || !lcp || !dist) { ss_set_error("null pointer"); return SS_ERR_INVALID_ARG; }
     hipStream_t st = (hipStream_t)stream;
-    k_dist_exact<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(offsets, (u32)n, perm, lcp, dist);
+    {
+        SS_PROF("k_dist_exact", st, (double)n * 28.0);  // perm, lcp, offsets in; dist out
+        k_dist_exact<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(offsets, (u32)n, perm, lcp, dist);
+    }
     SS_CHECK_LAUNCH();
     return SS_OK;
 }

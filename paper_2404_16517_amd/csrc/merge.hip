@@ -684,6 +684,9 @@ struct MergeWs {
 };
 
 #define MERGE_MAX_K 65536
+// merge plan entries over all levels: <= 2k pairs plus one copy-through entry
+// per group and level (<= 18 levels)
+#define MERGE_PCAP(k) (20 * (size_t)(k) + 4)
 
 static void merge_layout(u64 n_out, u64 n_fc, u64 k, MergeWs *w, WsArena *a, WsCounter *c)
 {
@@ -695,9 +698,10 @@ static void merge_layout(u64 n_out, u64 n_fc, u64 k, MergeWs *w, WsArena *a, WsC
     } while (0)
     MT(G0, u32, n_out); MT(G1, u32, n_out); MT(L0, u32, n_out); MT(L1, u32, n_out);
     MT(F0, u32, n_out); MT(F1, u32, n_out); MT(K0, u64, n_out); MT(K1, u64, n_out);
-    MT(pg, u32, k + 2); MT(Cg, u32, k + 2); MT(rgroup, u32, k + 2); MT(rep, u32, k + 2);
-    MT(pc, u32, k + 2); MT(tstart, u32, k + 2); MT(sid, u32, k + 2); MT(pfirst, u8, k + 2);
-    MT(PA0, u64, k + 2); MT(PA1, u64, k + 2); MT(PB1, u64, k + 2); MT(P, u64, k + 2); MT(sb, u64, k + 2);
+    MT(pg, u32, MERGE_PCAP(k)); MT(Cg, u32, k + 2); MT(rgroup, u32, k + 2); MT(rep, u32, k + 2);
+    MT(sid, u32, k + 2); MT(P, u64, k + 2); MT(sb, u64, k + 2);
+    MT(pc, u32, MERGE_PCAP(k)); MT(pfirst, u8, MERGE_PCAP(k)); MT(tstart, u32, MERGE_PCAP(k) + 64);
+    MT(PA0, u64, MERGE_PCAP(k)); MT(PA1, u64, MERGE_PCAP(k)); MT(PB1, u64, MERGE_PCAP(k));
 #undef MT
 }
 
@@ -782,8 +786,9 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
     SS_CHECK_LAUNCH();
     u32 bad;
     u64 sufN;
-    SS_TRY(ss_read_u32(w.dec.bad, &bad, 1, st));
-    SS_TRY(ss_read_u64(suf_off + n_fc, &sufN, 1, st));
+    SS_HIP(hipMemcpyAsync(&bad, w.dec.bad, sizeof(u32), hipMemcpyDeviceToHost, st));
+    SS_HIP(hipMemcpyAsync(&sufN, suf_off + n_fc, sizeof(u64), hipMemcpyDeviceToHost, st));
+    SS_HIP(hipStreamSynchronize(st));
     if (bad) {
         ss_set_error("malformed front-coded runs (code %u): runs must start with e = 0 and e_i <= d_i, "
                      "e_i <= d_{i-1}", bad);
@@ -803,26 +808,22 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
                                                                  w.G0, w.L0, w.F0);
     SS_CHECK_LAUNCH();
     const FcView V{fc_lcp, fc_len, w.dec.psv, suf_off, suf, sufN};
-    {
-        // group of every run, first non-empty run of every group, group depths, keys
-        std::vector<u32> rg(k), rep(groups, 0);
-        for (u32 g = 0; g < groups; g++) {
-            bool found = false;
-            for (u32 j = go[g]; j < go[g + 1]; j++) {
-                rg[j] = g;
-                if (!found && re[j] > rb[j]) { rep[g] = j; found = true; }
-            }
+    // group of every run, first non-empty run of every group, group depths, keys
+    std::vector<u32> rg(k), rep(groups, 0);
+    for (u32 g = 0; g < groups; g++) {
+        bool found = false;
+        for (u32 j = go[g]; j < go[g + 1]; j++) {
+            rg[j] = g;
+            if (!found && re[j] > rb[j]) { rep[g] = j; found = true; }
         }
-        SS_HIP(hipMemcpyAsync(w.rgroup, rg.data(), sizeof(u32) * k, hipMemcpyHostToDevice, st));
-        SS_HIP(hipMemcpyAsync(w.rep, rep.data(), sizeof(u32) * groups, hipMemcpyHostToDevice, st));
-        SS_HIP(hipMemsetAsync(w.Cg, 0xFF, sizeof(u32) * groups, st));
-        k_group_depth<<<(unsigned)ceil_div(k, 64), 64, 0, st>>>(w.P, w.rgroup, w.rep, k, w.G0, w.F0, V, w.Cg);
-        SS_CHECK_LAUNCH();
-        k_merge_keys<<<(unsigned)ceil_div(n_out, 256), 256, 0, st>>>(w.P, w.rgroup, k, (u32)n_out, w.G0, w.Cg, V,
-                                                                     w.K0);
-        SS_CHECK_LAUNCH();
-        SS_HIP(hipStreamSynchronize(st));  // the host vectors above must outlive the copies
     }
+    SS_HIP(hipMemcpyAsync(w.rgroup, rg.data(), sizeof(u32) * k, hipMemcpyHostToDevice, st));
+    SS_HIP(hipMemcpyAsync(w.rep, rep.data(), sizeof(u32) * groups, hipMemcpyHostToDevice, st));
+    SS_HIP(hipMemsetAsync(w.Cg, 0xFF, sizeof(u32) * groups, st));
+    k_group_depth<<<(unsigned)ceil_div(k, 64), 64, 0, st>>>(w.P, w.rgroup, w.rep, k, w.G0, w.F0, V, w.Cg);
+    SS_CHECK_LAUNCH();
+    k_merge_keys<<<(unsigned)ceil_div(n_out, 256), 256, 0, st>>>(w.P, w.rgroup, k, (u32)n_out, w.G0, w.Cg, V, w.K0);
+    SS_CHECK_LAUNCH();
     u32 *G = w.G0, *L = w.L0, *F = w.F0, *Go = w.G1, *Lo = w.L1, *Fo = w.F1;
     u64 *K = w.K0, *Ko = w.K1;
     std::vector<u32> pgv;
@@ -832,11 +833,16 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
         for (u32 j = go[g]; j < go[g + 1]; j++) segs[g].push_back({P[j], P[j + 1]});
     std::vector<u64> pa0, pa1, pb1;
     std::vector<u32> ts;
+    // plan every level on the host, upload the plan once, launch all levels
+    struct LevelPlan { size_t off, ts_off; u32 npt; };
+    std::vector<LevelPlan> plan;
+    std::vector<u32> tsv;
     for (;;) {
         bool more = false;
         for (auto &sg : segs) more |= sg.size() > 1;
         if (!more) break;
-        pa0.clear(); pa1.clear(); pb1.clear(); ts.assign(1, 0); pgv.clear();
+        LevelPlan L0{pa0.size(), tsv.size(), 0};
+        tsv.push_back(0);
         std::vector<std::vector<std::pair<u64, u64>>> nxt(groups);
         for (u32 g = 0; g < groups; g++) {
             auto &sg = segs[g];
@@ -844,43 +850,41 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
                 const u64 A0 = sg[m].first, A1 = sg[m].second;
                 const u64 B1 = (m + 1 < sg.size()) ? sg[m + 1].second : A1;
                 nxt[g].push_back({A0, B1});
-                if (sg.size() == 1) continue;  // a lone run of its group is final
+                if (sg.size() == 1 && A1 == A0) continue;  // empty finished group: nothing to move
+                // pairs, odd runs and finished groups (copied through to the other buffer)
                 pa0.push_back(A0); pa1.push_back(A1); pb1.push_back(B1); pgv.push_back(g);
                 const u64 sz = B1 - A0;
-                ts.push_back(ts.back() + (u32)ceil_div(sz ? sz : 1, MW_TILE));
+                tsv.push_back(tsv.back() + (u32)ceil_div(sz ? sz : 1, MW_TILE));
             }
         }
-        const u32 np = (u32)pa0.size();
-        // groups already merged keep their arrays: copy them through as lone pairs
-        for (u32 g = 0; g < groups; g++) {
-            if (segs[g].size() == 1 && segs[g][0].second > segs[g][0].first) {
-                pa0.push_back(segs[g][0].first); pa1.push_back(segs[g][0].second); pb1.push_back(segs[g][0].second);
-                pgv.push_back(g);
-                const u64 sz = segs[g][0].second - segs[g][0].first;
-                ts.push_back(ts.back() + (u32)ceil_div(sz, MW_TILE));
-            }
-        }
-        const u32 npt = (u32)pa0.size();
-        if (npt > k + 1) {
-            ss_set_error("internal: too many merge pairs");
-            return SS_ERR_INVALID_ARG;
-        }
-        (void)np;
-        SS_HIP(hipMemcpyAsync(w.PA0, pa0.data(), sizeof(u64) * npt, hipMemcpyHostToDevice, st));
-        SS_HIP(hipMemcpyAsync(w.PA1, pa1.data(), sizeof(u64) * npt, hipMemcpyHostToDevice, st));
-        SS_HIP(hipMemcpyAsync(w.PB1, pb1.data(), sizeof(u64) * npt, hipMemcpyHostToDevice, st));
-        SS_HIP(hipMemcpyAsync(w.tstart, ts.data(), sizeof(u32) * (npt + 1), hipMemcpyHostToDevice, st));
-        SS_HIP(hipMemcpyAsync(w.pg, pgv.data(), sizeof(u32) * npt, hipMemcpyHostToDevice, st));
-        MergeLevel M{G, L, F, Go, Lo, Fo, K, Ko, w.pg, w.Cg, w.PA0, w.PA1, w.PB1, w.tstart, w.pc, w.pfirst, npt, V};
-        k_pair_info<<<(unsigned)ceil_div(npt, 64), 64, 0, st>>>(M);
-        SS_CHECK_LAUNCH();
-        const u32 nblk = ts[npt];
-        if (nblk > 0) {
-            k_merge_level<<<nblk, MW_NT, 0, st>>>(M, nblk);
-            SS_CHECK_LAUNCH();
-        }
-        SS_HIP(hipStreamSynchronize(st));  // keeps the host vectors alive until the copies ran
+        L0.npt = (u32)(pa0.size() - L0.off);
+        plan.push_back(L0);
         segs.swap(nxt);
+    }
+    const size_t npairs_all = pa0.size();
+    if (npairs_all > MERGE_PCAP(k)) {
+        ss_set_error("internal: merge plan exceeds its workspace");
+        return SS_ERR_INVALID_ARG;
+    }
+    if (npairs_all) {
+        SS_HIP(hipMemcpyAsync(w.PA0, pa0.data(), sizeof(u64) * npairs_all, hipMemcpyHostToDevice, st));
+        SS_HIP(hipMemcpyAsync(w.PA1, pa1.data(), sizeof(u64) * npairs_all, hipMemcpyHostToDevice, st));
+        SS_HIP(hipMemcpyAsync(w.PB1, pb1.data(), sizeof(u64) * npairs_all, hipMemcpyHostToDevice, st));
+        SS_HIP(hipMemcpyAsync(w.pg, pgv.data(), sizeof(u32) * npairs_all, hipMemcpyHostToDevice, st));
+        SS_HIP(hipMemcpyAsync(w.tstart, tsv.data(), sizeof(u32) * tsv.size(), hipMemcpyHostToDevice, st));
+    }
+    for (const LevelPlan &lp : plan) {
+        MergeLevel M{G, L, F, Go, Lo, Fo, K, Ko, w.pg + lp.off, w.Cg, w.PA0 + lp.off, w.PA1 + lp.off,
+                     w.PB1 + lp.off, w.tstart + lp.ts_off, w.pc + lp.off, w.pfirst + lp.off, lp.npt, V};
+        k_pair_info<<<(unsigned)ceil_div(lp.npt, 64), 64, 0, st>>>(M);
+        SS_CHECK_LAUNCH();
+        const u32 nblk = tsv[lp.ts_off + lp.npt];
+        if (nblk > 0) {
+            // every element's id, LCP, bound and key read once and written once
+            SS_PROF("k_merge_level", st, (double)n_out * 40.0);
+            k_merge_level<<<nblk, MW_NT, 0, st>>>(M, nblk);
+        }
+        SS_CHECK_LAUNCH();
         std::swap(G, Go);
         std::swap(L, Lo);
         std::swap(F, Fo);
@@ -889,5 +893,6 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
     k_merge_out<<<(unsigned)ceil_div(n_out, 256), 256, 0, st>>>(G, L, (u32)n_out, w.sb, w.sid, kne, fc_id,
                                                                 out_src, out_id, out_lcp);
     SS_CHECK_LAUNCH();
+    SS_HIP(hipStreamSynchronize(st));  // the host plan vectors must outlive their copies
     return SS_OK;
 }

@@ -93,18 +93,13 @@ extern "C" int ss_gather_strings(const uint8_t *bytes, uint64_t N, const uint64_
 
 // --------------------------------------------------------------- buckets
 
-// bounds[j] = #{ i : s_perm[i] <= f_j }: binary search over the sorted array.
-// All strings between the current bounds share min(lcp_lo, lcp_hi) bytes with
-// f, so each comparison starts there.
-__global__ void k_bounds(const u8 *bytes, u64 N, const u64 *off, u64 n, const u32 *perm, const u8 *sb,
-                         u64 sN, const u64 *soff, u32 r, u64 *bounds)
+// Upper bound of splitter f in the sorted positions [lo, hi): the number of
+// strings <= f.  All strings between the current bounds share
+// min(lcp_lo, lcp_hi) bytes with f, so each comparison starts there.
+__device__ u64 bound_search(const u8 *bytes, u64 N, const u64 *off, const u32 *perm, u64 lo, u64 hi,
+                            const u8 *sb, u64 sN, u64 fo, u64 fl)
 {
-    const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j == 0) bounds[0] = 0;
-    if (j == r) bounds[r] = n;
-    if (j == 0 || j >= r) return;
-    const u64 fo = soff[j - 1], fl = soff[j] - fo;
-    u64 lo = 0, hi = n, llo = 0, lhi = 0;
+    u64 llo = 0, lhi = 0;
     while (lo < hi) {
         const u64 mid = (lo + hi) >> 1;
         const u32 p = perm[mid];
@@ -120,7 +115,22 @@ __global__ void k_bounds(const u8 *bytes, u64 N, const u64 *off, u64 n, const u3
             lhi = lc;
         }
     }
-    bounds[j] = lo;
+    return lo;
+}
+
+// bounds of set b: run_off[b*(r+1) + j] = set_off[b] + #{ s in set b : s <= f_j }
+// (set_off == NULL: one set [0, n))
+__global__ void k_bounds(const u8 *bytes, u64 N, const u64 *off, const u64 *set_off, u64 n, u32 nsets,
+                         const u32 *perm, const u8 *sb, u64 sN, const u64 *soff, u32 r, u64 *bounds)
+{
+    const u64 t = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (u64)nsets * (r + 1)) return;
+    const u32 b = (u32)(t / (r + 1)), j = (u32)(t % (r + 1));
+    const u64 lo = set_off ? set_off[b] : 0, hi = set_off ? set_off[b + 1] : n;
+    if (j == 0) { bounds[t] = lo; return; }
+    if (j == r) { bounds[t] = hi; return; }
+    const u64 fo = soff[j - 1], fl = soff[j] - fo;
+    bounds[t] = bound_search(bytes, N, off, perm, lo, hi, sb, sN, fo, fl);
 }
 
 extern "C" int ss_bucket_bounds(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
@@ -133,7 +143,7 @@ extern "C" int ss_bucket_bounds(const uint8_t *bytes, uint64_t N, const uint64_t
         return SS_ERR_INVALID_ARG;
     }
     hipStream_t st = (hipStream_t)stream;
-    k_bounds<<<(unsigned)ceil_div((u64)r + 1, 256), 256, 0, st>>>(bytes, N, offsets, n, perm, spl_bytes,
+    k_bounds<<<(unsigned)ceil_div((u64)r + 1, 256), 256, 0, st>>>(bytes, N, offsets, nullptr, n, 1, perm, spl_bytes,
                                                                   spl_N, spl_offsets, r, bounds);
     SS_CHECK_LAUNCH();
     return SS_OK;
@@ -142,14 +152,17 @@ extern "C" int ss_bucket_bounds(const uint8_t *bytes, uint64_t N, const uint64_t
 // ---------------------------------------------------------- front coding
 
 // e_i, d_i, id_i and the literal length d_i - e_i of every sorted position.
+// run_off holds nb = sets*(r+1) non-decreasing bucket bounds (the bounds of
+// all sets, one after the other); position i starts a bucket iff some bound
+// equals i, and otherwise the largest bound below i is its bucket's start.
 __global__ __launch_bounds__(256) void k_fc_meta(const u64 *off, u32 n, const u32 *perm, const u32 *lcp,
-                                                 const u32 *dist, const u64 *run_off, u32 r, u32 *fc_lcp,
+                                                 const u32 *dist, const u64 *run_off, u32 nb, u32 *fc_lcp,
                                                  u32 *fc_len, u32 *fc_id, u64 *sizes, u32 *bad)
 {
     const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     // bucket start: the largest run_off[j] <= i
-    u32 lo = 0, hi = r;  // run_off has r+1 entries
+    u32 lo = 0, hi = nb - 1;
     while (hi - lo > 1) {
         u32 mid = (lo + hi) >> 1;
         if (run_off[mid] <= i) lo = mid;
@@ -179,26 +192,25 @@ __global__ void k_add_base(u64 *a, u64 n, u64 base)
 #define CP_NT 256
 #define CP_PER 16
 
+#define CP_MAXS 1024  // strings whose metadata a workgroup stages in LDS
+
 // Output-ordered copy of literal bytes: each thread writes 16 consecutive
-// output bytes; the workgroup first finds the range of strings its 4096 bytes
-// cover, then each thread locates its string inside that range.
+// output bytes.  The workgroup finds the strings its 4096 bytes cover, stages
+// their output starts and source addresses in LDS, and every thread walks its
+// bytes through that table (a workgroup covering more than CP_MAXS strings,
+// i.e. mostly empty literals, searches the global arrays instead).
 __global__ __launch_bounds__(CP_NT) void k_fc_copy(const u8 *bytes, const u64 *off, u32 n, const u32 *perm,
-                                                   const u32 *fc_lcp, const u64 *suf_off_abs, u64 base, u64 total,
+                                                   const u32 *fc_lcp, const u64 *suf_off, u64 base, u64 total,
                                                    u8 *suf)
 {
-    // suf_off_abs includes `base`; positions below are relative to it
-    struct Rel {
-        const u64 *p; u64 b;
-        __device__ u64 operator[](u64 i) const { return p[i] - b; }
-    } suf_off{suf_off_abs, base};
-    suf += base;
     __shared__ u32 range[2];
+    __shared__ u64 sstart[CP_MAXS + 1];
+    __shared__ u64 ssrc[CP_MAXS];
     const u64 c0 = (u64)blockIdx.x * CP_NT * CP_PER;
     const u64 c1 = (c0 + CP_NT * CP_PER < total) ? c0 + CP_NT * CP_PER : total;
     if (threadIdx.x < 2) {
-        const u64 q = threadIdx.x == 0 ? c0 : c1 - 1;
-        // largest i with suf_off[i] <= q
-        u32 lo = 0, hi = n;
+        const u64 q = (threadIdx.x == 0 ? c0 : c1 - 1) + base;
+        u32 lo = 0, hi = n;  // largest i with suf_off[i] <= q
         while (hi - lo > 1) {
             u32 mid = (lo + hi) >> 1;
             if (suf_off[mid] <= q) lo = mid;
@@ -207,35 +219,65 @@ __global__ __launch_bounds__(CP_NT) void k_fc_copy(const u8 *bytes, const u64 *o
         range[threadIdx.x] = lo;
     }
     __syncthreads();
-    const u64 q0 = c0 + (u64)threadIdx.x * CP_PER;
-    if (q0 >= c1) return;
-    u32 lo = range[0], hi = range[1] + 1;
-    while (hi - lo > 1) {
-        u32 mid = (lo + hi) >> 1;
-        if (suf_off[mid] <= q0) lo = mid;
-        else hi = mid;
-    }
-    u32 i = lo;
-    u64 so = suf_off[i], se = suf_off[i + 1];
-    u64 src = off[perm[i]] + fc_lcp[i];
-    u8 buf[CP_PER];
-    const u32 cnt = (u32)((c1 - q0) < CP_PER ? (c1 - q0) : CP_PER);
-#pragma unroll
-    for (u32 t = 0; t < CP_PER; t++) {
-        if (t < cnt) {
-            const u64 q = q0 + t;
-            while (q >= se) {
-                i++;
-                so = se;
-                se = suf_off[i + 1];
-                src = off[perm[i]] + fc_lcp[i];
-            }
-            buf[t] = bytes[src + (q - so)];
-        } else {
-            buf[t] = 0;
+    const u32 i0 = range[0], i1 = range[1];
+    const u32 ns = i1 - i0 + 1;
+    const bool staged = ns <= CP_MAXS;
+    if (staged) {
+        for (u32 k = threadIdx.x; k <= ns; k += CP_NT) {
+            sstart[k] = suf_off[i0 + k] - base;  // i0 + ns <= n: suf_off has n+1 entries
+            if (k < ns) ssrc[k] = off[perm[i0 + k]] + fc_lcp[i0 + k];
         }
     }
-    u8 *dst = suf + q0;
+    __syncthreads();
+    const u64 q0 = c0 + (u64)threadIdx.x * CP_PER;
+    if (q0 >= c1) return;
+    const u32 cnt = (u32)((c1 - q0) < CP_PER ? (c1 - q0) : CP_PER);
+    u8 buf[CP_PER];
+    if (staged) {
+        u32 lo = 0, hi = ns;  // largest k with sstart[k] <= q0
+        while (hi - lo > 1) {
+            u32 mid = (lo + hi) >> 1;
+            if (sstart[mid] <= q0) lo = mid;
+            else hi = mid;
+        }
+        u32 k = lo;
+#pragma unroll
+        for (u32 t = 0; t < CP_PER; t++) {
+            if (t < cnt) {
+                const u64 q = q0 + t;
+                while (q >= sstart[k + 1]) k++;
+                buf[t] = bytes[ssrc[k] + (q - sstart[k])];
+            } else {
+                buf[t] = 0;
+            }
+        }
+    } else {
+        u32 lo = i0, hi = i1 + 1;
+        while (hi - lo > 1) {
+            u32 mid = (lo + hi) >> 1;
+            if (suf_off[mid] - base <= q0) lo = mid;
+            else hi = mid;
+        }
+        u32 i = lo;
+        u64 so = suf_off[i] - base, se = suf_off[i + 1] - base;
+        u64 src = off[perm[i]] + fc_lcp[i];
+#pragma unroll
+        for (u32 t = 0; t < CP_PER; t++) {
+            if (t < cnt) {
+                const u64 q = q0 + t;
+                while (q >= se) {
+                    i++;
+                    so = se;
+                    se = suf_off[i + 1] - base;
+                    src = off[perm[i]] + fc_lcp[i];
+                }
+                buf[t] = bytes[src + (q - so)];
+            } else {
+                buf[t] = 0;
+            }
+        }
+    }
+    u8 *dst = suf + base + q0;
     if (cnt == CP_PER && (((uintptr_t)dst) & 15) == 0) {
         uint4 v;
         v.x = buf[0] | (buf[1] << 8) | (buf[2] << 16) | ((u32)buf[3] << 24);
@@ -256,17 +298,16 @@ extern "C" size_t ss_partition_encode_workspace(uint64_t n)
     return c.used;
 }
 
-extern "C" int ss_partition_encode(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
-                                   const uint32_t *perm, const uint32_t *lcp, const uint32_t *dist,
-                                   const uint8_t *spl_bytes, uint64_t spl_N, const uint64_t *spl_offsets,
-                                   uint32_t r, uint64_t *run_off, uint32_t *fc_lcp, uint32_t *fc_len,
-                                   uint32_t *fc_id, uint64_t *suf_off, uint8_t *suf, uint64_t suf_base,
-                                   uint64_t suf_cap, uint64_t *suf_total_host, void *ws, size_t ws_bytes,
-                                   void *stream)
+static int encode_impl(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n, const uint64_t *set_off,
+                       uint32_t nsets, const uint32_t *perm, const uint32_t *lcp, const uint32_t *dist,
+                       const uint8_t *spl_bytes, uint64_t spl_N, const uint64_t *spl_offsets, uint32_t r,
+                       uint64_t *run_off, uint32_t *fc_lcp, uint32_t *fc_len, uint32_t *fc_id, uint64_t *suf_off,
+                       uint8_t *suf, uint64_t suf_base, uint64_t suf_cap, uint64_t *suf_total_host, void *ws,
+                       size_t ws_bytes, void *stream)
 {
-    ss_clear_error();
     if (n >= 0xFFFFFFFFull) { ss_set_error("n too large"); return SS_ERR_TOO_LARGE; }
-    if (r == 0 || !run_off || !suf_off || (n > 0 && (!offsets || !perm || !lcp || !fc_lcp || !fc_len || !fc_id))) {
+    if (r == 0 || nsets == 0 || !run_off || !suf_off || (r > 1 && !spl_offsets) ||
+        (n > 0 && (!offsets || !perm || !lcp || !fc_lcp || !fc_len || !fc_id))) {
         ss_set_error("partition_encode: bad arguments");
         return SS_ERR_INVALID_ARG;
     }
@@ -278,11 +319,18 @@ extern "C" int ss_partition_encode(const uint8_t *bytes, uint64_t N, const uint6
         ss_set_error("workspace too small: need %zu bytes", ss_partition_encode_workspace(n));
         return SS_ERR_WORKSPACE;
     }
-    SS_TRY(ss_bucket_bounds(bytes, N, offsets, n, perm, spl_bytes, spl_N, spl_offsets, r, run_off, stream));
+    const u64 nb = (u64)nsets * (r + 1);
+    k_bounds<<<(unsigned)ceil_div(nb, 64), 64, 0, st>>>(bytes, N, offsets, set_off, n, nsets, perm, spl_bytes,
+                                                        spl_N, spl_offsets, r, run_off);
+    SS_CHECK_LAUNCH();
     SS_HIP(hipMemsetAsync(bad, 0, sizeof(u32), st));
     if (n > 0) {
-        k_fc_meta<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(offsets, (u32)n, perm, lcp, dist, run_off, r,
-                                                               fc_lcp, fc_len, fc_id, suf_off, bad);
+        {
+            // perm, lcp, offsets, dist in; e, d, id and the literal length out
+            SS_PROF("k_fc_meta", st, (double)n * (dist ? 48.0 : 44.0));
+            k_fc_meta<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(offsets, (u32)n, perm, lcp, dist, run_off, (u32)nb,
+                                                                   fc_lcp, fc_len, fc_id, suf_off, bad);
+        }
         SS_CHECK_LAUNCH();
     }
     SS_TRY(ss_scan_exclusive<u64>(suf_off, suf_off, n, scratch, st));
@@ -301,16 +349,51 @@ extern "C" int ss_partition_encode(const uint8_t *bytes, uint64_t N, const uint6
         return SS_ERR_INVALID_ARG;
     }
     if (suf_base + total > suf_cap) {
-        ss_set_error("literal bytes %llu exceed capacity %llu", (unsigned long long)total,
+        ss_set_error("literal bytes %llu exceed capacity %llu", (unsigned long long)(suf_base + total),
                      (unsigned long long)suf_cap);
         return SS_ERR_CAPACITY;
     }
     if (suf_total_host) *suf_total_host = total;
     if (total > 0) {
-        k_fc_copy<<<(unsigned)ceil_div(total, CP_NT * CP_PER), CP_NT, 0, st>>>(bytes, offsets, (u32)n, perm,
-                                                                             fc_lcp, suf_off, suf_base, total,
-                                                                             suf);
+        {
+            // literal bytes read and written; per string its perm, offsets, e and suf_off
+            SS_PROF("k_fc_copy", st, 2.0 * (double)total + (double)n * 24.0);
+            k_fc_copy<<<(unsigned)ceil_div(total, CP_NT * CP_PER), CP_NT, 0, st>>>(bytes, offsets, (u32)n, perm,
+                                                                                 fc_lcp, suf_off, suf_base, total,
+                                                                                 suf);
+        }
         SS_CHECK_LAUNCH();
     }
     return SS_OK;
+}
+
+extern "C" int ss_partition_encode(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                                   const uint32_t *perm, const uint32_t *lcp, const uint32_t *dist,
+                                   const uint8_t *spl_bytes, uint64_t spl_N, const uint64_t *spl_offsets,
+                                   uint32_t r, uint64_t *run_off, uint32_t *fc_lcp, uint32_t *fc_len,
+                                   uint32_t *fc_id, uint64_t *suf_off, uint8_t *suf, uint64_t suf_base,
+                                   uint64_t suf_cap, uint64_t *suf_total_host, void *ws, size_t ws_bytes,
+                                   void *stream)
+{
+    ss_clear_error();
+    return encode_impl(bytes, N, offsets, n, nullptr, 1, perm, lcp, dist, spl_bytes, spl_N, spl_offsets, r, run_off,
+                       fc_lcp, fc_len, fc_id, suf_off, suf, suf_base, suf_cap, suf_total_host, ws, ws_bytes, stream);
+}
+
+extern "C" int ss_partition_encode_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                                         const uint64_t *set_off, uint32_t num_sets, const uint32_t *perm,
+                                         const uint32_t *lcp, const uint32_t *dist, const uint8_t *spl_bytes,
+                                         uint64_t spl_N, const uint64_t *spl_offsets, uint32_t r, uint64_t *run_off,
+                                         uint32_t *fc_lcp, uint32_t *fc_len, uint32_t *fc_id, uint64_t *suf_off,
+                                         uint8_t *suf, uint64_t suf_base, uint64_t suf_cap,
+                                         uint64_t *suf_total_host, void *ws, size_t ws_bytes, void *stream)
+{
+    ss_clear_error();
+    if (!set_off || num_sets == 0) {
+        ss_set_error("partition_encode_batch needs set_off and num_sets >= 1");
+        return SS_ERR_INVALID_ARG;
+    }
+    return encode_impl(bytes, N, offsets, n, set_off, num_sets, perm, lcp, dist, spl_bytes, spl_N, spl_offsets, r,
+                       run_off, fc_lcp, fc_len, fc_id, suf_off, suf, suf_base, suf_cap, suf_total_host, ws,
+                       ws_bytes, stream);
 }

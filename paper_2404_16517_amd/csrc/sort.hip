@@ -34,7 +34,13 @@
 #define LDS_NT 512
 #define LDS_CAP 2048  // elements per LDS tile (2 x the largest cutover)
 
-enum { C_SMALL = 0, C_LARGE = 1, C_NEXT = 2, C_IDENT = 3, C_BND = 4, C_NCTR = 8 };
+// counters: list lengths, and the tile / element totals of the lists being
+// built (so that grids are known without reading the lists back)
+enum {
+    C_SMALL = 0, C_LARGE = 1, C_NEXT = 2, C_IDENT = 3, C_BND = 4,
+    C_LTILES = 5, C_SMALLN = 6, C_NTILES = 7, C_ITILES = 8, C_LELEM = 9, C_NELEM = 12, C_NCTR = 16
+};
+// ctr[10..11]: 64-bit sum of size * skip over the routed segments
 
 // ------------------------------------------------------------ wave helpers
 
@@ -60,6 +66,14 @@ __device__ __forceinline__ u32 wave_append(bool pred, u32 *counter)
     if (__lane_id() == leader) base = atomicAdd(counter, (u32)__popcll(m));
     base = __shfl(base, leader, 64);
     return base + (u32)__popcll(m & lanemask_lt());
+}
+
+// Wave-aggregated atomic add of per-lane values.
+__device__ __forceinline__ void wave_add(u32 v, u32 *counter)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (__lane_id() == 0 && v) atomicAdd(counter, v);
 }
 
 __device__ __forceinline__ u32 seg_of_tile(const u32 *tstart, u32 nseg, u32 t)
@@ -192,7 +206,7 @@ __global__ __launch_bounds__(NT) void k_keys(const Seg *segs, const u32 *tstart,
 }
 
 // Apply the skip, route each active segment to the LDS list or the radix list.
-__global__ void k_classify(const Seg *act, u32 nact, const u32 *skipv, u32 small_max, Seg *small,
+__global__ void k_classify(const Seg *act, u32 nact, const u32 *skipv, u32 small_max, u32 tile, Seg *small,
                            Seg *large, u32 *ctr)
 {
     u32 j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,6 +223,16 @@ __global__ void k_classify(const Seg *act, u32 nact, const u32 *skipv, u32 small
     if (sm) small[a] = g;
     u32 b = wave_append(lg, &ctr[C_LARGE]);
     if (lg) large[b] = g;
+    const u32 sz = g.end - g.begin;
+    {
+        u64 sk = (valid && (act[j].aux & SEG_SKIP)) ? (u64)sz * skipv[j] : 0ull;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sk += __shfl_xor(sk, o, 64);
+        if (__lane_id() == 0 && sk) atomicAdd((unsigned long long *)&ctr[10], (unsigned long long)sk);
+    }
+    wave_add(sm ? sz : 0u, &ctr[C_SMALLN]);
+    wave_add(lg ? (sz + tile - 1) / tile : 0u, &ctr[C_LTILES]);
+    wave_add(lg ? sz : 0u, &ctr[C_LELEM]);
 }
 
 // ------------------------------------------------------------ radix passes
@@ -260,8 +284,32 @@ struct EmitOut {
     u32 *ctr;
     u8 *scat;
     u32 small_max;
+    u32 tile;
     int plain;
 };
+
+__device__ __forceinline__ void push_next(Seg *next, u32 *ctr, Seg g)
+{
+    const u32 a = atomicAdd(&ctr[C_NEXT], 1u);
+    next[a] = g;
+    atomicAdd(&ctr[C_NTILES], (g.end - g.begin + ETILE - 1) / ETILE);
+    atomicAdd(&ctr[C_NELEM], g.end - g.begin);
+}
+
+__device__ __forceinline__ void push_small(const EmitOut &o, Seg g)
+{
+    const u32 a = atomicAdd(&o.ctr[C_SMALL], 1u);
+    o.small[a] = g;
+    atomicAdd(&o.ctr[C_SMALLN], g.end - g.begin);
+}
+
+__device__ __forceinline__ void push_large(const EmitOut &o, Seg g)
+{
+    const u32 a = atomicAdd(&o.ctr[C_LARGE], 1u);
+    o.large_next[a] = g;
+    atomicAdd(&o.ctr[C_LTILES], (g.end - g.begin + o.tile - 1) / o.tile);
+    atomicAdd(&o.ctr[C_LELEM], g.end - g.begin);
+}
 
 // A run of strings with equal keys (all 8 key bytes): continue next round, or
 // equal strings.
@@ -269,11 +317,11 @@ __device__ __forceinline__ void emit_exhausted(const EmitOut &o, u32 b, u32 e, u
 {
     if (o.plain) return;
     if (cnt == 8) {
-        u32 a = atomicAdd(&o.ctr[C_NEXT], 1u);
-        o.next[a] = Seg{b, e, depth + 7, SEG_SKIP};
+        push_next(o.next, o.ctr, Seg{b, e, depth + 7, SEG_SKIP});
     } else {
         u32 a = atomicAdd(&o.ctr[C_IDENT], 1u);
         o.ident[a] = Seg{b, e, depth + cnt, 0};
+        atomicAdd(&o.ctr[C_ITILES], (e - b + ETILE - 1) / ETILE);
     }
 }
 
@@ -302,32 +350,65 @@ __global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart
         // bytes level..fb-1 are common to the whole segment: no scatter needed
         if (d == 0) {
             o.scat[s] = 0;
-            u32 a = atomicAdd(&o.ctr[C_LARGE], 1u);
-            o.large_next[a] = Seg{g.begin, g.end, g.depth, fb};
+            push_large(o, Seg{g.begin, g.end, g.depth, fb});
         }
         return;
     }
     if (d == 0) o.scat[s] = 1;
+    // this digit's bucket, and what it becomes; appends are aggregated per
+    // workgroup (one global atomic per counter)
+    enum { K_NONE = 0, K_SMALL, K_LARGE, K_NEXT, K_IDENT };
+    __shared__ u32 lcount[5], lsum[6], gbase[5];
+    if (d < 5) lcount[d] = 0;
+    if (d < 6) lsum[d] = 0;
+    __syncthreads();
     const u32 e = 256u * ts + d * T;
     const u32 base = hist[256u * ts];
     const u32 start = hist[e] - base;
     const u32 cnt = hist[e + T] - hist[e];
-    if (cnt == 0) return;
     const u32 sb = g.begin + start, se = sb + cnt;
-    if (start > 0 && !o.plain) {
-        u32 a = atomicAdd(&o.ctr[C_BND], 1u);
-        o.bnd[a] = make_uint2(sb, g.depth);
+    const bool has_bnd = cnt > 0 && start > 0 && !o.plain;
+    u32 kind = K_NONE;
+    Seg ns = {sb, se, g.depth, 0};
+    if (cnt >= 2) {
+        if (level == 7) {
+            if (!o.plain) {
+                if (d == 8) { kind = K_NEXT; ns = Seg{sb, se, g.depth + 7, SEG_SKIP}; }
+                else { kind = K_IDENT; ns = Seg{sb, se, g.depth + d, 0}; }
+            }
+        } else if (cnt <= o.small_max) {
+            kind = K_SMALL;
+        } else {
+            kind = K_LARGE;
+            ns.aux = level + 1;
+        }
     }
-    if (cnt == 1) return;
-    if (level == 7) {
-        emit_exhausted(o, sb, se, g.depth, d);
-    } else if (cnt <= o.small_max) {
-        u32 a = atomicAdd(&o.ctr[C_SMALL], 1u);
-        o.small[a] = Seg{sb, se, g.depth, 0};
-    } else {
-        u32 a = atomicAdd(&o.ctr[C_LARGE], 1u);
-        o.large_next[a] = Seg{sb, se, g.depth, level + 1};
+    const u32 bslot = has_bnd ? atomicAdd(&lcount[0], 1u) : 0u;
+    const u32 slot = kind ? atomicAdd(&lcount[kind], 1u) : 0u;
+    if (kind == K_SMALL) atomicAdd(&lsum[0], cnt);
+    if (kind == K_LARGE) { atomicAdd(&lsum[1], (cnt + o.tile - 1) / o.tile); atomicAdd(&lsum[2], cnt); }
+    if (kind == K_NEXT) { atomicAdd(&lsum[3], (cnt + ETILE - 1) / ETILE); atomicAdd(&lsum[4], cnt); }
+    if (kind == K_IDENT) atomicAdd(&lsum[5], (cnt + ETILE - 1) / ETILE);
+    __syncthreads();
+    if (d == 0) {
+        gbase[0] = lcount[0] ? atomicAdd(&o.ctr[C_BND], lcount[0]) : 0u;
+        gbase[K_SMALL] = lcount[K_SMALL] ? atomicAdd(&o.ctr[C_SMALL], lcount[K_SMALL]) : 0u;
+        gbase[K_LARGE] = lcount[K_LARGE] ? atomicAdd(&o.ctr[C_LARGE], lcount[K_LARGE]) : 0u;
+        gbase[K_NEXT] = lcount[K_NEXT] ? atomicAdd(&o.ctr[C_NEXT], lcount[K_NEXT]) : 0u;
+        gbase[K_IDENT] = lcount[K_IDENT] ? atomicAdd(&o.ctr[C_IDENT], lcount[K_IDENT]) : 0u;
+        if (lsum[0]) atomicAdd(&o.ctr[C_SMALLN], lsum[0]);
+        if (lsum[1]) atomicAdd(&o.ctr[C_LTILES], lsum[1]);
+        if (lsum[2]) atomicAdd(&o.ctr[C_LELEM], lsum[2]);
+        if (lsum[3]) atomicAdd(&o.ctr[C_NTILES], lsum[3]);
+        if (lsum[4]) atomicAdd(&o.ctr[C_NELEM], lsum[4]);
+        if (lsum[5]) atomicAdd(&o.ctr[C_ITILES], lsum[5]);
     }
+    __syncthreads();
+    if (has_bnd) o.bnd[gbase[0] + bslot] = make_uint2(sb, g.depth);
+    if (kind == K_SMALL) o.small[gbase[K_SMALL] + slot] = ns;
+    if (kind == K_LARGE) o.large_next[gbase[K_LARGE] + slot] = ns;
+    if (kind == K_NEXT) o.next[gbase[K_NEXT] + slot] = ns;
+    if (kind == K_IDENT) o.ident[gbase[K_IDENT] + slot] = ns;
 }
 
 // Stable scatter of (key, payload) by the current byte into the B arrays.
@@ -448,6 +529,8 @@ __global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32
     __shared__ u32 spref[LDS_CAP / 2 + 1];
     __shared__ u32 sbeg[LDS_CAP / 2];
     __shared__ u32 sdep[LDS_CAP / 2];
+    __shared__ Seg nq[LDS_CAP / 2];  // next-round segments found in this tile
+    __shared__ u32 nq_count, nq_tiles, nq_elems, nq_base;
     const u32 t = blockIdx.x;
     const u32 lo = t * H, hi = lo + H;
     // j0 = first segment with pref >= lo, j1 = first with pref >= hi
@@ -464,6 +547,7 @@ __global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32
     const u32 ns = j1 - j0;
     const u32 base = pref[j0];
     const u32 cnt = pref[j1] - base;
+    if (threadIdx.x == 0) { nq_count = 0; nq_tiles = 0; nq_elems = 0; }
     for (u32 k = threadIdx.x; k <= ns; k += LDS_NT) spref[k] = pref[j0 + k] - base;
     for (u32 k = threadIdx.x; k < ns; k += LDS_NT) {
         Seg g = small[j0 + k];
@@ -529,21 +613,31 @@ __global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32
         if (last) {
             u32 x = first, y = e;  // first index in [first, e] with key == kb
             while (x < y) { u32 m = (x + y) >> 1; if (skey[m] < kb) x = m + 1; else y = m; }
-            const u32 slot = atomicAdd(&ctr[C_NEXT], 1u);
-            next[slot] = Seg{sbeg[a] + (x - first), pos + 1, dep + 7, SEG_SKIP};
+            const Seg ns{sbeg[a] + (x - first), pos + 1, dep + 7, SEG_SKIP};
+            const u32 slot = atomicAdd(&nq_count, 1u);
+            nq[slot] = ns;
+            atomicAdd(&nq_tiles, (ns.end - ns.begin + ETILE - 1) / ETILE);
+            atomicAdd(&nq_elems, ns.end - ns.begin);
         }
     }
+    // publish this tile's next-round segments with one atomic per counter
+    __syncthreads();
+    if (threadIdx.x == 0 && nq_count) {
+        nq_base = atomicAdd(&ctr[C_NEXT], nq_count);
+        atomicAdd(&ctr[C_NTILES], nq_tiles);
+        atomicAdd(&ctr[C_NELEM], nq_elems);
+    }
+    __syncthreads();
+    for (u32 k = threadIdx.x; k < nq_count; k += LDS_NT) next[nq_base + k] = nq[k];
 }
 
 // ------------------------------------------------------------ host driver
 
-static int build_tiles(const Seg *segs, u32 nseg, u32 tile, u32 *tstart, void *scan_scratch,
-                       hipStream_t st, u32 *total)
+static int build_tiles(const Seg *segs, u32 nseg, u32 tile, u32 *tstart, void *scan_scratch, hipStream_t st)
 {
     k_tile_counts<<<(unsigned)ceil_div(nseg, 256), 256, 0, st>>>(segs, nseg, tile, tstart);
     SS_CHECK_LAUNCH();
-    SS_TRY(ss_scan_exclusive<u32>(tstart, tstart, nseg, (u32 *)scan_scratch, st));
-    return ss_read_u32(tstart + nseg, total, 1, st);
+    return ss_scan_exclusive<u32>(tstart, tstart, nseg, (u32 *)scan_scratch, st);
 }
 
 void sort_ws_layout(u64 n, SortWs *w, WsArena *a, WsCounter *c)
@@ -583,52 +677,73 @@ void sort_ws_layout(u64 n, SortWs *w, WsArena *a, WsCounter *c)
 }
 
 // Run rounds until no segment is unresolved.  The caller prepared w.act
-// (nact segments), the payload array `vals`, and in PLAIN mode the keys.
-int sort_rounds(const SortJob &J, SortWs &w, u32 nact)
+// (nact segments covering atiles element tiles), the payload array `vals`,
+// and in PLAIN mode the keys.  The host reads the counters once after the
+// routing, once per radix level and once at the end of a round.
+int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
 {
     hipStream_t st = J.stream;
     const u32 SM = (u32)g_small_max;
     const u32 TL = (u32)g_tile;
     u32 *lcp = J.lcp;
     u32 h[C_NCTR];
+    u64 round_elems = J.n_first;
     while (nact > 0) {
         SS_HIP(hipMemsetAsync(w.ctr, 0, sizeof(u32) * C_NCTR, st));
         if (!J.plain) {
-            u32 ntile;
-            SS_TRY(build_tiles(w.act, nact, ETILE, w.tstart, w.scan_scratch, st, &ntile));
+            SS_TRY(build_tiles(w.act, nact, ETILE, w.tstart, w.scan_scratch, st));
             SS_HIP(hipMemsetAsync(w.skipv, 0xFF, sizeof(u32) * nact, st));
-            k_skip<<<ntile, NT, 0, st>>>(w.act, w.tstart, nact, J.bytes, J.N, J.off, J.vals, w.skipv);
+            {
+                // algorithmic bytes: perm + offsets per string, plus the common prefix
+                // and one word (added once the skips are known)
+                SS_PROF("k_skip", st, (double)round_elems * 28.0);
+                k_skip<<<atiles, NT, 0, st>>>(w.act, w.tstart, nact, J.bytes, J.N, J.off, J.vals, w.skipv);
+            }
             SS_CHECK_LAUNCH();
-            k_keys<<<ntile, NT, 0, st>>>(w.act, w.tstart, nact, J.bytes, J.N, J.off, J.vals, w.skipv,
-                                          w.keyA);
+            {
+                SS_PROF("k_keys", st, (double)round_elems * 36.0);  // perm, offsets, 8 B read, key write
+                k_keys<<<atiles, NT, 0, st>>>(w.act, w.tstart, nact, J.bytes, J.N, J.off, J.vals, w.skipv, w.keyA);
+            }
             SS_CHECK_LAUNCH();
         }
-        k_classify<<<(unsigned)ceil_div(nact, 256), 256, 0, st>>>(w.act, nact, w.skipv, SM, w.small,
-                                                                   w.largeA, w.ctr);
+        k_classify<<<(unsigned)ceil_div(nact, 256), 256, 0, st>>>(w.act, nact, w.skipv, SM, TL, w.small, w.largeA,
+                                                                   w.ctr);
         SS_CHECK_LAUNCH();
         SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, st));
-        u32 nlarge = h[C_LARGE];
+        if (!J.plain) ss_prof_add_bytes("k_skip", (double)(h[10] | ((u64)h[11] << 32)));
+        u32 nlarge = h[C_LARGE], ltiles = h[C_LTILES], lelem = h[C_LELEM];
         Seg *LA = w.largeA, *LB = w.largeB;
         while (nlarge > 0) {
-            u32 ntile;
-            SS_TRY(build_tiles(LA, nlarge, TL, w.tstart, w.scan_scratch, st, &ntile));
+            SS_TRY(build_tiles(LA, nlarge, TL, w.tstart, w.scan_scratch, st));
             SS_HIP(hipMemsetAsync(w.smin, 0xFF, sizeof(u64) * nlarge, st));
             SS_HIP(hipMemsetAsync(w.smax, 0, sizeof(u64) * nlarge, st));
-            k_hist<<<ntile, NT, 0, st>>>(LA, w.tstart, nlarge, TL, w.keyA, w.hist, w.smin, w.smax);
+            {
+                SS_PROF("k_hist", st, (double)lelem * 8.0);  // read the keys
+                k_hist<<<ltiles, NT, 0, st>>>(LA, w.tstart, nlarge, TL, w.keyA, w.hist, w.smin, w.smax);
+            }
             SS_CHECK_LAUNCH();
-            SS_TRY(ss_scan_exclusive<u32>(w.hist, w.hist, (u64)ntile * 256, (u32 *)w.scan_scratch, st));
+            SS_TRY(ss_scan_exclusive<u32>(w.hist, w.hist, (u64)ltiles * 256, (u32 *)w.scan_scratch, st));
             SS_HIP(hipMemsetAsync(w.ctr + C_LARGE, 0, sizeof(u32), st));
-            EmitOut eo{w.small, LB, w.nxt, w.ident, w.bnd, w.ctr, w.scat, SM, J.plain};
+            SS_HIP(hipMemsetAsync(w.ctr + C_LTILES, 0, sizeof(u32), st));
+            SS_HIP(hipMemsetAsync(w.ctr + C_LELEM, 0, sizeof(u32), st));
+            EmitOut eo{w.small, LB, w.nxt, w.ident, w.bnd, w.ctr, w.scat, SM, TL, J.plain};
             k_emit<<<nlarge, 256, 0, st>>>(LA, w.tstart, nlarge, w.hist, w.smin, w.smax, eo);
             SS_CHECK_LAUNCH();
-            k_scatter<<<ntile, NT, 0, st>>>(LA, w.tstart, nlarge, TL, w.hist, w.scat, w.keyA, J.vals,
-                                             w.keyB, w.valB);
+            {
+                SS_PROF("k_scatter", st, (double)lelem * 24.0);  // key+payload in and out
+                k_scatter<<<ltiles, NT, 0, st>>>(LA, w.tstart, nlarge, TL, w.hist, w.scat, w.keyA, J.vals, w.keyB,
+                                                  w.valB);
+            }
             SS_CHECK_LAUNCH();
-            k_copyback<<<ntile, NT, 0, st>>>(LA, w.tstart, nlarge, TL, w.scat, w.keyB, w.valB, w.keyA,
-                                              J.vals);
+            {
+                SS_PROF("k_copyback", st, (double)lelem * 24.0);
+                k_copyback<<<ltiles, NT, 0, st>>>(LA, w.tstart, nlarge, TL, w.scat, w.keyB, w.valB, w.keyA, J.vals);
+            }
             SS_CHECK_LAUNCH();
             SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, st));
             nlarge = h[C_LARGE];
+            ltiles = h[C_LTILES];
+            lelem = h[C_LELEM];
             Seg *tmp = LA; LA = LB; LB = tmp;
         }
         const u32 nsmall = h[C_SMALL];
@@ -636,27 +751,28 @@ int sort_rounds(const SortJob &J, SortWs &w, u32 nact)
             k_sizes<<<(unsigned)ceil_div(nsmall, 256), 256, 0, st>>>(w.small, nsmall, w.spref);
             SS_CHECK_LAUNCH();
             SS_TRY(ss_scan_exclusive<u32>(w.spref, w.spref, nsmall, (u32 *)w.scan_scratch, st));
-            u32 tot;
-            SS_TRY(ss_read_u32(w.spref + nsmall, &tot, 1, st));
-            const u32 ntile = (u32)ceil_div(tot, SM);
-            k_lds_sort<<<ntile, LDS_NT, 0, st>>>(w.small, w.spref, nsmall, SM, w.keyA, J.vals, lcp, w.nxt,
-                                                  w.ctr, J.plain);
+            const u32 ntile = (u32)ceil_div(h[C_SMALLN], SM);
+            {
+                SS_PROF("k_lds_sort", st, (double)h[C_SMALLN] * 28.0);  // key+payload in/out, LCP out
+                k_lds_sort<<<ntile, LDS_NT, 0, st>>>(w.small, w.spref, nsmall, SM, w.keyA, J.vals, lcp, w.nxt, w.ctr,
+                                                      J.plain);
+            }
+            SS_CHECK_LAUNCH();
+        }
+        if (J.plain) break;
+        if (h[C_BND] > 0) {
+            k_boundary<<<(unsigned)ceil_div(h[C_BND], 256), 256, 0, st>>>(w.bnd, h[C_BND], w.keyA, lcp);
+            SS_CHECK_LAUNCH();
+        }
+        if (h[C_IDENT] > 0) {
+            SS_TRY(build_tiles(w.ident, h[C_IDENT], ETILE, w.tstart, w.scan_scratch, st));
+            k_ident<<<h[C_ITILES], NT, 0, st>>>(w.ident, w.tstart, h[C_IDENT], lcp);
             SS_CHECK_LAUNCH();
         }
         SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, st));
-        if (!J.plain) {
-            if (h[C_BND] > 0) {
-                k_boundary<<<(unsigned)ceil_div(h[C_BND], 256), 256, 0, st>>>(w.bnd, h[C_BND], w.keyA, lcp);
-                SS_CHECK_LAUNCH();
-            }
-            if (h[C_IDENT] > 0) {
-                u32 ntile;
-                SS_TRY(build_tiles(w.ident, h[C_IDENT], ETILE, w.tstart, w.scan_scratch, st, &ntile));
-                k_ident<<<ntile, NT, 0, st>>>(w.ident, w.tstart, h[C_IDENT], lcp);
-                SS_CHECK_LAUNCH();
-            }
-        }
-        nact = J.plain ? 0 : h[C_NEXT];
+        nact = h[C_NEXT];
+        atiles = h[C_NTILES];
+        round_elems = h[C_NELEM];
         Seg *tmp = w.act; w.act = w.nxt; w.nxt = tmp;
     }
     return SS_OK;
@@ -687,8 +803,10 @@ __global__ void k_init_sets(const u64 *set_off, u32 nsets, Seg *act, u32 *ctr, u
         if (e > b) lcp[b] = 0;
     }
     bool two = valid && e > b + 1;
-    u32 a = wave_append(two, &ctr[0]);
+    u32 a = wave_append(two, &ctr[C_NEXT]);
     if (two) act[a] = Seg{b, e, 0, SEG_SKIP};
+    wave_add(two ? (e - b + ETILE - 1) / ETILE : 0u, &ctr[C_NTILES]);
+    wave_add(two ? e - b : 0u, &ctr[C_NELEM]);
 }
 
 __global__ void k_localize(const u64 *set_off, u32 nsets, u32 n, u32 *perm)
@@ -741,12 +859,12 @@ extern "C" int ss_sort(const uint8_t *bytes, uint64_t N, const uint64_t *offsets
         ss_set_error("workspace too small: need %zu bytes", ss_sort_workspace(n));
         return SS_ERR_WORKSPACE;
     }
-    SortJob J{bytes, N, offsets, perm, lcp ? lcp : w.lcp_scratch, 0, st};
+    SortJob J{bytes, N, offsets, perm, lcp ? lcp : w.lcp_scratch, 0, st, n};
     k_iota<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(perm, (u32)n);
     SS_CHECK_LAUNCH();
     k_init_single<<<1, 1, 0, st>>>(w.act, (u32)n, J.lcp);
     SS_CHECK_LAUNCH();
-    return sort_rounds(J, w, n >= 2 ? 1 : 0);
+    return sort_rounds(J, w, n >= 2 ? 1 : 0, (u32)ceil_div(n, ETILE));
 }
 
 extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
@@ -768,15 +886,16 @@ extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *o
         ss_set_error("workspace too small: need %zu bytes", ss_sort_workspace(n));
         return SS_ERR_WORKSPACE;
     }
-    SortJob J{bytes, N, offsets, perm_local, lcp ? lcp : w.lcp_scratch, 0, st};
+    SortJob J{bytes, N, offsets, perm_local, lcp ? lcp : w.lcp_scratch, 0, st, 0};
     k_iota<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(perm_local, (u32)n);
     SS_CHECK_LAUNCH();
     SS_HIP(hipMemsetAsync(w.ctr, 0, sizeof(u32) * C_NCTR, st));
     k_init_sets<<<(unsigned)ceil_div(num_sets, 256), 256, 0, st>>>(set_off, num_sets, w.act, w.ctr, J.lcp);
     SS_CHECK_LAUNCH();
-    u32 nact;
-    SS_TRY(ss_read_u32(w.ctr, &nact, 1, st));
-    SS_TRY(sort_rounds(J, w, nact));
+    u32 h[C_NCTR];
+    SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, st));
+    J.n_first = h[C_NELEM];
+    SS_TRY(sort_rounds(J, w, h[C_NEXT], h[C_NTILES]));
     k_localize<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(set_off, num_sets, (u32)n, perm_local);
     SS_CHECK_LAUNCH();
     return SS_OK;

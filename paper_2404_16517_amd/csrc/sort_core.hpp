@@ -32,7 +32,9 @@ struct SortJob {
     u32 *lcp;   // LCP output (string sort)
     int plain;  // 1: sort raw 64-bit keys in keyA, no LCP, single round
     hipStream_t stream;
+    u64 n_first;  // strings in the first round's segments (for byte accounting)
 };
 
 void sort_ws_layout(u64 n, SortWs *w, WsArena *a, WsCounter *c);
-int sort_rounds(const SortJob &J, SortWs &w, u32 nact);
+// nact segments in w.act covering `atiles` element tiles of 2048.
+int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles);

@@ -3,6 +3,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+#include <string>
+#include <vector>
+
 #include "common.hpp"
 
 static thread_local char g_err[512];
@@ -189,3 +193,99 @@ template u64 ss_scan_scratch_elems<u32>(u64);
 template u64 ss_scan_scratch_elems<u64>(u64);
 template int ss_scan_exclusive<u32>(const u32 *, u32 *, u64, u32 *, hipStream_t);
 template int ss_scan_exclusive<u64>(const u64 *, u64 *, u64, u64 *, hipStream_t);
+
+// ------------------------------------------------------------ profiling
+
+bool g_prof_on = false;
+
+namespace {
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+    double bytes;
+};
+std::mutex g_prof_mu;
+std::vector<ProfRec> g_prof;
+
+void prof_clear()
+{
+    for (auto &r : g_prof) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    g_prof.clear();
+}
+}  // namespace
+
+ProfScope::ProfScope(const char *n, hipStream_t s, double b) : name(n), st(s), bytes(b), a(nullptr), on(g_prof_on)
+{
+    if (!on) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventRecord(a, st) != hipSuccess) on = false;
+}
+
+ProfScope::~ProfScope()
+{
+    if (!on) return;
+    hipEvent_t b;
+    if (hipEventCreate(&b) != hipSuccess) return;
+    if (hipEventRecord(b, st) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.push_back(ProfRec{name, a, b, bytes});
+}
+
+void ss_prof_add_bytes(const char *name, double bytes)
+{
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (size_t i = g_prof.size(); i-- > 0;)
+        if (g_prof[i].name == name) {
+            g_prof[i].bytes += bytes;
+            return;
+        }
+}
+
+extern "C" void ss_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_clear();
+    g_prof_on = on != 0;
+}
+
+extern "C" int ss_profile_query(const char *name, double *ms, double *bytes, uint32_t *launches)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    double t = 0, by = 0;
+    uint32_t cnt = 0;
+    for (auto &r : g_prof) {
+        if (r.name != name) continue;
+        float e = 0;
+        hipEventSynchronize(r.b);
+        if (hipEventElapsedTime(&e, r.a, r.b) != hipSuccess) continue;
+        t += e;
+        by += r.bytes;
+        cnt++;
+    }
+    if (ms) *ms = t;
+    if (bytes) *bytes = by;
+    if (launches) *launches = cnt;
+    return cnt ? SS_OK : SS_ERR_INVALID_ARG;
+}
+
+extern "C" size_t ss_profile_names(char *buf, size_t cap)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    std::vector<std::string> names;
+    for (auto &r : g_prof) {
+        bool seen = false;
+        for (auto &x : names) seen |= (x == r.name);
+        if (!seen) names.push_back(r.name);
+    }
+    std::string all;
+    for (size_t i = 0; i < names.size(); i++) all += (i ? "," : "") + names[i];
+    if (buf && cap) {
+        size_t m = all.size() < cap - 1 ? all.size() : cap - 1;
+        memcpy(buf, all.data(), m);
+        buf[m] = 0;
+    }
+    return all.size();
+}

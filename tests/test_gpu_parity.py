@@ -380,3 +380,41 @@ def test_lcp_merge_groups_runs_in_place():
         np.testing.assert_array_equal(L[out:out + m], rlcp)
         out += m
     assert out == len(S)
+
+
+@pytest.mark.parametrize("pdms", [False, True])
+def test_partition_encode_batch_matches_oracle_per_set(pdms):
+    """Each processing element's sorted array split with common splitters, all in one call."""
+    sets, bounds = synth.random_sets(7, 50, 4000, len_lo=1, len_hi=30, seed=8)
+    g = sets.to(DEV)
+    perm_l, lcp = ss.sort_batch(g.bytes, g.offsets, bounds.to(DEV))
+    base = torch.repeat_interleave(bounds[:-1], bounds[1:] - bounds[:-1]).to(DEV).to(torch.int32)
+    perm = perm_l + base
+    dist = ss.dist_prefix(g.bytes, g.offsets, 8, 64)[0] if pdms else None
+    strs = sets.as_list()
+    spl = sorted(random.Random(3).sample(strs, 11))
+    sp = synth.from_list(spl).to(DEV)
+    fc = ss.partition_encode_batch(g.bytes, g.offsets, bounds.to(DEV), perm, lcp, dist, sp.bytes, sp.offsets)
+    torch.cuda.synchronize()
+    b, o = oracle.strings_np(sets)
+    sbn, son = oracle.strings_np(synth.from_list(spl))
+    d_ref = oracle.dist_prefix(b, o, 8, 64)[0] if pdms else None
+    r = len(spl) + 1
+    RO = u64(fc["run_off"]).reshape(len(bounds) - 1, r + 1)
+    FL, FD, FI, SO = u32(fc["lcp"]), u32(fc["len"]), u32(fc["id"]), u64(fc["suf_off"])
+    SUF = fc["suf"][:fc["total"]].cpu().numpy()
+    for j in range(len(bounds) - 1):
+        a, e = int(bounds[j]), int(bounds[j + 1])
+        sub_o = (o[a:e + 1] - o[a]).astype(np.uint64)
+        sub_b = b[int(o[a]):int(o[e])]
+        pr = oracle.sort(sub_b, sub_o)
+        prg = (pr + a).astype(np.uint32)
+        lr = oracle.lcp(sub_b, sub_o, pr)
+        bb = oracle.bucket_bounds(b, o, prg, sbn, son)
+        np.testing.assert_array_equal(RO[j], bb + np.uint64(a))
+        ref = oracle.fc_encode(b, o, prg, lr, d_ref, bb)
+        np.testing.assert_array_equal(FL[a:e], ref["lcp"])
+        np.testing.assert_array_equal(FD[a:e], ref["len"])
+        np.testing.assert_array_equal(FI[a:e], ref["id"])
+        np.testing.assert_array_equal(SO[a:e] - SO[a], ref["suf_off"][:e - a])
+        assert bytes(SUF[int(SO[a]):int(SO[e])]) == bytes(ref["suf"])
