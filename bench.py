@@ -127,6 +127,61 @@ def verify_dn(s, order, mlcp, dist, dpx):
     return bool(ok)
 
 
+def batch_leg(ss, torch, synth, num_sets=1024, lo=1e3, hi=1e5, reps=3):
+    """Many independent sorts: one batched launch sequence vs one call per set."""
+    dev = torch.device("cuda:0")
+    S, bounds = synth.random_sets(num_sets, lo, hi, seed=5, device=dev)
+    bl = bounds.tolist()
+    bd = bounds.to(dev)
+    ws = torch.empty(ss.lib().ss_sort_workspace(S.n), dtype=torch.uint8, device=dev)
+    pb, lb = ss.sort_batch(S.bytes, S.offsets, bd, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        pb, lb = ss.sort_batch(S.bytes, S.offsets, bd, ws=ws)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+
+    def per_job():
+        outs = []
+        for a, b in zip(bl[:-1], bl[1:]):
+            outs.append(ss.sort(S.bytes, S.offsets[a:b + 1], ws=ws))
+        return outs
+    per_job()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        outs = per_job()
+    torch.cuda.synchronize()
+    tj = (time.perf_counter() - t0) / reps
+    same = torch.equal(torch.cat([o[0] for o in outs]), pb) and torch.equal(torch.cat([o[1] for o in outs]), lb)
+    return {"sets": num_sets, "set_sizes": f"log-uniform [{lo:.0f}, {hi:.0f}]", "strings": S.n, "bytes": S.N,
+            "batched_jobs_per_s": num_sets / tb, "per_job_jobs_per_s": num_sets / tj, "speedup": tj / tb,
+            "batched_GBps": S.N / tb / 1e9, "results_identical": bool(same)}
+
+
+def serve_leg(ss, torch, synth, count=48, lo=1e3, hi=1e6, budget_gb=200.0, slots=4, load=0.7):
+    """Poisson request trace served with continuous batching vs one job at a time."""
+    from paper_2404_16517_amd import serve
+    dev = torch.device("cuda:0")
+    reqs = synth.poisson_requests(count, qps=1.0, size_lo=lo, size_hi=hi, seed=7)
+    inputs = {r.rid: synth.request_strings(r, device=dev) for r in reqs}
+    torch.cuda.synchronize()
+    serve.serve_sequential(reqs[:4], inputs)  # warm-up
+    seq, t_seq = serve.serve_sequential(reqs, inputs)
+    capacity = count / t_seq
+    scale = 1.0 / (capacity * load)   # arrivals at `load` x the sequential capacity
+    jobs, makespan = serve.serve_trace(reqs, inputs, int(budget_gb * 1e9), slots=slots, time_scale=scale)
+    lat = [j.done_s - j.arrival_s for j in jobs]
+    same = all(all(torch.equal(a, b) for a, b in zip(j.result, seq[j.rid])) for j in jobs)
+    total_bytes = sum(x.N for x in inputs.values())
+    return {"requests": count, "sizes": f"log-uniform [{lo:.0f}, {hi:.0f}] strings", "slots": slots,
+            "budget_GB": budget_gb, "offered_qps": capacity * load,
+            "p50_ms": serve.percentile(lat, 0.5) * 1e3, "p99_ms": serve.percentile(lat, 0.99) * 1e3,
+            "served_jobs_per_s": count / makespan, "sequential_jobs_per_s": capacity,
+            "served_GBps": total_bytes / makespan / 1e9, "results_identical": bool(same)}
+
+
 def cpu_baseline(s_host, p, v, target_s=15.0):
     """The CPU oracle running the same step on a bounded prefix of the input."""
     import numpy as np
@@ -202,6 +257,10 @@ def main():
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--stages", action="store_true", help="per-stage times on stderr")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-per-job leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GB",
+                    help="only run a plain device-to-device copy of this many GB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -211,7 +270,18 @@ def main():
     import paper_2404_16517_amd as ss
     import synth
 
+    from paper_2404_16517_amd import autotune
+    tuned = autotune.apply()
     dev = torch.device("cuda:0")
+    if args.calibrate_copy > 0:
+        nbytes = int(args.calibrate_copy * 1e9) // 16 * 16
+        src = torch.ones(nbytes, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 3}))
+        return
     t0 = time.time()
     s = synth.dn_strings(args.n, args.length, args.ratio, seed=0, device=dev)
     torch.cuda.synchronize()
@@ -273,6 +343,12 @@ def main():
         out["kernels_gbs"] = {k: (v[1] / (v[0] / 1e3) / 1e9 if v[0] > 0 else None) for k, v in prof.items()}
     if args.stages:
         out["stages_ms"] = {k: sum(v) / len(v) for k, v in stages.items()}
+    if not args.no_batch:
+        out["batch"] = batch_leg(ss, torch, synth)
+        print(f"# batch leg: {out['batch']}", file=sys.stderr, flush=True)
+    if not args.no_serve:
+        out["serve"] = serve_leg(ss, torch, synth)
+        print(f"# serve leg: {out['serve']}", file=sys.stderr, flush=True)
     if not args.no_cpu:
         host = synth.StringSet(s.bytes[: int(s.offsets[min(s.n, 2_000_000)])].cpu(),
                                s.offsets[: min(s.n, 2_000_000) + 1].cpu(), dict(s.meta))
