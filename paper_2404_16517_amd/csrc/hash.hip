@@ -96,58 +96,87 @@ __global__ __launch_bounds__(256) void k_hash_round(const u32 *act, u32 A, const
     if (lane == 0) {
         state[i] = C;
         keys[j] = kr_finish(C, m, bits);
-        vals[j] = i;
+        vals[j] = j;  // position in the active list (kept in input order)
     }
+}
+
+#define PRE_MAX 64  // the first pass hashes up to this many bytes of every string
+#define PRE_SLOTS 8
+
+struct PreLens {
+    u64 l[PRE_SLOTS];  // prefix lengths of the precomputed rounds (l_0, 2 l_0, ...)
+    u32 count;
+};
+
+// First pass: a group of 8 lanes reads the first min(len, W) bytes of one
+// string once (W = the last precomputed prefix length <= 64; lane j holds
+// bytes [8j, 8j+8), i.e. limbs 2j and 2j+1) and emits the key of every round
+// whose prefix length is <= W, by input index.  For a prefix of L limbs,
+// C = sum_j (limb_2j*B + limb_2j+1) * B^(L-2-2j) over lanes with both limbs in
+// the prefix, plus limb_2j for the lane whose second limb is past the prefix.
+// Keys of later rounds continue from the Horner state of the W-prefix.
+__global__ __launch_bounds__(256) void k_hash_first(u32 n, const u8 *bytes, u64 N, const u64 *off, PreLens P,
+                                                    u32 bits, BPow bp, u64 *state, u64 *pre)
+{
+    const u32 lane = threadIdx.x & 7;
+    const u32 i = blockIdx.x * 32 + (threadIdx.x >> 3);
+    if (i >= n) return;  // whole group leaves together
+    const u64 o = off[i], len = off[i + 1] - o;
+    const u64 W = P.l[P.count - 1];
+    const u64 mw = len < W ? len : W;
+    const u64 q = 8ull * lane;
+    const u32 take = q < mw ? (u32)((mw - q) < 8 ? (mw - q) : 8) : 0u;
+    const u64 w = load_le(bytes, N, o + q, take);
+    const u64 a = w & 0xFFFFFFFFull, b = w >> 32;
+    const u64 v = addmod61(mulmod61(a, KR_B), b);
+    u64 C = 0;
+    for (u32 r = 0; r < P.count; r++) {
+        const u64 m = len < P.l[r] ? len : P.l[r];
+        const u32 L = (u32)((m + 3) / 4);
+        u64 c = 0;
+        if (2 * lane + 1 < L) c = mulmod61(v, bp.p[L - 2 - 2 * lane]);
+        else if (2 * lane + 1 == L) c = a;
+#pragma unroll
+        for (int s2 = 4; s2 > 0; s2 >>= 1) c = addmod61(c, __shfl_xor(c, s2, 8));
+        C = c;
+        if (lane == 0) pre[(u64)r * n + i] = kr_finish(c, m, bits);
+    }
+    if (lane == 0) state[i] = C;
+}
+
+// Keys of a precomputed round for the active list (payload = list position).
+__global__ __launch_bounds__(256) void k_gather_keys(const u32 *act, u32 A, const u64 *pre_r, u64 *keys, u32 *vals)
+{
+    const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= A) return;
+    keys[j] = pre_r[act ? act[j] : j];
+    vals[j] = j;
 }
 
 __device__ __forceinline__ u64 lanemask_lt_h() { return (1ull << __lane_id()) - 1ull; }
 
-#define DD_PER 8
-
 // Finish strings whose key is unique among the active ones or whose length is
-// <= l; the rest form the next active list (one atomic per workgroup).
-__global__ __launch_bounds__(256) void k_dedup(const u64 *keys, const u32 *vals, u32 A, const u64 *off,
-                                               u64 l, u32 *dist, u32 *next, u32 *ctr)
+// <= l; the others are flagged (by their position in the active list) to stay.
+__global__ __launch_bounds__(256) void k_dedup(const u64 *keys, const u32 *vals, u32 A, const u32 *act,
+                                               const u64 *off, u64 l, u32 *dist, u32 *keep)
 {
-    __shared__ u32 wsum[4];
-    __shared__ u32 base_s;
-    u32 iv[DD_PER];
-    u32 mask = 0;
-#pragma unroll
-    for (int r = 0; r < DD_PER; r++) {
-        iv[r] = 0;
-        const u32 j = blockIdx.x * (256 * DD_PER) + r * 256 + threadIdx.x;
-        if (j < A) {
-            const u64 k = keys[j];
-            const bool dup = (j > 0 && keys[j - 1] == k) || (j + 1 < A && keys[j + 1] == k);
-            const u32 i = vals[j];
-            const u64 len = off[i + 1] - off[i];
-            if (!dup || len <= l) dist[i] = (u32)(len < l ? len : l);
-            else mask |= 1u << r;
-            iv[r] = i;
-        }
-    }
-    const u32 c = (u32)__popc(mask);
-    // block exclusive scan of c
-    u32 x = c;
-    const u32 lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        u32 y = __shfl_up(x, o, 64);
-        if (lane >= (u32)o) x += y;
-    }
-    if (lane == 63) wsum[wid] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        u32 t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-        base_s = t ? atomicAdd(ctr, t) : 0u;
-    }
-    __syncthreads();
-    u32 pre = x - c + base_s;
-    for (u32 w = 0; w < wid; w++) pre += wsum[w];
-#pragma unroll
-    for (int r = 0; r < DD_PER; r++)
-        if ((mask >> r) & 1u) next[pre++] = iv[r];
+    const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= A) return;
+    const u64 k = keys[j];
+    const bool dup = (j > 0 && keys[j - 1] == k) || (j + 1 < A && keys[j + 1] == k);
+    const u32 p = vals[j];
+    const u32 i = act ? act[p] : p;
+    const u64 len = off[i + 1] - off[i];
+    const bool stay = dup && len > l;
+    if (!stay) dist[i] = (u32)(len < l ? len : l);
+    keep[p] = stay ? 1u : 0u;
+}
+
+// Ordered compaction of the active list by the keep flags (pos = exclusive scan).
+__global__ void k_compact(const u32 *act, u32 A, const u32 *keep, const u32 *pos, u32 *next)
+{
+    const u32 p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < A && keep[p]) next[pos[p]] = act ? act[p] : p;
 }
 
 __global__ void k_one_seg(Seg *act, u32 A) { act[0] = Seg{0, A, 0, 0}; }
@@ -161,26 +190,22 @@ __global__ void k_neq(const u64 *keys, u32 A, u32 *flag)
 
 struct PdWs {
     SortWs sw;
-    u32 *vals, *actA, *actB, *ctr;
-    u64 *state;
+    u32 *vals, *actA, *actB, *ctr, *keep, *kpos;
+    u64 *state, *pre, *scan_scratch;
 };
 
 static void pd_layout(u64 n, PdWs *w, WsArena *a, WsCounter *c)
 {
     sort_ws_layout(n, &w->sw, a, c);
-    if (a) {
-        w->vals = a->take<u32>(n);
-        w->actA = a->take<u32>(n);
-        w->actB = a->take<u32>(n);
-        w->state = a->take<u64>(n);
-        w->ctr = a->take<u32>(4);
-    } else {
-        c->take<u32>(n);
-        c->take<u32>(n);
-        c->take<u32>(n);
-        c->take<u64>(n);
-        c->take<u32>(4);
-    }
+#define PT(field, T, cnt)                       \
+    do {                                         \
+        if (a) w->field = a->take<T>(cnt);       \
+        else c->take<T>(cnt);                    \
+    } while (0)
+    PT(vals, u32, n); PT(actA, u32, n); PT(actB, u32, n); PT(state, u64, n); PT(ctr, u32, 4);
+    PT(keep, u32, n); PT(kpos, u32, n + 1); PT(scan_scratch, u64, ss_scan_scratch_elems<u64>(n + 1));
+    PT(pre, u64, (u64)PRE_SLOTS * n);
+#undef PT
 }
 
 extern "C" size_t ss_dist_prefix_workspace(uint64_t n)
@@ -231,17 +256,31 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
     BPow bp;
     bp.p[0] = 1;
     for (int t = 1; t <= 16; t++) bp.p[t] = (u64)(((unsigned __int128)bp.p[t - 1] * KR_B) % KR_P);
+    // rounds whose prefix length is at most PRE_MAX are hashed in one first pass
+    PreLens P{};
+    for (u64 L = init_len; L <= PRE_MAX && P.count < PRE_SLOTS; L *= 2) P.l[P.count++] = L;
+    if (P.count) {
+        // the first line of every string, once
+        SS_PROF("k_hash_first", st, (double)n * (double)P.l[P.count - 1] + (double)n * (24.0 + 8.0 * P.count));
+        k_hash_first<<<(unsigned)ceil_div(n, 32), 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits, bp, w.state,
+                                                                 w.pre);
+    }
+    SS_CHECK_LAUNCH();
     u32 A = (u32)n;
-    const u32 *act = nullptr;
+    const u32 *act = nullptr;  // the active strings, in input order (NULL = all)
     u32 *nxt = w.actA;
     u64 lprev = 0, l = init_len;
     u32 rounds = 0;
     while (A > 0) {
         if (++rounds > 64) { ss_set_error("prefix doubling did not terminate"); return SS_ERR_INVALID_ARG; }
-        {
+        if (rounds <= P.count) {
+            k_gather_keys<<<(unsigned)ceil_div(A, 256), 256, 0, st>>>(act, A, w.pre + (u64)(rounds - 1) * n,
+                                                                      w.sw.keyA, w.vals);
+            SS_CHECK_LAUNCH();
+        } else {
             // new prefix bytes (exact for strings of length >= l), offsets, list entry,
             // hash state in/out, key and payload out
-            SS_PROF("k_hash_round", st, (double)A * (double)(l - lprev) + (double)A * (act ? 48.0 : 36.0));
+            SS_PROF("k_hash_round", st, (double)A * (double)(l - lprev) + (double)A * 48.0);
             const u64 nb = l - lprev;
             if (nb <= 8)
                 k_hash_round<1><<<(unsigned)ceil_div(A, 256), 256, 0, st>>>(act, A, bytes, N, offsets, lprev, l,
@@ -272,14 +311,16 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
                 SS_TRY(sort_rounds(J, w.sw, 1, (u32)ceil_div(A, 2048)));
             }
         }
-        SS_HIP(hipMemsetAsync(w.ctr, 0, sizeof(u32), st));
         {
-            SS_PROF("k_dedup", st, (double)A * 32.0);  // key, payload, offsets, one 4-byte write
-            k_dedup<<<(unsigned)ceil_div(A, 256 * DD_PER), 256, 0, st>>>(w.sw.keyA, w.vals, A, offsets, l,
-                                                                         dist_approx, nxt, w.ctr);
+            SS_PROF("k_dedup", st, (double)A * 40.0);  // key, payload, list entry, offsets, one write
+            k_dedup<<<(unsigned)ceil_div(A, 256), 256, 0, st>>>(w.sw.keyA, w.vals, A, act, offsets, l, dist_approx,
+                                                                w.keep);
         }
         SS_CHECK_LAUNCH();
-        SS_TRY(ss_read_u32(w.ctr, &A, 1, st));
+        SS_TRY(ss_scan_exclusive<u32>(w.keep, w.kpos, A, (u32 *)w.scan_scratch, st));
+        k_compact<<<(unsigned)ceil_div(A, 256), 256, 0, st>>>(act, A, w.keep, w.kpos, nxt);
+        SS_CHECK_LAUNCH();
+        SS_TRY(ss_read_u32(w.kpos + A, &A, 1, st));
         act = nxt;
         nxt = (nxt == w.actA) ? w.actB : w.actA;
         lprev = l;
