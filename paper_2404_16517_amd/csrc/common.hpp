@@ -85,6 +85,8 @@ struct ProfScope {
 #define SS_PROF(name, stream, bytes) ProfScope ss_prof_scope_(name, stream, (double)(bytes))
 // add bytes to the latest record of `name` (for counts known only after a read-back)
 void ss_prof_add_bytes(const char *name, double bytes);
+// forget the latest record of `name` (a launch that turned out to have no work)
+void ss_prof_drop_last(const char *name);
 
 // Tunables (set by ss_set_tuning).
 extern int g_small_max;

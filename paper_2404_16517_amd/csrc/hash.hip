@@ -1,9 +1,10 @@
 // Approximate distinguishing prefixes by prefix doubling (Section 4; proof
 // outline in Appendix C) with exact duplicate detection: hash each active
-// string's l-prefix, sort (hash, index) pairs, and a neighbour scan finds the
-// duplicates (the local form of Appendix B's sorting-based detection).
+// string's l-prefix and find the keys that occur more than once among the
+// active strings.  The paper detects them by sorting (hash, index) pairs and
+// scanning neighbours (Appendix B); on one GPU an open-addressing table of the
+// keys gives the same multiplicities in two passes without the sort.
 #include "common.hpp"
-#include "sort_core.hpp"
 
 #define KR_P 0x1FFFFFFFFFFFFFFFull  // 2^61 - 1
 #define KR_B 0x0B3C4D5E6F708192ull  // base
@@ -65,10 +66,11 @@ struct BPow {
 // limbs, and the group combines them as
 // C <- C * B^L + sum_j v_j * B^(limbs after lane j).
 template <int HG>
-__global__ __launch_bounds__(256) void k_hash_round(const u32 *act, u32 A, const u8 *bytes, u64 N,
+__global__ __launch_bounds__(256) void k_hash_round(const u32 *act, const u32 *cnt, const u8 *bytes, u64 N,
                                                     const u64 *off, u64 lprev, u64 l, u32 bits,
-                                                    u64 *state, u64 *keys, u32 *vals, BPow bp)
+                                                    u64 *state, u64 *keys, BPow bp)
 {
+    const u32 A = *cnt;
     const u32 g = threadIdx.x / HG, lane = threadIdx.x % HG;
     const u32 j = blockIdx.x * (256 / HG) + g;
     if (j >= A) return;  // whole group leaves together
@@ -96,12 +98,11 @@ __global__ __launch_bounds__(256) void k_hash_round(const u32 *act, u32 A, const
     if (lane == 0) {
         state[i] = C;
         keys[j] = kr_finish(C, m, bits);
-        vals[j] = j;  // position in the active list (kept in input order)
     }
 }
 
 #define PRE_MAX 64  // the first pass hashes up to this many bytes of every string
-#define PRE_SLOTS 8
+#define PRE_SLOTS 5  // 4, 8, 16, 32, 64
 
 struct PreLens {
     u64 l[PRE_SLOTS];  // prefix lengths of the precomputed rounds (l_0, 2 l_0, ...)
@@ -144,67 +145,157 @@ __global__ __launch_bounds__(256) void k_hash_first(u32 n, const u8 *bytes, u64 
     if (lane == 0) state[i] = C;
 }
 
-// Keys of a precomputed round for the active list (payload = list position).
-__global__ __launch_bounds__(256) void k_gather_keys(const u32 *act, u32 A, const u64 *pre_r, u64 *keys, u32 *vals)
+// ------------------------------------------------------------ duplicates
+//
+// Keys are < 2^61 (residues mod 2^61-1, possibly masked to fewer bits), so the
+// all-ones word marks an empty slot and bit 62 marks a key seen twice or more.
+
+#define TAB_EMPTY 0xFFFFFFFFFFFFFFFFull
+#define TAB_DUP (1ull << 62)
+
+enum { DM_TABLE = 0, DM_ALLDUP = 1, DM_UNIQUE = 2 };
+
+__device__ __forceinline__ u32 tab_slot(u64 key, u32 logT)
 {
+    return (u32)((key * 0x9E3779B97F4A7C15ull) >> (64 - logT));  // Fibonacci hashing
+}
+
+// Key of active entry j: by list position (hash rounds) or by input index
+// (rounds hashed in the first pass).
+__device__ __forceinline__ u64 key_of(const u64 *keys, int kin, u32 i, u32 j) { return keys[kin ? i : j]; }
+
+__global__ void k_store_u32(u32 *p, u32 v) { *p = v; }
+
+// For every round hashed in the first pass, over all strings: flags[2r] = 1 if
+// some key differs from string 0's, flags[2r+1] = 1 if some string has
+// length <= l_r.  A round with neither (and n >= 2) changes nothing.
+__global__ __launch_bounds__(256) void k_pre_flags(const u64 *pre, u32 n, const u64 *off, PreLens P, u32 *flags)
+{
+    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    const u64 len = i < n ? off[i + 1] - off[i] : 0;
+    for (u32 r = 0; r < P.count; r++) {
+        const bool d = i < n && pre[(u64)r * n + i] != pre[(u64)r * n];
+        const bool sh = i < n && len <= P.l[r];
+        const u64 bd = __ballot(d), bs = __ballot(sh);
+        if ((threadIdx.x & 63) == 0) {
+            if (bd) flags[2 * r] = 1u;
+            if (bs) flags[2 * r + 1] = 1u;
+        }
+    }
+}
+
+// The same two flags for one round over the active list.
+__global__ __launch_bounds__(256) void k_flags(const u64 *keys, int kin, const u32 *act, const u32 *cnt,
+                                               const u64 *off, u64 l, u32 *flags)
+{
+    const u32 A = *cnt;
+    const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    bool d = false, sh = false;
+    if (j < A) {
+        const u32 i = act ? act[j] : j;
+        const u32 i0 = act ? act[0] : 0u;
+        d = key_of(keys, kin, i, j) != key_of(keys, kin, i0, 0);
+        sh = off[i + 1] - off[i] <= l;
+    }
+    const u64 bd = __ballot(d), bs = __ballot(sh);
+    if ((threadIdx.x & 63) == 0) {
+        if (bd) flags[0] = 1u;
+        if (bs) flags[1] = 1u;
+    }
+}
+
+// Insert every active key into the table (linear probing); a key found
+// already present gets the duplicate mark.  The table has at least twice as
+// many slots as keys, so every probe sequence ends.
+__global__ __launch_bounds__(256) void k_tab_insert(const u64 *keys, int kin, const u32 *act, const u32 *cnt,
+                                                    u64 *tab, u32 logT)
+{
+    const u32 A = *cnt;
     const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= A) return;
-    keys[j] = pre_r[act ? act[j] : j];
-    vals[j] = j;
+    const u32 i = act ? act[j] : j;
+    const u64 key = key_of(keys, kin, i, j);
+    const u32 mask = (1u << logT) - 1u;
+    u32 s = tab_slot(key, logT);
+    for (u32 probe = 0; probe <= mask; probe++, s = (s + 1) & mask) {
+        u64 cur = __hip_atomic_load(&tab[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == TAB_EMPTY) {
+            cur = atomicCAS((unsigned long long *)&tab[s], TAB_EMPTY, key);
+            if (cur == TAB_EMPTY) return;  // inserted
+        }
+        if ((cur & ~TAB_DUP) == key) {
+            if (!(cur & TAB_DUP)) atomicOr((unsigned long long *)&tab[s], TAB_DUP);
+            return;
+        }
+    }
 }
 
-__device__ __forceinline__ u64 lanemask_lt_h() { return (1ull << __lane_id()) - 1ull; }
-
-// Finish strings whose key is unique among the active ones or whose length is
-// <= l; the others are flagged (by their position in the active list) to stay.
-__global__ __launch_bounds__(256) void k_dedup(const u64 *keys, const u32 *vals, u32 A, const u32 *act,
-                                               const u64 *off, u64 l, u32 *dist, u32 *keep)
+// Finish the active strings whose key is unique (or whose length is <= l):
+// dist = min(len, l).  The others are appended to the next active list
+// (one atomic per workgroup; lists keep input order within a workgroup).
+__global__ __launch_bounds__(256) void k_dedup(const u64 *keys, int kin, const u32 *act, const u32 *cnt,
+                                               const u64 *off, u64 l, int mode, const u64 *tab, u32 logT,
+                                               u32 *dist, u32 *next, u32 *ncnt)
 {
+    __shared__ u32 wcount[4], base;
+    const u32 A = *cnt;
     const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= A) return;
-    const u64 k = keys[j];
-    const bool dup = (j > 0 && keys[j - 1] == k) || (j + 1 < A && keys[j + 1] == k);
-    const u32 p = vals[j];
-    const u32 i = act ? act[p] : p;
-    const u64 len = off[i + 1] - off[i];
-    const bool stay = dup && len > l;
-    if (!stay) dist[i] = (u32)(len < l ? len : l);
-    keep[p] = stay ? 1u : 0u;
-}
-
-// Ordered compaction of the active list by the keep flags (pos = exclusive scan).
-__global__ void k_compact(const u32 *act, u32 A, const u32 *keep, const u32 *pos, u32 *next)
-{
-    const u32 p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < A && keep[p]) next[pos[p]] = act ? act[p] : p;
-}
-
-__global__ void k_one_seg(Seg *act, u32 A) { act[0] = Seg{0, A, 0, 0}; }
-
-// flag = 1 if some key differs from keys[0] (then the keys must be sorted)
-__global__ void k_neq(const u64 *keys, u32 A, u32 *flag)
-{
-    const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < A && keys[j] != keys[0]) *flag = 1u;
+    bool stay = false;
+    u32 i = 0;
+    if (j < A) {
+        i = act ? act[j] : j;
+        const u64 len = off[i + 1] - off[i];
+        bool dup = mode == DM_ALLDUP;
+        if (mode == DM_TABLE) {
+            const u64 key = key_of(keys, kin, i, j);
+            const u32 mask = (1u << logT) - 1u;
+            u32 s = tab_slot(key, logT);
+            for (u32 probe = 0; probe <= mask; probe++, s = (s + 1) & mask) {
+                const u64 v = tab[s];
+                if ((v & ~TAB_DUP) == key) {
+                    dup = (v & TAB_DUP) != 0;
+                    break;
+                }
+            }
+        }
+        stay = dup && len > l;
+        if (!stay) dist[i] = (u32)(len < l ? len : l);
+    }
+    const u64 b = __ballot(stay);
+    const u32 lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) wcount[w] = (u32)__popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const u32 t = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+        base = t ? atomicAdd(ncnt, t) : 0u;
+    }
+    __syncthreads();
+    u32 woff = base;
+    for (u32 k = 0; k < w; k++) woff += wcount[k];
+    if (stay) next[woff + (u32)__popcll(b & lanemask_lt())] = i;
 }
 
 struct PdWs {
-    SortWs sw;
-    u32 *vals, *actA, *actB, *ctr, *keep, *kpos;
-    u64 *state, *pre, *scan_scratch;
+    u32 *actA, *actB, *ctr;
+    u64 *keys, *state, *pre, *tab;
 };
+
+static u32 tab_log(u64 A)
+{
+    u32 lg = 10;
+    while ((1ull << lg) < 2 * A) lg++;
+    return lg;
+}
 
 static void pd_layout(u64 n, PdWs *w, WsArena *a, WsCounter *c)
 {
-    sort_ws_layout(n, &w->sw, a, c);
 #define PT(field, T, cnt)                       \
     do {                                         \
         if (a) w->field = a->take<T>(cnt);       \
         else c->take<T>(cnt);                    \
     } while (0)
-    PT(vals, u32, n); PT(actA, u32, n); PT(actB, u32, n); PT(state, u64, n); PT(ctr, u32, 4);
-    PT(keep, u32, n); PT(kpos, u32, n + 1); PT(scan_scratch, u64, ss_scan_scratch_elems<u64>(n + 1));
-    PT(pre, u64, (u64)PRE_SLOTS * n);
+    PT(actA, u32, n); PT(actB, u32, n); PT(ctr, u32, 16); PT(keys, u64, n); PT(state, u64, n);
+    PT(pre, u64, (u64)PRE_SLOTS * n); PT(tab, u64, 1ull << tab_log(n));
 #undef PT
 }
 
@@ -256,73 +347,113 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
     BPow bp;
     bp.p[0] = 1;
     for (int t = 1; t <= 16; t++) bp.p[t] = (u64)(((unsigned __int128)bp.p[t - 1] * KR_B) % KR_P);
+    // counters: [0], [1] active-list lengths (current / next, swapped per
+    // round), [2], [3] the round's flags, [4..] flags of the first-pass rounds
+    u32 *ctr = w.ctr;
+    k_store_u32<<<1, 1, 0, st>>>(ctr, (u32)n);
+    SS_CHECK_LAUNCH();
     // rounds whose prefix length is at most PRE_MAX are hashed in one first pass
     PreLens P{};
     for (u64 L = init_len; L <= PRE_MAX && P.count < PRE_SLOTS; L *= 2) P.l[P.count++] = L;
+    u32 pf[2 * PRE_SLOTS] = {};
     if (P.count) {
-        // the first line of every string, once
-        SS_PROF("k_hash_first", st, (double)n * (double)P.l[P.count - 1] + (double)n * (24.0 + 8.0 * P.count));
-        k_hash_first<<<(unsigned)ceil_div(n, 32), 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits, bp, w.state,
-                                                                 w.pre);
+        {
+            // the first line of every string, once
+            SS_PROF("k_hash_first", st,
+                    (double)n * (double)P.l[P.count - 1] + (double)n * (24.0 + 8.0 * P.count));
+            k_hash_first<<<(unsigned)ceil_div(n, 32), 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits, bp,
+                                                                     w.state, w.pre);
+        }
+        SS_CHECK_LAUNCH();
+        SS_HIP(hipMemsetAsync(ctr + 4, 0, sizeof(u32) * 2 * P.count, st));
+        k_pre_flags<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(w.pre, (u32)n, offsets, P, ctr + 4);
+        SS_CHECK_LAUNCH();
+        SS_TRY(ss_read_u32(ctr + 4, pf, 2 * P.count, st));
     }
-    SS_CHECK_LAUNCH();
-    u32 A = (u32)n;
-    const u32 *act = nullptr;  // the active strings, in input order (NULL = all)
+    u32 Ah = (u32)n;           // active count (exact after each flag read)
+    const u32 *act = nullptr;  // the active strings (NULL = all, in input order)
     u32 *nxt = w.actA;
+    int ci = 0;                // which counter holds the current count
     u64 lprev = 0, l = init_len;
     u32 rounds = 0;
-    while (A > 0) {
-        if (++rounds > 64) { ss_set_error("prefix doubling did not terminate"); return SS_ERR_INVALID_ARG; }
-        if (rounds <= P.count) {
-            k_gather_keys<<<(unsigned)ceil_div(A, 256), 256, 0, st>>>(act, A, w.pre + (u64)(rounds - 1) * n,
-                                                                      w.sw.keyA, w.vals);
-            SS_CHECK_LAUNCH();
+    for (;;) {
+        const u64 *keys;
+        int kin;
+        if (rounds < P.count) {
+            keys = w.pre + (u64)rounds * n;
+            kin = 1;
         } else {
-            // new prefix bytes (exact for strings of length >= l), offsets, list entry,
-            // hash state in/out, key and payload out
-            SS_PROF("k_hash_round", st, (double)A * (double)(l - lprev) + (double)A * 48.0);
+            // bytes are charged once the active count is read back
+            SS_PROF("k_hash_round", st, 0.0);
             const u64 nb = l - lprev;
+            const u32 *cc = ctr + ci;
             if (nb <= 8)
-                k_hash_round<1><<<(unsigned)ceil_div(A, 256), 256, 0, st>>>(act, A, bytes, N, offsets, lprev, l,
-                                                                           hash_bits, w.state, w.sw.keyA, w.vals, bp);
+                k_hash_round<1><<<(unsigned)ceil_div(Ah, 256), 256, 0, st>>>(act, cc, bytes, N, offsets, lprev, l,
+                                                                            hash_bits, w.state, w.keys, bp);
             else if (nb <= 16)
-                k_hash_round<2><<<(unsigned)ceil_div(A, 128), 256, 0, st>>>(act, A, bytes, N, offsets, lprev, l,
-                                                                           hash_bits, w.state, w.sw.keyA, w.vals, bp);
+                k_hash_round<2><<<(unsigned)ceil_div(Ah, 128), 256, 0, st>>>(act, cc, bytes, N, offsets, lprev, l,
+                                                                            hash_bits, w.state, w.keys, bp);
             else if (nb <= 32)
-                k_hash_round<4><<<(unsigned)ceil_div(A, 64), 256, 0, st>>>(act, A, bytes, N, offsets, lprev, l,
-                                                                          hash_bits, w.state, w.sw.keyA, w.vals, bp);
+                k_hash_round<4><<<(unsigned)ceil_div(Ah, 64), 256, 0, st>>>(act, cc, bytes, N, offsets, lprev, l,
+                                                                           hash_bits, w.state, w.keys, bp);
             else
-                k_hash_round<8><<<(unsigned)ceil_div(A, 32), 256, 0, st>>>(act, A, bytes, N, offsets, lprev, l,
-                                                                          hash_bits, w.state, w.sw.keyA, w.vals, bp);
-        }
-        SS_CHECK_LAUNCH();
-        if (A >= 2) {
-            // all keys equal (e.g. a prefix shared by every string): every
-            // string is a duplicate and no sort is needed
-            SS_HIP(hipMemsetAsync(w.ctr + 1, 0, sizeof(u32), st));
-            k_neq<<<(unsigned)ceil_div(A, 256), 256, 0, st>>>(w.sw.keyA, A, w.ctr + 1);
+                k_hash_round<8><<<(unsigned)ceil_div(Ah, 32), 256, 0, st>>>(act, cc, bytes, N, offsets, lprev, l,
+                                                                           hash_bits, w.state, w.keys, bp);
             SS_CHECK_LAUNCH();
-            u32 differ;
-            SS_TRY(ss_read_u32(w.ctr + 1, &differ, 1, st));
-            if (differ) {
-                k_one_seg<<<1, 1, 0, st>>>(w.sw.act, A);
-                SS_CHECK_LAUNCH();
-                SortJob J{bytes, N, offsets, w.vals, nullptr, 1, st, A};
-                SS_TRY(sort_rounds(J, w.sw, 1, (u32)ceil_div(A, 2048)));
+            keys = w.keys;
+            kin = 0;
+        }
+        u32 differ, shrt;
+        if (!act && rounds < P.count) {
+            differ = pf[2 * rounds];
+            shrt = pf[2 * rounds + 1];
+        } else {
+            SS_HIP(hipMemsetAsync(ctr + 2, 0, 2 * sizeof(u32), st));
+            k_flags<<<(unsigned)ceil_div(Ah, 256), 256, 0, st>>>(keys, kin, act, ctr + ci, offsets, l, ctr + 2);
+            SS_CHECK_LAUNCH();
+            u32 h[4];
+            SS_TRY(ss_read_u32(ctr, h, 4, st));
+            Ah = h[ci];
+            differ = h[2];
+            shrt = h[3];
+            if (rounds >= P.count) {
+                // new prefix bytes (exact for strings of length >= l), offsets, list
+                // entry, hash state in/out, key out; a launch over an empty list is
+                // not counted
+                if (Ah == 0) ss_prof_drop_last("k_hash_round");
+                else ss_prof_add_bytes("k_hash_round", (double)Ah * (double)(l - lprev) + (double)Ah * 44.0);
             }
         }
+        if (Ah == 0) break;
+        if (++rounds > 64) { ss_set_error("prefix doubling did not terminate"); return SS_ERR_INVALID_ARG; }
+        if (Ah >= 2 && !differ && !shrt) {
+            // one key shared by all and no short string: nothing finishes
+            lprev = l;
+            l *= 2;
+            continue;
+        }
+        const int mode = Ah == 1 ? DM_UNIQUE : (differ ? DM_TABLE : DM_ALLDUP);
+        u32 logT = 0;
+        if (mode == DM_TABLE) {
+            logT = tab_log(Ah);
+            SS_HIP(hipMemsetAsync(w.tab, 0xFF, sizeof(u64) << logT, st));
+            {
+                SS_PROF("k_tab_insert", st, (double)Ah * 28.0);  // list entry, key, slot read + write
+                k_tab_insert<<<(unsigned)ceil_div(Ah, 256), 256, 0, st>>>(keys, kin, act, ctr + ci, w.tab, logT);
+            }
+            SS_CHECK_LAUNCH();
+        }
+        SS_HIP(hipMemsetAsync(ctr + (ci ^ 1), 0, sizeof(u32), st));
         {
-            SS_PROF("k_dedup", st, (double)A * 40.0);  // key, payload, list entry, offsets, one write
-            k_dedup<<<(unsigned)ceil_div(A, 256), 256, 0, st>>>(w.sw.keyA, w.vals, A, act, offsets, l, dist_approx,
-                                                                w.keep);
+            // list entry, offsets, key, slot, dist or next entry
+            SS_PROF("k_dedup", st, (double)Ah * (mode == DM_TABLE ? 40.0 : 24.0));
+            k_dedup<<<(unsigned)ceil_div(Ah, 256), 256, 0, st>>>(keys, kin, act, ctr + ci, offsets, l, mode, w.tab,
+                                                                 logT, dist_approx, nxt, ctr + (ci ^ 1));
         }
         SS_CHECK_LAUNCH();
-        SS_TRY(ss_scan_exclusive<u32>(w.keep, w.kpos, A, (u32 *)w.scan_scratch, st));
-        k_compact<<<(unsigned)ceil_div(A, 256), 256, 0, st>>>(act, A, w.keep, w.kpos, nxt);
-        SS_CHECK_LAUNCH();
-        SS_TRY(ss_read_u32(w.kpos + A, &A, 1, st));
         act = nxt;
         nxt = (nxt == w.actA) ? w.actB : w.actA;
+        ci ^= 1;
         lprev = l;
         l *= 2;
     }

@@ -5,9 +5,11 @@
 // followed by its literal.  Its bytes [e_i, d_i) are its own literal; bytes
 // [e_j, e_i) with j = psv(i) = the nearest earlier position with e_j < e_i are
 // string j's literal, and so on down the psv chain to an e = 0 position (every
-// run starts with e = 0).  psv is found first inside 256-element blocks (LDS),
-// then by skipping blocks and 65536-element superblocks whose minimum is not
-// smaller.  Each output 16-byte word then walks the chain of its string.
+// run starts with e = 0).  psv is found by a min-tree search: inside each
+// 1024-element block on a tree in LDS, else on a binary tree of the block
+// minima (climb to the nearest left subtree holding a smaller value, descend to
+// its rightmost such block, then its rightmost such 16-element chunk).  Each output 16-byte word then walks
+// the chain of its string.
 //
 // Merge.  The paper merges r runs with an LCP loser tree.  Here the runs are
 // merged pairwise in log2 k levels; each level is split into fixed-size output
@@ -22,8 +24,7 @@
 
 #include "common.hpp"
 
-#define DB 256      // psv block
-#define DSB 65536   // psv superblock
+#define PSV_NONE 0xFFFFFFFFu
 
 // ---------------------------------------------------------------- decode
 
@@ -43,71 +44,168 @@ __global__ __launch_bounds__(256) void k_check_runs(const u64 *run_off, u32 k, c
     }
 }
 
-__global__ __launch_bounds__(DB) void k_psv_block(const u32 *e, u32 n, u32 *psv, u32 *bmin)
+#define PB 1024  // psv block (one workgroup)
+#define PC 16    // chunk whose minimum is kept for the far search
+#define PCB (PB / PC)
+
+// psv inside each block of PB entries (PSV_NONE if the answer lies before the
+// block).  The block minimum goes to leaf P + block of the tree T, the minima
+// of its PC-entry chunks to cm[block * PCB ..].
+__global__ __launch_bounds__(PB) void k_psv_block(const u32 *e, u32 n, u32 *psv, u32 *T, u32 P, u32 *cm)
 {
-    __shared__ u32 se[DB];
-    const u32 b0 = blockIdx.x * DB;
+    __shared__ u32 t[2 * PB];  // heap: node x has children 2x, 2x+1; leaves PB..2PB-1
+    const u32 b0 = blockIdx.x * PB;
     const u32 i = b0 + threadIdx.x;
     const u32 v = i < n ? e[i] : 0xFFFFFFFFu;
-    se[threadIdx.x] = v;
+    t[PB + threadIdx.x] = v;
     __syncthreads();
+    for (u32 c = PB / 2; c >= 1; c >>= 1) {
+        if (threadIdx.x < c) {
+            const u32 x = c + threadIdx.x;
+            const u32 a = t[2 * x], b = t[2 * x + 1];
+            t[x] = a < b ? a : b;
+        }
+        __syncthreads();
+    }
     if (i < n) {
-        u32 res = 0xFFFFFFFFu;  // not found in block
+        u32 res = PSV_NONE;
         if (v > 0) {
-            for (int j = (int)threadIdx.x - 1; j >= 0; j--) {
-                if (se[j] < v) { res = b0 + (u32)j; break; }
+            u32 x = PB + threadIdx.x;
+            bool found = false;
+            while (x > 1) {
+                if ((x & 1) && t[x - 1] < v) {
+                    x = x - 1;
+                    found = true;
+                    break;
+                }
+                x >>= 1;
+            }
+            if (found) {
+                while (x < PB) {
+                    x = 2 * x + 1;
+                    if (t[x] >= v) x--;
+                }
+                res = b0 + (x - PB);
             }
         }
         psv[i] = res;
     }
-    // block minimum
-    u32 m = v;
-    for (int o = 32; o > 0; o >>= 1) { u32 y = __shfl_xor(m, o, 64); m = y < m ? y : m; }
-    __shared__ u32 wm[DB / 64];
-    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    if (threadIdx.x == 0) T[P + blockIdx.x] = t[1];
+    if (threadIdx.x < PCB) cm[(u64)blockIdx.x * PCB + threadIdx.x] = t[PCB + threadIdx.x];
+}
+
+// Internal nodes of the tree T: each workgroup takes up to 512 nodes of one
+// level (m nodes, indices m..2m-1) and writes `lv` levels above them.
+__global__ __launch_bounds__(256) void k_tree_up(u32 *T, u32 m, u32 lv)
+{
+    __shared__ u32 s[512];
+    const u32 cnt = m < 512 ? m : 512;
+    const u32 base = m + blockIdx.x * cnt;
+    for (u32 q = threadIdx.x; q < cnt; q += 256) s[q] = T[base + q];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        u32 r = wm[0];
-        for (int w = 1; w < DB / 64; w++) r = wm[w] < r ? wm[w] : r;
-        bmin[blockIdx.x] = r;
+    u32 c = cnt, b = base;
+    for (u32 L = 0; L < lv; L++) {
+        c >>= 1;
+        b >>= 1;
+        u32 v = 0;
+        if (threadIdx.x < c) {
+            const u32 x = s[2 * threadIdx.x], y = s[2 * threadIdx.x + 1];
+            v = x < y ? x : y;
+        }
+        __syncthreads();
+        if (threadIdx.x < c) {
+            s[threadIdx.x] = v;
+            T[b + threadIdx.x] = v;
+        }
+        __syncthreads();
     }
 }
 
-__global__ void k_min_reduce(const u32 *in, u32 nin, u32 group, u32 *out)
-{
-    const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-    const u32 a = j * group;
-    if (a >= nin) return;
-    u32 m = 0xFFFFFFFFu;
-    for (u32 t = a; t < a + group && t < nin; t++) m = in[t] < m ? in[t] : m;
-    out[j] = m;
-}
-
-// psv for positions whose answer lies before their block.
-__global__ __launch_bounds__(256) void k_psv_far(const u32 *e, u32 n, const u32 *bmin, const u32 *smin,
-                                                 u32 *psv)
+// psv for positions whose answer lies before their block: nearest left
+// subtree of T with a smaller minimum, its rightmost such block, that block's
+// rightmost such chunk, that chunk's rightmost such entry.
+__global__ __launch_bounds__(256) void k_psv_far(const u32 *e, u32 n, const u32 *T, u32 P, const u32 *cm, u32 *psv)
 {
     const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const u32 v = e[i];
-    if (v == 0 || psv[i] != 0xFFFFFFFFu) return;
-    const u32 blk = i / DB;
-    const u32 per = DSB / DB;
-    int b = (int)blk - 1;
-    // blocks of the own superblock
-    const int sb_first = (int)(blk / per) * (int)per;
-    while (b >= sb_first && bmin[b] >= v) b--;
-    if (b < sb_first) {
-        int s = (int)(blk / per) - 1;
-        while (s >= 0 && smin[s] >= v) s--;
-        if (s < 0) { psv[i] = 0xFFFFFFFFu; return; }  // malformed input (no e = 0 before)
-        b = s * (int)per + (int)per - 1;
-        while (bmin[b] >= v) b--;
+    if (v == 0 || psv[i] != PSV_NONE) return;
+    u32 x = P + i / PB;
+    bool found = false;
+    while (x > 1) {
+        if ((x & 1) && T[x - 1] < v) {
+            x = x - 1;
+            found = true;
+            break;
+        }
+        x >>= 1;
     }
-    int j = b * DB + DB - 1;
-    if (j > (int)n - 1) j = (int)n - 1;
-    while (e[j] >= v) j--;
-    psv[i] = (u32)j;
+    if (!found) return;  // malformed input (no e = 0 before): stays PSV_NONE
+    while (x < P) {
+        x = 2 * x + 1;
+        if (T[x] >= v) x--;
+    }
+    const u32 blk = x - P;
+    const uint4 *c4 = (const uint4 *)(cm + (u64)blk * PCB);  // 256-byte aligned workspace
+    uint4 w[PCB / 4];
+#pragma unroll
+    for (int q = 0; q < PCB / 4; q++) w[q] = c4[q];
+    int c = -1;
+#pragma unroll
+    for (int q = 0; q < PCB / 4; q++) {
+        if (w[q].x < v) c = 4 * q;
+        if (w[q].y < v) c = 4 * q + 1;
+        if (w[q].z < v) c = 4 * q + 2;
+        if (w[q].w < v) c = 4 * q + 3;
+    }
+    // the block minimum is < v, so some chunk qualifies (c >= 0), and that
+    // chunk's entries all lie below n (padding entries are all-ones)
+    const u32 lo = blk * PB + (u32)c * PC;
+    u32 ev[PC];
+#pragma unroll
+    for (int q = 0; q < PC; q++) ev[q] = (lo + q < n) ? e[lo + q] : 0xFFFFFFFFu;
+    u32 r = lo;
+#pragma unroll
+    for (int q = 0; q < PC; q++)
+        if (ev[q] < v) r = lo + (u32)q;
+    psv[i] = r;
+}
+
+// Tree size (leaves) for n entries.
+static u32 psv_leaves(u64 n)
+{
+    const u64 nb = ceil_div(n, PB);
+    u32 P = 1;
+    while (P < nb) P <<= 1;
+    return P;
+}
+
+// psv of every entry of e[0..n) (n >= 1).  T holds 2 * psv_leaves(n) words,
+// cm psv_leaves(n) * PCB words (256-byte aligned).
+static int psv_build(const u32 *e, u64 n, u32 *psv, u32 *T, u32 *cm, hipStream_t st)
+{
+    const u32 nb = (u32)ceil_div(n, PB);
+    const u32 P = psv_leaves(n);
+    if (P > nb) SS_HIP(hipMemsetAsync(T + P + nb, 0xFF, sizeof(u32) * (P - nb), st));
+    {
+        SS_PROF("k_psv_block", st, (double)n * 8.0);  // e in, psv out
+        k_psv_block<<<nb, PB, 0, st>>>(e, (u32)n, psv, T, P, cm);
+    }
+    SS_CHECK_LAUNCH();
+    for (u32 m = P; m > 1;) {
+        u32 lv = 0;
+        while (lv < 9 && (m >> lv) > 1) lv++;
+        const u32 blocks = m > 512 ? m / 512 : 1;
+        k_tree_up<<<blocks, 256, 0, st>>>(T, m, lv);
+        SS_CHECK_LAUNCH();
+        m >>= lv;
+    }
+    {
+        SS_PROF("k_psv_far", st, (double)n * 8.0);  // e and psv in (far entries: a few more words)
+        k_psv_far<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(e, (u32)n, T, P, cm, psv);
+    }
+    SS_CHECK_LAUNCH();
+    return SS_OK;
 }
 
 #define DC_NT 256
@@ -186,23 +284,23 @@ __global__ void k_widen(const u32 *d, u32 n, u64 *out)
 }
 
 struct DecWs {
-    u32 *psv, *bmin, *smin, *bad;
+    u32 *psv, *tree, *cmin, *bad;
     u64 *scratch;
 };
 
 static void dec_layout(u64 n, DecWs *w, WsArena *a, WsCounter *c)
 {
-    const u64 nb = n / DB + 2, ns = n / DSB + 2;
+    const u64 nt = 2 * (u64)psv_leaves(n);
     if (a) {
         w->psv = a->take<u32>(n + 1);
-        w->bmin = a->take<u32>(nb);
-        w->smin = a->take<u32>(ns);
+        w->tree = a->take<u32>(nt);
+        w->cmin = a->take<u32>(nt / 2 * PCB);
         w->bad = a->take<u32>(4);
         w->scratch = a->take<u64>(ss_scan_scratch_elems<u64>(n + 1));
     } else {
         c->take<u32>(n + 1);
-        c->take<u32>(nb);
-        c->take<u32>(ns);
+        c->take<u32>(nt);
+        c->take<u32>(nt / 2 * PCB);
         c->take<u32>(4);
         c->take<u64>(ss_scan_scratch_elems<u64>(n + 1));
     }
@@ -235,15 +333,7 @@ static int decode_impl(u32 k, const u64 *run_off, const u32 *e, const u32 *d, co
         return SS_ERR_CAPACITY;
     }
     if (n == 0 || total == 0) return SS_OK;
-    const u32 nb = (u32)ceil_div(n, DB);
-    k_psv_block<<<nb, DB, 0, st>>>(e, (u32)n, w.psv, w.bmin);
-    SS_CHECK_LAUNCH();
-    const u32 per = DSB / DB;
-    const u32 ns = (u32)ceil_div(nb, per);
-    k_min_reduce<<<(unsigned)ceil_div(ns, 256), 256, 0, st>>>(w.bmin, nb, per, w.smin);
-    SS_CHECK_LAUNCH();
-    k_psv_far<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(e, (u32)n, w.bmin, w.smin, w.psv);
-    SS_CHECK_LAUNCH();
+    SS_TRY(psv_build(e, n, w.psv, w.tree, w.cmin, st));
     k_decode<<<(unsigned)ceil_div(total, DC_NT * DC_PER), DC_NT, 0, st>>>(e, d, suf_off, suf, w.psv, (u32)n, out_off,
                                                                        total, out);
     SS_CHECK_LAUNCH();
@@ -795,15 +885,7 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
         return SS_ERR_INVALID_ARG;
     }
     // psv chains over the whole front-coded array (no decoding of the strings)
-    const u32 nb = (u32)ceil_div(n_fc, DB);
-    k_psv_block<<<nb, DB, 0, st>>>(fc_lcp, (u32)n_fc, w.dec.psv, w.dec.bmin);
-    SS_CHECK_LAUNCH();
-    const u32 per = DSB / DB;
-    const u32 nsb = (u32)ceil_div(nb, per);
-    k_min_reduce<<<(unsigned)ceil_div(nsb, 256), 256, 0, st>>>(w.dec.bmin, nb, per, w.dec.smin);
-    SS_CHECK_LAUNCH();
-    k_psv_far<<<(unsigned)ceil_div(n_fc, 256), 256, 0, st>>>(fc_lcp, (u32)n_fc, w.dec.bmin, w.dec.smin, w.dec.psv);
-    SS_CHECK_LAUNCH();
+    SS_TRY(psv_build(fc_lcp, n_fc, w.dec.psv, w.dec.tree, w.dec.cmin, st));
     k_merge_init<<<(unsigned)ceil_div(n_out, 256), 256, 0, st>>>(run_begin, w.P, k, (u32)n_out, fc_lcp, w.dec.psv,
                                                                  w.G0, w.L0, w.F0);
     SS_CHECK_LAUNCH();

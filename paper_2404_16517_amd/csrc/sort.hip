@@ -138,49 +138,98 @@ __global__ void k_sizes(const Seg *segs, u32 nseg, u32 *out)
 
 // ------------------------------------------------------------ round kernels
 
-#define SKG 16  // lanes per string in the skip kernel: 128 consecutive bytes per step
+#define SKG 8     // lanes per string in the skip kernel: 64 consecutive bytes per step
+#define SKU 2     // strings per lane group in flight
+#define SKFS 256  // words (8 bytes) of the segment's first string staged in LDS
 
 // Minimum LCP of every member with the segment's first string, from `depth`.
-// A group of 16 lanes compares 128 consecutive bytes of one member with the
-// first string per step (coalesced reads of both).
+// A group of 8 lanes compares 64 consecutive bytes of each of two members per
+// step; the first string's bytes [depth, depth + 2048) come from LDS.
 __global__ __launch_bounds__(NT) void k_skip(const Seg *segs, const u32 *tstart, u32 nseg,
                                              const u8 *bytes, u64 N, const u64 *off,
                                              const u32 *perm, u32 *skipv)
 {
+    __shared__ u64 fsw[SKFS];
     const u32 t = blockIdx.x;
     const u32 s = seg_of_tile(tstart, nseg, t);
     const Seg g = segs[s];
-    if (!(g.aux & SEG_SKIP)) return;
+    if (!(g.aux & SEG_SKIP)) return;  // uniform over the workgroup
     const u32 lt = t - tstart[s];
     const u32 b0 = g.begin + lt * ETILE;
     const u32 b1 = min(g.end, b0 + ETILE);
     const u32 f = perm[g.begin];
     const u64 fo = off[f], fl = off[f + 1] - fo;
+    const u64 fd = fl > g.depth ? fl - g.depth : 0;  // first-string bytes from depth
+    for (u32 q = threadIdx.x; q < SKFS; q += NT) {
+        const u64 k = 8ull * q;
+        fsw[q] = k < fd ? load_be(bytes, N, fo + g.depth + k, (u32)((fd - k) < 8 ? (fd - k) : 8)) : 0ull;
+    }
+    __syncthreads();
     const u32 grp = threadIdx.x / SKG, lane = threadIdx.x % SKG;
     u64 best = ~0ull;
-    for (u32 i = b0 + grp; i < b1; i += NT / SKG) {
-        const u32 p = perm[i];
-        const u64 o = off[p], l = off[p + 1] - o;
-        const u64 m = l < fl ? l : fl;
-        u64 res = m;
-        for (u64 x = g.depth; x < m; x += 8 * SKG) {
-            const u64 q = x + 8 * lane;
-            const u32 take = q < m ? (u32)((m - q) < 8 ? (m - q) : 8) : 0u;
-            const u64 wa = load_be(bytes, N, o + q, take);
-            const u64 wb = load_be(bytes, N, fo + q, take);
-            u64 pos = (wa != wb) ? q + (__clzll(wa ^ wb) >> 3) : ~0ull;
+    for (u32 i = b0 + grp * SKU; i < b1; i += (NT / SKG) * SKU) {
+        u64 o[SKU], m[SKU], x[SKU], res[SKU];
+        bool act[SKU];
 #pragma unroll
-            for (int s2 = SKG / 2; s2 > 0; s2 >>= 1) {
-                const u64 y = __shfl_xor(pos, s2, SKG);
-                pos = y < pos ? y : pos;
-            }
-            if (pos != ~0ull) {
-                res = pos;
-                break;
+        for (int u = 0; u < SKU; u++) {
+            act[u] = false;
+            res[u] = ~0ull;
+            o[u] = 0;
+            m[u] = 0;
+            x[u] = g.depth;
+            if (i + u < b1) {
+                const u32 p = perm[i + u];
+                o[u] = off[p];
+                const u64 l = off[p + 1] - o[u];
+                m[u] = l < fl ? l : fl;
+                res[u] = m[u];
+                act[u] = x[u] < m[u];
             }
         }
-        const u64 c = res - g.depth;
-        best = c < best ? c : best;
+        bool any = false;
+#pragma unroll
+        for (int u = 0; u < SKU; u++) any |= act[u];
+        while (any) {  // uniform over the lane group
+            u64 pos[SKU];
+#pragma unroll
+            for (int u = 0; u < SKU; u++) {
+                pos[u] = ~0ull;
+                if (!act[u]) continue;
+                const u64 q = x[u] + 8 * lane;
+                if (q >= m[u]) continue;
+                const u32 take = (m[u] - q) < 8 ? (u32)(m[u] - q) : 8u;
+                const u64 wa = load_be(bytes, N, o[u] + q, take);
+                const u64 k = q - g.depth;  // multiple of 8
+                u64 wb = k < 8ull * SKFS ? fsw[k >> 3] : load_be(bytes, N, fo + q, take);
+                if (take < 8) wb &= ~0ull << (64 - 8 * take);
+                if (wa != wb) pos[u] = q + (__clzll(wa ^ wb) >> 3);
+            }
+            any = false;
+#pragma unroll
+            for (int u = 0; u < SKU; u++) {
+#pragma unroll
+                for (int s2 = SKG / 2; s2 > 0; s2 >>= 1) {
+                    const u64 y = __shfl_xor(pos[u], s2, SKG);
+                    pos[u] = y < pos[u] ? y : pos[u];
+                }
+                if (act[u]) {
+                    if (pos[u] != ~0ull) {
+                        res[u] = pos[u];
+                        act[u] = false;
+                    } else {
+                        x[u] += 8 * SKG;
+                        act[u] = x[u] < m[u];
+                    }
+                }
+                any |= act[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SKU; u++)
+            if (i + u < b1) {
+                const u64 c = res[u] > g.depth ? res[u] - g.depth : 0ull;
+                best = c < best ? c : best;
+            }
     }
     const u32 b32 = best > 0xFFFFFFFFull ? 0xFFFFFFFFu : (u32)best;
     const u32 bm = block_min(b32);
@@ -288,107 +337,104 @@ struct EmitOut {
     int plain;
 };
 
-__device__ __forceinline__ void push_next(Seg *next, u32 *ctr, Seg g)
-{
-    const u32 a = atomicAdd(&ctr[C_NEXT], 1u);
-    next[a] = g;
-    atomicAdd(&ctr[C_NTILES], (g.end - g.begin + ETILE - 1) / ETILE);
-    atomicAdd(&ctr[C_NELEM], g.end - g.begin);
-}
+enum { K_NONE = 0, K_SMALL, K_LARGE, K_NEXT, K_IDENT };
 
-__device__ __forceinline__ void push_small(const EmitOut &o, Seg g)
-{
-    const u32 a = atomicAdd(&o.ctr[C_SMALL], 1u);
-    o.small[a] = g;
-    atomicAdd(&o.ctr[C_SMALLN], g.end - g.begin);
-}
+// What digit d of radix segment s becomes: an entry for one of the lists
+// (kind, seg) and/or a bucket boundary (sb, depth) for the LCP pass.
+struct EmitItem {
+    u32 kind;
+    Seg ns;
+    bool bnd;
+    uint2 bv;
+};
 
-__device__ __forceinline__ void push_large(const EmitOut &o, Seg g)
+__device__ __forceinline__ EmitItem emit_item(const Seg *segs, const u32 *tstart, const u32 *hist, const u64 *smin,
+                                              const u64 *smax, const EmitOut &o, u32 s, u32 d, bool *scat)
 {
-    const u32 a = atomicAdd(&o.ctr[C_LARGE], 1u);
-    o.large_next[a] = g;
-    atomicAdd(&o.ctr[C_LTILES], (g.end - g.begin + o.tile - 1) / o.tile);
-    atomicAdd(&o.ctr[C_LELEM], g.end - g.begin);
-}
-
-// A run of strings with equal keys (all 8 key bytes): continue next round, or
-// equal strings.
-__device__ __forceinline__ void emit_exhausted(const EmitOut &o, u32 b, u32 e, u32 depth, u32 cnt)
-{
-    if (o.plain) return;
-    if (cnt == 8) {
-        push_next(o.next, o.ctr, Seg{b, e, depth + 7, SEG_SKIP});
-    } else {
-        u32 a = atomicAdd(&o.ctr[C_IDENT], 1u);
-        o.ident[a] = Seg{b, e, depth + cnt, 0};
-        atomicAdd(&o.ctr[C_ITILES], (e - b + ETILE - 1) / ETILE);
-    }
-}
-
-// One workgroup per radix segment: digit counts from the scanned histogram,
-// emission of the sub-segments.
-__global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart, u32 nseg,
-                                              const u32 *hist, const u64 *smin, const u64 *smax,
-                                              EmitOut o)
-{
-    const u32 s = blockIdx.x;
-    const u32 d = threadIdx.x;
+    EmitItem it{K_NONE, Seg{0, 0, 0, 0}, false, make_uint2(0, 0)};
     const Seg g = segs[s];
-    const u32 ts = tstart[s];
-    const u32 T = tstart[s + 1] - ts;
     const u32 level = g.aux & 15;
     const u64 mn = smin[s], mx = smax[s];
     if (mn == mx) {
-        if (d == 0) {
-            o.scat[s] = 0;
-            emit_exhausted(o, g.begin, g.end, g.depth, (u32)(mn & 0xFF));
+        // one key for the whole segment (all 8 bytes): continue next round,
+        // or equal strings
+        *scat = false;
+        const u32 cnt = (u32)(mn & 0xFF);
+        if (d == 0 && !o.plain) {
+            if (cnt == 8) { it.kind = K_NEXT; it.ns = Seg{g.begin, g.end, g.depth + 7, SEG_SKIP}; }
+            else { it.kind = K_IDENT; it.ns = Seg{g.begin, g.end, g.depth + cnt, 0}; }
         }
-        return;
+        return it;
     }
     const u32 fb = __clzll(mn ^ mx) >> 3;  // first byte where the keys differ
     if (fb > level) {
         // bytes level..fb-1 are common to the whole segment: no scatter needed
-        if (d == 0) {
-            o.scat[s] = 0;
-            push_large(o, Seg{g.begin, g.end, g.depth, fb});
-        }
-        return;
+        *scat = false;
+        if (d == 0) { it.kind = K_LARGE; it.ns = Seg{g.begin, g.end, g.depth, fb}; }
+        return it;
     }
-    if (d == 0) o.scat[s] = 1;
-    // this digit's bucket, and what it becomes; appends are aggregated per
-    // workgroup (one global atomic per counter)
-    enum { K_NONE = 0, K_SMALL, K_LARGE, K_NEXT, K_IDENT };
-    __shared__ u32 lcount[5], lsum[6], gbase[5];
-    if (d < 5) lcount[d] = 0;
-    if (d < 6) lsum[d] = 0;
-    __syncthreads();
+    *scat = true;
+    const u32 ts = tstart[s];
+    const u32 T = tstart[s + 1] - ts;
     const u32 e = 256u * ts + d * T;
     const u32 base = hist[256u * ts];
     const u32 start = hist[e] - base;
     const u32 cnt = hist[e + T] - hist[e];
     const u32 sb = g.begin + start, se = sb + cnt;
-    const bool has_bnd = cnt > 0 && start > 0 && !o.plain;
-    u32 kind = K_NONE;
-    Seg ns = {sb, se, g.depth, 0};
+    it.bnd = cnt > 0 && start > 0 && !o.plain;
+    it.bv = make_uint2(sb, g.depth);
+    it.ns = Seg{sb, se, g.depth, 0};
     if (cnt >= 2) {
         if (level == 7) {
             if (!o.plain) {
-                if (d == 8) { kind = K_NEXT; ns = Seg{sb, se, g.depth + 7, SEG_SKIP}; }
-                else { kind = K_IDENT; ns = Seg{sb, se, g.depth + d, 0}; }
+                if (d == 8) { it.kind = K_NEXT; it.ns = Seg{sb, se, g.depth + 7, SEG_SKIP}; }
+                else { it.kind = K_IDENT; it.ns = Seg{sb, se, g.depth + d, 0}; }
             }
         } else if (cnt <= o.small_max) {
-            kind = K_SMALL;
+            it.kind = K_SMALL;
         } else {
-            kind = K_LARGE;
-            ns.aux = level + 1;
+            it.kind = K_LARGE;
+            it.ns.aux = level + 1;
         }
     }
-    const u32 bslot = has_bnd ? atomicAdd(&lcount[0], 1u) : 0u;
-    const u32 slot = kind ? atomicAdd(&lcount[kind], 1u) : 0u;
-    if (kind == K_SMALL) atomicAdd(&lsum[0], cnt);
-    if (kind == K_LARGE) { atomicAdd(&lsum[1], (cnt + o.tile - 1) / o.tile); atomicAdd(&lsum[2], cnt); }
-    if (kind == K_NEXT) { atomicAdd(&lsum[3], (cnt + ETILE - 1) / ETILE); atomicAdd(&lsum[4], cnt); }
-    if (kind == K_IDENT) atomicAdd(&lsum[5], (cnt + ETILE - 1) / ETILE);
+    return it;
+}
+
+#define EPB 8  // radix segments per workgroup in k_emit
+
+// Digit counts from the scanned histogram and emission of the sub-segments.
+// A workgroup takes EPB segments (thread d = digit d): it counts its entries in
+// LDS, reserves room in every list with one global atomic per list, and then
+// writes the entries.
+__global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart, u32 nseg,
+                                              const u32 *hist, const u64 *smin, const u64 *smax,
+                                              EmitOut o)
+{
+    __shared__ u32 lcount[5], lslot[5], lsum[6], gbase[5];
+    const u32 d = threadIdx.x;
+    if (d < 5) { lcount[d] = 0; lslot[d] = 0; }
+    if (d < 6) lsum[d] = 0;
+    __syncthreads();
+    const u32 s0 = blockIdx.x * EPB;
+    EmitItem it[EPB];
+#pragma unroll
+    for (u32 q = 0; q < EPB; q++) {
+        const u32 s = s0 + q;
+        it[q].kind = K_NONE;
+        it[q].bnd = false;
+        if (s >= nseg) continue;
+        bool sc = false;
+        it[q] = emit_item(segs, tstart, hist, smin, smax, o, s, d, &sc);
+        if (d == 0) o.scat[s] = sc ? 1 : 0;
+        const EmitItem &x = it[q];
+        const u32 cnt = x.ns.end - x.ns.begin;
+        if (x.bnd) atomicAdd(&lcount[0], 1u);
+        if (x.kind) atomicAdd(&lcount[x.kind], 1u);
+        if (x.kind == K_SMALL) atomicAdd(&lsum[0], cnt);
+        if (x.kind == K_LARGE) { atomicAdd(&lsum[1], (cnt + o.tile - 1) / o.tile); atomicAdd(&lsum[2], cnt); }
+        if (x.kind == K_NEXT) { atomicAdd(&lsum[3], (cnt + ETILE - 1) / ETILE); atomicAdd(&lsum[4], cnt); }
+        if (x.kind == K_IDENT) atomicAdd(&lsum[5], (cnt + ETILE - 1) / ETILE);
+    }
     __syncthreads();
     if (d == 0) {
         gbase[0] = lcount[0] ? atomicAdd(&o.ctr[C_BND], lcount[0]) : 0u;
@@ -404,11 +450,17 @@ __global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart
         if (lsum[5]) atomicAdd(&o.ctr[C_ITILES], lsum[5]);
     }
     __syncthreads();
-    if (has_bnd) o.bnd[gbase[0] + bslot] = make_uint2(sb, g.depth);
-    if (kind == K_SMALL) o.small[gbase[K_SMALL] + slot] = ns;
-    if (kind == K_LARGE) o.large_next[gbase[K_LARGE] + slot] = ns;
-    if (kind == K_NEXT) o.next[gbase[K_NEXT] + slot] = ns;
-    if (kind == K_IDENT) o.ident[gbase[K_IDENT] + slot] = ns;
+#pragma unroll
+    for (u32 q = 0; q < EPB; q++) {
+        const EmitItem &x = it[q];
+        if (x.bnd) o.bnd[gbase[0] + atomicAdd(&lslot[0], 1u)] = x.bv;
+        if (x.kind) {
+            const u32 a = gbase[x.kind] + atomicAdd(&lslot[x.kind], 1u);
+            Seg *dst = x.kind == K_SMALL ? o.small : x.kind == K_LARGE ? o.large_next
+                     : x.kind == K_NEXT ? o.next : o.ident;
+            dst[a] = x.ns;
+        }
+    }
 }
 
 // Stable scatter of (key, payload) by the current byte into the B arrays.
@@ -727,7 +779,8 @@ int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
             SS_HIP(hipMemsetAsync(w.ctr + C_LTILES, 0, sizeof(u32), st));
             SS_HIP(hipMemsetAsync(w.ctr + C_LELEM, 0, sizeof(u32), st));
             EmitOut eo{w.small, LB, w.nxt, w.ident, w.bnd, w.ctr, w.scat, SM, TL, J.plain};
-            k_emit<<<nlarge, 256, 0, st>>>(LA, w.tstart, nlarge, w.hist, w.smin, w.smax, eo);
+            k_emit<<<(unsigned)ceil_div(nlarge, EPB), 256, 0, st>>>(LA, w.tstart, nlarge, w.hist, w.smin, w.smax,
+                                                                     eo);
             SS_CHECK_LAUNCH();
             {
                 SS_PROF("k_scatter", st, (double)lelem * 24.0);  // key+payload in and out

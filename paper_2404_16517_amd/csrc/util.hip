@@ -244,6 +244,19 @@ void ss_prof_add_bytes(const char *name, double bytes)
         }
 }
 
+void ss_prof_drop_last(const char *name)
+{
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (size_t i = g_prof.size(); i-- > 0;)
+        if (g_prof[i].name == name) {
+            hipEventDestroy(g_prof[i].a);
+            hipEventDestroy(g_prof[i].b);
+            g_prof.erase(g_prof.begin() + (long)i);
+            return;
+        }
+}
+
 extern "C" void ss_profile_enable(int on)
 {
     std::lock_guard<std::mutex> lk(g_prof_mu);

@@ -231,6 +231,43 @@ def test_partition_encode_matches_oracle(pdms, r):
     assert bytes(db.cpu().numpy()) == bytes(rb)
 
 
+def _fc_patterns(n, runs, seed):
+    """Valid front-coded arrays (e_0 = 0 per run, e_i <= d_i, e_i <= d_(i-1)) whose
+    LCP sequence has far previous-smaller values: long plateaus broken by rare
+    dips, staircases, sawtooths and random stretches."""
+    rng = np.random.default_rng(seed)
+    d = rng.integers(20, 90, size=n).astype(np.int64)
+    e = np.empty(n, np.int64)
+    q = n // 4
+    e[:q] = 18
+    if q:
+        e[:q][rng.integers(0, q, size=3)] = 1                 # plateau, dips ~100k apart
+    e[q:2 * q] = np.arange(q) % 85                             # staircase
+    e[2 * q:3 * q] = 80 - (np.arange(q) % 79)                  # sawtooth down
+    e[3 * q:] = rng.integers(0, 60, size=n - 3 * q)            # random
+    prev = np.concatenate([[0], d[:-1]])
+    e = np.minimum(np.minimum(e, d), prev)
+    run_off = np.linspace(0, n, runs + 1).astype(np.uint64)
+    e[run_off[:-1].astype(np.int64)] = 0
+    lit = d - e
+    suf_off = np.concatenate([[0], np.cumsum(lit)]).astype(np.uint64)
+    suf = rng.integers(65, 91, size=int(suf_off[-1])).astype(np.uint8)
+    return run_off, e.astype(np.uint32), d.astype(np.uint32), suf_off, suf
+
+
+@pytest.mark.parametrize("n,runs", [(1, 1), (255, 1), (257, 2), (400_000, 3)])
+def test_fc_decode_far_previous_smaller(n, runs):
+    run_off, e, d, suf_off, suf = _fc_patterns(n, runs, seed=n)
+    _log(f"[decode] n={n} runs={runs}")
+    T = lambda a, dt: torch.from_numpy(a.view(dt).copy()).to(DEV)
+    db, doff = ss.fc_decode(T(run_off, np.int64), T(e, np.int32), T(d, np.int32), T(suf_off, np.int64),
+                            torch.from_numpy(suf.copy()).to(DEV))
+    torch.cuda.synchronize()
+    rb, roff = oracle.fc_decode(run_off, e, d, suf_off, suf)
+    np.testing.assert_array_equal(u64(doff), roff)
+    assert bytes(db.cpu().numpy()) == bytes(rb)
+
+
 def test_bucket_bounds_with_external_splitters():
     s = synth.text_strings(20_000, seed=6, median=8)
     strs = s.as_list()
