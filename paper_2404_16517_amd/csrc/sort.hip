@@ -16,14 +16,13 @@
 //          over that window, end-of-string below every byte;
 //       3. sorts each segment by (key, input index): segments larger than the
 //          LDS cutover go through MSD byte passes (histogram, global scan,
-//          stable scatter), smaller ones are packed into LDS tiles and sorted
-//          by a bitonic network;
+//          stable scatter); segments of up to 128 strings are sorted by one
+//          wavefront each with a bitonic network in registers; the others are
+//          packed into LDS tiles and sorted by a bitonic network in LDS;
 //       4. where neighbours' keys differ the LCP is final and is written; runs
 //          of equal keys whose strings continue become next round's segments
 //          at depth + 7; runs of equal keys whose strings end are equal
 //          strings (LCP = length, order = input index).
-//   * The same machinery, in PLAIN mode, sorts raw 64-bit keys with a 32-bit
-//     payload (duplicate detection of prefix hashes, Appendix B).
 #include <string.h>
 
 #include "common.hpp"
@@ -38,8 +37,10 @@
 // built (so that grids are known without reading the lists back)
 enum {
     C_SMALL = 0, C_LARGE = 1, C_NEXT = 2, C_IDENT = 3, C_BND = 4,
-    C_LTILES = 5, C_SMALLN = 6, C_NTILES = 7, C_ITILES = 8, C_LELEM = 9, C_NELEM = 12, C_NCTR = 16
+    C_LTILES = 5, C_SMALLN = 6, C_NTILES = 7, C_ITILES = 8, C_LELEM = 9, C_NELEM = 12, C_TINY = 13,
+    C_TINYN = 14, C_NCTR = 16
 };
+#define WS_MAX 128  // segments of up to this many strings: one wavefront each
 // ctr[10..11]: 64-bit sum of size * skip over the routed segments
 
 // ------------------------------------------------------------ wave helpers
@@ -255,8 +256,8 @@ __global__ __launch_bounds__(NT) void k_keys(const Seg *segs, const u32 *tstart,
 }
 
 // Apply the skip, route each active segment to the LDS list or the radix list.
-__global__ void k_classify(const Seg *act, u32 nact, const u32 *skipv, u32 small_max, u32 tile, Seg *small,
-                           Seg *large, u32 *ctr)
+__global__ void k_classify(const Seg *act, u32 nact, const u32 *skipv, u32 small_max, u32 tile, Seg *tiny,
+                           Seg *small, Seg *large, u32 *ctr)
 {
     u32 j = blockIdx.x * blockDim.x + threadIdx.x;
     bool valid = j < nact;
@@ -266,8 +267,11 @@ __global__ void k_classify(const Seg *act, u32 nact, const u32 *skipv, u32 small
         if (g.aux & SEG_SKIP) g.depth += skipv[j];
         g.aux = 0;
     }
-    bool sm = valid && (g.end - g.begin) <= small_max;
-    bool lg = valid && !sm;
+    const bool ty = valid && (g.end - g.begin) <= WS_MAX;
+    const bool sm = valid && !ty && (g.end - g.begin) <= small_max;
+    const bool lg = valid && !ty && !sm;
+    const u32 c = wave_append(ty, &ctr[C_TINY]);
+    if (ty) tiny[c] = g;
     u32 a = wave_append(sm, &ctr[C_SMALL]);
     if (sm) small[a] = g;
     u32 b = wave_append(lg, &ctr[C_LARGE]);
@@ -279,6 +283,7 @@ __global__ void k_classify(const Seg *act, u32 nact, const u32 *skipv, u32 small
         for (int o = 32; o > 0; o >>= 1) sk += __shfl_xor(sk, o, 64);
         if (__lane_id() == 0 && sk) atomicAdd((unsigned long long *)&ctr[10], (unsigned long long)sk);
     }
+    wave_add(ty ? sz : 0u, &ctr[C_TINYN]);
     wave_add(sm ? sz : 0u, &ctr[C_SMALLN]);
     wave_add(lg ? (sz + tile - 1) / tile : 0u, &ctr[C_LTILES]);
     wave_add(lg ? sz : 0u, &ctr[C_LELEM]);
@@ -328,16 +333,15 @@ __global__ __launch_bounds__(NT) void k_hist(const Seg *segs, const u32 *tstart,
 }
 
 struct EmitOut {
-    Seg *small, *large_next, *next, *ident;
+    Seg *tiny, *small, *large_next, *next, *ident;
     uint2 *bnd;
     u32 *ctr;
     u8 *scat;
     u32 small_max;
     u32 tile;
-    int plain;
 };
 
-enum { K_NONE = 0, K_SMALL, K_LARGE, K_NEXT, K_IDENT };
+enum { K_NONE = 0, K_SMALL, K_LARGE, K_NEXT, K_IDENT, K_TINY, K_KINDS };
 
 // What digit d of radix segment s becomes: an entry for one of the lists
 // (kind, seg) and/or a bucket boundary (sb, depth) for the LCP pass.
@@ -360,7 +364,7 @@ __device__ __forceinline__ EmitItem emit_item(const Seg *segs, const u32 *tstart
         // or equal strings
         *scat = false;
         const u32 cnt = (u32)(mn & 0xFF);
-        if (d == 0 && !o.plain) {
+        if (d == 0) {
             if (cnt == 8) { it.kind = K_NEXT; it.ns = Seg{g.begin, g.end, g.depth + 7, SEG_SKIP}; }
             else { it.kind = K_IDENT; it.ns = Seg{g.begin, g.end, g.depth + cnt, 0}; }
         }
@@ -381,15 +385,15 @@ __device__ __forceinline__ EmitItem emit_item(const Seg *segs, const u32 *tstart
     const u32 start = hist[e] - base;
     const u32 cnt = hist[e + T] - hist[e];
     const u32 sb = g.begin + start, se = sb + cnt;
-    it.bnd = cnt > 0 && start > 0 && !o.plain;
+    it.bnd = cnt > 0 && start > 0;
     it.bv = make_uint2(sb, g.depth);
     it.ns = Seg{sb, se, g.depth, 0};
     if (cnt >= 2) {
         if (level == 7) {
-            if (!o.plain) {
-                if (d == 8) { it.kind = K_NEXT; it.ns = Seg{sb, se, g.depth + 7, SEG_SKIP}; }
-                else { it.kind = K_IDENT; it.ns = Seg{sb, se, g.depth + d, 0}; }
-            }
+            if (d == 8) { it.kind = K_NEXT; it.ns = Seg{sb, se, g.depth + 7, SEG_SKIP}; }
+            else { it.kind = K_IDENT; it.ns = Seg{sb, se, g.depth + d, 0}; }
+        } else if (cnt <= WS_MAX) {
+            it.kind = K_TINY;
         } else if (cnt <= o.small_max) {
             it.kind = K_SMALL;
         } else {
@@ -410,10 +414,10 @@ __global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart
                                               const u32 *hist, const u64 *smin, const u64 *smax,
                                               EmitOut o)
 {
-    __shared__ u32 lcount[5], lslot[5], lsum[6], gbase[5];
+    __shared__ u32 lcount[K_KINDS], lslot[K_KINDS], lsum[7], gbase[K_KINDS];
     const u32 d = threadIdx.x;
-    if (d < 5) { lcount[d] = 0; lslot[d] = 0; }
-    if (d < 6) lsum[d] = 0;
+    if (d < K_KINDS) { lcount[d] = 0; lslot[d] = 0; }
+    if (d < 7) lsum[d] = 0;
     __syncthreads();
     const u32 s0 = blockIdx.x * EPB;
     EmitItem it[EPB];
@@ -434,6 +438,7 @@ __global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart
         if (x.kind == K_LARGE) { atomicAdd(&lsum[1], (cnt + o.tile - 1) / o.tile); atomicAdd(&lsum[2], cnt); }
         if (x.kind == K_NEXT) { atomicAdd(&lsum[3], (cnt + ETILE - 1) / ETILE); atomicAdd(&lsum[4], cnt); }
         if (x.kind == K_IDENT) atomicAdd(&lsum[5], (cnt + ETILE - 1) / ETILE);
+        if (x.kind == K_TINY) atomicAdd(&lsum[6], cnt);
     }
     __syncthreads();
     if (d == 0) {
@@ -442,12 +447,14 @@ __global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart
         gbase[K_LARGE] = lcount[K_LARGE] ? atomicAdd(&o.ctr[C_LARGE], lcount[K_LARGE]) : 0u;
         gbase[K_NEXT] = lcount[K_NEXT] ? atomicAdd(&o.ctr[C_NEXT], lcount[K_NEXT]) : 0u;
         gbase[K_IDENT] = lcount[K_IDENT] ? atomicAdd(&o.ctr[C_IDENT], lcount[K_IDENT]) : 0u;
+        gbase[K_TINY] = lcount[K_TINY] ? atomicAdd(&o.ctr[C_TINY], lcount[K_TINY]) : 0u;
         if (lsum[0]) atomicAdd(&o.ctr[C_SMALLN], lsum[0]);
         if (lsum[1]) atomicAdd(&o.ctr[C_LTILES], lsum[1]);
         if (lsum[2]) atomicAdd(&o.ctr[C_LELEM], lsum[2]);
         if (lsum[3]) atomicAdd(&o.ctr[C_NTILES], lsum[3]);
         if (lsum[4]) atomicAdd(&o.ctr[C_NELEM], lsum[4]);
         if (lsum[5]) atomicAdd(&o.ctr[C_ITILES], lsum[5]);
+        if (lsum[6]) atomicAdd(&o.ctr[C_TINYN], lsum[6]);
     }
     __syncthreads();
 #pragma unroll
@@ -456,8 +463,8 @@ __global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart
         if (x.bnd) o.bnd[gbase[0] + atomicAdd(&lslot[0], 1u)] = x.bv;
         if (x.kind) {
             const u32 a = gbase[x.kind] + atomicAdd(&lslot[x.kind], 1u);
-            Seg *dst = x.kind == K_SMALL ? o.small : x.kind == K_LARGE ? o.large_next
-                     : x.kind == K_NEXT ? o.next : o.ident;
+            Seg *dst = x.kind == K_TINY ? o.tiny : x.kind == K_SMALL ? o.small
+                     : x.kind == K_LARGE ? o.large_next : x.kind == K_NEXT ? o.next : o.ident;
             dst[a] = x.ns;
         }
     }
@@ -573,7 +580,7 @@ __device__ __forceinline__ bool lds_greater(u16 sa, u64 ka, u32 va, u16 sb, u64 
 // with a bitonic network in LDS.
 __global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32 *pref, u32 nsmall,
                                                      u32 H, u64 *keys, u32 *vals, u32 *lcp, Seg *next,
-                                                     u32 *ctr, int plain)
+                                                     u32 *ctr)
 {
     __shared__ u64 skey[LDS_CAP];
     __shared__ u32 sval[LDS_CAP];
@@ -649,7 +656,7 @@ __global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32
         const u64 kb = skey[e];
         vals[pos] = sval[e];
         keys[pos] = kb;
-        if (plain || e == first) continue;
+        if (e == first) continue;
         const u64 ka = skey[e - 1];
         const u32 dep = sdep[a];
         if (ka != kb) {
@@ -683,6 +690,129 @@ __global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32
     for (u32 k = threadIdx.x; k < nq_count; k += LDS_NT) next[nq_base + k] = nq[k];
 }
 
+#define WS_SPB 16  // tiny segments per workgroup (4 wavefronts, 4 segments each)
+
+__device__ __forceinline__ bool kv_greater(u64 ka, u32 va, u64 kb, u32 vb)
+{
+    return ka != kb ? ka > kb : va > vb;
+}
+
+// Bitonic compare-exchange of element e with the element j lanes away
+// (j < 64) in a merge of size k: the lower index of an ascending pair keeps
+// the smaller (key, payload).
+__device__ __forceinline__ void ws_step(u64 &key, u32 &val, u32 e, u32 j, u32 k)
+{
+    const u64 pk = __shfl_xor(key, (int)j, 64);
+    const u32 pv = __shfl_xor(val, (int)j, 64);
+    const bool want_small = ((e & j) == 0) == ((e & k) == 0);
+    if (want_small == kv_greater(key, val, pk, pv)) {
+        key = pk;
+        val = pv;
+    }
+}
+
+// LCP of sorted element e (e >= 1) from its predecessor's key, as in the LDS
+// sort; returns whether e is the last of a run of >= 2 equal full keys (a
+// next-round segment).
+__device__ __forceinline__ bool ws_finish(u32 e, u32 cnt, u64 ka, u64 kb, u64 kn, u32 dep, u32 *lcp_out)
+{
+    if (e == 0 || e >= cnt) return false;
+    if (ka != kb) {
+        *lcp_out = key_lcp(ka, kb, dep);
+        return false;
+    }
+    const u32 c8 = (u32)(kb & 0xFF);
+    if (c8 < 8) {
+        *lcp_out = dep + c8;
+        return false;
+    }
+    return e + 1 == cnt || kn != kb;
+}
+
+__device__ __forceinline__ u32 hibit(u64 m) { return 63u - (u32)__clzll(m); }
+
+// Segments of 2..128 strings, one wavefront each: bitonic sort of
+// (key, payload) in registers (element e = lane + 64 r, r = 0, 1), then LCPs
+// and next-round runs as in the LDS sort.  Next-round segments are collected
+// per workgroup and published with one atomic per counter.
+__global__ __launch_bounds__(256) void k_wave_sort(const Seg *tiny, u32 ntiny, u64 *keys, u32 *vals, u32 *lcp,
+                                                   Seg *next, u32 *ctr)
+{
+    __shared__ Seg nq[WS_SPB * (WS_MAX / 2)];
+    __shared__ u32 nq_count, nq_tiles, nq_elems, nq_base;
+    if (threadIdx.x == 0) { nq_count = 0; nq_tiles = 0; nq_elems = 0; }
+    __syncthreads();
+    const u32 lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (u32 q = 0; q < WS_SPB / 4; q++) {
+        const u32 sidx = blockIdx.x * WS_SPB + q * 4 + wv;
+        if (sidx >= ntiny) break;  // uniform over the wavefront
+        const Seg g = tiny[sidx];
+        const u32 cnt = g.end - g.begin;
+        const u32 e0 = lane, e1 = lane + 64;
+        u64 k0 = ~0ull, k1 = ~0ull;
+        u32 v0 = 0xFFFFFFFFu, v1 = 0xFFFFFFFFu;
+        if (e0 < cnt) { k0 = keys[g.begin + e0]; v0 = vals[g.begin + e0]; }
+        if (e1 < cnt) { k1 = keys[g.begin + e1]; v1 = vals[g.begin + e1]; }
+        u32 P = 2;
+        while (P < cnt) P <<= 1;
+        for (u32 k = 2; k <= P; k <<= 1) {
+            for (u32 j = k >> 1; j > 0; j >>= 1) {
+                if (j == 64) {
+                    // partner of e0 is e1 in the same lane (k == 128: ascending)
+                    if (kv_greater(k0, v0, k1, v1)) {
+                        const u64 tk = k0; k0 = k1; k1 = tk;
+                        const u32 tv = v0; v0 = v1; v1 = tv;
+                    }
+                } else {
+                    ws_step(k0, v0, e0, j, k);
+                    if (P == 128) ws_step(k1, v1, e1, j, k);
+                }
+            }
+        }
+        if (e0 < cnt) { keys[g.begin + e0] = k0; vals[g.begin + e0] = v0; }
+        if (e1 < cnt) { keys[g.begin + e1] = k1; vals[g.begin + e1] = v1; }
+        // neighbours in sorted order
+        const u64 k0_last = __shfl(k0, 63, 64), k1_first = __shfl(k1, 0, 64);
+        const u64 up0 = __shfl_up(k0, 1, 64), up1 = __shfl_up(k1, 1, 64);
+        const u64 dn0 = __shfl_down(k0, 1, 64), dn1 = __shfl_down(k1, 1, 64);
+        const u64 pa0 = up0, pa1 = lane ? up1 : k0_last;
+        const u64 nx0 = lane < 63 ? dn0 : k1_first, nx1 = dn1;
+        u32 l0 = 0, l1 = 0;
+        const bool r0 = ws_finish(e0, cnt, pa0, k0, nx0, g.depth, &l0);
+        const bool r1 = ws_finish(e1, cnt, pa1, k1, nx1, g.depth, &l1);
+        // LCP writes (skipped for the first element and for equal full keys)
+        if (e0 >= 1 && e0 < cnt && !(pa0 == k0 && (k0 & 0xFF) == 8)) lcp[g.begin + e0] = l0;
+        if (e1 < cnt && !(pa1 == k1 && (k1 & 0xFF) == 8)) lcp[g.begin + e1] = l1;
+        // run starts, to find where each run of equal full keys begins
+        const u64 m0 = __ballot(e0 < cnt && (e0 == 0 || pa0 != k0));
+        const u64 m1 = __ballot(e1 < cnt && pa1 != k1);
+        const u64 le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        if (r0) {
+            const u32 f = hibit(m0 & le);
+            const Seg ns{g.begin + f, g.begin + e0 + 1, g.depth + 7, SEG_SKIP};
+            nq[atomicAdd(&nq_count, 1u)] = ns;
+            atomicAdd(&nq_tiles, (ns.end - ns.begin + ETILE - 1) / ETILE);
+            atomicAdd(&nq_elems, ns.end - ns.begin);
+        }
+        if (r1) {
+            const u64 mm = m1 & le;
+            const u32 f = mm ? 64u + hibit(mm) : hibit(m0);
+            const Seg ns{g.begin + f, g.begin + e1 + 1, g.depth + 7, SEG_SKIP};
+            nq[atomicAdd(&nq_count, 1u)] = ns;
+            atomicAdd(&nq_tiles, (ns.end - ns.begin + ETILE - 1) / ETILE);
+            atomicAdd(&nq_elems, ns.end - ns.begin);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && nq_count) {
+        nq_base = atomicAdd(&ctr[C_NEXT], nq_count);
+        atomicAdd(&ctr[C_NTILES], nq_tiles);
+        atomicAdd(&ctr[C_NELEM], nq_elems);
+    }
+    __syncthreads();
+    for (u32 k = threadIdx.x; k < nq_count; k += 256) next[nq_base + k] = nq[k];
+}
+
 // ------------------------------------------------------------ host driver
 
 static int build_tiles(const Seg *segs, u32 nseg, u32 tile, u32 *tstart, void *scan_scratch, hipStream_t st)
@@ -711,6 +841,7 @@ void sort_ws_layout(u64 n, SortWs *w, WsArena *a, WsCounter *c)
     TAKE(lcp_scratch, u32, n);
     TAKE(act, Seg, nseg);
     TAKE(nxt, Seg, nseg);
+    TAKE(tiny, Seg, nseg);
     TAKE(small, Seg, nseg);
     TAKE(ident, Seg, nseg);
     TAKE(largeA, Seg, nlarge);
@@ -729,9 +860,9 @@ void sort_ws_layout(u64 n, SortWs *w, WsArena *a, WsCounter *c)
 }
 
 // Run rounds until no segment is unresolved.  The caller prepared w.act
-// (nact segments covering atiles element tiles), the payload array `vals`,
-// and in PLAIN mode the keys.  The host reads the counters once after the
-// routing, once per radix level and once at the end of a round.
+// (nact segments covering atiles element tiles) and the payload array `vals`.
+// The host reads the counters once after the routing, once per radix level
+// and once at the end of a round.
 int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
 {
     hipStream_t st = J.stream;
@@ -742,7 +873,7 @@ int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
     u64 round_elems = J.n_first;
     while (nact > 0) {
         SS_HIP(hipMemsetAsync(w.ctr, 0, sizeof(u32) * C_NCTR, st));
-        if (!J.plain) {
+        {
             SS_TRY(build_tiles(w.act, nact, ETILE, w.tstart, w.scan_scratch, st));
             SS_HIP(hipMemsetAsync(w.skipv, 0xFF, sizeof(u32) * nact, st));
             {
@@ -758,11 +889,11 @@ int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
             }
             SS_CHECK_LAUNCH();
         }
-        k_classify<<<(unsigned)ceil_div(nact, 256), 256, 0, st>>>(w.act, nact, w.skipv, SM, TL, w.small, w.largeA,
-                                                                   w.ctr);
+        k_classify<<<(unsigned)ceil_div(nact, 256), 256, 0, st>>>(w.act, nact, w.skipv, SM, TL, w.tiny, w.small,
+                                                                   w.largeA, w.ctr);
         SS_CHECK_LAUNCH();
         SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, st));
-        if (!J.plain) ss_prof_add_bytes("k_skip", (double)(h[10] | ((u64)h[11] << 32)));
+        ss_prof_add_bytes("k_skip", (double)(h[10] | ((u64)h[11] << 32)));
         u32 nlarge = h[C_LARGE], ltiles = h[C_LTILES], lelem = h[C_LELEM];
         Seg *LA = w.largeA, *LB = w.largeB;
         while (nlarge > 0) {
@@ -778,7 +909,7 @@ int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
             SS_HIP(hipMemsetAsync(w.ctr + C_LARGE, 0, sizeof(u32), st));
             SS_HIP(hipMemsetAsync(w.ctr + C_LTILES, 0, sizeof(u32), st));
             SS_HIP(hipMemsetAsync(w.ctr + C_LELEM, 0, sizeof(u32), st));
-            EmitOut eo{w.small, LB, w.nxt, w.ident, w.bnd, w.ctr, w.scat, SM, TL, J.plain};
+            EmitOut eo{w.tiny, w.small, LB, w.nxt, w.ident, w.bnd, w.ctr, w.scat, SM, TL};
             k_emit<<<(unsigned)ceil_div(nlarge, EPB), 256, 0, st>>>(LA, w.tstart, nlarge, w.hist, w.smin, w.smax,
                                                                      eo);
             SS_CHECK_LAUNCH();
@@ -799,6 +930,15 @@ int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
             lelem = h[C_LELEM];
             Seg *tmp = LA; LA = LB; LB = tmp;
         }
+        const u32 ntiny = h[C_TINY];
+        if (ntiny > 0) {
+            {
+                SS_PROF("k_wave_sort", st, (double)h[C_TINYN] * 28.0);  // key+payload in/out, LCP out
+                k_wave_sort<<<(unsigned)ceil_div(ntiny, WS_SPB), 256, 0, st>>>(w.tiny, ntiny, w.keyA, J.vals, lcp,
+                                                                               w.nxt, w.ctr);
+            }
+            SS_CHECK_LAUNCH();
+        }
         const u32 nsmall = h[C_SMALL];
         if (nsmall > 0) {
             k_sizes<<<(unsigned)ceil_div(nsmall, 256), 256, 0, st>>>(w.small, nsmall, w.spref);
@@ -807,12 +947,11 @@ int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
             const u32 ntile = (u32)ceil_div(h[C_SMALLN], SM);
             {
                 SS_PROF("k_lds_sort", st, (double)h[C_SMALLN] * 28.0);  // key+payload in/out, LCP out
-                k_lds_sort<<<ntile, LDS_NT, 0, st>>>(w.small, w.spref, nsmall, SM, w.keyA, J.vals, lcp, w.nxt, w.ctr,
-                                                      J.plain);
+                k_lds_sort<<<ntile, LDS_NT, 0, st>>>(w.small, w.spref, nsmall, SM, w.keyA, J.vals, lcp, w.nxt,
+                                                      w.ctr);
             }
             SS_CHECK_LAUNCH();
         }
-        if (J.plain) break;
         if (h[C_BND] > 0) {
             k_boundary<<<(unsigned)ceil_div(h[C_BND], 256), 256, 0, st>>>(w.bnd, h[C_BND], w.keyA, lcp);
             SS_CHECK_LAUNCH();
@@ -912,7 +1051,7 @@ extern "C" int ss_sort(const uint8_t *bytes, uint64_t N, const uint64_t *offsets
         ss_set_error("workspace too small: need %zu bytes", ss_sort_workspace(n));
         return SS_ERR_WORKSPACE;
     }
-    SortJob J{bytes, N, offsets, perm, lcp ? lcp : w.lcp_scratch, 0, st, n};
+    SortJob J{bytes, N, offsets, perm, lcp ? lcp : w.lcp_scratch, st, n};
     k_iota<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(perm, (u32)n);
     SS_CHECK_LAUNCH();
     k_init_single<<<1, 1, 0, st>>>(w.act, (u32)n, J.lcp);
@@ -939,7 +1078,7 @@ extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *o
         ss_set_error("workspace too small: need %zu bytes", ss_sort_workspace(n));
         return SS_ERR_WORKSPACE;
     }
-    SortJob J{bytes, N, offsets, perm_local, lcp ? lcp : w.lcp_scratch, 0, st, 0};
+    SortJob J{bytes, N, offsets, perm_local, lcp ? lcp : w.lcp_scratch, st, 0};
     k_iota<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(perm_local, (u32)n);
     SS_CHECK_LAUNCH();
     SS_HIP(hipMemsetAsync(w.ctr, 0, sizeof(u32) * C_NCTR, st));

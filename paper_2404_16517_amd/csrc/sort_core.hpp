@@ -1,5 +1,4 @@
-// Segmented sort machinery shared by the string sort and the duplicate
-// detection of prefix doubling.
+// Segmented string sort machinery (workspace layout and the round driver).
 #pragma once
 #include "common.hpp"
 
@@ -14,7 +13,7 @@ enum { SEG_SKIP = 16 };
 struct SortWs {
     u64 *keyA, *keyB;
     u32 *valB, *lcp_scratch;
-    Seg *act, *nxt, *small, *ident, *largeA, *largeB;
+    Seg *act, *nxt, *tiny, *small, *ident, *largeA, *largeB;
     uint2 *bnd;
     u32 *skipv;
     u64 *smin, *smax;
@@ -28,9 +27,8 @@ struct SortJob {
     const u8 *bytes;
     u64 N;
     const u64 *off;
-    u32 *vals;  // payload: input indices (string sort) or any 32-bit payload (PLAIN)
-    u32 *lcp;   // LCP output (string sort)
-    int plain;  // 1: sort raw 64-bit keys in keyA, no LCP, single round
+    u32 *vals;  // payload: input indices
+    u32 *lcp;   // LCP output
     hipStream_t stream;
     u64 n_first;  // strings in the first round's segments (for byte accounting)
 };

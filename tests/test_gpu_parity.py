@@ -82,6 +82,23 @@ def test_sort_random_small_alphabets(seed):
     _check_sort(synth.from_list(strs), f"random seed={seed}")
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_sort_segment_size_boundaries(seed):
+    """Groups whose sizes straddle the per-wavefront (64, 128) and LDS cutovers,
+    with duplicates and equal 8-byte windows inside groups (next-round runs)."""
+    rng = random.Random(seed)
+    strs = []
+    for size in [2, 3, 17, 63, 64, 65, 127, 128, 129, 200, 1000, 1025]:
+        for i in range(size):
+            tail = bytes(rng.choice(b"AB") for _ in range(rng.randint(0, 12)))
+            if i % 5 == 0:
+                tail = b"SAMEWINDOW" + tail  # equal key windows, strings continue
+            strs.append(b"G%04d:" % size + tail)
+    strs += strs[: len(strs) // 7]  # exact duplicates
+    rng.shuffle(strs)
+    _check_sort(synth.from_list(strs), f"size-boundaries seed={seed}")
+
+
 def test_sort_empty_input():
     g = synth.from_list([]).to(DEV)
     perm, lcp = ss.sort(g.bytes, g.offsets)
