@@ -9,12 +9,26 @@
 #define KR_P 0x1FFFFFFFFFFFFFFFull  // 2^61 - 1
 #define KR_B 0x0B3C4D5E6F708192ull  // base
 
-// a*b mod 2^61-1 for a, b < 2^61, using 2^64 = 8 (mod p).
+// a*b mod 2^61-1 for a, b < 2^61.  With 32-bit halves (a1, b1 < 2^29):
+// a*b = a0 b0 + (a0 b1 + a1 b0) 2^32 + a1 b1 2^64, and 2^61 = 1, 2^64 = 8
+// (mod p); the middle term times 2^32 folds as (mid mod 2^29) 2^32 + mid / 2^29.
 __device__ __forceinline__ u64 mulmod61(u64 a, u64 b)
 {
-    const u64 lo = a * b;
-    const u64 hi = __umul64hi(a, b);  // < 2^58
-    u64 r = (lo & KR_P) + (lo >> 61) + (hi << 3);
+    const u32 a0 = (u32)a, a1 = (u32)(a >> 32), b0 = (u32)b, b1 = (u32)(b >> 32);
+    const u64 p00 = (u64)a0 * b0;
+    const u64 mid = (u64)a0 * b1 + (u64)a1 * b0;  // < 2^62
+    const u64 p11 = (u64)a1 * b1;                 // < 2^58
+    u64 r = (p00 & KR_P) + (p00 >> 61) + ((mid & 0x1FFFFFFFull) << 32) + (mid >> 29) + (p11 << 3);
+    r = (r & KR_P) + (r >> 61);
+    return r >= KR_P ? r - KR_P : r;
+}
+
+// a*b mod 2^61-1 for a < 2^32, b < 2^61.
+__device__ __forceinline__ u64 mulmod61_32(u32 a, u64 b)
+{
+    const u64 p00 = (u64)a * (u32)b;
+    const u64 mid = (u64)a * (u32)(b >> 32);  // < 2^61
+    u64 r = (p00 & KR_P) + (p00 >> 61) + ((mid & 0x1FFFFFFFull) << 32) + (mid >> 29);
     r = (r & KR_P) + (r >> 61);
     return r >= KR_P ? r - KR_P : r;
 }
@@ -34,7 +48,7 @@ __device__ __forceinline__ u64 kr_extend(const u8 *bytes, u64 N, u64 o, u64 from
         const u32 take = r < 8 ? (u32)r : 8u;
         const u64 w = load_le(bytes, N, o + q, take);
         C = addmod61(mulmod61(C, KR_B), w & 0xFFFFFFFFull);
-        if (take > 4) C = addmod61(mulmod61(C, KR_B), w >> 32);
+        if (take > 4) C = addmod61(mulmod61(C, KR_B), w >> 32);  // limbs < 2^32 <= p
     }
     return C;
 }
@@ -59,45 +73,79 @@ struct BPow {
     u64 p[17];  // B^0 .. B^16 mod p
 };
 
-// One doubling round: key of the min(l, len)-prefix of every active string,
-// continuing the Horner state of the previous round (bytes [lprev, l) only).
-// A group of HG lanes (1, 2, 4 or 8, matched to the new bytes of the round)
-// reads 8*HG consecutive bytes of one string per step; lane j folds its two
-// limbs, and the group combines them as
-// C <- C * B^L + sum_j v_j * B^(limbs after lane j).
-template <int HG>
+#define HU 2  // strings per lane group in flight in the hash kernels
+
+// Doubling rounds from the Horner state at lprev: the key of the
+// min(l1, len)-prefix of every active string and, when l2 != 0, also of the
+// min(l2, len)-prefix (two rounds from one read of bytes [lprev, l2); needs
+// (l1 - lprev) % 64 == 0).  A group of 8 lanes takes HU strings; per step it
+// reads 64 consecutive bytes of each, lane j folds its two limbs, and the group
+// combines them as C <- C * B^L + sum_j v_j * B^(limbs after lane j).
 __global__ __launch_bounds__(256) void k_hash_round(const u32 *act, const u32 *cnt, const u8 *bytes, u64 N,
-                                                    const u64 *off, u64 lprev, u64 l, u32 bits,
-                                                    u64 *state, u64 *keys, BPow bp)
+                                                    const u64 *off, u64 lprev, u64 l1, u64 l2, u32 bits,
+                                                    u64 *state, u64 *keys1, u64 *keys2, BPow bp)
 {
     const u32 A = *cnt;
-    const u32 g = threadIdx.x / HG, lane = threadIdx.x % HG;
-    const u32 j = blockIdx.x * (256 / HG) + g;
-    if (j >= A) return;  // whole group leaves together
-    const u32 i = act ? act[j] : j;
-    const u64 o = off[i], len = off[i + 1] - o;
-    const u64 m = l < len ? l : len;
-    u64 C = lprev ? state[i] : 0ull;
-    for (u64 x = lprev; x < m; x += 8 * HG) {
-        const u64 q = x + 8 * lane;
-        const u32 take = q < m ? (u32)((m - q) < 8 ? (m - q) : 8) : 0u;
-        const u64 w = load_le(bytes, N, o + q, take);
-        const u32 nl = take == 0 ? 0u : (take > 4 ? 2u : 1u);
-        u64 v = 0;
-        if (nl == 2) v = addmod61(mulmod61(w & 0xFFFFFFFFull, KR_B), w >> 32);
-        else if (nl == 1) v = w & 0xFFFFFFFFull;
-        const u64 rem = m - x;
-        const u32 Lstep = (u32)((rem >= 8 * HG ? 8 * HG : rem) + 3) / 4;
-        const u32 before = 2 * lane < Lstep ? 2 * lane : Lstep;
-        const u32 after = Lstep - before - nl;
-        u64 t = nl ? (after ? mulmod61(v, bp.p[after]) : v) : 0ull;
+    const u32 lane = threadIdx.x & 7;
+    const u32 j0 = (blockIdx.x * 32 + (threadIdx.x >> 3)) * HU;
+    if (j0 >= A) return;  // whole group leaves together
+    const u64 lend = l2 ? l2 : l1;
+    u32 ii[HU];
+    u64 o[HU], len[HU], m[HU], C[HU], C1[HU];
+    u64 xmax = lprev;
 #pragma unroll
-        for (int s2 = HG / 2; s2 > 0; s2 >>= 1) t = addmod61(t, __shfl_xor(t, s2, HG));
-        C = addmod61(mulmod61(C, bp.p[Lstep]), t);
+    for (int u = 0; u < HU; u++) {
+        ii[u] = 0; o[u] = 0; len[u] = 0; m[u] = lprev; C[u] = 0;
+        if (j0 + u < A) {
+            ii[u] = act ? act[j0 + u] : j0 + u;
+            o[u] = off[ii[u]];
+            len[u] = off[ii[u] + 1] - o[u];
+            m[u] = lend < len[u] ? lend : len[u];
+            if (lprev) C[u] = state[ii[u]];
+        }
+        C1[u] = C[u];
+        xmax = m[u] > xmax ? m[u] : xmax;
+    }
+    for (u64 x = lprev; x < xmax; x += 64) {
+        u64 w[HU];
+        u32 take[HU];
+#pragma unroll
+        for (int u = 0; u < HU; u++) {
+            const u64 q = x + 8 * lane;
+            take[u] = q < m[u] ? (u32)((m[u] - q) < 8 ? (m[u] - q) : 8) : 0u;
+            w[u] = load_le(bytes, N, o[u] + q, take[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < HU; u++) {
+            if (x >= m[u]) continue;  // uniform over the lane group
+            const u32 nl = take[u] == 0 ? 0u : (take[u] > 4 ? 2u : 1u);
+            u64 v = 0;
+            if (nl == 2) v = addmod61(mulmod61_32((u32)w[u], KR_B), w[u] >> 32);
+            else if (nl == 1) v = w[u] & 0xFFFFFFFFull;
+            const u64 rem = m[u] - x;
+            const u32 Lstep = (u32)((rem >= 64 ? 64 : rem) + 3) / 4;
+            const u32 before = 2 * lane < Lstep ? 2 * lane : Lstep;
+            const u32 after = Lstep - before - nl;
+            u64 t = nl ? (after ? mulmod61(v, bp.p[after]) : v) : 0ull;
+#pragma unroll
+            for (int s2 = 4; s2 > 0; s2 >>= 1) t = addmod61(t, __shfl_xor(t, s2, 8));
+            C[u] = addmod61(mulmod61(C[u], bp.p[Lstep]), t);
+            if (l2 && x + 64 == l1) C1[u] = C[u];
+        }
     }
     if (lane == 0) {
-        state[i] = C;
-        keys[j] = kr_finish(C, m, bits);
+#pragma unroll
+        for (int u = 0; u < HU; u++) {
+            if (j0 + u >= A) continue;
+            state[ii[u]] = C[u];
+            if (l2) {
+                const u64 m1 = len[u] < l1 ? len[u] : l1;
+                keys1[j0 + u] = kr_finish(m[u] <= l1 ? C[u] : C1[u], m1, bits);
+                keys2[j0 + u] = kr_finish(C[u], m[u], bits);
+            } else {
+                keys1[j0 + u] = kr_finish(C[u], m[u], bits);
+            }
+        }
     }
 }
 
@@ -109,40 +157,59 @@ struct PreLens {
     u32 count;
 };
 
-// First pass: a group of 8 lanes reads the first min(len, W) bytes of one
-// string once (W = the last precomputed prefix length <= 64; lane j holds
-// bytes [8j, 8j+8), i.e. limbs 2j and 2j+1) and emits the key of every round
-// whose prefix length is <= W, by input index.  For a prefix of L limbs,
-// C = sum_j (limb_2j*B + limb_2j+1) * B^(L-2-2j) over lanes with both limbs in
-// the prefix, plus limb_2j for the lane whose second limb is past the prefix.
-// Keys of later rounds continue from the Horner state of the W-prefix.
+// First pass: a group of 8 lanes takes HU strings and reads the first
+// min(len, W) bytes of each once (W = the last precomputed prefix length
+// <= 64; lane j holds bytes [8j, 8j+8), i.e. limbs 2j and 2j+1) and emits the
+// key of every round whose prefix length is <= W, by input index.  For a
+// prefix of L limbs, C = sum_j (limb_2j*B + limb_2j+1) * B^(L-2-2j) over lanes
+// with both limbs in the prefix, plus limb_2j for the lane whose second limb is
+// past the prefix.  Lane r finishes round r's key.  Keys of later rounds
+// continue from the Horner state of the W-prefix.
 __global__ __launch_bounds__(256) void k_hash_first(u32 n, const u8 *bytes, u64 N, const u64 *off, PreLens P,
                                                     u32 bits, BPow bp, u64 *state, u64 *pre)
 {
     const u32 lane = threadIdx.x & 7;
-    const u32 i = blockIdx.x * 32 + (threadIdx.x >> 3);
-    if (i >= n) return;  // whole group leaves together
-    const u64 o = off[i], len = off[i + 1] - o;
+    const u32 i0 = (blockIdx.x * 32 + (threadIdx.x >> 3)) * HU;
+    if (i0 >= n) return;  // whole group leaves together
     const u64 W = P.l[P.count - 1];
-    const u64 mw = len < W ? len : W;
-    const u64 q = 8ull * lane;
-    const u32 take = q < mw ? (u32)((mw - q) < 8 ? (mw - q) : 8) : 0u;
-    const u64 w = load_le(bytes, N, o + q, take);
-    const u64 a = w & 0xFFFFFFFFull, b = w >> 32;
-    const u64 v = addmod61(mulmod61(a, KR_B), b);
-    u64 C = 0;
-    for (u32 r = 0; r < P.count; r++) {
-        const u64 m = len < P.l[r] ? len : P.l[r];
-        const u32 L = (u32)((m + 3) / 4);
-        u64 c = 0;
-        if (2 * lane + 1 < L) c = mulmod61(v, bp.p[L - 2 - 2 * lane]);
-        else if (2 * lane + 1 == L) c = a;
+    u64 w[HU], len[HU];
 #pragma unroll
-        for (int s2 = 4; s2 > 0; s2 >>= 1) c = addmod61(c, __shfl_xor(c, s2, 8));
-        C = c;
-        if (lane == 0) pre[(u64)r * n + i] = kr_finish(c, m, bits);
+    for (int u = 0; u < HU; u++) {
+        w[u] = 0;
+        len[u] = 0;
+        if (i0 + u < n) {
+            const u64 o = off[i0 + u];
+            len[u] = off[i0 + u + 1] - o;
+            const u64 mw = len[u] < W ? len[u] : W;
+            const u64 q = 8ull * lane;
+            const u32 take = q < mw ? (u32)((mw - q) < 8 ? (mw - q) : 8) : 0u;
+            w[u] = load_le(bytes, N, o + q, take);
+        }
     }
-    if (lane == 0) state[i] = C;
+#pragma unroll
+    for (int u = 0; u < HU; u++) {
+        const u32 i = i0 + u;
+        if (i >= n) break;  // uniform over the lane group
+        const u32 a = (u32)w[u];
+        const u64 v = addmod61(mulmod61_32(a, KR_B), w[u] >> 32);
+        u64 C = 0, mine = 0, mm = 0;
+        for (u32 r = 0; r < P.count; r++) {
+            const u64 m = len[u] < P.l[r] ? len[u] : P.l[r];
+            const u32 L = (u32)((m + 3) / 4);
+            u64 c = 0;
+            if (2 * lane + 1 < L) c = mulmod61(v, bp.p[L - 2 - 2 * lane]);
+            else if (2 * lane + 1 == L) c = a;
+#pragma unroll
+            for (int s2 = 4; s2 > 0; s2 >>= 1) c = addmod61(c, __shfl_xor(c, s2, 8));
+            if (lane == r) {
+                mine = c;
+                mm = m;
+            }
+            C = c;
+        }
+        if (lane < P.count) pre[(u64)lane * n + i] = kr_finish(mine, mm, bits);
+        if (lane == 0) state[i] = C;
+    }
 }
 
 // ------------------------------------------------------------ duplicates
@@ -232,10 +299,11 @@ __global__ __launch_bounds__(256) void k_tab_insert(const u64 *keys, int kin, co
 
 // Finish the active strings whose key is unique (or whose length is <= l):
 // dist = min(len, l).  The others are appended to the next active list
-// (one atomic per workgroup; lists keep input order within a workgroup).
+// (one atomic per workgroup; lists keep input order within a workgroup),
+// with their key for the next round when a two-round pass computed it.
 __global__ __launch_bounds__(256) void k_dedup(const u64 *keys, int kin, const u32 *act, const u32 *cnt,
                                                const u64 *off, u64 l, int mode, const u64 *tab, u32 logT,
-                                               u32 *dist, u32 *next, u32 *ncnt)
+                                               u32 *dist, u32 *next, u32 *ncnt, const u64 *carry, u64 *carry_out)
 {
     __shared__ u32 wcount[4], base;
     const u32 A = *cnt;
@@ -272,12 +340,16 @@ __global__ __launch_bounds__(256) void k_dedup(const u64 *keys, int kin, const u
     __syncthreads();
     u32 woff = base;
     for (u32 k = 0; k < w; k++) woff += wcount[k];
-    if (stay) next[woff + (u32)__popcll(b & lanemask_lt())] = i;
+    if (stay) {
+        const u32 slot = woff + (u32)__popcll(b & lanemask_lt());
+        next[slot] = i;
+        if (carry) carry_out[slot] = carry[j];  // next round's key, already computed
+    }
 }
 
 struct PdWs {
     u32 *actA, *actB, *ctr;
-    u64 *keys, *state, *pre, *tab;
+    u64 *keys, *keysB, *keysC, *state, *pre, *tab;
 };
 
 static u32 tab_log(u64 A)
@@ -294,7 +366,8 @@ static void pd_layout(u64 n, PdWs *w, WsArena *a, WsCounter *c)
         if (a) w->field = a->take<T>(cnt);       \
         else c->take<T>(cnt);                    \
     } while (0)
-    PT(actA, u32, n); PT(actB, u32, n); PT(ctr, u32, 16); PT(keys, u64, n); PT(state, u64, n);
+    PT(actA, u32, n); PT(actB, u32, n); PT(ctr, u32, 16); PT(keys, u64, n); PT(keysB, u64, n);
+    PT(keysC, u64, n); PT(state, u64, n);
     PT(pre, u64, (u64)PRE_SLOTS * n); PT(tab, u64, 1ull << tab_log(n));
 #undef PT
 }
@@ -361,8 +434,8 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
             // the first line of every string, once
             SS_PROF("k_hash_first", st,
                     (double)n * (double)P.l[P.count - 1] + (double)n * (24.0 + 8.0 * P.count));
-            k_hash_first<<<(unsigned)ceil_div(n, 32), 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits, bp,
-                                                                     w.state, w.pre);
+            k_hash_first<<<(unsigned)ceil_div(n, 32 * HU), 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits,
+                                                                          bp, w.state, w.pre);
         }
         SS_CHECK_LAUNCH();
         SS_HIP(hipMemsetAsync(ctr + 4, 0, sizeof(u32) * 2 * P.count, st));
@@ -376,32 +449,35 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
     int ci = 0;                // which counter holds the current count
     u64 lprev = 0, l = init_len;
     u32 rounds = 0;
+    bool last_trivial = false;  // the previous round finished no string
+    // this round's keys (list order) from a two-round pass: written to keysB,
+    // compacted into keysC when the round before them shrank the list
+    const u64 *pend = nullptr;
     for (;;) {
         const u64 *keys;
-        int kin;
+        const u64 *pend_next = nullptr;
+        int kin = 0;
+        u64 lhashed = 0;  // prefix length of this round's hash launch (0: none)
         if (rounds < P.count) {
             keys = w.pre + (u64)rounds * n;
             kin = 1;
+        } else if (pend) {
+            keys = pend;
         } else {
-            // bytes are charged once the active count is read back
-            SS_PROF("k_hash_round", st, 0.0);
-            const u64 nb = l - lprev;
-            const u32 *cc = ctr + ci;
-            if (nb <= 8)
-                k_hash_round<1><<<(unsigned)ceil_div(Ah, 256), 256, 0, st>>>(act, cc, bytes, N, offsets, lprev, l,
-                                                                            hash_bits, w.state, w.keys, bp);
-            else if (nb <= 16)
-                k_hash_round<2><<<(unsigned)ceil_div(Ah, 128), 256, 0, st>>>(act, cc, bytes, N, offsets, lprev, l,
-                                                                            hash_bits, w.state, w.keys, bp);
-            else if (nb <= 32)
-                k_hash_round<4><<<(unsigned)ceil_div(Ah, 64), 256, 0, st>>>(act, cc, bytes, N, offsets, lprev, l,
-                                                                           hash_bits, w.state, w.keys, bp);
-            else
-                k_hash_round<8><<<(unsigned)ceil_div(Ah, 32), 256, 0, st>>>(act, cc, bytes, N, offsets, lprev, l,
-                                                                           hash_bits, w.state, w.keys, bp);
+            // When the previous round finished nothing, hash this round and the
+            // next from one read (the next round's keys wait in keysB).
+            const bool two = last_trivial && lprev > 0 && (l - lprev) % 64 == 0;
+            {
+                // bytes are charged once the active count is read back
+                SS_PROF("k_hash_round", st, 0.0);
+                k_hash_round<<<(unsigned)ceil_div(Ah, 32 * HU), 256, 0, st>>>(
+                    act, ctr + ci, bytes, N, offsets, lprev, l, two ? 2 * l : 0, hash_bits, w.state, w.keys,
+                    w.keysB, bp);
+            }
             SS_CHECK_LAUNCH();
             keys = w.keys;
-            kin = 0;
+            lhashed = two ? 2 * l : l;
+            if (two) pend_next = w.keysB;
         }
         u32 differ, shrt;
         if (!act && rounds < P.count) {
@@ -416,22 +492,28 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
             Ah = h[ci];
             differ = h[2];
             shrt = h[3];
-            if (rounds >= P.count) {
-                // new prefix bytes (exact for strings of length >= l), offsets, list
-                // entry, hash state in/out, key out; a launch over an empty list is
-                // not counted
+            if (lhashed) {
+                // new prefix bytes (exact for strings of length >= the prefix),
+                // offsets, list entry, hash state in/out, keys out; a launch over an
+                // empty list is not counted
                 if (Ah == 0) ss_prof_drop_last("k_hash_round");
-                else ss_prof_add_bytes("k_hash_round", (double)Ah * (double)(l - lprev) + (double)Ah * 44.0);
+                else
+                    ss_prof_add_bytes("k_hash_round", (double)Ah * (double)(lhashed - lprev) +
+                                                          (double)Ah * (pend_next ? 52.0 : 44.0));
             }
         }
+        pend = nullptr;
         if (Ah == 0) break;
         if (++rounds > 64) { ss_set_error("prefix doubling did not terminate"); return SS_ERR_INVALID_ARG; }
         if (Ah >= 2 && !differ && !shrt) {
             // one key shared by all and no short string: nothing finishes
+            last_trivial = true;
+            pend = pend_next;
             lprev = l;
             l *= 2;
             continue;
         }
+        last_trivial = false;
         const int mode = Ah == 1 ? DM_UNIQUE : (differ ? DM_TABLE : DM_ALLDUP);
         u32 logT = 0;
         if (mode == DM_TABLE) {
@@ -445,12 +527,14 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
         }
         SS_HIP(hipMemsetAsync(ctr + (ci ^ 1), 0, sizeof(u32), st));
         {
-            // list entry, offsets, key, slot, dist or next entry
-            SS_PROF("k_dedup", st, (double)Ah * (mode == DM_TABLE ? 40.0 : 24.0));
+            // list entry, offsets, key, slot, dist or next entry (and a carried key)
+            SS_PROF("k_dedup", st, (double)Ah * ((mode == DM_TABLE ? 40.0 : 24.0) + (pend_next ? 16.0 : 0.0)));
             k_dedup<<<(unsigned)ceil_div(Ah, 256), 256, 0, st>>>(keys, kin, act, ctr + ci, offsets, l, mode, w.tab,
-                                                                 logT, dist_approx, nxt, ctr + (ci ^ 1));
+                                                                 logT, dist_approx, nxt, ctr + (ci ^ 1), pend_next,
+                                                                 w.keysC);
         }
         SS_CHECK_LAUNCH();
+        if (pend_next) pend = w.keysC;
         act = nxt;
         nxt = (nxt == w.actA) ? w.actB : w.actA;
         ci ^= 1;

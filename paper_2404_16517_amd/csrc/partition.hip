@@ -189,104 +189,56 @@ __global__ void k_add_base(u64 *a, u64 n, u64 base)
     if (i < n) a[i] += base;
 }
 
-#define CP_NT 256
-#define CP_PER 16
+#define CS_NT 256     // strings per workgroup in the literal copy (one thread each)
+#define CS_BUF 16384  // LDS staging bytes
 
-#define CP_MAXS 1024  // strings whose metadata a workgroup stages in LDS
-
-// Output-ordered copy of literal bytes: each thread writes 16 consecutive
-// output bytes.  The workgroup finds the strings its 4096 bytes cover, stages
-// their output starts and source addresses in LDS, and every thread walks its
-// bytes through that table (a workgroup covering more than CP_MAXS strings,
-// i.e. mostly empty literals, searches the global arrays instead).
-__global__ __launch_bounds__(CP_NT) void k_fc_copy(const u8 *bytes, const u64 *off, u32 n, const u32 *perm,
-                                                   const u32 *fc_lcp, const u64 *suf_off, u64 base, u64 total,
-                                                   u8 *suf)
+// Literal bytes of strings [i0, i0+256) (string i's bytes [e_i, d_i) go to
+// suf[suf_off[i] ..]).  Each thread reads its string's literal with aligned
+// 8-byte words; when the workgroup's output span fits the LDS buffer the
+// literals are packed there and written out in aligned 16-byte words (bytes
+// at the two ends, which neighbouring workgroups share, one by one),
+// otherwise each thread writes its literal directly.
+__global__ __launch_bounds__(CS_NT) void k_fc_copy(const u8 *bytes, u64 N, const u64 *off, u32 n, const u32 *perm,
+                                                   const u32 *fc_lcp, const u64 *suf_off, u8 *suf)
 {
-    __shared__ u32 range[2];
-    __shared__ u64 sstart[CP_MAXS + 1];
-    __shared__ u64 ssrc[CP_MAXS];
-    const u64 c0 = (u64)blockIdx.x * CP_NT * CP_PER;
-    const u64 c1 = (c0 + CP_NT * CP_PER < total) ? c0 + CP_NT * CP_PER : total;
-    if (threadIdx.x < 2) {
-        const u64 q = (threadIdx.x == 0 ? c0 : c1 - 1) + base;
-        u32 lo = 0, hi = n;  // largest i with suf_off[i] <= q
-        while (hi - lo > 1) {
-            u32 mid = (lo + hi) >> 1;
-            if (suf_off[mid] <= q) lo = mid;
-            else hi = mid;
-        }
-        range[threadIdx.x] = lo;
-    }
-    __syncthreads();
-    const u32 i0 = range[0], i1 = range[1];
-    const u32 ns = i1 - i0 + 1;
-    const bool staged = ns <= CP_MAXS;
-    if (staged) {
-        for (u32 k = threadIdx.x; k <= ns; k += CP_NT) {
-            sstart[k] = suf_off[i0 + k] - base;  // i0 + ns <= n: suf_off has n+1 entries
-            if (k < ns) ssrc[k] = off[perm[i0 + k]] + fc_lcp[i0 + k];
-        }
-    }
-    __syncthreads();
-    const u64 q0 = c0 + (u64)threadIdx.x * CP_PER;
-    if (q0 >= c1) return;
-    const u32 cnt = (u32)((c1 - q0) < CP_PER ? (c1 - q0) : CP_PER);
-    u8 buf[CP_PER];
-    if (staged) {
-        u32 lo = 0, hi = ns;  // largest k with sstart[k] <= q0
-        while (hi - lo > 1) {
-            u32 mid = (lo + hi) >> 1;
-            if (sstart[mid] <= q0) lo = mid;
-            else hi = mid;
-        }
-        u32 k = lo;
-#pragma unroll
-        for (u32 t = 0; t < CP_PER; t++) {
-            if (t < cnt) {
-                const u64 q = q0 + t;
-                while (q >= sstart[k + 1]) k++;
-                buf[t] = bytes[ssrc[k] + (q - sstart[k])];
+    __shared__ uint4 buf4[CS_BUF / 16];
+    u8 *buf = (u8 *)buf4;
+    const u32 i0 = blockIdx.x * CS_NT;
+    const u32 i1 = (i0 + CS_NT < n) ? i0 + CS_NT : n;
+    const u64 S0 = suf_off[i0], S1 = suf_off[i1];
+    const u64 span = S1 - S0;
+    const u32 mis = (u32)(((uintptr_t)(suf + S0)) & 15);  // buf[mis] holds output byte S0
+    const bool staged = span + mis <= CS_BUF;
+    const u32 i = i0 + threadIdx.x;
+    if (i < i1) {
+        const u64 so = suf_off[i], len = suf_off[i + 1] - so;
+        const u64 src = off[perm[i]] + fc_lcp[i];
+        for (u64 k = 0; k < len; k += 8) {
+            const u32 take = (len - k) < 8 ? (u32)(len - k) : 8u;
+            const u64 w = load_le(bytes, N, src + k, take);
+            if (staged) {
+                const u64 b = so - S0 + mis + k;
+                for (u32 t = 0; t < take; t++) buf[b + t] = (u8)(w >> (8 * t));
+            } else if (take == 8 && (((uintptr_t)(suf + so + k)) & 7) == 0) {
+                *(u64 *)(suf + so + k) = w;
             } else {
-                buf[t] = 0;
-            }
-        }
-    } else {
-        u32 lo = i0, hi = i1 + 1;
-        while (hi - lo > 1) {
-            u32 mid = (lo + hi) >> 1;
-            if (suf_off[mid] - base <= q0) lo = mid;
-            else hi = mid;
-        }
-        u32 i = lo;
-        u64 so = suf_off[i] - base, se = suf_off[i + 1] - base;
-        u64 src = off[perm[i]] + fc_lcp[i];
-#pragma unroll
-        for (u32 t = 0; t < CP_PER; t++) {
-            if (t < cnt) {
-                const u64 q = q0 + t;
-                while (q >= se) {
-                    i++;
-                    so = se;
-                    se = suf_off[i + 1] - base;
-                    src = off[perm[i]] + fc_lcp[i];
-                }
-                buf[t] = bytes[src + (q - so)];
-            } else {
-                buf[t] = 0;
+                for (u32 t = 0; t < take; t++) suf[so + k + t] = (u8)(w >> (8 * t));
             }
         }
     }
-    u8 *dst = suf + base + q0;
-    if (cnt == CP_PER && (((uintptr_t)dst) & 15) == 0) {
-        uint4 v;
-        v.x = buf[0] | (buf[1] << 8) | (buf[2] << 16) | ((u32)buf[3] << 24);
-        v.y = buf[4] | (buf[5] << 8) | (buf[6] << 16) | ((u32)buf[7] << 24);
-        v.z = buf[8] | (buf[9] << 8) | (buf[10] << 16) | ((u32)buf[11] << 24);
-        v.w = buf[12] | (buf[13] << 8) | (buf[14] << 16) | ((u32)buf[15] << 24);
-        *(uint4 *)dst = v;
-    } else {
-        for (u32 t = 0; t < cnt; t++) dst[t] = buf[t];
+    if (!staged) return;  // uniform over the workgroup
+    __syncthreads();
+    const u32 nchunk = (u32)((span + mis + 15) / 16);
+    for (u32 c = threadIdx.x; c < nchunk; c += CS_NT) {
+        const u64 r = 16ull * c;  // buffer offset of the chunk; output byte S0 - mis + r
+        if (r >= mis && r + 16 - mis <= span) {
+            *(uint4 *)(suf + (S0 + r - mis)) = buf4[c];
+        } else {
+            for (u32 t = 0; t < 16; t++) {
+                const u64 q = r + t;
+                if (q >= mis && q - mis < span) suf[S0 + q - mis] = buf[q];
+            }
+        }
     }
 }
 
@@ -358,9 +310,8 @@ static int encode_impl(const uint8_t *bytes, uint64_t N, const uint64_t *offsets
         {
             // literal bytes read and written; per string its perm, offsets, e and suf_off
             SS_PROF("k_fc_copy", st, 2.0 * (double)total + (double)n * 24.0);
-            k_fc_copy<<<(unsigned)ceil_div(total, CP_NT * CP_PER), CP_NT, 0, st>>>(bytes, offsets, (u32)n, perm,
-                                                                                 fc_lcp, suf_off, suf_base, total,
-                                                                                 suf);
+            k_fc_copy<<<(unsigned)ceil_div(n, CS_NT), CS_NT, 0, st>>>(bytes, N, offsets, (u32)n, perm, fc_lcp,
+                                                                       suf_off, suf);
         }
         SS_CHECK_LAUNCH();
     }

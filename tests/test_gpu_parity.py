@@ -187,10 +187,29 @@ def test_prefix_keys_truncated_match_oracle(m):
     assert [int(x) for x in got] == exp
 
 
-@pytest.mark.parametrize("case", ["c0", "text", "text_bits12", "text_bits8", "edge"])
+def _deep_mixed(seed):
+    """Strings sharing 100+ bytes: some distinguished by 128 bytes, some by 256,
+    duplicated ones that end at 300 bytes, and a group sharing 1500 bytes, so
+    that rounds are skipped, hashed two at a time, and shrink in between."""
+    rng = random.Random(seed)
+    rnd = lambda k: bytes(rng.choice(b"ACGT") for _ in range(k))
+    strs = [b"P" * 100 + rnd(20) for _ in range(1000)]
+    strs += [b"P" * 200 + rnd(20) for _ in range(1000)]
+    dups = [b"P" * 280 + rnd(20) for _ in range(30)]
+    strs += [d for d in dups for _ in range(10)]
+    strs += [b"P" * 1500 + rnd(10) for _ in range(500)]
+    rng.shuffle(strs)
+    return synth.from_list(strs)
+
+
+@pytest.mark.parametrize("case", ["c0", "text", "text_bits12", "text_bits8", "edge", "dn_long", "deep_mixed"])
 def test_dist_prefix_matches_oracle(case):
     if case == "c0":
         s, bits = synth.dn_strings(100_000, 100, 0.5, seed=0), 64
+    elif case == "dn_long":
+        s, bits = synth.dn_strings(50_000, 500, 0.5, seed=3), 64
+    elif case == "deep_mixed":
+        s, bits = _deep_mixed(4), 64
     elif case == "edge":
         s, bits = synth.from_list(EDGE_SETS["prefix_chain"] + EDGE_SETS["zero_ff"] + EDGE_SETS["all_equal"]), 64
     else:
@@ -221,8 +240,39 @@ def _partition(s, r, pdms):
 @pytest.mark.parametrize("pdms", [False, True])
 @pytest.mark.parametrize("r", [1, 2, 16, 300])
 def test_partition_encode_matches_oracle(pdms, r):
-    s = synth.text_strings(30_000, seed=5, median=20)
-    _log(f"[partition] r={r} pdms={pdms}")
+    _check_partition(synth.text_strings(30_000, seed=5, median=20), r, pdms)
+
+
+@pytest.mark.parametrize("pdms", [False, True])
+def test_partition_encode_long_literals(pdms):
+    """300-byte strings: whole-string literals overflow the staging buffer of
+    the literal copy (direct writes); PDMS literals stay short (staged)."""
+    _check_partition(synth.dn_strings(20_000, 300, 0.3, seed=8), 5, pdms)
+
+
+@pytest.mark.parametrize("base", [7, 4096 + 9])
+def test_partition_encode_unaligned_suf_base(base):
+    """Literals written at an odd offset of a shared buffer: bytes outside
+    [base, base + total) stay untouched and suf_off is absolute."""
+    s = synth.text_strings(20_000, seed=9, median=24)
+    _log(f"[partition] suf_base={base}")
+    g, perm, lcp, dist, ids, sb, so, fc = _partition(s, 4, True)
+    t = fc["total"]
+    cap = base + t + 64
+    out = dict(run_off=torch.empty_like(fc["run_off"]), lcp=torch.empty_like(fc["lcp"]),
+               len=torch.empty_like(fc["len"]), id=torch.empty_like(fc["id"]),
+               suf_off=torch.empty_like(fc["suf_off"]),
+               suf=torch.full((cap,), 0xEE, dtype=torch.uint8, device=DEV))
+    fc2 = ss.partition_encode(g.bytes, g.offsets, perm, lcp, dist, sb, so, out=out, suf_base=base)
+    torch.cuda.synchronize()
+    buf = fc2["suf"].cpu().numpy()
+    assert bytes(buf[base:base + t]) == bytes(fc["suf"].cpu().numpy())
+    assert (buf[:base] == 0xEE).all() and (buf[base + t:] == 0xEE).all()
+    np.testing.assert_array_equal(u64(fc2["suf_off"]).astype(np.int64) - base, u64(fc["suf_off"]).astype(np.int64))
+
+
+def _check_partition(s, r, pdms):
+    _log(f"[partition] n={s.n} r={r} pdms={pdms}")
     g, perm, lcp, dist, ids, sb, so, fc = _partition(s, r, pdms)
     b, o = oracle.strings_np(s)
     p_ref = oracle.sort(b, o)
