@@ -504,26 +504,6 @@ __global__ __launch_bounds__(256) void k_merge_init(const u64 *run_begin, const 
     F[x] = res;
 }
 
-// Per pair of runs: LCP and order of their first strings.
-__global__ void k_pair_info(MergeLevel M)
-{
-    const u32 p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= M.npairs) return;
-    const u64 A0 = M.PA0[p], A1 = M.PA1[p], B1 = M.PB1[p];
-    u32 c = 0;
-    u8 fa = 1;
-    if (A1 > A0 && B1 > A1) {
-        u64 l;
-        const int r = fc_cmp(M.V, M.G[A0], M.G[A1], 0, &l);
-        c = (u32)l;
-        fa = r <= 0 ? 1 : 0;
-    } else if (A1 == A0) {
-        fa = 0;
-    }
-    M.pc[p] = c;
-    M.pfirst[p] = fa;
-}
-
 #define MW_NT 256
 #define MW_IPT 8
 #define MW_TILE (MW_NT * MW_IPT)  // outputs per workgroup
@@ -544,15 +524,50 @@ __device__ u32 corank_global(const MergeLevel &M, u64 A0, u32 na, u64 B0, u32 nb
     return xlo;
 }
 
+// Per output tile of one merge level: the LCP and order of its pair's two
+// first strings (from the group depth on, with the cached keys; written by the
+// pair's first tile) and the co-rank of the tile's first output, so that the
+// merge kernel starts without a global search.
+__global__ void k_merge_split(MergeLevel M, u32 nblocks, u32 *split)
+{
+    const u32 t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nblocks) return;
+    u32 lo = 0, hi = M.npairs;
+    while (hi - lo > 1) {
+        u32 mid = (lo + hi) >> 1;
+        if (M.tstart[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    const u32 p = lo;
+    const u64 A0 = M.PA0[p], A1 = M.PA1[p], B1 = M.PB1[p];
+    const u32 na = (u32)(A1 - A0), nb = (u32)(B1 - A1);
+    const u32 C = M.Cg[M.pg[p]];
+    u32 c = 0;
+    u8 fa = 1;
+    if (na > 0 && nb > 0) {
+        u64 l;
+        const int r = cmp_elem(M.V, M.G[A0], M.K[A0], M.G[A1], M.K[A1], C, C, &l);
+        c = (u32)l;
+        fa = r <= 0 ? 1 : 0;
+    } else if (na == 0) {
+        fa = 0;
+    }
+    if (t == M.tstart[p]) {
+        M.pc[p] = c;
+        M.pfirst[p] = fa;
+    }
+    const u32 d0 = (t - M.tstart[p]) * MW_TILE;
+    split[t] = d0 >= na + nb ? na : corank_global(M, A0, na, A1, nb, d0, c, C);
+}
+
 // One merge level, merge-path style: each workgroup produces MW_TILE outputs of
 // one pair.  Its A and B windows (plus the element before each) are staged in
 // LDS; every thread co-ranks its 8 outputs inside the window and merges them
 // with the LCP rule; outputs are written back through LDS.
-__global__ __launch_bounds__(MW_NT) void k_merge_level(MergeLevel M, u32 nblocks)
+__global__ __launch_bounds__(MW_NT) void k_merge_level(MergeLevel M, u32 nblocks, const u32 *split)
 {
     __shared__ u32 sG[MW_TILE + 2], sL[MW_TILE + 2], sF[MW_TILE + 2];
     __shared__ u64 sK[MW_TILE + 2];
-    __shared__ u32 win[4];
     const u32 blk = blockIdx.x;
     if (blk >= nblocks) return;
     u32 lo = 0, hi = M.npairs;
@@ -571,10 +586,8 @@ __global__ __launch_bounds__(MW_NT) void k_merge_level(MergeLevel M, u32 nblocks
     const u32 c = M.pc[p];
     const u32 C = M.Cg[M.pg[p]];
     const bool firstA = M.pfirst[p] != 0;
-    if (threadIdx.x == 0) win[0] = corank_global(M, A0, na, B0, nb, d0, c, C);
-    if (threadIdx.x == 64) win[1] = (d1 == tot) ? na : corank_global(M, A0, na, B0, nb, d1, c, C);
-    __syncthreads();
-    const u32 a0 = win[0], a1 = win[1];
+    const u32 a0 = split[blk];
+    const u32 a1 = (d1 == tot) ? na : split[blk + 1];
     const u32 b0 = d0 - a0, b1 = d1 - a1;
     const u32 wa = a1 - a0, wb = b1 - b0;
     // LDS layout: [pa | A window (wa) | pb | B window (wb)], pa/pb = element before the window
@@ -768,7 +781,7 @@ __global__ __launch_bounds__(256) void k_check_merge_runs(const u64 *rb, const u
 
 struct MergeWs {
     DecWs dec;
-    u32 *G0, *G1, *L0, *L1, *F0, *F1, *pc, *tstart, *sid, *pg, *Cg, *rgroup, *rep;
+    u32 *G0, *G1, *L0, *L1, *F0, *F1, *pc, *tstart, *sid, *pg, *Cg, *rgroup, *rep, *split;
     u8 *pfirst;
     u64 *PA0, *PA1, *PB1, *P, *sb, *K0, *K1;
 };
@@ -792,6 +805,7 @@ static void merge_layout(u64 n_out, u64 n_fc, u64 k, MergeWs *w, WsArena *a, WsC
     MT(sid, u32, k + 2); MT(P, u64, k + 2); MT(sb, u64, k + 2);
     MT(pc, u32, MERGE_PCAP(k)); MT(pfirst, u8, MERGE_PCAP(k)); MT(tstart, u32, MERGE_PCAP(k) + 64);
     MT(PA0, u64, MERGE_PCAP(k)); MT(PA1, u64, MERGE_PCAP(k)); MT(PB1, u64, MERGE_PCAP(k));
+    MT(split, u32, n_out / MW_TILE + MERGE_PCAP(k) + 64);  // tiles of one level
 #undef MT
 }
 
@@ -958,13 +972,13 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
     for (const LevelPlan &lp : plan) {
         MergeLevel M{G, L, F, Go, Lo, Fo, K, Ko, w.pg + lp.off, w.Cg, w.PA0 + lp.off, w.PA1 + lp.off,
                      w.PB1 + lp.off, w.tstart + lp.ts_off, w.pc + lp.off, w.pfirst + lp.off, lp.npt, V};
-        k_pair_info<<<(unsigned)ceil_div(lp.npt, 64), 64, 0, st>>>(M);
-        SS_CHECK_LAUNCH();
         const u32 nblk = tsv[lp.ts_off + lp.npt];
         if (nblk > 0) {
+            k_merge_split<<<(unsigned)ceil_div(nblk, 64), 64, 0, st>>>(M, nblk, w.split);
+            SS_CHECK_LAUNCH();
             // every element's id, LCP, bound and key read once and written once
             SS_PROF("k_merge_level", st, (double)n_out * 40.0);
-            k_merge_level<<<nblk, MW_NT, 0, st>>>(M, nblk);
+            k_merge_level<<<nblk, MW_NT, 0, st>>>(M, nblk, w.split);
         }
         SS_CHECK_LAUNCH();
         std::swap(G, Go);
