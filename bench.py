@@ -23,6 +23,7 @@ value = N / (seconds per step), in GB/s ("string bytes sorted per second").
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -161,25 +162,40 @@ def batch_leg(ss, torch, synth, num_sets=1024, lo=1e3, hi=1e5, reps=3):
 
 
 def serve_leg(ss, torch, synth, count=48, lo=1e3, hi=1e6, budget_gb=200.0, slots=4, load=0.7):
-    """Poisson request trace served with continuous batching vs one job at a time."""
+    """Sort requests served with continuous batching (`slots` concurrent
+    streams, HBM-budget admission) against one job at a time, at equal output:
+    throughput with every request queued at once, and latency of a Poisson
+    trace offered at `load` x the one-at-a-time capacity (both servers replay
+    the same trace).  Each served result must equal the job run alone."""
     from paper_2404_16517_amd import serve
     dev = torch.device("cuda:0")
     reqs = synth.poisson_requests(count, qps=1.0, size_lo=lo, size_hi=hi, seed=7)
     inputs = {r.rid: synth.request_strings(r, device=dev) for r in reqs}
     torch.cuda.synchronize()
+    budget = int(budget_gb * 1e9)
     serve.serve_sequential(reqs[:4], inputs)  # warm-up
-    seq, t_seq = serve.serve_sequential(reqs, inputs)
+    alone, t_seq = serve.serve_sequential(reqs, inputs)
     capacity = count / t_seq
-    scale = 1.0 / (capacity * load)   # arrivals at `load` x the sequential capacity
-    jobs, makespan = serve.serve_trace(reqs, inputs, int(budget_gb * 1e9), slots=slots, time_scale=scale)
+    # saturation: all requests waiting at t = 0
+    jobs_sat, span_sat = serve.serve_trace(reqs, inputs, budget, slots=slots, time_scale=0.0)
+    _, span_one = serve.serve_trace(reqs, inputs, budget, slots=1, time_scale=0.0)
+    # latency at a fixed offered load
+    scale = 1.0 / (capacity * load)
+    jobs, makespan = serve.serve_trace(reqs, inputs, budget, slots=slots, time_scale=scale)
+    jobs1, _ = serve.serve_trace(reqs, inputs, budget, slots=1, time_scale=scale)
     lat = [j.done_s - j.arrival_s for j in jobs]
-    same = all(all(torch.equal(a, b) for a, b in zip(j.result, seq[j.rid])) for j in jobs)
+    lat1 = [j.done_s - j.arrival_s for j in jobs1]
+    same = all(all(torch.equal(a, b) for a, b in zip(j.result, alone[j.rid])) for j in jobs + jobs_sat)
     total_bytes = sum(x.N for x in inputs.values())
     return {"requests": count, "sizes": f"log-uniform [{lo:.0f}, {hi:.0f}] strings", "slots": slots,
-            "budget_GB": budget_gb, "offered_qps": capacity * load,
+            "budget_GB": budget_gb,
+            "saturated_jobs_per_s": count / span_sat, "one_at_a_time_jobs_per_s": count / span_one,
+            "saturated_speedup": span_one / span_sat, "saturated_GBps": total_bytes / span_sat / 1e9,
+            "offered_qps": capacity * load,
             "p50_ms": serve.percentile(lat, 0.5) * 1e3, "p99_ms": serve.percentile(lat, 0.99) * 1e3,
-            "served_jobs_per_s": count / makespan, "sequential_jobs_per_s": capacity,
-            "served_GBps": total_bytes / makespan / 1e9, "results_identical": bool(same)}
+            "one_at_a_time_p50_ms": serve.percentile(lat1, 0.5) * 1e3,
+            "one_at_a_time_p99_ms": serve.percentile(lat1, 0.99) * 1e3,
+            "results_identical": bool(same)}
 
 
 def cpu_baseline(s_host, p, v, target_s=15.0):
@@ -244,6 +260,45 @@ def cpu_baseline(s_host, p, v, target_s=15.0):
                       f"single-threaded C oracle, {dt:.1f} s"}
 
 
+# Kernel -> the source files its code comes from (for the staleness check of
+# committed counter summaries).
+KERNEL_SOURCES = {
+    "k_hash_round": ["paper_2404_16517_amd/csrc/hash.hip", "paper_2404_16517_amd/csrc/common.hpp"],
+    "k_hash_first": ["paper_2404_16517_amd/csrc/hash.hip", "paper_2404_16517_amd/csrc/common.hpp"],
+    "k_skip": ["paper_2404_16517_amd/csrc/sort.hip", "paper_2404_16517_amd/csrc/common.hpp"],
+}
+DEFAULT_WORKLOAD = dict(n=16_000_000, length=500, ratio=0.5, pes=16, sampling=2)
+
+
+def sources_digest(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic(kernel, args):
+    """HBM bytes per launch of `kernel` from its committed counter summary
+    (profiles/<kernel>_dn16M_traffic.txt), or None when there is none, the
+    workload is not the default one, or the kernel's sources changed since."""
+    if any(getattr(args, k) != v for k, v in DEFAULT_WORKLOAD.items()) or kernel not in KERNEL_SOURCES:
+        return None
+    path = os.path.join(ROOT, "profiles", f"{kernel}_dn16M_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    digest = per = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("# sources sha256 "):
+                digest = line.split()[3]
+            elif line.startswith("traffic_per_launch_bytes "):
+                per = float(line.split()[1])
+    if digest is None or per is None or digest != sources_digest(KERNEL_SOURCES[kernel]):
+        return None
+    return per
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +314,8 @@ def main():
     ap.add_argument("--stages", action="store_true", help="per-stage times on stderr")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-per-job leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time the steps without the per-launch events (no roofline)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GB",
                     help="only run a plain device-to-device copy of this many GB (counter calibration)")
     args = ap.parse_args()
@@ -292,7 +349,7 @@ def main():
         pipe.step(Marks(torch, False))
     torch.cuda.synchronize()
     stages = {}
-    ss.profile_enable(True)   # HIP events around the library's kernels during the timed steps
+    ss.profile_enable(not args.no_profile)  # HIP events around the library's kernels in the timed steps
     t0 = time.perf_counter()
     for _ in range(args.steps):
         mk = Marks(torch, args.stages)
@@ -336,7 +393,8 @@ def main():
         ms, by, cnt = prof[name]
         achieved = by / (ms / 1e3) / 1e9 if ms > 0 else 0.0
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": name,
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(name, args),
+                           "kernel": name,
                            "launches_per_step": cnt / args.steps, "avg_launch_ms": ms / max(cnt, 1),
                            "algorithmic_bytes_per_launch": by / max(cnt, 1)}
         out["kernels_ms_per_step"] = {k: v[0] / args.steps for k, v in sorted(prof.items(), key=lambda x: -x[1][0])}

@@ -108,8 +108,9 @@ int ss_dist_exact(const uint64_t *offsets, uint64_t n, const uint32_t *perm,
 size_t ss_dist_prefix_workspace(uint64_t n);
 
 /* Approximate distinguishing prefixes by prefix doubling (Section 4; proof
- * outline in Appendix C) with exact duplicate detection by sorting (hash,
- * index) pairs and scanning neighbours (Appendix B).  Round t hashes the
+ * outline in Appendix C) with exact duplicate detection (the multiplicity of
+ * each key among the active strings, as Appendix B's sort-and-scan finds it;
+ * here counted in a hash table of the keys).  Round t hashes the
  * l_t-prefix of every active string, l_t = init_len * 2^t; a string finishes
  * when its key is unique among the active strings or its length is <= l_t,
  * with dist_approx = min(l_t, len).  Result: dist_approx >= dist for every
@@ -127,6 +128,8 @@ size_t ss_dist_prefix_workspace(uint64_t n);
 int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
                    uint32_t init_len, uint32_t hash_bits, uint32_t *dist_approx,
                    uint32_t *rounds_host, void *ws, size_t ws_bytes, void *stream);
+/* (Synchronises the stream: the number of active strings is read back every
+ * round.) */
 
 /* The prefix-doubling key of each string's first min(m, len) bytes, masked to
  * hash_bits (same hash as ss_dist_prefix; exposed so that the hash can be

@@ -540,6 +540,13 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
         ci ^= 1;
         lprev = l;
         l *= 2;
+        if (Ah >= (1u << 20)) {
+            // a large list: read the new count now rather than launch the next
+            // round over it blindly (a launch over ~A/64 workgroups that may all
+            // find the list empty costs about as much as this read-back)
+            SS_TRY(ss_read_u32(ctr + ci, &Ah, 1, st));
+            if (Ah == 0) break;
+        }
     }
     if (rounds_host) *rounds_host = rounds;
     return SS_OK;
