@@ -101,11 +101,10 @@ template <class T> int ss_scan_exclusive(const T *in, T *out, u64 n, T *scratch,
 
 // ------------------------------------------------------------ byte loads
 
-// The first `take` (0..8) bytes at bytes[a..] packed big-endian into the top
-// bytes of a 64-bit word (byte a -> bits 63..56), the rest zero.  Reads only
-// inside [bytes, bytes + N): uses two aligned 8-byte loads when they fit and
-// byte loads otherwise.
-__device__ __forceinline__ u64 load_be(const u8 *__restrict__ bytes, u64 N, u64 a, u32 take)
+// The first `take` (0..8) bytes at bytes[a..] as a little-endian word
+// (byte a -> bits 7..0), the rest zero.  Reads only inside [bytes, bytes + N):
+// two aligned 8-byte loads when they fit, byte loads otherwise.
+__device__ __forceinline__ u64 load_le(const u8 *__restrict__ bytes, u64 N, u64 a, u32 take)
 {
     if (take == 0) return 0;
     const uintptr_t p = (uintptr_t)(bytes + a);
@@ -115,28 +114,23 @@ __device__ __forceinline__ u64 load_be(const u8 *__restrict__ bytes, u64 N, u64 
     u64 v;
     if (base >= lo && base + ((sh + take > 8) ? 16 : 8) <= hi) {
         const u64 *w = (const u64 *)base;
-        u64 w0 = w[0];
-        if (sh == 0) {
-            v = w0;
-        } else if (sh + take <= 8) {
-            v = w0 >> (8 * sh);
-        } else {
-            u64 w1 = w[1];
-            v = (w0 >> (8 * sh)) | (w1 << (64 - 8 * sh));
-        }
-        v = __builtin_bswap64(v);
+        const u64 w0 = w[0];
+        if (sh == 0) v = w0;
+        else if (sh + take <= 8) v = w0 >> (8 * sh);
+        else v = (w0 >> (8 * sh)) | (w[1] << (64 - 8 * sh));
     } else {
         v = 0;
-        for (u32 t = 0; t < take; t++) v |= (u64)bytes[a + t] << (56 - 8 * t);
+        for (u32 t = 0; t < take; t++) v |= (u64)bytes[a + t] << (8 * t);
     }
-    if (take < 8) v &= ~0ull << (64 - 8 * take);
+    if (take < 8) v &= (1ull << (8 * take)) - 1ull;
     return v;
 }
 
-// Little-endian 8-byte window starting at bytes[a], zero beyond `take` bytes.
-__device__ __forceinline__ u64 load_le(const u8 *__restrict__ bytes, u64 N, u64 a, u32 take)
+// The same bytes packed big-endian into the top of a 64-bit word (byte a ->
+// bits 63..56), the rest zero: integer order of such words is byte order.
+__device__ __forceinline__ u64 load_be(const u8 *__restrict__ bytes, u64 N, u64 a, u32 take)
 {
-    return __builtin_bswap64(load_be(bytes, N, a, take));
+    return __builtin_bswap64(load_le(bytes, N, a, take));
 }
 
 // Radix key of a string at byte depth d: the next 7 bytes (zero-padded)

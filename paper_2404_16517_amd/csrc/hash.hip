@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_prefix_keys(const u8 *bytes, u64 N, con
 }
 
 struct BPow {
-    u64 p[17];  // B^0 .. B^16 mod p
+    u64 p[32];  // B^0 .. B^31 mod p
 };
 
 #define HU 2  // strings per lane group in flight in the hash kernels
@@ -78,9 +78,13 @@ struct BPow {
 // Doubling rounds from the Horner state at lprev: the key of the
 // min(l1, len)-prefix of every active string and, when l2 != 0, also of the
 // min(l2, len)-prefix (two rounds from one read of bytes [lprev, l2); needs
-// (l1 - lprev) % 64 == 0).  A group of 8 lanes takes HU strings; per step it
-// reads 64 consecutive bytes of each, lane j folds its two limbs, and the group
-// combines them as C <- C * B^L + sum_j v_j * B^(limbs after lane j).
+// (l1 - lprev) % 64 == 0).  A group of 8 lanes takes HU strings and reads 64
+// consecutive bytes of each per step; lane j holds limbs 2j, 2j+1 of the step
+// as v_j = limb_2j * B + limb_2j+1.  Lanes accumulate across full steps,
+// acc_j <- acc_j * B^16 + v_j (lane 7 starts from the previous state), so that
+// the prefix hash after the steps is C = sum_j acc_j * B^(14-2j); the lane
+// reduction is paid only where a key is read out.  A partial last step of
+// Lp limbs gives C = sum_j (acc_j * B^(14-2j+Lp) + v_j * B^(limbs after v_j)).
 __global__ __launch_bounds__(256) void k_hash_round(const u32 *act, const u32 *cnt, const u8 *bytes, u64 N,
                                                     const u64 *off, u64 lprev, u64 l1, u64 l2, u32 bits,
                                                     u64 *state, u64 *keys1, u64 *keys2, BPow bp)
@@ -90,8 +94,9 @@ __global__ __launch_bounds__(256) void k_hash_round(const u32 *act, const u32 *c
     const u32 j0 = (blockIdx.x * 32 + (threadIdx.x >> 3)) * HU;
     if (j0 >= A) return;  // whole group leaves together
     const u64 lend = l2 ? l2 : l1;
+    const u64 pw = bp.p[14 - 2 * lane], b16 = bp.p[16];
     u32 ii[HU];
-    u64 o[HU], len[HU], m[HU], C[HU], C1[HU];
+    u64 o[HU], len[HU], m[HU], acc[HU], C[HU], C1[HU];
     u64 xmax = lprev;
 #pragma unroll
     for (int u = 0; u < HU; u++) {
@@ -104,6 +109,7 @@ __global__ __launch_bounds__(256) void k_hash_round(const u32 *act, const u32 *c
             if (lprev) C[u] = state[ii[u]];
         }
         C1[u] = C[u];
+        acc[u] = lane == 7 ? C[u] : 0ull;
         xmax = m[u] > xmax ? m[u] : xmax;
     }
     for (u64 x = lprev; x < xmax; x += 64) {
@@ -121,16 +127,27 @@ __global__ __launch_bounds__(256) void k_hash_round(const u32 *act, const u32 *c
             const u32 nl = take[u] == 0 ? 0u : (take[u] > 4 ? 2u : 1u);
             u64 v = 0;
             if (nl == 2) v = addmod61(mulmod61_32((u32)w[u], KR_B), w[u] >> 32);
-            else if (nl == 1) v = w[u] & 0xFFFFFFFFull;
-            const u64 rem = m[u] - x;
-            const u32 Lstep = (u32)((rem >= 64 ? 64 : rem) + 3) / 4;
-            const u32 before = 2 * lane < Lstep ? 2 * lane : Lstep;
-            const u32 after = Lstep - before - nl;
-            u64 t = nl ? (after ? mulmod61(v, bp.p[after]) : v) : 0ull;
+            else if (nl == 1) v = w[u];
+            if (x + 64 <= m[u]) {
+                acc[u] = addmod61(mulmod61(acc[u], b16), v);
+                const bool at_l1 = l2 && x + 64 == l1;
+                if (at_l1 || x + 64 == m[u]) {
+                    u64 t = mulmod61(acc[u], pw);
 #pragma unroll
-            for (int s2 = 4; s2 > 0; s2 >>= 1) t = addmod61(t, __shfl_xor(t, s2, 8));
-            C[u] = addmod61(mulmod61(C[u], bp.p[Lstep]), t);
-            if (l2 && x + 64 == l1) C1[u] = C[u];
+                    for (int s2 = 4; s2 > 0; s2 >>= 1) t = addmod61(t, __shfl_xor(t, s2, 8));
+                    if (at_l1) C1[u] = t;
+                    C[u] = t;
+                }
+            } else {
+                const u32 Lp = (u32)((m[u] - x + 3) / 4);
+                const u32 before = 2 * lane < Lp ? 2 * lane : Lp;
+                const u32 after = Lp - before - nl;
+                u64 t = mulmod61(acc[u], bp.p[14 - 2 * lane + Lp]);
+                if (nl) t = addmod61(t, after ? mulmod61(v, bp.p[after]) : v);
+#pragma unroll
+                for (int s2 = 4; s2 > 0; s2 >>= 1) t = addmod61(t, __shfl_xor(t, s2, 8));
+                C[u] = t;
+            }
         }
     }
     if (lane == 0) {
@@ -157,14 +174,47 @@ struct PreLens {
     u32 count;
 };
 
+// Sums over the 8 lanes of a group of NV (4 or 8) values per lane, scattered:
+// afterwards lane j holds the total of value j % NV (reduce-scatter: each
+// exchange halves the values a lane keeps).
+template <int NV>
+__device__ __forceinline__ u64 lane_reduce_scatter(const u64 (&c)[8], u32 lane)
+{
+    u64 m4[4];
+    if (NV == 8) {
+        const bool hi = (lane >> 2) & 1;  // keep values 4..7
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const u64 give = hi ? c[k] : c[4 + k];
+            m4[k] = addmod61(hi ? c[4 + k] : c[k], __shfl_xor(give, 4, 8));
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; k++) m4[k] = c[k];
+    }
+    const bool b1 = (lane >> 1) & 1, b0 = lane & 1;
+    u64 m2[2];
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        const u64 give = b1 ? m4[k] : m4[2 + k];
+        m2[k] = addmod61(b1 ? m4[2 + k] : m4[k], __shfl_xor(give, 2, 8));
+    }
+    const u64 give = b0 ? m2[0] : m2[1];
+    u64 r = addmod61(b0 ? m2[1] : m2[0], __shfl_xor(give, 1, 8));
+    if (NV == 4) r = addmod61(r, __shfl_xor(r, 4, 8));  // the two quads
+    return r;
+}
+
 // First pass: a group of 8 lanes takes HU strings and reads the first
 // min(len, W) bytes of each once (W = the last precomputed prefix length
 // <= 64; lane j holds bytes [8j, 8j+8), i.e. limbs 2j and 2j+1) and emits the
 // key of every round whose prefix length is <= W, by input index.  For a
 // prefix of L limbs, C = sum_j (limb_2j*B + limb_2j+1) * B^(L-2-2j) over lanes
 // with both limbs in the prefix, plus limb_2j for the lane whose second limb is
-// past the prefix.  Lane r finishes round r's key.  Keys of later rounds
-// continue from the Horner state of the W-prefix.
+// past the prefix.  One reduce-scatter leaves round r's sum in lane r, which
+// finishes that round's key.  Keys of later rounds continue from the Horner
+// state of the W-prefix.
+template <int NV>
 __global__ __launch_bounds__(256) void k_hash_first(u32 n, const u8 *bytes, u64 N, const u64 *off, PreLens P,
                                                     u32 bits, BPow bp, u64 *state, u64 *pre)
 {
@@ -186,29 +236,30 @@ __global__ __launch_bounds__(256) void k_hash_first(u32 n, const u8 *bytes, u64 
             w[u] = load_le(bytes, N, o + q, take);
         }
     }
+    const u32 r = lane % NV;  // the round this lane finishes
+    const u64 lr = r < P.count ? P.l[r] : 0;
 #pragma unroll
     for (int u = 0; u < HU; u++) {
         const u32 i = i0 + u;
         if (i >= n) break;  // uniform over the lane group
         const u32 a = (u32)w[u];
         const u64 v = addmod61(mulmod61_32(a, KR_B), w[u] >> 32);
-        u64 C = 0, mine = 0, mm = 0;
-        for (u32 r = 0; r < P.count; r++) {
-            const u64 m = len[u] < P.l[r] ? len[u] : P.l[r];
-            const u32 L = (u32)((m + 3) / 4);
-            u64 c = 0;
-            if (2 * lane + 1 < L) c = mulmod61(v, bp.p[L - 2 - 2 * lane]);
-            else if (2 * lane + 1 == L) c = a;
+        u64 c[8];
 #pragma unroll
-            for (int s2 = 4; s2 > 0; s2 >>= 1) c = addmod61(c, __shfl_xor(c, s2, 8));
-            if (lane == r) {
-                mine = c;
-                mm = m;
-            }
-            C = c;
+        for (int q = 0; q < 8; q++) {
+            c[q] = 0;
+            if (q >= NV || (u32)q >= P.count) continue;
+            const u64 m = len[u] < P.l[q] ? len[u] : P.l[q];
+            const u32 L = (u32)((m + 3) / 4);
+            if (2 * lane + 1 < L) c[q] = mulmod61(v, bp.p[L - 2 - 2 * lane]);
+            else if (2 * lane + 1 == L) c[q] = a;
         }
-        if (lane < P.count) pre[(u64)lane * n + i] = kr_finish(mine, mm, bits);
-        if (lane == 0) state[i] = C;
+        const u64 sum = lane_reduce_scatter<NV>(c, lane);
+        if (lane < NV && r < P.count) {
+            const u64 m = len[u] < lr ? len[u] : lr;
+            pre[(u64)r * n + i] = kr_finish(sum, m, bits);
+            if (r == P.count - 1) state[i] = sum;
+        }
     }
 }
 
@@ -419,7 +470,7 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
     }
     BPow bp;
     bp.p[0] = 1;
-    for (int t = 1; t <= 16; t++) bp.p[t] = (u64)(((unsigned __int128)bp.p[t - 1] * KR_B) % KR_P);
+    for (int t = 1; t < 32; t++) bp.p[t] = (u64)(((unsigned __int128)bp.p[t - 1] * KR_B) % KR_P);
     // counters: [0], [1] active-list lengths (current / next, swapped per
     // round), [2], [3] the round's flags, [4..] flags of the first-pass rounds
     u32 *ctr = w.ctr;
@@ -434,8 +485,12 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
             // the first line of every string, once
             SS_PROF("k_hash_first", st,
                     (double)n * (double)P.l[P.count - 1] + (double)n * (24.0 + 8.0 * P.count));
-            k_hash_first<<<(unsigned)ceil_div(n, 32 * HU), 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits,
-                                                                          bp, w.state, w.pre);
+            if (P.count <= 4)
+                k_hash_first<4><<<(unsigned)ceil_div(n, 32 * HU), 256, 0, st>>>((u32)n, bytes, N, offsets, P,
+                                                                                hash_bits, bp, w.state, w.pre);
+            else
+                k_hash_first<8><<<(unsigned)ceil_div(n, 32 * HU), 256, 0, st>>>((u32)n, bytes, N, offsets, P,
+                                                                                hash_bits, bp, w.state, w.pre);
         }
         SS_CHECK_LAUNCH();
         SS_HIP(hipMemsetAsync(ctr + 4, 0, sizeof(u32) * 2 * P.count, st));

@@ -465,45 +465,6 @@ __device__ __forceinline__ int cmp_elem(const FcView &V, u32 gx, u64 kx, u32 gy,
     return fc_cmp(V, gx, gy, bound, lcp);
 }
 
-// Output-space element x of run j: its front-coded position, its LCP with the
-// run predecessor, and a lower bound on its LCP with the run's first string:
-// min(e) over the run up to x, read off the psv chain (the chain's last
-// element before an e = 0 position carries that minimum); chains longer than
-// 64 steps give the trivial bound 0.
-__global__ __launch_bounds__(256) void k_merge_init(const u64 *run_begin, const u64 *P, u32 k, u32 n_out,
-                                                    const u32 *e, const u32 *psv, u32 *G, u32 *L, u32 *F)
-{
-    const u32 x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n_out) return;
-    u32 lo = 0, hi = k;  // largest j with P[j] <= x
-    while (hi - lo > 1) {
-        u32 mid = (lo + hi) >> 1;
-        if (P[mid] <= x) lo = mid;
-        else hi = mid;
-    }
-    const u32 start = (u32)run_begin[lo];
-    const u32 g = start + (x - (u32)P[lo]);
-    G[x] = g;
-    if (g == start) {
-        L[x] = 0;
-        F[x] = F_FIRST;
-        return;
-    }
-    L[x] = e[g];
-    u32 z = g, res = 0;
-    if (e[g] > 0) {
-        for (int step = 0; step < 64; step++) {
-            const u32 j = psv[z];
-            if (e[j] == 0) {
-                res = (j == start) ? e[z] : 0u;
-                break;
-            }
-            z = j;
-        }
-    }
-    F[x] = res;
-}
-
 #define MW_NT 256
 #define MW_IPT 8
 #define MW_TILE (MW_NT * MW_IPT)  // outputs per workgroup
@@ -587,7 +548,15 @@ __global__ __launch_bounds__(MW_NT) void k_merge_level(MergeLevel M, u32 nblocks
     const u32 C = M.Cg[M.pg[p]];
     const bool firstA = M.pfirst[p] != 0;
     const u32 a0 = split[blk];
-    const u32 a1 = (d1 == tot) ? na : split[blk + 1];
+    u32 a1 = (d1 == tot) ? na : split[blk + 1];
+    // Keep the windows inside both runs even if the co-ranks are not monotone
+    // (runs that violate the sortedness precondition): na >= a1 >= a0,
+    // a1 - a0 <= d1 - d0, and d1 - a1 <= nb.
+    {
+        const u32 lo = max(a0, d1 > nb ? d1 - nb : 0u);
+        const u32 hi = min(a0 + (d1 - d0), na);
+        a1 = a1 < lo ? lo : (a1 > hi ? hi : a1);
+    }
     const u32 b0 = d0 - a0, b1 = d1 - a1;
     const u32 wa = a1 - a0, wb = b1 - b0;
     // LDS layout: [pa | A window (wa) | pb | B window (wb)], pa/pb = element before the window
@@ -703,47 +672,309 @@ __global__ __launch_bounds__(MW_NT) void k_merge_level(MergeLevel M, u32 nblocks
     }
 }
 
+#define RM_PARTS 32  // workgroups per run
+
+// Minimum LCP-with-predecessor over each run except its first element, i.e.
+// the LCP of the run's first and last strings: RM_PARTS workgroups per run
+// (blockIdx.y = part), one atomic each.
+__global__ __launch_bounds__(256) void k_run_min(const u64 *run_begin, const u64 *P, const u32 *e, u32 *runmin)
+{
+    __shared__ u32 wmin[4];
+    const u32 r = blockIdx.x;
+    const u64 b = run_begin[r], n = P[r + 1] - P[r];
+    const u64 i0 = 1 + (n * blockIdx.y) / RM_PARTS, i1 = 1 + (n * (blockIdx.y + 1)) / RM_PARTS;
+    u32 mn = 0xFFFFFFFFu;
+    for (u64 i = i0 + threadIdx.x; i < i1 && i < n; i += 256) {
+        const u32 v = e[b + i];
+        mn = v < mn ? v : mn;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const u32 y = __shfl_xor(mn, o, 64);
+        mn = y < mn ? y : mn;
+    }
+    if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = mn;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u32 m = wmin[0];
+        for (int w = 1; w < 4; w++) m = wmin[w] < m ? wmin[w] : m;
+        if (m != 0xFFFFFFFFu) atomicMin(&runmin[r], m);
+    }
+}
+
 // Common prefix length of each group: every string of run r shares
-// min(lcp(head of the group's first run, head of r), F[last of r]) bytes with
-// the group's first head, where F[last] = lcp(head of r, last of r).
-__global__ void k_group_depth(const u64 *P, const u32 *run_group, const u32 *rep, u32 k, const u32 *G, const u32 *F,
-                              FcView V, u32 *Cg)
+// min(lcp(head of the group's first run, head of r), runmin[r]) bytes with the
+// group's first head.
+__global__ void k_group_depth(const u64 *run_begin, const u64 *P, const u32 *run_group, const u32 *rep, u32 k,
+                              const u32 *runmin, FcView V, u32 *Cg)
 {
     const u32 r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= k) return;
-    const u64 a = P[r], b = P[r + 1];
-    if (b == a) return;
+    if (P[r + 1] == P[r]) return;
     const u32 g = run_group[r];
     const u32 r0 = rep[g];
-    u32 v = 0xFFFFFFFFu;
+    u32 v = runmin[r];
     if (r0 != r) {
         u64 l;
-        fc_cmp(V, G[P[r0]], G[a], 0, &l);
-        v = (u32)l;
+        fc_cmp(V, (u32)run_begin[r0], (u32)run_begin[r], 0, &l);
+        v = min(v, (u32)l);
     }
-    if (b - a >= 2) v = min(v, F[b - 1]);
     atomicMin(&Cg[g], v);
 }
 
-__global__ __launch_bounds__(256) void k_merge_keys(const u64 *P, const u32 *run_group, u32 k, u32 n_out,
-                                                    const u32 *G, const u32 *Cg, FcView V, u64 *K)
+// ---- per-element state of the merge by one segmented scan over the runs
+//
+// Output position x of run r is front-coded entry g = run_begin[r] + x - P[r]
+// with LCP e_g to its predecessor (0 at the run start).  Its state is
+//   G = g, L = e_g, F = min e over (start, x] (the LCP with the run head; all
+//   ones at the start), K = bytes [C, C+7) of its string and min(d_g - C, 8),
+// C = the group's common prefix.  F and K follow a scan with the operator
+// (reset, m, p, v): F restarts at run starts and takes minima; the 7-byte
+// window at C keeps its first p bytes from the predecessor's window
+// (p = clamp(e_g - C, 0, 7)) and takes the rest, v, from the entry's literal.
+struct MOp {
+    u32 rp;  // bit 3: reset, bits 0..2: p
+    u32 m;
+    u64 v;
+};
+
+__device__ __forceinline__ MOp mop_id() { return MOp{7u, 0xFFFFFFFFu, 0ull}; }
+
+// a, then b
+__device__ __forceinline__ MOp mop_cat(MOp a, MOp b)
 {
-    const u32 x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n_out) return;
-    u32 lo = 0, hi = k;
+    const u32 pa = a.rp & 7u, pb = b.rp & 7u;
+    const u64 keep = pb ? (~0ull << (64 - 8 * pb)) : 0ull;
+    MOp r;
+    r.rp = ((a.rp | b.rp) & 8u) | (pa < pb ? pa : pb);
+    r.m = (b.rp & 8u) ? b.m : (a.m < b.m ? a.m : b.m);
+    r.v = (a.v & keep) | (b.v & ~keep);
+    return r;
+}
+
+__device__ __forceinline__ MOp mop_shfl_up(MOp a, u32 d)
+{
+    MOp r;
+    r.rp = __shfl_up(a.rp, d, 64);
+    r.m = __shfl_up(a.m, d, 64);
+    r.v = __shfl_up(a.v, d, 64);
+    return r;
+}
+
+__device__ __forceinline__ MOp mop_shfl(MOp a, u32 src)
+{
+    MOp r;
+    r.rp = __shfl(a.rp, src, 64);
+    r.m = __shfl(a.m, src, 64);
+    r.v = __shfl(a.v, src, 64);
+    return r;
+}
+
+struct MScan {
+    const u64 *run_begin, *P;
+    const u32 *run_group, *Cg;
+    u32 k, n_out;
+    FcView V;
+};
+
+// The run holding the positions being walked: its output range [pr, pr1),
+// front-coded start and group depth, kept in registers.
+struct RunCur {
+    u32 r;
+    u64 pr, pr1, rb;
+    u32 C;
+};
+
+__device__ __forceinline__ RunCur run_cur(const MScan &S, u32 r)
+{
+    return RunCur{r, S.P[r], S.P[r + 1], S.run_begin[r], S.Cg[S.run_group[r]]};
+}
+
+// advance to the run containing x (x >= the current run's start)
+__device__ __forceinline__ void run_seek(const MScan &S, RunCur &c, u64 x)
+{
+    while (c.pr1 <= x) {
+        c.r++;
+        c.pr = c.pr1;
+        c.pr1 = S.P[c.r + 1];
+        c.rb = S.run_begin[c.r];
+        c.C = S.Cg[S.run_group[c.r]];
+    }
+}
+
+// The operator of output position x (in run c); its low byte carries the
+// element's length count min(d_g - C, 8), so that the inclusive operator at x
+// is the element's cached key.  *g_out, *e_out: its entry and LCP.
+__device__ __forceinline__ MOp mop_of(const MScan &S, const RunCur &c, u64 x, u32 *g_out, u32 *e_out)
+{
+    const bool start = x == c.pr;
+    const u32 g = (u32)(c.rb + (x - c.pr));
+    const u32 e = start ? 0u : S.V.e[g];
+    const u32 d = S.V.d[g];
+    const u32 C = c.C;
+    *g_out = g;
+    *e_out = e;
+    const u32 cnt = d > C ? (d - C < 8 ? d - C : 8u) : 0u;
+    MOp o;
+    const u32 p = e > C ? (e - C < 7 ? e - C : 7u) : 0u;
+    o.rp = (start ? 8u : 0u) | p;
+    o.m = start ? 0xFFFFFFFFu : e;
+    o.v = cnt;
+    const u32 from = C + p;  // first window byte the entry's literal supplies (>= e)
+    const u32 to = d < C + 7 ? d : C + 7;
+    if (p < 7 && to > from)
+        o.v |= load_be(S.V.suf, S.V.sufN, S.V.suf_off[g] + (from - e), to - from) >> (8 * p);
+    return o;
+}
+
+__device__ __forceinline__ u32 run_of(const u64 *P, u32 k, u64 x)
+{
+    u32 lo = 0, hi = k;  // largest j with P[j] <= x
     while (hi - lo > 1) {
-        u32 mid = (lo + hi) >> 1;
+        const u32 mid = (lo + hi) >> 1;
         if (P[mid] <= x) lo = mid;
         else hi = mid;
     }
-    const u32 C = Cg[run_group[lo]];
-    const u32 g = G[x];
-    const u64 len = V.d[g];
-    const u64 rem = len > C ? len - C : 0;
-    const u32 take = rem < 7 ? (u32)rem : 7u;
-    const u64 data = fc_load_be(V, g, C, take);
-    const u32 cnt = rem < 8 ? (u32)rem : 8u;
-    K[x] = (data & ~0xFFull) | cnt;
+    return lo;
+}
+
+#define MS_PER 8
+#define MS_ITEMS (256 * MS_PER)  // elements per workgroup
+
+// The workgroup's operators in LDS, read with consecutive lanes on consecutive
+// elements; returns this thread's composite of its MS_PER consecutive ones.
+__device__ __forceinline__ MOp mscan_stage(const MScan &S, u64 x0, MOp *ops)
+{
+    __shared__ u32 rfirst;
+    if (threadIdx.x == 0) rfirst = x0 < S.n_out ? run_of(S.P, S.k, x0) : 0u;
+    __syncthreads();
+    RunCur c = run_cur(S, rfirst);
+    for (u32 q = 0; q < MS_PER; q++) {
+        const u32 i = q * 256 + threadIdx.x;
+        const u64 x = x0 + i;
+        MOp o = mop_id();
+        if (x < S.n_out) {
+            run_seek(S, c, x);
+            u32 g, e;
+            o = mop_of(S, c, x, &g, &e);
+        }
+        ops[i] = o;
+    }
+    __syncthreads();
+    MOp t = mop_id();
+#pragma unroll
+    for (u32 q = 0; q < MS_PER; q++) t = mop_cat(t, ops[threadIdx.x * MS_PER + q]);
+    return t;
+}
+
+// Ordered reduction / exclusive scan of one operator per thread over a
+// 256-thread workgroup.
+__device__ __forceinline__ MOp block_mop_reduce(MOp a)
+{
+    __shared__ MOp wsum[4];
+    const u32 lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (u32 d = 1; d < 64; d <<= 1) {
+        const MOp y = mop_shfl_up(a, d);
+        if (lane >= d) a = mop_cat(y, a);
+    }
+    if (lane == 63) wsum[wv] = a;
+    __syncthreads();
+    MOp t = wsum[0];
+    for (u32 w = 1; w < 4; w++) t = mop_cat(t, wsum[w]);
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ MOp block_mop_exclusive(MOp a, MOp carry)
+{
+    __shared__ MOp wsum[4];
+    const u32 lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    MOp inc = a;
+#pragma unroll
+    for (u32 d = 1; d < 64; d <<= 1) {
+        const MOp y = mop_shfl_up(inc, d);
+        if (lane >= d) inc = mop_cat(y, inc);
+    }
+    if (lane == 63) wsum[wv] = inc;
+    MOp ex = mop_shfl_up(inc, 1);
+    if (lane == 0) ex = mop_id();
+    __syncthreads();
+    MOp pre = carry;
+    for (u32 w = 0; w < wv; w++) pre = mop_cat(pre, wsum[w]);
+    __syncthreads();
+    return mop_cat(pre, ex);
+}
+
+// Phase 1: the operator of every MS_ITEMS-element block.
+__global__ __launch_bounds__(256) void k_mscan_reduce(MScan S, MOp *blk)
+{
+    __shared__ MOp ops[MS_ITEMS];
+    MOp t = mscan_stage(S, (u64)blockIdx.x * MS_ITEMS, ops);
+    t = block_mop_reduce(t);
+    if (threadIdx.x == 0) blk[blockIdx.x] = t;
+}
+
+// Phase 2: exclusive scan of the block operators (one workgroup of 1024:
+// each thread composes a chunk, the chunk composites are scanned by
+// wavefront shuffles and one pass over the 16 wavefront totals).
+__global__ __launch_bounds__(1024) void k_mscan_top(MOp *blk, u32 nb)
+{
+    __shared__ MOp wtot[16];
+    const u32 per = (nb + 1023) / 1024;
+    const u32 c0 = threadIdx.x * per, c1 = (c0 + per < nb) ? c0 + per : nb;
+    MOp t = mop_id();
+    for (u32 i = c0; i < c1; i++) t = mop_cat(t, blk[i]);
+    const u32 lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    MOp inc = t;
+#pragma unroll
+    for (u32 d = 1; d < 64; d <<= 1) {
+        const MOp y = mop_shfl_up(inc, d);
+        if (lane >= d) inc = mop_cat(y, inc);
+    }
+    if (lane == 63) wtot[wv] = inc;
+    MOp ex = mop_shfl_up(inc, 1);
+    if (lane == 0) ex = mop_id();
+    __syncthreads();
+    MOp pre = mop_id();
+    for (u32 w = 0; w < wv; w++) pre = mop_cat(pre, wtot[w]);
+    pre = mop_cat(pre, ex);
+    for (u32 i = c0; i < c1; i++) {
+        const MOp v = blk[i];
+        blk[i] = pre;
+        pre = mop_cat(pre, v);
+    }
+}
+
+// Phase 3: every element's inclusive operator -> G, L, F, K (written with
+// consecutive lanes on consecutive elements).
+__global__ __launch_bounds__(256) void k_mscan_apply(MScan S, const MOp *blk, u32 *G, u32 *L, u32 *F, u64 *K)
+{
+    __shared__ MOp ops[MS_ITEMS];
+    const u64 x0 = (u64)blockIdx.x * MS_ITEMS;
+    const MOp t = mscan_stage(S, x0, ops);
+    MOp st = block_mop_exclusive(t, blk[blockIdx.x]);
+#pragma unroll
+    for (u32 q = 0; q < MS_PER; q++) {
+        const u32 i = threadIdx.x * MS_PER + q;
+        st = mop_cat(st, ops[i]);
+        ops[i].m = st.m;
+        ops[i].v = st.v;
+    }
+    __syncthreads();
+    RunCur c = run_cur(S, x0 < S.n_out ? run_of(S.P, S.k, x0) : 0u);
+    for (u32 q = 0; q < MS_PER; q++) {
+        const u32 i = q * 256 + threadIdx.x;
+        const u64 x = x0 + i;
+        if (x >= S.n_out) break;
+        run_seek(S, c, x);
+        const bool start = x == c.pr;
+        const u32 g = (u32)(c.rb + (x - c.pr));
+        G[x] = g;
+        L[x] = start ? 0u : S.V.e[g];
+        F[x] = ops[i].m;
+        K[x] = ops[i].v;
+    }
 }
 
 // Source (run, position) of every output: runs sorted by their front-coded
@@ -781,7 +1012,8 @@ __global__ __launch_bounds__(256) void k_check_merge_runs(const u64 *rb, const u
 
 struct MergeWs {
     DecWs dec;
-    u32 *G0, *G1, *L0, *L1, *F0, *F1, *pc, *tstart, *sid, *pg, *Cg, *rgroup, *rep, *split;
+    u32 *G0, *G1, *L0, *L1, *F0, *F1, *pc, *tstart, *sid, *pg, *Cg, *rgroup, *rep, *split, *runmin;
+    MOp *mblk;
     u8 *pfirst;
     u64 *PA0, *PA1, *PB1, *P, *sb, *K0, *K1;
 };
@@ -806,6 +1038,7 @@ static void merge_layout(u64 n_out, u64 n_fc, u64 k, MergeWs *w, WsArena *a, WsC
     MT(pc, u32, MERGE_PCAP(k)); MT(pfirst, u8, MERGE_PCAP(k)); MT(tstart, u32, MERGE_PCAP(k) + 64);
     MT(PA0, u64, MERGE_PCAP(k)); MT(PA1, u64, MERGE_PCAP(k)); MT(PB1, u64, MERGE_PCAP(k));
     MT(split, u32, n_out / MW_TILE + MERGE_PCAP(k) + 64);  // tiles of one level
+    MT(runmin, u32, k + 2); MT(mblk, MOp, n_out / MS_ITEMS + 2);
 #undef MT
 }
 
@@ -900,9 +1133,6 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
     }
     // psv chains over the whole front-coded array (no decoding of the strings)
     SS_TRY(psv_build(fc_lcp, n_fc, w.dec.psv, w.dec.tree, w.dec.cmin, st));
-    k_merge_init<<<(unsigned)ceil_div(n_out, 256), 256, 0, st>>>(run_begin, w.P, k, (u32)n_out, fc_lcp, w.dec.psv,
-                                                                 w.G0, w.L0, w.F0);
-    SS_CHECK_LAUNCH();
     const FcView V{fc_lcp, fc_len, w.dec.psv, suf_off, suf, sufN};
     // group of every run, first non-empty run of every group, group depths, keys
     std::vector<u32> rg(k), rep(groups, 0);
@@ -916,9 +1146,22 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
     SS_HIP(hipMemcpyAsync(w.rgroup, rg.data(), sizeof(u32) * k, hipMemcpyHostToDevice, st));
     SS_HIP(hipMemcpyAsync(w.rep, rep.data(), sizeof(u32) * groups, hipMemcpyHostToDevice, st));
     SS_HIP(hipMemsetAsync(w.Cg, 0xFF, sizeof(u32) * groups, st));
-    k_group_depth<<<(unsigned)ceil_div(k, 64), 64, 0, st>>>(w.P, w.rgroup, w.rep, k, w.G0, w.F0, V, w.Cg);
+    SS_HIP(hipMemsetAsync(w.runmin, 0xFF, sizeof(u32) * k, st));
+    k_run_min<<<dim3(k, RM_PARTS), 256, 0, st>>>(run_begin, w.P, fc_lcp, w.runmin);
     SS_CHECK_LAUNCH();
-    k_merge_keys<<<(unsigned)ceil_div(n_out, 256), 256, 0, st>>>(w.P, w.rgroup, k, (u32)n_out, w.G0, w.Cg, V, w.K0);
+    k_group_depth<<<(unsigned)ceil_div(k, 64), 64, 0, st>>>(run_begin, w.P, w.rgroup, w.rep, k, w.runmin, V, w.Cg);
+    SS_CHECK_LAUNCH();
+    {
+        // front-coded LCP, length, literal offset and up to 7 literal bytes in (twice), state out
+        SS_PROF("k_mscan", st, (double)n_out * (2.0 * 24.0 + 20.0));
+        const MScan S{run_begin, w.P, w.rgroup, w.Cg, k, (u32)n_out, V};
+        const u32 nb = (u32)ceil_div(n_out, MS_ITEMS);
+        k_mscan_reduce<<<nb, 256, 0, st>>>(S, w.mblk);
+        SS_CHECK_LAUNCH();
+        k_mscan_top<<<1, 1024, 0, st>>>(w.mblk, nb);
+        SS_CHECK_LAUNCH();
+        k_mscan_apply<<<nb, 256, 0, st>>>(S, w.mblk, w.G0, w.L0, w.F0, w.K0);
+    }
     SS_CHECK_LAUNCH();
     u32 *G = w.G0, *L = w.L0, *F = w.F0, *Go = w.G1, *Lo = w.L1, *Fo = w.F1;
     u64 *K = w.K0, *Ko = w.K1;

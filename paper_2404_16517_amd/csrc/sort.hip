@@ -145,10 +145,13 @@ __global__ void k_sizes(const Seg *segs, u32 nseg, u32 *out)
 
 // Minimum LCP of every member with the segment's first string, from `depth`.
 // A group of 8 lanes compares 64 consecutive bytes of each of two members per
-// step; the first string's bytes [depth, depth + 2048) come from LDS.
+// step; the first string's bytes [depth, depth + 2048) come from LDS.  Each
+// member also leaves its first mismatch position, its remaining length there
+// (capped at 8) and its 8 bytes there (mword, mpr), from which k_keys builds
+// its key without reading the string again.
 __global__ __launch_bounds__(NT) void k_skip(const Seg *segs, const u32 *tstart, u32 nseg,
                                              const u8 *bytes, u64 N, const u64 *off,
-                                             const u32 *perm, u32 *skipv)
+                                             const u32 *perm, u32 *skipv, u64 *mword, uint2 *mpr)
 {
     __shared__ u64 fsw[SKFS];
     const u32 t = blockIdx.x;
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(NT) void k_skip(const Seg *segs, const u32 *tstart,
     const u32 grp = threadIdx.x / SKG, lane = threadIdx.x % SKG;
     u64 best = ~0ull;
     for (u32 i = b0 + grp * SKU; i < b1; i += (NT / SKG) * SKU) {
-        u64 o[SKU], m[SKU], x[SKU], res[SKU];
+        u64 o[SKU], m[SKU], x[SKU], res[SKU], len[SKU];
         bool act[SKU];
 #pragma unroll
         for (int u = 0; u < SKU; u++) {
@@ -177,11 +180,13 @@ __global__ __launch_bounds__(NT) void k_skip(const Seg *segs, const u32 *tstart,
             res[u] = ~0ull;
             o[u] = 0;
             m[u] = 0;
+            len[u] = 0;
             x[u] = g.depth;
             if (i + u < b1) {
                 const u32 p = perm[i + u];
                 o[u] = off[p];
                 const u64 l = off[p + 1] - o[u];
+                len[u] = l;
                 m[u] = l < fl ? l : fl;
                 res[u] = m[u];
                 act[u] = x[u] < m[u];
@@ -230,6 +235,12 @@ __global__ __launch_bounds__(NT) void k_skip(const Seg *segs, const u32 *tstart,
             if (i + u < b1) {
                 const u64 c = res[u] > g.depth ? res[u] - g.depth : 0ull;
                 best = c < best ? c : best;
+                if (lane == 0) {
+                    const u64 rem = len[u] - res[u];
+                    const u32 tk = rem < 8 ? (u32)rem : 8u;
+                    mword[i + u] = load_be(bytes, N, o[u] + res[u], tk);
+                    mpr[i + u] = make_uint2((u32)res[u], tk);
+                }
             }
     }
     const u32 b32 = best > 0xFFFFFFFFull ? 0xFFFFFFFFu : (u32)best;
@@ -239,19 +250,46 @@ __global__ __launch_bounds__(NT) void k_skip(const Seg *segs, const u32 *tstart,
 
 __global__ __launch_bounds__(NT) void k_keys(const Seg *segs, const u32 *tstart, u32 nseg,
                                              const u8 *bytes, u64 N, const u64 *off,
-                                             const u32 *perm, const u32 *skipv, u64 *keys)
+                                             const u32 *perm, const u32 *skipv, const u64 *mword,
+                                             const uint2 *mpr, u64 *keys)
 {
+    __shared__ u64 fw;
     const u32 t = blockIdx.x;
     const u32 s = seg_of_tile(tstart, nseg, t);
     const Seg g = segs[s];
     const u32 lt = t - tstart[s];
     const u32 b0 = g.begin + lt * ETILE;
     const u32 b1 = min(g.end, b0 + ETILE);
-    const u64 d = (u64)g.depth + ((g.aux & SEG_SKIP) ? skipv[s] : 0u);
+    if (!(g.aux & SEG_SKIP)) {
+        const u64 d = g.depth;
+        for (u32 i = b0 + threadIdx.x; i < b1; i += NT) {
+            const u32 p = perm[i];
+            const u64 o = off[p], l = off[p + 1] - o;
+            keys[i] = make_key(bytes, N, o, l, d);
+        }
+        return;
+    }
+    // A member agrees with the segment's first string up to its mismatch
+    // position pos >= d, so its key at d is the first string's bytes [d, pos)
+    // followed by its own bytes from pos (mword).
+    const u64 d = (u64)g.depth + skipv[s];
+    if (threadIdx.x == 0) {
+        const u32 f = perm[g.begin];
+        const u64 fo = off[f], fl = off[f + 1] - fo;
+        const u64 r = fl - d;  // the first string is a member: fl >= d
+        fw = load_be(bytes, N, fo + d, r < 7 ? (u32)r : 7u);
+    }
+    __syncthreads();
     for (u32 i = b0 + threadIdx.x; i < b1; i += NT) {
-        const u32 p = perm[i];
-        const u64 o = off[p], l = off[p + 1] - o;
-        keys[i] = make_key(bytes, N, o, l, d);
+        const uint2 pr = mpr[i];
+        const u32 k = pr.x - (u32)d;  // bytes shared with the first string beyond d
+        u64 data = fw;
+        if (k < 7) {
+            const u64 keep = k ? (~0ull << (64 - 8 * k)) : 0ull;
+            data = (fw & keep) | (mword[i] >> (8 * k));
+        }
+        const u32 cnt = pr.y + k < 8 ? pr.y + k : 8u;
+        keys[i] = (data & ~0xFFull) | cnt;
     }
 }
 
@@ -837,6 +875,8 @@ void sort_ws_layout(u64 n, SortWs *w, WsArena *a, WsCounter *c)
     } while (0)
     TAKE(keyA, u64, n);
     TAKE(keyB, u64, n);
+    TAKE(mword, u64, n);
+    TAKE(mpr, uint2, n);
     TAKE(valB, u32, n);
     TAKE(lcp_scratch, u32, n);
     TAKE(act, Seg, nseg);
@@ -877,15 +917,17 @@ int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
             SS_TRY(build_tiles(w.act, nact, ETILE, w.tstart, w.scan_scratch, st));
             SS_HIP(hipMemsetAsync(w.skipv, 0xFF, sizeof(u32) * nact, st));
             {
-                // algorithmic bytes: perm + offsets per string, plus the common prefix
-                // and one word (added once the skips are known)
-                SS_PROF("k_skip", st, (double)round_elems * 28.0);
-                k_skip<<<atiles, NT, 0, st>>>(w.act, w.tstart, nact, J.bytes, J.N, J.off, J.vals, w.skipv);
+                // algorithmic bytes: perm + offsets + one word per string, its mismatch
+                // record out, plus the common prefix (added once the skips are known)
+                SS_PROF("k_skip", st, (double)round_elems * 44.0);
+                k_skip<<<atiles, NT, 0, st>>>(w.act, w.tstart, nact, J.bytes, J.N, J.off, J.vals, w.skipv,
+                                              w.mword, w.mpr);
             }
             SS_CHECK_LAUNCH();
             {
-                SS_PROF("k_keys", st, (double)round_elems * 36.0);  // perm, offsets, 8 B read, key write
-                k_keys<<<atiles, NT, 0, st>>>(w.act, w.tstart, nact, J.bytes, J.N, J.off, J.vals, w.skipv, w.keyA);
+                SS_PROF("k_keys", st, (double)round_elems * 24.0);  // mismatch record in, key out
+                k_keys<<<atiles, NT, 0, st>>>(w.act, w.tstart, nact, J.bytes, J.N, J.off, J.vals, w.skipv,
+                                              w.mword, w.mpr, w.keyA);
             }
             SS_CHECK_LAUNCH();
         }

@@ -11,7 +11,8 @@ struct Seg {
 enum { SEG_SKIP = 16 };
 
 struct SortWs {
-    u64 *keyA, *keyB;
+    u64 *keyA, *keyB, *mword;  // mword, mpr: each member's first mismatch with its segment's first string
+    uint2 *mpr;
     u32 *valB, *lcp_scratch;
     Seg *act, *nxt, *tiny, *small, *ident, *largeA, *largeB;
     uint2 *bnd;
