@@ -320,7 +320,7 @@ def main():
                     help="only run a plain device-to-device copy of this many GB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only (use --gpus 1); the multi-GPU design is described, not built", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -80,7 +80,8 @@ int ss_sort(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t 
  *   perm_local[i] (out, n)  index WITHIN its set of the string at position i
  *                           of that set's sorted order (positions are global).
  *   lcp[i] (out, n)         LCP array of each set (0 at each set start); may be NULL.
- * Uses the ss_sort workspace for n. */
+ * Uses the ss_sort workspace for n.  INVALID_ARG if set_off is malformed
+ * (checked on the device; the call reads one word back). */
 int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
                   const uint64_t *set_off, uint32_t num_sets, uint32_t *perm_local,
                   uint32_t *lcp, void *ws, size_t ws_bytes, void *stream);

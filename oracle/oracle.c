@@ -22,7 +22,7 @@
  *     oracle computes the merge result by its plain definition (a stable sort of
  *     the union), which the LCP loser tree reaches faster.
  *
- * Readings where the paper is silent (each also listed in the design doc):
+ * Readings where the paper is silent:
  *   R1 strings carry explicit lengths; a string that is a proper prefix of
  *      another is smaller (the end sentinel sorts below every byte, Section 2),
  *      and lengths / dist count bytes only (no sentinel).

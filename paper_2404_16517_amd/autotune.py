@@ -6,7 +6,7 @@ sorted in LDS) and the radix tile (elements per workgroup in radix passes),
 and writes the fastest combination to a JSON table.  ``apply()`` loads a table
 and sets the library's tuning.  Results never depend on the tuning, only time.
 
-    python -m paper_2404_16517_amd.autotune --out gpurun_out/tuning.json
+    python -m paper_2404_16517_amd.autotune --out tuning.json
 """
 from __future__ import annotations
 

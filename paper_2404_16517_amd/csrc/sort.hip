@@ -1101,6 +1101,29 @@ extern "C" int ss_sort(const uint8_t *bytes, uint64_t N, const uint64_t *offsets
     return sort_rounds(J, w, n >= 2 ? 1 : 0, (u32)ceil_div(n, ETILE));
 }
 
+// set_off: non-decreasing, set_off[0] = 0, set_off[num_sets] = n
+__global__ void k_check_sets(const u64 *set_off, u32 nsets, u64 n, u32 *bad)
+{
+    const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > nsets) return;
+    const u64 v = set_off[j];
+    if ((j == 0 && v != 0) || (j == nsets && v != n) || v > n || (j > 0 && v < set_off[j - 1])) atomicOr(bad, 1u);
+}
+
+static int check_sets(const u64 *set_off, u32 num_sets, u64 n, u32 *scratch, hipStream_t st)
+{
+    SS_HIP(hipMemsetAsync(scratch, 0, sizeof(u32), st));
+    k_check_sets<<<(unsigned)ceil_div((u64)num_sets + 1, 256), 256, 0, st>>>(set_off, num_sets, n, scratch);
+    SS_CHECK_LAUNCH();
+    u32 bad;
+    SS_TRY(ss_read_u32(scratch, &bad, 1, st));
+    if (bad) {
+        ss_set_error("set_off must be non-decreasing with set_off[0] = 0 and set_off[num_sets] = n");
+        return SS_ERR_INVALID_ARG;
+    }
+    return SS_OK;
+}
+
 extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
                              const uint64_t *set_off, uint32_t num_sets, uint32_t *perm_local,
                              uint32_t *lcp, void *ws, size_t ws_bytes, void *stream)
@@ -1120,6 +1143,7 @@ extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *o
         ss_set_error("workspace too small: need %zu bytes", ss_sort_workspace(n));
         return SS_ERR_WORKSPACE;
     }
+    SS_TRY(check_sets(set_off, num_sets, n, w.ctr, st));
     SortJob J{bytes, N, offsets, perm_local, lcp ? lcp : w.lcp_scratch, st, 0};
     k_iota<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(perm_local, (u32)n);
     SS_CHECK_LAUNCH();

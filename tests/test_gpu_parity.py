@@ -151,6 +151,14 @@ def test_sort_batch_equals_single_sorts():
         np.testing.assert_array_equal(Lc[a:e], oracle.lcp(sub_b, sub_o, pr))
 
 
+def test_sort_batch_rejects_malformed_sets():
+    s = synth.from_list([b"A", b"B", b"C"])
+    g = s.to(DEV)
+    for bad in ([0, 2, 1, 3], [0, 1, 2], [1, 2, 3]):
+        with pytest.raises(ss.StrsortError):
+            ss.sort_batch(g.bytes, g.offsets, torch.tensor(bad, device=DEV))
+
+
 def test_sort_batch_with_empty_and_single_sets():
     strs = [b"C", b"A", b"B", b"Z", b"Y", b"Y"]
     s = synth.from_list(strs)
