@@ -63,8 +63,7 @@ class Pipeline:
         perm = perm_l + self.pos_base
         ev("sort_batch+lcp")
         # 3. regular sampling (v+1 samples per PE) and splitters
-        samp = torch.cat([ss.select_splitters(perm[a:b], self.v + 2)
-                          for a, b in zip(self.bounds[:-1], self.bounds[1:])])
+        samp = ss.select_splitters_batch(perm, self.set_off, self.v + 2)
         sb, so = ss.gather_strings(B, O, samp)
         sperm, _ = ss.sort(sb, so, with_lcp=False)
         fid = ss.select_splitters(sperm, p)

@@ -146,6 +146,19 @@ int ss_prefix_keys(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, ui
 int ss_select_splitters(uint64_t n, const uint32_t *perm, uint32_t r, uint32_t *splitter_ids,
                         void *stream);
 
+/* Workspace bytes for ss_select_splitters_batch (a constant). */
+size_t ss_select_splitters_batch_workspace(void);
+
+/* Regular sampling of Section 3.1 applied to every set of a batch in one
+ * launch: set b is positions [set_off[b], set_off[b+1]) of perm (n_b strings),
+ * and splitter_ids[b*(r-1) + j-1] = perm[set_off[b] + ceil(j*n_b/r) - 1] for
+ * j = 1..r-1.  perm (in, n), set_off (in, num_sets+1), splitter_ids (out,
+ * num_sets*(r-1)).  INVALID_ARG if a set is empty or set_off is not increasing
+ * from 0 to n (checked on the device, so the call synchronises the stream;
+ * the samples of a bad set are 0xFFFFFFFF). */
+int ss_select_splitters_batch(const uint32_t *perm, uint64_t n, const uint64_t *set_off, uint32_t num_sets,
+                              uint32_t r, uint32_t *splitter_ids, void *ws, size_t ws_bytes, void *stream);
+
 /* Workspace bytes for ss_gather_strings of m strings. */
 size_t ss_gather_workspace(uint64_t m);
 

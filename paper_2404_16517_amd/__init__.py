@@ -50,6 +50,8 @@ def lib():
             "ss_dist_prefix": ([P, U64, P, U64, U32, U32, P, P, P, SZ, P], I32),
             "ss_prefix_keys": ([P, U64, P, U64, U32, U32, P, P], I32),
             "ss_select_splitters": ([U64, P, U32, P, P], I32),
+            "ss_select_splitters_batch_workspace": ([], SZ),
+            "ss_select_splitters_batch": ([P, U64, P, U32, U32, P, P, SZ, P], I32),
             "ss_gather_workspace": ([U64], SZ),
             "ss_gather_strings": ([P, U64, P, U64, P, U64, P, P, U64, P, SZ, P], I32),
             "ss_bucket_bounds": ([P, U64, P, U64, P, P, U64, P, U32, P, P], I32),
@@ -194,6 +196,18 @@ def select_splitters(perm: torch.Tensor, r: int):
     n = perm.numel()
     ids = _u32(max(r - 1, 0), perm.device)
     _check(lib().ss_select_splitters(n, _p(perm.contiguous()), r, _p(ids), _stream(perm.device)))
+    return ids
+
+
+def select_splitters_batch(perm: torch.Tensor, set_off: torch.Tensor, r: int):
+    """Regular samples of every set of a batch; (num_sets * (r-1),) uint32."""
+    n = perm.numel()
+    so = set_off.to(device=perm.device, dtype=torch.int64).contiguous()
+    k = max(so.numel() - 1, 0)
+    ids = _u32(max(k * (r - 1), 0), perm.device)
+    ws = _ws(lib().ss_select_splitters_batch_workspace(), perm.device)
+    _check(lib().ss_select_splitters_batch(_p(perm.contiguous()), n, _p(so), k, r, _p(ids),
+                                           _p(ws), ws.numel(), _stream(perm.device)))
     return ids
 
 

@@ -371,6 +371,7 @@ __global__ __launch_bounds__(256) void k_dedup(const u64 *keys, int kin, const u
             u32 s = tab_slot(key, logT);
             for (u32 probe = 0; probe <= mask; probe++, s = (s + 1) & mask) {
                 const u64 v = tab[s];
+                if (v == TAB_EMPTY) break;  // not in the table (cannot happen for an inserted key)
                 if ((v & ~TAB_DUP) == key) {
                     dup = (v & TAB_DUP) != 0;
                     break;

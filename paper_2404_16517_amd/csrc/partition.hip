@@ -30,6 +30,66 @@ extern "C" int ss_select_splitters(uint64_t n, const uint32_t *perm, uint32_t r,
     return SS_OK;
 }
 
+// The same sampling applied to every set b of a batch (set b = positions
+// [set_off[b], set_off[b+1]) of perm): one thread per (set, j).  Thread j = 1
+// of each set also checks that the set is non-empty and well placed; a bad set
+// raises *bad and its samples are written as 0xFFFFFFFF without reading perm.
+__global__ void k_select_batch(const u32 *perm, u64 n, const u64 *set_off, u32 num_sets, u32 r, u32 *ids,
+                               u32 *bad)
+{
+    const u64 t = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    const u32 per = r - 1;
+    if (t >= (u64)num_sets * per) return;
+    const u32 b = (u32)(t / per);
+    const u32 j = (u32)(t - (u64)b * per) + 1;
+    const u64 lo = set_off[b], hi = set_off[b + 1];
+    const bool ok = lo < hi && hi <= n;
+    if (j == 1 && (!ok || (b == 0 && lo != 0) || (b == num_sets - 1 && hi != n))) atomicOr(bad, 1u);
+    u32 v = 0xFFFFFFFFu;
+    if (ok) {
+        const u64 m = hi - lo;
+        v = perm[lo + ((u64)j * m + r - 1) / r - 1];
+    }
+    ids[t] = v;
+}
+
+extern "C" size_t ss_select_splitters_batch_workspace(void) { return 256; }
+
+extern "C" int ss_select_splitters_batch(const uint32_t *perm, uint64_t n, const uint64_t *set_off,
+                                         uint32_t num_sets, uint32_t r, uint32_t *splitter_ids, void *ws,
+                                         size_t ws_bytes, void *stream)
+{
+    ss_clear_error();
+    if (n == 0 || r == 0 || num_sets == 0 || !perm || !set_off || (r > 1 && !splitter_ids)) {
+        ss_set_error("select_splitters_batch needs n >= 1, r >= 1, num_sets >= 1 and non-null arrays");
+        return SS_ERR_INVALID_ARG;
+    }
+    if ((u64)num_sets * (r - 1) >= 0xFFFFFFFFull) {
+        ss_set_error("num_sets * (r - 1) too large");
+        return SS_ERR_TOO_LARGE;
+    }
+    if (r == 1) return SS_OK;
+    if (!ws || ws_bytes < sizeof(u32)) {
+        ss_set_error("workspace too small: need %zu bytes", ss_select_splitters_batch_workspace());
+        return SS_ERR_WORKSPACE;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    u32 *bad = (u32 *)ws;
+    SS_HIP(hipMemsetAsync(bad, 0, sizeof(u32), st));
+    const u64 total = (u64)num_sets * (r - 1);
+    k_select_batch<<<(unsigned)ceil_div(total, 256), 256, 0, st>>>(perm, n, set_off, num_sets, r, splitter_ids,
+                                                                   bad);
+    SS_CHECK_LAUNCH();
+    u32 h;
+    SS_TRY(ss_read_u32(bad, &h, 1, st));
+    if (h) {
+        ss_set_error("every set must be non-empty, with set_off[0] = 0, set_off[num_sets] = n and "
+                     "set_off increasing");
+        return SS_ERR_INVALID_ARG;
+    }
+    return SS_OK;
+}
+
 // ---------------------------------------------------------------- gather
 
 __global__ void k_gather_lens(const u64 *off, const u32 *ids, u32 m, u64 *out)

@@ -279,6 +279,32 @@ def test_partition_encode_unaligned_suf_base(base):
     np.testing.assert_array_equal(u64(fc2["suf_off"]).astype(np.int64) - base, u64(fc["suf_off"]).astype(np.int64))
 
 
+@pytest.mark.parametrize("r", [1, 2, 3, 17, 300])
+def test_select_splitters_batch_matches_per_set(r):
+    """One launch samples every set: same ids as regular sampling of each set
+    on its own (ragged set sizes, sets smaller than r included)."""
+    rng = np.random.default_rng(r)
+    sizes = np.concatenate([[1, 2, 5, 16, 17], rng.integers(1, 5000, 40), [70_001]])
+    set_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(set_off[-1])
+    perm = rng.integers(0, 2**32 - 1, n, dtype=np.uint32)
+    _log(f"[select_batch] r={r} sets={len(sizes)} n={n}")
+    ids = ss.select_splitters_batch(torch.from_numpy(perm.view(np.int32)).to(DEV),
+                                    torch.from_numpy(set_off).to(DEV), r)
+    ref = [oracle.select_splitters(int(b - a), perm[a:b], r) for a, b in zip(set_off[:-1], set_off[1:])]
+    ref = np.concatenate(ref) if r > 1 else np.zeros(0, np.uint32)
+    np.testing.assert_array_equal(u32(ids), ref)
+
+
+def test_select_splitters_batch_rejects_empty_and_malformed_sets():
+    perm = torch.arange(6, dtype=torch.int32, device=DEV)
+    for bad in ([0, 0, 6], [0, 3, 3, 6], [0, 4, 2, 6], [0, 3, 5], [1, 3, 6], [0, 3, 7]):
+        with pytest.raises(ss.StrsortError):
+            ss.select_splitters_batch(perm, torch.tensor(bad, device=DEV), 4)
+    ok = ss.select_splitters_batch(perm, torch.tensor([0, 2, 6], device=DEV), 2)
+    assert list(u32(ok)) == [0, 3]
+
+
 def _check_partition(s, r, pdms):
     _log(f"[partition] n={s.n} r={r} pdms={pdms}")
     g, perm, lcp, dist, ids, sb, so, fc = _partition(s, r, pdms)
