@@ -43,9 +43,6 @@ class Pipeline:
         self.n = n
         self.bounds = [n * i // p for i in range(p + 1)]
         self.set_off = torch.tensor(self.bounds, dtype=torch.int64, device=dev)
-        # chunk start of every position (to turn PE-local indices into global ones)
-        sizes = torch.tensor([self.bounds[i + 1] - self.bounds[i] for i in range(p)], device=dev)
-        self.pos_base = torch.repeat_interleave(self.set_off[:-1].to(torch.int32), sizes)
         self.ws_sort = torch.empty(ss.lib().ss_sort_workspace(n), dtype=torch.uint8, device=dev)
         self.ws_pd = torch.empty(ss.lib().ss_dist_prefix_workspace(n), dtype=torch.uint8, device=dev)
         self.ws_merge = torch.empty(ss.lib().ss_lcp_merge_workspace(n, n, p * p), dtype=torch.uint8, device=dev)
@@ -59,8 +56,7 @@ class Pipeline:
         dpx, rounds = ss.dist_prefix(B, O, 8, 64, ws=self.ws_pd)
         ev("dist_prefix")
         # 2. every PE sorts its array (+ LCP), one batched launch sequence
-        perm_l, lcp = ss.sort_batch(B, O, self.set_off, ws=self.ws_sort)
-        perm = perm_l + self.pos_base
+        perm, lcp = ss.sort_batch(B, O, self.set_off, ws=self.ws_sort, global_ids=True)
         ev("sort_batch+lcp")
         # 3. regular sampling (v+1 samples per PE) and splitters
         samp = ss.select_splitters_batch(perm, self.set_off, self.v + 2)
@@ -78,16 +74,10 @@ class Pipeline:
         run_begin = ro[:, :-1].t().reshape(-1)                          # group j = bucket j, run i = PE i
         run_end = ro[:, 1:].t().reshape(-1)
         src, order, mlcp = ss.lcp_merge(run_begin, run_end, self.group_off, fc["lcp"], fc["len"], fc["id"],
-                                        fc["suf_off"], fc["suf"], ws=self.ws_merge)
+                                        fc["suf_off"], fc["suf"], ws=self.ws_merge, n_out=self.n)
         ev("lcp_merge")
         # 6. LCPs across bucket boundaries, exact distinguishing prefixes
-        sizes = (run_end - run_begin).view(p, p).sum(1)
-        starts = torch.cumsum(sizes, 0)[:-1]
-        starts = starts[(starts > 0) & (starts < self.n)]
-        if starts.numel():
-            pairs = torch.stack([order[starts - 1], order[starts]], 1).reshape(-1).contiguous()
-            pl = ss.lcp(B, O, pairs)
-            mlcp[starts] = pl.view(-1, 2)[:, 1]
+        ss.join_group_lcps(B, O, order, mlcp, run_begin, run_end, self.group_off)
         dist = ss.dist_exact(O, order, mlcp)
         ev("dist_exact")
         return order, mlcp, dist, dpx, rounds

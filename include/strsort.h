@@ -77,14 +77,18 @@ int ss_sort(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t 
  * processing element sorts its own array in Section 3).  set_off (device,
  * num_sets+1 entries, non-decreasing, set_off[0] = 0, set_off[num_sets] = n)
  * gives the string-index bounds of each set within one string array.
- *   perm_local[i] (out, n)  index WITHIN its set of the string at position i
- *                           of that set's sorted order (positions are global).
- *   lcp[i] (out, n)         LCP array of each set (0 at each set start); may be NULL.
+ *   perm[i] (out, n)  the string at position i of its set's sorted order
+ *                     (positions are global): its index WITHIN the set, or,
+ *                     with SS_BATCH_GLOBAL_IDS in flags, its index in the
+ *                     whole string array.
+ *   lcp[i] (out, n)   LCP array of each set (0 at each set start); may be NULL.
  * Uses the ss_sort workspace for n.  INVALID_ARG if set_off is malformed
- * (checked on the device; the call reads one word back). */
+ * (checked on the device; the call reads one word back) or flags has an
+ * unknown bit. */
+#define SS_BATCH_GLOBAL_IDS 1u
 int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
-                  const uint64_t *set_off, uint32_t num_sets, uint32_t *perm_local,
-                  uint32_t *lcp, void *ws, size_t ws_bytes, void *stream);
+                  const uint64_t *set_off, uint32_t num_sets, uint32_t *perm, uint32_t *lcp,
+                  uint32_t flags, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------- LCP and dist */
 
@@ -93,6 +97,17 @@ int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uin
  * values of perm index the string array (which may hold more than n strings). */
 int ss_lcp(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
            const uint32_t *perm, uint32_t *lcp, void *stream);
+
+/* LCPs across group boundaries of a multi-group merge (Section 3: the merged
+ * buckets, concatenated in bucket order, form the sorted output).  The groups
+ * and runs are those given to ss_lcp_merge (run_begin, run_end: k entries;
+ * group_off: groups+1 entries; all device), order = its out_id (n_out), lcp =
+ * its out_lcp (in/out, n_out).  For every non-empty group g >= 1 whose first
+ * output position G is > 0: lcp[G] = lcp(s_order[G-1], s_order[G]); nothing
+ * else changes.  The values of order index the string array. */
+int ss_join_group_lcps(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, const uint32_t *order,
+                       uint64_t n_out, uint32_t k, const uint64_t *run_begin, const uint64_t *run_end,
+                       uint32_t groups, const uint32_t *group_off, uint32_t *lcp, void *stream);
 
 /* Exact distinguishing prefix length (Section 2): the characters needed to
  * rank a string, dist(s) = min(len(s), 1 + max over t != s of lcp(s, t)),
@@ -164,10 +179,12 @@ size_t ss_gather_workspace(uint64_t m);
 
 /* Copy strings ids[0..m) of a string array into a new string array
  * (out_offsets: m+1 entries, out_offsets[0] = 0; out_bytes capacity out_cap).
- * Used to materialise splitter strings.  CAPACITY if out_cap is too small. */
+ * Used to materialise splitter strings.  *total_host (host, may be NULL)
+ * receives the byte total (the call reads it back).  CAPACITY if out_cap is
+ * too small: out_offsets and *total_host are then valid, no bytes are copied. */
 int ss_gather_strings(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
                       const uint32_t *ids, uint64_t m, uint64_t *out_offsets, uint8_t *out_bytes,
-                      uint64_t out_cap, void *ws, size_t ws_bytes, void *stream);
+                      uint64_t out_cap, uint64_t *total_host, void *ws, size_t ws_bytes, void *stream);
 
 /* Bucket boundaries for r-1 sorted splitters (Section 3, step 1:
  * B^j = { s : f_j < s <= f_{j+1} }, f_0 = -inf, f_r = +inf):
@@ -264,12 +281,14 @@ size_t ss_lcp_merge_workspace(uint64_t n_out, uint64_t n_fc, uint32_t k);
  *   out_lcp[i] = LCP with the previous string of the same group (0 for the
  *                group's first).
  * Equal strings keep (run, position) order.  The runs are read in place; no
- * decoded copy is made. */
+ * decoded copy is made.  out_cap is the capacity of each output array
+ * (CAPACITY if n_out exceeds it); *n_out_host (host, may be NULL) receives
+ * n_out.  The call reads the run bounds back (it synchronises the stream). */
 int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_t *run_end, uint32_t groups,
                  const uint32_t *group_off, uint64_t n_fc, const uint32_t *fc_lcp,
                  const uint32_t *fc_len, const uint32_t *fc_id, const uint64_t *suf_off,
                  const uint8_t *suf, uint64_t *out_src, uint32_t *out_id, uint32_t *out_lcp,
-                 void *ws, size_t ws_bytes, void *stream);
+                 uint64_t out_cap, uint64_t *n_out_host, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------ profiling */
 

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libstrsort.so")
 
 SS_TUNE_SMALL_MAX = 1
 SS_TUNE_TILE = 2
+SS_ERR_CAPACITY = -5
 
 
 class StrsortError(RuntimeError):
@@ -43,7 +44,7 @@ def lib():
             "ss_version": ([], I32),
             "ss_sort_workspace": ([U64], SZ),
             "ss_sort": ([P, U64, P, U64, P, P, P, SZ, P], I32),
-            "ss_sort_batch": ([P, U64, P, U64, P, U32, P, P, P, SZ, P], I32),
+            "ss_sort_batch": ([P, U64, P, U64, P, U32, P, P, U32, P, SZ, P], I32),
             "ss_lcp": ([P, U64, P, U64, P, P, P], I32),
             "ss_dist_exact": ([P, U64, P, P, P, P], I32),
             "ss_dist_prefix_workspace": ([U64], SZ),
@@ -53,7 +54,7 @@ def lib():
             "ss_select_splitters_batch_workspace": ([], SZ),
             "ss_select_splitters_batch": ([P, U64, P, U32, U32, P, P, SZ, P], I32),
             "ss_gather_workspace": ([U64], SZ),
-            "ss_gather_strings": ([P, U64, P, U64, P, U64, P, P, U64, P, SZ, P], I32),
+            "ss_gather_strings": ([P, U64, P, U64, P, U64, P, P, U64, P, P, SZ, P], I32),
             "ss_bucket_bounds": ([P, U64, P, U64, P, P, U64, P, U32, P, P], I32),
             "ss_partition_encode_workspace": ([U64], SZ),
             "ss_partition_encode": ([P, U64, P, U64, P, P, P, P, U64, P, U32, P, P, P, P, P, P, U64, U64, P, P, SZ,
@@ -66,7 +67,8 @@ def lib():
             "ss_profile_names": ([ctypes.c_char_p, SZ], SZ),
             "ss_fc_decode": ([U32, P, P, P, P, P, U64, P, P, U64, P, SZ, P], I32),
             "ss_lcp_merge_workspace": ([U64, U64, U32], SZ),
-            "ss_lcp_merge": ([U32, P, P, U32, P, U64, P, P, P, P, P, P, P, P, P, SZ, P], I32),
+            "ss_lcp_merge": ([U32, P, P, U32, P, U64, P, P, P, P, P, P, P, P, U64, P, P, SZ, P], I32),
+            "ss_join_group_lcps": ([P, U64, P, P, U64, U32, P, P, U32, P, P, P], I32),
             "ss_set_tuning": ([I32, I32], I32),
         }
         for name, (args, res) in sig.items():
@@ -133,9 +135,13 @@ def sort(bytes_, offsets, with_lcp: bool = True, ws: torch.Tensor | None = None)
     return perm, lcp
 
 
-def sort_batch(bytes_, offsets, set_off: torch.Tensor, with_lcp: bool = True, ws=None):
+SS_BATCH_GLOBAL_IDS = 1
+
+
+def sort_batch(bytes_, offsets, set_off: torch.Tensor, with_lcp: bool = True, ws=None, global_ids: bool = False):
     """Independent sorts of the sets [set_off[j], set_off[j+1]) in one launch sequence.
-    Returns (perm_local int32[n], lcp int32[n] or None)."""
+    Returns (perm int32[n], lcp int32[n] or None); perm holds indices within
+    each set, or indices of the whole array with ``global_ids``."""
     b, o, n = _dev_strings(bytes_, offsets)
     dev = b.device
     so = set_off.to(device=dev, dtype=torch.int64).contiguous()
@@ -144,8 +150,8 @@ def sort_batch(bytes_, offsets, set_off: torch.Tensor, with_lcp: bool = True, ws
     need = lib().ss_sort_workspace(n)
     if ws is None or ws.numel() < need:
         ws = _ws(need, dev)
-    _check(lib().ss_sort_batch(_p(b), b.numel(), _p(o), n, _p(so), so.numel() - 1, _p(perm), _p(lcp), _p(ws),
-                               ws.numel(), _stream(dev)))
+    _check(lib().ss_sort_batch(_p(b), b.numel(), _p(o), n, _p(so), so.numel() - 1, _p(perm), _p(lcp),
+                               SS_BATCH_GLOBAL_IDS if global_ids else 0, _p(ws), ws.numel(), _stream(dev)))
     return perm, lcp
 
 
@@ -211,18 +217,27 @@ def select_splitters_batch(perm: torch.Tensor, set_off: torch.Tensor, r: int):
     return ids
 
 
-def gather_strings(bytes_, offsets, ids: torch.Tensor):
+def gather_strings(bytes_, offsets, ids: torch.Tensor, cap_hint: int | None = None):
+    """Strings ids[0..m) as a new string array (bytes, offsets).  The byte
+    buffer starts at ``cap_hint`` bytes (default 1 KiB per string) and is
+    regrown once to the exact total if that is too small."""
     b, o, n = _dev_strings(bytes_, offsets)
     dev = b.device
     m = ids.numel()
     out_off = torch.empty(m + 1, dtype=torch.int64, device=dev)
-    lens = (o[1:] - o[:-1])
-    cap = int(lens.max()) * m if (m and n) else 0
-    out = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
     ws = _ws(lib().ss_gather_workspace(m), dev)
-    _check(lib().ss_gather_strings(_p(b), b.numel(), _p(o), n, _p(ids.contiguous()), m, _p(out_off), _p(out),
-                                   cap, _p(ws), ws.numel(), _stream(dev)))
-    return out[:int(out_off[-1])], out_off
+    idc = ids.contiguous()
+    cap = int(cap_hint) if cap_hint is not None else 1024 * m
+    total = ctypes.c_uint64(0)
+    for _ in range(2):
+        out = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
+        rc = lib().ss_gather_strings(_p(b), b.numel(), _p(o), n, _p(idc), m, _p(out_off), _p(out), cap,
+                                     ctypes.byref(total), _p(ws), ws.numel(), _stream(dev))
+        if rc != SS_ERR_CAPACITY:
+            break
+        cap = int(total.value)
+    _check(rc)
+    return out[:int(total.value)], out_off
 
 
 def bucket_bounds(bytes_, offsets, perm, spl_bytes, spl_offsets):
@@ -330,10 +345,11 @@ def fc_decode(run_off, fc_lcp, fc_len, suf_off, suf):
     return out[:total], out_off
 
 
-def lcp_merge(run_begin, run_end, group_off, fc_lcp, fc_len, fc_id, suf_off, suf, ws=None):
+def lcp_merge(run_begin, run_end, group_off, fc_lcp, fc_len, fc_id, suf_off, suf, ws=None, n_out=None):
     """LCP-aware merge of the runs [run_begin[j], run_end[j]) of shared
     front-coded arrays, one merged sequence per group of runs
-    (group g = runs group_off[g]..group_off[g+1]-1).
+    (group g = runs group_off[g]..group_off[g+1]-1).  ``n_out`` (the total run
+    size), when the caller knows it, saves computing it here.
     Returns (src int64[n_out], id int32[n_out], lcp int32[n_out])."""
     dev = fc_lcp.device
     n_fc = fc_lcp.numel()
@@ -341,15 +357,35 @@ def lcp_merge(run_begin, run_end, group_off, fc_lcp, fc_len, fc_id, suf_off, suf
     re_ = run_end.to(device=dev, dtype=torch.int64).contiguous()
     go = group_off.to(device=dev, dtype=torch.int32).contiguous()
     k = rb.numel()
-    n_out = int((re_ - rb).sum()) if k else 0
+    if n_out is None:
+        n_out = int((re_ - rb).sum()) if k else 0
     need = lib().ss_lcp_merge_workspace(n_out, n_fc, k)
     if ws is None or ws.numel() < need:
         ws = _ws(need, dev)
     src = torch.empty(max(n_out, 0), dtype=torch.int64, device=dev)
     idv, lc = _u32(n_out, dev), _u32(n_out, dev)
+    got = ctypes.c_uint64(0)
     _check(lib().ss_lcp_merge(k, _p(rb), _p(re_), go.numel() - 1, _p(go), n_fc, _p(fc_lcp), _p(fc_len), _p(fc_id),
-                              _p(suf_off), _p(suf), _p(src), _p(idv), _p(lc), _p(ws), ws.numel(), _stream(dev)))
+                              _p(suf_off), _p(suf), _p(src), _p(idv), _p(lc), n_out, ctypes.byref(got), _p(ws),
+                              ws.numel(), _stream(dev)))
+    if got.value != n_out:
+        raise StrsortError(f"runs hold {got.value} entries, n_out = {n_out}")
     return src, idv, lc
+
+
+def join_group_lcps(bytes_, offsets, order, lcp_, run_begin, run_end, group_off):
+    """Set lcp_ (in place) at the first position of every merged group to the
+    LCP with the last string of the groups before it."""
+    b, o, _ = _dev_strings(bytes_, offsets)
+    dev = b.device
+    rb = run_begin.to(device=dev, dtype=torch.int64).contiguous()
+    re_ = run_end.to(device=dev, dtype=torch.int64).contiguous()
+    go = group_off.to(device=dev, dtype=torch.int32).contiguous()
+    if not lcp_.is_contiguous() or lcp_.numel() != order.numel():
+        raise StrsortError("lcp must be contiguous and sized like order")
+    _check(lib().ss_join_group_lcps(_p(b), b.numel(), _p(o), _p(order.contiguous()), order.numel(), rb.numel(),
+                                    _p(rb), _p(re_), go.numel() - 1, _p(go), _p(lcp_), _stream(dev)))
+    return lcp_
 
 
 def lcp_merge_runs(run_off, fc_lcp, fc_len, fc_id, suf_off, suf, ws=None):

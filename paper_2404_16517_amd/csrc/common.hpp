@@ -200,6 +200,39 @@ __device__ __forceinline__ int str_cmp_from(const u8 *__restrict__ ba, u64 Na, u
     return la < lb ? -1 : (la > lb ? 1 : 0);
 }
 
+// Three-way comparison of strings a and b of one buffer by a whole wavefront:
+// lane l holds bytes [512c + 8l, 512c + 8l + 8) of round c, so one round
+// covers 512 bytes.  The lowest lane that sees a difference or the end of the
+// shorter string decides.  Every lane gets the result and the LCP.  Must be
+// called by all 64 lanes with the same arguments.
+__device__ __forceinline__ int wave_str_cmp(const u8 *__restrict__ bytes, u64 N, u64 oa, u64 la, u64 ob,
+                                            u64 lb, u64 *lcp_out)
+{
+    const u64 m = la < lb ? la : lb;
+    const u32 lane = __lane_id();
+    for (u64 c = 0;; c += 512) {
+        const u64 q = c + 8ull * lane;
+        const u32 take = q < m ? (m - q < 8 ? (u32)(m - q) : 8u) : 0u;
+        const u64 wa = load_be(bytes, N, oa + q, take);
+        const u64 wb = load_be(bytes, N, ob + q, take);
+        const u64 stop = __ballot(wa != wb || take < 8);
+        if (stop) {
+            const int src = __ffsll((unsigned long long)stop) - 1;
+            u64 l;
+            int r;
+            if (wa != wb) {
+                l = q + (__clzll(wa ^ wb) >> 3);
+                r = wa < wb ? -1 : 1;
+            } else {
+                l = q + take;
+                r = la < lb ? -1 : (la > lb ? 1 : 0);
+            }
+            *lcp_out = __shfl(l, src);
+            return __shfl(r, src);
+        }
+    }
+}
+
 // Binary search: number of entries of the sorted array a[0..n) that are <= x.
 template <class T>
 __device__ __forceinline__ u64 upper_bound_dev(const T *a, u64 n, T x)

@@ -16,6 +16,58 @@ __global__ __launch_bounds__(256) void k_lcp(const u8 *bytes, u64 N, const u64 *
     lcp[i] = (u32)str_lcp_from(bytes, N, oa, la, ob, lb, 0);
 }
 
+// Wave-wide sum of a 64-bit value (every lane gets it).
+__device__ __forceinline__ u64 wave_sum_u64(u64 v)
+{
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
+    return v;
+}
+
+// One wavefront per group g >= 1: the group's first output position G is the
+// total size of the runs of groups before it; if the group is not empty and
+// G > 0, lcp[G] becomes the LCP of the strings at output positions G-1 and G.
+__global__ __launch_bounds__(256) void k_join_groups(const u8 *bytes, u64 N, const u64 *off, const u32 *order,
+                                                     u64 n_out, u32 k, const u64 *rb, const u64 *re,
+                                                     u32 groups, const u32 *go, u32 *lcp)
+{
+    const u32 g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const u32 lane = threadIdx.x & 63;
+    if (g == 0 || g >= groups) return;  // uniform over the wavefront
+    const u32 r1 = go[g + 1] < k ? go[g + 1] : k;
+    const u32 r0 = go[g] < r1 ? go[g] : r1;
+    u64 before = 0, own = 0;
+    for (u32 r = lane; r < r1; r += 64) {
+        const u64 sz = re[r] - rb[r];
+        if (r < r0) before += sz;
+        else own += sz;
+    }
+    before = wave_sum_u64(before);
+    own = wave_sum_u64(own);
+    if (own == 0 || before == 0 || before >= n_out) return;
+    const u32 a = order[before - 1], b = order[before];
+    const u64 oa = off[a], ob = off[b];
+    u64 l;
+    wave_str_cmp(bytes, N, oa, off[a + 1] - oa, ob, off[b + 1] - ob, &l);
+    if (lane == 0) lcp[before] = (u32)l;
+}
+
+extern "C" int ss_join_group_lcps(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, const uint32_t *order,
+                                  uint64_t n_out, uint32_t k, const uint64_t *run_begin, const uint64_t *run_end,
+                                  uint32_t groups, const uint32_t *group_off, uint32_t *lcp, void *stream)
+{
+    ss_clear_error();
+    if (groups == 0 || k == 0 || !offsets || !run_begin || !run_end || !group_off || (n_out > 0 && (!order || !lcp))) {
+        ss_set_error("join_group_lcps needs groups >= 1, k >= 1 and non-null arrays");
+        return SS_ERR_INVALID_ARG;
+    }
+    if (groups < 2 || n_out == 0) return SS_OK;
+    hipStream_t st = (hipStream_t)stream;
+    k_join_groups<<<(unsigned)ceil_div(groups, 4), 256, 0, st>>>(bytes, N, offsets, order, n_out, k, run_begin,
+                                                                 run_end, groups, group_off, lcp);
+    SS_CHECK_LAUNCH();
+    return SS_OK;
+}
+
 // dist of the string at sorted position i = min(len, 1 + max(lcp[i], lcp[i+1])),
 // lcp[n] := 0; written at its input index.
 __global__ __launch_bounds__(256) void k_dist_exact(const u64 *off, u32 n, const u32 *perm,

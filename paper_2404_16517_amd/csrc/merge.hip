@@ -996,6 +996,23 @@ __global__ void k_merge_out(const u32 *G, const u32 *L, u32 n_out, const u64 *sb
     lcp[x] = L[x];
 }
 
+// Host-plan header: [0] check flag, [1] literal-buffer size, [2, 2+k) run
+// begins, [2+k, 2+2k) run ends, then the group offsets as packed u32.
+__global__ __launch_bounds__(256) void k_merge_header(const u64 *rb, const u64 *re, u32 k, const u32 *go,
+                                                      u32 groups, const u32 *bad, const u64 *sufN, u64 *H)
+{
+    const u64 t = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        H[0] = bad ? *bad : 0u;
+        H[1] = sufN ? *sufN : 0ull;
+    }
+    if (t < k) {
+        H[2 + t] = rb[t];
+        H[2 + k + t] = re[t];
+    }
+    if (t <= groups) ((u32 *)(H + 2 + 2 * (u64)k))[t] = go[t];
+}
+
 __global__ __launch_bounds__(256) void k_check_merge_runs(const u64 *rb, const u64 *re, u32 k, u64 n_fc,
                                                           const u32 *e, const u32 *d, u32 *bad)
 {
@@ -1053,7 +1070,8 @@ extern "C" size_t ss_lcp_merge_workspace(uint64_t n_out, uint64_t n_fc, uint32_t
 extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_t *run_end, uint32_t groups,
                             const uint32_t *group_off, uint64_t n_fc, const uint32_t *fc_lcp, const uint32_t *fc_len,
                             const uint32_t *fc_id, const uint64_t *suf_off, const uint8_t *suf, uint64_t *out_src,
-                            uint32_t *out_id, uint32_t *out_lcp, void *ws, size_t ws_bytes, void *stream)
+                            uint32_t *out_id, uint32_t *out_lcp, uint64_t out_cap, uint64_t *n_out_host, void *ws,
+                            size_t ws_bytes, void *stream)
 {
     ss_clear_error();
     if (n_fc >= 0xFFFFFFFFull) { ss_set_error("n_fc too large"); return SS_ERR_TOO_LARGE; }
@@ -1062,12 +1080,58 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
         return SS_ERR_INVALID_ARG;
     }
     hipStream_t st = (hipStream_t)stream;
+    // The format check of the front-coded runs runs on the device before the
+    // run bounds are known on the host, so that one read-back serves both.
+    // Its flag lives in the decoding part of the workspace, whose placement
+    // depends on n_fc only.
+    WsArena a0(ws, ws_bytes);
+    DecWs d0;
+    dec_layout(n_fc, &d0, &a0, nullptr);
+    if (a0.overflow || !ws) {
+        ss_set_error("workspace too small for %llu front-coded entries", (unsigned long long)n_fc);
+        return SS_ERR_WORKSPACE;
+    }
+    const bool have_fc = fc_lcp && fc_len && fc_id && suf_off;
+    if (have_fc) {
+        SS_HIP(hipMemsetAsync(d0.bad, 0, sizeof(u32), st));
+        k_check_merge_runs<<<(unsigned)ceil_div((n_fc > k ? n_fc : k) + 1, 256), 256, 0, st>>>(
+            run_begin, run_end, k, n_fc, fc_lcp, fc_len, d0.bad);
+        SS_CHECK_LAUNCH();
+    }
+    // Everything the host plan needs, packed on the device into one staging
+    // array (after the decoding part of the workspace; the merge arrays reuse
+    // that space later) and brought back by one copy.
     std::vector<u64> rb(k), re(k);
     std::vector<u32> go(groups + 1);
-    SS_HIP(hipMemcpyAsync(rb.data(), run_begin, sizeof(u64) * k, hipMemcpyDeviceToHost, st));
-    SS_HIP(hipMemcpyAsync(re.data(), run_end, sizeof(u64) * k, hipMemcpyDeviceToHost, st));
-    SS_HIP(hipMemcpyAsync(go.data(), group_off, sizeof(u32) * (groups + 1), hipMemcpyDeviceToHost, st));
-    SS_HIP(hipStreamSynchronize(st));
+    const u64 hdr = 2 + 2 * (u64)k + ((u64)groups + 2) / 2;
+    u64 *stage = a0.take<u64>(hdr);
+    std::vector<u64> H(hdr);
+    if (stage) {
+        const u64 nt = (u64)k > (u64)groups + 1 ? (u64)k : (u64)groups + 1;
+        k_merge_header<<<(unsigned)ceil_div(nt, 256), 256, 0, st>>>(run_begin, run_end, k, group_off, groups,
+                                                                    have_fc ? d0.bad : nullptr,
+                                                                    have_fc ? suf_off + n_fc : nullptr, stage);
+        SS_CHECK_LAUNCH();
+        SS_HIP(hipMemcpyAsync(H.data(), stage, sizeof(u64) * hdr, hipMemcpyDeviceToHost, st));
+        SS_HIP(hipStreamSynchronize(st));
+        memcpy(rb.data(), H.data() + 2, sizeof(u64) * k);
+        memcpy(re.data(), H.data() + 2 + k, sizeof(u64) * k);
+        memcpy(go.data(), H.data() + 2 + 2 * (u64)k, sizeof(u32) * (groups + 1));
+    } else {
+        H[0] = H[1] = 0;
+        u32 b32 = 0;
+        if (have_fc) {
+            SS_HIP(hipMemcpyAsync(&b32, d0.bad, sizeof(u32), hipMemcpyDeviceToHost, st));
+            SS_HIP(hipMemcpyAsync(&H[1], suf_off + n_fc, sizeof(u64), hipMemcpyDeviceToHost, st));
+        }
+        SS_HIP(hipMemcpyAsync(rb.data(), run_begin, sizeof(u64) * k, hipMemcpyDeviceToHost, st));
+        SS_HIP(hipMemcpyAsync(re.data(), run_end, sizeof(u64) * k, hipMemcpyDeviceToHost, st));
+        SS_HIP(hipMemcpyAsync(go.data(), group_off, sizeof(u32) * (groups + 1), hipMemcpyDeviceToHost, st));
+        SS_HIP(hipStreamSynchronize(st));
+        H[0] = b32;
+    }
+    const u32 bad = (u32)H[0];
+    const u64 sufN = H[1];
     if (go[0] != 0 || go[groups] != k) {
         ss_set_error("group_off must start at 0 and end at k");
         return SS_ERR_INVALID_ARG;
@@ -1087,9 +1151,20 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
             return SS_ERR_INVALID_ARG;
         }
     const u64 n_out = P[k];
+    if (n_out_host) *n_out_host = n_out;
     if (n_out == 0) return SS_OK;
-    if (!fc_lcp || !fc_len || !fc_id || !suf_off || !out_src || !out_id || !out_lcp) {
+    if (n_out > out_cap) {
+        ss_set_error("merge output has %llu entries, capacity %llu", (unsigned long long)n_out,
+                     (unsigned long long)out_cap);
+        return SS_ERR_CAPACITY;
+    }
+    if (!have_fc || !out_src || !out_id || !out_lcp) {
         ss_set_error("lcp_merge: null array");
+        return SS_ERR_INVALID_ARG;
+    }
+    if (bad) {
+        ss_set_error("malformed front-coded runs (code %u): runs must start with e = 0 and e_i <= d_i, "
+                     "e_i <= d_{i-1}", bad);
         return SS_ERR_INVALID_ARG;
     }
     // non-empty runs sorted by front-coded start, to map positions back to runs
@@ -1110,27 +1185,13 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
     WsArena a(ws, ws_bytes);
     MergeWs w;
     merge_layout(n_out, n_fc, k, &w, &a, nullptr);
-    if (a.overflow || !ws) {
+    if (a.overflow) {
         ss_set_error("workspace too small: need %zu bytes", ss_lcp_merge_workspace(n_out, n_fc, k));
         return SS_ERR_WORKSPACE;
     }
     SS_HIP(hipMemcpyAsync(w.P, P.data(), sizeof(u64) * (k + 1), hipMemcpyHostToDevice, st));
     SS_HIP(hipMemcpyAsync(w.sb, sbv.data(), sizeof(u64) * kne, hipMemcpyHostToDevice, st));
     SS_HIP(hipMemcpyAsync(w.sid, sidv.data(), sizeof(u32) * kne, hipMemcpyHostToDevice, st));
-    SS_HIP(hipMemsetAsync(w.dec.bad, 0, sizeof(u32), st));
-    k_check_merge_runs<<<(unsigned)ceil_div((n_fc > k ? n_fc : k) + 1, 256), 256, 0, st>>>(
-        run_begin, run_end, k, n_fc, fc_lcp, fc_len, w.dec.bad);
-    SS_CHECK_LAUNCH();
-    u32 bad;
-    u64 sufN;
-    SS_HIP(hipMemcpyAsync(&bad, w.dec.bad, sizeof(u32), hipMemcpyDeviceToHost, st));
-    SS_HIP(hipMemcpyAsync(&sufN, suf_off + n_fc, sizeof(u64), hipMemcpyDeviceToHost, st));
-    SS_HIP(hipStreamSynchronize(st));
-    if (bad) {
-        ss_set_error("malformed front-coded runs (code %u): runs must start with e = 0 and e_i <= d_i, "
-                     "e_i <= d_{i-1}", bad);
-        return SS_ERR_INVALID_ARG;
-    }
     // psv chains over the whole front-coded array (no decoding of the strings)
     SS_TRY(psv_build(fc_lcp, n_fc, w.dec.psv, w.dec.tree, w.dec.cmin, st));
     const FcView V{fc_lcp, fc_len, w.dec.psv, suf_off, suf, sufN};

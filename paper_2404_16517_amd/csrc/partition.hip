@@ -118,7 +118,7 @@ extern "C" size_t ss_gather_workspace(uint64_t m)
 
 extern "C" int ss_gather_strings(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
                                  const uint32_t *ids, uint64_t m, uint64_t *out_offsets, uint8_t *out_bytes,
-                                 uint64_t out_cap, void *ws, size_t ws_bytes, void *stream)
+                                 uint64_t out_cap, uint64_t *total_host, void *ws, size_t ws_bytes, void *stream)
 {
     ss_clear_error();
     (void)N; (void)n;
@@ -138,6 +138,7 @@ extern "C" int ss_gather_strings(const uint8_t *bytes, uint64_t N, const uint64_
     SS_TRY(ss_scan_exclusive<u64>(out_offsets, out_offsets, m, scratch, st));
     u64 total;
     SS_TRY(ss_read_u64(out_offsets + m, &total, 1, st));
+    if (total_host) *total_host = total;
     if (total > out_cap) {
         ss_set_error("gather needs %llu bytes, capacity %llu", (unsigned long long)total,
                      (unsigned long long)out_cap);

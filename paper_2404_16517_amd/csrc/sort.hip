@@ -131,6 +131,31 @@ __global__ void k_tile_counts(const Seg *segs, u32 nseg, u32 tile, u32 *out)
     if (j < nseg) out[j] = (segs[j].end - segs[j].begin + tile - 1) / tile;
 }
 
+// Tile counts of the active segments for a round; also resets the segments'
+// skip minima and (thread 0) the round counters.
+__global__ void k_round_tiles(const Seg *segs, u32 nseg, u32 tile, u32 *out, u32 *skipv, u32 *ctr)
+{
+    u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < C_NCTR) ctr[j] = 0;
+    if (j < nseg) {
+        out[j] = (segs[j].end - segs[j].begin + tile - 1) / tile;
+        skipv[j] = 0xFFFFFFFFu;
+    }
+}
+
+// Tile counts of the radix segments of a level; also resets their key minima
+// and maxima and (thread 0) the counters of the next level's radix list.
+__global__ void k_level_tiles(const Seg *segs, u32 nseg, u32 tile, u32 *out, u64 *smin, u64 *smax, u32 *ctr)
+{
+    u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0) { ctr[C_LARGE] = 0; ctr[C_LTILES] = 0; ctr[C_LELEM] = 0; }
+    if (j < nseg) {
+        out[j] = (segs[j].end - segs[j].begin + tile - 1) / tile;
+        smin[j] = ~0ull;
+        smax[j] = 0;
+    }
+}
+
 __global__ void k_sizes(const Seg *segs, u32 nseg, u32 *out)
 {
     u32 j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -912,10 +937,11 @@ int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
     u32 h[C_NCTR];
     u64 round_elems = J.n_first;
     while (nact > 0) {
-        SS_HIP(hipMemsetAsync(w.ctr, 0, sizeof(u32) * C_NCTR, st));
         {
-            SS_TRY(build_tiles(w.act, nact, ETILE, w.tstart, w.scan_scratch, st));
-            SS_HIP(hipMemsetAsync(w.skipv, 0xFF, sizeof(u32) * nact, st));
+            const u32 nt = nact > C_NCTR ? nact : C_NCTR;
+            k_round_tiles<<<(unsigned)ceil_div(nt, 256), 256, 0, st>>>(w.act, nact, ETILE, w.tstart, w.skipv, w.ctr);
+            SS_CHECK_LAUNCH();
+            SS_TRY(ss_scan_exclusive<u32>(w.tstart, w.tstart, nact, (u32 *)w.scan_scratch, st));
             {
                 // algorithmic bytes: perm + offsets + one word per string, its mismatch
                 // record out, plus the common prefix (added once the skips are known)
@@ -939,18 +965,16 @@ int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
         u32 nlarge = h[C_LARGE], ltiles = h[C_LTILES], lelem = h[C_LELEM];
         Seg *LA = w.largeA, *LB = w.largeB;
         while (nlarge > 0) {
-            SS_TRY(build_tiles(LA, nlarge, TL, w.tstart, w.scan_scratch, st));
-            SS_HIP(hipMemsetAsync(w.smin, 0xFF, sizeof(u64) * nlarge, st));
-            SS_HIP(hipMemsetAsync(w.smax, 0, sizeof(u64) * nlarge, st));
+            k_level_tiles<<<(unsigned)ceil_div(nlarge, 256), 256, 0, st>>>(LA, nlarge, TL, w.tstart, w.smin, w.smax,
+                                                                           w.ctr);
+            SS_CHECK_LAUNCH();
+            SS_TRY(ss_scan_exclusive<u32>(w.tstart, w.tstart, nlarge, (u32 *)w.scan_scratch, st));
             {
                 SS_PROF("k_hist", st, (double)lelem * 8.0);  // read the keys
                 k_hist<<<ltiles, NT, 0, st>>>(LA, w.tstart, nlarge, TL, w.keyA, w.hist, w.smin, w.smax);
             }
             SS_CHECK_LAUNCH();
             SS_TRY(ss_scan_exclusive<u32>(w.hist, w.hist, (u64)ltiles * 256, (u32 *)w.scan_scratch, st));
-            SS_HIP(hipMemsetAsync(w.ctr + C_LARGE, 0, sizeof(u32), st));
-            SS_HIP(hipMemsetAsync(w.ctr + C_LTILES, 0, sizeof(u32), st));
-            SS_HIP(hipMemsetAsync(w.ctr + C_LELEM, 0, sizeof(u32), st));
             EmitOut eo{w.tiny, w.small, LB, w.nxt, w.ident, w.bnd, w.ctr, w.scat, SM, TL};
             k_emit<<<(unsigned)ceil_div(nlarge, EPB), 256, 0, st>>>(LA, w.tstart, nlarge, w.hist, w.smin, w.smax,
                                                                      eo);
@@ -1079,6 +1103,41 @@ static int sort_common_checks(const uint8_t *bytes, const uint64_t *offsets, uin
     return SS_OK;
 }
 
+// Few strings (n <= RANK_MAX): one launch, no rounds.  Block i ranks string i
+// among all others, (string, index) order: rank = #{ j : s_j < s_i, or s_j =
+// s_i and j < i }.  The LCP with the predecessor in sorted order is the largest
+// LCP of s_i with any string ranked before it (LCPs along a sorted sequence
+// are range minima of the adjacent ones).
+#define RANK_MAX 256
+#define RANK_NT 512
+__global__ __launch_bounds__(RANK_NT) void k_rank_sort(const u8 *bytes, u64 N, const u64 *off, u32 n, u32 *perm,
+                                                       u32 *lcp)
+{
+    __shared__ u32 s_cnt[RANK_NT / 64], s_max[RANK_NT / 64];
+    const u32 i = blockIdx.x;
+    const u32 wv = threadIdx.x >> 6;
+    const u64 oi = off[i], li = off[i + 1] - oi;
+    u32 cnt = 0, mx = 0;
+    for (u32 j = wv; j < n; j += RANK_NT / 64) {
+        if (j == i) continue;  // uniform over the wavefront
+        const u64 oj = off[j], lj = off[j + 1] - oj;
+        u64 l;
+        const int c = wave_str_cmp(bytes, N, oj, lj, oi, li, &l);
+        if (c < 0 || (c == 0 && j < i)) {
+            cnt++;
+            if (l > mx) mx = (u32)l;
+        }
+    }
+    if ((threadIdx.x & 63) == 0) { s_cnt[wv] = cnt; s_max[wv] = mx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u32 r = 0, m = 0;
+        for (u32 w = 0; w < RANK_NT / 64; w++) { r += s_cnt[w]; m = s_max[w] > m ? s_max[w] : m; }
+        perm[r] = i;
+        if (lcp) lcp[r] = m;
+    }
+}
+
 extern "C" int ss_sort(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
                        uint32_t *perm, uint32_t *lcp, void *ws, size_t ws_bytes, void *stream)
 {
@@ -1092,6 +1151,11 @@ extern "C" int ss_sort(const uint8_t *bytes, uint64_t N, const uint64_t *offsets
     if (a.overflow || !ws) {
         ss_set_error("workspace too small: need %zu bytes", ss_sort_workspace(n));
         return SS_ERR_WORKSPACE;
+    }
+    if (n <= RANK_MAX) {
+        k_rank_sort<<<(unsigned)n, RANK_NT, 0, st>>>(bytes, N, offsets, (u32)n, perm, lcp);
+        SS_CHECK_LAUNCH();
+        return SS_OK;
     }
     SortJob J{bytes, N, offsets, perm, lcp ? lcp : w.lcp_scratch, st, n};
     k_iota<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(perm, (u32)n);
@@ -1126,12 +1190,16 @@ static int check_sets(const u64 *set_off, u32 num_sets, u64 n, u32 *scratch, hip
 
 extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
                              const uint64_t *set_off, uint32_t num_sets, uint32_t *perm_local,
-                             uint32_t *lcp, void *ws, size_t ws_bytes, void *stream)
+                             uint32_t *lcp, uint32_t flags, void *ws, size_t ws_bytes, void *stream)
 {
     ss_clear_error();
     SS_TRY(sort_common_checks(bytes, offsets, n, perm_local));
     if (num_sets == 0 || !set_off) {
         ss_set_error("batch needs num_sets >= 1 and set_off");
+        return SS_ERR_INVALID_ARG;
+    }
+    if (flags & ~SS_BATCH_GLOBAL_IDS) {
+        ss_set_error("unknown flags 0x%x", flags);
         return SS_ERR_INVALID_ARG;
     }
     if (n == 0) return SS_OK;
@@ -1154,7 +1222,9 @@ extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *o
     SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, st));
     J.n_first = h[C_NELEM];
     SS_TRY(sort_rounds(J, w, h[C_NEXT], h[C_NTILES]));
-    k_localize<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(set_off, num_sets, (u32)n, perm_local);
-    SS_CHECK_LAUNCH();
+    if (!(flags & SS_BATCH_GLOBAL_IDS)) {
+        k_localize<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(set_off, num_sets, (u32)n, perm_local);
+        SS_CHECK_LAUNCH();
+    }
     return SS_OK;
 }

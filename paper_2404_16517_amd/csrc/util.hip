@@ -67,12 +67,15 @@ int ss_read_u64(const u64 *dev, u64 *host, int count, hipStream_t s)
 
 // ---------------------------------------------------------------- scans
 //
-// Three phases: per-block sums, one-workgroup scan of the block sums, then a
-// per-block scan that adds the block's offset.  Blocks hold SCAN_ITEMS items.
+// Arrays of up to SCAN_ONE_MAX items: one workgroup, one launch.  Longer ones
+// take three phases: per-block sums, one-workgroup scan of the block sums,
+// then a per-block scan that adds the block's offset.  Blocks hold SCAN_ITEMS
+// items.
 
 #define SCAN_NT 256
 #define SCAN_PER 16
 #define SCAN_ITEMS (SCAN_NT * SCAN_PER)
+#define SCAN_ONE_MAX 16384  // arrays up to this length: one launch
 
 template <class T>
 __device__ __forceinline__ T wave_incl_scan(T x)
@@ -170,12 +173,36 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_apply(const T *in, T *out, u64
 
 template <class T> __global__ void k_zero_one(T *out) { out[0] = 0; }
 
+// Short arrays in one launch: thread t owns a contiguous chunk; every thread
+// reads its chunk before the block scan's barriers, so in == out is fine.
+template <class T>
+__global__ __launch_bounds__(1024) void k_scan_one(const T *in, T *out, u64 n)
+{
+    const u64 per = (n + 1023) / 1024;
+    const u64 c0 = threadIdx.x * per, c1 = (c0 + per < n) ? c0 + per : n;
+    T s = 0;
+    for (u64 i = c0; i < c1; i++) s += in[i];
+    T tot;
+    T pre = block_excl_scan<T, 1024>(s, &tot);
+    for (u64 i = c0; i < c1; i++) {
+        const T v = in[i];
+        out[i] = pre;
+        pre += v;
+    }
+    if (threadIdx.x == 0) out[n] = tot;
+}
+
 template <class T> u64 ss_scan_scratch_elems(u64 n) { return ceil_div(n, SCAN_ITEMS) + 1; }
 
 template <class T> int ss_scan_exclusive(const T *in, T *out, u64 n, T *scratch, hipStream_t s)
 {
     if (n == 0) {
         k_zero_one<T><<<1, 1, 0, s>>>(out);
+        SS_CHECK_LAUNCH();
+        return SS_OK;
+    }
+    if (n <= SCAN_ONE_MAX) {
+        k_scan_one<T><<<1, 1024, 0, s>>>(in, out, n);
         SS_CHECK_LAUNCH();
         return SS_OK;
     }

@@ -67,6 +67,10 @@ def _check_sort(s: synth.StringSet, name=""):
 def test_sort_lcp_dist_edge_sets(name):
     s = synth.from_list(EDGE_SETS[name])
     g, perm, lcp, b, o, p_ref = _check_sort(s, name)
+    # the same set through the round-based path (a one-set batch)
+    pb, lb = ss.sort_batch(g.bytes, g.offsets, torch.tensor([0, s.n], device=DEV))
+    np.testing.assert_array_equal(u32(pb), p_ref)
+    np.testing.assert_array_equal(u32(lb), u32(lcp))
     d = ss.dist_exact(g.offsets, perm, lcp)
     lcp_ref = oracle.lcp(b, o, p_ref)
     np.testing.assert_array_equal(u32(d), oracle.dist_exact(o, p_ref, lcp_ref))
@@ -97,6 +101,29 @@ def test_sort_segment_size_boundaries(seed):
     strs += strs[: len(strs) // 7]  # exact duplicates
     rng.shuffle(strs)
     _check_sort(synth.from_list(strs), f"size-boundaries seed={seed}")
+
+
+@pytest.mark.parametrize("n", [2, 3, 64, 200, 255, 256, 257])
+def test_sort_few_strings(n):
+    """Up to 256 strings take the one-launch rank sort: duplicates, empty
+    strings, prefixes of each other and common prefixes longer than one
+    512-byte comparison round."""
+    rng = random.Random(n)
+    strs = []
+    for i in range(n):
+        kind = i % 5
+        if kind == 0:
+            strs.append(b"")
+        elif kind == 1:
+            strs.append(b"L" * rng.choice([511, 512, 513, 700, 1030]) + bytes([rng.choice(b"AB")]))
+        elif kind == 2:
+            strs.append(b"L" * rng.randint(0, 40))
+        else:
+            strs.append(bytes(rng.choice(b"ABC") for _ in range(rng.randint(1, 10))))
+    strs += strs[: n // 9]
+    strs = strs[:n]
+    rng.shuffle(strs)
+    _check_sort(synth.from_list(strs), f"few n={n}")
 
 
 def test_sort_empty_input():
@@ -149,6 +176,16 @@ def test_sort_batch_equals_single_sorts():
         pr = oracle.sort(sub_b, sub_o)
         np.testing.assert_array_equal(P[a:e], pr)
         np.testing.assert_array_equal(Lc[a:e], oracle.lcp(sub_b, sub_o, pr))
+
+
+def test_sort_batch_global_ids():
+    sets, bounds = synth.random_sets(9, 1, 5000, seed=4)
+    g = sets.to(DEV)
+    pl, ll = ss.sort_batch(g.bytes, g.offsets, bounds.to(DEV))
+    pg, lg = ss.sort_batch(g.bytes, g.offsets, bounds.to(DEV), global_ids=True)
+    base = np.repeat(bounds[:-1].numpy(), (bounds[1:] - bounds[:-1]).numpy()).astype(np.uint32)
+    np.testing.assert_array_equal(u32(pg), u32(pl) + base)
+    np.testing.assert_array_equal(u32(lg), u32(ll))
 
 
 def test_sort_batch_rejects_malformed_sets():
@@ -303,6 +340,19 @@ def test_select_splitters_batch_rejects_empty_and_malformed_sets():
             ss.select_splitters_batch(perm, torch.tensor(bad, device=DEV), 4)
     ok = ss.select_splitters_batch(perm, torch.tensor([0, 2, 6], device=DEV), 2)
     assert list(u32(ok)) == [0, 3]
+
+
+@pytest.mark.parametrize("hint", [None, 0, 1, 37])
+def test_gather_strings_capacity_hint(hint):
+    """The byte buffer is regrown once when the hint is too small."""
+    s = synth.text_strings(5000, seed=14, median=30)
+    g = s.to(DEV)
+    ids = torch.tensor([4999, 0, 17, 17, 2500, 3], dtype=torch.int32, device=DEV)
+    gb, go = ss.gather_strings(g.bytes, g.offsets, ids, cap_hint=hint)
+    strs = s.as_list()
+    want = [strs[i] for i in ids.tolist()]
+    assert bytes(gb.cpu().numpy()) == b"".join(want)
+    np.testing.assert_array_equal(go.cpu().numpy(), np.cumsum([0] + [len(x) for x in want]))
 
 
 def _check_partition(s, r, pdms):
@@ -556,3 +606,62 @@ def test_partition_encode_batch_matches_oracle_per_set(pdms):
         np.testing.assert_array_equal(FI[a:e], ref["id"])
         np.testing.assert_array_equal(SO[a:e] - SO[a], ref["suf_off"][:e - a])
         assert bytes(SUF[int(SO[a]):int(SO[e])]) == bytes(ref["suf"])
+
+
+def _pipeline(sets, bounds, spl, pdms):
+    """The one-device form of the distributed sort: per-set sorts, common
+    splitters, bucket partition + front coding, one merge per bucket, LCPs
+    joined across buckets, exact distinguishing prefixes."""
+    g = sets.to(DEV)
+    so = bounds.to(DEV)
+    p = len(bounds) - 1
+    perm, lcp = ss.sort_batch(g.bytes, g.offsets, so, global_ids=True)
+    dist = ss.dist_prefix(g.bytes, g.offsets, 8, 64)[0] if pdms else None
+    sp = synth.from_list(spl).to(DEV)
+    fc = ss.partition_encode_batch(g.bytes, g.offsets, so, perm, lcp, dist, sp.bytes, sp.offsets)
+    r = len(spl) + 1
+    ro = fc["run_off"].view(p, r + 1)
+    run_begin = ro[:, :-1].t().reshape(-1)      # group j = bucket j, run i = set i
+    run_end = ro[:, 1:].t().reshape(-1)
+    group_off = torch.arange(0, p * r + 1, p, dtype=torch.int32, device=DEV)
+    _, order, mlcp = ss.lcp_merge(run_begin, run_end, group_off, fc["lcp"], fc["len"], fc["id"],
+                                  fc["suf_off"], fc["suf"], n_out=sets.n)
+    ss.join_group_lcps(g.bytes, g.offsets, order, mlcp, run_begin, run_end, group_off)
+    dist_x = ss.dist_exact(g.offsets, order, mlcp)
+    torch.cuda.synchronize()
+    return order, mlcp, dist_x
+
+
+@pytest.mark.parametrize("pdms", [False, True])
+@pytest.mark.parametrize("spl_kind", ["sampled", "empty_buckets"])
+def test_pipeline_join_group_lcps(pdms, spl_kind):
+    """Whole order, its LCP array (joined at every bucket boundary) and the
+    exact distinguishing prefixes against the oracle on all strings."""
+    sets, bounds = synth.random_sets(6, 20, 3000, len_lo=0, len_hi=40, seed=12)
+    strs = sets.as_list()
+    if spl_kind == "sampled":
+        spl = sorted(random.Random(5).sample(strs, 9))
+    else:  # repeated and extreme splitters leave buckets empty
+        mid = sorted(strs)[len(strs) // 2]
+        spl = sorted([b"", b"", mid, mid, mid, b"\xff" * 3, b"\xff" * 3])
+    _log(f"[pipeline] n={sets.n} pdms={pdms} splitters={spl_kind}")
+    order, mlcp, dist_x = _pipeline(sets, bounds, spl, pdms)
+    b, o = oracle.strings_np(sets)
+    p_ref = oracle.sort(b, o)
+    l_ref = oracle.lcp(b, o, p_ref)
+    np.testing.assert_array_equal(u32(order), p_ref)
+    np.testing.assert_array_equal(u32(mlcp), l_ref)
+    np.testing.assert_array_equal(u32(dist_x), oracle.dist_exact(o, p_ref, l_ref))
+
+
+def test_join_group_lcps_leaves_other_positions():
+    """Only the first position of each non-empty group after the first changes."""
+    s = synth.from_list([b"AAA", b"AAB", b"AB", b"B", b"BA", b"BAA"])
+    g = s.to(DEV)
+    order = torch.arange(6, dtype=torch.int32, device=DEV)
+    lcp = torch.full((6,), 77, dtype=torch.int32, device=DEV)
+    rb = torch.tensor([0, 2, 2, 3], dtype=torch.int64, device=DEV)   # runs: [0,2) [2,2) [2,3) [3,6)
+    re_ = torch.tensor([2, 2, 3, 6], dtype=torch.int64, device=DEV)
+    go = torch.tensor([0, 1, 2, 3, 4], dtype=torch.int32, device=DEV)  # group 1 is empty
+    ss.join_group_lcps(g.bytes, g.offsets, order, lcp, rb, re_, go)
+    assert list(u32(lcp)) == [77, 77, 1, 0, 77, 77]
