@@ -174,91 +174,139 @@ struct PreLens {
     u32 count;
 };
 
-// Sums over the 8 lanes of a group of NV (4 or 8) values per lane, scattered:
-// afterwards lane j holds the total of value j % NV (reduce-scatter: each
-// exchange halves the values a lane keeps).
-template <int NV>
-__device__ __forceinline__ u64 lane_reduce_scatter(const u64 (&c)[8], u32 lane)
+// First pass as a matrix product.  With the byte weights
+// w_i = 256^(i mod 4) B^-(i/4 + 1) (mod p), the m-byte prefix of a string has
+// G = sum_{i<m} byte_i w_i and Horner value H = B^L G (L = ceil(m/4) limbs,
+// the last zero-padded), the same value as limb-by-limb Horner.  Each weight
+// is split into nine 7-bit digits, w_i = sum_d c_id 2^(7d), so that
+// S_rd = sum_{i<l_r} (byte_i - 128) c_id is an int8 dot product (bytes past
+// the string count as 0; the -128 offset makes them signed and is undone by
+// the constant 128 sum_{i<l_r} w_i).  One v_mfma_i32_16x16x64_i8 takes 64
+// prefix bytes of 16 strings (B operand: column = string) against 16
+// (round, digit) rows of weights (A operand); three of them cover five rounds
+// x nine digits.  Multiplying by 2^(7d) mod 2^61-1 is a 61-bit rotation.
+struct FirstW {
+    u64 ib[16];           // B^-(j+1) mod p for limbs j < 16 (the first 64 bytes)
+    u64 corr[PRE_SLOTS];  // 128 sum_{i<l_r} w_i mod p
+};
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ u64 rot61(u64 x, u32 k)  // x 2^k mod 2^61-1, x < p, k < 61
 {
-    u64 m4[4];
-    if (NV == 8) {
-        const bool hi = (lane >> 2) & 1;  // keep values 4..7
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const u64 give = hi ? c[k] : c[4 + k];
-            m4[k] = addmod61(hi ? c[4 + k] : c[k], __shfl_xor(give, 4, 8));
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < 4; k++) m4[k] = c[k];
-    }
-    const bool b1 = (lane >> 1) & 1, b0 = lane & 1;
-    u64 m2[2];
-#pragma unroll
-    for (int k = 0; k < 2; k++) {
-        const u64 give = b1 ? m4[k] : m4[2 + k];
-        m2[k] = addmod61(b1 ? m4[2 + k] : m4[k], __shfl_xor(give, 2, 8));
-    }
-    const u64 give = b0 ? m2[0] : m2[1];
-    u64 r = addmod61(b0 ? m2[1] : m2[0], __shfl_xor(give, 1, 8));
-    if (NV == 4) r = addmod61(r, __shfl_xor(r, 4, 8));  // the two quads
-    return r;
+    return k == 0 ? x : (((x << k) & KR_P) | (x >> (61 - k)));
 }
 
-// First pass: a group of 8 lanes takes HU strings and reads the first
-// min(len, W) bytes of each once (W = the last precomputed prefix length
-// <= 64; lane j holds bytes [8j, 8j+8), i.e. limbs 2j and 2j+1) and emits the
-// key of every round whose prefix length is <= W, by input index.  For a
-// prefix of L limbs, C = sum_j (limb_2j*B + limb_2j+1) * B^(L-2-2j) over lanes
-// with both limbs in the prefix, plus limb_2j for the lane whose second limb is
-// past the prefix.  One reduce-scatter leaves round r's sum in lane r, which
-// finishes that round's key.  Keys of later rounds continue from the Horner
-// state of the W-prefix.
-template <int NV>
-__global__ __launch_bounds__(256) void k_hash_first(u32 n, const u8 *bytes, u64 N, const u64 *off, PreLens P,
-                                                    u32 bits, BPow bp, u64 *state, u64 *pre)
+__device__ __forceinline__ u64 modp_i32(int s) { return s >= 0 ? (u64)s : (u64)((long long)s + (long long)KR_P); }
+
+// Bytes [a, a+take) (take <= 16) as two little-endian words, the rest zero;
+// reads only inside [bytes, bytes + N).
+__device__ __forceinline__ void load16_le(const u8 *__restrict__ bytes, u64 N, u64 a, u32 take, u64 &lo, u64 &hi)
 {
-    const u32 lane = threadIdx.x & 7;
-    const u32 i0 = (blockIdx.x * 32 + (threadIdx.x >> 3)) * HU;
-    if (i0 >= n) return;  // whole group leaves together
-    const u64 W = P.l[P.count - 1];
-    u64 w[HU], len[HU];
-#pragma unroll
-    for (int u = 0; u < HU; u++) {
-        w[u] = 0;
-        len[u] = 0;
-        if (i0 + u < n) {
-            const u64 o = off[i0 + u];
-            len[u] = off[i0 + u + 1] - o;
-            const u64 mw = len[u] < W ? len[u] : W;
-            const u64 q = 8ull * lane;
-            const u32 take = q < mw ? (u32)((mw - q) < 8 ? (mw - q) : 8) : 0u;
-            w[u] = load_le(bytes, N, o + q, take);
+    lo = hi = 0;
+    if (take == 0) return;
+    const uintptr_t p = (uintptr_t)(bytes + a);
+    const uintptr_t base = p & ~(uintptr_t)7;
+    const u32 sh = (u32)(p & 7);
+    const u32 nw = (sh + take + 7) / 8;  // aligned words touched, 1..3
+    if (base >= (uintptr_t)bytes && base + 8 * nw <= (uintptr_t)(bytes + N)) {
+        const u64 *w = (const u64 *)base;
+        const u64 w0 = w[0], w1 = nw > 1 ? w[1] : 0ull, w2 = nw > 2 ? w[2] : 0ull;
+        if (sh == 0) {
+            lo = w0;
+            hi = w1;
+        } else {
+            lo = (w0 >> (8 * sh)) | (w1 << (64 - 8 * sh));
+            hi = (w1 >> (8 * sh)) | (w2 << (64 - 8 * sh));
+        }
+    } else {
+        for (u32 t = 0; t < take; t++) {
+            const u64 v = (u64)bytes[a + t];
+            if (t < 8) lo |= v << (8 * t);
+            else hi |= v << (8 * (t - 8));
         }
     }
-    const u32 r = lane % NV;  // the round this lane finishes
-    const u64 lr = r < P.count ? P.l[r] : 0;
+    if (take < 8) {
+        lo &= (1ull << (8 * take)) - 1ull;
+        hi = 0;
+    } else if (take < 16) {
+        hi &= take == 8 ? 0ull : ((1ull << (8 * (take - 8))) - 1ull);
+    }
+}
+
+// Row assignment of the weight operand: lane group g of the result (rows
+// 4g..4g+3 of each of the three tiles, twelve slots) holds round g's nine
+// digits in slots 0..8 and digits 3g..3g+2 of round 4 in slots 9..11.
+__device__ __forceinline__ bool first_slot(u32 g, u32 slot, u32 *r, u32 *d)
+{
+    if (slot < 9) { *r = g; *d = slot; return true; }
+    if (g < 3) { *r = 4; *d = 3 * g + (slot - 9); return true; }
+    return false;
+}
+
+__global__ __launch_bounds__(256) void k_hash_first(u32 n, const u8 *bytes, u64 N, const u64 *off, PreLens P,
+                                                    u32 bits, BPow bp, FirstW fw, u64 *state, u64 *pre)
+{
+    const u32 lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const u64 W = P.l[P.count - 1];
+    // weight operand (A): row col of each tile, k-group g = prefix bytes [16g, 16g+16)
+    v4i wa[3];
 #pragma unroll
-    for (int u = 0; u < HU; u++) {
-        const u32 i = i0 + u;
-        if (i >= n) break;  // uniform over the lane group
-        const u32 a = (u32)w[u];
-        const u64 v = addmod61(mulmod61_32(a, KR_B), w[u] >> 32);
-        u64 c[8];
+    for (int T = 0; T < 3; T++) {
+        u32 r, d;
+        const bool valid = first_slot(col >> 2, 4 * T + (col & 3), &r, &d) && r < P.count;
+        u32 wd[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-            c[q] = 0;
-            if (q >= NV || (u32)q >= P.count) continue;
-            const u64 m = len[u] < P.l[q] ? len[u] : P.l[q];
-            const u32 L = (u32)((m + 3) / 4);
-            if (2 * lane + 1 < L) c[q] = mulmod61(v, bp.p[L - 2 - 2 * lane]);
-            else if (2 * lane + 1 == L) c[q] = a;
+        for (int b = 0; b < 16; b++) {
+            const u32 pos = 16 * g + b;
+            u32 c = 0;
+            if (valid && pos < P.l[r]) c = (u32)((rot61(fw.ib[pos >> 2], 8 * (pos & 3)) >> (7 * d)) & 127u);
+            wd[b >> 2] |= c << (8 * (b & 3));
         }
-        const u64 sum = lane_reduce_scatter<NV>(c, lane);
-        if (lane < NV && r < P.count) {
-            const u64 m = len[u] < lr ? len[u] : lr;
-            pre[(u64)r * n + i] = kr_finish(sum, m, bits);
-            if (r == P.count - 1) state[i] = sum;
+        wa[T] = v4i{(int)wd[0], (int)wd[1], (int)wd[2], (int)wd[3]};
+    }
+    const u32 ntiles = (n + 15) / 16;
+    const u32 wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (u32 tile = wave; tile < ntiles; tile += nwaves) {  // uniform over the wavefront
+        const u32 i = tile * 16 + col;
+        u64 len = 0, lo = 0, hi = 0;
+        if (i < n) {
+            const u64 o = off[i];
+            len = off[i + 1] - o;
+            const u64 mw = len < W ? len : W;
+            const u64 q = 16ull * g;
+            const u32 take = q < mw ? (u32)((mw - q) < 16 ? (mw - q) : 16) : 0u;
+            load16_le(bytes, N, o + q, take, lo, hi);
+        }
+        lo ^= 0x8080808080808080ull;  // byte - 128 as int8
+        hi ^= 0x8080808080808080ull;
+        const v4i xb = v4i{(int)(u32)lo, (int)(u32)(lo >> 32), (int)(u32)hi, (int)(u32)(hi >> 32)};
+        v4i acc[3];
+#pragma unroll
+        for (int T = 0; T < 3; T++)
+            acc[T] = __builtin_amdgcn_mfma_i32_16x16x64_i8(wa[T], xb, v4i{0, 0, 0, 0}, 0, 0, 0);
+        // this lane: string i, result rows 4g..4g+3 of every tile = slots 0..11 of group g
+        u64 G = fw.corr[g < P.count ? g : 0], G4 = 0;
+#pragma unroll
+        for (int slot = 0; slot < 12; slot++) {
+            const int s = acc[slot >> 2][slot & 3];
+            if (slot < 9) G = addmod61(G, rot61(modp_i32(s), 7 * slot));
+            else if (g < 3) G4 = addmod61(G4, rot61(modp_i32(s), 7 * (3 * g + (slot - 9))));
+        }
+        G4 = addmod61(G4, __shfl_xor(G4, 16));
+        G4 = addmod61(G4, __shfl_xor(G4, 32));
+        if (i < n) {
+            // lane group g finishes round g; group 3 also round 4
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                const u32 r = k == 0 ? g : 4u;
+                if ((k == 1 && g != 3) || r >= P.count) continue;
+                const u64 Gr = k == 0 ? G : addmod61(G4, fw.corr[4]);
+                const u64 m = len < P.l[r] ? len : P.l[r];
+                const u64 H = mulmod61(Gr, bp.p[(m + 3) / 4]);
+                pre[(u64)r * n + i] = kr_finish(H, m, bits);
+                if (r == P.count - 1) state[i] = H;
+            }
         }
     }
 }
@@ -447,6 +495,34 @@ extern "C" int ss_prefix_keys(const uint8_t *bytes, uint64_t N, const uint64_t *
     return SS_OK;
 }
 
+static u64 host_mulmod(u64 a, u64 b) { return (u64)(((unsigned __int128)a * b) % KR_P); }
+
+static u64 host_powmod(u64 a, u64 e)
+{
+    u64 r = 1;
+    for (; e; e >>= 1, a = host_mulmod(a, a))
+        if (e & 1) r = host_mulmod(r, a);
+    return r;
+}
+
+// Weights of the first pass: inverse powers of the base (B^(p-2) = B^-1 by
+// Fermat, p prime) and the offset corrections of each round.
+static FirstW first_weights(const PreLens &P)
+{
+    FirstW f{};
+    const u64 binv = host_powmod(KR_B, KR_P - 2);
+    u64 x = binv;
+    for (int j = 0; j < 16; j++, x = host_mulmod(x, binv)) f.ib[j] = x;
+    u64 sum = 0;
+    u32 r = 0;
+    for (u32 i = 0; i < PRE_MAX && r < P.count; i++) {
+        const u64 wi = host_mulmod(f.ib[i / 4], 1ull << (8 * (i % 4)));
+        sum = (sum + wi) % KR_P;
+        while (r < P.count && i + 1 == P.l[r]) f.corr[r++] = host_mulmod(sum, 128);
+    }
+    return f;
+}
+
 extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
                               uint32_t init_len, uint32_t hash_bits, uint32_t *dist_approx,
                               uint32_t *rounds_host, void *ws, size_t ws_bytes, void *stream)
@@ -486,12 +562,10 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
             // the first line of every string, once
             SS_PROF("k_hash_first", st,
                     (double)n * (double)P.l[P.count - 1] + (double)n * (24.0 + 8.0 * P.count));
-            if (P.count <= 4)
-                k_hash_first<4><<<(unsigned)ceil_div(n, 32 * HU), 256, 0, st>>>((u32)n, bytes, N, offsets, P,
-                                                                                hash_bits, bp, w.state, w.pre);
-            else
-                k_hash_first<8><<<(unsigned)ceil_div(n, 32 * HU), 256, 0, st>>>((u32)n, bytes, N, offsets, P,
-                                                                                hash_bits, bp, w.state, w.pre);
+            const u64 tiles = ceil_div(n, 16);
+            const unsigned blocks = (unsigned)(ceil_div(tiles, 4) < 2048 ? ceil_div(tiles, 4) : 2048);
+            k_hash_first<<<blocks, 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits, bp, first_weights(P),
+                                                 w.state, w.pre);
         }
         SS_CHECK_LAUNCH();
         SS_HIP(hipMemsetAsync(ctr + 4, 0, sizeof(u32) * 2 * P.count, st));
