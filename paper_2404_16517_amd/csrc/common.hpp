@@ -103,26 +103,66 @@ template <class T> int ss_scan_exclusive(const T *in, T *out, u64 n, T *scratch,
 
 // The first `take` (0..8) bytes at bytes[a..] as a little-endian word
 // (byte a -> bits 7..0), the rest zero.  Reads only inside [bytes, bytes + N):
-// two aligned 8-byte loads when they fit, byte loads otherwise.
+// the two aligned 8-byte words around the bytes when both lie inside, byte
+// loads otherwise.  Both words are loaded unconditionally (no branch between
+// them, so several calls can have their loads in flight together), through a
+// pointer derived from `bytes` so that they stay global-memory loads.
 __device__ __forceinline__ u64 load_le(const u8 *__restrict__ bytes, u64 N, u64 a, u32 take)
 {
     if (take == 0) return 0;
-    const uintptr_t p = (uintptr_t)(bytes + a);
-    const uintptr_t base = p & ~(uintptr_t)7;
-    const u32 sh = (u32)(p & 7);
-    const uintptr_t lo = (uintptr_t)bytes, hi = (uintptr_t)(bytes + N);
+    const u8 *pb = bytes + a;
+    const u32 sh = (u32)((uintptr_t)pb & 7);
+    const uintptr_t base = (uintptr_t)pb - sh;
     u64 v;
-    if (base >= lo && base + ((sh + take > 8) ? 16 : 8) <= hi) {
-        const u64 *w = (const u64 *)base;
-        const u64 w0 = w[0];
-        if (sh == 0) v = w0;
-        else if (sh + take <= 8) v = w0 >> (8 * sh);
-        else v = (w0 >> (8 * sh)) | (w[1] << (64 - 8 * sh));
+    if (base >= (uintptr_t)bytes && base + 16 <= (uintptr_t)(bytes + N)) {
+        const u64 *w = (const u64 *)(pb - sh);
+        const u64 w0 = w[0], w1 = w[1];
+        v = sh == 0 ? w0 : ((w0 >> (8 * sh)) | (w1 << (64 - 8 * sh)));
     } else {
         v = 0;
         for (u32 t = 0; t < take; t++) v |= (u64)bytes[a + t] << (8 * t);
     }
     if (take < 8) v &= (1ull << (8 * take)) - 1ull;
+    return v;
+}
+
+// load_le in two halves, for callers that issue the loads of several words
+// before combining any of them.
+struct Raw8 {
+    u64 w0, w1, a;
+    u32 sh, take;
+    bool ok;
+};
+
+__device__ __forceinline__ Raw8 raw8_issue(const u8 *__restrict__ bytes, u64 N, u64 a, u32 take)
+{
+    Raw8 r;
+    r.a = a;
+    r.take = take;
+    const u8 *pb = bytes + a;
+    r.sh = (u32)((uintptr_t)pb & 7);
+    const uintptr_t base = (uintptr_t)pb - r.sh;
+    r.ok = take > 0 && base >= (uintptr_t)bytes && base + 16 <= (uintptr_t)(bytes + N);
+    r.w0 = r.w1 = 0;
+    if (r.ok) {
+        const u64 *w = (const u64 *)(pb - r.sh);
+        r.w0 = w[0];
+        r.w1 = w[1];
+    }
+    return r;
+}
+
+__device__ __forceinline__ u64 raw8_le(const u8 *__restrict__ bytes, const Raw8 &r)
+{
+    if (r.take == 0) return 0;
+    u64 v;
+    if (r.ok) {
+        v = r.sh == 0 ? r.w0 : ((r.w0 >> (8 * r.sh)) | (r.w1 << (64 - 8 * r.sh)));
+    } else {
+        v = 0;
+        for (u32 t = 0; t < r.take; t++) v |= (u64)bytes[r.a + t] << (8 * t);
+    }
+    if (r.take < 8) v &= (1ull << (8 * r.take)) - 1ull;
     return v;
 }
 

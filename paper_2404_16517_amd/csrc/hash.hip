@@ -73,99 +73,6 @@ struct BPow {
     u64 p[32];  // B^0 .. B^31 mod p
 };
 
-#define HU 2  // strings per lane group in flight in the hash kernels
-
-// Doubling rounds from the Horner state at lprev: the key of the
-// min(l1, len)-prefix of every active string and, when l2 != 0, also of the
-// min(l2, len)-prefix (two rounds from one read of bytes [lprev, l2); needs
-// (l1 - lprev) % 64 == 0).  A group of 8 lanes takes HU strings and reads 64
-// consecutive bytes of each per step; lane j holds limbs 2j, 2j+1 of the step
-// as v_j = limb_2j * B + limb_2j+1.  Lanes accumulate across full steps,
-// acc_j <- acc_j * B^16 + v_j (lane 7 starts from the previous state), so that
-// the prefix hash after the steps is C = sum_j acc_j * B^(14-2j); the lane
-// reduction is paid only where a key is read out.  A partial last step of
-// Lp limbs gives C = sum_j (acc_j * B^(14-2j+Lp) + v_j * B^(limbs after v_j)).
-__global__ __launch_bounds__(256) void k_hash_round(const u32 *act, const u32 *cnt, const u8 *bytes, u64 N,
-                                                    const u64 *off, u64 lprev, u64 l1, u64 l2, u32 bits,
-                                                    u64 *state, u64 *keys1, u64 *keys2, BPow bp)
-{
-    const u32 A = *cnt;
-    const u32 lane = threadIdx.x & 7;
-    const u32 j0 = (blockIdx.x * 32 + (threadIdx.x >> 3)) * HU;
-    if (j0 >= A) return;  // whole group leaves together
-    const u64 lend = l2 ? l2 : l1;
-    const u64 pw = bp.p[14 - 2 * lane], b16 = bp.p[16];
-    u32 ii[HU];
-    u64 o[HU], len[HU], m[HU], acc[HU], C[HU], C1[HU];
-    u64 xmax = lprev;
-#pragma unroll
-    for (int u = 0; u < HU; u++) {
-        ii[u] = 0; o[u] = 0; len[u] = 0; m[u] = lprev; C[u] = 0;
-        if (j0 + u < A) {
-            ii[u] = act ? act[j0 + u] : j0 + u;
-            o[u] = off[ii[u]];
-            len[u] = off[ii[u] + 1] - o[u];
-            m[u] = lend < len[u] ? lend : len[u];
-            if (lprev) C[u] = state[ii[u]];
-        }
-        C1[u] = C[u];
-        acc[u] = lane == 7 ? C[u] : 0ull;
-        xmax = m[u] > xmax ? m[u] : xmax;
-    }
-    for (u64 x = lprev; x < xmax; x += 64) {
-        u64 w[HU];
-        u32 take[HU];
-#pragma unroll
-        for (int u = 0; u < HU; u++) {
-            const u64 q = x + 8 * lane;
-            take[u] = q < m[u] ? (u32)((m[u] - q) < 8 ? (m[u] - q) : 8) : 0u;
-            w[u] = load_le(bytes, N, o[u] + q, take[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < HU; u++) {
-            if (x >= m[u]) continue;  // uniform over the lane group
-            const u32 nl = take[u] == 0 ? 0u : (take[u] > 4 ? 2u : 1u);
-            u64 v = 0;
-            if (nl == 2) v = addmod61(mulmod61_32((u32)w[u], KR_B), w[u] >> 32);
-            else if (nl == 1) v = w[u];
-            if (x + 64 <= m[u]) {
-                acc[u] = addmod61(mulmod61(acc[u], b16), v);
-                const bool at_l1 = l2 && x + 64 == l1;
-                if (at_l1 || x + 64 == m[u]) {
-                    u64 t = mulmod61(acc[u], pw);
-#pragma unroll
-                    for (int s2 = 4; s2 > 0; s2 >>= 1) t = addmod61(t, __shfl_xor(t, s2, 8));
-                    if (at_l1) C1[u] = t;
-                    C[u] = t;
-                }
-            } else {
-                const u32 Lp = (u32)((m[u] - x + 3) / 4);
-                const u32 before = 2 * lane < Lp ? 2 * lane : Lp;
-                const u32 after = Lp - before - nl;
-                u64 t = mulmod61(acc[u], bp.p[14 - 2 * lane + Lp]);
-                if (nl) t = addmod61(t, after ? mulmod61(v, bp.p[after]) : v);
-#pragma unroll
-                for (int s2 = 4; s2 > 0; s2 >>= 1) t = addmod61(t, __shfl_xor(t, s2, 8));
-                C[u] = t;
-            }
-        }
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int u = 0; u < HU; u++) {
-            if (j0 + u >= A) continue;
-            state[ii[u]] = C[u];
-            if (l2) {
-                const u64 m1 = len[u] < l1 ? len[u] : l1;
-                keys1[j0 + u] = kr_finish(m[u] <= l1 ? C[u] : C1[u], m1, bits);
-                keys2[j0 + u] = kr_finish(C[u], m[u], bits);
-            } else {
-                keys1[j0 + u] = kr_finish(C[u], m[u], bits);
-            }
-        }
-    }
-}
-
 #define PRE_MAX 64  // the first pass hashes up to this many bytes of every string
 #define PRE_SLOTS 5  // 4, 8, 16, 32, 64
 
@@ -192,6 +99,8 @@ struct FirstW {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
+#define HF_T 2  // first pass: tiles of 16 strings whose loads are issued together
+
 __device__ __forceinline__ u64 rot61(u64 x, u32 k)  // x 2^k mod 2^61-1, x < p, k < 61
 {
     return k == 0 ? x : (((x << k) & KR_P) | (x >> (61 - k)));
@@ -200,38 +109,67 @@ __device__ __forceinline__ u64 rot61(u64 x, u32 k)  // x 2^k mod 2^61-1, x < p, 
 __device__ __forceinline__ u64 modp_i32(int s) { return s >= 0 ? (u64)s : (u64)((long long)s + (long long)KR_P); }
 
 // Bytes [a, a+take) (take <= 16) as two little-endian words, the rest zero;
-// reads only inside [bytes, bytes + N).
-__device__ __forceinline__ void load16_le(const u8 *__restrict__ bytes, u64 N, u64 a, u32 take, u64 &lo, u64 &hi)
+// reads only inside [bytes, bytes + N).  Split in two so that callers can
+// issue the loads of several windows before combining any: issue() loads the
+// three aligned words around the window when all of them lie inside the
+// buffer, finish() shifts them into place (or reads bytes one by one near the
+// buffer's ends).
+struct Win16 {
+    u64 w0, w1, w2;
+    u64 a;
+    u32 take, sh;
+    bool ok;
+};
+
+__device__ __forceinline__ Win16 win16_issue(const u8 *__restrict__ bytes, u64 N, u64 a, u32 take)
+{
+    Win16 r;
+    r.a = a;
+    r.take = take;
+    const u8 *pb = bytes + a;
+    r.sh = (u32)((uintptr_t)pb & 7);
+    const u8 *base = pb - r.sh;  // aligned; derived from bytes, so a global-memory pointer
+    r.ok = take > 0 && base >= bytes && base + 24 <= bytes + N;
+    r.w0 = r.w1 = r.w2 = 0;
+    if (r.ok) {
+        const u64 *w = (const u64 *)base;
+        r.w0 = w[0];
+        r.w1 = w[1];
+        r.w2 = w[2];
+    }
+    return r;
+}
+
+__device__ __forceinline__ void win16_finish(const u8 *__restrict__ bytes, const Win16 &r, u64 &lo, u64 &hi)
 {
     lo = hi = 0;
-    if (take == 0) return;
-    const uintptr_t p = (uintptr_t)(bytes + a);
-    const uintptr_t base = p & ~(uintptr_t)7;
-    const u32 sh = (u32)(p & 7);
-    const u32 nw = (sh + take + 7) / 8;  // aligned words touched, 1..3
-    if (base >= (uintptr_t)bytes && base + 8 * nw <= (uintptr_t)(bytes + N)) {
-        const u64 *w = (const u64 *)base;
-        const u64 w0 = w[0], w1 = nw > 1 ? w[1] : 0ull, w2 = nw > 2 ? w[2] : 0ull;
-        if (sh == 0) {
-            lo = w0;
-            hi = w1;
+    if (r.take == 0) return;
+    if (r.ok) {
+        if (r.sh == 0) {
+            lo = r.w0;
+            hi = r.w1;
         } else {
-            lo = (w0 >> (8 * sh)) | (w1 << (64 - 8 * sh));
-            hi = (w1 >> (8 * sh)) | (w2 << (64 - 8 * sh));
+            lo = (r.w0 >> (8 * r.sh)) | (r.w1 << (64 - 8 * r.sh));
+            hi = (r.w1 >> (8 * r.sh)) | (r.w2 << (64 - 8 * r.sh));
         }
     } else {
-        for (u32 t = 0; t < take; t++) {
-            const u64 v = (u64)bytes[a + t];
+        for (u32 t = 0; t < r.take; t++) {
+            const u64 v = (u64)bytes[r.a + t];
             if (t < 8) lo |= v << (8 * t);
             else hi |= v << (8 * (t - 8));
         }
     }
-    if (take < 8) {
-        lo &= (1ull << (8 * take)) - 1ull;
+    if (r.take < 8) {
+        lo &= (1ull << (8 * r.take)) - 1ull;
         hi = 0;
-    } else if (take < 16) {
-        hi &= take == 8 ? 0ull : ((1ull << (8 * (take - 8))) - 1ull);
+    } else if (r.take < 16) {
+        hi &= r.take == 8 ? 0ull : ((1ull << (8 * (r.take - 8))) - 1ull);
     }
+}
+
+__device__ __forceinline__ void load16_le(const u8 *__restrict__ bytes, u64 N, u64 a, u32 take, u64 &lo, u64 &hi)
+{
+    win16_finish(bytes, win16_issue(bytes, N, a, take), lo, hi);
 }
 
 // Row assignment of the weight operand: lane group g of the result (rows
@@ -249,63 +187,244 @@ __global__ __launch_bounds__(256) void k_hash_first(u32 n, const u8 *bytes, u64 
 {
     const u32 lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
     const u64 W = P.l[P.count - 1];
-    // weight operand (A): row col of each tile, k-group g = prefix bytes [16g, 16g+16)
+    // weight operand (A): row col of each tile, k-group g = prefix bytes [16g, 16g+16).
+    // Kernel-argument arrays are read with constant indices only (selects by
+    // lane instead of indexed loads).
+    u64 lr[PRE_SLOTS];
+#pragma unroll
+    for (int r = 0; r < PRE_SLOTS; r++) lr[r] = (u32)r < P.count ? P.l[r] : 0;
+    u64 ww[16];  // w_pos for pos = 16g + b
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const u64 ib = g == 0 ? fw.ib[q] : g == 1 ? fw.ib[4 + q] : g == 2 ? fw.ib[8 + q] : fw.ib[12 + q];
+#pragma unroll
+        for (int b = 0; b < 4; b++) ww[4 * q + b] = rot61(ib, 8 * b);
+    }
     v4i wa[3];
 #pragma unroll
     for (int T = 0; T < 3; T++) {
-        u32 r, d;
+        u32 r = 0, d = 0;
         const bool valid = first_slot(col >> 2, 4 * T + (col & 3), &r, &d) && r < P.count;
+        u64 lim = 0;
+#pragma unroll
+        for (int k = 0; k < PRE_SLOTS; k++)
+            if ((u32)k == r) lim = lr[k];
         u32 wd[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int b = 0; b < 16; b++) {
             const u32 pos = 16 * g + b;
-            u32 c = 0;
-            if (valid && pos < P.l[r]) c = (u32)((rot61(fw.ib[pos >> 2], 8 * (pos & 3)) >> (7 * d)) & 127u);
+            const u32 c = (valid && pos < lim) ? (u32)((ww[b] >> (7 * d)) & 127u) : 0u;
             wd[b >> 2] |= c << (8 * (b & 3));
         }
         wa[T] = v4i{(int)wd[0], (int)wd[1], (int)wd[2], (int)wd[3]};
     }
+    const u64 corr_g = g == 0 ? fw.corr[0] : g == 1 ? fw.corr[1] : g == 2 ? fw.corr[2] : fw.corr[3];
+    const u64 lg = g == 0 ? lr[0] : g == 1 ? lr[1] : g == 2 ? lr[2] : lr[3];
     const u32 ntiles = (n + 15) / 16;
     const u32 wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
-    for (u32 tile = wave; tile < ntiles; tile += nwaves) {  // uniform over the wavefront
-        const u32 i = tile * 16 + col;
-        u64 len = 0, lo = 0, hi = 0;
-        if (i < n) {
-            const u64 o = off[i];
-            len = off[i + 1] - o;
-            const u64 mw = len < W ? len : W;
+    for (u32 t0 = wave * HF_T; t0 < ntiles; t0 += nwaves * HF_T) {  // uniform over the wavefront
+        // HF_T tiles at a time: all their loads first
+        u64 len[HF_T], o[HF_T];
+        Win16 wn[HF_T];
+#pragma unroll
+        for (int f = 0; f < HF_T; f++) {  // offsets of all tiles, then their windows
+            const u32 i = (t0 + f) * 16 + col;
+            const u32 ic = i < n ? i : n - 1;  // loads without a branch; len 0 past the end
+            o[f] = off[ic];
+            const u64 e = off[ic + 1];
+            len[f] = i < n ? e - o[f] : 0;
+        }
+#pragma unroll
+        for (int f = 0; f < HF_T; f++) {
+            const u64 mw = len[f] < W ? len[f] : W;
             const u64 q = 16ull * g;
             const u32 take = q < mw ? (u32)((mw - q) < 16 ? (mw - q) : 16) : 0u;
-            load16_le(bytes, N, o + q, take, lo, hi);
+            wn[f] = win16_issue(bytes, N, o[f] + q, take);
         }
-        lo ^= 0x8080808080808080ull;  // byte - 128 as int8
-        hi ^= 0x8080808080808080ull;
-        const v4i xb = v4i{(int)(u32)lo, (int)(u32)(lo >> 32), (int)(u32)hi, (int)(u32)(hi >> 32)};
-        v4i acc[3];
 #pragma unroll
-        for (int T = 0; T < 3; T++)
-            acc[T] = __builtin_amdgcn_mfma_i32_16x16x64_i8(wa[T], xb, v4i{0, 0, 0, 0}, 0, 0, 0);
-        // this lane: string i, result rows 4g..4g+3 of every tile = slots 0..11 of group g
-        u64 G = fw.corr[g < P.count ? g : 0], G4 = 0;
+        for (int f = 0; f < HF_T; f++) {
+            if (t0 + f >= ntiles) break;  // uniform over the wavefront
+            const u32 i = (t0 + f) * 16 + col;
+            u64 lo, hi;
+            win16_finish(bytes, wn[f], lo, hi);
+            lo ^= 0x8080808080808080ull;  // byte - 128 as int8
+            hi ^= 0x8080808080808080ull;
+            const v4i xb = v4i{(int)(u32)lo, (int)(u32)(lo >> 32), (int)(u32)hi, (int)(u32)(hi >> 32)};
+            v4i acc[3];
 #pragma unroll
-        for (int slot = 0; slot < 12; slot++) {
-            const int s = acc[slot >> 2][slot & 3];
-            if (slot < 9) G = addmod61(G, rot61(modp_i32(s), 7 * slot));
-            else if (g < 3) G4 = addmod61(G4, rot61(modp_i32(s), 7 * (3 * g + (slot - 9))));
+            for (int T = 0; T < 3; T++)
+                acc[T] = __builtin_amdgcn_mfma_i32_16x16x64_i8(wa[T], xb, v4i{0, 0, 0, 0}, 0, 0, 0);
+            // this lane: string i, result rows 4g..4g+3 of every tile = slots 0..11 of group g
+            u64 G = corr_g, G4 = 0;
+#pragma unroll
+            for (int slot = 0; slot < 12; slot++) {
+                const int sv = acc[slot >> 2][slot & 3];
+                if (slot < 9) G = addmod61(G, rot61(modp_i32(sv), 7 * slot));
+                else if (g < 3) G4 = addmod61(G4, rot61(modp_i32(sv), 7 * (3 * g + (slot - 9))));
+            }
+            G4 = addmod61(G4, __shfl_xor(G4, 16));
+            G4 = addmod61(G4, __shfl_xor(G4, 32));
+            if (i < n) {
+                // lane group g finishes round g; group 3 also round 4
+#pragma unroll
+                for (int k = 0; k < 2; k++) {
+                    const u32 r = k == 0 ? g : 4u;
+                    if ((k == 1 && g != 3) || r >= P.count) continue;
+                    const u64 Gr = k == 0 ? G : addmod61(G4, fw.corr[4]);
+                    const u64 lim = k == 0 ? lg : lr[4];
+                    const u64 m = len[f] < lim ? len[f] : lim;
+                    const u64 H = mulmod61(Gr, bp.p[(m + 3) / 4]);
+                    pre[(u64)r * n + i] = kr_finish(H, m, bits);
+                    if (r == P.count - 1) state[i] = Gr;  // later rounds continue from G
+                }
+            }
         }
-        G4 = addmod61(G4, __shfl_xor(G4, 16));
-        G4 = addmod61(G4, __shfl_xor(G4, 32));
-        if (i < n) {
-            // lane group g finishes round g; group 3 also round 4
+    }
+}
+
+// Later rounds continue the same sum, G_l = G_lprev + sum_{lprev<=i<l} byte_i
+// w_i, over a list of active strings.  Positions are taken in chunks of 1024
+// bytes: inside chunk c, w_(1024c+P) = w_P B^(-256c), so one table of digit
+// weights for P < 1024 (built in LDS by each workgroup) serves every chunk and
+// the int32 sums of a chunk are scaled by B^(-256c) once.  Each byte is split
+// as 128 h + low (h in {0,1}, low < 128) so that both MFMA operands are
+// non-negative and bytes past the string (zero) add nothing: two
+// v_mfma_i32_16x16x64_i8 per 64-byte step and 16 strings.
+struct RoundW {
+    u64 iblo[16];  // B^-(r+1), r < 16
+    u64 ibhi[16];  // B^-16k, k < 16
+    u64 ibc0;      // B^-256c for the chunk of the first step
+    u64 ib256;     // B^-256
+    u64 bl1, bl2;  // B^(l1/4), B^(l2/4)
+    u64 b2[32];    // B^(2^k)
+};
+
+// B^L mod p from the table of squares (strings that end inside the round).
+__device__ __forceinline__ u64 kr_pow(u64 L, const RoundW &rw)
+{
+    u64 r = 1;
+    for (u32 k = 0; L; k++, L >>= 1)
+        if (L & 1) r = mulmod61(r, rw.b2[k]);
+    return r;
+}
+
+#define RW_STEPS 16  // 64-byte steps per 1024-byte chunk
+#define RW_U 4       // steps whose loads are issued together
+
+__global__ __launch_bounds__(256) void k_hash_round(const u32 *act, const u32 *cnt, const u8 *bytes, u64 N,
+                                                    const u64 *off, u64 lprev, u64 l1, u64 l2, u32 bits,
+                                                    u64 *state, u64 *keys1, u64 *keys2, RoundW rw)
+{
+    __shared__ v4i wtab[RW_STEPS * 64];  // [step of the chunk][lane]: the weight operand
+    const u32 lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    for (u32 e = threadIdx.x; e < RW_STEPS * 64; e += blockDim.x) {
+        const u32 s = e >> 6, ln = e & 63, d = ln & 15, kg = ln >> 4;
+        u32 wd[4] = {0, 0, 0, 0};
+        if (d < 9) {
 #pragma unroll
-            for (int k = 0; k < 2; k++) {
-                const u32 r = k == 0 ? g : 4u;
-                if ((k == 1 && g != 3) || r >= P.count) continue;
-                const u64 Gr = k == 0 ? G : addmod61(G4, fw.corr[4]);
-                const u64 m = len < P.l[r] ? len : P.l[r];
-                const u64 H = mulmod61(Gr, bp.p[(m + 3) / 4]);
-                pre[(u64)r * n + i] = kr_finish(H, m, bits);
-                if (r == P.count - 1) state[i] = H;
+            for (int q = 0; q < 4; q++) {  // the four limbs of the lane's 16 positions
+                const u32 j = 16 * s + 4 * kg + q;
+                const u64 ib = mulmod61(rw.iblo[j & 15], rw.ibhi[j >> 4]);
+#pragma unroll
+                for (int b = 0; b < 4; b++) {
+                    const u32 c = (u32)((rot61(ib, 8 * b) >> (7 * d)) & 127u);
+                    wd[q] |= c << (8 * b);
+                }
+            }
+        }
+        wtab[e] = v4i{(int)wd[0], (int)wd[1], (int)wd[2], (int)wd[3]};
+    }
+    __syncthreads();
+    const u32 A = *cnt;
+    const u64 lend = l2 ? l2 : l1;
+    const u32 ntiles = (A + 15) / 16;
+    const u32 wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
+    const u64 x0 = lprev & ~63ull;
+    for (u32 tile = wave; tile < ntiles; tile += nwaves) {  // uniform over the wavefront
+        const u32 j = tile * 16 + col;
+        const bool valid = j < A;
+        u32 i = 0;
+        u64 o = 0, len = 0, m = 0, G = 0;
+        if (valid) {
+            i = act ? act[j] : j;
+            o = off[i];
+            len = off[i + 1] - o;
+            m = len < lend ? len : lend;
+            if (lprev) G = state[i];
+        }
+        u64 xmax = m;
+#pragma unroll
+        for (int s2 = 1; s2 < 16; s2 <<= 1) {
+            const u64 t = __shfl_xor(xmax, s2);
+            xmax = t > xmax ? t : xmax;
+        }
+        u64 G1 = G, ibc = rw.ibc0;
+        v4i Sl = v4i{0, 0, 0, 0}, Sh = v4i{0, 0, 0, 0};
+        for (u64 xb = x0; xb < xmax; xb += 64 * RW_U) {  // uniform over the wavefront
+            // the loads of RW_U steps first, then their products
+            Win16 wn[RW_U];
+#pragma unroll
+            for (int u = 0; u < RW_U; u++) {
+                const u64 a0 = xb + 64 * u + 16ull * g;
+                const u64 hi_pos = a0 + 16 < m ? a0 + 16 : m;
+                const u32 take = hi_pos > a0 ? (u32)(hi_pos - a0) : 0u;
+                wn[u] = win16_issue(bytes, N, o + a0, take);
+            }
+            u64 lo[RW_U], hi[RW_U];
+#pragma unroll
+            for (int u = 0; u < RW_U; u++) win16_finish(bytes, wn[u], lo[u], hi[u]);
+#pragma unroll
+            for (int u = 0; u < RW_U; u++) {
+                const u64 x = xb + 64 * u;
+                if (x >= xmax) break;  // uniform over the wavefront
+                const u64 a0 = x + 16ull * g;
+                if (a0 < lprev) {  // bytes below lprev are in G already
+                    const u64 skip = lprev - a0 < 16 ? lprev - a0 : 16;
+                    if (skip >= 8) {
+                        lo[u] = 0;
+                        hi[u] &= skip == 16 ? 0ull : ~((1ull << (8 * (skip - 8))) - 1ull);
+                    } else {
+                        lo[u] &= ~((1ull << (8 * skip)) - 1ull);
+                    }
+                }
+                const u64 l7 = 0x7F7F7F7F7F7F7F7Full, h1 = 0x0101010101010101ull;
+                const u64 lo7 = lo[u] & l7, hi7 = hi[u] & l7, loh = (lo[u] >> 7) & h1, hih = (hi[u] >> 7) & h1;
+                const v4i xl = v4i{(int)(u32)lo7, (int)(u32)(lo7 >> 32), (int)(u32)hi7, (int)(u32)(hi7 >> 32)};
+                const v4i xh = v4i{(int)(u32)loh, (int)(u32)(loh >> 32), (int)(u32)hih, (int)(u32)(hih >> 32)};
+                const v4i wa = wtab[((x & 1023) >> 6) * 64 + lane];
+                Sl = __builtin_amdgcn_mfma_i32_16x16x64_i8(wa, xl, Sl, 0, 0, 0);
+                Sh = __builtin_amdgcn_mfma_i32_16x16x64_i8(wa, xh, Sh, 0, 0, 0);
+                const u64 xn = x + 64;
+                const bool at_l1 = l2 && xn == l1;
+                if ((xn & 1023) == 0 || xn >= xmax || at_l1) {
+                    // rows 4g..4g+3 of this lane are digits 4g+t (digits 9..15 are zero rows)
+                    u64 V = 0;
+#pragma unroll
+                    for (int t = 0; t < 4; t++) {
+                        const u32 d = 4 * g + t;
+                        if (d < 9) V = addmod61(V, rot61((u64)(u32)Sl[t] + 128ull * (u64)(u32)Sh[t], 7 * d));
+                    }
+                    V = addmod61(V, __shfl_xor(V, 16));
+                    V = addmod61(V, __shfl_xor(V, 32));
+                    G = addmod61(G, mulmod61(V, ibc));
+                    Sl = v4i{0, 0, 0, 0};
+                    Sh = v4i{0, 0, 0, 0};
+                    if (at_l1) G1 = G;
+                    if ((xn & 1023) == 0) ibc = mulmod61(ibc, rw.ib256);
+                }
+            }
+        }
+        if (valid && g == 0) {
+            state[i] = G;
+            if (l2) {
+                const u64 m1 = len < l1 ? len : l1;
+                const u64 H1 = mulmod61(m <= l1 ? G : G1, m1 == l1 ? rw.bl1 : kr_pow((m1 + 3) / 4, rw));
+                const u64 H2 = mulmod61(G, m == l2 ? rw.bl2 : kr_pow((m + 3) / 4, rw));
+                keys1[j] = kr_finish(H1, m1, bits);
+                keys2[j] = kr_finish(H2, m, bits);
+            } else {
+                const u64 H = mulmod61(G, m == l1 ? rw.bl1 : kr_pow((m + 3) / 4, rw));
+                keys1[j] = kr_finish(H, m, bits);
             }
         }
     }
@@ -523,6 +642,26 @@ static FirstW first_weights(const PreLens &P)
     return f;
 }
 
+// Weights of a later round: inverse powers for the LDS table, the chunk
+// scale of the first step and the powers that turn G into Horner values.
+static RoundW round_weights(u64 lprev, u64 l1, u64 l2)
+{
+    RoundW r{};
+    const u64 binv = host_powmod(KR_B, KR_P - 2);
+    u64 x = binv;
+    for (int k = 0; k < 16; k++, x = host_mulmod(x, binv)) r.iblo[k] = x;
+    const u64 b16 = host_powmod(binv, 16);
+    u64 y = 1;
+    for (int k = 0; k < 16; k++, y = host_mulmod(y, b16)) r.ibhi[k] = y;
+    r.ib256 = host_powmod(binv, 256);
+    r.ibc0 = host_powmod(r.ib256, (lprev & ~63ull) / 1024);
+    r.bl1 = host_powmod(KR_B, l1 / 4);
+    r.bl2 = l2 ? host_powmod(KR_B, l2 / 4) : 0;
+    u64 z = KR_B;
+    for (int k = 0; k < 32; k++, z = host_mulmod(z, z)) r.b2[k] = z;
+    return r;
+}
+
 extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
                               uint32_t init_len, uint32_t hash_bits, uint32_t *dist_approx,
                               uint32_t *rounds_host, void *ws, size_t ws_bytes, void *stream)
@@ -562,7 +701,7 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
             // the first line of every string, once
             SS_PROF("k_hash_first", st,
                     (double)n * (double)P.l[P.count - 1] + (double)n * (24.0 + 8.0 * P.count));
-            const u64 tiles = ceil_div(n, 16);
+            const u64 tiles = ceil_div(n, 16 * HF_T);
             const unsigned blocks = (unsigned)(ceil_div(tiles, 4) < 2048 ? ceil_div(tiles, 4) : 2048);
             k_hash_first<<<blocks, 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits, bp, first_weights(P),
                                                  w.state, w.pre);
@@ -596,13 +735,16 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
         } else {
             // When the previous round finished nothing, hash this round and the
             // next from one read (the next round's keys wait in keysB).
-            const bool two = last_trivial && lprev > 0 && (l - lprev) % 64 == 0;
+            // (the first round's key is read out at a 64-byte step boundary)
+            const bool two = last_trivial && lprev > 0 && l % 64 == 0;
             {
                 // bytes are charged once the active count is read back
                 SS_PROF("k_hash_round", st, 0.0);
-                k_hash_round<<<(unsigned)ceil_div(Ah, 32 * HU), 256, 0, st>>>(
+                const u64 tiles = ceil_div(Ah, 16);
+                const u64 nb = ceil_div(tiles, 4);
+                k_hash_round<<<(unsigned)(nb < 1024 ? (nb ? nb : 1) : 1024), 256, 0, st>>>(
                     act, ctr + ci, bytes, N, offsets, lprev, l, two ? 2 * l : 0, hash_bits, w.state, w.keys,
-                    w.keysB, bp);
+                    w.keysB, round_weights(lprev, l, two ? 2 * l : 0));
             }
             SS_CHECK_LAUNCH();
             keys = w.keys;

@@ -222,14 +222,20 @@ __global__ __launch_bounds__(NT) void k_skip(const Seg *segs, const u32 *tstart,
         for (int u = 0; u < SKU; u++) any |= act[u];
         while (any) {  // uniform over the lane group
             u64 pos[SKU];
+            Raw8 ra[SKU];
+#pragma unroll
+            for (int u = 0; u < SKU; u++) {  // the loads of all strings first
+                const u64 q = x[u] + 8 * lane;
+                const u32 take = (act[u] && q < m[u]) ? ((m[u] - q) < 8 ? (u32)(m[u] - q) : 8u) : 0u;
+                ra[u] = raw8_issue(bytes, N, o[u] + q, take);
+            }
 #pragma unroll
             for (int u = 0; u < SKU; u++) {
                 pos[u] = ~0ull;
-                if (!act[u]) continue;
+                if (ra[u].take == 0) continue;
                 const u64 q = x[u] + 8 * lane;
-                if (q >= m[u]) continue;
-                const u32 take = (m[u] - q) < 8 ? (u32)(m[u] - q) : 8u;
-                const u64 wa = load_be(bytes, N, o[u] + q, take);
+                const u32 take = ra[u].take;
+                const u64 wa = __builtin_bswap64(raw8_le(bytes, ra[u]));
                 const u64 k = q - g.depth;  // multiple of 8
                 u64 wb = k < 8ull * SKFS ? fsw[k >> 3] : load_be(bytes, N, fo + q, take);
                 if (take < 8) wb &= ~0ull << (64 - 8 * take);

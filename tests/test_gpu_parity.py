@@ -269,6 +269,35 @@ def test_dist_prefix_matches_oracle(case):
     assert rounds == r_ref
 
 
+def _very_deep(seed):
+    """Groups sharing 700, 2100 and 4500 bytes (several 1024-byte chunks of
+    the later doubling rounds), with duplicates among the deepest."""
+    rng = random.Random(seed)
+    rnd = lambda k: bytes(rng.choice(b"ACGT") for _ in range(k))
+    strs = [b"Q" * 700 + rnd(12) for _ in range(300)]
+    strs += [b"Q" * 2100 + rnd(12) for _ in range(300)]
+    deep = [b"Q" * 4500 + rnd(6) for _ in range(40)]
+    strs += [x for x in deep for _ in range(3)]
+    strs += [b"Q" * k for k in range(0, 5000, 97)]
+    rng.shuffle(strs)
+    return synth.from_list(strs)
+
+
+@pytest.mark.parametrize("init_len", [4, 12, 64, 100, 128])
+@pytest.mark.parametrize("bits", [64, 16])
+def test_dist_prefix_init_lengths(init_len, bits):
+    """First-pass and later rounds at every alignment of the round lengths
+    (rounds that start inside a 64-byte step, no first pass at all)."""
+    s = _very_deep(init_len + bits)
+    _log(f"[dist_prefix] very_deep init={init_len} bits={bits} n={s.n}")
+    g = s.to(DEV)
+    d, rounds = ss.dist_prefix(g.bytes, g.offsets, init_len, bits)
+    b, o = oracle.strings_np(s)
+    ref, r_ref, coll = oracle.dist_prefix(b, o, init_len, bits)
+    np.testing.assert_array_equal(u32(d), ref)
+    assert rounds == r_ref
+
+
 # ---------------------------------------------------------- partition / coding
 
 def _partition(s, r, pdms):
