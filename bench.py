@@ -73,12 +73,14 @@ class Pipeline:
         ro = fc["run_off"].view(p, p + 1)                              # [PE, bucket bound], absolute
         run_begin = ro[:, :-1].t().reshape(-1)                          # group j = bucket j, run i = PE i
         run_end = ro[:, 1:].t().reshape(-1)
-        src, order, mlcp = ss.lcp_merge(run_begin, run_end, self.group_off, fc["lcp"], fc["len"], fc["id"],
-                                        fc["suf_off"], fc["suf"], ws=self.ws_merge, n_out=self.n)
+        _, order, mlcp, mlen = ss.lcp_merge(run_begin, run_end, self.group_off, fc["lcp"], fc["len"], fc["id"],
+                                              fc["suf_off"], fc["suf"], ws=self.ws_merge, n_out=self.n,
+                                              with_len=True, with_src=False)
         ev("lcp_merge")
-        # 6. LCPs across bucket boundaries, exact distinguishing prefixes
+        # 6. LCPs across bucket boundaries, exact distinguishing prefixes (the
+        #    merged prefix lengths bound them: dist <= approximate dist <= len)
         ss.join_group_lcps(B, O, order, mlcp, run_begin, run_end, self.group_off)
-        dist = ss.dist_exact(O, order, mlcp)
+        dist = ss.dist_exact_bounded(order, mlcp, mlen)
         ev("dist_exact")
         return order, mlcp, dist, dpx, rounds
 

@@ -118,6 +118,15 @@ int ss_join_group_lcps(const uint8_t *bytes, uint64_t N, const uint64_t *offsets
 int ss_dist_exact(const uint64_t *offsets, uint64_t n, const uint32_t *perm,
                   const uint32_t *lcp, uint32_t *dist, void *stream);
 
+/* The same dist from a bound instead of the string array: for the string at
+ * sorted position i, any d[i] with dist <= d[i] <= len gives
+ * dist = min(d[i], 1 + max(lcp[i], lcp[i+1])) (if 1 + max <= d[i] it is <=
+ * len; otherwise dist = len = d[i]).  Approximate distinguishing prefixes
+ * (ss_dist_prefix) qualify, and so do the fc_len values of a merge output
+ * (out_len).  perm, lcp, d (in, n), dist (out, by input index). */
+int ss_dist_exact_bounded(const uint32_t *perm, const uint32_t *lcp, const uint32_t *d, uint64_t n,
+                          uint32_t *dist, void *stream);
+
 /* ----------------------------------------------------- prefix doubling */
 
 /* Workspace bytes for ss_dist_prefix on n strings. */
@@ -276,10 +285,11 @@ size_t ss_lcp_merge_workspace(uint64_t n_out, uint64_t n_fc, uint32_t k);
  *     groups+1 entries, group_off[0] = 0, group_off[groups] = k).
  * Output, n_out = sum of run sizes entries: group g's merged sequence occupies
  * the positions after all runs of earlier groups, in merged order:
- *   out_src[i] = (run << 32) | position within the run,
+ *   out_src[i] = (run << 32) | position within the run (may be NULL),
  *   out_id[i]  = fc_id of that element,
  *   out_lcp[i] = LCP with the previous string of the same group (0 for the
- *                group's first).
+ *                group's first),
+ *   out_len[i] = fc_len of that element (may be NULL).
  * Equal strings keep (run, position) order.  The runs are read in place; no
  * decoded copy is made.  out_cap is the capacity of each output array
  * (CAPACITY if n_out exceeds it); *n_out_host (host, may be NULL) receives
@@ -288,7 +298,8 @@ int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_t *run_end,
                  const uint32_t *group_off, uint64_t n_fc, const uint32_t *fc_lcp,
                  const uint32_t *fc_len, const uint32_t *fc_id, const uint64_t *suf_off,
                  const uint8_t *suf, uint64_t *out_src, uint32_t *out_id, uint32_t *out_lcp,
-                 uint64_t out_cap, uint64_t *n_out_host, void *ws, size_t ws_bytes, void *stream);
+                 uint32_t *out_len, uint64_t out_cap, uint64_t *n_out_host, void *ws, size_t ws_bytes,
+                 void *stream);
 
 /* ------------------------------------------------------------ profiling */
 

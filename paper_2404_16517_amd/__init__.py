@@ -67,7 +67,8 @@ def lib():
             "ss_profile_names": ([ctypes.c_char_p, SZ], SZ),
             "ss_fc_decode": ([U32, P, P, P, P, P, U64, P, P, U64, P, SZ, P], I32),
             "ss_lcp_merge_workspace": ([U64, U64, U32], SZ),
-            "ss_lcp_merge": ([U32, P, P, U32, P, U64, P, P, P, P, P, P, P, P, U64, P, P, SZ, P], I32),
+            "ss_lcp_merge": ([U32, P, P, U32, P, U64, P, P, P, P, P, P, P, P, P, U64, P, P, SZ, P], I32),
+            "ss_dist_exact_bounded": ([P, P, P, U64, P, P], I32),
             "ss_join_group_lcps": ([P, U64, P, P, U64, U32, P, P, U32, P, P, P], I32),
             "ss_set_tuning": ([I32, I32], I32),
         }
@@ -161,6 +162,19 @@ def lcp(bytes_, offsets, perm):
     n = perm.numel()
     out = _u32(n, b.device)
     _check(lib().ss_lcp(_p(b), b.numel(), _p(o), n, _p(perm.contiguous()), _p(out), _stream(b.device)))
+    return out
+
+
+def dist_exact_bounded(perm, lcp_, d, n_strings=None):
+    """Exact distinguishing prefixes by input index from a per-position bound
+    d (dist <= d <= len), e.g. the merged fc_len values."""
+    n = perm.numel()
+    if lcp_.numel() != n or d.numel() != n:
+        raise StrsortError("perm, lcp and d must have the same length")
+    size = n if n_strings is None else int(n_strings)
+    out = torch.zeros(max(size, 0), dtype=torch.int32, device=perm.device)
+    _check(lib().ss_dist_exact_bounded(_p(perm.contiguous()), _p(lcp_.contiguous()), _p(d.contiguous()), n,
+                                       _p(out), _stream(perm.device)))
     return out
 
 
@@ -345,12 +359,15 @@ def fc_decode(run_off, fc_lcp, fc_len, suf_off, suf):
     return out[:total], out_off
 
 
-def lcp_merge(run_begin, run_end, group_off, fc_lcp, fc_len, fc_id, suf_off, suf, ws=None, n_out=None):
+def lcp_merge(run_begin, run_end, group_off, fc_lcp, fc_len, fc_id, suf_off, suf, ws=None, n_out=None,
+              with_len=False, with_src=True):
     """LCP-aware merge of the runs [run_begin[j], run_end[j]) of shared
     front-coded arrays, one merged sequence per group of runs
     (group g = runs group_off[g]..group_off[g+1]-1).  ``n_out`` (the total run
     size), when the caller knows it, saves computing it here.
-    Returns (src int64[n_out], id int32[n_out], lcp int32[n_out])."""
+    Returns (src int64[n_out] or None without ``with_src``, id int32[n_out],
+    lcp int32[n_out]), and the merged fc_len values as a fourth array with
+    ``with_len``."""
     dev = fc_lcp.device
     n_fc = fc_lcp.numel()
     rb = run_begin.to(device=dev, dtype=torch.int64).contiguous()
@@ -362,15 +379,17 @@ def lcp_merge(run_begin, run_end, group_off, fc_lcp, fc_len, fc_id, suf_off, suf
     need = lib().ss_lcp_merge_workspace(n_out, n_fc, k)
     if ws is None or ws.numel() < need:
         ws = _ws(need, dev)
-    src = torch.empty(max(n_out, 0), dtype=torch.int64, device=dev)
+    src = torch.empty(max(n_out, 0), dtype=torch.int64, device=dev) if with_src else None
     idv, lc = _u32(n_out, dev), _u32(n_out, dev)
+    ln = _u32(n_out, dev) if with_len else None
     got = ctypes.c_uint64(0)
     _check(lib().ss_lcp_merge(k, _p(rb), _p(re_), go.numel() - 1, _p(go), n_fc, _p(fc_lcp), _p(fc_len), _p(fc_id),
-                              _p(suf_off), _p(suf), _p(src), _p(idv), _p(lc), n_out, ctypes.byref(got), _p(ws),
-                              ws.numel(), _stream(dev)))
+                              _p(suf_off), _p(suf), _p(src) if with_src else None, _p(idv), _p(lc),
+                              _p(ln) if with_len else None, n_out,
+                              ctypes.byref(got), _p(ws), ws.numel(), _stream(dev)))
     if got.value != n_out:
         raise StrsortError(f"runs hold {got.value} entries, n_out = {n_out}")
-    return src, idv, lc
+    return (src, idv, lc, ln) if with_len else (src, idv, lc)
 
 
 def join_group_lcps(bytes_, offsets, order, lcp_, run_begin, run_end, group_off):

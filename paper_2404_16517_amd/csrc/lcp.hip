@@ -96,6 +96,35 @@ extern "C" int ss_lcp(const uint8_t *bytes, uint64_t N, const uint64_t *offsets,
     return SS_OK;
 }
 
+// dist from a bound d with dist <= d <= len: min(d, 1 + max(lcp[i], lcp[i+1])).
+__global__ __launch_bounds__(256) void k_dist_bounded(u32 n, const u32 *perm, const u32 *lcp, const u32 *d,
+                                                      u32 *dist)
+{
+    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const u32 a = lcp[i];
+    const u32 b = (i + 1 < n) ? lcp[i + 1] : 0u;
+    const u64 m = (u64)(a > b ? a : b) + 1;
+    const u32 di = d[i];
+    dist[perm[i]] = (u32)(m < di ? m : di);
+}
+
+extern "C" int ss_dist_exact_bounded(const uint32_t *perm, const uint32_t *lcp, const uint32_t *d, uint64_t n,
+                                     uint32_t *dist, void *stream)
+{
+    ss_clear_error();
+    if (n >= 0xFFFFFFFFull) { ss_set_error("n too large"); return SS_ERR_TOO_LARGE; }
+    if (n == 0) return SS_OK;
+    if (!perm || !lcp || !d || !dist) { ss_set_error("null pointer"); return SS_ERR_INVALID_ARG; }
+    hipStream_t st = (hipStream_t)stream;
+    {
+        SS_PROF("k_dist_exact", st, (double)n * 16.0);  // perm, lcp, d in; dist out
+        k_dist_bounded<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>((u32)n, perm, lcp, d, dist);
+    }
+    SS_CHECK_LAUNCH();
+    return SS_OK;
+}
+
 extern "C" int ss_dist_exact(const uint64_t *offsets, uint64_t n, const uint32_t *perm,
                              const uint32_t *lcp, uint32_t *dist, void *stream)
 {

@@ -980,20 +980,23 @@ __global__ __launch_bounds__(256) void k_mscan_apply(MScan S, const MOp *blk, u3
 // Source (run, position) of every output: runs sorted by their front-coded
 // start (sb, sid) locate the run of a front-coded position.
 __global__ void k_merge_out(const u32 *G, const u32 *L, u32 n_out, const u64 *sb, const u32 *sid, u32 k,
-                            const u32 *fc_id, u64 *src, u32 *id, u32 *lcp)
+                            const u32 *fc_id, const u32 *fc_len, u64 *src, u32 *id, u32 *lcp, u32 *len)
 {
     const u32 x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n_out) return;
     const u32 g = G[x];
-    u32 lo = 0, hi = k;  // largest j with sb[j] <= g
-    while (hi - lo > 1) {
-        u32 mid = (lo + hi) >> 1;
-        if (sb[mid] <= g) lo = mid;
-        else hi = mid;
+    if (src) {
+        u32 lo = 0, hi = k;  // largest j with sb[j] <= g
+        while (hi - lo > 1) {
+            u32 mid = (lo + hi) >> 1;
+            if (sb[mid] <= g) lo = mid;
+            else hi = mid;
+        }
+        src[x] = ((u64)sid[lo] << 32) | (u64)(g - sb[lo]);
     }
-    src[x] = ((u64)sid[lo] << 32) | (u64)(g - sb[lo]);
     id[x] = fc_id[g];
     lcp[x] = L[x];
+    if (len) len[x] = fc_len[g];
 }
 
 // Host-plan header: [0] check flag, [1] literal-buffer size, [2, 2+k) run
@@ -1070,8 +1073,8 @@ extern "C" size_t ss_lcp_merge_workspace(uint64_t n_out, uint64_t n_fc, uint32_t
 extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_t *run_end, uint32_t groups,
                             const uint32_t *group_off, uint64_t n_fc, const uint32_t *fc_lcp, const uint32_t *fc_len,
                             const uint32_t *fc_id, const uint64_t *suf_off, const uint8_t *suf, uint64_t *out_src,
-                            uint32_t *out_id, uint32_t *out_lcp, uint64_t out_cap, uint64_t *n_out_host, void *ws,
-                            size_t ws_bytes, void *stream)
+                            uint32_t *out_id, uint32_t *out_lcp, uint32_t *out_len, uint64_t out_cap,
+                            uint64_t *n_out_host, void *ws, size_t ws_bytes, void *stream)
 {
     ss_clear_error();
     if (n_fc >= 0xFFFFFFFFull) { ss_set_error("n_fc too large"); return SS_ERR_TOO_LARGE; }
@@ -1158,7 +1161,7 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
                      (unsigned long long)out_cap);
         return SS_ERR_CAPACITY;
     }
-    if (!have_fc || !out_src || !out_id || !out_lcp) {
+    if (!have_fc || !out_id || !out_lcp) {
         ss_set_error("lcp_merge: null array");
         return SS_ERR_INVALID_ARG;
     }
@@ -1290,8 +1293,8 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
         std::swap(F, Fo);
         std::swap(K, Ko);
     }
-    k_merge_out<<<(unsigned)ceil_div(n_out, 256), 256, 0, st>>>(G, L, (u32)n_out, w.sb, w.sid, kne, fc_id,
-                                                                out_src, out_id, out_lcp);
+    k_merge_out<<<(unsigned)ceil_div(n_out, 256), 256, 0, st>>>(G, L, (u32)n_out, w.sb, w.sid, kne, fc_id, fc_len,
+                                                                out_src, out_id, out_lcp, out_len);
     SS_CHECK_LAUNCH();
     SS_HIP(hipStreamSynchronize(st));  // the host plan vectors must outlive their copies
     return SS_OK;

@@ -62,10 +62,10 @@ def test_argument_errors_without_device():
     assert L.ss_select_splitters_batch(P(8), 10, P(8), 0, 4, P(8), P(8), 256, None) == -1
     assert L.ss_select_splitters_batch(P(8), 10, P(8), 2, 4, P(8), P(8), 0, None) == -2
     # merge needs 1 <= k <= 65536
-    assert L.ss_lcp_merge(0, P(8), P(8), 1, P(8), 1, P(8), P(8), P(8), P(8), P(8), P(8), P(8), P(8), 1, None,
-                          None, 0, None) == -1
-    assert L.ss_lcp_merge(4, P(8), P(8), 0, P(8), 1, P(8), P(8), P(8), P(8), P(8), P(8), P(8), P(8), 1, None,
-                          None, 0, None) == -1
+    assert L.ss_lcp_merge(0, P(8), P(8), 1, P(8), 1, P(8), P(8), P(8), P(8), P(8), P(8), P(8), P(8), None, 1,
+                          None, None, 0, None) == -1
+    assert L.ss_lcp_merge(4, P(8), P(8), 0, P(8), 1, P(8), P(8), P(8), P(8), P(8), P(8), P(8), P(8), None, 1,
+                          None, None, 0, None) == -1
 
 
 def test_tuning_validation():

@@ -653,11 +653,18 @@ def _pipeline(sets, bounds, spl, pdms):
     run_begin = ro[:, :-1].t().reshape(-1)      # group j = bucket j, run i = set i
     run_end = ro[:, 1:].t().reshape(-1)
     group_off = torch.arange(0, p * r + 1, p, dtype=torch.int32, device=DEV)
-    _, order, mlcp = ss.lcp_merge(run_begin, run_end, group_off, fc["lcp"], fc["len"], fc["id"],
-                                  fc["suf_off"], fc["suf"], n_out=sets.n)
+    src, order, mlcp, mlen = ss.lcp_merge(run_begin, run_end, group_off, fc["lcp"], fc["len"], fc["id"],
+                                          fc["suf_off"], fc["suf"], n_out=sets.n, with_len=True)
+    # out_len is the fc_len entry of each merged element
+    rb = run_begin.cpu().numpy()
+    S = u64(src)
+    pos = rb[(S >> np.uint64(32)).astype(np.int64)] + (S & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    np.testing.assert_array_equal(u32(mlen), u32(fc["len"])[pos])
     ss.join_group_lcps(g.bytes, g.offsets, order, mlcp, run_begin, run_end, group_off)
     dist_x = ss.dist_exact(g.offsets, order, mlcp)
+    dist_b = ss.dist_exact_bounded(order, mlcp, mlen)
     torch.cuda.synchronize()
+    np.testing.assert_array_equal(u32(dist_b), u32(dist_x))
     return order, mlcp, dist_x
 
 
