@@ -365,12 +365,13 @@ __device__ __forceinline__ u32 digit_of(u64 k, u32 level) { return (u32)(k >> (5
 // Per-tile histogram of the segment's current byte, digit-major per segment:
 // hist[256*tstart[s] + d*T_s + lt].  Also the segment's min and max key.
 __global__ __launch_bounds__(NT) void k_hist(const Seg *segs, const u32 *tstart, u32 nseg, u32 tile,
-                                             const u64 *keys, u32 *hist, u64 *smin, u64 *smax)
+                                             const u64 *keyA, const u64 *keyB, u32 *hist, u64 *smin, u64 *smax)
 {
     __shared__ u32 h[256];
     const u32 t = blockIdx.x;
     const u32 s = seg_of_tile(tstart, nseg, t);
     const Seg g = segs[s];
+    const u64 *keys = (g.aux & SEG_INB) ? keyB : keyA;
     const u32 T = tstart[s + 1] - tstart[s];
     const u32 lt = t - tstart[s];
     const u32 level = g.aux & 15;
@@ -406,6 +407,7 @@ struct EmitOut {
     uint2 *bnd;
     u32 *ctr;
     u8 *scat;
+    u8 *kinds;
     u32 small_max;
     u32 tile;
 };
@@ -427,7 +429,10 @@ __device__ __forceinline__ EmitItem emit_item(const Seg *segs, const u32 *tstart
     EmitItem it{K_NONE, Seg{0, 0, 0, 0}, false, make_uint2(0, 0)};
     const Seg g = segs[s];
     const u32 level = g.aux & 15;
+    const u32 pf = g.aux & SEG_INB;  // where the segment's data is now
     const u64 mn = smin[s], mx = smax[s];
+    // next-round and equal-string runs (and singletons) end in A: the settle
+    // pass copies them there; the other kinds carry their buffer flag
     if (mn == mx) {
         // one key for the whole segment (all 8 bytes): continue next round,
         // or equal strings
@@ -443,10 +448,11 @@ __device__ __forceinline__ EmitItem emit_item(const Seg *segs, const u32 *tstart
     if (fb > level) {
         // bytes level..fb-1 are common to the whole segment: no scatter needed
         *scat = false;
-        if (d == 0) { it.kind = K_LARGE; it.ns = Seg{g.begin, g.end, g.depth, fb}; }
+        if (d == 0) { it.kind = K_LARGE; it.ns = Seg{g.begin, g.end, g.depth, fb | pf}; }
         return it;
     }
     *scat = true;
+    const u32 cf = pf ? 0u : (u32)SEG_INB;  // the scatter writes the other arrays
     const u32 ts = tstart[s];
     const u32 T = tstart[s + 1] - ts;
     const u32 e = 256u * ts + d * T;
@@ -456,7 +462,7 @@ __device__ __forceinline__ EmitItem emit_item(const Seg *segs, const u32 *tstart
     const u32 sb = g.begin + start, se = sb + cnt;
     it.bnd = cnt > 0 && start > 0;
     it.bv = make_uint2(sb, g.depth);
-    it.ns = Seg{sb, se, g.depth, 0};
+    it.ns = Seg{sb, se, g.depth, cf};
     if (cnt >= 2) {
         if (level == 7) {
             if (d == 8) { it.kind = K_NEXT; it.ns = Seg{sb, se, g.depth + 7, SEG_SKIP}; }
@@ -467,7 +473,7 @@ __device__ __forceinline__ EmitItem emit_item(const Seg *segs, const u32 *tstart
             it.kind = K_SMALL;
         } else {
             it.kind = K_LARGE;
-            it.ns.aux = level + 1;
+            it.ns.aux = (level + 1) | cf;
         }
     }
     return it;
@@ -499,6 +505,7 @@ __global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart
         bool sc = false;
         it[q] = emit_item(segs, tstart, hist, smin, smax, o, s, d, &sc);
         if (d == 0) o.scat[s] = sc ? 1 : 0;
+        o.kinds[256u * s + d] = (u8)it[q].kind;
         const EmitItem &x = it[q];
         const u32 cnt = x.ns.end - x.ns.begin;
         if (x.bnd) atomicAdd(&lcount[0], 1u);
@@ -539,10 +546,11 @@ __global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart
     }
 }
 
-// Stable scatter of (key, payload) by the current byte into the B arrays.
+// Stable scatter of (key, payload) by the current byte into the other pair
+// of arrays (A -> B or B -> A, by the segment's flag).
 __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tstart, u32 nseg, u32 tile,
-                                                const u32 *hist, const u8 *scat, const u64 *keyA,
-                                                const u32 *valA, u64 *keyB, u32 *valB)
+                                                const u32 *hist, const u8 *scat, u64 *keyA, u32 *valA,
+                                                u64 *keyB, u32 *valB)
 {
     __shared__ u32 run[256];
     __shared__ u32 wcnt[NT / 64][256];
@@ -550,6 +558,11 @@ __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tsta
     const u32 s = seg_of_tile(tstart, nseg, t);
     if (!scat[s]) return;
     const Seg g = segs[s];
+    const bool inb = g.aux & SEG_INB;
+    const u64 *ksrc = inb ? keyB : keyA;
+    const u32 *vsrc = inb ? valB : valA;
+    u64 *kdst = inb ? keyA : keyB;
+    u32 *vdst = inb ? valA : valB;
     const u32 ts = tstart[s];
     const u32 T = tstart[s + 1] - ts;
     const u32 lt = t - ts;
@@ -565,8 +578,8 @@ __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tsta
         u64 k = 0;
         u32 v = 0;
         if (valid) {
-            k = keyA[i];
-            v = valA[i];
+            k = ksrc[i];
+            v = vsrc[i];
         }
         const u32 d = digit_of(k, level);
 #pragma unroll
@@ -589,27 +602,45 @@ __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tsta
         __syncthreads();
         if (valid) {
             const u32 dst = wcnt[wid][d] + rank;
-            keyB[dst] = k;
-            valB[dst] = v;
+            kdst[dst] = k;
+            vdst[dst] = v;
         }
         __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(NT) void k_copyback(const Seg *segs, const u32 *tstart, u32 nseg, u32 tile,
-                                                 const u8 *scat, const u64 *keyB, const u32 *valB,
-                                                 u64 *keyA, u32 *valA)
+// After a level: buckets that no later kernel rewrites (singletons, runs for
+// the next round, equal strings) are copied to A when the level left them in
+// B.  Scattered segments read back their digits to find them; an unscattered
+// segment that became such a run is copied whole.
+__global__ __launch_bounds__(NT) void k_settle(const Seg *segs, const u32 *tstart, u32 nseg, u32 tile,
+                                               const u8 *scat, const u8 *kinds, const u64 *keyB,
+                                               const u32 *valB, u64 *keyA, u32 *valA)
 {
     const u32 t = blockIdx.x;
     const u32 s = seg_of_tile(tstart, nseg, t);
-    if (!scat[s]) return;
     const Seg g = segs[s];
+    const bool inb = g.aux & SEG_INB;
+    const u32 level = g.aux & 15;
     const u32 lt = t - tstart[s];
     const u32 b0 = g.begin + lt * tile;
     const u32 b1 = min(g.end, b0 + tile);
-    for (u32 i = b0 + threadIdx.x; i < b1; i += NT) {
-        keyA[i] = keyB[i];
-        valA[i] = valB[i];
+    const u8 *kd = kinds + 256u * s;
+    if (scat[s]) {
+        if (inb) return;  // scattered into A
+        for (u32 i = b0 + threadIdx.x; i < b1; i += NT) {
+            const u64 k = keyB[i];
+            const u32 c = kd[digit_of(k, level)];
+            if (c == K_NONE || c == K_NEXT || c == K_IDENT) {
+                keyA[i] = k;
+                valA[i] = valB[i];
+            }
+        }
+    } else if (inb && (kd[0] == K_NEXT || kd[0] == K_IDENT)) {
+        for (u32 i = b0 + threadIdx.x; i < b1; i += NT) {
+            keyA[i] = keyB[i];
+            valA[i] = valB[i];
+        }
     }
 }
 
@@ -648,8 +679,8 @@ __device__ __forceinline__ bool lds_greater(u16 sa, u64 ka, u32 va, u16 sb, u64 
 // sizes <= H a tile holds < 2H elements.  Sorted by (segment, key, payload)
 // with a bitonic network in LDS.
 __global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32 *pref, u32 nsmall,
-                                                     u32 H, u64 *keys, u32 *vals, u32 *lcp, Seg *next,
-                                                     u32 *ctr)
+                                                     u32 H, u64 *keys, u32 *vals, const u64 *keyB,
+                                                     const u32 *valB, u32 *lcp, Seg *next, u32 *ctr)
 {
     __shared__ u64 skey[LDS_CAP];
     __shared__ u32 sval[LDS_CAP];
@@ -657,6 +688,7 @@ __global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32
     __shared__ u32 spref[LDS_CAP / 2 + 1];
     __shared__ u32 sbeg[LDS_CAP / 2];
     __shared__ u32 sdep[LDS_CAP / 2];
+    __shared__ u8 sinb[LDS_CAP / 2];
     __shared__ Seg nq[LDS_CAP / 2];  // next-round segments found in this tile
     __shared__ u32 nq_count, nq_tiles, nq_elems, nq_base;
     const u32 t = blockIdx.x;
@@ -681,6 +713,7 @@ __global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32
         Seg g = small[j0 + k];
         sbeg[k] = g.begin;
         sdep[k] = g.depth;
+        sinb[k] = (g.aux & SEG_INB) ? 1 : 0;
     }
     __syncthreads();
     u32 P = 2;
@@ -690,8 +723,8 @@ __global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32
             u32 a = 0, b = ns;  // largest k with spref[k] <= e
             while (b - a > 1) { u32 m = (a + b) >> 1; if (spref[m] <= e) a = m; else b = m; }
             const u32 pos = sbeg[a] + (e - spref[a]);
-            skey[e] = keys[pos];
-            sval[e] = vals[pos];
+            skey[e] = sinb[a] ? keyB[pos] : keys[pos];  // read where the segment is, write A
+            sval[e] = sinb[a] ? valB[pos] : vals[pos];
             sseg[e] = (u16)a;
         } else {
             skey[e] = ~0ull;
@@ -804,8 +837,8 @@ __device__ __forceinline__ u32 hibit(u64 m) { return 63u - (u32)__clzll(m); }
 // (key, payload) in registers (element e = lane + 64 r, r = 0, 1), then LCPs
 // and next-round runs as in the LDS sort.  Next-round segments are collected
 // per workgroup and published with one atomic per counter.
-__global__ __launch_bounds__(256) void k_wave_sort(const Seg *tiny, u32 ntiny, u64 *keys, u32 *vals, u32 *lcp,
-                                                   Seg *next, u32 *ctr)
+__global__ __launch_bounds__(256) void k_wave_sort(const Seg *tiny, u32 ntiny, u64 *keys, u32 *vals,
+                                                   const u64 *keyB, const u32 *valB, u32 *lcp, Seg *next, u32 *ctr)
 {
     __shared__ Seg nq[WS_SPB * (WS_MAX / 2)];
     __shared__ u32 nq_count, nq_tiles, nq_elems, nq_base;
@@ -820,8 +853,10 @@ __global__ __launch_bounds__(256) void k_wave_sort(const Seg *tiny, u32 ntiny, u
         const u32 e0 = lane, e1 = lane + 64;
         u64 k0 = ~0ull, k1 = ~0ull;
         u32 v0 = 0xFFFFFFFFu, v1 = 0xFFFFFFFFu;
-        if (e0 < cnt) { k0 = keys[g.begin + e0]; v0 = vals[g.begin + e0]; }
-        if (e1 < cnt) { k1 = keys[g.begin + e1]; v1 = vals[g.begin + e1]; }
+        const u64 *ks = (g.aux & SEG_INB) ? keyB : keys;  // read where the segment is, write A
+        const u32 *vs = (g.aux & SEG_INB) ? valB : vals;
+        if (e0 < cnt) { k0 = ks[g.begin + e0]; v0 = vs[g.begin + e0]; }
+        if (e1 < cnt) { k1 = ks[g.begin + e1]; v1 = vs[g.begin + e1]; }
         u32 P = 2;
         while (P < cnt) P <<= 1;
         for (u32 k = 2; k <= P; k <<= 1) {
@@ -922,6 +957,7 @@ void sort_ws_layout(u64 n, SortWs *w, WsArena *a, WsCounter *c)
     TAKE(smin, u64, nlarge);
     TAKE(smax, u64, nlarge);
     TAKE(scat, u8, nlarge);
+    TAKE(kinds, u8, 256 * nlarge);
     TAKE(tstart, u32, nseg + 1);
     TAKE(spref, u32, nseg + 1);
     TAKE(hist, u32, nscan);
@@ -977,11 +1013,11 @@ int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
             SS_TRY(ss_scan_exclusive<u32>(w.tstart, w.tstart, nlarge, (u32 *)w.scan_scratch, st));
             {
                 SS_PROF("k_hist", st, (double)lelem * 8.0);  // read the keys
-                k_hist<<<ltiles, NT, 0, st>>>(LA, w.tstart, nlarge, TL, w.keyA, w.hist, w.smin, w.smax);
+                k_hist<<<ltiles, NT, 0, st>>>(LA, w.tstart, nlarge, TL, w.keyA, w.keyB, w.hist, w.smin, w.smax);
             }
             SS_CHECK_LAUNCH();
             SS_TRY(ss_scan_exclusive<u32>(w.hist, w.hist, (u64)ltiles * 256, (u32 *)w.scan_scratch, st));
-            EmitOut eo{w.tiny, w.small, LB, w.nxt, w.ident, w.bnd, w.ctr, w.scat, SM, TL};
+            EmitOut eo{w.tiny, w.small, LB, w.nxt, w.ident, w.bnd, w.ctr, w.scat, w.kinds, SM, TL};
             k_emit<<<(unsigned)ceil_div(nlarge, EPB), 256, 0, st>>>(LA, w.tstart, nlarge, w.hist, w.smin, w.smax,
                                                                      eo);
             SS_CHECK_LAUNCH();
@@ -992,8 +1028,9 @@ int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
             }
             SS_CHECK_LAUNCH();
             {
-                SS_PROF("k_copyback", st, (double)lelem * 24.0);
-                k_copyback<<<ltiles, NT, 0, st>>>(LA, w.tstart, nlarge, TL, w.scat, w.keyB, w.valB, w.keyA, J.vals);
+                SS_PROF("k_settle", st, (double)lelem * 8.0);  // at most the scattered keys read back
+                k_settle<<<ltiles, NT, 0, st>>>(LA, w.tstart, nlarge, TL, w.scat, w.kinds, w.keyB, w.valB, w.keyA,
+                                                J.vals);
             }
             SS_CHECK_LAUNCH();
             SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, st));
@@ -1006,8 +1043,8 @@ int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
         if (ntiny > 0) {
             {
                 SS_PROF("k_wave_sort", st, (double)h[C_TINYN] * 28.0);  // key+payload in/out, LCP out
-                k_wave_sort<<<(unsigned)ceil_div(ntiny, WS_SPB), 256, 0, st>>>(w.tiny, ntiny, w.keyA, J.vals, lcp,
-                                                                               w.nxt, w.ctr);
+                k_wave_sort<<<(unsigned)ceil_div(ntiny, WS_SPB), 256, 0, st>>>(w.tiny, ntiny, w.keyA, J.vals, w.keyB,
+                                                                               w.valB, lcp, w.nxt, w.ctr);
             }
             SS_CHECK_LAUNCH();
         }
@@ -1019,8 +1056,8 @@ int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
             const u32 ntile = (u32)ceil_div(h[C_SMALLN], SM);
             {
                 SS_PROF("k_lds_sort", st, (double)h[C_SMALLN] * 28.0);  // key+payload in/out, LCP out
-                k_lds_sort<<<ntile, LDS_NT, 0, st>>>(w.small, w.spref, nsmall, SM, w.keyA, J.vals, lcp, w.nxt,
-                                                      w.ctr);
+                k_lds_sort<<<ntile, LDS_NT, 0, st>>>(w.small, w.spref, nsmall, SM, w.keyA, J.vals, w.keyB, w.valB,
+                                                      lcp, w.nxt, w.ctr);
             }
             SS_CHECK_LAUNCH();
         }

@@ -4,11 +4,13 @@
 
 // A contiguous range [begin, end) of sorted positions whose strings share a
 // known prefix of `depth` bytes.  aux: bits 0..3 = current key byte of a radix
-// pass, bit 4 = compute the common-prefix skip first.
+// pass, bit 4 = compute the common-prefix skip first, bit 5 = the segment's
+// keys and payload are in the B arrays (radix levels alternate between A and
+// B; everything final is in A).
 struct Seg {
     u32 begin, end, depth, aux;
 };
-enum { SEG_SKIP = 16 };
+enum { SEG_SKIP = 16, SEG_INB = 32 };
 
 struct SortWs {
     u64 *keyA, *keyB, *mword;  // mword, mpr: each member's first mismatch with its segment's first string
@@ -19,6 +21,7 @@ struct SortWs {
     u32 *skipv;
     u64 *smin, *smax;
     u8 *scat;
+    u8 *kinds;  // per radix segment and digit: what the bucket became
     u32 *tstart, *spref, *hist;
     u64 *scan_scratch;
     u32 *ctr;
