@@ -340,18 +340,48 @@ __global__ __launch_bounds__(256) void k_hash_round(const u32 *act, const u32 *c
     const u32 ntiles = (A + 15) / 16;
     const u32 wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
     const u64 x0 = lprev & ~63ull;
+    // Software pipeline over this wave's tiles: the list entry of the tile
+    // after next and the offsets and state of the next tile are loaded while
+    // the current tile's bytes are in flight.  Indices past the list are
+    // clamped to its last entry so that the loads need no branch.
+    auto entry = [&](u32 tile) -> u32 {
+        const u32 jj = tile * 16 + col;
+        const u32 jc = jj < A ? jj : A - 1;
+        return act ? act[jc] : jc;
+    };
+    u32 i_cur = 0, i_nxt = 0;
+    u64 o_cur = 0, e_cur = 0, G_cur = 0;
+    if (wave < ntiles) {
+        i_cur = entry(wave);
+        o_cur = off[i_cur];
+        e_cur = off[i_cur + 1];
+        if (lprev) G_cur = state[i_cur];
+        i_nxt = entry(wave + nwaves < ntiles ? wave + nwaves : wave);
+    }
     for (u32 tile = wave; tile < ntiles; tile += nwaves) {  // uniform over the wavefront
         const u32 j = tile * 16 + col;
         const bool valid = j < A;
-        u32 i = 0;
-        u64 o = 0, len = 0, m = 0, G = 0;
-        if (valid) {
-            i = act ? act[j] : j;
-            o = off[i];
-            len = off[i + 1] - o;
-            m = len < lend ? len : lend;
-            if (lprev) G = state[i];
+        const u32 i = i_cur;
+        const u64 o = o_cur;
+        const u64 len = valid ? e_cur - o_cur : 0;
+        const u64 m = len < lend ? len : lend;
+        u64 G = valid ? G_cur : 0;
+        // next tile's offsets and state, the entry after that
+        const bool more = tile + nwaves < ntiles;
+        const u32 i_n = i_nxt;
+        u64 o_n = 0, e_n = 0, G_n = 0;
+        u32 i_nn = i_n;
+        if (more) {
+            o_n = off[i_n];
+            e_n = off[i_n + 1];
+            if (lprev) G_n = state[i_n];
+            i_nn = entry(tile + 2 * nwaves < ntiles ? tile + 2 * nwaves : tile + nwaves);
         }
+        i_cur = i_n;
+        o_cur = o_n;
+        e_cur = e_n;
+        G_cur = G_n;
+        i_nxt = i_nn;
         u64 xmax = m;
 #pragma unroll
         for (int s2 = 1; s2 < 16; s2 <<= 1) {
