@@ -182,9 +182,38 @@ __device__ __forceinline__ bool first_slot(u32 g, u32 slot, u32 *r, u32 *d)
     return false;
 }
 
-__global__ __launch_bounds__(256) void k_hash_first(u32 n, const u8 *bytes, u64 N, const u64 *off, PreLens P,
-                                                    u32 bits, BPow bp, FirstW fw, u64 *state, u64 *pre)
+// Round flags, three words per round: [0] minimum key, [1] maximum key,
+// [2] nonzero if some string is no longer than the round's prefix length.
+// Initialised by k_flag_init; all keys are equal iff min == max.
+__device__ __forceinline__ void flags_reduce16(u64 &mn, u64 &mx, u64 &sh)
 {
+#pragma unroll
+    for (int d = 1; d < 16; d <<= 1) {
+        const u64 a = __shfl_xor(mn, d), b = __shfl_xor(mx, d), c = __shfl_xor(sh, d);
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+        sh |= c;
+    }
+}
+
+__device__ __forceinline__ void flags_commit(u64 *f, u64 mn, u64 mx, u64 sh)
+{
+    if (mn != ~0ull) atomicMin((unsigned long long *)&f[0], (unsigned long long)mn);
+    if (mx != 0ull) atomicMax((unsigned long long *)&f[1], (unsigned long long)mx);
+    if (sh) atomicOr((unsigned long long *)&f[2], 1ull);
+}
+
+__global__ void k_flag_init(u64 *f, u32 words)
+{
+    const u32 t = threadIdx.x;
+    if (t < words) f[t] = (t % 3 == 0) ? ~0ull : 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_hash_first(u32 n, const u8 *bytes, u64 N, const u64 *off, PreLens P,
+                                                    u32 bits, BPow bp, FirstW fw, u64 *state, u64 *pre, u64 *fl)
+{
+    // this lane's round flags: round g, and round 4 in lane group 3
+    u64 fmn[2] = {~0ull, ~0ull}, fmx[2] = {0, 0}, fsh[2] = {0, 0};
     const u32 lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
     const u64 W = P.l[P.count - 1];
     // weight operand (A): row col of each tile, k-group g = prefix bytes [16g, 16g+16).
@@ -274,11 +303,21 @@ __global__ __launch_bounds__(256) void k_hash_first(u32 n, const u8 *bytes, u64 
                     const u64 lim = k == 0 ? lg : lr[4];
                     const u64 m = len[f] < lim ? len[f] : lim;
                     const u64 H = mulmod61(Gr, bp.p[(m + 3) / 4]);
-                    pre[(u64)r * n + i] = kr_finish(H, m, bits);
+                    const u64 key = kr_finish(H, m, bits);
+                    pre[(u64)r * n + i] = key;
                     if (r == P.count - 1) state[i] = Gr;  // later rounds continue from G
+                    fmn[k] = key < fmn[k] ? key : fmn[k];
+                    fmx[k] = key > fmx[k] ? key : fmx[k];
+                    if (len[f] <= lim) fsh[k] = 1;
                 }
             }
         }
+    }
+#pragma unroll
+    for (int k = 0; k < 2; k++) flags_reduce16(fmn[k], fmx[k], fsh[k]);
+    if (col == 0) {
+        if (g < P.count) flags_commit(fl + 3 * g, fmn[0], fmx[0], fsh[0]);
+        if (g == 3 && P.count > 4) flags_commit(fl + 12, fmn[1], fmx[1], fsh[1]);
     }
 }
 
@@ -313,8 +352,10 @@ __device__ __forceinline__ u64 kr_pow(u64 L, const RoundW &rw)
 
 __global__ __launch_bounds__(256) void k_hash_round(const u32 *act, const u32 *cnt, const u8 *bytes, u64 N,
                                                     const u64 *off, u64 lprev, u64 l1, u64 l2, u32 bits,
-                                                    u64 *state, u64 *keys1, u64 *keys2, RoundW rw)
+                                                    u64 *state, u64 *keys1, u64 *keys2, RoundW rw, u64 *rf)
 {
+    // round flags of this lane's keys (rounds l1 and l2), committed per wavefront
+    u64 fmn[2] = {~0ull, ~0ull}, fmx[2] = {0, 0}, fsh[2] = {0, 0};
     __shared__ v4i wtab[RW_STEPS * 64];  // [step of the chunk][lane]: the weight operand
     const u32 lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
     for (u32 e = threadIdx.x; e < RW_STEPS * 64; e += blockDim.x) {
@@ -446,17 +487,32 @@ __global__ __launch_bounds__(256) void k_hash_round(const u32 *act, const u32 *c
         }
         if (valid && g == 0) {
             state[i] = G;
+            u64 k1, k2 = 0;
             if (l2) {
                 const u64 m1 = len < l1 ? len : l1;
                 const u64 H1 = mulmod61(m <= l1 ? G : G1, m1 == l1 ? rw.bl1 : kr_pow((m1 + 3) / 4, rw));
                 const u64 H2 = mulmod61(G, m == l2 ? rw.bl2 : kr_pow((m + 3) / 4, rw));
-                keys1[j] = kr_finish(H1, m1, bits);
-                keys2[j] = kr_finish(H2, m, bits);
+                k1 = kr_finish(H1, m1, bits);
+                k2 = kr_finish(H2, m, bits);
+                keys1[j] = k1;
+                keys2[j] = k2;
+                fmn[1] = k2 < fmn[1] ? k2 : fmn[1];
+                fmx[1] = k2 > fmx[1] ? k2 : fmx[1];
+                if (len <= l2) fsh[1] = 1;
             } else {
                 const u64 H = mulmod61(G, m == l1 ? rw.bl1 : kr_pow((m + 3) / 4, rw));
-                keys1[j] = kr_finish(H, m, bits);
+                k1 = kr_finish(H, m, bits);
+                keys1[j] = k1;
             }
+            fmn[0] = k1 < fmn[0] ? k1 : fmn[0];
+            fmx[0] = k1 > fmx[0] ? k1 : fmx[0];
+            if (len <= l1) fsh[0] = 1;
         }
+    }
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        flags_reduce16(fmn[k], fmx[k], fsh[k]);  // lane group 0 holds the values
+        if (lane == 0 && (k == 0 || l2)) flags_commit(rf + 3 * k, fmn[k], fmx[k], fsh[k]);
     }
 }
 
@@ -481,25 +537,9 @@ __device__ __forceinline__ u64 key_of(const u64 *keys, int kin, u32 i, u32 j) { 
 
 __global__ void k_store_u32(u32 *p, u32 v) { *p = v; }
 
-// For every round hashed in the first pass, over all strings: flags[2r] = 1 if
-// some key differs from string 0's, flags[2r+1] = 1 if some string has
-// length <= l_r.  A round with neither (and n >= 2) changes nothing.
-__global__ __launch_bounds__(256) void k_pre_flags(const u64 *pre, u32 n, const u64 *off, PreLens P, u32 *flags)
-{
-    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
-    const u64 len = i < n ? off[i + 1] - off[i] : 0;
-    for (u32 r = 0; r < P.count; r++) {
-        const bool d = i < n && pre[(u64)r * n + i] != pre[(u64)r * n];
-        const bool sh = i < n && len <= P.l[r];
-        const u64 bd = __ballot(d), bs = __ballot(sh);
-        if ((threadIdx.x & 63) == 0) {
-            if (bd) flags[2 * r] = 1u;
-            if (bs) flags[2 * r + 1] = 1u;
-        }
-    }
-}
-
-// The same two flags for one round over the active list.
+// For one round over the active list: flags[0] = 1 if some key differs from
+// the first entry's, flags[1] = 1 if some string has length <= l.  A round
+// with neither (and at least two strings) changes nothing.
 __global__ __launch_bounds__(256) void k_flags(const u64 *keys, int kin, const u32 *act, const u32 *cnt,
                                                const u64 *off, u64 l, u32 *flags)
 {
@@ -596,9 +636,15 @@ __global__ __launch_bounds__(256) void k_dedup(const u64 *keys, int kin, const u
     }
 }
 
+// hdr: words 0..7 hold the u32 counters, 8..22 the first-pass round flags (three
+// per round), 23..28 the flags of a hash launch (rounds l and 2l); the host
+// reads them back together.
+#define HDR_WORDS 32
+#define HDR_FIRST 8
+#define HDR_ROUND (HDR_FIRST + 3 * PRE_SLOTS)
 struct PdWs {
     u32 *actA, *actB, *ctr;
-    u64 *keys, *keysB, *keysC, *state, *pre, *tab;
+    u64 *hdr, *keys, *keysB, *keysC, *state, *pre, *tab;
 };
 
 static u32 tab_log(u64 A)
@@ -615,10 +661,11 @@ static void pd_layout(u64 n, PdWs *w, WsArena *a, WsCounter *c)
         if (a) w->field = a->take<T>(cnt);       \
         else c->take<T>(cnt);                    \
     } while (0)
-    PT(actA, u32, n); PT(actB, u32, n); PT(ctr, u32, 16); PT(keys, u64, n); PT(keysB, u64, n);
+    PT(actA, u32, n); PT(actB, u32, n); PT(hdr, u64, HDR_WORDS); PT(keys, u64, n); PT(keysB, u64, n);
     PT(keysC, u64, n); PT(state, u64, n);
     PT(pre, u64, (u64)PRE_SLOTS * n); PT(tab, u64, 1ull << tab_log(n));
 #undef PT
+    if (a) w->ctr = (u32 *)w->hdr;
 }
 
 extern "C" size_t ss_dist_prefix_workspace(uint64_t n)
@@ -720,6 +767,7 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
     // counters: [0], [1] active-list lengths (current / next, swapped per
     // round), [2], [3] the round's flags, [4..] flags of the first-pass rounds
     u32 *ctr = w.ctr;
+    u64 *fl_first = w.hdr + HDR_FIRST, *fl_round = w.hdr + HDR_ROUND;
     k_store_u32<<<1, 1, 0, st>>>(ctr, (u32)n);
     SS_CHECK_LAUNCH();
     // rounds whose prefix length is at most PRE_MAX are hashed in one first pass
@@ -733,14 +781,18 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
                     (double)n * (double)P.l[P.count - 1] + (double)n * (24.0 + 8.0 * P.count));
             const u64 tiles = ceil_div(n, 16 * HF_T);
             const unsigned blocks = (unsigned)(ceil_div(tiles, 4) < 2048 ? ceil_div(tiles, 4) : 2048);
+            k_flag_init<<<1, 64, 0, st>>>(fl_first, 3 * P.count);
+            SS_CHECK_LAUNCH();
             k_hash_first<<<blocks, 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits, bp, first_weights(P),
-                                                 w.state, w.pre);
+                                                 w.state, w.pre, fl_first);
         }
         SS_CHECK_LAUNCH();
-        SS_HIP(hipMemsetAsync(ctr + 4, 0, sizeof(u32) * 2 * P.count, st));
-        k_pre_flags<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(w.pre, (u32)n, offsets, P, ctr + 4);
-        SS_CHECK_LAUNCH();
-        SS_TRY(ss_read_u32(ctr + 4, pf, 2 * P.count, st));
+        u64 F[3 * PRE_SLOTS];
+        SS_TRY(ss_read_u64(fl_first, F, 3 * P.count, st));
+        for (u32 r = 0; r < P.count; r++) {
+            pf[2 * r] = F[3 * r] != F[3 * r + 1];
+            pf[2 * r + 1] = F[3 * r + 2] != 0;
+        }
     }
     u32 Ah = (u32)n;           // active count (exact after each flag read)
     const u32 *act = nullptr;  // the active strings (NULL = all, in input order)
@@ -752,16 +804,28 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
     // this round's keys (list order) from a two-round pass: written to keysB,
     // compacted into keysC when the round before them shrank the list
     const u64 *pend = nullptr;
+    // flags of the pending round from the two-round launch, valid while the
+    // list has not changed since (the round in between finished nothing)
+    bool pend_flags = false;
+    u32 pend_differ = 0, pend_shrt = 0;
     for (;;) {
         const u64 *keys;
         const u64 *pend_next = nullptr;
         int kin = 0;
         u64 lhashed = 0;  // prefix length of this round's hash launch (0: none)
+        bool fused_flags = false;  // this round's flags come from the hash launch
+        bool have_flags = false;   // ... or from the previous launch (pending round)
+        u32 differ = 0, shrt = 0;
         if (rounds < P.count) {
             keys = w.pre + (u64)rounds * n;
             kin = 1;
         } else if (pend) {
             keys = pend;
+            if (pend_flags) {
+                have_flags = true;
+                differ = pend_differ;
+                shrt = pend_shrt;
+            }
         } else {
             // When the previous round finished nothing, hash this round and the
             // next from one read (the next round's keys wait in keysB).
@@ -772,19 +836,41 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
                 SS_PROF("k_hash_round", st, 0.0);
                 const u64 tiles = ceil_div(Ah, 16);
                 const u64 nb = ceil_div(tiles, 4);
+                k_flag_init<<<1, 64, 0, st>>>(fl_round, 6);
                 k_hash_round<<<(unsigned)(nb < 1024 ? (nb ? nb : 1) : 1024), 256, 0, st>>>(
                     act, ctr + ci, bytes, N, offsets, lprev, l, two ? 2 * l : 0, hash_bits, w.state, w.keys,
-                    w.keysB, round_weights(lprev, l, two ? 2 * l : 0));
+                    w.keysB, round_weights(lprev, l, two ? 2 * l : 0), fl_round);
             }
             SS_CHECK_LAUNCH();
             keys = w.keys;
             lhashed = two ? 2 * l : l;
             if (two) pend_next = w.keysB;
+            fused_flags = true;
         }
-        u32 differ, shrt;
+        pend_flags = false;
         if (!act && rounds < P.count) {
             differ = pf[2 * rounds];
             shrt = pf[2 * rounds + 1];
+        } else if (have_flags) {
+            // pending round of a two-round launch over an unchanged list: Ah holds
+        } else if (fused_flags) {
+            // the counters and the launch's flags in one read-back
+            u64 H[HDR_ROUND + 6];
+            SS_TRY(ss_read_u64(w.hdr, H, HDR_ROUND + 6, st));
+            const u32 *h = (const u32 *)H;
+            Ah = h[ci];
+            const u64 *R = H + HDR_ROUND;
+            differ = R[0] != R[1];
+            shrt = R[2] != 0;
+            if (pend_next) {
+                pend_flags = true;
+                pend_differ = R[3] != R[4];
+                pend_shrt = R[5] != 0;
+            }
+            if (Ah == 0) ss_prof_drop_last("k_hash_round");
+            else
+                ss_prof_add_bytes("k_hash_round", (double)Ah * (double)(lhashed - lprev) +
+                                                      (double)Ah * (pend_next ? 52.0 : 44.0));
         } else {
             SS_HIP(hipMemsetAsync(ctr + 2, 0, 2 * sizeof(u32), st));
             k_flags<<<(unsigned)ceil_div(Ah, 256), 256, 0, st>>>(keys, kin, act, ctr + ci, offsets, l, ctr + 2);
@@ -810,12 +896,13 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
         if (Ah >= 2 && !differ && !shrt) {
             // one key shared by all and no short string: nothing finishes
             last_trivial = true;
-            pend = pend_next;
+            pend = pend_next;  // (its flags stay valid: the list is unchanged)
             lprev = l;
             l *= 2;
             continue;
         }
         last_trivial = false;
+        pend_flags = false;  // this round changes the list
         const int mode = Ah == 1 ? DM_UNIQUE : (differ ? DM_TABLE : DM_ALLDUP);
         u32 logT = 0;
         if (mode == DM_TABLE) {
