@@ -287,3 +287,16 @@ __device__ __forceinline__ u64 upper_bound_dev(const T *a, u64 n, T x)
 }
 
 __device__ __forceinline__ u64 lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
+
+// Wave-aggregated append: returns the slot for lanes with pred set.  Must be
+// reached by the whole wavefront.
+__device__ __forceinline__ u32 wave_append(bool pred, u32 *counter)
+{
+    u64 m = __ballot(pred);
+    if (m == 0) return 0;
+    u32 leader = __ffsll((unsigned long long)m) - 1;
+    u32 base = 0;
+    if (__lane_id() == leader) base = atomicAdd(counter, (u32)__popcll(m));
+    base = __shfl(base, leader, 64);
+    return base + (u32)__popcll(m & lanemask_lt());
+}

@@ -51,7 +51,8 @@ __global__ __launch_bounds__(256) void k_check_runs(const u64 *run_off, u32 k, c
 // psv inside each block of PB entries (PSV_NONE if the answer lies before the
 // block).  The block minimum goes to leaf P + block of the tree T, the minima
 // of its PC-entry chunks to cm[block * PCB ..].
-__global__ __launch_bounds__(PB) void k_psv_block(const u32 *e, u32 n, u32 *psv, u32 *T, u32 P, u32 *cm)
+__global__ __launch_bounds__(PB) void k_psv_block(const u32 *e, u32 n, u32 *psv, u32 *T, u32 P, u32 *cm,
+                                                 u32 *farl, u32 *fcnt)
 {
     __shared__ u32 t[2 * PB];  // heap: node x has children 2x, 2x+1; leaves PB..2PB-1
     const u32 b0 = blockIdx.x * PB;
@@ -67,6 +68,7 @@ __global__ __launch_bounds__(PB) void k_psv_block(const u32 *e, u32 n, u32 *psv,
         }
         __syncthreads();
     }
+    bool far = false;  // the answer lies before this block: left to k_psv_far
     if (i < n) {
         u32 res = PSV_NONE;
         if (v > 0) {
@@ -87,8 +89,23 @@ __global__ __launch_bounds__(PB) void k_psv_block(const u32 *e, u32 n, u32 *psv,
                 }
                 res = b0 + (x - PB);
             }
+            far = !found;
         }
         psv[i] = res;
+    }
+    // this block's far entries, compacted to farl[b0 ..], their count in fcnt[block]
+    __shared__ u32 wcnt[PB / 64];
+    const u64 fm = __ballot(far);
+    const u32 wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) wcnt[wid] = (u32)__popcll(fm);
+    __syncthreads();
+    u32 wb = 0;
+    for (u32 q = 0; q < wid; q++) wb += wcnt[q];
+    if (far) farl[b0 + wb + (u32)__popcll(fm & lanemask_lt())] = i;
+    if (threadIdx.x == 0) {
+        u32 tot = 0;
+        for (u32 q = 0; q < PB / 64; q++) tot += wcnt[q];
+        fcnt[blockIdx.x] = tot;
     }
     if (threadIdx.x == 0) T[P + blockIdx.x] = t[1];
     if (threadIdx.x < PCB) cm[(u64)blockIdx.x * PCB + threadIdx.x] = t[PCB + threadIdx.x];
@@ -124,12 +141,10 @@ __global__ __launch_bounds__(256) void k_tree_up(u32 *T, u32 m, u32 lv)
 // psv for positions whose answer lies before their block: nearest left
 // subtree of T with a smaller minimum, its rightmost such block, that block's
 // rightmost such chunk, that chunk's rightmost such entry.
-__global__ __launch_bounds__(256) void k_psv_far(const u32 *e, u32 n, const u32 *T, u32 P, const u32 *cm, u32 *psv)
+__device__ __forceinline__ void psv_far_one(const u32 *e, const u32 *T, u32 P, const u32 *cm, u32 i, u32 n,
+                                            u32 *psv)
 {
-    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     const u32 v = e[i];
-    if (v == 0 || psv[i] != PSV_NONE) return;
     u32 x = P + i / PB;
     bool found = false;
     while (x > 1) {
@@ -171,6 +186,17 @@ __global__ __launch_bounds__(256) void k_psv_far(const u32 *e, u32 n, const u32 
     psv[i] = r;
 }
 
+// Workgroup b takes the far entries k_psv_block b left, packed at
+// farl[b*PB ..] (fcnt[b] of them); each walk is a chain of dependent loads,
+// so packing keeps the walks of a block in as few wavefronts as possible.
+__global__ __launch_bounds__(256) void k_psv_far(const u32 *e, const u32 *T, u32 P, const u32 *cm, const u32 *farl,
+                                                 const u32 *fcnt, u32 n, u32 *psv)
+{
+    const u32 cnt = fcnt[blockIdx.x];
+    const u32 *lst = farl + (u64)blockIdx.x * PB;
+    for (u32 q = threadIdx.x; q < cnt; q += blockDim.x) psv_far_one(e, T, P, cm, lst[q], n, psv);
+}
+
 // Tree size (leaves) for n entries.
 static u32 psv_leaves(u64 n)
 {
@@ -182,14 +208,15 @@ static u32 psv_leaves(u64 n)
 
 // psv of every entry of e[0..n) (n >= 1).  T holds 2 * psv_leaves(n) words,
 // cm psv_leaves(n) * PCB words (256-byte aligned).
-static int psv_build(const u32 *e, u64 n, u32 *psv, u32 *T, u32 *cm, hipStream_t st)
+static int psv_build(const u32 *e, u64 n, u32 *psv, u32 *T, u32 *cm, u32 *farl, u32 *fcnt, hipStream_t st)
 {
+    if (n == 0) return SS_OK;
     const u32 nb = (u32)ceil_div(n, PB);
     const u32 P = psv_leaves(n);
     if (P > nb) SS_HIP(hipMemsetAsync(T + P + nb, 0xFF, sizeof(u32) * (P - nb), st));
     {
         SS_PROF("k_psv_block", st, (double)n * 8.0);  // e in, psv out
-        k_psv_block<<<nb, PB, 0, st>>>(e, (u32)n, psv, T, P, cm);
+        k_psv_block<<<nb, PB, 0, st>>>(e, (u32)n, psv, T, P, cm, farl, fcnt);
     }
     SS_CHECK_LAUNCH();
     for (u32 m = P; m > 1;) {
@@ -201,8 +228,9 @@ static int psv_build(const u32 *e, u64 n, u32 *psv, u32 *T, u32 *cm, hipStream_t
         m >>= lv;
     }
     {
-        SS_PROF("k_psv_far", st, (double)n * 8.0);  // e and psv in (far entries: a few more words)
-        k_psv_far<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(e, (u32)n, T, P, cm, psv);
+        // (far entries only: their value, the tree path, one chunk)
+        SS_PROF("k_psv_far", st, 0.0);
+        k_psv_far<<<nb, 256, 0, st>>>(e, T, P, cm, farl, fcnt, (u32)n, psv);
     }
     SS_CHECK_LAUNCH();
     return SS_OK;
@@ -284,7 +312,7 @@ __global__ void k_widen(const u32 *d, u32 n, u64 *out)
 }
 
 struct DecWs {
-    u32 *psv, *tree, *cmin, *bad;
+    u32 *psv, *tree, *cmin, *bad, *far, *fcnt;
     u64 *scratch;
 };
 
@@ -296,12 +324,16 @@ static void dec_layout(u64 n, DecWs *w, WsArena *a, WsCounter *c)
         w->tree = a->take<u32>(nt);
         w->cmin = a->take<u32>(nt / 2 * PCB);
         w->bad = a->take<u32>(4);
+        w->far = a->take<u32>(n + 1);
+        w->fcnt = a->take<u32>(ceil_div(n, PB) + 1);
         w->scratch = a->take<u64>(ss_scan_scratch_elems<u64>(n + 1));
     } else {
         c->take<u32>(n + 1);
         c->take<u32>(nt);
         c->take<u32>(nt / 2 * PCB);
         c->take<u32>(4);
+        c->take<u32>(n + 1);
+        c->take<u32>(ceil_div(n, PB) + 1);
         c->take<u64>(ss_scan_scratch_elems<u64>(n + 1));
     }
 }
@@ -333,7 +365,7 @@ static int decode_impl(u32 k, const u64 *run_off, const u32 *e, const u32 *d, co
         return SS_ERR_CAPACITY;
     }
     if (n == 0 || total == 0) return SS_OK;
-    SS_TRY(psv_build(e, n, w.psv, w.tree, w.cmin, st));
+    SS_TRY(psv_build(e, n, w.psv, w.tree, w.cmin, w.far, w.fcnt, st));
     k_decode<<<(unsigned)ceil_div(total, DC_NT * DC_PER), DC_NT, 0, st>>>(e, d, suf_off, suf, w.psv, (u32)n, out_off,
                                                                        total, out);
     SS_CHECK_LAUNCH();
@@ -1196,7 +1228,7 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
     SS_HIP(hipMemcpyAsync(w.sb, sbv.data(), sizeof(u64) * kne, hipMemcpyHostToDevice, st));
     SS_HIP(hipMemcpyAsync(w.sid, sidv.data(), sizeof(u32) * kne, hipMemcpyHostToDevice, st));
     // psv chains over the whole front-coded array (no decoding of the strings)
-    SS_TRY(psv_build(fc_lcp, n_fc, w.dec.psv, w.dec.tree, w.dec.cmin, st));
+    SS_TRY(psv_build(fc_lcp, n_fc, w.dec.psv, w.dec.tree, w.dec.cmin, w.dec.far, w.dec.fcnt, st));
     const FcView V{fc_lcp, fc_len, w.dec.psv, suf_off, suf, sufN};
     // group of every run, first non-empty run of every group, group depths, keys
     std::vector<u32> rg(k), rep(groups, 0);

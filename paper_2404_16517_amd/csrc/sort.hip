@@ -57,18 +57,6 @@ __device__ __forceinline__ u64 match_digit(u32 digit, bool valid)
     return m;
 }
 
-// Wave-aggregated append: returns the slot for lanes with pred set.
-__device__ __forceinline__ u32 wave_append(bool pred, u32 *counter)
-{
-    u64 m = __ballot(pred);
-    if (m == 0) return 0;
-    u32 leader = __ffsll((unsigned long long)m) - 1;
-    u32 base = 0;
-    if (__lane_id() == leader) base = atomicAdd(counter, (u32)__popcll(m));
-    base = __shfl(base, leader, 64);
-    return base + (u32)__popcll(m & lanemask_lt());
-}
-
 // Wave-aggregated atomic add of per-lane values.
 __device__ __forceinline__ void wave_add(u32 v, u32 *counter)
 {
