@@ -1147,8 +1147,7 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
                                                                     have_fc ? d0.bad : nullptr,
                                                                     have_fc ? suf_off + n_fc : nullptr, stage);
         SS_CHECK_LAUNCH();
-        SS_HIP(hipMemcpyAsync(H.data(), stage, sizeof(u64) * hdr, hipMemcpyDeviceToHost, st));
-        SS_HIP(hipStreamSynchronize(st));
+        SS_TRY(ss_read_bytes(stage, H.data(), sizeof(u64) * hdr, st));
         memcpy(rb.data(), H.data() + 2, sizeof(u64) * k);
         memcpy(re.data(), H.data() + 2 + k, sizeof(u64) * k);
         memcpy(go.data(), H.data() + 2 + 2 * (u64)k, sizeof(u32) * (groups + 1));

@@ -1,6 +1,8 @@
 // Splitters, bucket boundaries and LCP compression of buckets (Section 3,
 // steps 1-2; LCP compression from Section 2; distinguishing prefixes only in
 // the prefix-doubling variant of Section 4).
+#include <string.h>
+
 #include "common.hpp"
 
 // ------------------------------------------------------------- splitters
@@ -311,6 +313,8 @@ extern "C" size_t ss_partition_encode_workspace(uint64_t n)
     return c.used;
 }
 
+__global__ void k_put_u64(u64 *dst, const u64 *src) { *dst = *src; }
+
 static int encode_impl(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n, const uint64_t *set_off,
                        uint32_t nsets, const uint32_t *perm, const uint32_t *lcp, const uint32_t *dist,
                        const uint8_t *spl_bytes, uint64_t spl_N, const uint64_t *spl_offsets, uint32_t r,
@@ -351,11 +355,14 @@ static int encode_impl(const uint8_t *bytes, uint64_t N, const uint64_t *offsets
         k_add_base<<<(unsigned)ceil_div(n + 1, 256), 256, 0, st>>>(suf_off, n + 1, suf_base);
         SS_CHECK_LAUNCH();
     }
+    // the check flag and the literal total side by side, one read-back
+    k_put_u64<<<1, 1, 0, st>>>((u64 *)(bad + 2), suf_off + n);
+    SS_CHECK_LAUNCH();
+    u32 hw[4];
+    SS_TRY(ss_read_u32(bad, hw, 4, st));
+    const u32 hbad = hw[0];
     u64 total;
-    u32 hbad;
-    SS_HIP(hipMemcpyAsync(&total, suf_off + n, sizeof(u64), hipMemcpyDeviceToHost, st));
-    SS_HIP(hipMemcpyAsync(&hbad, bad, sizeof(u32), hipMemcpyDeviceToHost, st));
-    SS_HIP(hipStreamSynchronize(st));
+    memcpy(&total, hw + 2, sizeof(u64));
     total -= suf_base;
     if (hbad) {
         ss_set_error("front coding needs lcp <= dist <= len at every position");

@@ -51,18 +51,66 @@ extern "C" int ss_set_tuning(int param, int value)
     return SS_ERR_INVALID_ARG;
 }
 
+// Small read-backs go through pinned host buffers (a copy into pageable
+// memory is staged by the runtime and costs a second round trip).  The
+// buffers come from a pool that grows to the number of threads reading at
+// once and lives as long as the process; a thread takes one per read.
+namespace {
+constexpr size_t PIN_BYTES = 65536;
+std::mutex g_pin_mu;
+std::vector<void *> g_pin_free;
+
+void *pin_take()
+{
+    {
+        std::lock_guard<std::mutex> lk(g_pin_mu);
+        if (!g_pin_free.empty()) {
+            void *p = g_pin_free.back();
+            g_pin_free.pop_back();
+            return p;
+        }
+    }
+    void *p = nullptr;
+    if (hipHostMalloc(&p, PIN_BYTES, hipHostMallocDefault) != hipSuccess) return nullptr;
+    return p;
+}
+
+void pin_give(void *p)
+{
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    g_pin_free.push_back(p);
+}
+
+int read_back(const void *dev, void *host, size_t bytes, hipStream_t s)
+{
+    void *p = bytes <= PIN_BYTES ? pin_take() : nullptr;
+    if (!p) {
+        SS_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s));
+        SS_HIP(hipStreamSynchronize(s));
+        return SS_OK;
+    }
+    hipError_t e = hipMemcpyAsync(p, dev, bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) memcpy(host, p, bytes);
+    pin_give(p);
+    if (e != hipSuccess) {
+        ss_set_error("HIP error %s in a read-back", hipGetErrorString(e));
+        return SS_ERR_HIP;
+    }
+    return SS_OK;
+}
+}  // namespace
+
+int ss_read_bytes(const void *dev, void *host, size_t bytes, hipStream_t s) { return read_back(dev, host, bytes, s); }
+
 int ss_read_u32(const u32 *dev, u32 *host, int count, hipStream_t s)
 {
-    SS_HIP(hipMemcpyAsync(host, dev, sizeof(u32) * count, hipMemcpyDeviceToHost, s));
-    SS_HIP(hipStreamSynchronize(s));
-    return SS_OK;
+    return read_back(dev, host, sizeof(u32) * (size_t)count, s);
 }
 
 int ss_read_u64(const u64 *dev, u64 *host, int count, hipStream_t s)
 {
-    SS_HIP(hipMemcpyAsync(host, dev, sizeof(u64) * count, hipMemcpyDeviceToHost, s));
-    SS_HIP(hipStreamSynchronize(s));
-    return SS_OK;
+    return read_back(dev, host, sizeof(u64) * (size_t)count, s);
 }
 
 // ---------------------------------------------------------------- scans
