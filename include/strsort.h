@@ -282,7 +282,8 @@ size_t ss_lcp_merge_workspace(uint64_t n_out, uint64_t n_fc, uint32_t k);
  *     k entries each); runs must not overlap; every non-empty run starts with
  *     e = 0 and is sorted.
  *   Groups: group g merges runs [group_off[g], group_off[g+1]) (device,
- *     groups+1 entries, group_off[0] = 0, group_off[groups] = k).
+ *     groups+1 entries, group_off[0] = 0, group_off[groups] = k,
+ *     1 <= groups <= k).
  * Output, n_out = sum of run sizes entries: group g's merged sequence occupies
  * the positions after all runs of earlier groups, in merged order:
  *   out_src[i] = (run << 32) | position within the run (may be NULL),

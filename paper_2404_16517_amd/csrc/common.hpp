@@ -70,6 +70,10 @@ struct WsCounter {
 int ss_read_u32(const u32 *dev, u32 *host, int count, hipStream_t s);
 int ss_read_u64(const u64 *dev, u64 *host, int count, hipStream_t s);
 int ss_read_bytes(const void *dev, void *host, size_t bytes, hipStream_t s);
+// Pinned host staging for asynchronous uploads (NULL if none can be had);
+// release after enqueueing the copies from it.
+void *ss_upload_take(size_t bytes);
+int ss_upload_release(void *p, hipStream_t s);
 
 // Opt-in launch timing (ss_profile_enable): a scope records an event pair on
 // the stream around the launch it encloses.

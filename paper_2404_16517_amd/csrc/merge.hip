@@ -1085,13 +1085,47 @@ static void merge_layout(u64 n_out, u64 n_fc, u64 k, MergeWs *w, WsArena *a, WsC
     } while (0)
     MT(G0, u32, n_out); MT(G1, u32, n_out); MT(L0, u32, n_out); MT(L1, u32, n_out);
     MT(F0, u32, n_out); MT(F1, u32, n_out); MT(K0, u64, n_out); MT(K1, u64, n_out);
-    MT(pg, u32, MERGE_PCAP(k)); MT(Cg, u32, k + 2); MT(rgroup, u32, k + 2); MT(rep, u32, k + 2);
-    MT(sid, u32, k + 2); MT(P, u64, k + 2); MT(sb, u64, k + 2);
-    MT(pc, u32, MERGE_PCAP(k)); MT(pfirst, u8, MERGE_PCAP(k)); MT(tstart, u32, MERGE_PCAP(k) + 64);
+    // host-planned arrays, in two contiguous blocks (each uploaded in one copy)
+    MT(P, u64, k + 2); MT(sb, u64, k + 2); MT(sid, u32, k + 2); MT(rgroup, u32, k + 2); MT(rep, u32, k + 2);
     MT(PA0, u64, MERGE_PCAP(k)); MT(PA1, u64, MERGE_PCAP(k)); MT(PB1, u64, MERGE_PCAP(k));
+    MT(pg, u32, MERGE_PCAP(k)); MT(tstart, u32, MERGE_PCAP(k) + 64);
+    MT(Cg, u32, k + 2); MT(pc, u32, MERGE_PCAP(k)); MT(pfirst, u8, MERGE_PCAP(k));
     MT(split, u32, n_out / MW_TILE + MERGE_PCAP(k) + 64);  // tiles of one level
     MT(runmin, u32, k + 2); MT(mblk, MOp, n_out / MS_ITEMS + 2);
 #undef MT
+}
+
+// Host arrays to device arrays that lie in one block in this order: staged in
+// pinned memory at the same relative offsets and uploaded by one asynchronous
+// copy (the staging buffer is reused once the copy has run).  Without pinned
+// memory: one copy each, and a wait before the host arrays go away.
+struct UpPart {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+
+static int upload_parts(const UpPart *parts, int np, hipStream_t st)
+{
+    u8 *base = (u8 *)parts[0].dst;
+    const size_t span = (size_t)((u8 *)parts[np - 1].dst - base) + parts[np - 1].bytes;
+    void *pin = ss_upload_take(span);
+    if (!pin) {
+        for (int q = 0; q < np; q++)
+            if (parts[q].bytes) SS_HIP(hipMemcpyAsync(parts[q].dst, parts[q].src, parts[q].bytes,
+                                                      hipMemcpyHostToDevice, st));
+        SS_HIP(hipStreamSynchronize(st));
+        return SS_OK;
+    }
+    for (int q = 0; q < np; q++)
+        if (parts[q].bytes) memcpy((u8 *)pin + ((u8 *)parts[q].dst - base), parts[q].src, parts[q].bytes);
+    const hipError_t e = hipMemcpyAsync(base, pin, span, hipMemcpyHostToDevice, st);
+    ss_upload_release(pin, st);
+    if (e != hipSuccess) {
+        ss_set_error("plan upload failed: %s", hipGetErrorString(e));
+        return SS_ERR_HIP;
+    }
+    return SS_OK;
 }
 
 extern "C" size_t ss_lcp_merge_workspace(uint64_t n_out, uint64_t n_fc, uint32_t k)
@@ -1110,8 +1144,8 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
 {
     ss_clear_error();
     if (n_fc >= 0xFFFFFFFFull) { ss_set_error("n_fc too large"); return SS_ERR_TOO_LARGE; }
-    if (k == 0 || k > MERGE_MAX_K || groups == 0 || !run_begin || !run_end || !group_off) {
-        ss_set_error("lcp_merge: bad arguments (1 <= k <= %d, groups >= 1)", MERGE_MAX_K);
+    if (k == 0 || k > MERGE_MAX_K || groups == 0 || groups > k || !run_begin || !run_end || !group_off) {
+        ss_set_error("lcp_merge: bad arguments (1 <= k <= %d, 1 <= groups <= k)", MERGE_MAX_K);
         return SS_ERR_INVALID_ARG;
     }
     hipStream_t st = (hipStream_t)stream;
@@ -1223,9 +1257,7 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
         ss_set_error("workspace too small: need %zu bytes", ss_lcp_merge_workspace(n_out, n_fc, k));
         return SS_ERR_WORKSPACE;
     }
-    SS_HIP(hipMemcpyAsync(w.P, P.data(), sizeof(u64) * (k + 1), hipMemcpyHostToDevice, st));
-    SS_HIP(hipMemcpyAsync(w.sb, sbv.data(), sizeof(u64) * kne, hipMemcpyHostToDevice, st));
-    SS_HIP(hipMemcpyAsync(w.sid, sidv.data(), sizeof(u32) * kne, hipMemcpyHostToDevice, st));
+
     // psv chains over the whole front-coded array (no decoding of the strings)
     SS_TRY(psv_build(fc_lcp, n_fc, w.dec.psv, w.dec.tree, w.dec.cmin, w.dec.far, w.dec.fcnt, st));
     const FcView V{fc_lcp, fc_len, w.dec.psv, suf_off, suf, sufN};
@@ -1238,8 +1270,14 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
             if (!found && re[j] > rb[j]) { rep[g] = j; found = true; }
         }
     }
-    SS_HIP(hipMemcpyAsync(w.rgroup, rg.data(), sizeof(u32) * k, hipMemcpyHostToDevice, st));
-    SS_HIP(hipMemcpyAsync(w.rep, rep.data(), sizeof(u32) * groups, hipMemcpyHostToDevice, st));
+    {
+        const UpPart parts[] = {{w.P, P.data(), sizeof(u64) * (k + 1)},
+                                {w.sb, sbv.data(), sizeof(u64) * kne},
+                                {w.sid, sidv.data(), sizeof(u32) * kne},
+                                {w.rgroup, rg.data(), sizeof(u32) * k},
+                                {w.rep, rep.data(), sizeof(u32) * groups}};
+        SS_TRY(upload_parts(parts, 5, st));
+    }
     SS_HIP(hipMemsetAsync(w.Cg, 0xFF, sizeof(u32) * groups, st));
     SS_HIP(hipMemsetAsync(w.runmin, 0xFF, sizeof(u32) * k, st));
     k_run_min<<<dim3(k, RM_PARTS), 256, 0, st>>>(run_begin, w.P, fc_lcp, w.runmin);
@@ -1301,11 +1339,12 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
         return SS_ERR_INVALID_ARG;
     }
     if (npairs_all) {
-        SS_HIP(hipMemcpyAsync(w.PA0, pa0.data(), sizeof(u64) * npairs_all, hipMemcpyHostToDevice, st));
-        SS_HIP(hipMemcpyAsync(w.PA1, pa1.data(), sizeof(u64) * npairs_all, hipMemcpyHostToDevice, st));
-        SS_HIP(hipMemcpyAsync(w.PB1, pb1.data(), sizeof(u64) * npairs_all, hipMemcpyHostToDevice, st));
-        SS_HIP(hipMemcpyAsync(w.pg, pgv.data(), sizeof(u32) * npairs_all, hipMemcpyHostToDevice, st));
-        SS_HIP(hipMemcpyAsync(w.tstart, tsv.data(), sizeof(u32) * tsv.size(), hipMemcpyHostToDevice, st));
+        const UpPart parts[] = {{w.PA0, pa0.data(), sizeof(u64) * npairs_all},
+                                {w.PA1, pa1.data(), sizeof(u64) * npairs_all},
+                                {w.PB1, pb1.data(), sizeof(u64) * npairs_all},
+                                {w.pg, pgv.data(), sizeof(u32) * npairs_all},
+                                {w.tstart, tsv.data(), sizeof(u32) * tsv.size()}};
+        SS_TRY(upload_parts(parts, 5, st));
     }
     for (const LevelPlan &lp : plan) {
         MergeLevel M{G, L, F, Go, Lo, Fo, K, Ko, w.pg + lp.off, w.Cg, w.PA0 + lp.off, w.PA1 + lp.off,
@@ -1327,6 +1366,5 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
     k_merge_out<<<(unsigned)ceil_div(n_out, 256), 256, 0, st>>>(G, L, (u32)n_out, w.sb, w.sid, kne, fc_id, fc_len,
                                                                 out_src, out_id, out_lcp, out_len);
     SS_CHECK_LAUNCH();
-    SS_HIP(hipStreamSynchronize(st));  // the host plan vectors must outlive their copies
     return SS_OK;
 }

@@ -222,15 +222,25 @@ __global__ __launch_bounds__(256) void k_fc_meta(const u64 *off, u32 n, const u3
                                                  const u32 *dist, const u64 *run_off, u32 nb, u32 *fc_lcp,
                                                  u32 *fc_len, u32 *fc_id, u64 *sizes, u32 *bad)
 {
-    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    // bucket start: the largest run_off[j] <= i
-    u32 lo = 0, hi = nb - 1;
-    while (hi - lo > 1) {
-        u32 mid = (lo + hi) >> 1;
-        if (run_off[mid] <= i) lo = mid;
-        else hi = mid;
+    // bucket start: the largest run_off[j] <= i.  The workgroup's positions
+    // are contiguous: one search for its first position, then each thread
+    // steps forward over the (few) bucket bounds inside the workgroup.
+    __shared__ u32 s_lo;
+    const u32 i0 = blockIdx.x * blockDim.x;
+    if (threadIdx.x == 0) {
+        u32 lo = 0, hi = nb - 1;
+        while (hi - lo > 1) {
+            u32 mid = (lo + hi) >> 1;
+            if (run_off[mid] <= i0) lo = mid;
+            else hi = mid;
+        }
+        s_lo = lo;
     }
+    __syncthreads();
+    const u32 i = i0 + threadIdx.x;
+    if (i >= n) return;
+    u32 lo = s_lo;
+    while (lo + 2 < nb && run_off[lo + 1] <= i) lo++;
     const u32 e = (run_off[lo] == i) ? 0u : lcp[i];
     const u32 p = perm[i];
     const u64 len = off[p + 1] - off[p];

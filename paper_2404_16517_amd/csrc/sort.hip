@@ -38,7 +38,7 @@
 enum {
     C_SMALL = 0, C_LARGE = 1, C_NEXT = 2, C_IDENT = 3, C_BND = 4,
     C_LTILES = 5, C_SMALLN = 6, C_NTILES = 7, C_ITILES = 8, C_LELEM = 9, C_NELEM = 12, C_TINY = 13,
-    C_TINYN = 14, C_NCTR = 16
+    C_TINYN = 14, C_BADSET = 15, C_NCTR = 16
 };
 #define WS_MAX 128  // segments of up to this many strings: one wavefront each
 // ctr[10..11]: 64-bit sum of size * skip over the routed segments
@@ -1081,15 +1081,25 @@ __global__ void k_init_single(Seg *act, u32 n, u32 *lcp)
     lcp[0] = 0;
 }
 
-__global__ void k_init_sets(const u64 *set_off, u32 nsets, Seg *act, u32 *ctr, u32 *lcp)
+// One segment per set of two or more strings.  A set whose bounds are not
+// well placed (set_off non-decreasing from 0 to n) raises ctr[C_BADSET] and
+// writes nothing, so a malformed set_off never leads outside the arrays; the
+// host reads the flag with the counters.
+__global__ void k_init_sets(const u64 *set_off, u32 nsets, u64 n, Seg *act, u32 *ctr, u32 *lcp)
 {
     u32 j = blockIdx.x * blockDim.x + threadIdx.x;
     bool valid = j < nsets;
     u32 b = 0, e = 0;
     if (valid) {
-        b = (u32)set_off[j];
-        e = (u32)set_off[j + 1];
-        if (e > b) lcp[b] = 0;
+        const u64 b64 = set_off[j], e64 = set_off[j + 1];
+        if (e64 < b64 || e64 > n || (j == 0 && b64 != 0) || (j + 1 == nsets && e64 != n)) {
+            atomicOr(&ctr[C_BADSET], 1u);
+            valid = false;
+        } else {
+            b = (u32)b64;
+            e = (u32)e64;
+            if (e > b) lcp[b] = 0;
+        }
     }
     bool two = valid && e > b + 1;
     u32 a = wave_append(two, &ctr[C_NEXT]);
@@ -1196,29 +1206,6 @@ extern "C" int ss_sort(const uint8_t *bytes, uint64_t N, const uint64_t *offsets
     return sort_rounds(J, w, n >= 2 ? 1 : 0, (u32)ceil_div(n, ETILE));
 }
 
-// set_off: non-decreasing, set_off[0] = 0, set_off[num_sets] = n
-__global__ void k_check_sets(const u64 *set_off, u32 nsets, u64 n, u32 *bad)
-{
-    const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j > nsets) return;
-    const u64 v = set_off[j];
-    if ((j == 0 && v != 0) || (j == nsets && v != n) || v > n || (j > 0 && v < set_off[j - 1])) atomicOr(bad, 1u);
-}
-
-static int check_sets(const u64 *set_off, u32 num_sets, u64 n, u32 *scratch, hipStream_t st)
-{
-    SS_HIP(hipMemsetAsync(scratch, 0, sizeof(u32), st));
-    k_check_sets<<<(unsigned)ceil_div((u64)num_sets + 1, 256), 256, 0, st>>>(set_off, num_sets, n, scratch);
-    SS_CHECK_LAUNCH();
-    u32 bad;
-    SS_TRY(ss_read_u32(scratch, &bad, 1, st));
-    if (bad) {
-        ss_set_error("set_off must be non-decreasing with set_off[0] = 0 and set_off[num_sets] = n");
-        return SS_ERR_INVALID_ARG;
-    }
-    return SS_OK;
-}
-
 extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
                              const uint64_t *set_off, uint32_t num_sets, uint32_t *perm_local,
                              uint32_t *lcp, uint32_t flags, void *ws, size_t ws_bytes, void *stream)
@@ -1242,15 +1229,18 @@ extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *o
         ss_set_error("workspace too small: need %zu bytes", ss_sort_workspace(n));
         return SS_ERR_WORKSPACE;
     }
-    SS_TRY(check_sets(set_off, num_sets, n, w.ctr, st));
     SortJob J{bytes, N, offsets, perm_local, lcp ? lcp : w.lcp_scratch, st, 0};
     k_iota<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(perm_local, (u32)n);
     SS_CHECK_LAUNCH();
     SS_HIP(hipMemsetAsync(w.ctr, 0, sizeof(u32) * C_NCTR, st));
-    k_init_sets<<<(unsigned)ceil_div(num_sets, 256), 256, 0, st>>>(set_off, num_sets, w.act, w.ctr, J.lcp);
+    k_init_sets<<<(unsigned)ceil_div(num_sets, 256), 256, 0, st>>>(set_off, num_sets, n, w.act, w.ctr, J.lcp);
     SS_CHECK_LAUNCH();
     u32 h[C_NCTR];
     SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, st));
+    if (h[C_BADSET]) {
+        ss_set_error("set_off must be non-decreasing with set_off[0] = 0 and set_off[num_sets] = n");
+        return SS_ERR_INVALID_ARG;
+    }
     J.n_first = h[C_NELEM];
     SS_TRY(sort_rounds(J, w, h[C_NEXT], h[C_NTILES]));
     if (!(flags & SS_BATCH_GLOBAL_IDS)) {

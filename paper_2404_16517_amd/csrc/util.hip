@@ -103,6 +103,58 @@ int read_back(const void *dev, void *host, size_t bytes, hipStream_t s)
 
 int ss_read_bytes(const void *dev, void *host, size_t bytes, hipStream_t s) { return read_back(dev, host, bytes, s); }
 
+// Pinned staging for uploads that must not wait: a buffer is taken, filled,
+// copied from asynchronously, and handed back with an event recorded after
+// the copy; it is reused once that event has completed.
+namespace {
+struct UpBuf {
+    void *p;
+    size_t cap;
+    hipEvent_t ev;
+    bool busy, pending;
+};
+std::mutex g_up_mu;
+std::vector<UpBuf> g_up;
+}  // namespace
+
+void *ss_upload_take(size_t bytes)
+{
+    std::lock_guard<std::mutex> lk(g_up_mu);
+    for (auto &b : g_up) {
+        if (b.busy || b.cap < bytes) continue;
+        if (b.pending) {
+            if (hipEventQuery(b.ev) != hipSuccess) continue;  // its last copy is still running
+            b.pending = false;
+        }
+        b.busy = true;
+        return b.p;
+    }
+    UpBuf b{nullptr, bytes > 65536 ? bytes : 65536, nullptr, true, false};
+    if (hipHostMalloc(&b.p, b.cap, hipHostMallocDefault) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) {
+        hipHostFree(b.p);
+        return nullptr;
+    }
+    g_up.push_back(b);
+    return b.p;
+}
+
+int ss_upload_release(void *p, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_up_mu);
+    for (auto &b : g_up)
+        if (b.p == p) {
+            b.busy = false;
+            b.pending = hipEventRecord(b.ev, s) == hipSuccess;
+            if (!b.pending) {
+                // no event: wait for the stream instead, then the buffer is free
+                hipStreamSynchronize(s);
+            }
+            return SS_OK;
+        }
+    return SS_OK;
+}
+
 int ss_read_u32(const u32 *dev, u32 *host, int count, hipStream_t s)
 {
     return read_back(dev, host, sizeof(u32) * (size_t)count, s);

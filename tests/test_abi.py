@@ -66,6 +66,9 @@ def test_argument_errors_without_device():
                           None, None, 0, None) == -1
     assert L.ss_lcp_merge(4, P(8), P(8), 0, P(8), 1, P(8), P(8), P(8), P(8), P(8), P(8), P(8), P(8), None, 1,
                           None, None, 0, None) == -1
+    # more groups than runs
+    assert L.ss_lcp_merge(2, P(8), P(8), 3, P(8), 1, P(8), P(8), P(8), P(8), P(8), P(8), P(8), P(8), None, 1,
+                          None, None, 0, None) == -1
 
 
 def test_tuning_validation():
