@@ -298,6 +298,27 @@ def test_dist_prefix_init_lengths(init_len, bits):
     assert rounds == r_ref
 
 
+@pytest.mark.parametrize("case", ["text300k_bits64", "text300k_bits20", "dn200k", "dups200k"])
+def test_dist_prefix_two_level_detection(case):
+    """Lists long enough for the bitmap pre-filter of duplicate detection:
+    unique keys, keys colliding by the hash width, and many repeated strings."""
+    if case.startswith("text"):
+        s, bits = synth.text_strings(300_000, seed=21), int(case.split("bits")[1])
+    elif case == "dn200k":
+        s, bits = synth.dn_strings(200_000, 120, 0.5, seed=22), 64
+    else:
+        base = synth.text_strings(70_000, seed=23, median=16).as_list()
+        rng = random.Random(23)
+        s, bits = synth.from_list([rng.choice(base) for _ in range(200_000)]), 64
+    _log(f"[dist_prefix] {case} n={s.n}")
+    g = s.to(DEV)
+    d, rounds = ss.dist_prefix(g.bytes, g.offsets, 8, bits)
+    b, o = oracle.strings_np(s)
+    ref, r_ref, coll = oracle.dist_prefix(b, o, 8, bits)
+    np.testing.assert_array_equal(u32(d), ref)
+    assert rounds == r_ref
+
+
 # ---------------------------------------------------------- partition / coding
 
 def _partition(s, r, pdms):
