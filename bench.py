@@ -9,20 +9,24 @@ on one GPU; PE i holds the i-th 1/p of the input, and the exchange between
 PEs is replaced by runs that already sit in HBM:
   1. approximate distinguishing prefixes by prefix doubling (hash rounds +
      duplicate detection over all strings),
-  2. every PE sorts its array and builds its LCP array (one batched launch),
+  2. every PE sorts its array and builds its LCP array (one batched launch);
+     steps 1 and 2 are independent: with --overlap, 1 runs on a second
+     stream, driven by a worker thread, while 2 and 3 run (joined before 4),
   3. regular sampling with sampling factor v = 2: v+1 samples per PE, sorted,
      splitters f_j = V[j|V|/p - 1],
   4. every PE splits its array into p buckets and front-codes the
      distinguishing prefixes of each bucket,
   5. bucket j merges the p runs it receives with the LCP-aware merge (all p
      merges in one call),
-  6. exact distinguishing prefixes of the final order (after joining the LCPs
-     across bucket boundaries).
+  6. exact distinguishing prefixes of the final order, by merged position as
+     each PE holds its output (after joining the LCPs across bucket
+     boundaries).
 value = N / (seconds per step), in GB/s ("string bytes sorted per second").
 """
 from __future__ import annotations
 
 import argparse
+import concurrent.futures
 import hashlib
 import json
 import os
@@ -36,9 +40,13 @@ HBM_PEAK_GBS = 8000.0
 
 
 class Pipeline:
-    def __init__(self, B, O, p, v, ss, torch):
+    def __init__(self, B, O, p, v, ss, torch, overlap=False):
         self.B, self.O, self.p, self.v, self.ss, self.torch = B, O, p, v, ss, torch
         dev = B.device
+        self.overlap = overlap
+        if overlap:
+            self.side = torch.cuda.Stream(device=dev)
+            self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=1)
         n = O.numel() - 1
         self.n = n
         self.bounds = [n * i // p for i in range(p + 1)]
@@ -52,9 +60,16 @@ class Pipeline:
     def step(self, marks):
         ss, torch, B, O, p = self.ss, self.torch, self.B, self.O, self.p
         ev = marks.mark
-        # 1. prefix doubling over all strings
-        dpx, rounds = ss.dist_prefix(B, O, 8, 64, ws=self.ws_pd)
-        ev("dist_prefix")
+        # 1. prefix doubling over all strings (on the side stream: it shares
+        #    nothing with 2 and 3 but the input, and its host thread's waits
+        #    for its own read-backs do not hold up the sort's launches)
+        if self.overlap:
+            main = torch.cuda.current_stream()
+            self.side.wait_stream(main)
+            fut = self.pool.submit(self._dist_prefix, marks)
+        else:
+            dpx, rounds = ss.dist_prefix(B, O, 8, 64, ws=self.ws_pd)
+            ev("dist_prefix")
         # 2. every PE sorts its array (+ LCP), one batched launch sequence
         perm, lcp = ss.sort_batch(B, O, self.set_off, ws=self.ws_sort, global_ids=True)
         ev("sort_batch+lcp")
@@ -65,6 +80,11 @@ class Pipeline:
         fid = ss.select_splitters(sperm, p)
         fb, fo = ss.gather_strings(sb, so, fid)
         ev("splitters")
+        if self.overlap:
+            dpx, rounds = fut.result()
+            main.wait_stream(self.side)
+            dpx.record_stream(main)
+            ev("join")
         # 4. every PE splits its array into p buckets and front-codes the
         #    distinguishing prefixes (all PEs in one batched call)
         fc = ss.partition_encode_batch(B, O, self.set_off, perm, lcp, dpx, fb, fo, ws=self.ws_pe)
@@ -80,25 +100,38 @@ class Pipeline:
         # 6. LCPs across bucket boundaries, exact distinguishing prefixes (the
         #    merged prefix lengths bound them: dist <= approximate dist <= len)
         ss.join_group_lcps(B, O, order, mlcp, run_begin, run_end, self.group_off)
-        dist = ss.dist_exact_bounded(order, mlcp, mlen)
+        dist = ss.dist_exact_bounded(None, mlcp, mlen)  # by merged position
         ev("dist_exact")
         return order, mlcp, dist, dpx, rounds
 
+    def _dist_prefix(self, marks):
+        with self.torch.cuda.stream(self.side):
+            marks.mark("side_start", side=True)
+            r = self.ss.dist_prefix(self.B, self.O, 8, 64, ws=self.ws_pd)
+            marks.mark("dist_prefix (side stream)", side=True)
+            return r
+
 
 class Marks:
+    """Events between the stages; each stage's time runs from the previous
+    event on its own stream (the main one, or the side one)."""
+
     def __init__(self, torch, record):
-        self.torch, self.record, self.ev = torch, record, []
+        self.torch, self.record, self.ev, self.side = torch, record, [], []
         if record:
             self.mark("start")
 
-    def mark(self, name):
+    def mark(self, name, side=False):
         if self.record:
             e = self.torch.cuda.Event(enable_timing=True)
             e.record()
-            self.ev.append((name, e))
+            (self.side if side else self.ev).append((name, e))
 
     def times(self):
-        return {b: ea.elapsed_time(eb) for (a, ea), (b, eb) in zip(self.ev[:-1], self.ev[1:])}
+        t = {}
+        for ev in (self.ev, self.side):
+            t.update({b: ea.elapsed_time(eb) for (a, ea), (b, eb) in zip(ev[:-1], ev[1:])})
+        return t
 
 
 def verify_dn(s, order, mlcp, dist, dpx):
@@ -112,7 +145,7 @@ def verify_dn(s, order, mlcp, dist, dpx):
     ok = np.array_equal(order.cpu().numpy().view(np.uint32), perm_ref)
     ok &= np.array_equal(mlcp.cpu().numpy().view(np.uint32), cf.dn_lcp(n, k, F))
     d_sorted = cf.dn_dist_sorted(n, k, F, L)
-    ok &= np.array_equal(dist.cpu().numpy().view(np.uint32)[perm_ref], d_sorted)
+    ok &= np.array_equal(dist.cpu().numpy().view(np.uint32), d_sorted)
     d_in = np.empty(n, np.uint32)
     d_in[perm_ref] = d_sorted
     ok &= np.array_equal(dpx.cpu().numpy().view(np.uint32), cf.doubling_closed_form(d_in, np.full(n, L), 8))
@@ -303,6 +336,9 @@ def main():
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--stages", action="store_true", help="per-stage times on stderr")
+    ap.add_argument("--overlap", action="store_true",
+                    help="run prefix doubling on a second stream beside the sort (per-kernel times then "
+                         "include the other stream's kernels)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-per-job leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-profile", action="store_true",
@@ -334,8 +370,10 @@ def main():
     s = synth.dn_strings(args.n, args.length, args.ratio, seed=0, device=dev)
     torch.cuda.synchronize()
     print(f"# generated n={s.n} N={s.N} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    pipe = Pipeline(s.bytes, s.offsets, args.pes, args.sampling, ss, torch)
+    pipe = Pipeline(s.bytes, s.offsets, args.pes, args.sampling, ss, torch, overlap=args.overlap)
 
+    # (the warm-up steps also fill the library's pool of profiling events)
+    ss.profile_enable(not args.no_profile)
     for _ in range(args.warmup):
         pipe.step(Marks(torch, False))
     torch.cuda.synchronize()
@@ -374,7 +412,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"D/N-ratio strings n={s.n} len={args.length} D/N={args.ratio}",
                    "n": s.n, "N": s.N, "virtual_pes": args.pes, "sampling_factor": args.sampling,
-                   "doubling_rounds": rounds},
+                   "doubling_rounds": rounds, "streams": 2 if args.overlap else 1},
         "strings_per_s": s.n / dt,
         "hbm_frac_of_N_per_step": s.N / dt / 1e9 / HBM_PEAK_GBS,
         "verified": verified,

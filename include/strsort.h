@@ -123,7 +123,10 @@ int ss_dist_exact(const uint64_t *offsets, uint64_t n, const uint32_t *perm,
  * dist = min(d[i], 1 + max(lcp[i], lcp[i+1])) (if 1 + max <= d[i] it is <=
  * len; otherwise dist = len = d[i]).  Approximate distinguishing prefixes
  * (ss_dist_prefix) qualify, and so do the fc_len values of a merge output
- * (out_len).  perm, lcp, d (in, n), dist (out, by input index). */
+ * (out_len).  perm, lcp, d (in, n), dist (out, n or more, by input index:
+ * dist[perm[i]]).  perm may be NULL: then dist[i] is written, by sorted
+ * position (the layout of a PE's merged output, whose strings' input indices
+ * belong to other PEs), and every read and write is sequential. */
 int ss_dist_exact_bounded(const uint32_t *perm, const uint32_t *lcp, const uint32_t *d, uint64_t n,
                           uint32_t *dist, void *stream);
 

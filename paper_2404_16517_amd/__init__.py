@@ -166,15 +166,19 @@ def lcp(bytes_, offsets, perm):
 
 
 def dist_exact_bounded(perm, lcp_, d, n_strings=None):
-    """Exact distinguishing prefixes by input index from a per-position bound
-    d (dist <= d <= len), e.g. the merged fc_len values."""
-    n = perm.numel()
-    if lcp_.numel() != n or d.numel() != n:
+    """Exact distinguishing prefixes from a per-position bound d (dist <= d <=
+    len), e.g. the merged fc_len values: by input index (``perm`` given), or
+    by sorted position (``perm`` None)."""
+    n = lcp_.numel()
+    if d.numel() != n or (perm is not None and perm.numel() != n):
         raise StrsortError("perm, lcp and d must have the same length")
-    size = n if n_strings is None else int(n_strings)
-    out = torch.zeros(max(size, 0), dtype=torch.int32, device=perm.device)
-    _check(lib().ss_dist_exact_bounded(_p(perm.contiguous()), _p(lcp_.contiguous()), _p(d.contiguous()), n,
-                                       _p(out), _stream(perm.device)))
+    if perm is None:
+        out = torch.empty(n, dtype=torch.int32, device=lcp_.device)
+    else:
+        size = n if n_strings is None else int(n_strings)
+        out = torch.zeros(max(size, 0), dtype=torch.int32, device=perm.device)
+    _check(lib().ss_dist_exact_bounded(_p(perm.contiguous()) if perm is not None else None, _p(lcp_.contiguous()),
+                                       _p(d.contiguous()), n, _p(out), _stream(lcp_.device)))
     return out
 
 

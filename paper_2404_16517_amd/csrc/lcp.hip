@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void k_dist_bounded(u32 n, const u32 *perm, co
     const u32 b = (i + 1 < n) ? lcp[i + 1] : 0u;
     const u64 m = (u64)(a > b ? a : b) + 1;
     const u32 di = d[i];
-    dist[perm[i]] = (u32)(m < di ? m : di);
+    dist[perm ? perm[i] : i] = (u32)(m < di ? m : di);
 }
 
 extern "C" int ss_dist_exact_bounded(const uint32_t *perm, const uint32_t *lcp, const uint32_t *d, uint64_t n,
@@ -115,10 +115,10 @@ extern "C" int ss_dist_exact_bounded(const uint32_t *perm, const uint32_t *lcp, 
     ss_clear_error();
     if (n >= 0xFFFFFFFFull) { ss_set_error("n too large"); return SS_ERR_TOO_LARGE; }
     if (n == 0) return SS_OK;
-    if (!perm || !lcp || !d || !dist) { ss_set_error("null pointer"); return SS_ERR_INVALID_ARG; }
+    if (!lcp || !d || !dist) { ss_set_error("null pointer"); return SS_ERR_INVALID_ARG; }
     hipStream_t st = (hipStream_t)stream;
     {
-        SS_PROF("k_dist_exact", st, (double)n * 16.0);  // perm, lcp, d in; dist out
+        SS_PROF("k_dist_exact", st, (double)n * (perm ? 16.0 : 12.0));  // perm, lcp, d in; dist out
         k_dist_bounded<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>((u32)n, perm, lcp, d, dist);
     }
     SS_CHECK_LAUNCH();

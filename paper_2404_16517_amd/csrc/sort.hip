@@ -152,119 +152,201 @@ __global__ void k_sizes(const Seg *segs, u32 nseg, u32 *out)
 
 // ------------------------------------------------------------ round kernels
 
-#define SKG 8     // lanes per string in the skip kernel: 64 consecutive bytes per step
-#define SKU 2     // strings per lane group in flight
-#define SKFS 256  // words (8 bytes) of the segment's first string staged in LDS
+#define SKB 16      // strings per wavefront batch in the skip kernel
+#define SKC_LONG 18  // 16-byte chunks per string of a long window (covers >= 273 bytes)
+#define SKC_SHORT 5  // ... of a short window (covers >= 65 bytes)
+#define SKR 5120     // LDS bytes per wavefront: five 1 KiB transfer rows
+#define SKFS 256     // words (8 bytes) of the segment's first string staged in LDS
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// 8 bytes (little-endian) at any byte offset of LDS, from aligned words.
+__device__ __forceinline__ u64 lds_le8(const u8 *R, u32 a)
+{
+    const u32 *p = (const u32 *)(R + (a & ~3u));
+    const u32 r = a & 3u;
+    u64 v = (u64)p[0] | ((u64)p[1] << 32);
+    if (r) v = (v >> (8 * r)) | ((u64)p[2] << (64 - 8 * r));
+    return v;
+}
+
+__device__ __forceinline__ u64 mask_le(u64 v, u32 take) { return take >= 8 ? v : (v & ((1ull << (8 * take)) - 1ull)); }
+
+// Copy the window chunks of the batch's strings into the wavefront's LDS rows:
+// chunk c of string s (16 bytes at the string's 16-aligned window start wa[s]
+// plus 16c, relative to `bytes`) goes to R + 16 (CH s + c); wn[s] chunks are
+// copied (0 for a window reaching outside the byte array, which is compared
+// from global memory instead).
+template <int CH>
+__device__ __forceinline__ void skip_copy(const u8 *bytes, u8 *R, u32 lane, const u64 *wa, const u32 *wn)
+{
+    constexpr int T = (SKB * CH + 63) / 64;
+    u64 ad[T];
+    bool ok[T];
+#pragma unroll
+    for (int t = 0; t < T; t++) {  // every address first: the copies then issue back to back
+        u32 slot = 64 * t + lane;
+        asm volatile("" : "+v"(slot));  // recomputed per window rather than held in registers
+        const u32 s = slot / CH, c = slot % CH;
+        ad[t] = wa[s & 15] + 16u * c;
+        ok[t] = s < SKB && c < wn[s & 15];
+    }
+#pragma unroll
+    for (int t = 0; t < T; t++)
+        if (ok[t]) __builtin_amdgcn_global_load_lds((const void *)(bytes + ad[t]), (lds_void *)(R + 1024 * t), 16, 0, 0);
+}
+
+// First mismatch of a member with the first string in [x, lim): each of the
+// member's four lanes compares words q, q+4, q+8, ... (8 bytes each) of the
+// window.  Returns the position (~0 if none) after a minimum over the four.
+// Positions are string-relative (strings are shorter than 2^32 bytes).
+template <int CH>
+__device__ __forceinline__ u32 skip_cmp(const u8 *bytes, u64 N, const u8 *R, const u64 *fsw, u32 s, u32 q,
+                                        u32 x, u32 lim, u32 sh, bool edge, u64 o, u64 fo, u32 depth)
+{
+    constexpr int WPL = (16 * CH + 31) / 32;  // words per lane
+    const u32 rl = lim - x;                    // window bytes to compare (<= 16 CH)
+    const u32 k0 = (x - depth) >> 3;           // first-string word of the window start
+    const u32 rb = 16 * CH * s + sh;           // LDS offset of the window start
+    u32 best = 0xFFFFFFFFu;
+#pragma unroll 3
+    for (int k = 0; k < WPL; k++) {
+        const u32 w = q + 4 * k;
+        const u32 rel = 8 * w;
+        const u32 take = rel < rl ? ((rl - rel) < 8 ? rl - rel : 8u) : 0u;
+        u64 wa = 0, wb = 0;
+        if (take) {
+            wa = edge ? load_le(bytes, N, o + x + rel, take) : mask_le(lds_le8(R, rb + rel), take);
+            const u32 kw = k0 + w;
+            wb = kw < SKFS ? mask_le(fsw[kw], take) : load_le(bytes, N, fo + x + rel, take);
+        }
+        const u64 d = wa ^ wb;
+        const u32 mp = d ? rel + (u32)(__builtin_ctzll(d) >> 3) : 0xFFFFFFFFu;
+        best = mp < best ? mp : best;
+    }
+#pragma unroll
+    for (int o2 = 1; o2 < 4; o2 <<= 1) {
+        const u32 y = __shfl_xor(best, o2, 64);
+        best = y < best ? y : best;
+    }
+    return best == 0xFFFFFFFFu ? best : x + best;
+}
 
 // Minimum LCP of every member with the segment's first string, from `depth`.
-// A group of 8 lanes compares 64 consecutive bytes of each of two members per
-// step; the first string's bytes [depth, depth + 2048) come from LDS.  Each
-// member also leaves its first mismatch position, its remaining length there
-// (capped at 8) and its 8 bytes there (mword, mpr), from which k_keys builds
-// its key without reading the string again.
+// Each wavefront takes its members 16 at a time, four lanes per member: the
+// window of every member (a short one of >= 65 bytes, or a long one of >= 273
+// bytes once most members of the previous batch reached past 48 bytes) is
+// copied from global memory into LDS by the transfer unit, then the four lanes
+// compare it, 8 bytes at a time, against the first string's bytes
+// [depth, depth + 2048) in LDS.  Members not resolved inside their window
+// continue with the next one.  Each member also leaves its first mismatch
+// position, its remaining length there (capped at 8) and its 8 bytes there
+// (mword, mpr), from which k_keys builds its key without reading the string
+// again.
 __global__ __launch_bounds__(NT) void k_skip(const Seg *segs, const u32 *tstart, u32 nseg,
                                              const u8 *bytes, u64 N, const u64 *off,
                                              const u32 *perm, u32 *skipv, u64 *mword, uint2 *mpr)
 {
     __shared__ u64 fsw[SKFS];
+    __shared__ __attribute__((aligned(16))) u8 rows[(NT / 64) * SKR];
+    __shared__ u64 wwa[NT / 64][SKB];  // per wavefront: window start of each member
+    __shared__ u32 wwn[NT / 64][SKB];  // ... and its chunk count
     const u32 t = blockIdx.x;
-    const u32 s = seg_of_tile(tstart, nseg, t);
-    const Seg g = segs[s];
+    const u32 sg = seg_of_tile(tstart, nseg, t);
+    const Seg g = segs[sg];
     if (!(g.aux & SEG_SKIP)) return;  // uniform over the workgroup
-    const u32 lt = t - tstart[s];
+    const u32 lt = t - tstart[sg];
     const u32 b0 = g.begin + lt * ETILE;
     const u32 b1 = min(g.end, b0 + ETILE);
     const u32 f = perm[g.begin];
-    const u64 fo = off[f], fl = off[f + 1] - fo;
-    const u64 fd = fl > g.depth ? fl - g.depth : 0;  // first-string bytes from depth
+    const u64 fo = off[f];
+    const u32 fl = (u32)(off[f + 1] - fo);
+    const u32 depth = g.depth;
+    const u32 fd = fl > depth ? fl - depth : 0;  // first-string bytes from depth
     for (u32 q = threadIdx.x; q < SKFS; q += NT) {
-        const u64 k = 8ull * q;
-        fsw[q] = k < fd ? load_be(bytes, N, fo + g.depth + k, (u32)((fd - k) < 8 ? (fd - k) : 8)) : 0ull;
+        const u32 k = 8 * q;
+        fsw[q] = k < fd ? load_le(bytes, N, fo + depth + k, (fd - k) < 8 ? fd - k : 8u) : 0ull;
     }
     __syncthreads();
-    const u32 grp = threadIdx.x / SKG, lane = threadIdx.x % SKG;
-    u64 best = ~0ull;
-    for (u32 i = b0 + grp * SKU; i < b1; i += (NT / SKG) * SKU) {
-        u64 o[SKU], m[SKU], x[SKU], res[SKU], len[SKU];
-        bool act[SKU];
-#pragma unroll
-        for (int u = 0; u < SKU; u++) {
-            act[u] = false;
-            res[u] = ~0ull;
-            o[u] = 0;
-            m[u] = 0;
-            len[u] = 0;
-            x[u] = g.depth;
-            if (i + u < b1) {
-                const u32 p = perm[i + u];
-                o[u] = off[p];
-                const u64 l = off[p + 1] - o[u];
-                len[u] = l;
-                m[u] = l < fl ? l : fl;
-                res[u] = m[u];
-                act[u] = x[u] < m[u];
-            }
+    const u32 lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const u32 sl = lane >> 2, q = lane & 3;  // this lane's member of the batch, its quarter
+    u8 *R = rows + wv * SKR;
+    const u64 babs = (u64)(uintptr_t)bytes;
+    bool longw = false;  // window size of the next batch (uniform over the wavefront)
+    u32 best = 0xFFFFFFFFu;
+    for (u32 i0 = b0 + wv * SKB; i0 < b1; i0 += (NT / 64) * SKB) {
+        const u32 i = i0 + sl;
+        const bool valid = i < b1;
+        u64 o = 0;
+        u32 len = 0, m = 0;
+        if (valid) {
+            const u32 p = perm[i];
+            o = off[p];
+            len = (u32)(off[p + 1] - o);
+            m = len < fl ? len : fl;
         }
-        bool any = false;
-#pragma unroll
-        for (int u = 0; u < SKU; u++) any |= act[u];
-        while (any) {  // uniform over the lane group
-            u64 pos[SKU];
-            Raw8 ra[SKU];
-#pragma unroll
-            for (int u = 0; u < SKU; u++) {  // the loads of all strings first
-                const u64 q = x[u] + 8 * lane;
-                const u32 take = (act[u] && q < m[u]) ? ((m[u] - q) < 8 ? (u32)(m[u] - q) : 8u) : 0u;
-                ra[u] = raw8_issue(bytes, N, o[u] + q, take);
+        u32 res = m, x = depth;
+        bool act = valid && depth < m;
+        while (__ballot(act)) {  // uniform over the wavefront
+            const u32 CH = longw ? SKC_LONG : SKC_SHORT;
+            const u64 A0 = (babs + o + x) & ~15ull;
+            const u32 sh = (u32)((babs + o + x) & 15);
+            const u32 cov = 16 * CH - sh;                      // window bytes from x
+            const u32 wend = len - x < cov ? len : x + cov;    // copied: [x, wend)
+            const u32 lim = m - x < cov ? m : x + cov;         // compared: [x, lim)
+            const u32 nch = act ? (sh + (wend - x) + 15) / 16 : 0u;
+            // a window reaching outside the byte array is compared from global memory
+            const bool edge = act && (A0 < babs || A0 + 16ull * nch > babs + N);
+            if (q == 0) {  // (read back below by the same wavefront: LDS keeps its order)
+                wwa[wv][sl] = A0 - babs;
+                wwn[wv][sl] = edge ? 0u : nch;
             }
-#pragma unroll
-            for (int u = 0; u < SKU; u++) {
-                pos[u] = ~0ull;
-                if (ra[u].take == 0) continue;
-                const u64 q = x[u] + 8 * lane;
-                const u32 take = ra[u].take;
-                const u64 wa = __builtin_bswap64(raw8_le(bytes, ra[u]));
-                const u64 k = q - g.depth;  // multiple of 8
-                u64 wb = k < 8ull * SKFS ? fsw[k >> 3] : load_be(bytes, N, fo + q, take);
-                if (take < 8) wb &= ~0ull << (64 - 8 * take);
-                if (wa != wb) pos[u] = q + (__clzll(wa ^ wb) >> 3);
+            u32 mis;
+            if (longw) {
+                skip_copy<SKC_LONG>(bytes, R, lane, wwa[wv], wwn[wv]);
+                mis = skip_cmp<SKC_LONG>(bytes, N, R, fsw, sl, q, x, act ? lim : x, sh, edge, o, fo, depth);
+            } else {
+                skip_copy<SKC_SHORT>(bytes, R, lane, wwa[wv], wwn[wv]);
+                mis = skip_cmp<SKC_SHORT>(bytes, N, R, fsw, sl, q, x, act ? lim : x, sh, edge, o, fo, depth);
             }
-            any = false;
-#pragma unroll
-            for (int u = 0; u < SKU; u++) {
-#pragma unroll
-                for (int s2 = SKG / 2; s2 > 0; s2 >>= 1) {
-                    const u64 y = __shfl_xor(pos[u], s2, SKG);
-                    pos[u] = y < pos[u] ? y : pos[u];
-                }
-                if (act[u]) {
-                    if (pos[u] != ~0ull) {
-                        res[u] = pos[u];
-                        act[u] = false;
-                    } else {
-                        x[u] += 8 * SKG;
-                        act[u] = x[u] < m[u];
+            if (act) {
+                u32 r = mis;
+                if (r == 0xFFFFFFFFu && lim >= m) r = m;
+                if (r != 0xFFFFFFFFu) {
+                    // the member's 8 bytes at its mismatch, from the window when it holds them
+                    const u32 rem = len - r;
+                    const u32 tk = rem < 8 ? rem : 8u;
+                    if (q == 0) {
+                        u64 mw = 0;
+                        if (tk)
+                            mw = (!edge && r + tk <= wend) ? mask_le(lds_le8(R, 16 * CH * sl + sh + (r - x)), tk)
+                                                           : load_le(bytes, N, o + r, tk);
+                        mword[i] = __builtin_bswap64(mw);
+                        mpr[i] = make_uint2(r, tk);
                     }
+                    res = r;
+                    act = false;
+                } else {
+                    x += cov & ~7u;
                 }
-                any |= act[u];
             }
         }
-#pragma unroll
-        for (int u = 0; u < SKU; u++)
-            if (i + u < b1) {
-                const u64 c = res[u] > g.depth ? res[u] - g.depth : 0ull;
-                best = c < best ? c : best;
-                if (lane == 0) {
-                    const u64 rem = len[u] - res[u];
-                    const u32 tk = rem < 8 ? (u32)rem : 8u;
-                    mword[i + u] = load_be(bytes, N, o[u] + res[u], tk);
-                    mpr[i + u] = make_uint2((u32)res[u], tk);
-                }
+        // most of the batch reaching past 48 bytes from depth: long windows next
+        const bool far = valid && res >= depth + 48;
+        longw = __popcll(__ballot(far && q == 0)) >= SKB / 2;
+        if (valid && q == 0) {
+            const u32 c = res > depth ? res - depth : 0u;
+            best = c < best ? c : best;
+            if (m <= depth) {  // nothing to compare: the member ends at or before depth
+                const u32 rem = len - res;
+                const u32 tk = rem < 8 ? rem : 8u;
+                mword[i] = load_be(bytes, N, o + res, tk);
+                mpr[i] = make_uint2(res, tk);
             }
+        }
     }
-    const u32 b32 = best > 0xFFFFFFFFull ? 0xFFFFFFFFu : (u32)best;
-    const u32 bm = block_min(b32);
-    if (threadIdx.x == 0) atomicMin(&skipv[s], bm);
+    const u32 bm = block_min(best);
+    if (threadIdx.x == 0) atomicMin(&skipv[sg], bm);
 }
 
 __global__ __launch_bounds__(NT) void k_keys(const Seg *segs, const u32 *tstart, u32 nseg,
@@ -833,18 +915,35 @@ __global__ __launch_bounds__(256) void k_wave_sort(const Seg *tiny, u32 ntiny, u
     if (threadIdx.x == 0) { nq_count = 0; nq_tiles = 0; nq_elems = 0; }
     __syncthreads();
     const u32 lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const u32 e0 = lane, e1 = lane + 64;
+    // This wavefront's segments: all descriptors first, and each segment's
+    // keys and payload loaded while the previous one is being sorted.
+    Seg gq[WS_SPB / 4];
+#pragma unroll
+    for (u32 q = 0; q < WS_SPB / 4; q++) {
+        const u32 sidx = blockIdx.x * WS_SPB + q * 4 + wv;
+        gq[q] = sidx < ntiny ? tiny[sidx] : Seg{0, 0, 0, 0};
+    }
+    u64 nk0 = ~0ull, nk1 = ~0ull;
+    u32 nv0 = 0xFFFFFFFFu, nv1 = 0xFFFFFFFFu;
+    auto fetch = [&](const Seg &g) {
+        const u32 cnt = g.end - g.begin;
+        const u64 *ks = (g.aux & SEG_INB) ? keyB : keys;  // read where the segment is, write A
+        const u32 *vs = (g.aux & SEG_INB) ? valB : vals;
+        nk0 = ~0ull; nk1 = ~0ull; nv0 = 0xFFFFFFFFu; nv1 = 0xFFFFFFFFu;
+        if (e0 < cnt) { nk0 = ks[g.begin + e0]; nv0 = vs[g.begin + e0]; }
+        if (e1 < cnt) { nk1 = ks[g.begin + e1]; nv1 = vs[g.begin + e1]; }
+    };
+    fetch(gq[0]);
+#pragma unroll
     for (u32 q = 0; q < WS_SPB / 4; q++) {
         const u32 sidx = blockIdx.x * WS_SPB + q * 4 + wv;
         if (sidx >= ntiny) break;  // uniform over the wavefront
-        const Seg g = tiny[sidx];
+        const Seg g = gq[q];
         const u32 cnt = g.end - g.begin;
-        const u32 e0 = lane, e1 = lane + 64;
-        u64 k0 = ~0ull, k1 = ~0ull;
-        u32 v0 = 0xFFFFFFFFu, v1 = 0xFFFFFFFFu;
-        const u64 *ks = (g.aux & SEG_INB) ? keyB : keys;  // read where the segment is, write A
-        const u32 *vs = (g.aux & SEG_INB) ? valB : vals;
-        if (e0 < cnt) { k0 = ks[g.begin + e0]; v0 = vs[g.begin + e0]; }
-        if (e1 < cnt) { k1 = ks[g.begin + e1]; v1 = vs[g.begin + e1]; }
+        u64 k0 = nk0, k1 = nk1;
+        u32 v0 = nv0, v1 = nv1;
+        if (q + 1 < WS_SPB / 4) fetch(gq[q + 1]);
         u32 P = 2;
         while (P < cnt) P <<= 1;
         for (u32 k = 2; k <= P; k <<= 1) {

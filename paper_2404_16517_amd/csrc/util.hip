@@ -333,29 +333,62 @@ struct ProfRec {
 };
 std::mutex g_prof_mu;
 std::vector<ProfRec> g_prof;
+// Events are reused across profiling windows (creating two per launch costs
+// host time inside the timed region).  They only mark times on the device, so
+// they carry no system-scope fence.
+std::vector<hipEvent_t> g_ev_free;
 
 void prof_clear()
 {
     for (auto &r : g_prof) {
-        hipEventDestroy(r.a);
-        hipEventDestroy(r.b);
+        g_ev_free.push_back(r.a);
+        g_ev_free.push_back(r.b);
     }
     g_prof.clear();
+}
+
+hipEvent_t ev_take()
+{
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (!g_ev_free.empty()) {
+            hipEvent_t e = g_ev_free.back();
+            g_ev_free.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
+    return e;
+}
+
+void ev_give(hipEvent_t e)
+{
+    if (!e) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_ev_free.push_back(e);
 }
 }  // namespace
 
 ProfScope::ProfScope(const char *n, hipStream_t s, double b) : name(n), st(s), bytes(b), a(nullptr), on(g_prof_on)
 {
     if (!on) return;
-    if (hipEventCreate(&a) != hipSuccess || hipEventRecord(a, st) != hipSuccess) on = false;
+    a = ev_take();
+    if (!a || hipEventRecord(a, st) != hipSuccess) {
+        ev_give(a);
+        on = false;
+    }
 }
 
 ProfScope::~ProfScope()
 {
     if (!on) return;
-    hipEvent_t b;
-    if (hipEventCreate(&b) != hipSuccess) return;
-    if (hipEventRecord(b, st) != hipSuccess) return;
+    hipEvent_t b = ev_take();
+    if (!b || hipEventRecord(b, st) != hipSuccess) {
+        ev_give(a);
+        ev_give(b);
+        return;
+    }
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof.push_back(ProfRec{name, a, b, bytes});
 }
@@ -377,8 +410,8 @@ void ss_prof_drop_last(const char *name)
     std::lock_guard<std::mutex> lk(g_prof_mu);
     for (size_t i = g_prof.size(); i-- > 0;)
         if (g_prof[i].name == name) {
-            hipEventDestroy(g_prof[i].a);
-            hipEventDestroy(g_prof[i].b);
+            g_ev_free.push_back(g_prof[i].a);
+            g_ev_free.push_back(g_prof[i].b);
             g_prof.erase(g_prof.begin() + (long)i);
             return;
         }

@@ -47,6 +47,31 @@ EDGE_SETS = {
 }
 
 
+@pytest.mark.parametrize("name", ["n1", "n2_equal", "empty_strings", "prefix_chain", "zero_ff", "deep_shared"])
+@pytest.mark.parametrize("by_input", [True, False])
+def test_dist_exact_bounded_any_bound(name, by_input):
+    """dist from any bound dist <= d <= len equals the oracle's exact dist,
+    written by input index (perm given) or by sorted position (perm NULL)."""
+    s = synth.from_list(EDGE_SETS[name])
+    _log(f"[dist_bounded] {name} by_input={by_input}")
+    b, o = oracle.strings_np(s)
+    p_ref = oracle.sort(b, o)
+    l_ref = oracle.lcp(b, o, p_ref)
+    d_ref = oracle.dist_exact(o, p_ref, l_ref)
+    lens = np.diff(o.astype(np.int64))
+    rng = np.random.default_rng(3)
+    # a bound per sorted position anywhere in [dist, len]
+    lo = d_ref[p_ref].astype(np.int64)
+    hi = lens[p_ref]
+    bound = (lo + (rng.random(s.n) * (hi - lo + 1)).astype(np.int64)).astype(np.uint32)
+    perm = torch.from_numpy(p_ref.view(np.int32)).to(DEV)
+    lcp_ = torch.from_numpy(l_ref.view(np.int32)).to(DEV)
+    d = torch.from_numpy(bound.view(np.int32)).to(DEV)
+    out = ss.dist_exact_bounded(perm if by_input else None, lcp_, d)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(u32(out), d_ref if by_input else d_ref[p_ref])
+
+
 def _rand_strings(rng, n, alphabet, max_len):
     return [bytes(rng.choice(alphabet) for _ in range(rng.randint(0, max_len))) for _ in range(n)]
 
@@ -684,8 +709,10 @@ def _pipeline(sets, bounds, spl, pdms):
     ss.join_group_lcps(g.bytes, g.offsets, order, mlcp, run_begin, run_end, group_off)
     dist_x = ss.dist_exact(g.offsets, order, mlcp)
     dist_b = ss.dist_exact_bounded(order, mlcp, mlen)
+    dist_s = ss.dist_exact_bounded(None, mlcp, mlen)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(u32(dist_b), u32(dist_x))
+    np.testing.assert_array_equal(u32(dist_s), u32(dist_x)[u32(order)])
     return order, mlcp, dist_x
 
 
