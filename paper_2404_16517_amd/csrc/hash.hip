@@ -327,8 +327,19 @@ __global__ __launch_bounds__(256) void k_hash_first(u32 n, const u8 *bytes, u64 
 // weights for P < 1024 (built in LDS by each workgroup) serves every chunk and
 // the int32 sums of a chunk are scaled by B^(-256c) once.  Each byte is split
 // as 128 h + low (h in {0,1}, low < 128) so that both MFMA operands are
-// non-negative and bytes past the string (zero) add nothing: two
-// v_mfma_i32_16x16x64_i8 per 64-byte step and 16 strings.
+// non-negative and bytes past the string (zero) add nothing.
+//
+// One v_mfma_i32_32x32x32_i8 takes 32 bytes of 32 strings (B operand: column =
+// string, lane l holds string l mod 32, bytes 16 (l / 32) .. + 16 of the
+// block) against 32 weight rows (A operand).  Lane l's results are rows
+// 8 (r / 4) + 4 (l / 32) + r mod 4 of its string (r < 16): row set 0 (rows
+// 0..3, 8..11, 16, 17) lands in registers 0..9 of lane half 0, row set 1
+// (rows 4..7, 12..15, 20, 21) in registers 0..9 of half 1.  Set 0 holds the
+// full weights, set 1 the weights below l1 (two-round launches).  Register d
+// sums the products of the low bits with digit d and, from a second product
+// whose weight rows are shifted by one, of the high bits with digit d - 1
+// (128 c 2^(7(d-1)) = c 2^(7d)).  Every lane combines its own ten sums: half 0
+// carries G to l_end, half 1 carries G to l1, with no exchange between lanes.
 struct RoundW {
     u64 iblo[16];  // B^-(r+1), r < 16
     u64 ibhi[16];  // B^-16k, k < 16
@@ -348,172 +359,296 @@ __device__ __forceinline__ u64 kr_pow(u64 L, const RoundW &rw)
 }
 
 #define RW_STEPS 16  // 64-byte steps per 1024-byte chunk
-#define RW_U 4       // steps whose loads are issued together
+#define RP_STEPS 2   // 64-byte steps per pass
+#define RP_CH 9      // 16-byte chunks per string and pass (128 bytes at any alignment)
+#define RP_ROW 5120  // LDS bytes per wavefront: five 1 KiB copy rows (32 x 9 chunks)
 
-__global__ __launch_bounds__(256) void k_hash_round(const u32 *act, const u32 *cnt, const u8 *bytes, u64 N,
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef __attribute__((address_space(3))) void lds_void_h;
+
+// sum_d v_d 2^(7d) mod p for the ten digit sums v_d < 2^25 of one lane:
+// accumulated as a 128-bit integer (< 2^89), then folded with 2^64 = 8.
+__device__ __forceinline__ u64 digits_mod61(const v16i &S)
+{
+    u64 lo = 0, hi = 0;
+#pragma unroll
+    for (int d = 0; d < 10; d++) {
+        const u64 v = (u64)(u32)S[d];
+        const u64 a = d ? v << (7 * d) : v;
+        const u64 c = (d && 7 * d > 39) ? v >> (64 - 7 * d) : 0ull;
+        const u64 t = lo + a;
+        hi += c + (t < lo ? 1ull : 0ull);
+        lo = t;
+    }
+    u64 r = (lo & KR_P) + (lo >> 61) + (hi << 3);
+    r = (r & KR_P) + (r >> 61);
+    return r >= KR_P ? r - KR_P : r;
+}
+
+// 16 bytes (two little-endian words) at any byte offset of LDS, from aligned words.
+__device__ __forceinline__ void lds_le16(const u8 *R, u32 a, u64 &lo, u64 &hi)
+{
+    const u32 *p = (const u32 *)(R + (a & ~3u));
+    const u32 r = a & 3u;
+    u32 d[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++) d[k] = p[k];
+    u32 q[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) q[k] = r ? __builtin_amdgcn_alignbyte(d[k + 1], d[k], r) : d[k];
+    lo = (u64)q[0] | ((u64)q[1] << 32);
+    hi = (u64)q[2] | ((u64)q[3] << 32);
+}
+
+// One pass = RP_STEPS steps of a tile's 32 strings.  Before its products are
+// taken, every string's bytes of the pass are copied into the wavefront's LDS
+// rows by the transfer unit (chunk c of string s at 16 (RP_CH s + c), from
+// the string's 16-aligned pass start), so that each copy instruction reads
+// long runs of one string; the lanes then read their MFMA operands from LDS.
+// The copy of the next pass is issued before the current pass's products.
+__global__ __launch_bounds__(256, 4) void k_hash_round(const u32 *act, const u32 *cnt, const u8 *bytes, u64 N,
                                                     const u64 *off, u64 lprev, u64 l1, u64 l2, u32 bits,
                                                     u64 *state, u64 *keys1, u64 *keys2, RoundW rw, u64 *rf)
 {
-    // round flags of this lane's keys (rounds l1 and l2), committed per wavefront
-    u64 fmn[2] = {~0ull, ~0ull}, fmx[2] = {0, 0}, fsh[2] = {0, 0};
-    __shared__ v4i wtab[RW_STEPS * 64];  // [step of the chunk][lane]: the weight operand
-    const u32 lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
-    for (u32 e = threadIdx.x; e < RW_STEPS * 64; e += blockDim.x) {
-        const u32 s = e >> 6, ln = e & 63, d = ln & 15, kg = ln >> 4;
+    // digit weights: [step of the chunk][32-byte block][16-byte half][digit]
+    __shared__ v4i wtab[RW_STEPS * 2 * 2 * 9];
+    __shared__ __attribute__((aligned(16))) u8 rows[4 * RP_ROW];
+    __shared__ u64 pwa[4][32];  // per wavefront: pass start (16-aligned, relative) of each string
+    __shared__ u32 pwn[4][32];  // ... and its chunk count (0: not copied)
+    for (u32 e = threadIdx.x; e < RW_STEPS * 2 * 2 * 9; e += blockDim.x) {
+        const u32 d = e % 9, kh = (e / 9) & 1, kb = (e / 18) & 1, st = e / 36;
         u32 wd[4] = {0, 0, 0, 0};
-        if (d < 9) {
 #pragma unroll
-            for (int q = 0; q < 4; q++) {  // the four limbs of the lane's 16 positions
-                const u32 j = 16 * s + 4 * kg + q;
-                const u64 ib = mulmod61(rw.iblo[j & 15], rw.ibhi[j >> 4]);
+        for (int q = 0; q < 4; q++) {  // the four limbs of the 16 positions
+            const u32 j = 16 * st + 8 * kb + 4 * kh + q;
+            const u64 ib = mulmod61(rw.iblo[j & 15], rw.ibhi[j >> 4]);
 #pragma unroll
-                for (int b = 0; b < 4; b++) {
-                    const u32 c = (u32)((rot61(ib, 8 * b) >> (7 * d)) & 127u);
-                    wd[q] |= c << (8 * b);
-                }
+            for (int b = 0; b < 4; b++) {
+                const u32 c = (u32)((rot61(ib, 8 * b) >> (7 * d)) & 127u);
+                wd[q] |= c << (8 * b);
             }
         }
         wtab[e] = v4i{(int)wd[0], (int)wd[1], (int)wd[2], (int)wd[3]};
     }
     __syncthreads();
+    const u32 lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5, wv = threadIdx.x >> 6;
+    u8 *R = rows + wv * RP_ROW;
+    const u64 babs = (u64)(uintptr_t)bytes;
+    // this lane's weight row: register dr of row set 0 (full weights) or set 1
+    // (weights below l1); digit dr in the low-bit product, dr - 1 in the high-bit one
+    const u32 dr = 4 * (col >> 3) + (col & 3);
+    const bool rowl1 = (col & 4) != 0;
+    const bool rowlo = dr < 9, rowhi = dr >= 1 && dr < 10;
+    // positions inside a string fit in 32 bits
+    const bool two = l2 != 0;
+    const u32 L1 = (u32)l1, LP = (u32)lprev;
+    const u32 lend = two ? (u32)l2 : L1;
+    const u32 lmine = (two && h) ? L1 : lend;  // the round this lane finishes
+    u64 fmn = ~0ull, fmx = 0, fsh = 0;
     const u32 A = *cnt;
-    const u64 lend = l2 ? l2 : l1;
-    const u32 ntiles = (A + 15) / 16;
+    const u32 ntiles = (A + 31) / 32;
     const u32 wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
-    const u64 x0 = lprev & ~63ull;
-    // Software pipeline over this wave's tiles: the list entry of the tile
-    // after next and the offsets and state of the next tile are loaded while
-    // the current tile's bytes are in flight.  Indices past the list are
-    // clamped to its last entry so that the loads need no branch.
+    const u32 x0 = LP & ~63u;
+    // Indices past the list are clamped to its last entry so that the loads
+    // need no branch.
     auto entry = [&](u32 tile) -> u32 {
-        const u32 jj = tile * 16 + col;
+        const u32 jj = tile * 32 + col;
         const u32 jc = jj < A ? jj : A - 1;
         return act ? act[jc] : jc;
     };
-    u32 i_cur = 0, i_nxt = 0;
-    u64 o_cur = 0, e_cur = 0, G_cur = 0;
+    auto tile_xmax = [&](u32 m) -> u32 {
+#pragma unroll
+        for (int s2 = 1; s2 < 32; s2 <<= 1) {
+            const u32 t = __shfl_xor(m, s2);
+            m = t > m ? t : m;
+        }
+        return m;
+    };
+    // copy pass [xp, xp + 128) of this lane's string (string end m) into the rows
+    auto issue_copy = [&](u64 o, u32 m, u32 xp) {
+        const u64 A0 = (babs + o + xp) & ~15ull;
+        const u32 sh = (u32)((babs + o + xp) & 15);
+        const u32 need = m > xp ? ((m - xp < 64 * RP_STEPS ? m : xp + 64 * RP_STEPS) - xp) : 0u;
+        const u32 nch = need ? (sh + need + 15) / 16 : 0u;
+        const bool edge = nch && (A0 < babs || A0 + 16ull * nch > babs + N);
+        if (h == 0) {  // (read back below by the same wavefront: LDS keeps its order)
+            pwa[wv][col] = A0 - babs;
+            pwn[wv][col] = edge ? 0u : nch;
+        }
+        constexpr int T = (32 * RP_CH + 63) / 64;
+        u64 ad[T];
+        bool ok[T];
+#pragma unroll
+        for (int t = 0; t < T; t++) {  // every address first: the copies then issue back to back
+            u32 slot = 64 * t + lane;
+            asm volatile("" : "+v"(slot));  // recomputed per pass rather than held in registers
+            const u32 sx = slot / RP_CH, c = slot % RP_CH;
+            ad[t] = pwa[wv][sx & 31] + 16u * c;
+            ok[t] = sx < 32 && c < pwn[wv][sx & 31];
+        }
+#pragma unroll
+        for (int t = 0; t < T; t++)
+            if (ok[t]) __builtin_amdgcn_global_load_lds((const void *)(bytes + ad[t]), (lds_void_h *)(R + 1024 * t), 16, 0, 0);
+    };
     if (wave < ntiles) {
-        i_cur = entry(wave);
-        o_cur = off[i_cur];
-        e_cur = off[i_cur + 1];
-        if (lprev) G_cur = state[i_cur];
-        i_nxt = entry(wave + nwaves < ntiles ? wave + nwaves : wave);
-    }
-    for (u32 tile = wave; tile < ntiles; tile += nwaves) {  // uniform over the wavefront
-        const u32 j = tile * 16 + col;
-        const bool valid = j < A;
-        const u32 i = i_cur;
-        const u64 o = o_cur;
-        const u64 len = valid ? e_cur - o_cur : 0;
-        const u64 m = len < lend ? len : lend;
-        u64 G = valid ? G_cur : 0;
-        // next tile's offsets and state, the entry after that
-        const bool more = tile + nwaves < ntiles;
-        const u32 i_n = i_nxt;
-        u64 o_n = 0, e_n = 0, G_n = 0;
-        u32 i_nn = i_n;
+        // current tile: entry, offsets, state; the next tile's entry
+        u32 tile = wave;
+        u32 i_c = entry(tile);
+        bool valid = tile * 32 + col < A;
+        u64 o_c = off[i_c];
+        u32 len = valid ? (u32)(off[i_c + 1] - o_c) : 0u;
+        u64 G = (valid && lprev) ? state[i_c] : 0ull;
+        u32 i_n = entry(tile + nwaves < ntiles ? tile + nwaves : tile);
+        u64 o_n = 0, G_n = 0;
+        u32 len_n = 0;
+        bool more = tile + nwaves < ntiles;
         if (more) {
             o_n = off[i_n];
-            e_n = off[i_n + 1];
+            len_n = (u32)(off[i_n + 1] - o_n);
             if (lprev) G_n = state[i_n];
-            i_nn = entry(tile + 2 * nwaves < ntiles ? tile + 2 * nwaves : tile + nwaves);
         }
-        i_cur = i_n;
-        o_cur = o_n;
-        e_cur = e_n;
-        G_cur = G_n;
-        i_nxt = i_nn;
-        u64 xmax = m;
+        u32 i_nn = entry(tile + 2 * nwaves < ntiles ? tile + 2 * nwaves : tile);
+        u32 m = len < lend ? len : lend;
+        u32 xmax = tile_xmax(m);
+        u64 ibc = rw.ibc0;
+        v16i S = {};
+        u32 xp = x0;
+        issue_copy(o_c, m, xp);
+        for (;;) {  // passes; uniform over the wavefront
+            // this pass's operand bytes: [u][kb], 16 each (zero past the string)
+            u64 lo[RP_STEPS][2], hi[RP_STEPS][2];
+            {
+                const u32 sh = (u32)((babs + o_c + xp) & 15);
+                const u32 need = m > xp ? ((m - xp < 64 * RP_STEPS ? m : xp + 64 * RP_STEPS) - xp) : 0u;
+                const u32 nch = need ? (sh + need + 15) / 16 : 0u;
+                const u64 A0 = (babs + o_c + xp) & ~15ull;
+                const bool edge = nch && (A0 < babs || A0 + 16ull * nch > babs + N);
 #pragma unroll
-        for (int s2 = 1; s2 < 16; s2 <<= 1) {
-            const u64 t = __shfl_xor(xmax, s2);
-            xmax = t > xmax ? t : xmax;
-        }
-        u64 G1 = G, ibc = rw.ibc0;
-        v4i Sl = v4i{0, 0, 0, 0}, Sh = v4i{0, 0, 0, 0};
-        for (u64 xb = x0; xb < xmax; xb += 64 * RW_U) {  // uniform over the wavefront
-            // the loads of RW_U steps first, then their products
-            Win16 wn[RW_U];
+                for (int u = 0; u < RP_STEPS; u++)
 #pragma unroll
-            for (int u = 0; u < RW_U; u++) {
-                const u64 a0 = xb + 64 * u + 16ull * g;
-                const u64 hi_pos = a0 + 16 < m ? a0 + 16 : m;
-                const u32 take = hi_pos > a0 ? (u32)(hi_pos - a0) : 0u;
-                wn[u] = win16_issue(bytes, N, o + a0, take);
+                    for (int kb = 0; kb < 2; kb++) {
+                        const u32 rel = 64 * u + 32 * kb + 16 * h;
+                        const u32 take = need > rel ? ((need - rel) < 16 ? need - rel : 16u) : 0u;
+                        lo[u][kb] = hi[u][kb] = 0;
+                        if (take) {
+                            if (!edge) lds_le16(R, RP_CH * 16 * col + sh + rel, lo[u][kb], hi[u][kb]);
+                            else load16_le(bytes, N, o_c + xp + rel, take, lo[u][kb], hi[u][kb]);
+                            if (take < 8) {
+                                lo[u][kb] &= (1ull << (8 * take)) - 1ull;
+                                hi[u][kb] = 0;
+                            } else if (take < 16) {
+                                hi[u][kb] &= take == 8 ? 0ull : ((1ull << (8 * (take - 8))) - 1ull);
+                            }
+                        }
+                    }
             }
-            u64 lo[RW_U], hi[RW_U];
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the rows are read before the next copy
+            // the next pass: the rest of this tile, or the next tile's first
+            const bool tile_end = xp + 64 * RP_STEPS >= xmax;
+            u32 m_n = 0, xmax_n = 0;
+            bool valid_n = false;
+            if (!tile_end) {
+                issue_copy(o_c, m, xp + 64 * RP_STEPS);
+            } else if (more) {
+                valid_n = (tile + nwaves) * 32 + col < A;
+                if (!valid_n) len_n = 0;
+                m_n = len_n < lend ? len_n : lend;
+                xmax_n = tile_xmax(m_n);
+                issue_copy(o_n, m_n, x0);
+            }
+            // this pass's products
 #pragma unroll
-            for (int u = 0; u < RW_U; u++) win16_finish(bytes, wn[u], lo[u], hi[u]);
-#pragma unroll
-            for (int u = 0; u < RW_U; u++) {
-                const u64 x = xb + 64 * u;
+            for (int u = 0; u < RP_STEPS; u++) {
+                const u32 x = xp + 64 * u;
                 if (x >= xmax) break;  // uniform over the wavefront
-                const u64 a0 = x + 16ull * g;
-                if (a0 < lprev) {  // bytes below lprev are in G already
-                    const u64 skip = lprev - a0 < 16 ? lprev - a0 : 16;
-                    if (skip >= 8) {
-                        lo[u] = 0;
-                        hi[u] &= skip == 16 ? 0ull : ~((1ull << (8 * (skip - 8))) - 1ull);
-                    } else {
-                        lo[u] &= ~((1ull << (8 * skip)) - 1ull);
-                    }
-                }
-                const u64 l7 = 0x7F7F7F7F7F7F7F7Full, h1 = 0x0101010101010101ull;
-                const u64 lo7 = lo[u] & l7, hi7 = hi[u] & l7, loh = (lo[u] >> 7) & h1, hih = (hi[u] >> 7) & h1;
-                const v4i xl = v4i{(int)(u32)lo7, (int)(u32)(lo7 >> 32), (int)(u32)hi7, (int)(u32)(hi7 >> 32)};
-                const v4i xh = v4i{(int)(u32)loh, (int)(u32)(loh >> 32), (int)(u32)hih, (int)(u32)(hih >> 32)};
-                const v4i wa = wtab[((x & 1023) >> 6) * 64 + lane];
-                Sl = __builtin_amdgcn_mfma_i32_16x16x64_i8(wa, xl, Sl, 0, 0, 0);
-                Sh = __builtin_amdgcn_mfma_i32_16x16x64_i8(wa, xh, Sh, 0, 0, 0);
-                const u64 xn = x + 64;
-                const bool at_l1 = l2 && xn == l1;
-                if ((xn & 1023) == 0 || xn >= xmax || at_l1) {
-                    // rows 4g..4g+3 of this lane are digits 4g+t (digits 9..15 are zero rows)
-                    u64 V = 0;
+                const u32 sidx = (u32)((x & 1023) >> 6);
 #pragma unroll
-                    for (int t = 0; t < 4; t++) {
-                        const u32 d = 4 * g + t;
-                        if (d < 9) V = addmod61(V, rot61((u64)(u32)Sl[t] + 128ull * (u64)(u32)Sh[t], 7 * d));
+                for (int kb = 0; kb < 2; kb++) {
+                    u64 l0 = lo[u][kb], h0 = hi[u][kb];
+                    const u32 a0 = x + 32 * kb + 16 * h;
+                    if (a0 < LP) {  // bytes below lprev are in G already
+                        const u32 skip = LP - a0 < 16 ? LP - a0 : 16u;
+                        if (skip >= 8) {
+                            l0 = 0;
+                            h0 &= skip == 16 ? 0ull : ~((1ull << (8 * (skip - 8))) - 1ull);
+                        } else {
+                            l0 &= ~((1ull << (8 * skip)) - 1ull);
+                        }
                     }
-                    V = addmod61(V, __shfl_xor(V, 16));
-                    V = addmod61(V, __shfl_xor(V, 32));
-                    G = addmod61(G, mulmod61(V, ibc));
-                    Sl = v4i{0, 0, 0, 0};
-                    Sh = v4i{0, 0, 0, 0};
-                    if (at_l1) G1 = G;
+                    const u64 l7 = 0x7F7F7F7F7F7F7F7Full, h1 = 0x0101010101010101ull;
+                    const u64 lo7 = l0 & l7, hi7 = h0 & l7, loh = (l0 >> 7) & h1, hih = (h0 >> 7) & h1;
+                    const v4i xl = v4i{(int)(u32)lo7, (int)(u32)(lo7 >> 32), (int)(u32)hi7, (int)(u32)(hi7 >> 32)};
+                    const v4i xh = v4i{(int)(u32)loh, (int)(u32)(loh >> 32), (int)(u32)hih, (int)(u32)(hih >> 32)};
+                    // this lane's weight row for the block's 16 positions (lane half = 16-byte half);
+                    // rows of the l1 set are zero from l1 on (a two-round l1 is a multiple of 64,
+                    // so no block straddles it; single-round launches do not use that set)
+                    const v4i *wrow = wtab + ((sidx * 2 + kb) * 2 + h) * 9;
+                    const bool zero = rowl1 && x + 32 * kb >= L1;
+                    v4i wl = wrow[rowlo ? dr : 0], wh = wrow[rowhi ? dr - 1 : 0];
+                    if (!rowlo || zero) wl = v4i{0, 0, 0, 0};
+                    if (!rowhi || zero) wh = v4i{0, 0, 0, 0};
+                    S = __builtin_amdgcn_mfma_i32_32x32x32_i8(wl, xl, S, 0, 0, 0);
+                    S = __builtin_amdgcn_mfma_i32_32x32x32_i8(wh, xh, S, 0, 0, 0);
+                }
+                const u32 xn = x + 64;
+                if ((xn & 1023) == 0 || xn >= xmax) {
+                    // (half 1: the sum below l1; its rows are zero from l1 on)
+                    G = addmod61(G, mulmod61(digits_mod61(S), ibc));
+                    S = v16i{};
                     if ((xn & 1023) == 0) ibc = mulmod61(ibc, rw.ib256);
                 }
             }
-        }
-        if (valid && g == 0) {
-            state[i] = G;
-            u64 k1, k2 = 0;
-            if (l2) {
-                const u64 m1 = len < l1 ? len : l1;
-                const u64 H1 = mulmod61(m <= l1 ? G : G1, m1 == l1 ? rw.bl1 : kr_pow((m1 + 3) / 4, rw));
-                const u64 H2 = mulmod61(G, m == l2 ? rw.bl2 : kr_pow((m + 3) / 4, rw));
-                k1 = kr_finish(H1, m1, bits);
-                k2 = kr_finish(H2, m, bits);
-                keys1[j] = k1;
-                keys2[j] = k2;
-                fmn[1] = k2 < fmn[1] ? k2 : fmn[1];
-                fmx[1] = k2 > fmx[1] ? k2 : fmx[1];
-                if (len <= l2) fsh[1] = 1;
-            } else {
-                const u64 H = mulmod61(G, m == l1 ? rw.bl1 : kr_pow((m + 3) / 4, rw));
-                k1 = kr_finish(H, m, bits);
-                keys1[j] = k1;
+            if (!tile_end) {
+                xp += 64 * RP_STEPS;
+                continue;
             }
-            fmn[0] = k1 < fmn[0] ? k1 : fmn[0];
-            fmx[0] = k1 > fmx[0] ? k1 : fmx[0];
-            if (len <= l1) fsh[0] = 1;
+            // the tile's keys
+            if (valid && (!h || two)) {
+                const u32 j = tile * 32 + col;
+                const u32 mm = len < lmine ? len : lmine;
+                const u64 H = mulmod61(G, mm == lmine ? (lmine == L1 ? rw.bl1 : rw.bl2) : kr_pow((mm + 3) / 4, rw));
+                const u64 key = kr_finish(H, mm, bits);
+                if (h) keys1[j] = key;
+                else {
+                    state[i_c] = G;
+                    (two ? keys2 : keys1)[j] = key;
+                }
+                fmn = key < fmn ? key : fmn;
+                fmx = key > fmx ? key : fmx;
+                if (len <= lmine) fsh = 1;
+            }
+            if (!more) break;
+            // advance: the next tile becomes current (its first pass is in flight)
+            tile += nwaves;
+            i_c = i_n;
+            o_c = o_n;
+            valid = valid_n;
+            len = len_n;
+            m = m_n;
+            xmax = xmax_n;
+            G = valid ? G_n : 0;
+            ibc = rw.ibc0;
+            xp = x0;
+            more = tile + nwaves < ntiles;
+            i_n = i_nn;
+            if (more) {
+                o_n = off[i_n];
+                len_n = (u32)(off[i_n + 1] - o_n);
+                if (lprev) G_n = state[i_n];
+            }
+            i_nn = entry(tile + 2 * nwaves < ntiles ? tile + 2 * nwaves : tile);
         }
     }
 #pragma unroll
-    for (int k = 0; k < 2; k++) {
-        flags_reduce16(fmn[k], fmx[k], fsh[k]);  // lane group 0 holds the values
-        if (lane == 0 && (k == 0 || l2)) flags_commit(rf + 3 * k, fmn[k], fmx[k], fsh[k]);
+    for (int d = 1; d < 32; d <<= 1) {  // within each lane half
+        const u64 a = __shfl_xor(fmn, d), b = __shfl_xor(fmx, d), c = __shfl_xor(fsh, d);
+        fmn = a < fmn ? a : fmn;
+        fmx = b > fmx ? b : fmx;
+        fsh |= c;
     }
+    // flags: rf[0..2] round l1, rf[3..5] round l2
+    if (lane == 0) flags_commit(rf + (two ? 3 : 0), fmn, fmx, fsh);
+    if (lane == 32 && two) flags_commit(rf, fmn, fmx, fsh);
 }
 
 // ------------------------------------------------------------ duplicates
@@ -834,7 +969,7 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
             {
                 // bytes are charged once the active count is read back
                 SS_PROF("k_hash_round", st, 0.0);
-                const u64 tiles = ceil_div(Ah, 16);
+                const u64 tiles = ceil_div(Ah, 32);
                 const u64 nb = ceil_div(tiles, 4);
                 k_flag_init<<<1, 64, 0, st>>>(fl_round, 6);
                 k_hash_round<<<(unsigned)(nb < 1024 ? (nb ? nb : 1) : 1024), 256, 0, st>>>(

@@ -243,7 +243,7 @@ __device__ __forceinline__ u32 skip_cmp(const u8 *bytes, u64 N, const u8 *R, con
 // position, its remaining length there (capped at 8) and its 8 bytes there
 // (mword, mpr), from which k_keys builds its key without reading the string
 // again.
-__global__ __launch_bounds__(NT) void k_skip(const Seg *segs, const u32 *tstart, u32 nseg,
+__global__ __launch_bounds__(NT, 6) void k_skip(const Seg *segs, const u32 *tstart, u32 nseg,
                                              const u8 *bytes, u64 N, const u64 *off,
                                              const u32 *perm, u32 *skipv, u64 *mword, uint2 *mpr)
 {
