@@ -220,7 +220,7 @@ extern "C" int ss_bucket_bounds(const uint8_t *bytes, uint64_t N, const uint64_t
 // equals i, and otherwise the largest bound below i is its bucket's start.
 __global__ __launch_bounds__(256) void k_fc_meta(const u64 *off, u32 n, const u32 *perm, const u32 *lcp,
                                                  const u32 *dist, const u64 *run_off, u32 nb, u32 *fc_lcp,
-                                                 u32 *fc_len, u32 *fc_id, u64 *sizes, u32 *bad)
+                                                 u32 *fc_len, u32 *fc_id, u64 *sizes, u64 *lit_src, u32 *bad)
 {
     // bucket start: the largest run_off[j] <= i.  The workgroup's positions
     // are contiguous: one search for its first position, then each thread
@@ -243,11 +243,12 @@ __global__ __launch_bounds__(256) void k_fc_meta(const u64 *off, u32 n, const u3
     while (lo + 2 < nb && run_off[lo + 1] <= i) lo++;
     const u32 e = (run_off[lo] == i) ? 0u : lcp[i];
     const u32 p = perm[i];
-    const u64 len = off[p + 1] - off[p];
+    const u64 o = off[p], len = off[p + 1] - o;
     const u32 d = dist ? dist[p] : (u32)len;
     fc_lcp[i] = e;
     fc_len[i] = d;
     fc_id[i] = p;
+    lit_src[i] = o + e;  // where the literal starts, in sorted order for the copy
     if (e > d || d > len) {
         atomicOr(bad, 1u);
         sizes[i] = 0;
@@ -266,13 +267,14 @@ __global__ void k_add_base(u64 *a, u64 n, u64 base)
 #define CS_BUF 16384  // LDS staging bytes
 
 // Literal bytes of strings [i0, i0+256) (string i's bytes [e_i, d_i) go to
-// suf[suf_off[i] ..]).  Each thread reads its string's literal with aligned
+// suf[suf_off[i] ..]; lit_src[i] = offset of byte e_i, written in sorted order
+// by k_fc_meta).  Each thread reads its string's literal with aligned
 // 8-byte words; when the workgroup's output span fits the LDS buffer the
 // literals are packed there and written out in aligned 16-byte words (bytes
 // at the two ends, which neighbouring workgroups share, one by one),
 // otherwise each thread writes its literal directly.
-__global__ __launch_bounds__(CS_NT) void k_fc_copy(const u8 *bytes, u64 N, const u64 *off, u32 n, const u32 *perm,
-                                                   const u32 *fc_lcp, const u64 *suf_off, u8 *suf)
+__global__ __launch_bounds__(CS_NT) void k_fc_copy(const u8 *bytes, u64 N, u32 n, const u64 *lit_src,
+                                                   const u64 *suf_off, u8 *suf)
 {
     __shared__ uint4 buf4[CS_BUF / 16];
     u8 *buf = (u8 *)buf4;
@@ -285,7 +287,7 @@ __global__ __launch_bounds__(CS_NT) void k_fc_copy(const u8 *bytes, u64 N, const
     const u32 i = i0 + threadIdx.x;
     if (i < i1) {
         const u64 so = suf_off[i], len = suf_off[i + 1] - so;
-        const u64 src = off[perm[i]] + fc_lcp[i];
+        const u64 src = lit_src[i];
         for (u64 k = 0; k < len; k += 8) {
             const u32 take = (len - k) < 8 ? (u32)(len - k) : 8u;
             const u64 w = load_le(bytes, N, src + k, take);
@@ -320,6 +322,7 @@ extern "C" size_t ss_partition_encode_workspace(uint64_t n)
     WsCounter c;
     c.take<u64>(ss_scan_scratch_elems<u64>(n + 1));
     c.take<u32>(4);
+    c.take<u64>(n);  // literal source offsets
     return c.used;
 }
 
@@ -342,6 +345,7 @@ static int encode_impl(const uint8_t *bytes, uint64_t N, const uint64_t *offsets
     WsArena a(ws, ws_bytes);
     u64 *scratch = a.take<u64>(ss_scan_scratch_elems<u64>(n + 1));
     u32 *bad = a.take<u32>(4);
+    u64 *lit_src = a.take<u64>(n);
     if (a.overflow || !ws) {
         ss_set_error("workspace too small: need %zu bytes", ss_partition_encode_workspace(n));
         return SS_ERR_WORKSPACE;
@@ -353,10 +357,10 @@ static int encode_impl(const uint8_t *bytes, uint64_t N, const uint64_t *offsets
     SS_HIP(hipMemsetAsync(bad, 0, sizeof(u32), st));
     if (n > 0) {
         {
-            // perm, lcp, offsets, dist in; e, d, id and the literal length out
-            SS_PROF("k_fc_meta", st, (double)n * (dist ? 48.0 : 44.0));
+            // perm, lcp, offsets, dist in; e, d, id, the literal length and source out
+            SS_PROF("k_fc_meta", st, (double)n * (dist ? 56.0 : 52.0));
             k_fc_meta<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(offsets, (u32)n, perm, lcp, dist, run_off, (u32)nb,
-                                                                   fc_lcp, fc_len, fc_id, suf_off, bad);
+                                                                   fc_lcp, fc_len, fc_id, suf_off, lit_src, bad);
         }
         SS_CHECK_LAUNCH();
     }
@@ -387,9 +391,8 @@ static int encode_impl(const uint8_t *bytes, uint64_t N, const uint64_t *offsets
     if (total > 0) {
         {
             // literal bytes read and written; per string its perm, offsets, e and suf_off
-            SS_PROF("k_fc_copy", st, 2.0 * (double)total + (double)n * 24.0);
-            k_fc_copy<<<(unsigned)ceil_div(n, CS_NT), CS_NT, 0, st>>>(bytes, N, offsets, (u32)n, perm, fc_lcp,
-                                                                       suf_off, suf);
+            SS_PROF("k_fc_copy", st, 2.0 * (double)total + (double)n * 16.0);
+            k_fc_copy<<<(unsigned)ceil_div(n, CS_NT), CS_NT, 0, st>>>(bytes, N, (u32)n, lit_src, suf_off, suf);
         }
         SS_CHECK_LAUNCH();
     }

@@ -153,7 +153,7 @@ __global__ void k_sizes(const Seg *segs, u32 nseg, u32 *out)
 // ------------------------------------------------------------ round kernels
 
 #define SKB 16      // strings per wavefront batch in the skip kernel
-#define SKC_LONG 18  // 16-byte chunks per string of a long window (covers >= 273 bytes)
+#define SKC_LONG 17  // 16-byte chunks per string of a long window (covers >= 257 bytes)
 #define SKC_SHORT 5  // ... of a short window (covers >= 65 bytes)
 #define SKR 5120     // LDS bytes per wavefront: five 1 KiB transfer rows
 #define SKFS 256     // words (8 bytes) of the segment's first string staged in LDS
@@ -234,7 +234,7 @@ __device__ __forceinline__ u32 skip_cmp(const u8 *bytes, u64 N, const u8 *R, con
 
 // Minimum LCP of every member with the segment's first string, from `depth`.
 // Each wavefront takes its members 16 at a time, four lanes per member: the
-// window of every member (a short one of >= 65 bytes, or a long one of >= 273
+// window of every member (a short one of >= 65 bytes, or a long one of >= 257
 // bytes once most members of the previous batch reached past 48 bytes) is
 // copied from global memory into LDS by the transfer unit, then the four lanes
 // compare it, 8 bytes at a time, against the first string's bytes
