@@ -59,6 +59,14 @@ __device__ __forceinline__ u64 kr_finish(u64 C, u64 m, u32 bits)
     return bits >= 64 ? key : (key & ((1ull << bits) - 1));
 }
 
+// The same key from the sum G with H = B^L G: (H B + m) = G B^(L+1) + m, so one
+// product with bl1 = B^(L+1).
+__device__ __forceinline__ u64 kr_key(u64 G, u64 bl1, u64 m, u32 bits)
+{
+    u64 key = addmod61(mulmod61(G, bl1), m);
+    return bits >= 64 ? key : (key & ((1ull << bits) - 1));
+}
+
 __global__ __launch_bounds__(256) void k_prefix_keys(const u8 *bytes, u64 N, const u64 *off, u32 n,
                                                      u64 m, u32 bits, u64 *keys)
 {
@@ -302,8 +310,7 @@ __global__ __launch_bounds__(256) void k_hash_first(u32 n, const u8 *bytes, u64 
                     const u64 Gr = k == 0 ? G : addmod61(G4, fw.corr[4]);
                     const u64 lim = k == 0 ? lg : lr[4];
                     const u64 m = len[f] < lim ? len[f] : lim;
-                    const u64 H = mulmod61(Gr, bp.p[(m + 3) / 4]);
-                    const u64 key = kr_finish(H, m, bits);
+                    const u64 key = kr_key(Gr, bp.p[(m + 3) / 4 + 1], m, bits);
                     pre[(u64)r * n + i] = key;
                     if (r == P.count - 1) state[i] = Gr;  // later rounds continue from G
                     fmn[k] = key < fmn[k] ? key : fmn[k];
@@ -345,7 +352,7 @@ struct RoundW {
     u64 ibhi[16];  // B^-16k, k < 16
     u64 ibc0;      // B^-256c for the chunk of the first step
     u64 ib256;     // B^-256
-    u64 bl1, bl2;  // B^(l1/4), B^(l2/4)
+    u64 bl1, bl2;  // B^(l1/4 + 1), B^(l2/4 + 1)
     u64 b2[32];    // B^(2^k)
 };
 
@@ -606,8 +613,8 @@ __global__ __launch_bounds__(256, 4) void k_hash_round(const u32 *act, const u32
             if (valid && (!h || two)) {
                 const u32 j = tile * 32 + col;
                 const u32 mm = len < lmine ? len : lmine;
-                const u64 H = mulmod61(G, mm == lmine ? (lmine == L1 ? rw.bl1 : rw.bl2) : kr_pow((mm + 3) / 4, rw));
-                const u64 key = kr_finish(H, mm, bits);
+                const u64 key = kr_key(G, mm == lmine ? (lmine == L1 ? rw.bl1 : rw.bl2) : kr_pow((mm + 3) / 4 + 1, rw),
+                                       mm, bits);
                 if (h) keys1[j] = key;
                 else {
                     state[i_c] = G;
@@ -867,8 +874,8 @@ static RoundW round_weights(u64 lprev, u64 l1, u64 l2)
     for (int k = 0; k < 16; k++, y = host_mulmod(y, b16)) r.ibhi[k] = y;
     r.ib256 = host_powmod(binv, 256);
     r.ibc0 = host_powmod(r.ib256, (lprev & ~63ull) / 1024);
-    r.bl1 = host_powmod(KR_B, l1 / 4);
-    r.bl2 = l2 ? host_powmod(KR_B, l2 / 4) : 0;
+    r.bl1 = host_powmod(KR_B, l1 / 4 + 1);
+    r.bl2 = l2 ? host_powmod(KR_B, l2 / 4 + 1) : 0;
     u64 z = KR_B;
     for (int k = 0; k < 32; k++, z = host_mulmod(z, z)) r.b2[k] = z;
     return r;
