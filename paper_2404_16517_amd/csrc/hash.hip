@@ -93,21 +93,15 @@ struct PreLens {
 // w_i = 256^(i mod 4) B^-(i/4 + 1) (mod p), the m-byte prefix of a string has
 // G = sum_{i<m} byte_i w_i and Horner value H = B^L G (L = ceil(m/4) limbs,
 // the last zero-padded), the same value as limb-by-limb Horner.  Each weight
-// is split into nine 7-bit digits, w_i = sum_d c_id 2^(7d), so that
-// S_rd = sum_{i<l_r} (byte_i - 128) c_id is an int8 dot product (bytes past
-// the string count as 0; the -128 offset makes them signed and is undone by
-// the constant 128 sum_{i<l_r} w_i).  One v_mfma_i32_16x16x64_i8 takes 64
-// prefix bytes of 16 strings (B operand: column = string) against 16
-// (round, digit) rows of weights (A operand); three of them cover five rounds
-// x nine digits.  Multiplying by 2^(7d) mod 2^61-1 is a 61-bit rotation.
+// is split into nine 7-bit digits, w_i = sum_d c_id 2^(7d), so that each
+// digit sum is an int8 dot product of the prefix bytes with one digit column;
+// the first pass evaluates them for every precomputed round at once on the
+// 32x32x32 int8 MFMA (see the round kernel for the layout).
 struct FirstW {
-    u64 ib[16];           // B^-(j+1) mod p for limbs j < 16 (the first 64 bytes)
-    u64 corr[PRE_SLOTS];  // 128 sum_{i<l_r} w_i mod p
+    u64 ib[16];  // B^-(j+1) mod p for limbs j < 16 (the first 64 bytes)
 };
 
 typedef int v4i __attribute__((ext_vector_type(4)));
-
-#define HF_T 2  // first pass: tiles of 16 strings whose loads are issued together
 
 __device__ __forceinline__ u64 rot61(u64 x, u32 k)  // x 2^k mod 2^61-1, x < p, k < 61
 {
@@ -180,23 +174,14 @@ __device__ __forceinline__ void load16_le(const u8 *__restrict__ bytes, u64 N, u
     win16_finish(bytes, win16_issue(bytes, N, a, take), lo, hi);
 }
 
-// Row assignment of the weight operand: lane group g of the result (rows
-// 4g..4g+3 of each of the three tiles, twelve slots) holds round g's nine
-// digits in slots 0..8 and digits 3g..3g+2 of round 4 in slots 9..11.
-__device__ __forceinline__ bool first_slot(u32 g, u32 slot, u32 *r, u32 *d)
-{
-    if (slot < 9) { *r = g; *d = slot; return true; }
-    if (g < 3) { *r = 4; *d = 3 * g + (slot - 9); return true; }
-    return false;
-}
-
 // Round flags, three words per round: [0] minimum key, [1] maximum key,
 // [2] nonzero if some string is no longer than the round's prefix length.
 // Initialised by k_flag_init; all keys are equal iff min == max.
-__device__ __forceinline__ void flags_reduce16(u64 &mn, u64 &mx, u64 &sh)
+// Minimum, maximum and or of the flags over each lane half (32 lanes).
+__device__ __forceinline__ void flags_reduce32(u64 &mn, u64 &mx, u64 &sh)
 {
 #pragma unroll
-    for (int d = 1; d < 16; d <<= 1) {
+    for (int d = 1; d < 32; d <<= 1) {
         const u64 a = __shfl_xor(mn, d), b = __shfl_xor(mx, d), c = __shfl_xor(sh, d);
         mn = a < mn ? a : mn;
         mx = b > mx ? b : mx;
@@ -215,117 +200,6 @@ __global__ void k_flag_init(u64 *f, u32 words)
 {
     const u32 t = threadIdx.x;
     if (t < words) f[t] = (t % 3 == 0) ? ~0ull : 0ull;
-}
-
-__global__ __launch_bounds__(256) void k_hash_first(u32 n, const u8 *bytes, u64 N, const u64 *off, PreLens P,
-                                                    u32 bits, BPow bp, FirstW fw, u64 *state, u64 *pre, u64 *fl)
-{
-    // this lane's round flags: round g, and round 4 in lane group 3
-    u64 fmn[2] = {~0ull, ~0ull}, fmx[2] = {0, 0}, fsh[2] = {0, 0};
-    const u32 lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
-    const u64 W = P.l[P.count - 1];
-    // weight operand (A): row col of each tile, k-group g = prefix bytes [16g, 16g+16).
-    // Kernel-argument arrays are read with constant indices only (selects by
-    // lane instead of indexed loads).
-    u64 lr[PRE_SLOTS];
-#pragma unroll
-    for (int r = 0; r < PRE_SLOTS; r++) lr[r] = (u32)r < P.count ? P.l[r] : 0;
-    u64 ww[16];  // w_pos for pos = 16g + b
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const u64 ib = g == 0 ? fw.ib[q] : g == 1 ? fw.ib[4 + q] : g == 2 ? fw.ib[8 + q] : fw.ib[12 + q];
-#pragma unroll
-        for (int b = 0; b < 4; b++) ww[4 * q + b] = rot61(ib, 8 * b);
-    }
-    v4i wa[3];
-#pragma unroll
-    for (int T = 0; T < 3; T++) {
-        u32 r = 0, d = 0;
-        const bool valid = first_slot(col >> 2, 4 * T + (col & 3), &r, &d) && r < P.count;
-        u64 lim = 0;
-#pragma unroll
-        for (int k = 0; k < PRE_SLOTS; k++)
-            if ((u32)k == r) lim = lr[k];
-        u32 wd[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int b = 0; b < 16; b++) {
-            const u32 pos = 16 * g + b;
-            const u32 c = (valid && pos < lim) ? (u32)((ww[b] >> (7 * d)) & 127u) : 0u;
-            wd[b >> 2] |= c << (8 * (b & 3));
-        }
-        wa[T] = v4i{(int)wd[0], (int)wd[1], (int)wd[2], (int)wd[3]};
-    }
-    const u64 corr_g = g == 0 ? fw.corr[0] : g == 1 ? fw.corr[1] : g == 2 ? fw.corr[2] : fw.corr[3];
-    const u64 lg = g == 0 ? lr[0] : g == 1 ? lr[1] : g == 2 ? lr[2] : lr[3];
-    const u32 ntiles = (n + 15) / 16;
-    const u32 wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
-    for (u32 t0 = wave * HF_T; t0 < ntiles; t0 += nwaves * HF_T) {  // uniform over the wavefront
-        // HF_T tiles at a time: all their loads first
-        u64 len[HF_T], o[HF_T];
-        Win16 wn[HF_T];
-#pragma unroll
-        for (int f = 0; f < HF_T; f++) {  // offsets of all tiles, then their windows
-            const u32 i = (t0 + f) * 16 + col;
-            const u32 ic = i < n ? i : n - 1;  // loads without a branch; len 0 past the end
-            o[f] = off[ic];
-            const u64 e = off[ic + 1];
-            len[f] = i < n ? e - o[f] : 0;
-        }
-#pragma unroll
-        for (int f = 0; f < HF_T; f++) {
-            const u64 mw = len[f] < W ? len[f] : W;
-            const u64 q = 16ull * g;
-            const u32 take = q < mw ? (u32)((mw - q) < 16 ? (mw - q) : 16) : 0u;
-            wn[f] = win16_issue(bytes, N, o[f] + q, take);
-        }
-#pragma unroll
-        for (int f = 0; f < HF_T; f++) {
-            if (t0 + f >= ntiles) break;  // uniform over the wavefront
-            const u32 i = (t0 + f) * 16 + col;
-            u64 lo, hi;
-            win16_finish(bytes, wn[f], lo, hi);
-            lo ^= 0x8080808080808080ull;  // byte - 128 as int8
-            hi ^= 0x8080808080808080ull;
-            const v4i xb = v4i{(int)(u32)lo, (int)(u32)(lo >> 32), (int)(u32)hi, (int)(u32)(hi >> 32)};
-            v4i acc[3];
-#pragma unroll
-            for (int T = 0; T < 3; T++)
-                acc[T] = __builtin_amdgcn_mfma_i32_16x16x64_i8(wa[T], xb, v4i{0, 0, 0, 0}, 0, 0, 0);
-            // this lane: string i, result rows 4g..4g+3 of every tile = slots 0..11 of group g
-            u64 G = corr_g, G4 = 0;
-#pragma unroll
-            for (int slot = 0; slot < 12; slot++) {
-                const int sv = acc[slot >> 2][slot & 3];
-                if (slot < 9) G = addmod61(G, rot61(modp_i32(sv), 7 * slot));
-                else if (g < 3) G4 = addmod61(G4, rot61(modp_i32(sv), 7 * (3 * g + (slot - 9))));
-            }
-            G4 = addmod61(G4, __shfl_xor(G4, 16));
-            G4 = addmod61(G4, __shfl_xor(G4, 32));
-            if (i < n) {
-                // lane group g finishes round g; group 3 also round 4
-#pragma unroll
-                for (int k = 0; k < 2; k++) {
-                    const u32 r = k == 0 ? g : 4u;
-                    if ((k == 1 && g != 3) || r >= P.count) continue;
-                    const u64 Gr = k == 0 ? G : addmod61(G4, fw.corr[4]);
-                    const u64 lim = k == 0 ? lg : lr[4];
-                    const u64 m = len[f] < lim ? len[f] : lim;
-                    const u64 key = kr_key(Gr, bp.p[(m + 3) / 4 + 1], m, bits);
-                    pre[(u64)r * n + i] = key;
-                    if (r == P.count - 1) state[i] = Gr;  // later rounds continue from G
-                    fmn[k] = key < fmn[k] ? key : fmn[k];
-                    fmx[k] = key > fmx[k] ? key : fmx[k];
-                    if (len[f] <= lim) fsh[k] = 1;
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < 2; k++) flags_reduce16(fmn[k], fmx[k], fsh[k]);
-    if (col == 0) {
-        if (g < P.count) flags_commit(fl + 3 * g, fmn[0], fmx[0], fsh[0]);
-        if (g == 3 && P.count > 4) flags_commit(fl + 12, fmn[1], fmx[1], fsh[1]);
-    }
 }
 
 // Later rounds continue the same sum, G_l = G_lprev + sum_{lprev<=i<l} byte_i
@@ -646,16 +520,206 @@ __global__ __launch_bounds__(256, 4) void k_hash_round(const u32 *act, const u32
             i_nn = entry(tile + 2 * nwaves < ntiles ? tile + 2 * nwaves : tile);
         }
     }
-#pragma unroll
-    for (int d = 1; d < 32; d <<= 1) {  // within each lane half
-        const u64 a = __shfl_xor(fmn, d), b = __shfl_xor(fmx, d), c = __shfl_xor(fsh, d);
-        fmn = a < fmn ? a : fmn;
-        fmx = b > fmx ? b : fmx;
-        fsh |= c;
-    }
+    flags_reduce32(fmn, fmx, fsh);
     // flags: rf[0..2] round l1, rf[3..5] round l2
     if (lane == 0) flags_commit(rf + (two ? 3 : 0), fmn, fmx, fsh);
     if (lane == 32 && two) flags_commit(rf, fmn, fmx, fsh);
+}
+
+#define HF_CH 5      // 16-byte chunks per string in the first pass (64 bytes at any alignment)
+#define HF_ROW 3072  // LDS bytes per wavefront: three 1 KiB copy rows (32 x 5 chunks)
+#define HF_ACC 3     // accumulators: two rounds each (rounds 2a and 2a + 1 in the two row sets)
+
+// The first pass over tiles of 32 strings: their first min(len, W) bytes
+// (W = the longest precomputed round, <= 64) are copied into LDS by the
+// transfer unit, read into registers, and the next tile's copy is issued
+// before the current tile's products.  Accumulator a holds rounds 2a (row set
+// 0, lane half 0) and 2a + 1 (row set 1, half 1), with the weights of
+// positions past the round's length zero; each lane combines its own digit
+// sums into G of its rounds and writes their keys; the last round's G is the
+// state later rounds continue from.
+__global__ __launch_bounds__(256, 4) void k_hash_first(u32 n, const u8 *bytes, u64 N, const u64 *off, PreLens P,
+                                                       u32 bits, BPow bp, FirstW fw, u64 *state, u64 *pre, u64 *fl)
+{
+    __shared__ v4i wtab[HF_ACC][2][2][64];  // [accumulator][32-byte block][low/high product][lane]
+    __shared__ __attribute__((aligned(16))) u8 rows[4 * HF_ROW];
+    __shared__ u64 pwa[4][32];  // per wavefront: copy start (16-aligned, relative) of each string
+    __shared__ u32 pwn[4][32];  // ... and its chunk count (0: not copied)
+    __shared__ u64 s_ib[16], s_l[PRE_SLOTS];
+    // kernel-argument arrays are read with constant indices only
+    if (threadIdx.x < 16) {
+        u64 v = 0;
+#pragma unroll
+        for (int k = 0; k < 16; k++)
+            if (threadIdx.x == (u32)k) v = fw.ib[k];
+        s_ib[threadIdx.x] = v;
+    }
+    if (threadIdx.x < PRE_SLOTS) {
+        u64 v = 0;
+#pragma unroll
+        for (int k = 0; k < PRE_SLOTS; k++)
+            if (threadIdx.x == (u32)k) v = (u32)k < P.count ? P.l[k] : 0;
+        s_l[threadIdx.x] = v;
+    }
+    __syncthreads();
+    for (u32 e = threadIdx.x; e < HF_ACC * 2 * 2 * 64; e += blockDim.x) {
+        const u32 ln = e & 63, hl = (e >> 6) & 1, kb = (e >> 7) & 1, a = e >> 8;
+        const u32 rc = ln & 31, kh = ln >> 5;
+        const u32 dr = 4 * (rc >> 3) + (rc & 3);  // the row's register (digit) in its set
+        const u32 r = 2 * a + ((rc >> 2) & 1);     // the row's round
+        const bool ok = r < P.count && (hl ? (dr >= 1 && dr < 10) : dr < 9);
+        const u32 d = hl ? dr - 1 : dr;
+        const u64 lim = ok ? s_l[r < PRE_SLOTS ? r : 0] : 0;
+        u32 wd[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const u32 j = 8 * kb + 4 * kh + q;  // limb: positions 4j .. 4j+3
+            const u64 ib = s_ib[j];
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                const u32 c = (4 * j + b < lim) ? (u32)((rot61(ib, 8 * b) >> (7 * d)) & 127u) : 0u;
+                wd[q] |= c << (8 * b);
+            }
+        }
+        wtab[a][kb][hl][ln] = v4i{(int)wd[0], (int)wd[1], (int)wd[2], (int)wd[3]};
+    }
+    __syncthreads();
+    const u32 lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5, wv = threadIdx.x >> 6;
+    u8 *R = rows + wv * HF_ROW;
+    const u64 babs = (u64)(uintptr_t)bytes;
+    const u32 W = (u32)s_l[P.count - 1];
+    const u32 nacc = (P.count + 1) / 2;
+    u64 fmn[HF_ACC], fmx[HF_ACC], fsh[HF_ACC];
+#pragma unroll
+    for (int a = 0; a < HF_ACC; a++) {
+        fmn[a] = ~0ull;
+        fmx[a] = 0;
+        fsh[a] = 0;
+    }
+    const u32 ntiles = (n + 31) / 32;
+    const u32 wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
+    // copy [0, min(len, W)) of this lane's string into the rows
+    auto issue_copy = [&](u64 o, u32 m) {
+        const u64 A0 = (babs + o) & ~15ull;
+        const u32 sh = (u32)((babs + o) & 15);
+        const u32 nch = m ? (sh + m + 15) / 16 : 0u;
+        const bool edge = nch && (A0 < babs || A0 + 16ull * nch > babs + N);
+        if (h == 0) {  // (read back below by the same wavefront: LDS keeps its order)
+            pwa[wv][col] = A0 - babs;
+            pwn[wv][col] = edge ? 0u : nch;
+        }
+        constexpr int T = (32 * HF_CH + 63) / 64;
+        u64 ad[T];
+        bool ok[T];
+#pragma unroll
+        for (int t = 0; t < T; t++) {  // every address first: the copies then issue back to back
+            u32 slot = 64 * t + lane;
+            asm volatile("" : "+v"(slot));  // recomputed per tile rather than held in registers
+            const u32 sx = slot / HF_CH, c = slot % HF_CH;
+            ad[t] = pwa[wv][sx & 31] + 16u * c;
+            ok[t] = sx < 32 && c < pwn[wv][sx & 31];
+        }
+#pragma unroll
+        for (int t = 0; t < T; t++)
+            if (ok[t]) __builtin_amdgcn_global_load_lds((const void *)(bytes + ad[t]), (lds_void_h *)(R + 1024 * t), 16, 0, 0);
+    };
+    auto str_of = [&](u32 tile, u64 &o, u32 &len) {  // offsets of this lane's string of `tile`
+        const u32 i = tile * 32 + col;
+        const u32 ic = i < n ? i : n - 1;  // loads without a branch; len 0 past the end
+        o = off[ic];
+        const u64 e = off[ic + 1];
+        len = i < n ? (u32)(e - o) : 0u;
+    };
+    if (wave < ntiles) {
+        u32 tile = wave;
+        u64 o_c, o_n = 0;
+        u32 len_c, len_n = 0;
+        str_of(tile, o_c, len_c);
+        bool more = tile + nwaves < ntiles;
+        if (more) str_of(tile + nwaves, o_n, len_n);
+        issue_copy(o_c, len_c < W ? len_c : W);
+        for (;;) {  // tiles; uniform over the wavefront
+            const u32 m = len_c < W ? len_c : W;
+            u64 lo[2], hi[2];
+            {
+                const u32 sh = (u32)((babs + o_c) & 15);
+                const u32 nch = m ? (sh + m + 15) / 16 : 0u;
+                const u64 A0 = (babs + o_c) & ~15ull;
+                const bool edge = nch && (A0 < babs || A0 + 16ull * nch > babs + N);
+#pragma unroll
+                for (int kb = 0; kb < 2; kb++) {
+                    const u32 rel = 32 * kb + 16 * h;
+                    const u32 take = m > rel ? ((m - rel) < 16 ? m - rel : 16u) : 0u;
+                    lo[kb] = hi[kb] = 0;
+                    if (take) {
+                        if (!edge) lds_le16(R, HF_CH * 16 * col + sh + rel, lo[kb], hi[kb]);
+                        else load16_le(bytes, N, o_c + rel, take, lo[kb], hi[kb]);
+                        if (take < 8) {
+                            lo[kb] &= (1ull << (8 * take)) - 1ull;
+                            hi[kb] = 0;
+                        } else if (take < 16) {
+                            hi[kb] &= take == 8 ? 0ull : ((1ull << (8 * (take - 8))) - 1ull);
+                        }
+                    }
+                }
+            }
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the rows are read before the next copy
+            const u32 next = tile + nwaves;
+            u64 o_nn = 0;
+            u32 len_nn = 0;
+            if (more) {
+                issue_copy(o_n, len_n < W ? len_n : W);
+                if (next + nwaves < ntiles) str_of(next + nwaves, o_nn, len_nn);
+            }
+            // the tile's products: two per accumulator and block
+            v16i S[HF_ACC];
+#pragma unroll
+            for (int a = 0; a < HF_ACC; a++) S[a] = v16i{};
+#pragma unroll
+            for (int kb = 0; kb < 2; kb++) {
+                const u64 l7 = 0x7F7F7F7F7F7F7F7Full, h1 = 0x0101010101010101ull;
+                const u64 lo7 = lo[kb] & l7, hi7 = hi[kb] & l7, loh = (lo[kb] >> 7) & h1, hih = (hi[kb] >> 7) & h1;
+                const v4i xl = v4i{(int)(u32)lo7, (int)(u32)(lo7 >> 32), (int)(u32)hi7, (int)(u32)(hi7 >> 32)};
+                const v4i xh = v4i{(int)(u32)loh, (int)(u32)(loh >> 32), (int)(u32)hih, (int)(u32)(hih >> 32)};
+#pragma unroll
+                for (int a = 0; a < HF_ACC; a++) {
+                    if ((u32)a >= nacc) break;  // uniform
+                    S[a] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wtab[a][kb][0][lane], xl, S[a], 0, 0, 0);
+                    S[a] = __builtin_amdgcn_mfma_i32_32x32x32_i8(wtab[a][kb][1][lane], xh, S[a], 0, 0, 0);
+                }
+            }
+            const u32 i = tile * 32 + col;
+#pragma unroll
+            for (int a = 0; a < HF_ACC; a++) {
+                const u32 r = 2 * a + h;
+                if ((u32)a >= nacc) break;  // uniform
+                if (i < n && r < P.count) {
+                    const u64 G = digits_mod61(S[a]);
+                    const u32 lr = (u32)s_l[r];
+                    const u32 mr = len_c < lr ? len_c : lr;
+                    const u64 key = kr_key(G, bp.p[(mr + 3) / 4 + 1], mr, bits);
+                    pre[(u64)r * n + i] = key;
+                    if (r == P.count - 1) state[i] = G;  // later rounds continue from G
+                    fmn[a] = key < fmn[a] ? key : fmn[a];
+                    fmx[a] = key > fmx[a] ? key : fmx[a];
+                    if (len_c <= lr) fsh[a] = 1;
+                }
+            }
+            if (!more) break;
+            tile = next;
+            o_c = o_n;
+            len_c = len_n;
+            o_n = o_nn;
+            len_n = len_nn;
+            more = tile + nwaves < ntiles;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < HF_ACC; a++) {
+        flags_reduce32(fmn[a], fmx[a], fsh[a]);
+        const u32 r = 2 * a + h;
+        if (col == 0 && r < P.count) flags_commit(fl + 3 * r, fmn[a], fmx[a], fsh[a]);
+    }
 }
 
 // ------------------------------------------------------------ duplicates
@@ -845,19 +909,12 @@ static u64 host_powmod(u64 a, u64 e)
 
 // Weights of the first pass: inverse powers of the base (B^(p-2) = B^-1 by
 // Fermat, p prime) and the offset corrections of each round.
-static FirstW first_weights(const PreLens &P)
+static FirstW first_weights()
 {
     FirstW f{};
     const u64 binv = host_powmod(KR_B, KR_P - 2);
     u64 x = binv;
     for (int j = 0; j < 16; j++, x = host_mulmod(x, binv)) f.ib[j] = x;
-    u64 sum = 0;
-    u32 r = 0;
-    for (u32 i = 0; i < PRE_MAX && r < P.count; i++) {
-        const u64 wi = host_mulmod(f.ib[i / 4], 1ull << (8 * (i % 4)));
-        sum = (sum + wi) % KR_P;
-        while (r < P.count && i + 1 == P.l[r]) f.corr[r++] = host_mulmod(sum, 128);
-    }
     return f;
 }
 
@@ -921,11 +978,11 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
             // the first line of every string, once
             SS_PROF("k_hash_first", st,
                     (double)n * (double)P.l[P.count - 1] + (double)n * (24.0 + 8.0 * P.count));
-            const u64 tiles = ceil_div(n, 16 * HF_T);
+            const u64 tiles = ceil_div(n, 32);
             const unsigned blocks = (unsigned)(ceil_div(tiles, 4) < 2048 ? ceil_div(tiles, 4) : 2048);
             k_flag_init<<<1, 64, 0, st>>>(fl_first, 3 * P.count);
             SS_CHECK_LAUNCH();
-            k_hash_first<<<blocks, 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits, bp, first_weights(P),
+            k_hash_first<<<blocks, 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits, bp, first_weights(),
                                                  w.state, w.pre, fl_first);
         }
         SS_CHECK_LAUNCH();
