@@ -83,9 +83,10 @@ struct BPow {
 
 #define PRE_MAX 64  // the first pass hashes up to this many bytes of every string
 #define PRE_SLOTS 5  // 4, 8, 16, 32, 64
+#define PRE_ALL (PRE_SLOTS + 2)  // and 128, 256 when the first pass reads deeper
 
 struct PreLens {
-    u64 l[PRE_SLOTS];  // prefix lengths of the precomputed rounds (l_0, 2 l_0, ...)
+    u64 l[PRE_ALL];  // prefix lengths of the precomputed rounds (l_0, 2 l_0, ...)
     u32 count;
 };
 
@@ -281,254 +282,10 @@ __device__ __forceinline__ void lds_le16(const u8 *R, u32 a, u64 &lo, u64 &hi)
     hi = (u64)q[2] | ((u64)q[3] << 32);
 }
 
-// One pass = RP_STEPS steps of a tile's 32 strings.  Before its products are
-// taken, every string's bytes of the pass are copied into the wavefront's LDS
-// rows by the transfer unit (chunk c of string s at 16 (RP_CH s + c), from
-// the string's 16-aligned pass start), so that each copy instruction reads
-// long runs of one string; the lanes then read their MFMA operands from LDS.
-// The copy of the next pass is issued before the current pass's products.
-__global__ __launch_bounds__(256, 4) void k_hash_round(const u32 *act, const u32 *cnt, const u8 *bytes, u64 N,
-                                                    const u64 *off, u64 lprev, u64 l1, u64 l2, u32 bits,
-                                                    u64 *state, u64 *keys1, u64 *keys2, RoundW rw, u64 *rf)
-{
-    // digit weights: [step of the chunk][32-byte block][16-byte half][digit]
-    __shared__ v4i wtab[RW_STEPS * 2 * 2 * 9];
-    __shared__ __attribute__((aligned(16))) u8 rows[4 * RP_ROW];
-    __shared__ u64 pwa[4][32];  // per wavefront: pass start (16-aligned, relative) of each string
-    __shared__ u32 pwn[4][32];  // ... and its chunk count (0: not copied)
-    for (u32 e = threadIdx.x; e < RW_STEPS * 2 * 2 * 9; e += blockDim.x) {
-        const u32 d = e % 9, kh = (e / 9) & 1, kb = (e / 18) & 1, st = e / 36;
-        u32 wd[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int q = 0; q < 4; q++) {  // the four limbs of the 16 positions
-            const u32 j = 16 * st + 8 * kb + 4 * kh + q;
-            const u64 ib = mulmod61(rw.iblo[j & 15], rw.ibhi[j >> 4]);
-#pragma unroll
-            for (int b = 0; b < 4; b++) {
-                const u32 c = (u32)((rot61(ib, 8 * b) >> (7 * d)) & 127u);
-                wd[q] |= c << (8 * b);
-            }
-        }
-        wtab[e] = v4i{(int)wd[0], (int)wd[1], (int)wd[2], (int)wd[3]};
-    }
-    __syncthreads();
-    const u32 lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5, wv = threadIdx.x >> 6;
-    u8 *R = rows + wv * RP_ROW;
-    const u64 babs = (u64)(uintptr_t)bytes;
-    // this lane's weight row: register dr of row set 0 (full weights) or set 1
-    // (weights below l1); digit dr in the low-bit product, dr - 1 in the high-bit one
-    const u32 dr = 4 * (col >> 3) + (col & 3);
-    const bool rowl1 = (col & 4) != 0;
-    const bool rowlo = dr < 9, rowhi = dr >= 1 && dr < 10;
-    // positions inside a string fit in 32 bits
-    const bool two = l2 != 0;
-    const u32 L1 = (u32)l1, LP = (u32)lprev;
-    const u32 lend = two ? (u32)l2 : L1;
-    const u32 lmine = (two && h) ? L1 : lend;  // the round this lane finishes
-    u64 fmn = ~0ull, fmx = 0, fsh = 0;
-    const u32 A = *cnt;
-    const u32 ntiles = (A + 31) / 32;
-    const u32 wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
-    const u32 x0 = LP & ~63u;
-    // Indices past the list are clamped to its last entry so that the loads
-    // need no branch.
-    auto entry = [&](u32 tile) -> u32 {
-        const u32 jj = tile * 32 + col;
-        const u32 jc = jj < A ? jj : A - 1;
-        return act ? act[jc] : jc;
-    };
-    auto tile_xmax = [&](u32 m) -> u32 {
-#pragma unroll
-        for (int s2 = 1; s2 < 32; s2 <<= 1) {
-            const u32 t = __shfl_xor(m, s2);
-            m = t > m ? t : m;
-        }
-        return m;
-    };
-    // copy pass [xp, xp + 128) of this lane's string (string end m) into the rows
-    auto issue_copy = [&](u64 o, u32 m, u32 xp) {
-        const u64 A0 = (babs + o + xp) & ~15ull;
-        const u32 sh = (u32)((babs + o + xp) & 15);
-        const u32 need = m > xp ? ((m - xp < 64 * RP_STEPS ? m : xp + 64 * RP_STEPS) - xp) : 0u;
-        const u32 nch = need ? (sh + need + 15) / 16 : 0u;
-        const bool edge = nch && (A0 < babs || A0 + 16ull * nch > babs + N);
-        if (h == 0) {  // (read back below by the same wavefront: LDS keeps its order)
-            pwa[wv][col] = A0 - babs;
-            pwn[wv][col] = edge ? 0u : nch;
-        }
-        constexpr int T = (32 * RP_CH + 63) / 64;
-        u64 ad[T];
-        bool ok[T];
-#pragma unroll
-        for (int t = 0; t < T; t++) {  // every address first: the copies then issue back to back
-            u32 slot = 64 * t + lane;
-            asm volatile("" : "+v"(slot));  // recomputed per pass rather than held in registers
-            const u32 sx = slot / RP_CH, c = slot % RP_CH;
-            ad[t] = pwa[wv][sx & 31] + 16u * c;
-            ok[t] = sx < 32 && c < pwn[wv][sx & 31];
-        }
-#pragma unroll
-        for (int t = 0; t < T; t++)
-            if (ok[t]) __builtin_amdgcn_global_load_lds((const void *)(bytes + ad[t]), (lds_void_h *)(R + 1024 * t), 16, 0, 0);
-    };
-    if (wave < ntiles) {
-        // current tile: entry, offsets, state; the next tile's entry
-        u32 tile = wave;
-        u32 i_c = entry(tile);
-        bool valid = tile * 32 + col < A;
-        u64 o_c = off[i_c];
-        u32 len = valid ? (u32)(off[i_c + 1] - o_c) : 0u;
-        u64 G = (valid && lprev) ? state[i_c] : 0ull;
-        u32 i_n = entry(tile + nwaves < ntiles ? tile + nwaves : tile);
-        u64 o_n = 0, G_n = 0;
-        u32 len_n = 0;
-        bool more = tile + nwaves < ntiles;
-        if (more) {
-            o_n = off[i_n];
-            len_n = (u32)(off[i_n + 1] - o_n);
-            if (lprev) G_n = state[i_n];
-        }
-        u32 i_nn = entry(tile + 2 * nwaves < ntiles ? tile + 2 * nwaves : tile);
-        u32 m = len < lend ? len : lend;
-        u32 xmax = tile_xmax(m);
-        u64 ibc = rw.ibc0;
-        v16i S = {};
-        u32 xp = x0;
-        issue_copy(o_c, m, xp);
-        for (;;) {  // passes; uniform over the wavefront
-            // this pass's operand bytes: [u][kb], 16 each (zero past the string)
-            u64 lo[RP_STEPS][2], hi[RP_STEPS][2];
-            {
-                const u32 sh = (u32)((babs + o_c + xp) & 15);
-                const u32 need = m > xp ? ((m - xp < 64 * RP_STEPS ? m : xp + 64 * RP_STEPS) - xp) : 0u;
-                const u32 nch = need ? (sh + need + 15) / 16 : 0u;
-                const u64 A0 = (babs + o_c + xp) & ~15ull;
-                const bool edge = nch && (A0 < babs || A0 + 16ull * nch > babs + N);
-#pragma unroll
-                for (int u = 0; u < RP_STEPS; u++)
-#pragma unroll
-                    for (int kb = 0; kb < 2; kb++) {
-                        const u32 rel = 64 * u + 32 * kb + 16 * h;
-                        const u32 take = need > rel ? ((need - rel) < 16 ? need - rel : 16u) : 0u;
-                        lo[u][kb] = hi[u][kb] = 0;
-                        if (take) {
-                            if (!edge) lds_le16(R, RP_CH * 16 * col + sh + rel, lo[u][kb], hi[u][kb]);
-                            else load16_le(bytes, N, o_c + xp + rel, take, lo[u][kb], hi[u][kb]);
-                            if (take < 8) {
-                                lo[u][kb] &= (1ull << (8 * take)) - 1ull;
-                                hi[u][kb] = 0;
-                            } else if (take < 16) {
-                                hi[u][kb] &= take == 8 ? 0ull : ((1ull << (8 * (take - 8))) - 1ull);
-                            }
-                        }
-                    }
-            }
-            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the rows are read before the next copy
-            // the next pass: the rest of this tile, or the next tile's first
-            const bool tile_end = xp + 64 * RP_STEPS >= xmax;
-            u32 m_n = 0, xmax_n = 0;
-            bool valid_n = false;
-            if (!tile_end) {
-                issue_copy(o_c, m, xp + 64 * RP_STEPS);
-            } else if (more) {
-                valid_n = (tile + nwaves) * 32 + col < A;
-                if (!valid_n) len_n = 0;
-                m_n = len_n < lend ? len_n : lend;
-                xmax_n = tile_xmax(m_n);
-                issue_copy(o_n, m_n, x0);
-            }
-            // this pass's products
-#pragma unroll
-            for (int u = 0; u < RP_STEPS; u++) {
-                const u32 x = xp + 64 * u;
-                if (x >= xmax) break;  // uniform over the wavefront
-                const u32 sidx = (u32)((x & 1023) >> 6);
-#pragma unroll
-                for (int kb = 0; kb < 2; kb++) {
-                    u64 l0 = lo[u][kb], h0 = hi[u][kb];
-                    const u32 a0 = x + 32 * kb + 16 * h;
-                    if (a0 < LP) {  // bytes below lprev are in G already
-                        const u32 skip = LP - a0 < 16 ? LP - a0 : 16u;
-                        if (skip >= 8) {
-                            l0 = 0;
-                            h0 &= skip == 16 ? 0ull : ~((1ull << (8 * (skip - 8))) - 1ull);
-                        } else {
-                            l0 &= ~((1ull << (8 * skip)) - 1ull);
-                        }
-                    }
-                    const u64 l7 = 0x7F7F7F7F7F7F7F7Full, h1 = 0x0101010101010101ull;
-                    const u64 lo7 = l0 & l7, hi7 = h0 & l7, loh = (l0 >> 7) & h1, hih = (h0 >> 7) & h1;
-                    const v4i xl = v4i{(int)(u32)lo7, (int)(u32)(lo7 >> 32), (int)(u32)hi7, (int)(u32)(hi7 >> 32)};
-                    const v4i xh = v4i{(int)(u32)loh, (int)(u32)(loh >> 32), (int)(u32)hih, (int)(u32)(hih >> 32)};
-                    // this lane's weight row for the block's 16 positions (lane half = 16-byte half);
-                    // rows of the l1 set are zero from l1 on (a two-round l1 is a multiple of 64,
-                    // so no block straddles it; single-round launches do not use that set)
-                    const v4i *wrow = wtab + ((sidx * 2 + kb) * 2 + h) * 9;
-                    const bool zero = rowl1 && x + 32 * kb >= L1;
-                    v4i wl = wrow[rowlo ? dr : 0], wh = wrow[rowhi ? dr - 1 : 0];
-                    if (!rowlo || zero) wl = v4i{0, 0, 0, 0};
-                    if (!rowhi || zero) wh = v4i{0, 0, 0, 0};
-                    S = __builtin_amdgcn_mfma_i32_32x32x32_i8(wl, xl, S, 0, 0, 0);
-                    S = __builtin_amdgcn_mfma_i32_32x32x32_i8(wh, xh, S, 0, 0, 0);
-                }
-                const u32 xn = x + 64;
-                if ((xn & 1023) == 0 || xn >= xmax) {
-                    // (half 1: the sum below l1; its rows are zero from l1 on)
-                    G = addmod61(G, mulmod61(digits_mod61(S), ibc));
-                    S = v16i{};
-                    if ((xn & 1023) == 0) ibc = mulmod61(ibc, rw.ib256);
-                }
-            }
-            if (!tile_end) {
-                xp += 64 * RP_STEPS;
-                continue;
-            }
-            // the tile's keys
-            if (valid && (!h || two)) {
-                const u32 j = tile * 32 + col;
-                const u32 mm = len < lmine ? len : lmine;
-                const u64 key = kr_key(G, mm == lmine ? (lmine == L1 ? rw.bl1 : rw.bl2) : kr_pow((mm + 3) / 4 + 1, rw),
-                                       mm, bits);
-                if (h) keys1[j] = key;
-                else {
-                    state[i_c] = G;
-                    (two ? keys2 : keys1)[j] = key;
-                }
-                fmn = key < fmn ? key : fmn;
-                fmx = key > fmx ? key : fmx;
-                if (len <= lmine) fsh = 1;
-            }
-            if (!more) break;
-            // advance: the next tile becomes current (its first pass is in flight)
-            tile += nwaves;
-            i_c = i_n;
-            o_c = o_n;
-            valid = valid_n;
-            len = len_n;
-            m = m_n;
-            xmax = xmax_n;
-            G = valid ? G_n : 0;
-            ibc = rw.ibc0;
-            xp = x0;
-            more = tile + nwaves < ntiles;
-            i_n = i_nn;
-            if (more) {
-                o_n = off[i_n];
-                len_n = (u32)(off[i_n + 1] - o_n);
-                if (lprev) G_n = state[i_n];
-            }
-            i_nn = entry(tile + 2 * nwaves < ntiles ? tile + 2 * nwaves : tile);
-        }
-    }
-    flags_reduce32(fmn, fmx, fsh);
-    // flags: rf[0..2] round l1, rf[3..5] round l2
-    if (lane == 0) flags_commit(rf + (two ? 3 : 0), fmn, fmx, fsh);
-    if (lane == 32 && two) flags_commit(rf, fmn, fmx, fsh);
-}
+#define HF_ACC 3  // first pass: accumulators of two precomputed rounds each (rounds 2a, 2a + 1)
 
 #define HF_CH 5      // 16-byte chunks per string in the first pass (64 bytes at any alignment)
 #define HF_ROW 3072  // LDS bytes per wavefront: three 1 KiB copy rows (32 x 5 chunks)
-#define HF_ACC 3     // accumulators: two rounds each (rounds 2a and 2a + 1 in the two row sets)
 
 // The first pass over tiles of 32 strings: their first min(len, W) bytes
 // (W = the longest precomputed round, <= 64) are copied into LDS by the
@@ -537,10 +294,13 @@ __global__ __launch_bounds__(256, 4) void k_hash_round(const u32 *act, const u32
 // 0, lane half 0) and 2a + 1 (row set 1, half 1), with the weights of
 // positions past the round's length zero; each lane combines its own digit
 // sums into G of its rounds and writes their keys; the last round's G is the
-// state later rounds continue from.
+// state later rounds continue from.  When the deep word is set the deep
+// first pass does this work (and more), and this kernel returns at once.
 __global__ __launch_bounds__(256, 4) void k_hash_first(u32 n, const u8 *bytes, u64 N, const u64 *off, PreLens P,
-                                                       u32 bits, BPow bp, FirstW fw, u64 *state, u64 *pre, u64 *fl)
+                                                       u32 bits, BPow bp, FirstW fw, u64 *state, u64 *pre, u64 *fl,
+                                                       const u64 *deep)
 {
+    if (deep && *deep) return;  // uniform over the grid
     __shared__ v4i wtab[HF_ACC][2][2][64];  // [accumulator][32-byte block][low/high product][lane]
     __shared__ __attribute__((aligned(16))) u8 rows[4 * HF_ROW];
     __shared__ u64 pwa[4][32];  // per wavefront: copy start (16-aligned, relative) of each string
@@ -722,6 +482,438 @@ __global__ __launch_bounds__(256, 4) void k_hash_first(u32 n, const u8 *bytes, u
     }
 }
 
+
+// Arguments of a hashing pass over a list of strings (the first pass: all strings).
+struct PassArgs {
+    const u32 *act;    // active list (NULL: strings 0..n-1 in order)
+    const u32 *cnt;    // its length (device word); the first pass uses n
+    u32 n;             // number of strings (first pass)
+    const u8 *bytes;
+    u64 N;
+    const u64 *off;
+    u64 lprev, l1, l2; // continue G from lprev; keys at l1 (and l2 when nonzero)
+    u32 bits;
+    u64 *state;        // G by string index (in: at lprev; out: at the last round)
+    u64 *keys1, *keys2;  // round keys by list position
+    u64 *rf;           // flags of rounds l1 (rf[0..2]) and l2 (rf[3..5])
+    u64 *pre;          // first pass: keys of precomputed round r at pre[r n + i]
+    u64 *fl;           // first pass: flags of precomputed round r at fl[3r ..]
+    const u64 *deep;   // first pass: nonzero word = also precompute rounds l1 and l2
+};
+
+struct FirstArgs {
+    PreLens P;  // rounds up to 64 bytes
+    BPow bp;
+    FirstW fw;
+};
+
+// One pass = RP_STEPS steps of a tile's 32 strings.  Before its products are
+// taken, every string's bytes of the pass are copied into the wavefront's LDS
+// rows by the transfer unit (chunk c of string s at 16 (RP_CH s + c), from
+// the string's 16-aligned pass start), so that each copy instruction reads
+// long runs of one string; the lanes then read their MFMA operands from LDS.
+// The copy of the next pass is issued before the current pass's products.
+//
+// MODE 2: the deep first pass over all strings (MODE 1, the plain first
+// pass, is the standalone k_hash_first).  Its rounds up to 64 bytes come from
+// the first step: accumulator a holds rounds 2a (row set 0, lane
+// half 0) and 2a + 1 (set 1, half 1) with the weights of positions past each
+// round's length zero, and each lane writes the keys of its rounds.  MODE 2
+// (deep: most strings share a long prefix) continues the same read to
+// l2 = 256 and precomputes rounds l1 = 128 and l2 with the round machinery,
+// so such data are read once instead of in two passes.  Both first-pass
+// kernels are launched; the device word *deep lets exactly one of them work.
+template <int MODE>
+__device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, const FirstArgs *Fp)
+{
+    constexpr bool FIRST = MODE != 0;
+    if (FIRST) {  // uniform over the grid
+        const bool want = A.deep && *A.deep != 0;
+        if (want != (MODE == 2)) return;
+    }
+    // round weights: [step of the chunk][32-byte block][16-byte half][digit]
+    __shared__ v4i wtab[MODE != 1 ? RW_STEPS * 2 * 2 * 9 : 1];
+    // first-pass weights: [accumulator][32-byte block][low/high product][lane]
+    __shared__ v4i wfirst[FIRST ? HF_ACC * 2 * 2 * 64 : 1];
+    __shared__ __attribute__((aligned(16))) u8 rows[4 * RP_ROW];
+    __shared__ u64 pwa[4][32];  // per wavefront: pass start (16-aligned, relative) of each string
+    __shared__ u32 pwn[4][32];  // ... and its chunk count (0: not copied)
+    __shared__ u64 s_ib[16], s_l[PRE_SLOTS];
+    for (u32 e = threadIdx.x; e < (MODE != 1 ? RW_STEPS * 2 * 2 * 9 : 0); e += blockDim.x) {
+        const u32 d = e % 9, kh = (e / 9) & 1, kb = (e / 18) & 1, st = e / 36;
+        u32 wd[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < 4; q++) {  // the four limbs of the 16 positions
+            const u32 j = 16 * st + 8 * kb + 4 * kh + q;
+            const u64 ib = mulmod61(rw.iblo[j & 15], rw.ibhi[j >> 4]);
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                const u32 c = (u32)((rot61(ib, 8 * b) >> (7 * d)) & 127u);
+                wd[q] |= c << (8 * b);
+            }
+        }
+        wtab[e] = v4i{(int)wd[0], (int)wd[1], (int)wd[2], (int)wd[3]};
+    }
+    u32 c0 = 0;  // precomputed rounds up to 64 bytes (first pass)
+    if (FIRST) {
+        const FirstArgs &F = *Fp;
+        c0 = F.P.count;
+        // kernel-argument arrays are read with constant indices only
+        if (threadIdx.x < 16) {
+            u64 v = 0;
+#pragma unroll
+            for (int k = 0; k < 16; k++)
+                if (threadIdx.x == (u32)k) v = F.fw.ib[k];
+            s_ib[threadIdx.x] = v;
+        }
+        if (threadIdx.x < PRE_SLOTS) {
+            u64 v = 0;
+#pragma unroll
+            for (int k = 0; k < PRE_SLOTS; k++)
+                if (threadIdx.x == (u32)k) v = (u32)k < c0 ? F.P.l[k] : 0;
+            s_l[threadIdx.x] = v;
+        }
+        __syncthreads();
+        for (u32 e = threadIdx.x; e < HF_ACC * 2 * 2 * 64; e += blockDim.x) {
+            const u32 ln = e & 63, hl = (e >> 6) & 1, kb = (e >> 7) & 1, a = e >> 8;
+            const u32 rc = ln & 31, kh = ln >> 5;
+            const u32 dr = 4 * (rc >> 3) + (rc & 3);  // the row's register (digit) in its set
+            const u32 r = 2 * a + ((rc >> 2) & 1);     // the row's round
+            const bool ok = r < c0 && (hl ? (dr >= 1 && dr < 10) : dr < 9);
+            const u32 d = hl ? dr - 1 : dr;
+            const u64 lim = ok ? s_l[r < PRE_SLOTS ? r : 0] : 0;
+            u32 wd[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const u32 j = 8 * kb + 4 * kh + q;  // limb: positions 4j .. 4j+3
+                const u64 ib = s_ib[j];
+#pragma unroll
+                for (int b = 0; b < 4; b++) {
+                    const u32 c = (4 * j + b < lim) ? (u32)((rot61(ib, 8 * b) >> (7 * d)) & 127u) : 0u;
+                    wd[q] |= c << (8 * b);
+                }
+            }
+            wfirst[e] = v4i{(int)wd[0], (int)wd[1], (int)wd[2], (int)wd[3]};
+        }
+    }
+    __syncthreads();
+    const u32 lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5, wv = threadIdx.x >> 6;
+    u8 *R = rows + wv * RP_ROW;
+    const u64 babs = (u64)(uintptr_t)A.bytes;
+    const u8 *bytes = A.bytes;
+    const u64 N = A.N;
+    const u64 *off = A.off;
+    // this lane's weight row: register dr of row set 0 (full weights) or set 1
+    // (weights below l1); digit dr in the low-bit product, dr - 1 in the high-bit one
+    const u32 dr = 4 * (col >> 3) + (col & 3);
+    const bool rowl1 = (col & 4) != 0;
+    const bool rowlo = dr < 9, rowhi = dr >= 1 && dr < 10;
+    // the round machinery runs in every later round and in a deep first pass
+    constexpr bool deep = MODE == 2;
+    constexpr bool rpart = MODE != 1;
+    // positions inside a string fit in 32 bits
+    const bool two = rpart && A.l2 != 0;
+    const u32 L1 = (u32)A.l1, LP = FIRST ? 0u : (u32)A.lprev;
+    const u32 W = FIRST ? (u32)s_l[c0 - 1] : 0u;  // the longest round up to 64 bytes
+    const u32 lend = rpart ? (two ? (u32)A.l2 : L1) : W;
+    const u32 lmine = (two && h) ? L1 : lend;  // the round this lane finishes
+    // B^(lmine/4 + 1), selected bitwise (a select of the two loads becomes an
+    // indexed stack array)
+    const u64 selm = 0ull - (u64)(lmine == L1);
+    const u64 blmine = (rw.bl1 & selm) | (rw.bl2 & ~selm);
+    // (the same for the output of half 0's keys)
+    const u64 sel2 = 0ull - (u64)two;
+    u64 *const keys0 = (u64 *)(((uintptr_t)A.keys2 & sel2) | ((uintptr_t)A.keys1 & ~sel2));
+    const u32 nacc = (c0 + 1) / 2;
+    u64 fmn = ~0ull, fmx = 0, fsh = 0;
+    u64 ffmn[HF_ACC], ffmx[HF_ACC], ffsh[HF_ACC];
+#pragma unroll
+    for (int a = 0; a < HF_ACC; a++) {
+        ffmn[a] = ~0ull;
+        ffmx[a] = 0;
+        ffsh[a] = 0;
+    }
+    const u32 Acnt = FIRST ? A.n : *A.cnt;
+    const u32 ntiles = (Acnt + 31) / 32;
+    const u32 wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
+    const u32 x0 = LP & ~63u;
+    // Indices past the list are clamped to its last entry so that the loads
+    // need no branch.
+    auto entry = [&](u32 tile) -> u32 {
+        const u32 jj = tile * 32 + col;
+        const u32 jc = jj < Acnt ? jj : Acnt - 1;
+        return A.act ? A.act[jc] : jc;
+    };
+    auto tile_xmax = [&](u32 m) -> u32 {
+#pragma unroll
+        for (int s2 = 1; s2 < 32; s2 <<= 1) {
+            const u32 t = __shfl_xor(m, s2);
+            m = t > m ? t : m;
+        }
+        return m;
+    };
+    // copy pass [xp, xp + 128) of this lane's string (string end m) into the rows
+    auto issue_copy = [&](u64 o, u32 m, u32 xp) {
+        const u64 A0 = (babs + o + xp) & ~15ull;
+        const u32 sh = (u32)((babs + o + xp) & 15);
+        const u32 need = m > xp ? ((m - xp < 64 * RP_STEPS ? m : xp + 64 * RP_STEPS) - xp) : 0u;
+        const u32 nch = need ? (sh + need + 15) / 16 : 0u;
+        const bool edge = nch && (A0 < babs || A0 + 16ull * nch > babs + N);
+        if (h == 0) {  // (read back below by the same wavefront: LDS keeps its order)
+            pwa[wv][col] = A0 - babs;
+            pwn[wv][col] = edge ? 0u : nch;
+        }
+        constexpr int T = (32 * RP_CH + 63) / 64;
+        u64 ad[T];
+        bool ok[T];
+#pragma unroll
+        for (int t = 0; t < T; t++) {  // every address first: the copies then issue back to back
+            u32 slot = 64 * t + lane;
+            asm volatile("" : "+v"(slot));  // recomputed per pass rather than held in registers
+            const u32 sx = slot / RP_CH, c = slot % RP_CH;
+            ad[t] = pwa[wv][sx & 31] + 16u * c;
+            ok[t] = sx < 32 && c < pwn[wv][sx & 31];
+        }
+#pragma unroll
+        for (int t = 0; t < T; t++)
+            if (ok[t]) __builtin_amdgcn_global_load_lds((const void *)(bytes + ad[t]), (lds_void_h *)(R + 1024 * t), 16, 0, 0);
+    };
+    if (wave < ntiles) {
+        // current tile: entry, offsets, state; the next tile's entry
+        u32 tile = wave;
+        u32 i_c = entry(tile);
+        bool valid = tile * 32 + col < Acnt;
+        u64 o_c = off[i_c];
+        u32 len = valid ? (u32)(off[i_c + 1] - o_c) : 0u;
+        u64 G = (valid && LP) ? A.state[i_c] : 0ull;
+        u32 i_n = entry(tile + nwaves < ntiles ? tile + nwaves : tile);
+        u64 o_n = 0, G_n = 0;
+        u32 len_n = 0;
+        bool more = tile + nwaves < ntiles;
+        if (more) {
+            o_n = off[i_n];
+            len_n = (u32)(off[i_n + 1] - o_n);
+            if (LP) G_n = A.state[i_n];
+        }
+        u32 i_nn = entry(tile + 2 * nwaves < ntiles ? tile + 2 * nwaves : tile);
+        u32 m = len < lend ? len : lend;
+        u32 xmax = tile_xmax(m);
+        u64 ibc = rw.ibc0;
+        v16i S = {};
+        u32 xp = x0;
+        issue_copy(o_c, m, xp);
+        for (;;) {  // passes; uniform over the wavefront
+            // this pass's operand bytes: [u][kb], 16 each (zero past the string)
+            u64 lo[RP_STEPS][2], hi[RP_STEPS][2];
+            {
+                const u32 sh = (u32)((babs + o_c + xp) & 15);
+                const u32 need = m > xp ? ((m - xp < 64 * RP_STEPS ? m : xp + 64 * RP_STEPS) - xp) : 0u;
+                const u32 nch = need ? (sh + need + 15) / 16 : 0u;
+                const u64 A0 = (babs + o_c + xp) & ~15ull;
+                const bool edge = nch && (A0 < babs || A0 + 16ull * nch > babs + N);
+#pragma unroll
+                for (int u = 0; u < RP_STEPS; u++)
+#pragma unroll
+                    for (int kb = 0; kb < 2; kb++) {
+                        const u32 rel = 64 * u + 32 * kb + 16 * h;
+                        const u32 take = need > rel ? ((need - rel) < 16 ? need - rel : 16u) : 0u;
+                        lo[u][kb] = hi[u][kb] = 0;
+                        if (take) {
+                            if (!edge) lds_le16(R, RP_CH * 16 * col + sh + rel, lo[u][kb], hi[u][kb]);
+                            else load16_le(bytes, N, o_c + xp + rel, take, lo[u][kb], hi[u][kb]);
+                            if (take < 8) {
+                                lo[u][kb] &= (1ull << (8 * take)) - 1ull;
+                                hi[u][kb] = 0;
+                            } else if (take < 16) {
+                                hi[u][kb] &= take == 8 ? 0ull : ((1ull << (8 * (take - 8))) - 1ull);
+                            }
+                        }
+                    }
+            }
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the rows are read before the next copy
+            // the next pass: the rest of this tile, or the next tile's first
+            const bool tile_end = xp + 64 * RP_STEPS >= xmax;
+            u32 m_n = 0, xmax_n = 0;
+            bool valid_n = false;
+            if (!tile_end) {
+                issue_copy(o_c, m, xp + 64 * RP_STEPS);
+            } else if (more) {
+                valid_n = (tile + nwaves) * 32 + col < Acnt;
+                if (!valid_n) len_n = 0;
+                m_n = len_n < lend ? len_n : lend;
+                xmax_n = tile_xmax(m_n);
+                issue_copy(o_n, m_n, x0);
+            }
+            // this pass's products
+#pragma unroll
+            for (int u = 0; u < RP_STEPS; u++) {
+                const u32 x = xp + 64 * u;
+                const bool fstep = FIRST && x == 0;  // the first pass's rounds (taken even for empty strings)
+                if (x >= xmax && !fstep) break;      // uniform over the wavefront
+                const u32 sidx = (x & 1023) >> 6;
+                v4i xl[2], xh[2];
+#pragma unroll
+                for (int kb = 0; kb < 2; kb++) {
+                    u64 l0 = lo[u][kb], h0 = hi[u][kb];
+                    const u32 a0 = x + 32 * kb + 16 * h;
+                    if (a0 < LP) {  // bytes below lprev are in G already
+                        const u32 skip = LP - a0 < 16 ? LP - a0 : 16u;
+                        if (skip >= 8) {
+                            l0 = 0;
+                            h0 &= skip == 16 ? 0ull : ~((1ull << (8 * (skip - 8))) - 1ull);
+                        } else {
+                            l0 &= ~((1ull << (8 * skip)) - 1ull);
+                        }
+                    }
+                    const u64 l7 = 0x7F7F7F7F7F7F7F7Full, h1 = 0x0101010101010101ull;
+                    const u64 lo7 = l0 & l7, hi7 = h0 & l7, loh = (l0 >> 7) & h1, hih = (h0 >> 7) & h1;
+                    xl[kb] = v4i{(int)(u32)lo7, (int)(u32)(lo7 >> 32), (int)(u32)hi7, (int)(u32)(hi7 >> 32)};
+                    xh[kb] = v4i{(int)(u32)loh, (int)(u32)(loh >> 32), (int)(u32)hih, (int)(u32)(hih >> 32)};
+                    if (rpart) {
+                        // this lane's weight row for the block's 16 positions (lane half = 16-byte
+                        // half); rows of the l1 set are zero from l1 on (a two-round l1 is a
+                        // multiple of 64, so no block straddles it; single rounds do not use it)
+                        const v4i *wrow = wtab + ((sidx * 2 + kb) * 2 + h) * 9;
+                        const bool zero = rowl1 && x + 32 * kb >= L1;
+                        v4i wl = wrow[rowlo ? dr : 0], wh = wrow[rowhi ? dr - 1 : 0];
+                        if (!rowlo || zero) wl = v4i{0, 0, 0, 0};
+                        if (!rowhi || zero) wh = v4i{0, 0, 0, 0};
+                        S = __builtin_amdgcn_mfma_i32_32x32x32_i8(wl, xl[kb], S, 0, 0, 0);
+                        S = __builtin_amdgcn_mfma_i32_32x32x32_i8(wh, xh[kb], S, 0, 0, 0);
+                    }
+                }
+                if (fstep) {
+                    // the precomputed rounds, one accumulator at a time: keys of this
+                    // lane's rounds 2a + h
+                    const u32 i = tile * 32 + col;
+#pragma unroll
+                    for (int a = 0; a < HF_ACC; a++) {
+                        if ((u32)a >= nacc) break;  // uniform
+                        v16i S1 = {};
+#pragma unroll
+                        for (int kb = 0; kb < 2; kb++) {
+                            S1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(wfirst[((a * 2 + kb) * 2 + 0) * 64 + lane], xl[kb], S1, 0, 0, 0);
+                            S1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(wfirst[((a * 2 + kb) * 2 + 1) * 64 + lane], xh[kb], S1, 0, 0, 0);
+                        }
+                        const u32 r = 2 * a + h;
+                        if (i < Acnt && r < c0) {
+                            const u64 Gr = digits_mod61(S1);
+                            const u32 lr = (u32)s_l[r];
+                            const u32 mr = len < lr ? len : lr;
+                            const u64 key = kr_key(Gr, Fp->bp.p[(mr + 3) / 4 + 1], mr, A.bits);
+                            A.pre[(u64)r * Acnt + i] = key;
+                            if (!deep && r == c0 - 1) A.state[i] = Gr;  // later rounds continue from G
+                            ffmn[a] = key < ffmn[a] ? key : ffmn[a];
+                            ffmx[a] = key > ffmx[a] ? key : ffmx[a];
+                            if (len <= lr) ffsh[a] = 1;
+                        }
+                    }
+                }
+                const u32 xn = x + 64;
+                if (rpart && ((xn & 1023) == 0 || xn >= xmax)) {
+                    // (half 1: the sum below l1; its rows are zero from l1 on)
+                    G = addmod61(G, mulmod61(digits_mod61(S), ibc));
+                    S = v16i{};
+                    if ((xn & 1023) == 0) ibc = mulmod61(ibc, rw.ib256);
+                }
+            }
+            if (!tile_end) {
+                xp += 64 * RP_STEPS;
+                continue;
+            }
+            // the tile's keys of the round machinery
+            if (rpart && valid && (!h || two)) {
+                const u32 j = tile * 32 + col;
+                const u32 mm = len < lmine ? len : lmine;
+                const u64 key = kr_key(G, mm == lmine ? blmine : kr_pow((mm + 3) / 4 + 1, rw), mm, A.bits);
+                if (FIRST) {  // precomputed rounds c0 (l1) and c0 + 1 (l2), by string index
+                    A.pre[(u64)(c0 + (h ? 0u : 1u)) * Acnt + j] = key;
+                    if (!h) A.state[j] = G;
+                } else if (h) {
+                    A.keys1[j] = key;
+                } else {
+                    A.state[i_c] = G;
+                    keys0[j] = key;
+                }
+                fmn = key < fmn ? key : fmn;
+                fmx = key > fmx ? key : fmx;
+                if (len <= lmine) fsh = 1;
+            }
+            if (!more) break;
+            // advance: the next tile becomes current (its first pass is in flight)
+            tile += nwaves;
+            i_c = i_n;
+            o_c = o_n;
+            valid = valid_n;
+            len = len_n;
+            m = m_n;
+            xmax = xmax_n;
+            G = valid ? G_n : 0;
+            ibc = rw.ibc0;
+            xp = x0;
+            more = tile + nwaves < ntiles;
+            i_n = i_nn;
+            if (more) {
+                o_n = off[i_n];
+                len_n = (u32)(off[i_n + 1] - o_n);
+                if (LP) G_n = A.state[i_n];
+            }
+            i_nn = entry(tile + 2 * nwaves < ntiles ? tile + 2 * nwaves : tile);
+        }
+    }
+    if (rpart) {
+        flags_reduce32(fmn, fmx, fsh);
+        if (FIRST) {  // rounds l1 (lane half 1) and l2 (half 0) as precomputed rounds c0, c0 + 1
+            if (col == 0) flags_commit(A.fl + 3 * (c0 + (h ? 0u : 1u)), fmn, fmx, fsh);
+        } else {  // A.rf[0..2] round l1, A.rf[3..5] round l2
+            if (lane == 0) flags_commit(A.rf + (two ? 3 : 0), fmn, fmx, fsh);
+            if (lane == 32 && two) flags_commit(A.rf, fmn, fmx, fsh);
+        }
+    }
+    if (FIRST) {
+#pragma unroll
+        for (int a = 0; a < HF_ACC; a++) {
+            flags_reduce32(ffmn[a], ffmx[a], ffsh[a]);
+            const u32 r = 2 * a + h;
+            if (col == 0 && r < c0) flags_commit(A.fl + 3 * r, ffmn[a], ffmx[a], ffsh[a]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256, 4) void k_hash_round(PassArgs A, RoundW rw)
+{
+    hash_pass<0>(A, rw, nullptr);
+}
+
+__global__ __launch_bounds__(256, 3) void k_hash_first_deep(PassArgs A, RoundW rw, FirstArgs F)
+{
+    hash_pass<2>(A, rw, &F);
+}
+
+// Whether the first pass should also precompute rounds 128 and 256: at least
+// 90 % of up to 4096 evenly spaced strings are at least 128 bytes long and
+// share their first 64 bytes with the first of them (e.g. strings with a
+// long common prefix).  Only the amount of bytes read depends on it.
+__global__ __launch_bounds__(1024) void k_deep_probe(u32 n, const u8 *bytes, u64 N, const u64 *off, u64 *flag)
+{
+    __shared__ u32 cnt;
+    const u32 S = n < 4096 ? n : 4096;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const u64 o0 = off[0], l0 = off[1] - o0;
+    u32 c = 0;
+    for (u32 k = threadIdx.x; k < S; k += blockDim.x) {
+        const u32 i = (u32)((u64)k * n / S);
+        const u64 o = off[i], l = off[i + 1] - o;
+        bool same = l >= 128 && l0 >= 128;
+        for (u32 q = 0; q < 64 && same; q += 8) same = load_le(bytes, N, o + q, 8) == load_le(bytes, N, o0 + q, 8);
+        c += same ? 1u : 0u;
+    }
+    atomicAdd(&cnt, c);
+    __syncthreads();
+    if (threadIdx.x == 0) flag[0] = (10ull * cnt >= 9ull * S && S > 0) ? 1ull : 0ull;
+}
+
 // ------------------------------------------------------------ duplicates
 //
 // Keys are < 2^61 (residues mod 2^61-1, possibly masked to fewer bits), so the
@@ -842,12 +1034,13 @@ __global__ __launch_bounds__(256) void k_dedup(const u64 *keys, int kin, const u
     }
 }
 
-// hdr: words 0..7 hold the u32 counters, 8..22 the first-pass round flags (three
-// per round), 23..28 the flags of a hash launch (rounds l and 2l); the host
-// reads them back together.
-#define HDR_WORDS 32
+// hdr: words 0..7 hold the u32 counters, 8..28 the flags of the precomputed
+// rounds (three per round), 29 the first pass's deep decision, 30..35 the
+// flags of a hash launch (rounds l and 2l); the host reads them back together.
+#define HDR_WORDS 40
 #define HDR_FIRST 8
-#define HDR_ROUND (HDR_FIRST + 3 * PRE_SLOTS)
+#define HDR_DEEP (HDR_FIRST + 3 * PRE_ALL)
+#define HDR_ROUND (HDR_DEEP + 1)
 struct PdWs {
     u32 *actA, *actB, *ctr;
     u64 *hdr, *keys, *keysB, *keysC, *state, *pre, *tab;
@@ -869,7 +1062,7 @@ static void pd_layout(u64 n, PdWs *w, WsArena *a, WsCounter *c)
     } while (0)
     PT(actA, u32, n); PT(actB, u32, n); PT(hdr, u64, HDR_WORDS); PT(keys, u64, n); PT(keysB, u64, n);
     PT(keysC, u64, n); PT(state, u64, n);
-    PT(pre, u64, (u64)PRE_SLOTS * n); PT(tab, u64, 1ull << tab_log(n));
+    PT(pre, u64, (u64)PRE_ALL * n); PT(tab, u64, 1ull << tab_log(n));
 #undef PT
     if (a) w->ctr = (u32 *)w->hdr;
 }
@@ -972,22 +1165,63 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
     // rounds whose prefix length is at most PRE_MAX are hashed in one first pass
     PreLens P{};
     for (u64 L = init_len; L <= PRE_MAX && P.count < PRE_SLOTS; L *= 2) P.l[P.count++] = L;
-    u32 pf[2 * PRE_SLOTS] = {};
+    u32 pf[2 * PRE_ALL] = {};
     if (P.count) {
-        {
-            // the first line of every string, once
-            SS_PROF("k_hash_first", st,
-                    (double)n * (double)P.l[P.count - 1] + (double)n * (24.0 + 8.0 * P.count));
-            const u64 tiles = ceil_div(n, 32);
-            const unsigned blocks = (unsigned)(ceil_div(tiles, 4) < 2048 ? ceil_div(tiles, 4) : 2048);
-            k_flag_init<<<1, 64, 0, st>>>(fl_first, 3 * P.count);
+        // The first pass may also precompute the two rounds after 64 bytes
+        // (128 and 256) from the same read, when a sample of the strings shows
+        // a long shared prefix; the device decides, the flags read-back tells.
+        const u32 c0 = P.count;
+        const bool deep_ok = P.l[c0 - 1] == PRE_MAX;
+        const u64 tiles = ceil_div(n, 32);
+        const unsigned blocks = (unsigned)(ceil_div(tiles, 4) < 2048 ? ceil_div(tiles, 4) : 2048);
+        k_flag_init<<<1, 64, 0, st>>>(fl_first, 3 * PRE_ALL);
+        SS_CHECK_LAUNCH();
+        if (deep_ok) {
+            k_deep_probe<<<1, 1024, 0, st>>>((u32)n, bytes, N, offsets, w.hdr + HDR_DEEP);
             SS_CHECK_LAUNCH();
-            k_hash_first<<<blocks, 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits, bp, first_weights(),
-                                                 w.state, w.pre, fl_first);
+        }
+        PassArgs A{};
+        A.n = (u32)n;
+        A.bytes = bytes;
+        A.N = N;
+        A.off = offsets;
+        A.lprev = 0;
+        A.l1 = 2 * PRE_MAX;
+        A.l2 = 4 * PRE_MAX;
+        A.bits = hash_bits;
+        A.state = w.state;
+        A.pre = w.pre;
+        A.fl = fl_first;
+        A.deep = deep_ok ? w.hdr + HDR_DEEP : nullptr;
+        FirstArgs Fa{};
+        Fa.P = P;
+        Fa.bp = bp;
+        Fa.fw = first_weights();
+        const RoundW rwd = round_weights(0, 2 * PRE_MAX, 4 * PRE_MAX);
+        {
+            SS_PROF("k_hash_first", st, (double)n * (double)P.l[c0 - 1] + (double)n * (24.0 + 8.0 * c0));
+            k_hash_first<<<blocks, 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits, bp, Fa.fw, w.state, w.pre,
+                                                 fl_first, A.deep);
         }
         SS_CHECK_LAUNCH();
-        u64 F[3 * PRE_SLOTS];
-        SS_TRY(ss_read_u64(fl_first, F, 3 * P.count, st));
+        if (deep_ok) {
+            // the bytes are charged once the decision is read back
+            SS_PROF("k_hash_first_deep", st, 0.0);
+            k_hash_first_deep<<<blocks, 256, 0, st>>>(A, rwd, Fa);
+        }
+        SS_CHECK_LAUNCH();
+        u64 F[3 * PRE_ALL + 1];  // the flags of every precomputed round, then the deep word
+        SS_TRY(ss_read_u64(fl_first, F, 3 * PRE_ALL + 1, st));
+        if (deep_ok && F[3 * PRE_ALL]) {
+            P.l[c0] = 2 * PRE_MAX;
+            P.l[c0 + 1] = 4 * PRE_MAX;
+            P.count = c0 + 2;
+            ss_prof_drop_last("k_hash_first");  // (returned at once)
+            ss_prof_add_bytes("k_hash_first_deep",
+                              (double)n * (4.0 * PRE_MAX) + (double)n * (24.0 + 8.0 * (c0 + 2)));
+        } else if (deep_ok) {
+            ss_prof_drop_last("k_hash_first_deep");
+        }
         for (u32 r = 0; r < P.count; r++) {
             pf[2 * r] = F[3 * r] != F[3 * r + 1];
             pf[2 * r + 1] = F[3 * r + 2] != 0;
@@ -1036,9 +1270,22 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
                 const u64 tiles = ceil_div(Ah, 32);
                 const u64 nb = ceil_div(tiles, 4);
                 k_flag_init<<<1, 64, 0, st>>>(fl_round, 6);
+                PassArgs A{};
+                A.act = act;
+                A.cnt = ctr + ci;
+                A.bytes = bytes;
+                A.N = N;
+                A.off = offsets;
+                A.lprev = lprev;
+                A.l1 = l;
+                A.l2 = two ? 2 * l : 0;
+                A.bits = hash_bits;
+                A.state = w.state;
+                A.keys1 = w.keys;
+                A.keys2 = w.keysB;
+                A.rf = fl_round;
                 k_hash_round<<<(unsigned)(nb < 1024 ? (nb ? nb : 1) : 1024), 256, 0, st>>>(
-                    act, ctr + ci, bytes, N, offsets, lprev, l, two ? 2 * l : 0, hash_bits, w.state, w.keys,
-                    w.keysB, round_weights(lprev, l, two ? 2 * l : 0), fl_round);
+                    A, round_weights(lprev, l, two ? 2 * l : 0));
             }
             SS_CHECK_LAUNCH();
             keys = w.keys;

@@ -344,6 +344,58 @@ def test_dist_prefix_two_level_detection(case):
     assert rounds == r_ref
 
 
+def _deep_mix(n, shared, frac_odd, seed):
+    """Most strings share a `shared`-byte prefix (so the first pass also reads
+    to 256 bytes); a fraction differs early, some are short or end inside the
+    deep rounds, and repeats make duplicates at every depth."""
+    rng = random.Random(seed)
+    pre = bytes(rng.choice(b"ACGT") for _ in range(shared))
+    out = []
+    for k in range(n):
+        u = rng.random()
+        if u < frac_odd:  # differs early, random length
+            out.append(bytes(rng.choice(b"ACGT") for _ in range(rng.randint(0, 90))))
+        elif u < frac_odd + 0.02 and out:  # a repeat of an earlier string
+            out.append(out[rng.randrange(len(out))])
+        else:  # shared prefix, then a tail that ends anywhere up to 400 bytes
+            tail = bytes(rng.choice(b"ACGT") for _ in range(rng.randint(0, 400 - shared)))
+            out.append(pre + tail)
+    return synth.from_list(out)
+
+
+@pytest.mark.parametrize("case", ["deep5", "deep5_bits12", "deep8_init4", "shallow30", "deep_shared100"])
+def test_dist_prefix_deep_first_pass(case):
+    """The first pass's deep form (rounds 128 and 256 read with rounds <= 64)
+    against the oracle: lists where the sample decides for it (and, shallow30,
+    against it), with early finishers, short strings, strings ending inside
+    the deep rounds, repeats, and narrow keys whose collisions decide."""
+    bits, init = 64, 8
+    if case == "deep5":
+        s = _deep_mix(40_000, 150, 0.05, seed=31)
+    elif case == "deep5_bits12":
+        s, bits = _deep_mix(40_000, 150, 0.05, seed=32), 12
+    elif case == "deep8_init4":
+        s, init = _deep_mix(40_000, 140, 0.06, seed=33), 4
+    elif case == "shallow30":
+        s = _deep_mix(40_000, 150, 0.30, seed=34)
+    else:
+        s = _deep_mix(20_000, 300, 0.0, seed=35)
+    _log(f"[dist_prefix deep] {case} n={s.n}")
+    g = s.to(DEV)
+    ss.profile_enable(True)  # (the records name the first-pass kernel that worked)
+    try:
+        d, rounds = ss.dist_prefix(g.bytes, g.offsets, init, bits)
+        torch.cuda.synchronize()
+        ran = ss.profile_report()
+    finally:
+        ss.profile_enable(False)
+    assert ("k_hash_first_deep" in ran) == (case != "shallow30"), sorted(ran)
+    b, o = oracle.strings_np(s)
+    ref, r_ref, coll = oracle.dist_prefix(b, o, init, bits)
+    np.testing.assert_array_equal(u32(d), ref)
+    assert rounds == r_ref
+
+
 # ---------------------------------------------------------- partition / coding
 
 def _partition(s, r, pdms):
