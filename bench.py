@@ -10,8 +10,9 @@ PEs is replaced by runs that already sit in HBM:
   1. approximate distinguishing prefixes by prefix doubling (hash rounds +
      duplicate detection over all strings),
   2. every PE sorts its array and builds its LCP array (one batched launch);
-     steps 1 and 2 are independent: with --overlap, 1 runs on a second
-     stream, driven by a worker thread, while 2 and 3 run (joined before 4),
+     steps 1 and 2 are independent: 1 runs on a second stream, driven by a
+     worker thread, while 2 and 3 run (joined before 4; --serial runs them
+     one after the other on one stream),
   3. regular sampling with sampling factor v = 2: v+1 samples per PE, sorted,
      splitters f_j = V[j|V|/p - 1],
   4. every PE splits its array into p buckets and front-codes the
@@ -40,7 +41,7 @@ HBM_PEAK_GBS = 8000.0
 
 
 class Pipeline:
-    def __init__(self, B, O, p, v, ss, torch, overlap=False):
+    def __init__(self, B, O, p, v, ss, torch, overlap=True):
         self.B, self.O, self.p, self.v, self.ss, self.torch = B, O, p, v, ss, torch
         dev = B.device
         self.overlap = overlap
@@ -324,6 +325,17 @@ def committed_traffic(kernel, args):
     return per
 
 
+def roofline(prof, steps, args):
+    """Roofline object of the kernel with the largest event time."""
+    name = max(prof, key=lambda k: prof[k][0])
+    ms, by, cnt = prof[name]
+    achieved = by / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(name, args),
+            "kernel": name, "launches_per_step": cnt / steps, "avg_launch_ms": ms / max(cnt, 1),
+            "algorithmic_bytes_per_launch": by / max(cnt, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -337,9 +349,9 @@ def main():
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--stages", action="store_true", help="per-stage times on stderr")
-    ap.add_argument("--overlap", action="store_true",
-                    help="run prefix doubling on a second stream beside the sort (per-kernel times then "
-                         "include the other stream's kernels)")
+    ap.add_argument("--serial", action="store_true",
+                    help="run prefix doubling before the sort on one stream (by default it runs on a second "
+                         "stream beside the sort, and per-kernel times include the other stream's kernels)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-per-job leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-profile", action="store_true",
@@ -371,7 +383,7 @@ def main():
     s = synth.dn_strings(args.n, args.length, args.ratio, seed=0, device=dev)
     torch.cuda.synchronize()
     print(f"# generated n={s.n} N={s.N} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    pipe = Pipeline(s.bytes, s.offsets, args.pes, args.sampling, ss, torch, overlap=args.overlap)
+    pipe = Pipeline(s.bytes, s.offsets, args.pes, args.sampling, ss, torch, overlap=not args.serial)
 
     # (the warm-up steps also fill the library's pool of profiling events)
     ss.profile_enable(not args.no_profile)
@@ -413,22 +425,33 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"D/N-ratio strings n={s.n} len={args.length} D/N={args.ratio}",
                    "n": s.n, "N": s.N, "virtual_pes": args.pes, "sampling_factor": args.sampling,
-                   "doubling_rounds": rounds, "streams": 2 if args.overlap else 1},
+                   "doubling_rounds": rounds, "streams": 1 if args.serial else 2},
         "strings_per_s": s.n / dt,
         "hbm_frac_of_N_per_step": s.N / dt / 1e9 / HBM_PEAK_GBS,
         "verified": verified,
     }
     if prof:
-        name = max(prof, key=lambda k: prof[k][0])
-        ms, by, cnt = prof[name]
-        achieved = by / (ms / 1e3) / 1e9 if ms > 0 else 0.0
-        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(name, args),
-                           "kernel": name,
-                           "launches_per_step": cnt / args.steps, "avg_launch_ms": ms / max(cnt, 1),
-                           "algorithmic_bytes_per_launch": by / max(cnt, 1)}
+        out["roofline"] = roofline(prof, args.steps, args)
         out["kernels_ms_per_step"] = {k: v[0] / args.steps for k, v in sorted(prof.items(), key=lambda x: -x[1][0])}
         out["kernels_gbs"] = {k: (v[1] / (v[0] / 1e3) / 1e9 if v[0] > 0 else None) for k, v in prof.items()}
+        if pipe.overlap:
+            # The same kernels with the step on one stream (a few extra steps
+            # after the timed ones): each kernel's time without the other
+            # stream's kernels beside it.
+            pipe.overlap = False
+            pipe.step(Marks(torch, False))
+            torch.cuda.synchronize()
+            ss.profile_enable(True)
+            serial_steps = 3
+            for _ in range(serial_steps):
+                pipe.step(Marks(torch, False))
+            torch.cuda.synchronize()
+            sprof = ss.profile_report()
+            ss.profile_enable(False)
+            pipe.overlap = True
+            out["roofline_one_stream"] = roofline(sprof, serial_steps, args)
+            out["kernels_ms_per_step_one_stream"] = {k: v[0] / serial_steps for k, v in
+                                                     sorted(sprof.items(), key=lambda x: -x[1][0])}
     if args.stages:
         out["stages_ms"] = {k: sum(v) / len(v) for k, v in stages.items()}
     if not args.no_batch:
