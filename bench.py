@@ -349,6 +349,8 @@ def main():
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--stages", action="store_true", help="per-stage times on stderr")
+    ap.add_argument("--no-one-stream", action="store_true",
+                    help="skip the one-stream steps after the timed ones (roofline_one_stream)")
     ap.add_argument("--serial", action="store_true",
                     help="run prefix doubling before the sort on one stream (by default it runs on a second "
                          "stream beside the sort, and per-kernel times include the other stream's kernels)")
@@ -434,7 +436,7 @@ def main():
         out["roofline"] = roofline(prof, args.steps, args)
         out["kernels_ms_per_step"] = {k: v[0] / args.steps for k, v in sorted(prof.items(), key=lambda x: -x[1][0])}
         out["kernels_gbs"] = {k: (v[1] / (v[0] / 1e3) / 1e9 if v[0] > 0 else None) for k, v in prof.items()}
-        if pipe.overlap:
+        if pipe.overlap and not args.no_one_stream:
             # The same kernels with the step on one stream (a few extra steps
             # after the timed ones): each kernel's time without the other
             # stream's kernels beside it.

@@ -197,10 +197,47 @@ __device__ __forceinline__ void flags_commit(u64 *f, u64 mn, u64 mx, u64 sh)
     if (sh) atomicOr((unsigned long long *)&f[2], 1ull);
 }
 
-__global__ void k_flag_init(u64 *f, u32 words)
+__global__ void k_flag_init(u64 *f, u32 words, u32 zero_from)
 {
     const u32 t = threadIdx.x;
-    if (t < words) f[t] = (t % 3 == 0) ? ~0ull : 0ull;
+    if (t < words) f[t] = (t % 3 == 0 && t < zero_from) ? ~0ull : 0ull;
+}
+
+// Whether the first pass should also precompute rounds 128 and 256: at least
+// 90 % of up to 4096 evenly spaced strings are at least 128 bytes long and
+// share their first 64 bytes with the first of them (e.g. strings with a
+// long common prefix).  One thread per sampled string; *count (zeroed before)
+// receives the number that qualify.  Only the amount of bytes read depends on
+// the decision.
+#define DEEP_SAMPLE 4096
+__global__ __launch_bounds__(256) void k_deep_probe(u32 n, const u8 *bytes, u64 N, const u64 *off, u64 *count)
+{
+    const u32 S = n < DEEP_SAMPLE ? n : DEEP_SAMPLE;
+    const u32 k = blockIdx.x * blockDim.x + threadIdx.x;
+    bool same = false;
+    if (k < S) {
+        const u32 i = (u32)((u64)k * n / S);
+        const u64 o0 = off[0], l0 = off[1] - o0;
+        const u64 o = off[i], l = off[i + 1] - o;
+        u64 a[8], b[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) {  // every load first
+            a[q] = l >= 64 ? load_le(bytes, N, o + 8 * q, 8) : 0ull;
+            b[q] = l0 >= 64 ? load_le(bytes, N, o0 + 8 * q, 8) : 0ull;
+        }
+        same = l >= 128 && l0 >= 128;
+#pragma unroll
+        for (int q = 0; q < 8; q++) same = same && a[q] == b[q];
+    }
+    const u64 m = __ballot(same);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd((unsigned long long *)count, (unsigned long long)__popcll(m));
+}
+
+// The deep decision from the probe's count over the sample of n strings.
+__device__ __host__ __forceinline__ bool deep_from_count(u64 count, u32 n)
+{
+    const u64 S = n < DEEP_SAMPLE ? n : DEEP_SAMPLE;
+    return S > 0 && 10ull * count >= 9ull * S;
 }
 
 // Later rounds continue the same sum, G_l = G_lprev + sum_{lprev<=i<l} byte_i
@@ -300,7 +337,7 @@ __global__ __launch_bounds__(256, 4) void k_hash_first(u32 n, const u8 *bytes, u
                                                        u32 bits, BPow bp, FirstW fw, u64 *state, u64 *pre, u64 *fl,
                                                        const u64 *deep)
 {
-    if (deep && *deep) return;  // uniform over the grid
+    if (deep && deep_from_count(*deep, n)) return;  // uniform over the grid
     __shared__ v4i wtab[HF_ACC][2][2][64];  // [accumulator][32-byte block][low/high product][lane]
     __shared__ __attribute__((aligned(16))) u8 rows[4 * HF_ROW];
     __shared__ u64 pwa[4][32];  // per wavefront: copy start (16-aligned, relative) of each string
@@ -528,7 +565,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
 {
     constexpr bool FIRST = MODE != 0;
     if (FIRST) {  // uniform over the grid
-        const bool want = A.deep && *A.deep != 0;
+        const bool want = A.deep && deep_from_count(*A.deep, A.n);
         if (want != (MODE == 2)) return;
     }
     // round weights: [step of the chunk][32-byte block][16-byte half][digit]
@@ -890,30 +927,6 @@ __global__ __launch_bounds__(256, 3) void k_hash_first_deep(PassArgs A, RoundW r
     hash_pass<2>(A, rw, &F);
 }
 
-// Whether the first pass should also precompute rounds 128 and 256: at least
-// 90 % of up to 4096 evenly spaced strings are at least 128 bytes long and
-// share their first 64 bytes with the first of them (e.g. strings with a
-// long common prefix).  Only the amount of bytes read depends on it.
-__global__ __launch_bounds__(1024) void k_deep_probe(u32 n, const u8 *bytes, u64 N, const u64 *off, u64 *flag)
-{
-    __shared__ u32 cnt;
-    const u32 S = n < 4096 ? n : 4096;
-    if (threadIdx.x == 0) cnt = 0;
-    __syncthreads();
-    const u64 o0 = off[0], l0 = off[1] - o0;
-    u32 c = 0;
-    for (u32 k = threadIdx.x; k < S; k += blockDim.x) {
-        const u32 i = (u32)((u64)k * n / S);
-        const u64 o = off[i], l = off[i + 1] - o;
-        bool same = l >= 128 && l0 >= 128;
-        for (u32 q = 0; q < 64 && same; q += 8) same = load_le(bytes, N, o + q, 8) == load_le(bytes, N, o0 + q, 8);
-        c += same ? 1u : 0u;
-    }
-    atomicAdd(&cnt, c);
-    __syncthreads();
-    if (threadIdx.x == 0) flag[0] = (10ull * cnt >= 9ull * S && S > 0) ? 1ull : 0ull;
-}
-
 // ------------------------------------------------------------ duplicates
 //
 // Keys are < 2^61 (residues mod 2^61-1, possibly masked to fewer bits), so the
@@ -1174,10 +1187,12 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
         const bool deep_ok = P.l[c0 - 1] == PRE_MAX;
         const u64 tiles = ceil_div(n, 32);
         const unsigned blocks = (unsigned)(ceil_div(tiles, 4) < 2048 ? ceil_div(tiles, 4) : 2048);
-        k_flag_init<<<1, 64, 0, st>>>(fl_first, 3 * PRE_ALL);
+        // the flags of every precomputed round, then the probe's count (zero)
+        k_flag_init<<<1, 64, 0, st>>>(fl_first, 3 * PRE_ALL + 1, 3 * PRE_ALL);
         SS_CHECK_LAUNCH();
         if (deep_ok) {
-            k_deep_probe<<<1, 1024, 0, st>>>((u32)n, bytes, N, offsets, w.hdr + HDR_DEEP);
+            const u32 S = n < DEEP_SAMPLE ? (u32)n : DEEP_SAMPLE;
+            k_deep_probe<<<(S + 255) / 256, 256, 0, st>>>((u32)n, bytes, N, offsets, w.hdr + HDR_DEEP);
             SS_CHECK_LAUNCH();
         }
         PassArgs A{};
@@ -1212,7 +1227,7 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
         SS_CHECK_LAUNCH();
         u64 F[3 * PRE_ALL + 1];  // the flags of every precomputed round, then the deep word
         SS_TRY(ss_read_u64(fl_first, F, 3 * PRE_ALL + 1, st));
-        if (deep_ok && F[3 * PRE_ALL]) {
+        if (deep_ok && deep_from_count(F[3 * PRE_ALL], (u32)n)) {
             P.l[c0] = 2 * PRE_MAX;
             P.l[c0 + 1] = 4 * PRE_MAX;
             P.count = c0 + 2;
@@ -1269,7 +1284,7 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
                 SS_PROF("k_hash_round", st, 0.0);
                 const u64 tiles = ceil_div(Ah, 32);
                 const u64 nb = ceil_div(tiles, 4);
-                k_flag_init<<<1, 64, 0, st>>>(fl_round, 6);
+                k_flag_init<<<1, 64, 0, st>>>(fl_round, 6, 6);
                 PassArgs A{};
                 A.act = act;
                 A.cnt = ctr + ci;
