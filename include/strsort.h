@@ -226,7 +226,9 @@ size_t ss_partition_encode_workspace(uint64_t n);
  * full strings), splitters as in ss_bucket_bounds.  suf_cap: capacity of suf
  * in bytes (suf_base + N always suffices).  suf_total_host (host, out,
  * nullable): literal bytes written by this call.
- * Errors: CAPACITY if suf_cap is too small, INVALID_ARG if some e_i > d_i. */
+ * Errors: CAPACITY if suf_cap is too small (fc_lcp, fc_len, fc_id, suf_off are
+ * complete; no literal byte is written), INVALID_ARG if some e_i > d_i or
+ * d_i > len. */
 int ss_partition_encode(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
                         const uint32_t *perm, const uint32_t *lcp, const uint32_t *dist,
                         const uint8_t *spl_bytes, uint64_t spl_N, const uint64_t *spl_offsets,

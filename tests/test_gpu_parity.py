@@ -482,6 +482,33 @@ def test_gather_strings_capacity_hint(hint):
     np.testing.assert_array_equal(go.cpu().numpy(), np.cumsum([0] + [len(x) for x in want]))
 
 
+@pytest.mark.parametrize("short_by", [1, 5000])
+def test_partition_encode_capacity(short_by):
+    """A literal buffer shorter than the literals: CAPACITY, no literal byte
+    written, and the metadata and offsets complete."""
+    s = synth.text_strings(20_000, seed=10, median=24)
+    _log(f"[partition] capacity short by {short_by}")
+    g, perm, lcp, dist, ids, sb, so, fc = _partition(s, 4, True)
+    t = fc["total"]
+    cap = t - short_by
+    n = s.n
+    out = dict(run_off=torch.empty_like(fc["run_off"]), lcp=torch.empty_like(fc["lcp"]),
+               len=torch.empty_like(fc["len"]), id=torch.empty_like(fc["id"]),
+               suf_off=torch.empty_like(fc["suf_off"]),
+               suf=torch.full((t + 256,), 0xEE, dtype=torch.uint8, device=DEV))
+    ws = torch.empty(ss.lib().ss_partition_encode_workspace(n), dtype=torch.uint8, device=DEV)
+    rc = ss.lib().ss_partition_encode(ss._p(g.bytes), g.bytes.numel(), ss._p(g.offsets), n, ss._p(perm),
+                                      ss._p(lcp), ss._p(dist), ss._p(sb), sb.numel(), ss._p(so), so.numel(),
+                                      ss._p(out["run_off"]), ss._p(out["lcp"]), ss._p(out["len"]), ss._p(out["id"]),
+                                      ss._p(out["suf_off"]), ss._p(out["suf"]), 0, cap, None, ss._p(ws), ws.numel(),
+                                      ss._stream(g.bytes.device))
+    torch.cuda.synchronize()
+    assert rc == ss.SS_ERR_CAPACITY
+    for k in ("run_off", "lcp", "len", "id", "suf_off"):
+        np.testing.assert_array_equal(out[k].cpu().numpy(), fc[k].cpu().numpy())
+    assert (out["suf"].cpu().numpy() == 0xEE).all()
+
+
 def _check_partition(s, r, pdms):
     _log(f"[partition] n={s.n} r={r} pdms={pdms}")
     g, perm, lcp, dist, ids, sb, so, fc = _partition(s, r, pdms)
