@@ -938,13 +938,75 @@ __device__ __forceinline__ MOp block_mop_exclusive(MOp a, MOp carry)
     return mop_cat(pre, ex);
 }
 
-// Phase 1: the operator of every MS_ITEMS-element block.
+// Phase 1: the operator of every MS_ITEMS-element block.  Its reset, p and m
+// parts need only each element's e and d.  Of its window, byte k (k < 7) is
+// the one written by the block's last element with p <= k (a later element
+// with a larger p keeps it), and the count byte is the last element's, so at
+// most eight literal bytes are read per block instead of every element's.
 __global__ __launch_bounds__(256) void k_mscan_reduce(MScan S, MOp *blk)
 {
-    __shared__ MOp ops[MS_ITEMS];
-    MOp t = mscan_stage(S, (u64)blockIdx.x * MS_ITEMS, ops);
-    t = block_mop_reduce(t);
-    if (threadIdx.x == 0) blk[blockIdx.x] = t;
+    __shared__ u32 rfirst;
+    __shared__ u32 s_last[8];  // per window byte k < 7, and the count (7): last supplier + 1, block-relative
+    const u64 x0 = (u64)blockIdx.x * MS_ITEMS;
+    if (threadIdx.x == 0) rfirst = x0 < S.n_out ? run_of(S.P, S.k, x0) : 0u;
+    if (threadIdx.x < 8) s_last[threadIdx.x] = 0;
+    __syncthreads();
+    RunCur c = run_cur(S, rfirst);
+    MOp t = mop_id();
+    u32 lastk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const u64 xb = x0 + (u64)threadIdx.x * MS_PER;  // this thread's MS_PER consecutive elements
+#pragma unroll
+    for (u32 q = 0; q < MS_PER; q++) {
+        const u64 x = xb + q;
+        if (x >= S.n_out) break;
+        run_seek(S, c, x);
+        const bool start = x == c.pr;
+        const u32 g = (u32)(c.rb + (x - c.pr));
+        const u32 e = start ? 0u : S.V.e[g];
+        const u32 p = e > c.C ? (e - c.C < 7 ? e - c.C : 7u) : 0u;
+        MOp o;
+        o.rp = (start ? 8u : 0u) | p;
+        o.m = start ? 0xFFFFFFFFu : e;
+        o.v = 0;
+        t = mop_cat(t, o);
+        const u32 idx = threadIdx.x * MS_PER + q + 1;
+#pragma unroll
+        for (u32 k = 0; k < 7; k++)
+            if (p <= k) lastk[k] = idx;
+        lastk[7] = idx;
+    }
+#pragma unroll
+    for (u32 k = 0; k < 8; k++)
+        if (lastk[k]) atomicMax(&s_last[k], lastk[k]);
+    t = block_mop_reduce(t);  // (reset, p, m); its window is filled below
+    __shared__ u64 s_v[8];
+    if (threadIdx.x < 8) {
+        const u32 k = threadIdx.x, j = s_last[k];
+        u64 b = 0;
+        if (j) {
+            const u64 x = x0 + j - 1;
+            const RunCur cj = run_cur(S, run_of(S.P, S.k, x));
+            const bool start = x == cj.pr;
+            const u32 g = (u32)(cj.rb + (x - cj.pr));
+            const u32 e = start ? 0u : S.V.e[g];
+            const u32 d = S.V.d[g];
+            const u32 C = cj.C;
+            if (k == 7) {
+                b = d > C ? (d - C < 8 ? d - C : 8u) : 0u;  // the count byte
+            } else if (C + k < d) {  // byte at position C + k of the string (its literal starts at e <= C + k)
+                b = (u64)S.V.suf[S.V.suf_off[g] + (C + k - e)] << (8 * (7 - k));
+            }
+        }
+        s_v[k] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u64 v = 0;
+#pragma unroll
+        for (u32 k = 0; k < 8; k++) v |= s_v[k];
+        t.v = v;
+        blk[blockIdx.x] = t;
+    }
 }
 
 // Phase 2: exclusive scan of the block operators (one workgroup of 1024:
