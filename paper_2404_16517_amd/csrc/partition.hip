@@ -156,44 +156,94 @@ extern "C" int ss_gather_strings(const uint8_t *bytes, uint64_t N, const uint64_
 
 // --------------------------------------------------------------- buckets
 
-// Upper bound of splitter f in the sorted positions [lo, hi): the number of
-// strings <= f.  All strings between the current bounds share
-// min(lcp_lo, lcp_hi) bytes with f, so each comparison starts there.
-__device__ u64 bound_search(const u8 *bytes, u64 N, const u64 *off, const u32 *perm, u64 lo, u64 hi,
-                            const u8 *sb, u64 sN, u64 fo, u64 fl)
+// bounds of set b: run_off[b*(r+1) + j] = set_off[b] + #{ s in set b : s <= f_j }
+// (set_off == NULL: one set [0, n)).  One wavefront per bound: a 9-ary search
+// whose eight pivots per step are compared with f by eight lanes each (64
+// bytes per round, from the LCP that the interval's ends share with f).
+__global__ __launch_bounds__(256) void k_bounds(const u8 *bytes, u64 N, const u64 *off, const u64 *set_off, u64 n,
+                                                u32 nsets, const u32 *perm, const u8 *sb, u64 sN, const u64 *soff,
+                                                u32 r, u64 *bounds)
 {
-    u64 llo = 0, lhi = 0;
-    while (lo < hi) {
-        const u64 mid = (lo + hi) >> 1;
-        const u32 p = perm[mid];
-        const u64 o = off[p], l = off[p + 1] - o;
-        u64 lc;
-        const u64 from = llo < lhi ? llo : lhi;
-        const int c = str_cmp_from(bytes, N, o, l, sb, sN, fo, fl, from, &lc);
-        if (c <= 0) {  // s <= f
-            lo = mid + 1;
-            llo = lc;
-        } else {
-            hi = mid;
-            lhi = lc;
+    const u64 t = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const u32 lane = threadIdx.x & 63, grp = lane >> 3, gl = lane & 7;
+    if (t >= (u64)nsets * (r + 1)) return;  // uniform over the wavefront
+    const u32 b = (u32)(t / (r + 1)), j = (u32)(t % (r + 1));
+    u64 lo = set_off ? set_off[b] : 0, hi = set_off ? set_off[b + 1] : n;
+    if (j == 0 || j == r) {
+        if (lane == 0) bounds[t] = j == 0 ? lo : hi;
+        return;
+    }
+    const u64 fo = soff[j - 1], fl = soff[j] - fo;
+    u64 llo = 0, lhi = 0;  // LCPs of f with the strings just outside [lo, hi)
+    while (lo < hi) {      // uniform over the wavefront
+        const u64 len = hi - lo;
+        const u32 np = len < 8 ? (u32)len : 8u;
+        const bool act = grp < np;
+        const u64 piv = len < 8 ? lo + grp : lo + ((u64)(grp + 1) * len) / 9;  // increasing in grp
+        u64 o = 0, l = 0;
+        if (act) {
+            const u32 p = perm[piv];
+            o = off[p];
+            l = off[p + 1] - o;
+        }
+        const u64 m = l < fl ? l : fl;
+        u64 pos = llo < lhi ? llo : lhi;
+        int cmp = 0;
+        u64 lc = 0;
+        bool done = !act;
+        while (__ballot(!done)) {  // 64-byte rounds until every group has decided
+            u64 mis = ~0ull;
+            int sgn = 0;
+            if (!done) {
+                const u64 q = pos + 8ull * gl;
+                const u32 take = q < m ? (m - q < 8 ? (u32)(m - q) : 8u) : 0u;
+                if (take) {
+                    const u64 wa = load_be(bytes, N, o + q, take), wb = load_be(sb, sN, fo + q, take);
+                    if (wa != wb) {
+                        mis = q + (__clzll(wa ^ wb) >> 3);
+                        sgn = wa < wb ? -1 : 1;
+                    }
+                }
+            }
+            // the group's first mismatch and its sign (the lowest lane that has one)
+#pragma unroll
+            for (u32 d = 1; d < 8; d <<= 1) {
+                const u64 m2 = __shfl_xor(mis, d, 8);
+                const int s2 = __shfl_xor(sgn, d, 8);
+                if (m2 < mis) {
+                    mis = m2;
+                    sgn = s2;
+                }
+            }
+            if (!done) {
+                if (mis != ~0ull) {
+                    lc = mis;
+                    cmp = sgn;
+                    done = true;
+                } else if (pos + 64 >= m) {  // equal up to the shorter length
+                    lc = m;
+                    cmp = l < fl ? -1 : (l > fl ? 1 : 0);
+                    done = true;
+                } else {
+                    pos += 64;
+                }
+            }
+        }
+        // the first pivot above f: the interval between it and the one before
+        const u64 above = __ballot(act && gl == 0 && cmp > 0);
+        const u32 g = above ? (u32)(__builtin_ctzll(above) >> 3) : np;
+        const u64 pg = __shfl(piv, 8 * (g < np ? g : 0)), lg = __shfl(lc, 8 * (g < np ? g : 0));
+        const u64 pb = __shfl(piv, 8 * (g ? g - 1 : 0)), lb = __shfl(lc, 8 * (g ? g - 1 : 0));
+        if (g < np) {
+            hi = pg;
+            lhi = lg;
+        }
+        if (g > 0) {
+            lo = pb + 1;
+            llo = lb;
         }
     }
-    return lo;
-}
-
-// bounds of set b: run_off[b*(r+1) + j] = set_off[b] + #{ s in set b : s <= f_j }
-// (set_off == NULL: one set [0, n))
-__global__ void k_bounds(const u8 *bytes, u64 N, const u64 *off, const u64 *set_off, u64 n, u32 nsets,
-                         const u32 *perm, const u8 *sb, u64 sN, const u64 *soff, u32 r, u64 *bounds)
-{
-    const u64 t = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (u64)nsets * (r + 1)) return;
-    const u32 b = (u32)(t / (r + 1)), j = (u32)(t % (r + 1));
-    const u64 lo = set_off ? set_off[b] : 0, hi = set_off ? set_off[b + 1] : n;
-    if (j == 0) { bounds[t] = lo; return; }
-    if (j == r) { bounds[t] = hi; return; }
-    const u64 fo = soff[j - 1], fl = soff[j] - fo;
-    bounds[t] = bound_search(bytes, N, off, perm, lo, hi, sb, sN, fo, fl);
+    if (lane == 0) bounds[t] = lo;
 }
 
 extern "C" int ss_bucket_bounds(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
@@ -206,8 +256,8 @@ extern "C" int ss_bucket_bounds(const uint8_t *bytes, uint64_t N, const uint64_t
         return SS_ERR_INVALID_ARG;
     }
     hipStream_t st = (hipStream_t)stream;
-    k_bounds<<<(unsigned)ceil_div((u64)r + 1, 256), 256, 0, st>>>(bytes, N, offsets, nullptr, n, 1, perm, spl_bytes,
-                                                                  spl_N, spl_offsets, r, bounds);
+    k_bounds<<<(unsigned)ceil_div((u64)r + 1, 4), 256, 0, st>>>(bytes, N, offsets, nullptr, n, 1, perm, spl_bytes,
+                                                                spl_N, spl_offsets, r, bounds);
     SS_CHECK_LAUNCH();
     return SS_OK;
 }
@@ -351,7 +401,7 @@ static int encode_impl(const uint8_t *bytes, uint64_t N, const uint64_t *offsets
         return SS_ERR_WORKSPACE;
     }
     const u64 nb = (u64)nsets * (r + 1);
-    k_bounds<<<(unsigned)ceil_div(nb, 64), 64, 0, st>>>(bytes, N, offsets, set_off, n, nsets, perm, spl_bytes,
+    k_bounds<<<(unsigned)ceil_div(nb, 4), 256, 0, st>>>(bytes, N, offsets, set_off, n, nsets, perm, spl_bytes,
                                                         spl_N, spl_offsets, r, run_off);
     SS_CHECK_LAUNCH();
     SS_HIP(hipMemsetAsync(bad, 0, sizeof(u32), st));

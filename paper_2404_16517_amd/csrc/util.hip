@@ -246,28 +246,47 @@ __global__ __launch_bounds__(1024) void k_scan_single(T *sums, u64 nb)
     }
 }
 
+// Element (k, t) of a block is item b0 + k*SCAN_NT + t in global memory (so
+// that loads and stores are coalesced) and slot tr(...) of the LDS buffer;
+// each thread scans SCAN_PER consecutive items (blocked layout) from LDS.  One
+// pad slot per SCAN_PER items keeps the blocked reads off a single bank.
+__device__ __forceinline__ u32 scan_slot(u32 idx) { return idx + idx / SCAN_PER; }
+
 template <class T>
 __global__ __launch_bounds__(SCAN_NT) void k_scan_apply(const T *in, T *out, u64 n, const T *sums)
 {
+    __shared__ T buf[SCAN_ITEMS + SCAN_ITEMS / SCAN_PER];
     const u64 b0 = (u64)blockIdx.x * SCAN_ITEMS;
-    // thread t owns items b0 + t*SCAN_PER .. (+SCAN_PER): blocked layout
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; k++) {  // striped, coalesced loads
+        const u32 idx = (u32)k * SCAN_NT + threadIdx.x;
+        const u64 i = b0 + idx;
+        buf[scan_slot(idx)] = (i < n) ? in[i] : (T)0;
+    }
+    __syncthreads();
     T v[SCAN_PER];
     T s = 0;
-    const u64 i0 = b0 + (u64)threadIdx.x * SCAN_PER;
+    const u32 j0 = threadIdx.x * SCAN_PER;  // this thread's consecutive items
 #pragma unroll
     for (int k = 0; k < SCAN_PER; k++) {
-        u64 i = i0 + k;
-        v[k] = (i < n) ? in[i] : (T)0;
+        v[k] = buf[scan_slot(j0 + k)];
         s += v[k];
     }
     T tot;
-    T pre = block_excl_scan<T, SCAN_NT>(s, &tot) + sums[blockIdx.x];
+    T pre = block_excl_scan<T, SCAN_NT>(s, &tot) + sums[blockIdx.x];  // (its barriers order the reads above)
 #pragma unroll
     for (int k = 0; k < SCAN_PER; k++) {
-        u64 i = i0 + k;
-        if (i < n) out[i] = pre;
+        buf[scan_slot(j0 + k)] = pre;
         pre += v[k];
-        if (i + 1 == n) out[n] = pre;
+    }
+    // the last block's last thread holds the total (items past n count as 0)
+    if (threadIdx.x == SCAN_NT - 1 && b0 + SCAN_ITEMS >= n) out[n] = pre;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; k++) {  // striped, coalesced stores
+        const u32 idx = (u32)k * SCAN_NT + threadIdx.x;
+        const u64 i = b0 + idx;
+        if (i < n) out[i] = buf[scan_slot(idx)];
     }
 }
 
