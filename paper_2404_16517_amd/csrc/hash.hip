@@ -331,13 +331,11 @@ __device__ __forceinline__ void lds_le16(const u8 *R, u32 a, u64 &lo, u64 &hi)
 // 0, lane half 0) and 2a + 1 (row set 1, half 1), with the weights of
 // positions past the round's length zero; each lane combines its own digit
 // sums into G of its rounds and writes their keys; the last round's G is the
-// state later rounds continue from.  When the deep word is set the deep
-// first pass does this work (and more), and this kernel returns at once.
+// state later rounds continue from.  (When the deep first pass is chosen it
+// does this work and more, and this kernel is not launched.)
 __global__ __launch_bounds__(256, 4) void k_hash_first(u32 n, const u8 *bytes, u64 N, const u64 *off, PreLens P,
-                                                       u32 bits, BPow bp, FirstW fw, u64 *state, u64 *pre, u64 *fl,
-                                                       const u64 *deep)
+                                                       u32 bits, BPow bp, FirstW fw, u64 *state, u64 *pre, u64 *fl)
 {
-    if (deep && deep_from_count(*deep, n)) return;  // uniform over the grid
     __shared__ v4i wtab[HF_ACC][2][2][64];  // [accumulator][32-byte block][low/high product][lane]
     __shared__ __attribute__((aligned(16))) u8 rows[4 * HF_ROW];
     __shared__ u64 pwa[4][32];  // per wavefront: copy start (16-aligned, relative) of each string
@@ -535,7 +533,6 @@ struct PassArgs {
     u64 *rf;           // flags of rounds l1 (rf[0..2]) and l2 (rf[3..5])
     u64 *pre;          // first pass: keys of precomputed round r at pre[r n + i]
     u64 *fl;           // first pass: flags of precomputed round r at fl[3r ..]
-    const u64 *deep;   // first pass: nonzero word = also precompute rounds l1 and l2
 };
 
 struct FirstArgs {
@@ -558,16 +555,12 @@ struct FirstArgs {
 // round's length zero, and each lane writes the keys of its rounds.  MODE 2
 // (deep: most strings share a long prefix) continues the same read to
 // l2 = 256 and precomputes rounds l1 = 128 and l2 with the round machinery,
-// so such data are read once instead of in two passes.  Both first-pass
-// kernels are launched; the device word *deep lets exactly one of them work.
+// so such data are read once instead of in two passes.  The host reads the
+// probe's count back and launches one of the two first-pass kernels.
 template <int MODE>
 __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, const FirstArgs *Fp)
 {
     constexpr bool FIRST = MODE != 0;
-    if (FIRST) {  // uniform over the grid
-        const bool want = A.deep && deep_from_count(*A.deep, A.n);
-        if (want != (MODE == 2)) return;
-    }
     // round weights: [step of the chunk][32-byte block][16-byte half][digit]
     __shared__ v4i wtab[MODE != 1 ? RW_STEPS * 2 * 2 * 9 : 1];
     // first-pass weights: [accumulator][32-byte block][low/high product][lane]
@@ -662,14 +655,31 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
     const u64 sel2 = 0ull - (u64)two;
     u64 *const keys0 = (u64 *)(((uintptr_t)A.keys2 & sel2) | ((uintptr_t)A.keys1 & ~sel2));
     const u32 nacc = (c0 + 1) / 2;
-    u64 fmn = ~0ull, fmx = 0, fsh = 0;
-    u64 ffmn[HF_ACC], ffmx[HF_ACC], ffsh[HF_ACC];
+    // Flags of this lane's keys, per slot (the first pass's accumulators 0..2,
+    // then the round machinery): the first key seen, and bits 3s (a key was
+    // seen), 3s + 1 (a later key differed from it), 3s + 2 (a string was no
+    // longer than the round) -- all a round's keys are equal iff no lane saw
+    // two different ones and every lane's first key is the same.
+    u64 fk[HF_ACC + 1];
 #pragma unroll
-    for (int a = 0; a < HF_ACC; a++) {
-        ffmn[a] = ~0ull;
-        ffmx[a] = 0;
-        ffsh[a] = 0;
-    }
+    for (int a = 0; a <= HF_ACC; a++) fk[a] = 0;
+    u32 fb = 0;
+    auto note = [&](int slot, u64 key, bool shrt) {
+        const u32 hv = 1u << (3 * slot);
+        const bool seen = (fb & hv) != 0;
+        fb |= hv | ((seen && key != fk[slot]) ? hv << 1 : 0u) | (shrt ? hv << 2 : 0u);
+        fk[slot] = seen ? fk[slot] : key;
+    };
+    // the wavefront half's flags of one slot (as a minimum, maximum and short
+    // flag), committed by its lane 0
+    auto commit = [&](int slot, u64 *f, bool doit) {
+        const u32 b = fb >> (3 * slot);
+        u64 mn = (b & 1) ? ((b & 2) ? 0ull : fk[slot]) : ~0ull;
+        u64 mx = (b & 1) ? ((b & 2) ? ~0ull : fk[slot]) : 0ull;
+        u64 sh = (b >> 2) & 1;
+        flags_reduce32(mn, mx, sh);
+        if (doit) flags_commit(f, mn, mx, sh);
+    };
     const u32 Acnt = FIRST ? A.n : *A.cnt;
     const u32 ntiles = (Acnt + 31) / 32;
     const u32 wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
@@ -840,9 +850,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                             const u64 key = kr_key(Gr, Fp->bp.p[(mr + 3) / 4 + 1], mr, A.bits);
                             A.pre[(u64)r * Acnt + i] = key;
                             if (!deep && r == c0 - 1) A.state[i] = Gr;  // later rounds continue from G
-                            ffmn[a] = key < ffmn[a] ? key : ffmn[a];
-                            ffmx[a] = key > ffmx[a] ? key : ffmx[a];
-                            if (len <= lr) ffsh[a] = 1;
+                            note(a, key, len <= lr);
                         }
                     }
                 }
@@ -872,9 +880,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                     A.state[i_c] = G;
                     keys0[j] = key;
                 }
-                fmn = key < fmn ? key : fmn;
-                fmx = key > fmx ? key : fmx;
-                if (len <= lmine) fsh = 1;
+                note(HF_ACC, key, len <= lmine);
             }
             if (!more) break;
             // advance: the next tile becomes current (its first pass is in flight)
@@ -899,20 +905,16 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
         }
     }
     if (rpart) {
-        flags_reduce32(fmn, fmx, fsh);
-        if (FIRST) {  // rounds l1 (lane half 1) and l2 (half 0) as precomputed rounds c0, c0 + 1
-            if (col == 0) flags_commit(A.fl + 3 * (c0 + (h ? 0u : 1u)), fmn, fmx, fsh);
-        } else {  // A.rf[0..2] round l1, A.rf[3..5] round l2
-            if (lane == 0) flags_commit(A.rf + (two ? 3 : 0), fmn, fmx, fsh);
-            if (lane == 32 && two) flags_commit(A.rf, fmn, fmx, fsh);
-        }
+        if (FIRST)  // rounds l1 (lane half 1) and l2 (half 0) as precomputed rounds c0, c0 + 1
+            commit(HF_ACC, A.fl + 3 * (c0 + (h ? 0u : 1u)), col == 0);
+        else  // A.rf[0..2] round l1, A.rf[3..5] round l2
+            commit(HF_ACC, A.rf + ((two && !h) ? 3 : 0), col == 0 && (!h || two));
     }
     if (FIRST) {
 #pragma unroll
         for (int a = 0; a < HF_ACC; a++) {
-            flags_reduce32(ffmn[a], ffmx[a], ffsh[a]);
             const u32 r = 2 * a + h;
-            if (col == 0 && r < c0) flags_commit(A.fl + 3 * r, ffmn[a], ffmx[a], ffsh[a]);
+            commit(a, A.fl + 3 * r, col == 0 && r < c0);
         }
     }
 }
@@ -1182,7 +1184,7 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
     if (P.count) {
         // The first pass may also precompute the two rounds after 64 bytes
         // (128 and 256) from the same read, when a sample of the strings shows
-        // a long shared prefix; the device decides, the flags read-back tells.
+        // a long shared prefix (the probe's count is read back first).
         const u32 c0 = P.count;
         const bool deep_ok = P.l[c0 - 1] == PRE_MAX;
         const u64 tiles = ceil_div(n, 32);
@@ -1190,10 +1192,17 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
         // the flags of every precomputed round, then the probe's count (zero)
         k_flag_init<<<1, 64, 0, st>>>(fl_first, 3 * PRE_ALL + 1, 3 * PRE_ALL);
         SS_CHECK_LAUNCH();
+        bool deep = false;
         if (deep_ok) {
             const u32 S = n < DEEP_SAMPLE ? (u32)n : DEEP_SAMPLE;
             k_deep_probe<<<(S + 255) / 256, 256, 0, st>>>((u32)n, bytes, N, offsets, w.hdr + HDR_DEEP);
             SS_CHECK_LAUNCH();
+            // the decision is read back so that only the chosen kernel is
+            // launched (an idle launch beside other streams' work would still
+            // wait for room on the compute units)
+            u64 cnt = 0;
+            SS_TRY(ss_read_u64(w.hdr + HDR_DEEP, &cnt, 1, st));
+            deep = deep_from_count(cnt, (u32)n);
         }
         PassArgs A{};
         A.n = (u32)n;
@@ -1207,35 +1216,26 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
         A.state = w.state;
         A.pre = w.pre;
         A.fl = fl_first;
-        A.deep = deep_ok ? w.hdr + HDR_DEEP : nullptr;
         FirstArgs Fa{};
         Fa.P = P;
         Fa.bp = bp;
         Fa.fw = first_weights();
         const RoundW rwd = round_weights(0, 2 * PRE_MAX, 4 * PRE_MAX);
-        {
+        if (!deep) {
             SS_PROF("k_hash_first", st, (double)n * (double)P.l[c0 - 1] + (double)n * (24.0 + 8.0 * c0));
             k_hash_first<<<blocks, 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits, bp, Fa.fw, w.state, w.pre,
-                                                 fl_first, A.deep);
-        }
-        SS_CHECK_LAUNCH();
-        if (deep_ok) {
-            // the bytes are charged once the decision is read back
-            SS_PROF("k_hash_first_deep", st, 0.0);
+                                                 fl_first);
+        } else {
+            SS_PROF("k_hash_first_deep", st, (double)n * (4.0 * PRE_MAX) + (double)n * (24.0 + 8.0 * (c0 + 2)));
             k_hash_first_deep<<<blocks, 256, 0, st>>>(A, rwd, Fa);
         }
         SS_CHECK_LAUNCH();
-        u64 F[3 * PRE_ALL + 1];  // the flags of every precomputed round, then the deep word
-        SS_TRY(ss_read_u64(fl_first, F, 3 * PRE_ALL + 1, st));
-        if (deep_ok && deep_from_count(F[3 * PRE_ALL], (u32)n)) {
+        u64 F[3 * PRE_ALL];  // the flags of every precomputed round
+        SS_TRY(ss_read_u64(fl_first, F, 3 * PRE_ALL, st));
+        if (deep) {
             P.l[c0] = 2 * PRE_MAX;
             P.l[c0 + 1] = 4 * PRE_MAX;
             P.count = c0 + 2;
-            ss_prof_drop_last("k_hash_first");  // (returned at once)
-            ss_prof_add_bytes("k_hash_first_deep",
-                              (double)n * (4.0 * PRE_MAX) + (double)n * (24.0 + 8.0 * (c0 + 2)));
-        } else if (deep_ok) {
-            ss_prof_drop_last("k_hash_first_deep");
         }
         for (u32 r = 0; r < P.count; r++) {
             pf[2 * r] = F[3 * r] != F[3 * r + 1];
