@@ -548,28 +548,27 @@ struct FirstArgs {
 // long runs of one string; the lanes then read their MFMA operands from LDS.
 // The copy of the next pass is issued before the current pass's products.
 //
-// MODE 2: the deep first pass over all strings (MODE 1, the plain first
-// pass, is the standalone k_hash_first).  Its rounds up to 64 bytes come from
-// the first step: accumulator a holds rounds 2a (row set 0, lane
-// half 0) and 2a + 1 (set 1, half 1) with the weights of positions past each
-// round's length zero, and each lane writes the keys of its rounds.  MODE 2
-// (deep: most strings share a long prefix) continues the same read to
-// l2 = 256 and precomputes rounds l1 = 128 and l2 with the round machinery,
-// so such data are read once instead of in two passes.  The host reads the
-// probe's count back and launches one of the two first-pass kernels.
-template <int MODE>
+// FIRST: the deep first pass over all strings (the plain first pass is the
+// standalone k_hash_first).  Its rounds up to 64 bytes come from the first
+// step: accumulator a holds rounds 2a (row set 0, lane half 0) and 2a + 1
+// (set 1, half 1) with the weights of positions past each round's length
+// zero, and each lane writes the keys of its rounds.  It continues the same
+// read to l2 = 256 and precomputes rounds l1 = 128 and l2 with the round
+// machinery, so data whose strings mostly share a long prefix are read once
+// instead of in two passes.  The host reads the probe's count back and
+// launches one of the two first-pass kernels.
+template <bool FIRST>
 __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, const FirstArgs *Fp)
 {
-    constexpr bool FIRST = MODE != 0;
     // round weights: [step of the chunk][32-byte block][16-byte half][digit]
-    __shared__ v4i wtab[MODE != 1 ? RW_STEPS * 2 * 2 * 9 : 1];
+    __shared__ v4i wtab[RW_STEPS * 2 * 2 * 9];
     // first-pass weights: [accumulator][32-byte block][low/high product][lane]
     __shared__ v4i wfirst[FIRST ? HF_ACC * 2 * 2 * 64 : 1];
     __shared__ __attribute__((aligned(16))) u8 rows[4 * RP_ROW];
     __shared__ u64 pwa[4][32];  // per wavefront: pass start (16-aligned, relative) of each string
     __shared__ u32 pwn[4][32];  // ... and its chunk count (0: not copied)
     __shared__ u64 s_ib[16], s_l[PRE_SLOTS];
-    for (u32 e = threadIdx.x; e < (MODE != 1 ? RW_STEPS * 2 * 2 * 9 : 0); e += blockDim.x) {
+    for (u32 e = threadIdx.x; e < RW_STEPS * 2 * 2 * 9; e += blockDim.x) {
         const u32 d = e % 9, kh = (e / 9) & 1, kb = (e / 18) & 1, st = e / 36;
         u32 wd[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -638,14 +637,10 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
     const u32 dr = 4 * (col >> 3) + (col & 3);
     const bool rowl1 = (col & 4) != 0;
     const bool rowlo = dr < 9, rowhi = dr >= 1 && dr < 10;
-    // the round machinery runs in every later round and in a deep first pass
-    constexpr bool deep = MODE == 2;
-    constexpr bool rpart = MODE != 1;
     // positions inside a string fit in 32 bits
-    const bool two = rpart && A.l2 != 0;
+    const bool two = A.l2 != 0;
     const u32 L1 = (u32)A.l1, LP = FIRST ? 0u : (u32)A.lprev;
-    const u32 W = FIRST ? (u32)s_l[c0 - 1] : 0u;  // the longest round up to 64 bytes
-    const u32 lend = rpart ? (two ? (u32)A.l2 : L1) : W;
+    const u32 lend = two ? (u32)A.l2 : L1;
     const u32 lmine = (two && h) ? L1 : lend;  // the round this lane finishes
     // B^(lmine/4 + 1), selected bitwise (a select of the two loads becomes an
     // indexed stack array)
@@ -816,7 +811,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                     const u64 lo7 = l0 & l7, hi7 = h0 & l7, loh = (l0 >> 7) & h1, hih = (h0 >> 7) & h1;
                     xl[kb] = v4i{(int)(u32)lo7, (int)(u32)(lo7 >> 32), (int)(u32)hi7, (int)(u32)(hi7 >> 32)};
                     xh[kb] = v4i{(int)(u32)loh, (int)(u32)(loh >> 32), (int)(u32)hih, (int)(u32)(hih >> 32)};
-                    if (rpart) {
+                    {
                         // this lane's weight row for the block's 16 positions (lane half = 16-byte
                         // half); rows of the l1 set are zero from l1 on (a two-round l1 is a
                         // multiple of 64, so no block straddles it; single rounds do not use it)
@@ -849,13 +844,12 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                             const u32 mr = len < lr ? len : lr;
                             const u64 key = kr_key(Gr, Fp->bp.p[(mr + 3) / 4 + 1], mr, A.bits);
                             A.pre[(u64)r * Acnt + i] = key;
-                            if (!deep && r == c0 - 1) A.state[i] = Gr;  // later rounds continue from G
                             note(a, key, len <= lr);
                         }
                     }
                 }
                 const u32 xn = x + 64;
-                if (rpart && ((xn & 1023) == 0 || xn >= xmax)) {
+                if ((xn & 1023) == 0 || xn >= xmax) {
                     // (half 1: the sum below l1; its rows are zero from l1 on)
                     G = addmod61(G, mulmod61(digits_mod61(S), ibc));
                     S = v16i{};
@@ -867,7 +861,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                 continue;
             }
             // the tile's keys of the round machinery
-            if (rpart && valid && (!h || two)) {
+            if (valid && (!h || two)) {
                 const u32 j = tile * 32 + col;
                 const u32 mm = len < lmine ? len : lmine;
                 const u64 key = kr_key(G, mm == lmine ? blmine : kr_pow((mm + 3) / 4 + 1, rw), mm, A.bits);
@@ -904,12 +898,10 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
             i_nn = entry(tile + 2 * nwaves < ntiles ? tile + 2 * nwaves : tile);
         }
     }
-    if (rpart) {
-        if (FIRST)  // rounds l1 (lane half 1) and l2 (half 0) as precomputed rounds c0, c0 + 1
-            commit(HF_ACC, A.fl + 3 * (c0 + (h ? 0u : 1u)), col == 0);
-        else  // A.rf[0..2] round l1, A.rf[3..5] round l2
-            commit(HF_ACC, A.rf + ((two && !h) ? 3 : 0), col == 0 && (!h || two));
-    }
+    if (FIRST)  // rounds l1 (lane half 1) and l2 (half 0) as precomputed rounds c0, c0 + 1
+        commit(HF_ACC, A.fl + 3 * (c0 + (h ? 0u : 1u)), col == 0);
+    else  // A.rf[0..2] round l1, A.rf[3..5] round l2
+        commit(HF_ACC, A.rf + ((two && !h) ? 3 : 0), col == 0 && (!h || two));
     if (FIRST) {
 #pragma unroll
         for (int a = 0; a < HF_ACC; a++) {
@@ -921,12 +913,12 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
 
 __global__ __launch_bounds__(256, 4) void k_hash_round(PassArgs A, RoundW rw)
 {
-    hash_pass<0>(A, rw, nullptr);
+    hash_pass<false>(A, rw, nullptr);
 }
 
 __global__ __launch_bounds__(256, 3) void k_hash_first_deep(PassArgs A, RoundW rw, FirstArgs F)
 {
-    hash_pass<2>(A, rw, &F);
+    hash_pass<true>(A, rw, &F);
 }
 
 // ------------------------------------------------------------ duplicates
