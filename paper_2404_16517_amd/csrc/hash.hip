@@ -665,15 +665,36 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
         fb |= hv | ((seen && key != fk[slot]) ? hv << 1 : 0u) | (shrt ? hv << 2 : 0u);
         fk[slot] = seen ? fk[slot] : key;
     };
-    // the wavefront half's flags of one slot (as a minimum, maximum and short
-    // flag), committed by its lane 0
-    auto commit = [&](int slot, u64 *f, bool doit) {
+    // The flags of one slot as a minimum, maximum and short flag.  In the
+    // deep first pass each wavefront half's go to LDS and the workgroup's are
+    // committed once per lane half (the few global words take 4x fewer
+    // atomics); round passes commit per wavefront half.
+    __shared__ u64 s_fmn[FIRST ? HF_ACC + 1 : 1][4][2], s_fmx[FIRST ? HF_ACC + 1 : 1][4][2];
+    __shared__ u32 s_fsh[FIRST ? HF_ACC + 1 : 1][4][2];
+    auto stage = [&](int slot) {
         const u32 b = fb >> (3 * slot);
         u64 mn = (b & 1) ? ((b & 2) ? 0ull : fk[slot]) : ~0ull;
         u64 mx = (b & 1) ? ((b & 2) ? ~0ull : fk[slot]) : 0ull;
         u64 sh = (b >> 2) & 1;
         flags_reduce32(mn, mx, sh);
-        if (doit) flags_commit(f, mn, mx, sh);
+        if (col == 0) {
+            s_fmn[slot][wv][h] = mn;
+            s_fmx[slot][wv][h] = mx;
+            s_fsh[slot][wv][h] = (u32)sh;
+        }
+    };
+    auto commit = [&](int slot, u64 *f, bool doit) {  // (after a barrier)
+        if (wv == 0 && col == 0 && doit) {
+            u64 mn = ~0ull, mx = 0, sh = 0;
+#pragma unroll
+            for (int w = 0; w < 4; w++) {
+                const u64 a = s_fmn[slot][w][h], b = s_fmx[slot][w][h];
+                mn = a < mn ? a : mn;
+                mx = b > mx ? b : mx;
+                sh |= s_fsh[slot][w][h];
+            }
+            flags_commit(f, mn, mx, sh);
+        }
     };
     const u32 Acnt = FIRST ? A.n : *A.cnt;
     const u32 ntiles = (Acnt + 31) / 32;
@@ -898,16 +919,25 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
             i_nn = entry(tile + 2 * nwaves < ntiles ? tile + 2 * nwaves : tile);
         }
     }
-    if (FIRST)  // rounds l1 (lane half 1) and l2 (half 0) as precomputed rounds c0, c0 + 1
-        commit(HF_ACC, A.fl + 3 * (c0 + (h ? 0u : 1u)), col == 0);
-    else  // A.rf[0..2] round l1, A.rf[3..5] round l2
-        commit(HF_ACC, A.rf + ((two && !h) ? 3 : 0), col == 0 && (!h || two));
-    if (FIRST) {
+    if constexpr (FIRST) {
+        stage(HF_ACC);
+#pragma unroll
+        for (int a = 0; a < HF_ACC; a++) stage(a);
+        __syncthreads();
+        // rounds l1 (lane half 1) and l2 (half 0) as precomputed rounds c0, c0 + 1
+        commit(HF_ACC, A.fl + 3 * (c0 + (h ? 0u : 1u)), true);
 #pragma unroll
         for (int a = 0; a < HF_ACC; a++) {
             const u32 r = 2 * a + h;
-            commit(a, A.fl + 3 * r, col == 0 && r < c0);
+            commit(a, A.fl + 3 * r, r < c0);
         }
+    } else {  // A.rf[0..2] round l1, A.rf[3..5] round l2, per wavefront half
+        const u32 b = fb >> (3 * HF_ACC);
+        u64 mn = (b & 1) ? ((b & 2) ? 0ull : fk[HF_ACC]) : ~0ull;
+        u64 mx = (b & 1) ? ((b & 2) ? ~0ull : fk[HF_ACC]) : 0ull;
+        u64 sh = (b >> 2) & 1;
+        flags_reduce32(mn, mx, sh);
+        if (col == 0 && (!h || two)) flags_commit(A.rf + ((two && !h) ? 3 : 0), mn, mx, sh);
     }
 }
 
@@ -1219,7 +1249,10 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
                                                  fl_first);
         } else {
             SS_PROF("k_hash_first_deep", st, (double)n * (4.0 * PRE_MAX) + (double)n * (24.0 + 8.0 * (c0 + 2)));
-            k_hash_first_deep<<<blocks, 256, 0, st>>>(A, rwd, Fa);
+            // more, shorter workgroups than the plain pass: beside the other
+            // stream's kernels they give compute units back sooner
+            const unsigned dblocks = (unsigned)(ceil_div(tiles, 4) < 8192 ? ceil_div(tiles, 4) : 8192);
+            k_hash_first_deep<<<dblocks, 256, 0, st>>>(A, rwd, Fa);
         }
         SS_CHECK_LAUNCH();
         u64 F[3 * PRE_ALL];  // the flags of every precomputed round
