@@ -363,14 +363,34 @@ def _deep_mix(n, shared, frac_odd, seed):
     return synth.from_list(out)
 
 
-@pytest.mark.parametrize("case", ["deep5", "deep5_bits12", "deep8_init4", "shallow30", "deep_shared100"])
+def _equal_but_last(n, length, at, seed):
+    """n copies of one string; the last (in input order, so in the last
+    workgroup of the pass) differs at byte `at` (none when at is None)."""
+    rng = random.Random(seed)
+    base = bytes(rng.choice(b"ACGT") for _ in range(length))
+    strs = [base] * n
+    if at is not None:
+        strs[-1] = base[:at] + bytes([base[at] ^ 1]) + base[at + 1:]
+    return synth.from_list(strs)
+
+
+@pytest.mark.parametrize("case", ["deep5", "deep5_bits12", "deep8_init4", "shallow30", "deep_shared100",
+                                  "deep_all_equal", "deep_odd_last20", "deep_odd_last200"])
 def test_dist_prefix_deep_first_pass(case):
     """The first pass's deep form (rounds 128 and 256 read with rounds <= 64)
     against the oracle: lists where the sample decides for it (and, shallow30,
     against it), with early finishers, short strings, strings ending inside
-    the deep rounds, repeats, and narrow keys whose collisions decide."""
+    the deep rounds, repeats, and narrow keys whose collisions decide; and
+    rounds whose keys are all equal, or all equal but one in the last
+    workgroup (the per-workgroup flags must combine across the grid)."""
     bits, init = 64, 8
-    if case == "deep5":
+    if case == "deep_all_equal":
+        s = _equal_but_last(40_000, 300, None, seed=36)
+    elif case == "deep_odd_last20":
+        s = _equal_but_last(40_000, 300, 20, seed=37)
+    elif case == "deep_odd_last200":
+        s = _equal_but_last(40_000, 300, 200, seed=38)
+    elif case == "deep5":
         s = _deep_mix(40_000, 150, 0.05, seed=31)
     elif case == "deep5_bits12":
         s, bits = _deep_mix(40_000, 150, 0.05, seed=32), 12
