@@ -499,7 +499,10 @@ __device__ __forceinline__ int cmp_elem(const FcView &V, u32 gx, u64 kx, u32 gy,
 
 #define MW_NT 256
 #define MW_IPT 8
-#define MW_TILE (MW_NT * MW_IPT)  // outputs per workgroup
+// outputs per workgroup: four short of MW_NT * MW_IPT (the last thread takes
+// four), so that the LDS windows (MW_TILE + 2 entries of 20 bytes) fit four
+// workgroups per compute unit
+#define MW_TILE (MW_NT * MW_IPT - 4)
 
 // co-rank in global memory: number of A elements among the first d outputs
 __device__ u32 corank_global(const MergeLevel &M, u64 A0, u32 na, u64 B0, u32 nb, u32 d, u32 c, u32 C)
