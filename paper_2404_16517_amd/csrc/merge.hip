@@ -873,7 +873,9 @@ __device__ __forceinline__ u32 run_of(const u64 *P, u32 k, u64 x)
     return lo;
 }
 
-#define MS_PER 8
+// 7 elements per thread: the apply kernel's LDS operators (28 KB) then fit
+// five workgroups per compute unit
+#define MS_PER 7
 #define MS_ITEMS (256 * MS_PER)  // elements per workgroup
 
 // The workgroup's operators in LDS, read with consecutive lanes on consecutive
