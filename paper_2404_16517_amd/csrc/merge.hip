@@ -498,11 +498,10 @@ __device__ __forceinline__ int cmp_elem(const FcView &V, u32 gx, u64 kx, u32 gy,
 }
 
 #define MW_NT 256
-#define MW_IPT 8
-// outputs per workgroup: four short of MW_NT * MW_IPT (the last thread takes
-// four), so that the LDS windows (MW_TILE + 2 entries of 20 bytes) fit four
-// workgroups per compute unit
-#define MW_TILE (MW_NT * MW_IPT - 4)
+// 6 outputs per thread: the LDS windows (MW_TILE + 2 entries of 20 bytes,
+// 30.8 KB) and at most 102 VGPRs fit five workgroups per compute unit
+#define MW_IPT 6
+#define MW_TILE (MW_NT * MW_IPT)  // outputs per workgroup
 
 // co-rank in global memory: number of A elements among the first d outputs
 __device__ u32 corank_global(const MergeLevel &M, u64 A0, u32 na, u64 B0, u32 nb, u32 d, u32 c, u32 C)
@@ -560,7 +559,7 @@ __global__ void k_merge_split(MergeLevel M, u32 nblocks, u32 *split)
 // one pair.  Its A and B windows (plus the element before each) are staged in
 // LDS; every thread co-ranks its 8 outputs inside the window and merges them
 // with the LCP rule; outputs are written back through LDS.
-__global__ __launch_bounds__(MW_NT) void k_merge_level(MergeLevel M, u32 nblocks, const u32 *split)
+__global__ __launch_bounds__(MW_NT, 5) void k_merge_level(MergeLevel M, u32 nblocks, const u32 *split)
 {
     __shared__ u32 sG[MW_TILE + 2], sL[MW_TILE + 2], sF[MW_TILE + 2];
     __shared__ u64 sK[MW_TILE + 2];
