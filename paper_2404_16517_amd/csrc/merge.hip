@@ -498,9 +498,9 @@ __device__ __forceinline__ int cmp_elem(const FcView &V, u32 gx, u64 kx, u32 gy,
 }
 
 #define MW_NT 256
-// 6 outputs per thread: the LDS windows (MW_TILE + 2 entries of 20 bytes,
-// 30.8 KB) and at most 102 VGPRs fit five workgroups per compute unit
-#define MW_IPT 6
+// 5 outputs per thread: the LDS windows (MW_TILE + 2 entries of 20 bytes,
+// 25.6 KB) and at most 85 VGPRs fit six workgroups per compute unit
+#define MW_IPT 5
 #define MW_TILE (MW_NT * MW_IPT)  // outputs per workgroup
 
 // co-rank in global memory: number of A elements among the first d outputs
@@ -559,7 +559,7 @@ __global__ void k_merge_split(MergeLevel M, u32 nblocks, u32 *split)
 // one pair.  Its A and B windows (plus the element before each) are staged in
 // LDS; every thread co-ranks its 8 outputs inside the window and merges them
 // with the LCP rule; outputs are written back through LDS.
-__global__ __launch_bounds__(MW_NT, 5) void k_merge_level(MergeLevel M, u32 nblocks, const u32 *split)
+__global__ __launch_bounds__(MW_NT, 6) void k_merge_level(MergeLevel M, u32 nblocks, const u32 *split)
 {
     __shared__ u32 sG[MW_TILE + 2], sL[MW_TILE + 2], sF[MW_TILE + 2];
     __shared__ u64 sK[MW_TILE + 2];
