@@ -531,6 +531,7 @@ struct PassArgs {
     u64 *state;        // G by string index (in: at lprev; out: at the last round)
     u64 *keys1, *keys2;  // round keys by list position
     u64 *rf;           // flags of rounds l1 (rf[0..2]) and l2 (rf[3..5])
+    const v4i *wt;     // deep first pass: the weight tables (round, then first-pass), made by k_hash_weights
     u64 *pre;          // first pass: keys of precomputed round r at pre[r n + i]
     u64 *fl;           // first pass: flags of precomputed round r at fl[3r ..]
 };
@@ -540,6 +541,80 @@ struct FirstArgs {
     BPow bp;
     FirstW fw;
 };
+
+#define WT_ROUND (RW_STEPS * 2 * 2 * 9)  // round weights: [step of the chunk][32-byte block][16-byte half][digit]
+#define WT_FIRST (HF_ACC * 2 * 2 * 64)   // first-pass weights: [accumulator][32-byte block][low/high product][lane]
+
+// Round-weight entry e: the four limbs' 7-bit digit d of the 16 positions of
+// one step's 32-byte block half, as i8 operands.
+__device__ __forceinline__ v4i wtab_entry(u32 e, const RoundW &rw)
+{
+    const u32 d = e % 9, kh = (e / 9) & 1, kb = (e / 18) & 1, st = e / 36;
+    u32 wd[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < 4; q++) {  // the four limbs of the 16 positions
+        const u32 j = 16 * st + 8 * kb + 4 * kh + q;
+        const u64 ib = mulmod61(rw.iblo[j & 15], rw.ibhi[j >> 4]);
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const u32 c = (u32)((rot61(ib, 8 * b) >> (7 * d)) & 127u);
+            wd[q] |= c << (8 * b);
+        }
+    }
+    return v4i{(int)wd[0], (int)wd[1], (int)wd[2], (int)wd[3]};
+}
+
+// First-pass weight entry e (lane ln of accumulator a): the row's round keeps
+// the weights of positions below its length l[r], the rest are zero.
+__device__ __forceinline__ v4i wfirst_entry(u32 e, const u64 *ibs, const u64 *l, u32 c0)
+{
+    const u32 ln = e & 63, hl = (e >> 6) & 1, kb = (e >> 7) & 1, a = e >> 8;
+    const u32 rc = ln & 31, kh = ln >> 5;
+    const u32 dr = 4 * (rc >> 3) + (rc & 3);  // the row's register (digit) in its set
+    const u32 r = 2 * a + ((rc >> 2) & 1);     // the row's round
+    const bool ok = r < c0 && (hl ? (dr >= 1 && dr < 10) : dr < 9);
+    const u32 d = hl ? dr - 1 : dr;
+    const u64 lim = ok ? l[r < PRE_SLOTS ? r : 0] : 0;
+    u32 wd[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const u32 j = 8 * kb + 4 * kh + q;  // limb: positions 4j .. 4j+3
+        const u64 ib = ibs[j];
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const u32 c = (4 * j + b < lim) ? (u32)((rot61(ib, 8 * b) >> (7 * d)) & 127u) : 0u;
+            wd[q] |= c << (8 * b);
+        }
+    }
+    return v4i{(int)wd[0], (int)wd[1], (int)wd[2], (int)wd[3]};
+}
+
+// The deep first pass's weight tables (round weights, then first-pass
+// weights), once per call: wt[WT_ROUND + WT_FIRST].
+__global__ __launch_bounds__(256) void k_hash_weights(RoundW rw, FirstArgs F, v4i *wt)
+{
+    __shared__ u64 s_ib[16], s_l[PRE_SLOTS];
+    const u32 c0 = F.P.count;
+    // kernel-argument arrays are read with constant indices only
+    if (threadIdx.x < 16) {
+        u64 v = 0;
+#pragma unroll
+        for (int k = 0; k < 16; k++)
+            if (threadIdx.x == (u32)k) v = F.fw.ib[k];
+        s_ib[threadIdx.x] = v;
+    }
+    if (threadIdx.x < PRE_SLOTS) {
+        u64 v = 0;
+#pragma unroll
+        for (int k = 0; k < PRE_SLOTS; k++)
+            if (threadIdx.x == (u32)k) v = (u32)k < c0 ? F.P.l[k] : 0;
+        s_l[threadIdx.x] = v;
+    }
+    __syncthreads();
+    const u32 e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < WT_ROUND) wt[e] = wtab_entry(e, rw);
+    else if (e < WT_ROUND + WT_FIRST) wt[e] = wfirst_entry(e - WT_ROUND, s_ib, s_l, c0);
+}
 
 // One pass = RP_STEPS steps of a tile's 32 strings.  Before its products are
 // taken, every string's bytes of the pass are copied into the wavefront's LDS
@@ -561,68 +636,30 @@ template <bool FIRST>
 __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, const FirstArgs *Fp)
 {
     // round weights: [step of the chunk][32-byte block][16-byte half][digit]
-    __shared__ v4i wtab[RW_STEPS * 2 * 2 * 9];
+    __shared__ v4i wtab[WT_ROUND];
     // first-pass weights: [accumulator][32-byte block][low/high product][lane]
-    __shared__ v4i wfirst[FIRST ? HF_ACC * 2 * 2 * 64 : 1];
+    __shared__ v4i wfirst[FIRST ? WT_FIRST : 1];
     __shared__ __attribute__((aligned(16))) u8 rows[4 * RP_ROW];
     __shared__ u64 pwa[4][32];  // per wavefront: pass start (16-aligned, relative) of each string
     __shared__ u32 pwn[4][32];  // ... and its chunk count (0: not copied)
-    __shared__ u64 s_ib[16], s_l[PRE_SLOTS];
-    for (u32 e = threadIdx.x; e < RW_STEPS * 2 * 2 * 9; e += blockDim.x) {
-        const u32 d = e % 9, kh = (e / 9) & 1, kb = (e / 18) & 1, st = e / 36;
-        u32 wd[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int q = 0; q < 4; q++) {  // the four limbs of the 16 positions
-            const u32 j = 16 * st + 8 * kb + 4 * kh + q;
-            const u64 ib = mulmod61(rw.iblo[j & 15], rw.ibhi[j >> 4]);
-#pragma unroll
-            for (int b = 0; b < 4; b++) {
-                const u32 c = (u32)((rot61(ib, 8 * b) >> (7 * d)) & 127u);
-                wd[q] |= c << (8 * b);
-            }
-        }
-        wtab[e] = v4i{(int)wd[0], (int)wd[1], (int)wd[2], (int)wd[3]};
+    __shared__ u64 s_l[PRE_SLOTS];
+    if (FIRST) {  // the same tables for every workgroup: made once per call
+        for (u32 e = threadIdx.x; e < WT_ROUND; e += blockDim.x) wtab[e] = A.wt[e];
+        for (u32 e = threadIdx.x; e < WT_FIRST; e += blockDim.x) wfirst[e] = A.wt[WT_ROUND + e];
+    } else {
+        for (u32 e = threadIdx.x; e < WT_ROUND; e += blockDim.x) wtab[e] = wtab_entry(e, rw);
     }
     u32 c0 = 0;  // precomputed rounds up to 64 bytes (first pass)
     if (FIRST) {
         const FirstArgs &F = *Fp;
         c0 = F.P.count;
         // kernel-argument arrays are read with constant indices only
-        if (threadIdx.x < 16) {
-            u64 v = 0;
-#pragma unroll
-            for (int k = 0; k < 16; k++)
-                if (threadIdx.x == (u32)k) v = F.fw.ib[k];
-            s_ib[threadIdx.x] = v;
-        }
         if (threadIdx.x < PRE_SLOTS) {
             u64 v = 0;
 #pragma unroll
             for (int k = 0; k < PRE_SLOTS; k++)
                 if (threadIdx.x == (u32)k) v = (u32)k < c0 ? F.P.l[k] : 0;
             s_l[threadIdx.x] = v;
-        }
-        __syncthreads();
-        for (u32 e = threadIdx.x; e < HF_ACC * 2 * 2 * 64; e += blockDim.x) {
-            const u32 ln = e & 63, hl = (e >> 6) & 1, kb = (e >> 7) & 1, a = e >> 8;
-            const u32 rc = ln & 31, kh = ln >> 5;
-            const u32 dr = 4 * (rc >> 3) + (rc & 3);  // the row's register (digit) in its set
-            const u32 r = 2 * a + ((rc >> 2) & 1);     // the row's round
-            const bool ok = r < c0 && (hl ? (dr >= 1 && dr < 10) : dr < 9);
-            const u32 d = hl ? dr - 1 : dr;
-            const u64 lim = ok ? s_l[r < PRE_SLOTS ? r : 0] : 0;
-            u32 wd[4] = {0, 0, 0, 0};
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const u32 j = 8 * kb + 4 * kh + q;  // limb: positions 4j .. 4j+3
-                const u64 ib = s_ib[j];
-#pragma unroll
-                for (int b = 0; b < 4; b++) {
-                    const u32 c = (4 * j + b < lim) ? (u32)((rot61(ib, 8 * b) >> (7 * d)) & 127u) : 0u;
-                    wd[q] |= c << (8 * b);
-                }
-            }
-            wfirst[e] = v4i{(int)wd[0], (int)wd[1], (int)wd[2], (int)wd[3]};
         }
     }
     __syncthreads();
@@ -1081,6 +1118,7 @@ __global__ __launch_bounds__(256) void k_dedup(const u64 *keys, int kin, const u
 struct PdWs {
     u32 *actA, *actB, *ctr;
     u64 *hdr, *keys, *keysB, *keysC, *state, *pre, *tab;
+    v4i *wt;
 };
 
 static u32 tab_log(u64 A)
@@ -1099,7 +1137,7 @@ static void pd_layout(u64 n, PdWs *w, WsArena *a, WsCounter *c)
     } while (0)
     PT(actA, u32, n); PT(actB, u32, n); PT(hdr, u64, HDR_WORDS); PT(keys, u64, n); PT(keysB, u64, n);
     PT(keysC, u64, n); PT(state, u64, n);
-    PT(pre, u64, (u64)PRE_ALL * n); PT(tab, u64, 1ull << tab_log(n));
+    PT(pre, u64, (u64)PRE_ALL * n); PT(tab, u64, 1ull << tab_log(n)); PT(wt, v4i, WT_ROUND + WT_FIRST);
 #undef PT
     if (a) w->ctr = (u32 *)w->hdr;
 }
@@ -1252,6 +1290,9 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
             // more, shorter workgroups than the plain pass: beside the other
             // stream's kernels they give compute units back sooner
             const unsigned dblocks = (unsigned)(ceil_div(tiles, 4) < 8192 ? ceil_div(tiles, 4) : 8192);
+            k_hash_weights<<<(WT_ROUND + WT_FIRST + 255) / 256, 256, 0, st>>>(rwd, Fa, w.wt);
+            SS_CHECK_LAUNCH();
+            A.wt = w.wt;
             k_hash_first_deep<<<dblocks, 256, 0, st>>>(A, rwd, Fa);
         }
         SS_CHECK_LAUNCH();
