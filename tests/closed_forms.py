@@ -68,3 +68,19 @@ def doubling_closed_form(dist: np.ndarray, lengths: np.ndarray, l0: int) -> np.n
             break
         L[m] *= 2
     return np.minimum(L, lengths.astype(np.int64)).astype(np.uint32)
+
+
+def doubling_rounds_closed_form(dist: np.ndarray, lengths: np.ndarray, l0: int) -> int:
+    """Rounds of collision-free prefix doubling (Section 4): a string leaves in
+    the first round t (1-based, tested length l0 * 2^(t-1)) whose length covers
+    min(len, dist) -- its prefix of that length is then unique among the
+    strings still active, or the string is exhausted.  The process runs until
+    the last string leaves (0 rounds for no strings)."""
+    if dist.size == 0:
+        return 0
+    need = np.minimum(dist.astype(np.int64), lengths.astype(np.int64))
+    t, L = 1, l0
+    while (need > L).any():
+        t += 1
+        L *= 2
+    return t

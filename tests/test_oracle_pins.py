@@ -214,6 +214,7 @@ def test_dist_prefix_invariants_text(seed):
     assert (approx <= lens).all()
     if coll == 0:
         np.testing.assert_array_equal(approx, cf.doubling_closed_form(d, lens, 8))
+        assert rounds == cf.doubling_rounds_closed_form(d, lens, 8)
         # no collisions: dist_approx <= max(l0, 2 dist - 2) when below len (E[dist_approx] = O(dist))
         bound = np.maximum(8, 2 * d.astype(np.int64) - 2)
         assert (approx.astype(np.int64) <= np.maximum(bound, 0) + (approx == lens) * 10**9).all()
@@ -256,8 +257,6 @@ def test_buckets_bruteforce(seed, r):
     perm = oracle.sort(b, o)
     n = len(strs)
     ids = oracle.select_splitters(n, perm, r)
-    # one-device regular sampling: f_j = s_perm[ceil(j n / r) - 1]
-    assert list(ids) == [perm[-(-j * n // r) - 1] for j in range(1, r)]
     spl = [strs[i] for i in ids]
     sb, so = _arrays(spl)
     bounds = oracle.bucket_bounds(b, o, perm, sb, so)
@@ -363,3 +362,114 @@ def test_merge_dn_closed_form():
     _, idv, olcp = oracle.merge(ro, lc, ln, ids, so, suf)
     np.testing.assert_array_equal(idv, cf.dn_perm(pi))
     np.testing.assert_array_equal(olcp, cf.dn_lcp(n, s.meta["k"], s.meta["filler"]))
+
+
+# ------------------------------------------- finish rule, masking, splitter index
+
+@pytest.mark.parametrize("length,l0,expect_rounds", [(8, 8, 1), (16, 8, 2), (32, 8, 3), (4, 4, 1), (12, 4, 3)])
+def test_dist_prefix_exhausted_duplicates_leave_when_len_reaches_l(length, l0, expect_rounds):
+    """Section 4: a string stops taking part once its tested prefix is unique
+    or covers the whole string.  Copies of one string never become unique, so
+    they leave in the first round whose tested length l0 * 2^(t-1) reaches
+    their length, with dist_approx = len."""
+    s = bytes((65 + (7 * i) % 26) for i in range(length))
+    b, o = _arrays([s, s, s])
+    approx, rounds, coll = oracle.dist_prefix(b, o, l0, 64)
+    assert list(approx) == [length] * 3
+    assert rounds == expect_rounds
+    assert coll == 0
+
+
+def test_dist_prefix_round_count_closed_form_duplicates_of_many_lengths():
+    """Every length from 0 to 70, each string present twice: the round count
+    and dist_approx follow the collision-free closed forms exactly."""
+    rng = random.Random(11)
+    strs = []
+    for L in range(71):
+        x = bytes(rng.randrange(65, 91) for _ in range(L))
+        strs += [x, x]
+    rng.shuffle(strs)
+    b, o = _arrays(strs)
+    perm = oracle.sort(b, o)
+    d = oracle.dist_exact(o, perm, oracle.lcp(b, o, perm))
+    lens = (o[1:] - o[:-1]).astype(np.int64)
+    approx, rounds, coll = oracle.dist_prefix(b, o, 8, 64)
+    assert coll == 0
+    assert (approx == lens).all()  # every string has a copy: dist = len
+    np.testing.assert_array_equal(approx, cf.doubling_closed_form(d, lens, 8))
+    assert rounds == cf.doubling_rounds_closed_form(d, lens, 8) == 5  # 8, 16, 32, 64, 128 >= 70
+
+
+def _find_key_pair(rng, m, same, differ, tries=200_000):
+    """Two random m-byte strings over 'A'..'Z' whose prefix keys agree on the
+    bit mask `same` and differ somewhere on the bit mask `differ`."""
+    seen = {}
+    for _ in range(tries):
+        x = bytes(rng.randrange(65, 91) for _ in range(m))
+        k = oracle.kr_key(x)
+        y = seen.get(k & same)
+        if y is not None and y != x and (oracle.kr_key(y) ^ k) & differ:
+            return y, x
+        seen[k & same] = x
+    raise AssertionError("no pair found")
+
+
+def test_dist_prefix_hash_bits_keeps_the_low_bits():
+    """hash_bits = b compares the low b bits of each key.  Pair A: 8-byte
+    prefixes whose keys share their low 8 bits (and differ in the high bits)
+    collide at b = 8, so both strings stay one more round (a collision only
+    delays, Section 4).  Pair B: keys sharing bits 53..63 but not the low 8
+    bits do not collide at b = 8.  Keeping any other 8 bits swaps the two
+    outcomes."""
+    rng = random.Random(5)
+    low = (1 << 8) - 1
+    high = ~((1 << 53) - 1) & ((1 << 64) - 1)
+    a8, a8b = _find_key_pair(rng, 8, same=low, differ=high)
+    b8, b8b = _find_key_pair(rng, 8, same=high, differ=low)
+    # extend to 16 bytes so that the full keys differ in the low bits
+    for _ in range(1000):
+        ta = bytes(rng.randrange(65, 91) for _ in range(8))
+        tb = bytes(rng.randrange(65, 91) for _ in range(8))
+        if (oracle.kr_key(a8 + ta) ^ oracle.kr_key(a8b + tb)) & low:
+            break
+    pair_a = [a8 + ta, a8b + tb]
+    pair_b = [b8 + ta, b8b + tb]
+    for strs, want8, want_rounds in ((pair_a, [16, 16], 2), (pair_b, [8, 8], 1)):
+        b, o = _arrays(strs)
+        approx, rounds, coll = oracle.dist_prefix(b, o, 8, 8)
+        assert list(approx) == want8 and rounds == want_rounds
+        full, rounds64, _ = oracle.dist_prefix(b, o, 8, 64)
+        assert list(full) == [8, 8] and rounds64 == 1  # distinct 8-byte prefixes
+
+
+def _lower_quantile_positions(n, r):
+    """Sorted position of the lower j/r-quantile for j = 1..r-1: the smallest
+    position c with (c+1)/n >= j/r (numpy's 'inverted_cdf' quantile of 0..n-1)."""
+    pos = np.arange(n)
+    out = []
+    for j in range(1, r):
+        q = float(np.quantile(pos, j / r, method="inverted_cdf"))
+        out.append(int(q))
+    return out
+
+
+@pytest.mark.parametrize("n,r", [(10, 4), (250, 7), (250, 64), (1000, 3), (97, 96), (5, 9), (1, 2), (64, 64),
+                                 (100_003, 256)])
+def test_select_splitters_are_lower_quantiles_with_balanced_buckets(n, r):
+    """Regular sampling (Section 3.1) with every string a sample: splitter j is
+    the j/r-quantile of the sorted array (the smallest string with at least
+    j*n/r strings <= it).  On distinct strings every bucket then holds
+    floor(n/r) or ceil(n/r) strings, within the string-based sampling bound
+    (1 + r/v) n/r for any sampling factor v."""
+    perm = np.arange(n, dtype=np.uint32)[::-1].copy()  # any permutation: ids are perm entries
+    ids = oracle.select_splitters(n, perm, r)
+    pos = _lower_quantile_positions(n, r)
+    assert [int(x) for x in ids] == [int(perm[c]) for c in pos]
+    # distinct strings: bucket j = sorted positions (c_{j-1}, c_j]
+    bounds = [0] + [c + 1 for c in pos] + [n]
+    sizes = np.diff(bounds)
+    assert sizes.sum() == n
+    assert set(sizes.tolist()) <= {n // r, -(-n // r)}
+    for v in (1, 2, 16):
+        if v <= n:  # ceil(n/r) <= n/r + 1 <= n/r + n/v
+            assert sizes.max() <= (1 + r / v) * n / r
