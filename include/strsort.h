@@ -159,11 +159,22 @@ int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, ui
 /* (Synchronises the stream: the number of active strings is read back every
  * round.) */
 
-/* The prefix-doubling key of each string's first min(m, len) bytes, masked to
- * hash_bits (same hash as ss_dist_prefix; exposed so that the hash can be
- * checked on its own).  keys (out, n). */
-int ss_prefix_keys(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
-                   uint32_t m, uint32_t hash_bits, uint64_t *keys, void *stream);
+/* The keys of the first `rounds` prefix-doubling rounds of every string, as
+ * ss_dist_prefix's rounds compute them (Section 4: round t hashes the
+ * l_t-prefix, l_t = init_len * 2^t), with every string kept active:
+ *   keys[t*n + i] (out, rounds*n) = key of s_i[0, min(l_t, len)), masked to
+ *   hash_bits (same hash and arguments as ss_dist_prefix).
+ * first_pass_mode selects the form of the first pass over rounds with
+ * l_t <= 64: 0 = as ss_dist_prefix decides (a sampled probe), 1 = plain (up
+ * to 64 bytes), 2 = deep (also rounds 128 and 256; only when a round of
+ * exactly 64 bytes exists, else plain).  Later rounds go through the round
+ * kernel, two rounds per launch where ss_dist_prefix would also do so.
+ * Exposed so that the hash kernels can be checked key by key.  Uses the
+ * ss_dist_prefix workspace for n.  INVALID_ARG if rounds > 32 or
+ * l_{rounds-1} > 2^31. */
+int ss_doubling_keys(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                     uint32_t init_len, uint32_t hash_bits, uint32_t rounds, uint32_t first_pass_mode,
+                     uint64_t *keys, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------- splitters, buckets, coding */
 

@@ -49,7 +49,7 @@ def lib():
             "ss_dist_exact": ([P, U64, P, P, P, P], I32),
             "ss_dist_prefix_workspace": ([U64], SZ),
             "ss_dist_prefix": ([P, U64, P, U64, U32, U32, P, P, P, SZ, P], I32),
-            "ss_prefix_keys": ([P, U64, P, U64, U32, U32, P, P], I32),
+            "ss_doubling_keys": ([P, U64, P, U64, U32, U32, U32, U32, P, P, SZ, P], I32),
             "ss_select_splitters": ([U64, P, U32, P, P], I32),
             "ss_select_splitters_batch_workspace": ([], SZ),
             "ss_select_splitters_batch": ([P, U64, P, U32, U32, P, P, SZ, P], I32),
@@ -207,10 +207,21 @@ def dist_prefix(bytes_, offsets, init_len: int = 8, hash_bits: int = 64, ws=None
     return out, int(rounds.value)
 
 
-def prefix_keys(bytes_, offsets, m: int, hash_bits: int = 64):
+FIRST_PASS_MODES = {"auto": 0, "plain": 1, "deep": 2}
+
+
+def doubling_keys(bytes_, offsets, init_len: int, rounds: int, hash_bits: int = 64, first_pass: str = "auto",
+                  ws=None):
+    """Keys of the first ``rounds`` prefix-doubling rounds of every string
+    (all strings active): int64 tensor [rounds, n] of the masked keys."""
     b, o, n = _dev_strings(bytes_, offsets)
-    out = torch.empty(max(n, 0), dtype=torch.int64, device=b.device)
-    _check(lib().ss_prefix_keys(_p(b), b.numel(), _p(o), n, m, hash_bits, _p(out), _stream(b.device)))
+    dev = b.device
+    out = torch.empty((max(rounds, 0), max(n, 0)), dtype=torch.int64, device=dev)
+    need = lib().ss_dist_prefix_workspace(n)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, dev)
+    _check(lib().ss_doubling_keys(_p(b), b.numel(), _p(o), n, init_len, hash_bits, rounds,
+                                  FIRST_PASS_MODES[first_pass], _p(out), _p(ws), ws.numel(), _stream(dev)))
     return out
 
 

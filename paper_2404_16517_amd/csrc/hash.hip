@@ -39,42 +39,13 @@ __device__ __forceinline__ u64 addmod61(u64 a, u64 b)
     return r >= KR_P ? r - KR_P : r;
 }
 
-// Extend the Horner state C over bytes [from, m) of the string at `o` (from is
-// a multiple of 4; limbs are 4-byte little-endian, the last zero-padded).
-__device__ __forceinline__ u64 kr_extend(const u8 *bytes, u64 N, u64 o, u64 from, u64 m, u64 C)
-{
-    for (u64 q = from; q < m; q += 8) {
-        const u64 r = m - q;
-        const u32 take = r < 8 ? (u32)r : 8u;
-        const u64 w = load_le(bytes, N, o + q, take);
-        C = addmod61(mulmod61(C, KR_B), w & 0xFFFFFFFFull);
-        if (take > 4) C = addmod61(mulmod61(C, KR_B), w >> 32);  // limbs < 2^32 <= p
-    }
-    return C;
-}
-
-__device__ __forceinline__ u64 kr_finish(u64 C, u64 m, u32 bits)
-{
-    u64 key = addmod61(mulmod61(C, KR_B), m);
-    return bits >= 64 ? key : (key & ((1ull << bits) - 1));
-}
-
-// The same key from the sum G with H = B^L G: (H B + m) = G B^(L+1) + m, so one
-// product with bl1 = B^(L+1).
+// The key of an m-byte prefix from its weighted byte sum G (see the first
+// pass): the Horner value is H = B^L G (L limbs) and the key (H B + m) =
+// G B^(L+1) + m, so one product with bl1 = B^(L+1).
 __device__ __forceinline__ u64 kr_key(u64 G, u64 bl1, u64 m, u32 bits)
 {
     u64 key = addmod61(mulmod61(G, bl1), m);
     return bits >= 64 ? key : (key & ((1ull << bits) - 1));
-}
-
-__global__ __launch_bounds__(256) void k_prefix_keys(const u8 *bytes, u64 N, const u64 *off, u32 n,
-                                                     u64 m, u32 bits, u64 *keys)
-{
-    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const u64 o = off[i], len = off[i + 1] - o;
-    const u64 mm = m < len ? m : len;
-    keys[i] = kr_finish(kr_extend(bytes, N, o, 0, mm, 0), mm, bits);
 }
 
 struct BPow {
@@ -998,9 +969,10 @@ __global__ __launch_bounds__(256, 3) void k_hash_first_deep(PassArgs A, RoundW r
 
 enum { DM_TABLE = 0, DM_ALLDUP = 1, DM_UNIQUE = 2 };
 
-__device__ __forceinline__ u32 tab_slot(u64 key, u32 logT)
+// (64-bit slot arithmetic: tables of 2^32 slots and more, for n > 2^31 keys)
+__device__ __forceinline__ u64 tab_slot(u64 key, u32 logT)
 {
-    return (u32)((key * 0x9E3779B97F4A7C15ull) >> (64 - logT));  // Fibonacci hashing
+    return (key * 0x9E3779B97F4A7C15ull) >> (64 - logT);  // Fibonacci hashing
 }
 
 // Key of active entry j: by list position (hash rounds) or by input index
@@ -1042,9 +1014,9 @@ __global__ __launch_bounds__(256) void k_tab_insert(const u64 *keys, int kin, co
     if (j >= A) return;
     const u32 i = act ? act[j] : j;
     const u64 key = key_of(keys, kin, i, j);
-    const u32 mask = (1u << logT) - 1u;
-    u32 s = tab_slot(key, logT);
-    for (u32 probe = 0; probe <= mask; probe++, s = (s + 1) & mask) {
+    const u64 mask = (1ull << logT) - 1ull;
+    u64 s = tab_slot(key, logT);
+    for (u64 probe = 0; probe <= mask; probe++, s = (s + 1) & mask) {
         u64 cur = __hip_atomic_load(&tab[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (cur == TAB_EMPTY) {
             cur = atomicCAS((unsigned long long *)&tab[s], TAB_EMPTY, key);
@@ -1076,9 +1048,9 @@ __global__ __launch_bounds__(256) void k_dedup(const u64 *keys, int kin, const u
         bool dup = mode == DM_ALLDUP;
         if (mode == DM_TABLE) {
             const u64 key = key_of(keys, kin, i, j);
-            const u32 mask = (1u << logT) - 1u;
-            u32 s = tab_slot(key, logT);
-            for (u32 probe = 0; probe <= mask; probe++, s = (s + 1) & mask) {
+            const u64 mask = (1ull << logT) - 1ull;
+            u64 s = tab_slot(key, logT);
+            for (u64 probe = 0; probe <= mask; probe++, s = (s + 1) & mask) {
                 const u64 v = tab[s];
                 if (v == TAB_EMPTY) break;  // not in the table (cannot happen for an inserted key)
                 if ((v & ~TAB_DUP) == key) {
@@ -1150,21 +1122,6 @@ extern "C" size_t ss_dist_prefix_workspace(uint64_t n)
     return c.used;
 }
 
-extern "C" int ss_prefix_keys(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
-                              uint32_t m, uint32_t hash_bits, uint64_t *keys, void *stream)
-{
-    ss_clear_error();
-    if (n >= 0xFFFFFFFFull) { ss_set_error("n too large"); return SS_ERR_TOO_LARGE; }
-    if (hash_bits < 1 || hash_bits > 64) { ss_set_error("hash_bits must be 1..64"); return SS_ERR_INVALID_ARG; }
-    if (n == 0) return SS_OK;
-    if (!offsets || !keys) { ss_set_error("null pointer"); return SS_ERR_INVALID_ARG; }
-    hipStream_t st = (hipStream_t)stream;
-    k_prefix_keys<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(bytes, N, offsets, (u32)n, (u64)m, hash_bits,
-                                                               keys);
-    SS_CHECK_LAUNCH();
-    return SS_OK;
-}
-
 static u64 host_mulmod(u64 a, u64 b) { return (u64)(((unsigned __int128)a * b) % KR_P); }
 
 static u64 host_powmod(u64 a, u64 e)
@@ -1206,6 +1163,86 @@ static RoundW round_weights(u64 lprev, u64 l1, u64 l2)
     return r;
 }
 
+enum { FP_PROBE = 0, FP_PLAIN = 1, FP_DEEP = 2 };
+
+// The first pass over all n strings: the keys of every round whose prefix
+// length is at most PRE_MAX (and, in the deep form, of the two rounds after
+// it) into w.pre (round r at pre[r n + i]), their flags into the header, and
+// the running sum G at the last precomputed round into w.state.  mode: the
+// probe decides between the plain and the deep form (FP_PROBE; the probe's
+// count is read back), or the caller does.  P receives the precomputed
+// lengths (count 0: init_len > PRE_MAX, nothing launched).
+static int first_pass(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n, uint32_t init_len,
+                      uint32_t hash_bits, PdWs &w, int mode, PreLens &P, hipStream_t st)
+{
+    P = PreLens{};
+    for (u64 L = init_len; L <= PRE_MAX && P.count < PRE_SLOTS; L *= 2) P.l[P.count++] = L;
+    if (!P.count) return SS_OK;
+    BPow bp;
+    bp.p[0] = 1;
+    for (int t = 1; t < 32; t++) bp.p[t] = (u64)(((unsigned __int128)bp.p[t - 1] * KR_B) % KR_P);
+    u64 *fl_first = w.hdr + HDR_FIRST;
+    const u32 c0 = P.count;
+    // the deep form also precomputes the two rounds after 64 bytes (128 and
+    // 256) from the same read; it needs a round of exactly 64 bytes
+    const bool deep_ok = P.l[c0 - 1] == PRE_MAX;
+    const u64 tiles = ceil_div(n, 32);
+    const unsigned blocks = (unsigned)(ceil_div(tiles, 4) < 2048 ? ceil_div(tiles, 4) : 2048);
+    // the flags of every precomputed round, then the probe's count (zero)
+    k_flag_init<<<1, 64, 0, st>>>(fl_first, 3 * PRE_ALL + 1, 3 * PRE_ALL);
+    SS_CHECK_LAUNCH();
+    bool deep = mode == FP_DEEP && deep_ok;
+    if (mode == FP_PROBE && deep_ok) {
+        // deep when a sample of the strings shows a long shared prefix; the
+        // decision is read back so that only the chosen kernel is launched (an
+        // idle launch beside other streams' work would still wait for room on
+        // the compute units)
+        const u32 S = n < DEEP_SAMPLE ? (u32)n : DEEP_SAMPLE;
+        k_deep_probe<<<(S + 255) / 256, 256, 0, st>>>((u32)n, bytes, N, offsets, w.hdr + HDR_DEEP);
+        SS_CHECK_LAUNCH();
+        u64 cnt = 0;
+        SS_TRY(ss_read_u64(w.hdr + HDR_DEEP, &cnt, 1, st));
+        deep = deep_from_count(cnt, (u32)n);
+    }
+    PassArgs A{};
+    A.n = (u32)n;
+    A.bytes = bytes;
+    A.N = N;
+    A.off = offsets;
+    A.lprev = 0;
+    A.l1 = 2 * PRE_MAX;
+    A.l2 = 4 * PRE_MAX;
+    A.bits = hash_bits;
+    A.state = w.state;
+    A.pre = w.pre;
+    A.fl = fl_first;
+    FirstArgs Fa{};
+    Fa.P = P;
+    Fa.bp = bp;
+    Fa.fw = first_weights();
+    if (!deep) {
+        SS_PROF("k_hash_first", st, (double)n * (double)P.l[c0 - 1] + (double)n * (24.0 + 8.0 * c0));
+        k_hash_first<<<blocks, 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits, bp, Fa.fw, w.state, w.pre,
+                                             fl_first);
+        SS_CHECK_LAUNCH();
+    } else {
+        const RoundW rwd = round_weights(0, 2 * PRE_MAX, 4 * PRE_MAX);
+        k_hash_weights<<<(WT_ROUND + WT_FIRST + 255) / 256, 256, 0, st>>>(rwd, Fa, w.wt);
+        SS_CHECK_LAUNCH();
+        A.wt = w.wt;
+        // more, shorter workgroups than the plain pass: beside the other
+        // stream's kernels they give compute units back sooner
+        const unsigned dblocks = (unsigned)(ceil_div(tiles, 4) < 8192 ? ceil_div(tiles, 4) : 8192);
+        SS_PROF("k_hash_first_deep", st, (double)n * (4.0 * PRE_MAX) + (double)n * (24.0 + 8.0 * (c0 + 2)));
+        k_hash_first_deep<<<dblocks, 256, 0, st>>>(A, rwd, Fa);
+        SS_CHECK_LAUNCH();
+        P.l[c0] = 2 * PRE_MAX;
+        P.l[c0 + 1] = 4 * PRE_MAX;
+        P.count = c0 + 2;
+    }
+    return SS_OK;
+}
+
 extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
                               uint32_t init_len, uint32_t hash_bits, uint32_t *dist_approx,
                               uint32_t *rounds_host, void *ws, size_t ws_bytes, void *stream)
@@ -1239,70 +1276,11 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
     SS_CHECK_LAUNCH();
     // rounds whose prefix length is at most PRE_MAX are hashed in one first pass
     PreLens P{};
-    for (u64 L = init_len; L <= PRE_MAX && P.count < PRE_SLOTS; L *= 2) P.l[P.count++] = L;
     u32 pf[2 * PRE_ALL] = {};
+    SS_TRY(first_pass(bytes, N, offsets, n, init_len, hash_bits, w, FP_PROBE, P, st));
     if (P.count) {
-        // The first pass may also precompute the two rounds after 64 bytes
-        // (128 and 256) from the same read, when a sample of the strings shows
-        // a long shared prefix (the probe's count is read back first).
-        const u32 c0 = P.count;
-        const bool deep_ok = P.l[c0 - 1] == PRE_MAX;
-        const u64 tiles = ceil_div(n, 32);
-        const unsigned blocks = (unsigned)(ceil_div(tiles, 4) < 2048 ? ceil_div(tiles, 4) : 2048);
-        // the flags of every precomputed round, then the probe's count (zero)
-        k_flag_init<<<1, 64, 0, st>>>(fl_first, 3 * PRE_ALL + 1, 3 * PRE_ALL);
-        SS_CHECK_LAUNCH();
-        bool deep = false;
-        if (deep_ok) {
-            const u32 S = n < DEEP_SAMPLE ? (u32)n : DEEP_SAMPLE;
-            k_deep_probe<<<(S + 255) / 256, 256, 0, st>>>((u32)n, bytes, N, offsets, w.hdr + HDR_DEEP);
-            SS_CHECK_LAUNCH();
-            // the decision is read back so that only the chosen kernel is
-            // launched (an idle launch beside other streams' work would still
-            // wait for room on the compute units)
-            u64 cnt = 0;
-            SS_TRY(ss_read_u64(w.hdr + HDR_DEEP, &cnt, 1, st));
-            deep = deep_from_count(cnt, (u32)n);
-        }
-        PassArgs A{};
-        A.n = (u32)n;
-        A.bytes = bytes;
-        A.N = N;
-        A.off = offsets;
-        A.lprev = 0;
-        A.l1 = 2 * PRE_MAX;
-        A.l2 = 4 * PRE_MAX;
-        A.bits = hash_bits;
-        A.state = w.state;
-        A.pre = w.pre;
-        A.fl = fl_first;
-        FirstArgs Fa{};
-        Fa.P = P;
-        Fa.bp = bp;
-        Fa.fw = first_weights();
-        const RoundW rwd = round_weights(0, 2 * PRE_MAX, 4 * PRE_MAX);
-        if (!deep) {
-            SS_PROF("k_hash_first", st, (double)n * (double)P.l[c0 - 1] + (double)n * (24.0 + 8.0 * c0));
-            k_hash_first<<<blocks, 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits, bp, Fa.fw, w.state, w.pre,
-                                                 fl_first);
-        } else {
-            SS_PROF("k_hash_first_deep", st, (double)n * (4.0 * PRE_MAX) + (double)n * (24.0 + 8.0 * (c0 + 2)));
-            // more, shorter workgroups than the plain pass: beside the other
-            // stream's kernels they give compute units back sooner
-            const unsigned dblocks = (unsigned)(ceil_div(tiles, 4) < 8192 ? ceil_div(tiles, 4) : 8192);
-            k_hash_weights<<<(WT_ROUND + WT_FIRST + 255) / 256, 256, 0, st>>>(rwd, Fa, w.wt);
-            SS_CHECK_LAUNCH();
-            A.wt = w.wt;
-            k_hash_first_deep<<<dblocks, 256, 0, st>>>(A, rwd, Fa);
-        }
-        SS_CHECK_LAUNCH();
         u64 F[3 * PRE_ALL];  // the flags of every precomputed round
-        SS_TRY(ss_read_u64(fl_first, F, 3 * PRE_ALL, st));
-        if (deep) {
-            P.l[c0] = 2 * PRE_MAX;
-            P.l[c0 + 1] = 4 * PRE_MAX;
-            P.count = c0 + 2;
-        }
+        SS_TRY(ss_read_u64(w.hdr + HDR_FIRST, F, 3 * PRE_ALL, st));
         for (u32 r = 0; r < P.count; r++) {
             pf[2 * r] = F[3 * r] != F[3 * r + 1];
             pf[2 * r + 1] = F[3 * r + 2] != 0;
@@ -1465,5 +1443,75 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
         }
     }
     if (rounds_host) *rounds_host = rounds;
+    return SS_OK;
+}
+
+// The keys of the first `rounds` doubling rounds for every string, as the
+// rounds of ss_dist_prefix compute them (first pass, then round passes), with
+// every string kept active: keys[t n + i] = key of s_i[0, min(l_t, len)).
+extern "C" int ss_doubling_keys(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                                uint32_t init_len, uint32_t hash_bits, uint32_t rounds, uint32_t first_pass_mode,
+                                uint64_t *keys, void *ws, size_t ws_bytes, void *stream)
+{
+    ss_clear_error();
+    if (n >= 0xFFFFFFFFull) { ss_set_error("n too large"); return SS_ERR_TOO_LARGE; }
+    if (init_len == 0 || (init_len % 4) != 0) {
+        ss_set_error("init_len must be a positive multiple of 4");
+        return SS_ERR_INVALID_ARG;
+    }
+    if (hash_bits < 8 || hash_bits > 64) { ss_set_error("hash_bits must be 8..64"); return SS_ERR_INVALID_ARG; }
+    if (first_pass_mode > FP_DEEP) { ss_set_error("first_pass_mode must be 0, 1 or 2"); return SS_ERR_INVALID_ARG; }
+    if (rounds > 32 || ((u64)init_len << (rounds ? rounds - 1 : 0)) > (1ull << 31)) {
+        ss_set_error("too many rounds");
+        return SS_ERR_INVALID_ARG;
+    }
+    if (n == 0 || rounds == 0) return SS_OK;
+    if (!offsets || !keys) { ss_set_error("null pointer"); return SS_ERR_INVALID_ARG; }
+    hipStream_t st = (hipStream_t)stream;
+    WsArena a(ws, ws_bytes);
+    PdWs w;
+    pd_layout(n, &w, &a, nullptr);
+    if (a.overflow || !ws) {
+        ss_set_error("workspace too small: need %zu bytes", ss_dist_prefix_workspace(n));
+        return SS_ERR_WORKSPACE;
+    }
+    PreLens P{};
+    SS_TRY(first_pass(bytes, N, offsets, n, init_len, hash_bits, w, (int)first_pass_mode, P, st));
+    u32 t = 0;
+    for (; t < P.count && t < rounds; t++)
+        SS_HIP(hipMemcpyAsync(keys + (u64)t * n, w.pre + (u64)t * n, sizeof(u64) * n, hipMemcpyDeviceToDevice, st));
+    // the rounds after the first pass hash every string; two rounds per
+    // launch where the round kernel allows it (as after a round that finished
+    // nothing), so that both launch forms are exercised
+    k_store_u32<<<1, 1, 0, st>>>(w.ctr, (u32)n);
+    SS_CHECK_LAUNCH();
+    u64 lprev = P.count ? P.l[P.count - 1] : 0;
+    u64 l = (u64)init_len << t;
+    while (t < rounds) {
+        const bool two = lprev > 0 && l % 64 == 0 && t + 1 < rounds;
+        k_flag_init<<<1, 64, 0, st>>>(w.hdr + HDR_ROUND, 6, 6);
+        SS_CHECK_LAUNCH();
+        PassArgs A{};
+        A.act = nullptr;
+        A.cnt = w.ctr;
+        A.bytes = bytes;
+        A.N = N;
+        A.off = offsets;
+        A.lprev = lprev;
+        A.l1 = l;
+        A.l2 = two ? 2 * l : 0;
+        A.bits = hash_bits;
+        A.state = w.state;
+        A.keys1 = keys + (u64)t * n;
+        A.keys2 = two ? keys + (u64)(t + 1) * n : nullptr;
+        A.rf = w.hdr + HDR_ROUND;
+        const u64 nb = ceil_div(ceil_div(n, 32), 4);
+        k_hash_round<<<(unsigned)(nb < 1024 ? nb : 1024), 256, 0, st>>>(A, round_weights(lprev, l, two ? 2 * l : 0));
+        SS_CHECK_LAUNCH();
+        const u32 done = two ? 2 : 1;
+        lprev = l << (done - 1);
+        l <<= done;
+        t += done;
+    }
     return SS_OK;
 }

@@ -557,7 +557,7 @@ __global__ void k_merge_split(MergeLevel M, u32 nblocks, u32 *split)
 
 // One merge level, merge-path style: each workgroup produces MW_TILE outputs of
 // one pair.  Its A and B windows (plus the element before each) are staged in
-// LDS; every thread co-ranks its 8 outputs inside the window and merges them
+// LDS; every thread co-ranks its MW_IPT outputs inside the window and merges them
 // with the LCP rule; outputs are written back through LDS.
 __global__ __launch_bounds__(MW_NT, 6) void k_merge_level(MergeLevel M, u32 nblocks, const u32 *split)
 {

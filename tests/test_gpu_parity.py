@@ -233,7 +233,9 @@ def test_sort_batch_with_empty_and_single_sets():
 
 # ------------------------------------------------------------- prefix doubling
 
-def test_prefix_keys_match_golden_vectors():
+def test_doubling_keys_match_golden_vectors():
+    """Every round's key of the frozen vectors, through the matrix-core passes
+    (plain and deep first pass, then round passes up to 4096 bytes)."""
     path = os.path.join(os.path.dirname(__file__), "golden", "kr_vectors.txt")
     data, keys = [], []
     for line in open(path):
@@ -242,19 +244,49 @@ def test_prefix_keys_match_golden_vectors():
         h, k = line.split()
         data.append(bytes.fromhex(h) if h != "-" else b"")
         keys.append(int(k, 16))
+    assert max(len(x) for x in data) <= 4096
     g = synth.from_list(data).to(DEV)
-    got = u64(ss.prefix_keys(g.bytes, g.offsets, 0xFFFFFFFF, 64))
-    assert [int(x) for x in got] == keys
+    for mode in ("plain", "deep"):
+        got = ss.doubling_keys(g.bytes, g.offsets, 4, 11, 64, first_pass=mode)  # l = 4 .. 4096
+        last = u64(got[-1])
+        assert [int(x) for x in last] == keys, mode
+        for t in range(11):
+            l = 4 << t
+            assert [int(x) for x in u64(got[t])] == [oracle.kr_key(x[:l]) for x in data], (mode, t)
 
 
-@pytest.mark.parametrize("m", [0, 1, 4, 7, 8, 9, 16, 33])
-def test_prefix_keys_truncated_match_oracle(m):
-    s = synth.text_strings(500, seed=9, median=20)
-    strs = s.as_list()
-    g = s.to(DEV)
-    got = u64(ss.prefix_keys(g.bytes, g.offsets, m, 64))
-    exp = [oracle.kr_key(x[:m]) for x in strs]
-    assert [int(x) for x in got] == exp
+def _key_strings(seed):
+    """Text strings of mixed lengths (up to 2100 bytes) plus strings sharing
+    long prefixes, at every alignment of the byte buffer."""
+    rng = random.Random(seed)
+    strs = synth.text_strings(1500, seed=seed, median=30).as_list()
+    strs += [b"Q" * rng.randint(0, 300) + bytes(rng.randrange(256) for _ in range(rng.randint(0, 40)))
+             for _ in range(400)]
+    strs += [bytes(rng.randrange(256) for _ in range(rng.randint(1000, 2100))) for _ in range(60)]
+    strs += [b"", b"\x00", b"\xff" * 64, b"\x00" * 129]
+    rng.shuffle(strs)
+    return strs
+
+
+@pytest.mark.parametrize("mode", ["plain", "deep", "auto"])
+@pytest.mark.parametrize("init_len,bits", [(8, 64), (4, 64), (16, 20), (12, 64), (64, 8)])
+def test_doubling_keys_key_for_key(mode, init_len, bits):
+    """Keys of the first pass (plain or deep), the single-round and the
+    two-round passes equal the oracle's Karp-Rabin keys of each prefix, masked
+    to the low ``bits`` bits, for every string and round."""
+    strs = _key_strings(init_len + bits)
+    for lead in (0, 3):  # shift every string's alignment
+        g = synth.from_list([b"#" * lead] + strs).to(DEV)
+        rounds = 0
+        while (init_len << rounds) < 2400:
+            rounds += 1
+        got = ss.doubling_keys(g.bytes, g.offsets, init_len, rounds, bits, first_pass=mode)
+        mask = (1 << bits) - 1 if bits < 64 else (1 << 64) - 1
+        allstr = [b"#" * lead] + strs
+        for t in range(rounds):
+            l = init_len << t
+            exp = [oracle.kr_key(x[:l]) & mask for x in allstr]
+            assert [int(x) for x in u64(got[t])] == exp, (lead, t, l)
 
 
 def _deep_mixed(seed):
