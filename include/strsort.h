@@ -279,6 +279,28 @@ int ss_fc_decode(uint32_t k, const uint64_t *run_off, const uint32_t *fc_lcp,
                  uint64_t *out_offsets, uint8_t *out_bytes, uint64_t out_cap, void *ws,
                  size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): ss_fc_decode without a
+ * caller workspace and without any host read-back or allocation.  Its scratch
+ * is a static device array of the library (36 MiB, one copy per GPU, held
+ * until the process ends); n is limited to SS_FC_DECODE_NOALLOC_MAX entries
+ * (TOO_LARGE beyond, checked before anything is enqueued).  Arguments and
+ * outputs as in ss_fc_decode, except that the data-dependent checks are
+ * reported on the device instead of by the return value:
+ *   status (device, 1 word, out): 0 = decoded; 1 = malformed runs (nothing
+ *   decoded); 2 = the decoded bytes exceed out_cap (out_offsets is complete,
+ *   no byte is written).
+ * The call is asynchronous on `stream` (whose device must be the current
+ * device).  Every call on one GPU uses that GPU's one scratch array, which
+ * keeps the last call's contents: calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.  The
+ * first call on a device looks the array's device address up. */
+#define SS_FC_DECODE_NOALLOC_MAX (1u << 22)
+int ss_fc_decode_noalloc(uint32_t k, const uint64_t *run_off, const uint32_t *fc_lcp,
+                         const uint32_t *fc_len, const uint64_t *suf_off, const uint8_t *suf, uint64_t n,
+                         uint64_t *out_offsets, uint8_t *out_bytes, uint64_t out_cap, uint32_t *status,
+                         void *stream);
+
 /* ---------------------------------------------------------------- merge */
 
 /* Workspace bytes for ss_lcp_merge of n_out merged strings drawn from front-

@@ -66,6 +66,7 @@ def lib():
             "ss_profile_query": ([ctypes.c_char_p, P, P, P], I32),
             "ss_profile_names": ([ctypes.c_char_p, SZ], SZ),
             "ss_fc_decode": ([U32, P, P, P, P, P, U64, P, P, U64, P, SZ, P], I32),
+            "ss_fc_decode_noalloc": ([U32, P, P, P, P, P, U64, P, P, U64, P, P], I32),
             "ss_lcp_merge_workspace": ([U64, U64, U32], SZ),
             "ss_lcp_merge": ([U32, P, P, U32, P, U64, P, P, P, P, P, P, P, P, P, U64, P, P, SZ, P], I32),
             "ss_dist_exact_bounded": ([P, P, P, U64, P, P], I32),
@@ -372,6 +373,20 @@ def fc_decode(run_off, fc_lcp, fc_len, suf_off, suf):
     _check(lib().ss_fc_decode(k, _p(run_off), _p(fc_lcp), _p(fc_len), _p(suf_off), _p(suf), n, _p(out_off),
                               _p(out), total, _p(ws), ws.numel(), _stream(dev)))
     return out[:total], out_off
+
+
+SS_FC_DECODE_NOALLOC_MAX = 1 << 22
+
+
+def fc_decode_noalloc(run_off, fc_lcp, fc_len, suf_off, suf, out_offsets, out_bytes, status):
+    """ss_fc_decode_noalloc into caller-supplied outputs (the library allocates
+    nothing).  ``status`` is an int32 device tensor of one element: 0 decoded,
+    1 malformed runs, 2 capacity (``out_bytes.numel()``) exceeded."""
+    dev = fc_lcp.device
+    n = fc_lcp.numel()
+    k = run_off.numel() - 1
+    _check(lib().ss_fc_decode_noalloc(k, _p(run_off), _p(fc_lcp), _p(fc_len), _p(suf_off), _p(suf), n,
+                                      _p(out_offsets), _p(out_bytes), out_bytes.numel(), _p(status), _stream(dev)))
 
 
 def lcp_merge(run_begin, run_end, group_off, fc_lcp, fc_len, fc_id, suf_off, suf, ws=None, n_out=None,

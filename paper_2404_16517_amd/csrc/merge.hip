@@ -22,6 +22,8 @@
 #include <algorithm>
 #include <vector>
 
+#include <mutex>
+
 #include "common.hpp"
 
 #define PSV_NONE 0xFFFFFFFFu
@@ -42,6 +44,14 @@ __global__ __launch_bounds__(256) void k_check_runs(const u64 *run_off, u32 k, c
         if (e[i] > d[i]) atomicOr(bad, 4u);
         if (i > 0 && e[i] > d[i - 1]) atomicOr(bad, 4u);
     }
+}
+
+// p[0..count) = v (a kernel rather than hipMemsetAsync, so that a captured
+// graph holds no memset node).
+__global__ void k_fill_u32(u32 *p, u32 v, u32 count)
+{
+    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
 }
 
 #define PB 1024  // psv block (one workgroup)
@@ -213,7 +223,10 @@ static int psv_build(const u32 *e, u64 n, u32 *psv, u32 *T, u32 *cm, u32 *farl, 
     if (n == 0) return SS_OK;
     const u32 nb = (u32)ceil_div(n, PB);
     const u32 P = psv_leaves(n);
-    if (P > nb) SS_HIP(hipMemsetAsync(T + P + nb, 0xFF, sizeof(u32) * (P - nb), st));
+    if (P > nb) {
+        k_fill_u32<<<(unsigned)ceil_div(P - nb, 256), 256, 0, st>>>(T + P + nb, 0xFFFFFFFFu, P - nb);
+        SS_CHECK_LAUNCH();
+    }
     {
         SS_PROF("k_psv_block", st, (double)n * 8.0);  // e in, psv out
         k_psv_block<<<nb, PB, 0, st>>>(e, (u32)n, psv, T, P, cm, farl, fcnt);
@@ -239,13 +252,12 @@ static int psv_build(const u32 *e, u64 n, u32 *psv, u32 *T, u32 *cm, u32 *farl, 
 #define DC_NT 256
 #define DC_PER 16
 
-// Decoded bytes, 16 per thread, in output order.
-__global__ __launch_bounds__(DC_NT) void k_decode(const u32 *e, const u32 *d, const u64 *suf_off,
-                                                  const u8 *suf, const u32 *psv, u32 n, const u64 *out_off,
-                                                  u64 total, u8 *out)
+// Decoded bytes of output chunk c0 .. c0 + DC_NT*DC_PER, 16 per thread, in
+// output order (called by the whole workgroup; range is LDS).
+__device__ __forceinline__ void decode_chunk(u64 c0, const u32 *e, const u32 *d, const u64 *suf_off, const u8 *suf,
+                                             const u32 *psv, u32 n, const u64 *out_off, u64 total, u8 *out,
+                                             u32 *range)
 {
-    __shared__ u32 range[2];
-    const u64 c0 = (u64)blockIdx.x * DC_NT * DC_PER;
     const u64 c1 = (c0 + DC_NT * DC_PER < total) ? c0 + DC_NT * DC_PER : total;
     if (threadIdx.x < 2) {
         const u64 q = threadIdx.x == 0 ? c0 : c1 - 1;
@@ -259,7 +271,7 @@ __global__ __launch_bounds__(DC_NT) void k_decode(const u32 *e, const u32 *d, co
     }
     __syncthreads();
     const u64 q0 = c0 + (u64)threadIdx.x * DC_PER;
-    if (q0 >= c1) return;
+    if (q0 >= c1) return;  // (after the only barrier)
     u32 lo = range[0], hi = range[1] + 1;
     while (hi - lo > 1) {
         u32 mid = (lo + hi) >> 1;
@@ -305,6 +317,36 @@ __global__ __launch_bounds__(DC_NT) void k_decode(const u32 *e, const u32 *d, co
     }
 }
 
+__global__ __launch_bounds__(DC_NT) void k_decode(const u32 *e, const u32 *d, const u64 *suf_off,
+                                                  const u8 *suf, const u32 *psv, u32 n, const u64 *out_off,
+                                                  u64 total, u8 *out)
+{
+    __shared__ u32 range[2];
+    decode_chunk((u64)blockIdx.x * DC_NT * DC_PER, e, d, suf_off, suf, psv, n, out_off, total, out, range);
+}
+
+// The same with the total read on the device (out_off[n]) and the chunks
+// taken in a grid-stride loop; nothing is written unless *status is 0.
+__global__ __launch_bounds__(DC_NT) void k_decode_dev(const u32 *e, const u32 *d, const u64 *suf_off,
+                                                      const u8 *suf, const u32 *psv, u32 n, const u64 *out_off,
+                                                      const u32 *status, u8 *out)
+{
+    __shared__ u32 range[2];
+    if (*status != 0) return;
+    const u64 total = out_off[n];
+    for (u64 c0 = (u64)blockIdx.x * DC_NT * DC_PER; c0 < total; c0 += (u64)gridDim.x * DC_NT * DC_PER) {
+        decode_chunk(c0, e, d, suf_off, suf, psv, n, out_off, total, out, range);
+        __syncthreads();  // range is rewritten by the next chunk
+    }
+}
+
+// status = 0 (runs well formed, decoded bytes fit), 1 (malformed runs) or 2
+// (more decoded bytes than cap).
+__global__ void k_decode_status(const u32 *bad, const u64 *out_off, u32 n, u64 cap, u32 *status)
+{
+    *status = *bad ? 1u : (out_off[n] > cap ? 2u : 0u);
+}
+
 __global__ void k_widen(const u32 *d, u32 n, u64 *out)
 {
     const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -341,7 +383,8 @@ static void dec_layout(u64 n, DecWs *w, WsArena *a, WsCounter *c)
 static int decode_impl(u32 k, const u64 *run_off, const u32 *e, const u32 *d, const u64 *suf_off, const u8 *suf,
                        u64 n, u64 *out_off, u8 *out, u64 out_cap, DecWs &w, hipStream_t st)
 {
-    SS_HIP(hipMemsetAsync(w.bad, 0, sizeof(u32), st));
+    k_fill_u32<<<1, 64, 0, st>>>(w.bad, 0u, 1);
+    SS_CHECK_LAUNCH();
     const u64 grid = ceil_div((n > k ? n : k) + 1, 256);
     k_check_runs<<<(unsigned)grid, 256, 0, st>>>(run_off, k, e, d, (u32)n, w.bad);
     SS_CHECK_LAUNCH();
@@ -399,6 +442,97 @@ extern "C" int ss_fc_decode(uint32_t k, const uint64_t *run_off, const uint32_t 
     }
     return decode_impl(k, run_off, fc_lcp, fc_len, suf_off, suf, n, out_offsets, out_bytes, out_cap, w,
                        (hipStream_t)stream);
+}
+
+// ------------------------------------------------ allocation-free decode
+//
+// ss_fc_decode_noalloc keeps its scratch in one static device array per GPU
+// (the code object's copy on each device) instead of a caller workspace.  In
+// host code the array's name is only a stand-in: its device address is
+// looked up once per device with hipGetSymbolAddress (on the call's first
+// use of that device, with the device current) and only that address is
+// passed to kernels.  Calls on one device share the array: calls that
+// overlap on one GPU (different streams, or threads) race.
+
+#define FCD_NOALLOC_SCRATCH_BYTES (36u << 20)
+static __device__ __align__(256) unsigned char scratch[FCD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int FCD_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[FCD_MAX_DEVICES] = {};
+
+int scratch_address(void **out)
+{
+    int dev = 0;
+    SS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= FCD_MAX_DEVICES) {
+        ss_set_error("device index %d beyond %d", dev, FCD_MAX_DEVICES);
+        return SS_ERR_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            ss_set_error("hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+            return SS_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SS_OK;
+}
+}  // namespace
+
+extern "C" int ss_fc_decode_noalloc(uint32_t k, const uint64_t *run_off, const uint32_t *fc_lcp,
+                                    const uint32_t *fc_len, const uint64_t *suf_off, const uint8_t *suf,
+                                    uint64_t n, uint64_t *out_offsets, uint8_t *out_bytes, uint64_t out_cap,
+                                    uint32_t *status, void *stream)
+{
+    ss_clear_error();
+    if (n > SS_FC_DECODE_NOALLOC_MAX) {
+        ss_set_error("fc_decode_noalloc: n = %llu exceeds the limit of %u entries", (unsigned long long)n,
+                     (unsigned)SS_FC_DECODE_NOALLOC_MAX);
+        return SS_ERR_TOO_LARGE;
+    }
+    if (k == 0 || !run_off || !out_offsets || !status || (n > 0 && (!fc_lcp || !fc_len || !suf_off))) {
+        ss_set_error("fc_decode_noalloc: bad arguments");
+        return SS_ERR_INVALID_ARG;
+    }
+    if (ss_fc_decode_workspace(n) > FCD_NOALLOC_SCRATCH_BYTES) {  // (cannot happen below the limit)
+        ss_set_error("fc_decode_noalloc: scratch too small for n = %llu", (unsigned long long)n);
+        return SS_ERR_TOO_LARGE;
+    }
+    void *base = nullptr;
+    SS_TRY(scratch_address(&base));
+    hipStream_t st = (hipStream_t)stream;
+    WsArena a(base, FCD_NOALLOC_SCRATCH_BYTES);
+    DecWs w;
+    dec_layout(n, &w, &a, nullptr);
+    const u32 *e = fc_lcp, *d = fc_len;
+    // w.bad starts at zero on every call (the array keeps the last call's contents)
+    k_fill_u32<<<1, 64, 0, st>>>(w.bad, 0u, 1);
+    SS_CHECK_LAUNCH();
+    const u64 grid = ceil_div((n > k ? n : k) + 1, 256);
+    k_check_runs<<<(unsigned)grid, 256, 0, st>>>(run_off, k, e, d, (u32)n, w.bad);
+    SS_CHECK_LAUNCH();
+    if (n > 0) {
+        k_widen<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(d, (u32)n, out_offsets);
+        SS_CHECK_LAUNCH();
+    }
+    SS_TRY(ss_scan_exclusive<u64>(out_offsets, out_offsets, n, w.scratch, st));
+    k_decode_status<<<1, 1, 0, st>>>(w.bad, out_offsets, (u32)n, out_cap, status);
+    SS_CHECK_LAUNCH();
+    if (n == 0 || out_cap == 0) return SS_OK;
+    // the psv chains only read e (any values are safe); bytes are decoded
+    // only when the status is 0
+    SS_TRY(psv_build(e, n, w.psv, w.tree, w.cmin, w.far, w.fcnt, st));
+    const u64 chunks = ceil_div(out_cap, (u64)DC_NT * DC_PER);
+    k_decode_dev<<<(unsigned)(chunks < 4096 ? chunks : 4096), DC_NT, 0, st>>>(e, d, suf_off, suf, w.psv, (u32)n,
+                                                                            out_offsets, status, out_bytes);
+    SS_CHECK_LAUNCH();
+    return SS_OK;
 }
 
 // ----------------------------------------------------------------- merge
