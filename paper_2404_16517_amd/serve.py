@@ -7,7 +7,9 @@ each on its own HIP stream driven by its own host thread (the C-ABI releases
 the GIL), so their kernels overlap on the device.  Requests that do not fit yet
 wait; later, smaller ones may be admitted ahead of them (backfill) as long as
 the head of the queue has waited less than ``max_bypass`` admissions.  Results
-stay on the device.  Latency is arrival -> results ready.
+stay on the device and stay charged to the budget (with the request's input
+strings) until they are released; a finished job gives back only its
+workspace.  Latency is arrival -> results ready.
 
 The scheduling logic (``Scheduler``) is pure host code and is tested without a
 GPU; ``serve_trace`` runs it with the real executor.
@@ -23,8 +25,9 @@ from dataclasses import dataclass, field
 class Job:
     rid: int
     arrival_s: float
-    mem_bytes: int
+    mem_bytes: int          # everything the job holds while it runs
     payload: object = None
+    result_bytes: int = 0   # the part still held after it finishes (input + outputs), until release
     admitted_s: float | None = None
     done_s: float | None = None
     result: object = None
@@ -39,6 +42,7 @@ class Scheduler:
     max_bypass: int = 8
     used_bytes: int = 0
     running: dict = field(default_factory=dict)
+    held: dict = field(default_factory=dict)
     queue: list = field(default_factory=list)
     _bypassed: int = 0
 
@@ -66,17 +70,33 @@ class Scheduler:
         return out
 
     def finish(self, job: Job):
+        """The job's work is done: its workspace goes back to the budget; its
+        input and results stay charged until ``release``."""
         del self.running[job.rid]
-        self.used_bytes -= job.mem_bytes
+        self.used_bytes -= job.mem_bytes - job.result_bytes
+        self.held[job.rid] = job
+
+    def release(self, job: Job):
+        """The caller is done with the job's results (and input)."""
+        del self.held[job.rid]
+        self.used_bytes -= job.result_bytes
+
+    def stuck(self) -> bool:
+        """Nothing runs, yet the head of the queue cannot start: only releases
+        of held results can make room."""
+        return bool(self.queue) and not self.running and \
+            self.used_bytes + self.queue[0].mem_bytes > self.budget_bytes
 
 
-def job_mem_bytes(n: int, N: int) -> int:
-    """Device memory of one sort job: its strings, outputs and workspaces."""
+def job_bytes(n: int, N: int) -> tuple[int, int]:
+    """(device bytes while running, bytes still held after finishing) of one
+    sort job: its input strings and outputs are held until release, its
+    workspace only while it runs."""
     import paper_2404_16517_amd as ss
     L = ss.lib()
-    outputs = n * (4 + 4 + 4 + 4)  # perm, lcp, dist, dist_approx
+    held = N + 8 * (n + 1) + n * (4 + 4 + 4 + 4)  # input; perm, lcp, dist, dist_approx
     ws = max(L.ss_sort_workspace(n), L.ss_dist_prefix_workspace(n))
-    return N + 8 * (n + 1) + outputs + ws
+    return held + ws, held
 
 
 def run_job(strings, stream, ws=None):
@@ -91,26 +111,42 @@ def run_job(strings, stream, ws=None):
     return perm, lcp, dist, dpx
 
 
-def serve_trace(requests, inputs, budget_bytes: int, slots: int = 4, time_scale: float = 1.0):
+def serve_trace(requests, inputs, budget_bytes: int, slots: int = 4, time_scale: float = 1.0,
+                keep_results: bool = False, on_done=None):
     """Replay a request trace.  ``inputs[rid]`` is the request's device string set.
-    Returns (jobs, makespan_s)."""
+
+    ``on_done(job)`` (optional) is called by the job's worker thread once its
+    results are ready, e.g. to consume them; the results are then released
+    (the caller's hand-back), unless ``keep_results``: then they stay on the
+    device and charged to the budget until the trace ends, and a head request
+    that can never fit raises.  Returns (jobs, makespan_s)."""
     import torch
     sched = Scheduler(budget_bytes, slots)
     streams = [torch.cuda.Stream() for _ in range(slots)]
     free_streams = list(range(slots))
     lock = threading.Condition()
     done_events = []
-    jobs = {r.rid: Job(r.rid, r.arrival_s * time_scale,
-                       job_mem_bytes(inputs[r.rid].n, inputs[r.rid].N), inputs[r.rid]) for r in requests}
+    jobs = {}
+    for r in requests:
+        mem, held = job_bytes(inputs[r.rid].n, inputs[r.rid].N)
+        jobs[r.rid] = Job(r.rid, r.arrival_s * time_scale, mem, inputs[r.rid], held)
     pending = sorted(jobs.values(), key=lambda j: j.arrival_s)
     t0 = time.perf_counter()
     threads = []
+    errors = []
 
     def worker(job, sidx):
-        job.result = run_job(job.payload, streams[sidx])
+        try:
+            job.result = run_job(job.payload, streams[sidx])
+            if on_done is not None:
+                on_done(job)
+        except BaseException as exc:  # reported after the trace
+            errors.append(exc)
         with lock:
             job.done_s = time.perf_counter() - t0
             sched.finish(job)
+            if not keep_results:
+                sched.release(job)
             free_streams.append(sidx)
             done_events.append(job.rid)
             lock.notify_all()
@@ -129,6 +165,8 @@ def serve_trace(requests, inputs, budget_bytes: int, slots: int = 4, time_scale:
                 th = threading.Thread(target=worker, args=(job, sidx), daemon=True)
                 threads.append(th)
                 th.start()
+            if sched.stuck():
+                raise RuntimeError("budget held by kept results: the next request can never be admitted")
             finished = len(done_events)
             if finished >= len(jobs):
                 break
@@ -139,6 +177,8 @@ def serve_trace(requests, inputs, budget_bytes: int, slots: int = 4, time_scale:
             finished = len(done_events)
     for th in threads:
         th.join()
+    if errors:
+        raise errors[0]
     makespan = max(j.done_s for j in jobs.values()) - min(j.arrival_s for j in jobs.values())
     return list(jobs.values()), makespan
 

@@ -53,6 +53,7 @@ _ST_DUPJ = 0x32
 _ST_BYTE = 0x41
 _ST_SETLEN = 0x51
 _ST_SETBYTE = 0x52
+_ST_RUN = 0x61
 
 
 def _lsr(x: torch.Tensor, k: int) -> torch.Tensor:
@@ -301,6 +302,13 @@ def random_sets(num_sets: int, size_lo: float, size_hi: float, len_lo: int = 8, 
         ctr = torch.arange(b0, b1, dtype=torch.int64, device=dev)
         out[b0:b1] = (65 + _u32(seed, _ST_SETBYTE, ctr) % 26).to(torch.uint8)
     return StringSet(out, offsets, {"kind": "sets", "sizes": sizes}), bounds
+
+
+def random_runs(n: int, k: int, seed: int = 0, device="cpu") -> torch.Tensor:
+    """A uniformly random run index in [0, k) for each of n strings (the k-way
+    merge workload: strings dealt to k runs at random)."""
+    idx = torch.arange(n, dtype=torch.int64, device=torch.device(device))
+    return _u32(seed, _ST_RUN, idx) % k
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,132 @@
+"""GPU parity at the workloads' full sizes.
+
+At these sizes the oracle cannot redo the whole computation within a test, so
+each case is checked by what the oracle can compute one by one or by
+properties that hold at any size:
+
+* text strings, 50M (log-normal lengths, Zipf bytes, 20% duplicates): the
+  sorted order and LCP array by the oracle's linear-time check of every
+  adjacent pair; exact dist from them; prefix doubling by its collision-free
+  closed forms (dist_approx and the round count);
+* the k-way merge, 256 front-coded runs of 64M D/N strings of 64 bytes
+  (D/N 0.3), built from the D/N closed forms: the merged order and LCPs equal
+  the closed forms, with full strings and with distinguishing prefixes only;
+* 4096 independent sets of 1e3..1e6 strings (lengths 8..256): every set with
+  index = 0 mod 64, the smallest and the largest against the oracle's sort.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2404_16517_amd as ss
+import synth
+from tests import closed_forms as cf
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def test_text_50M_sort_lcp_and_prefix_doubling():
+    n = 50_000_000
+    _log("[full] text 50M: generate")
+    s = synth.text_strings(n, seed=0, device=DEV)
+    perm, lcp = ss.sort(s.bytes, s.offsets)
+    dpx, rounds = ss.dist_prefix(s.bytes, s.offsets, 8, 64)
+    torch.cuda.synchronize()
+    _log("[full] text 50M: check")
+    b = s.bytes.cpu().numpy()
+    o = s.offsets.cpu().numpy().view(np.uint64)
+    del s
+    p, l = u32(perm), u32(lcp)
+    assert oracle.check_sorted(b, o, p, l) == -1
+    dist = oracle.dist_exact(o, p, l)
+    lens = (o[1:] - o[:-1]).astype(np.int64)
+    d = u32(dpx)
+    assert (d >= dist).all()
+    np.testing.assert_array_equal(d, cf.doubling_closed_form(dist, lens, 8))
+    assert rounds == cf.doubling_rounds_closed_form(dist, lens, 8)
+
+
+def _dn_runs_front_coded(n, length, ratio, k, seed, pdms):
+    """k sorted front-coded runs of D/N strings dealt at random, from the
+    closed forms (order by pi, LCP from common base-26 digits); d = len, or the
+    collision-free doubling result in the PDMS variant.  Torch on the device."""
+    s = synth.dn_strings(n, length, ratio, seed=seed, device=DEV)
+    K, F = s.meta["k"], s.meta["filler"]
+    pi = s.meta["pi"].to(DEV)
+    run = synth.random_runs(n, k, seed, device=DEV)
+    ids = torch.sort(run * (1 << 32) + pi).indices           # runs in order, each sorted by pi
+    run_off = torch.zeros(k + 1, dtype=torch.int64, device=DEV)
+    run_off[1:] = torch.cumsum(torch.bincount(run, minlength=k), 0)
+    pv = pi[ids]
+    a, c = pv[:-1], pv[1:]
+    common = torch.zeros(n - 1, dtype=torch.int64, device=DEV)
+    alive = torch.ones(n - 1, dtype=torch.bool, device=DEV)
+    for dgt in range(K):
+        p = 26 ** (K - 1 - dgt)
+        alive &= (a // p) % 26 == (c // p) % 26
+        common += alive
+    e = torch.zeros(n, dtype=torch.int64, device=DEV)
+    e[1:] = F + common
+    e[run_off[:-1][run_off[:-1] < n]] = 0
+    dist = F + K  # every string's distinguishing prefix
+    dlen = min(length, 8 * 2 ** int(np.ceil(np.log2(dist / 8)))) if pdms else length
+    d = torch.full((n,), dlen, dtype=torch.int64, device=DEV)
+    lit = d - e
+    suf_off = torch.zeros(n + 1, dtype=torch.int64, device=DEV)
+    suf_off[1:] = torch.cumsum(lit, 0)
+    suf = torch.empty(int(suf_off[-1]), dtype=torch.uint8, device=DEV)
+    step = 1 << 22
+    for q0 in range(0, n, step):
+        q1 = min(n, q0 + step)
+        L = lit[q0:q1]
+        pos = torch.repeat_interleave(torch.arange(q0, q1, device=DEV), L)
+        t = torch.arange(int(suf_off[q0]), int(suf_off[q1]), device=DEV) - suf_off[pos]
+        suf[int(suf_off[q0]):int(suf_off[q1])] = s.bytes[ids[pos] * length + e[pos] + t]
+    i32 = lambda x: x.to(torch.int32)
+    return s, run_off, i32(e), i32(d), i32(ids), suf_off, suf
+
+
+@pytest.mark.parametrize("pdms", [False, True])
+def test_merge_256_runs_of_64M_dn_strings(pdms):
+    n, k = 64_000_000, 256
+    _log(f"[full] merge 256 runs x 64M, pdms={pdms}: build runs")
+    s, run_off, e, d, ids, suf_off, suf = _dn_runs_front_coded(n, 64, 0.3, k, 3, pdms)
+    assert (s.meta["k"], s.meta["filler"]) == (6, 13)
+    _log("[full] merge")
+    _, gid, glcp = ss.lcp_merge_runs(run_off, e, d, ids, suf_off, suf)
+    torch.cuda.synchronize()
+    pi = s.meta["pi"].numpy()
+    np.testing.assert_array_equal(u32(gid), cf.dn_perm(pi))
+    np.testing.assert_array_equal(u32(glcp), cf.dn_lcp(n, 6, 13))
+
+
+def test_4096_sets_of_1e3_to_1e6_strings_sampled_against_the_oracle():
+    _log("[full] 4096 sets: generate")
+    s, bounds = synth.random_sets(4096, 1e3, 1e6, 8, 256, seed=0, device=DEV)
+    sizes = np.diff(bounds.numpy())
+    n = int(bounds[-1])
+    _log(f"[full] 4096 sets: n={n} N={s.N}: sort")
+    perm, lcp = ss.sort_batch(s.bytes, s.offsets, bounds.to(DEV))
+    torch.cuda.synchronize()
+    pick = sorted(set(range(0, 4096, 64)) | {int(np.argmin(sizes)), int(np.argmax(sizes))})
+    assert sizes.min() >= 1000 and sizes.max() <= 1_000_000
+    offs = s.offsets
+    for j in pick:
+        a, c = int(bounds[j]), int(bounds[j + 1])
+        b0, b1 = int(offs[a]), int(offs[c])
+        b = s.bytes[b0:b1].cpu().numpy()
+        o = (offs[a:c + 1] - b0).cpu().numpy().view(np.uint64)
+        p_ref = oracle.sort(b, o)
+        np.testing.assert_array_equal(u32(perm[a:c]), p_ref, err_msg=f"set {j}")
+        np.testing.assert_array_equal(u32(lcp[a:c]), oracle.lcp(b, o, p_ref), err_msg=f"set {j}")
+    _log(f"[full] 4096 sets: {len(pick)} sets checked")

@@ -61,3 +61,31 @@ def test_deterministic_replay_of_a_poisson_trace():
 def test_percentile():
     assert percentile([1, 2, 3, 4], 0.5) == 2.5
     assert percentile([5], 0.99) == 5
+
+
+def test_results_stay_charged_until_released():
+    s = Scheduler(budget_bytes=100, slots=4)
+    a, b = Job(0, 0.0, 60, result_bytes=20), Job(1, 0.0, 50, result_bytes=10)
+    s.submit(a)
+    s.submit(b)
+    assert [j.rid for j in s.admissible()] == [0]      # 60 + 50 > 100
+    s.finish(a)
+    assert s.used_bytes == 20                           # workspace back, results held
+    assert [j.rid for j in s.admissible()] == [1]      # 20 + 50 <= 100
+    s.finish(b)
+    assert s.used_bytes == 30 and set(s.held) == {0, 1}
+    s.release(a)
+    s.release(b)
+    assert s.used_bytes == 0 and not s.held
+
+
+def test_stuck_when_held_results_block_the_head():
+    s = Scheduler(budget_bytes=100, slots=2)
+    a = Job(0, 0.0, 90, result_bytes=80)
+    s.submit(a)
+    s.admissible()
+    s.finish(a)                                        # 80 still held
+    s.submit(Job(1, 0.0, 30))
+    assert s.admissible() == [] and s.stuck()
+    s.release(a)
+    assert not s.stuck() and [j.rid for j in s.admissible()] == [1]
