@@ -90,6 +90,25 @@ int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uin
                   const uint64_t *set_off, uint32_t num_sets, uint32_t *perm, uint32_t *lcp,
                   uint32_t flags, void *ws, size_t ws_bytes, void *stream);
 
+/* The batched sort with the rounds driven from the device, for capture in a
+ * graph (ss_graph_begin / ss_graph_end) and for callers that must not wait on
+ * the host: the same result as ss_sort_batch, with nothing read back and
+ * nothing allocated; every launch has a fixed shape.  `rounds` sort rounds
+ * (each of up to 8 radix levels) are enqueued; a round resolves at least 7
+ * more bytes of every string it keeps, so ss_sort_batch_device_rounds(L)
+ * rounds finish any input whose strings are at most L bytes long.
+ *   status (device, 2 words, out): status[0] = segments still unresolved
+ *   after the last round (0: perm and lcp are complete; else the output is
+ *   incomplete and the call must be repeated with more rounds), status[1] = 1
+ *   if set_off is malformed (then nothing is sorted).
+ * Other arguments, outputs and workspace as in ss_sort_batch.  Rounds without
+ * work cost only launches that find empty lists. */
+uint32_t ss_sort_batch_device_rounds(uint32_t max_len);
+int ss_sort_batch_device(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                         const uint64_t *set_off, uint32_t num_sets, uint32_t *perm, uint32_t *lcp,
+                         uint32_t flags, uint32_t rounds, uint32_t *status, void *ws, size_t ws_bytes,
+                         void *stream);
+
 /* ------------------------------------------------------- LCP and dist */
 
 /* LCP array of a given order (Section 2): lcp[0] = 0,
@@ -339,6 +358,25 @@ int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_t *run_end,
                  const uint8_t *suf, uint64_t *out_src, uint32_t *out_id, uint32_t *out_lcp,
                  uint32_t *out_len, uint64_t out_cap, uint64_t *n_out_host, void *ws, size_t ws_bytes,
                  void *stream);
+
+/* ---------------------------------------------------------------- graphs */
+
+/* A launch sequence of library calls captured once from a stream and replayed
+ * with one launch (a HIP graph).  Between ss_graph_begin(stream) and
+ * ss_graph_end(stream, &g) the calling thread enqueues capturable calls on
+ * `stream` (not the null stream); they are recorded, not run.  Capturable:
+ * ss_sort_batch_device, ss_dist_exact, ss_dist_exact_bounded, ss_lcp,
+ * ss_select_splitters, ss_bucket_bounds, ss_fc_decode_noalloc (no read-back,
+ * no allocation).  Pointers and sizes are fixed at capture: a replay reads
+ * whatever the captured buffers hold then.  Kernel profiling must be off.
+ * ss_graph_launch enqueues one replay on `stream`; replays of one graph must
+ * not overlap (they share the captured buffers). */
+typedef struct ss_graph_s *ss_graph;
+int ss_graph_begin(void *stream);
+int ss_graph_end(void *stream, ss_graph *out);
+int ss_graph_launch(ss_graph g, void *stream);
+size_t ss_graph_nodes(ss_graph g); /* kernel and other nodes of the graph */
+void ss_graph_destroy(ss_graph g);
 
 /* ------------------------------------------------------------ profiling */
 

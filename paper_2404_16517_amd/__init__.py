@@ -45,6 +45,13 @@ def lib():
             "ss_sort_workspace": ([U64], SZ),
             "ss_sort": ([P, U64, P, U64, P, P, P, SZ, P], I32),
             "ss_sort_batch": ([P, U64, P, U64, P, U32, P, P, U32, P, SZ, P], I32),
+            "ss_sort_batch_device_rounds": ([U32], U32),
+            "ss_sort_batch_device": ([P, U64, P, U64, P, U32, P, P, U32, U32, P, P, SZ, P], I32),
+            "ss_graph_begin": ([P], I32),
+            "ss_graph_end": ([P, P], I32),
+            "ss_graph_launch": ([P, P], I32),
+            "ss_graph_nodes": ([P], SZ),
+            "ss_graph_destroy": ([P], None),
             "ss_lcp": ([P, U64, P, U64, P, P, P], I32),
             "ss_dist_exact": ([P, U64, P, P, P, P], I32),
             "ss_dist_prefix_workspace": ([U64], SZ),
@@ -157,6 +164,63 @@ def sort_batch(bytes_, offsets, set_off: torch.Tensor, with_lcp: bool = True, ws
     return perm, lcp
 
 
+def sort_batch_device_rounds(max_len: int) -> int:
+    """Rounds after which the device-driven sort is complete for strings of at most max_len bytes."""
+    return int(lib().ss_sort_batch_device_rounds(max_len))
+
+
+def sort_batch_device(bytes_, offsets, set_off, perm, lcp_, status, ws, rounds: int, global_ids: bool = False):
+    """Device-driven batch sort into caller-supplied buffers (nothing is read
+    back or allocated, so it can be captured in a Graph).  ``status``: int32
+    device tensor of 2 words (unresolved segments, malformed set_off)."""
+    b, o, n = _dev_strings(bytes_, offsets)
+    if perm.numel() < n or (lcp_ is not None and lcp_.numel() < n) or status.numel() < 2:
+        raise StrsortError("perm/lcp need n entries and status 2")
+    _check(lib().ss_sort_batch_device(_p(b), b.numel(), _p(o), n, _p(set_off), set_off.numel() - 1, _p(perm),
+                                      _p(lcp_), SS_BATCH_GLOBAL_IDS if global_ids else 0, rounds, _p(status),
+                                      _p(ws), ws.numel(), _stream(b.device)))
+
+
+class Graph:
+    """A captured launch sequence of library calls (ss_graph_*), replayed with one launch."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+
+    @classmethod
+    def capture(cls, fn, stream: "torch.cuda.Stream") -> "Graph":
+        """Record the library calls ``fn()`` makes on ``stream`` (made current
+        while it runs); every buffer they use must already exist."""
+        sp = ctypes.c_void_p(stream.cuda_stream)
+        with torch.cuda.stream(stream):
+            _check(lib().ss_graph_begin(sp))
+            h = ctypes.c_void_p()
+            try:
+                fn()
+            finally:
+                rc = lib().ss_graph_end(sp, ctypes.byref(h))
+        _check(rc)
+        return cls(h)
+
+    def launch(self, stream: "torch.cuda.Stream | None" = None):
+        st = stream.cuda_stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        _check(lib().ss_graph_launch(self._h, ctypes.c_void_p(st)))
+
+    def nodes(self) -> int:
+        return int(lib().ss_graph_nodes(self._h))
+
+    def close(self):
+        if self._h:
+            lib().ss_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def lcp(bytes_, offsets, perm):
     """LCP array of the order ``perm`` (perm values index ``offsets``)."""
     b, o, _ = _dev_strings(bytes_, offsets)
@@ -183,12 +247,14 @@ def dist_exact_bounded(perm, lcp_, d, n_strings=None):
     return out
 
 
-def dist_exact(offsets, perm, lcp_):
-    """Exact distinguishing prefixes by input index (sized like ``offsets``)."""
+def dist_exact(offsets, perm, lcp_, out=None):
+    """Exact distinguishing prefixes by input index (sized like ``offsets``),
+    into ``out`` when given (nothing is allocated then)."""
     n = perm.numel()
     if lcp_.numel() != n:
         raise StrsortError("perm and lcp must have the same length")
-    out = torch.zeros(max(offsets.numel() - 1, 0), dtype=torch.int32, device=offsets.device)
+    if out is None:
+        out = torch.zeros(max(offsets.numel() - 1, 0), dtype=torch.int32, device=offsets.device)
     _check(lib().ss_dist_exact(_p(offsets), n, _p(perm.contiguous()), _p(lcp_.contiguous()), _p(out),
                                _stream(offsets.device)))
     return out

@@ -103,6 +103,12 @@ extern int g_tile;
 // (in == out) is allowed.  Scratch: ss_scan_scratch_elems(n) elements of T.
 template <class T> u64 ss_scan_scratch_elems(u64 n);
 template <class T> int ss_scan_exclusive(const T *in, T *out, u64 n, T *scratch, hipStream_t s);
+// The same with the length read on the device, n = *n_dev * mult (a fixed
+// launch shape, no read-back; for captured graphs).  out[n] = total.
+// Scratch: ss_scan_dev_scratch_elems() elements of T.
+template <class T> u64 ss_scan_dev_scratch_elems();
+template <class T> int ss_scan_exclusive_dev(const T *in, T *out, const u32 *n_dev, u32 mult, T *scratch,
+                                             hipStream_t s);
 
 // ------------------------------------------------------------ byte loads
 

@@ -40,6 +40,12 @@ enum {
     C_LTILES = 5, C_SMALLN = 6, C_NTILES = 7, C_ITILES = 8, C_LELEM = 9, C_NELEM = 12, C_TINY = 13,
     C_TINYN = 14, C_BADSET = 15, C_NCTR = 16
 };
+// Headers that the round and level kernels read their list lengths from
+// (copied from the counters by k_round_begin / k_level_begin, so that the
+// counters can be reset for the lists being built): hdr[H_ACT] active
+// segments, hdr[H_LARGE] radix segments of the current level, hdr[H_HIST]
+// their histogram length (256 per tile).
+enum { H_ACT = 0, H_LARGE = 1, H_HIST = 2, H_REMAIN = 3, H_NHDR = 4 };
 #define WS_MAX 128  // segments of up to this many strings: one wavefront each
 // ctr[10..11]: 64-bit sum of size * skip over the routed segments
 
@@ -113,41 +119,68 @@ __device__ __forceinline__ T block_max(T v)
 
 // ------------------------------------------------------------ tile lists
 
-__global__ void k_tile_counts(const Seg *segs, u32 nseg, u32 tile, u32 *out)
+// Every kernel below reads the length of the list it works on from device
+// memory and takes its items in a grid-stride loop, so one launch shape
+// serves any length: the host either sizes the grid from counts it read back,
+// or launches a fixed grid without reading anything back.
+
+#define GSTRIDE(j, count) for (u32 j = blockIdx.x * blockDim.x + threadIdx.x; j < (count); j += gridDim.x * blockDim.x)
+
+__global__ void k_tile_counts(const Seg *segs, const u32 *nsegp, u32 tile, u32 *out)
 {
-    u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < nseg) out[j] = (segs[j].end - segs[j].begin + tile - 1) / tile;
+    const u32 nseg = *nsegp;
+    GSTRIDE(j, nseg) out[j] = (segs[j].end - segs[j].begin + tile - 1) / tile;
+}
+
+// Start of a round: the active list's length goes to the header, the
+// counters of the lists the round builds are reset.
+__global__ void k_round_begin(u32 *ctr, u32 *hdr)
+{
+    if (threadIdx.x == 0) hdr[H_ACT] = ctr[C_NEXT];
+    __syncthreads();
+    if (threadIdx.x < C_NCTR && threadIdx.x != C_BADSET) ctr[threadIdx.x] = 0;
 }
 
 // Tile counts of the active segments for a round; also resets the segments'
-// skip minima and (thread 0) the round counters.
-__global__ void k_round_tiles(const Seg *segs, u32 nseg, u32 tile, u32 *out, u32 *skipv, u32 *ctr)
+// skip minima.
+__global__ void k_round_tiles(const Seg *segs, const u32 *nsegp, u32 tile, u32 *out, u32 *skipv)
 {
-    u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < C_NCTR) ctr[j] = 0;
-    if (j < nseg) {
+    const u32 nseg = *nsegp;
+    GSTRIDE(j, nseg) {
         out[j] = (segs[j].end - segs[j].begin + tile - 1) / tile;
         skipv[j] = 0xFFFFFFFFu;
     }
 }
 
-// Tile counts of the radix segments of a level; also resets their key minima
-// and maxima and (thread 0) the counters of the next level's radix list.
-__global__ void k_level_tiles(const Seg *segs, u32 nseg, u32 tile, u32 *out, u64 *smin, u64 *smax, u32 *ctr)
+// Start of a radix level: the radix list's length and its histogram length
+// go to the header, the counters of the next level's radix list are reset.
+__global__ void k_level_begin(u32 *ctr, u32 *hdr)
 {
-    u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j == 0) { ctr[C_LARGE] = 0; ctr[C_LTILES] = 0; ctr[C_LELEM] = 0; }
-    if (j < nseg) {
+    if (threadIdx.x == 0) {
+        hdr[H_LARGE] = ctr[C_LARGE];
+        hdr[H_HIST] = 256u * ctr[C_LTILES];
+        ctr[C_LARGE] = 0;
+        ctr[C_LTILES] = 0;
+        ctr[C_LELEM] = 0;
+    }
+}
+
+// Tile counts of the radix segments of a level; also resets their key minima
+// and maxima.
+__global__ void k_level_tiles(const Seg *segs, const u32 *nsegp, u32 tile, u32 *out, u64 *smin, u64 *smax)
+{
+    const u32 nseg = *nsegp;
+    GSTRIDE(j, nseg) {
         out[j] = (segs[j].end - segs[j].begin + tile - 1) / tile;
         smin[j] = ~0ull;
         smax[j] = 0;
     }
 }
 
-__global__ void k_sizes(const Seg *segs, u32 nseg, u32 *out)
+__global__ void k_sizes(const Seg *segs, const u32 *nsegp, u32 *out)
 {
-    u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < nseg) out[j] = segs[j].end - segs[j].begin;
+    const u32 nseg = *nsegp;
+    GSTRIDE(j, nseg) out[j] = segs[j].end - segs[j].begin;
 }
 
 // ------------------------------------------------------------ round kernels
@@ -243,7 +276,7 @@ __device__ __forceinline__ u32 skip_cmp(const u8 *bytes, u64 N, const u8 *R, con
 // position, its remaining length there (capped at 8) and its 8 bytes there
 // (mword, mpr), from which k_keys builds its key without reading the string
 // again.
-__global__ __launch_bounds__(NT, 6) void k_skip(const Seg *segs, const u32 *tstart, u32 nseg,
+__global__ __launch_bounds__(NT, 6) void k_skip(const Seg *segs, const u32 *tstart, const u32 *nsegp,
                                              const u8 *bytes, u64 N, const u64 *off,
                                              const u32 *perm, u32 *skipv, u64 *mword, uint2 *mpr)
 {
@@ -251,10 +284,12 @@ __global__ __launch_bounds__(NT, 6) void k_skip(const Seg *segs, const u32 *tsta
     __shared__ __attribute__((aligned(16))) u8 rows[(NT / 64) * SKR];
     __shared__ u64 wwa[NT / 64][SKB];  // per wavefront: window start of each member
     __shared__ u32 wwn[NT / 64][SKB];  // ... and its chunk count
-    const u32 t = blockIdx.x;
+    const u32 nseg = *nsegp;
+    const u32 ntiles = tstart[nseg];
+    for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {  // (uniform over the workgroup)
     const u32 sg = seg_of_tile(tstart, nseg, t);
     const Seg g = segs[sg];
-    if (!(g.aux & SEG_SKIP)) return;  // uniform over the workgroup
+    if (!(g.aux & SEG_SKIP)) continue;  // uniform over the workgroup
     const u32 lt = t - tstart[sg];
     const u32 b0 = g.begin + lt * ETILE;
     const u32 b1 = min(g.end, b0 + ETILE);
@@ -345,17 +380,20 @@ __global__ __launch_bounds__(NT, 6) void k_skip(const Seg *segs, const u32 *tsta
             }
         }
     }
-    const u32 bm = block_min(best);
+    const u32 bm = block_min(best);  // (ends with a barrier: fsw and the rows are free again)
     if (threadIdx.x == 0) atomicMin(&skipv[sg], bm);
+    }
 }
 
-__global__ __launch_bounds__(NT) void k_keys(const Seg *segs, const u32 *tstart, u32 nseg,
+__global__ __launch_bounds__(NT) void k_keys(const Seg *segs, const u32 *tstart, const u32 *nsegp,
                                              const u8 *bytes, u64 N, const u64 *off,
                                              const u32 *perm, const u32 *skipv, const u64 *mword,
                                              const uint2 *mpr, u64 *keys)
 {
     __shared__ u64 fw;
-    const u32 t = blockIdx.x;
+    const u32 nseg = *nsegp;
+    const u32 ntiles = tstart[nseg];
+    for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const u32 s = seg_of_tile(tstart, nseg, t);
     const Seg g = segs[s];
     const u32 lt = t - tstart[s];
@@ -368,7 +406,7 @@ __global__ __launch_bounds__(NT) void k_keys(const Seg *segs, const u32 *tstart,
             const u64 o = off[p], l = off[p + 1] - o;
             keys[i] = make_key(bytes, N, o, l, d);
         }
-        return;
+        continue;  // (uniform over the workgroup)
     }
     // A member agrees with the segment's first string up to its mismatch
     // position pos >= d, so its key at d is the first string's bytes [d, pos)
@@ -392,13 +430,17 @@ __global__ __launch_bounds__(NT) void k_keys(const Seg *segs, const u32 *tstart,
         const u32 cnt = pr.y + k < 8 ? pr.y + k : 8u;
         keys[i] = (data & ~0xFFull) | cnt;
     }
+    __syncthreads();  // fw is rewritten by the next tile
+    }
 }
 
 // Apply the skip, route each active segment to the LDS list or the radix list.
-__global__ void k_classify(const Seg *act, u32 nact, const u32 *skipv, u32 small_max, u32 tile, Seg *tiny,
+__global__ void k_classify(const Seg *act, const u32 *nactp, const u32 *skipv, u32 small_max, u32 tile, Seg *tiny,
                            Seg *small, Seg *large, u32 *ctr)
 {
-    u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    const u32 nact = *nactp;
+    for (u32 j0 = blockIdx.x * blockDim.x; j0 < nact; j0 += gridDim.x * blockDim.x) {
+    const u32 j = j0 + threadIdx.x;
     bool valid = j < nact;
     Seg g = {0, 0, 0, 0};
     if (valid) {
@@ -426,6 +468,7 @@ __global__ void k_classify(const Seg *act, u32 nact, const u32 *skipv, u32 small
     wave_add(sm ? sz : 0u, &ctr[C_SMALLN]);
     wave_add(lg ? (sz + tile - 1) / tile : 0u, &ctr[C_LTILES]);
     wave_add(lg ? sz : 0u, &ctr[C_LELEM]);
+    }
 }
 
 // ------------------------------------------------------------ radix passes
@@ -434,11 +477,13 @@ __device__ __forceinline__ u32 digit_of(u64 k, u32 level) { return (u32)(k >> (5
 
 // Per-tile histogram of the segment's current byte, digit-major per segment:
 // hist[256*tstart[s] + d*T_s + lt].  Also the segment's min and max key.
-__global__ __launch_bounds__(NT) void k_hist(const Seg *segs, const u32 *tstart, u32 nseg, u32 tile,
+__global__ __launch_bounds__(NT) void k_hist(const Seg *segs, const u32 *tstart, const u32 *nsegp, u32 tile,
                                              const u64 *keyA, const u64 *keyB, u32 *hist, u64 *smin, u64 *smax)
 {
     __shared__ u32 h[256];
-    const u32 t = blockIdx.x;
+    const u32 nseg = *nsegp;
+    const u32 ntiles = tstart[nseg];
+    for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const u32 s = seg_of_tile(tstart, nseg, t);
     const Seg g = segs[s];
     const u64 *keys = (g.aux & SEG_INB) ? keyB : keyA;
@@ -465,10 +510,11 @@ __global__ __launch_bounds__(NT) void k_hist(const Seg *segs, const u32 *tstart,
     __syncthreads();
     hist[256u * tstart[s] + threadIdx.x * T + lt] = h[threadIdx.x];
     mn = block_min(mn);
-    mx = block_max(mx);
+    mx = block_max(mx);  // (ends with a barrier: h is free again)
     if (threadIdx.x == 0) {
         atomicMin((unsigned long long *)&smin[s], (unsigned long long)mn);
         atomicMax((unsigned long long *)&smax[s], (unsigned long long)mx);
+    }
     }
 }
 
@@ -555,16 +601,17 @@ __device__ __forceinline__ EmitItem emit_item(const Seg *segs, const u32 *tstart
 // A workgroup takes EPB segments (thread d = digit d): it counts its entries in
 // LDS, reserves room in every list with one global atomic per list, and then
 // writes the entries.
-__global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart, u32 nseg,
+__global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart, const u32 *nsegp,
                                               const u32 *hist, const u64 *smin, const u64 *smax,
                                               EmitOut o)
 {
     __shared__ u32 lcount[K_KINDS], lslot[K_KINDS], lsum[7], gbase[K_KINDS];
+    const u32 nseg = *nsegp;
+    for (u32 s0 = blockIdx.x * EPB; s0 < nseg; s0 += gridDim.x * EPB) {
     const u32 d = threadIdx.x;
     if (d < K_KINDS) { lcount[d] = 0; lslot[d] = 0; }
     if (d < 7) lsum[d] = 0;
     __syncthreads();
-    const u32 s0 = blockIdx.x * EPB;
     EmitItem it[EPB];
 #pragma unroll
     for (u32 q = 0; q < EPB; q++) {
@@ -614,19 +661,23 @@ __global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart
             dst[a] = x.ns;
         }
     }
+    __syncthreads();  // the LDS counters are reset for the next group
+    }
 }
 
 // Stable scatter of (key, payload) by the current byte into the other pair
 // of arrays (A -> B or B -> A, by the segment's flag).
-__global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tstart, u32 nseg, u32 tile,
+__global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tstart, const u32 *nsegp, u32 tile,
                                                 const u32 *hist, const u8 *scat, u64 *keyA, u32 *valA,
                                                 u64 *keyB, u32 *valB)
 {
     __shared__ u32 run[256];
     __shared__ u32 wcnt[NT / 64][256];
-    const u32 t = blockIdx.x;
+    const u32 nseg = *nsegp;
+    const u32 ntiles = tstart[nseg];
+    for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const u32 s = seg_of_tile(tstart, nseg, t);
-    if (!scat[s]) return;
+    if (!scat[s]) continue;  // (uniform over the workgroup)
     const Seg g = segs[s];
     const bool inb = g.aux & SEG_INB;
     const u64 *ksrc = inb ? keyB : keyA;
@@ -677,17 +728,21 @@ __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tsta
         }
         __syncthreads();
     }
+    __syncthreads();  // run is rewritten by the next tile
+    }
 }
 
 // After a level: buckets that no later kernel rewrites (singletons, runs for
 // the next round, equal strings) are copied to A when the level left them in
 // B.  Scattered segments read back their digits to find them; an unscattered
 // segment that became such a run is copied whole.
-__global__ __launch_bounds__(NT) void k_settle(const Seg *segs, const u32 *tstart, u32 nseg, u32 tile,
+__global__ __launch_bounds__(NT) void k_settle(const Seg *segs, const u32 *tstart, const u32 *nsegp, u32 tile,
                                                const u8 *scat, const u8 *kinds, const u64 *keyB,
                                                const u32 *valB, u64 *keyA, u32 *valA)
 {
-    const u32 t = blockIdx.x;
+    const u32 nseg = *nsegp;
+    const u32 ntiles = tstart[nseg];
+    for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const u32 s = seg_of_tile(tstart, nseg, t);
     const Seg g = segs[s];
     const bool inb = g.aux & SEG_INB;
@@ -697,7 +752,7 @@ __global__ __launch_bounds__(NT) void k_settle(const Seg *segs, const u32 *tstar
     const u32 b1 = min(g.end, b0 + tile);
     const u8 *kd = kinds + 256u * s;
     if (scat[s]) {
-        if (inb) return;  // scattered into A
+        if (inb) continue;  // scattered into A
         for (u32 i = b0 + threadIdx.x; i < b1; i += NT) {
             const u64 k = keyB[i];
             const u32 c = kd[digit_of(k, level)];
@@ -712,27 +767,32 @@ __global__ __launch_bounds__(NT) void k_settle(const Seg *segs, const u32 *tstar
             valA[i] = valB[i];
         }
     }
+    }
 }
 
-__global__ void k_boundary(const uint2 *bnd, u32 nb, const u64 *keys, u32 *lcp)
+__global__ void k_boundary(const uint2 *bnd, const u32 *nbp, const u64 *keys, u32 *lcp)
 {
-    u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nb) return;
-    uint2 b = bnd[j];
-    lcp[b.x] = key_lcp(keys[b.x - 1], keys[b.x], b.y);
+    const u32 nb = *nbp;
+    GSTRIDE(j, nb) {
+        const uint2 b = bnd[j];
+        lcp[b.x] = key_lcp(keys[b.x - 1], keys[b.x], b.y);
+    }
 }
 
 // Equal strings: LCP = their length for every member after the first.
-__global__ __launch_bounds__(NT) void k_ident(const Seg *segs, const u32 *tstart, u32 nseg, u32 *lcp)
+__global__ __launch_bounds__(NT) void k_ident(const Seg *segs, const u32 *tstart, const u32 *nsegp, u32 *lcp)
 {
-    const u32 t = blockIdx.x;
-    const u32 s = seg_of_tile(tstart, nseg, t);
-    const Seg g = segs[s];
-    const u32 lt = t - tstart[s];
-    const u32 b0 = g.begin + lt * ETILE;
-    const u32 b1 = min(g.end, b0 + ETILE);
-    for (u32 i = b0 + threadIdx.x; i < b1; i += NT)
-        if (i > g.begin) lcp[i] = g.depth;
+    const u32 nseg = *nsegp;
+    const u32 ntiles = tstart[nseg];
+    for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const u32 s = seg_of_tile(tstart, nseg, t);
+        const Seg g = segs[s];
+        const u32 lt = t - tstart[s];
+        const u32 b0 = g.begin + lt * ETILE;
+        const u32 b1 = min(g.end, b0 + ETILE);
+        for (u32 i = b0 + threadIdx.x; i < b1; i += NT)
+            if (i > g.begin) lcp[i] = g.depth;
+    }
 }
 
 // ------------------------------------------------------------- LDS sort
@@ -748,7 +808,7 @@ __device__ __forceinline__ bool lds_greater(u16 sa, u64 ka, u32 va, u16 sb, u64 
 // the concatenated small-segment space lies in [t*H, (t+1)*H); with segment
 // sizes <= H a tile holds < 2H elements.  Sorted by (segment, key, payload)
 // with a bitonic network in LDS.
-__global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32 *pref, u32 nsmall,
+__global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32 *pref, const u32 *nsmallp,
                                                      u32 H, u64 *keys, u32 *vals, const u64 *keyB,
                                                      const u32 *valB, u32 *lcp, Seg *next, u32 *ctr)
 {
@@ -761,7 +821,9 @@ __global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32
     __shared__ u8 sinb[LDS_CAP / 2];
     __shared__ Seg nq[LDS_CAP / 2];  // next-round segments found in this tile
     __shared__ u32 nq_count, nq_tiles, nq_elems, nq_base;
-    const u32 t = blockIdx.x;
+    const u32 nsmall = *nsmallp;
+    const u32 ntile = (pref[nsmall] + H - 1) / H;  // pref[nsmall]: strings in all small segments
+    for (u32 t = blockIdx.x; t < ntile; t += gridDim.x) {
     const u32 lo = t * H, hi = lo + H;
     // j0 = first segment with pref >= lo, j1 = first with pref >= hi
     u32 j0, j1;
@@ -773,7 +835,7 @@ __global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32
         while (a < b) { u32 m = (a + b) >> 1; if (pref[m] < hi) a = m + 1; else b = m; }
         j1 = a;
     }
-    if (j0 >= j1) return;
+    if (j0 >= j1) continue;  // (uniform over the workgroup)
     const u32 ns = j1 - j0;
     const u32 base = pref[j0];
     const u32 cnt = pref[j1] - base;
@@ -860,6 +922,8 @@ __global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32
     }
     __syncthreads();
     for (u32 k = threadIdx.x; k < nq_count; k += LDS_NT) next[nq_base + k] = nq[k];
+    __syncthreads();  // the LDS tables are rewritten by the next tile
+    }
 }
 
 #define WS_SPB 16  // tiny segments per workgroup (4 wavefronts, 4 segments each)
@@ -907,11 +971,13 @@ __device__ __forceinline__ u32 hibit(u64 m) { return 63u - (u32)__clzll(m); }
 // (key, payload) in registers (element e = lane + 64 r, r = 0, 1), then LCPs
 // and next-round runs as in the LDS sort.  Next-round segments are collected
 // per workgroup and published with one atomic per counter.
-__global__ __launch_bounds__(256) void k_wave_sort(const Seg *tiny, u32 ntiny, u64 *keys, u32 *vals,
+__global__ __launch_bounds__(256) void k_wave_sort(const Seg *tiny, const u32 *ntinyp, u64 *keys, u32 *vals,
                                                    const u64 *keyB, const u32 *valB, u32 *lcp, Seg *next, u32 *ctr)
 {
     __shared__ Seg nq[WS_SPB * (WS_MAX / 2)];
     __shared__ u32 nq_count, nq_tiles, nq_elems, nq_base;
+    const u32 ntiny = *ntinyp;
+    for (u32 grp = blockIdx.x; grp * WS_SPB < ntiny; grp += gridDim.x) {
     if (threadIdx.x == 0) { nq_count = 0; nq_tiles = 0; nq_elems = 0; }
     __syncthreads();
     const u32 lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -921,7 +987,7 @@ __global__ __launch_bounds__(256) void k_wave_sort(const Seg *tiny, u32 ntiny, u
     Seg gq[WS_SPB / 4];
 #pragma unroll
     for (u32 q = 0; q < WS_SPB / 4; q++) {
-        const u32 sidx = blockIdx.x * WS_SPB + q * 4 + wv;
+        const u32 sidx = grp * WS_SPB + q * 4 + wv;
         gq[q] = sidx < ntiny ? tiny[sidx] : Seg{0, 0, 0, 0};
     }
     u64 nk0 = ~0ull, nk1 = ~0ull;
@@ -937,7 +1003,7 @@ __global__ __launch_bounds__(256) void k_wave_sort(const Seg *tiny, u32 ntiny, u
     fetch(gq[0]);
 #pragma unroll
     for (u32 q = 0; q < WS_SPB / 4; q++) {
-        const u32 sidx = blockIdx.x * WS_SPB + q * 4 + wv;
+        const u32 sidx = grp * WS_SPB + q * 4 + wv;
         if (sidx >= ntiny) break;  // uniform over the wavefront
         const Seg g = gq[q];
         const u32 cnt = g.end - g.begin;
@@ -1002,16 +1068,11 @@ __global__ __launch_bounds__(256) void k_wave_sort(const Seg *tiny, u32 ntiny, u
     }
     __syncthreads();
     for (u32 k = threadIdx.x; k < nq_count; k += 256) next[nq_base + k] = nq[k];
+    __syncthreads();  // nq and its counters are reset for the next group
+    }
 }
 
 // ------------------------------------------------------------ host driver
-
-static int build_tiles(const Seg *segs, u32 nseg, u32 tile, u32 *tstart, void *scan_scratch, hipStream_t st)
-{
-    k_tile_counts<<<(unsigned)ceil_div(nseg, 256), 256, 0, st>>>(segs, nseg, tile, tstart);
-    SS_CHECK_LAUNCH();
-    return ss_scan_exclusive<u32>(tstart, tstart, nseg, (u32 *)scan_scratch, st);
-}
 
 void sort_ws_layout(u64 n, SortWs *w, WsArena *a, WsCounter *c)
 {
@@ -1049,120 +1110,218 @@ void sort_ws_layout(u64 n, SortWs *w, WsArena *a, WsCounter *c)
     TAKE(spref, u32, nseg + 1);
     TAKE(hist, u32, nscan);
     TAKE(scan_scratch, u64, ss_scan_scratch_elems<u64>(nscan));
+    TAKE(dscan, u32, ss_scan_dev_scratch_elems<u32>());
     TAKE(ctr, u32, C_NCTR);
+    TAKE(hdr, u32, H_NHDR);
 #undef TAKE
 }
 
-// Run rounds until no segment is unresolved.  The caller prepared w.act
-// (nact segments covering atiles element tiles) and the payload array `vals`.
-// The host reads the counters once after the routing, once per radix level
-// and once at the end of a round.
+// Launch shapes.  A kernel over a list takes its items in a grid-stride loop;
+// the host sizes its grid from the list's length when it knows it (read back),
+// otherwise it launches a fixed grid bounded by the largest list possible.
+static unsigned grid_of(u64 items, u64 per, u64 cap)
+{
+    const u64 g = ceil_div(items, per);
+    return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+// One round or level's lengths: known to the host (read back) or not.
+struct Known {
+    bool yes;
+    u32 v;
+};
+
+struct RoundCtx {
+    const SortJob &J;
+    SortWs &w;
+    u64 n;  // strings of the whole sort (bounds every list)
+    u32 SM, TL;
+};
+
+static int scan_u32(RoundCtx &C, u32 *arr, const u32 *n_dev, Known k)
+{
+    if (k.yes) return ss_scan_exclusive<u32>(arr, arr, k.v, (u32 *)C.w.scan_scratch, C.J.stream);
+    return ss_scan_exclusive_dev<u32>(arr, arr, n_dev, 1, C.w.dscan, C.J.stream);
+}
+
+// The part of a round before the radix levels: skip, keys, routing.
+static int round_head(RoundCtx &C, Known nact, Known atiles, u64 round_elems)
+{
+    SortWs &w = C.w;
+    const SortJob &J = C.J;
+    hipStream_t st = J.stream;
+    const u64 n = C.n;
+    k_round_begin<<<1, 64, 0, st>>>(w.ctr, w.hdr);
+    SS_CHECK_LAUNCH();
+    const u32 *nactp = w.hdr + H_ACT;
+    k_round_tiles<<<grid_of(nact.yes ? nact.v : n / 2, 256, 1024), 256, 0, st>>>(w.act, nactp, ETILE, w.tstart,
+                                                                               w.skipv);
+    SS_CHECK_LAUNCH();
+    SS_TRY(scan_u32(C, w.tstart, nactp, nact));
+    const unsigned tg = grid_of(atiles.yes ? atiles.v : n, atiles.yes ? 1 : ETILE, atiles.yes ? 1u << 30 : 2048);
+    {
+        // algorithmic bytes: perm + offsets + one word per string, its mismatch
+        // record out, plus the common prefix (added once the skips are known)
+        SS_PROF("k_skip", st, (double)round_elems * 44.0);
+        k_skip<<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr);
+    }
+    SS_CHECK_LAUNCH();
+    {
+        SS_PROF("k_keys", st, (double)round_elems * 24.0);  // mismatch record in, key out
+        k_keys<<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr,
+                                  w.keyA);
+    }
+    SS_CHECK_LAUNCH();
+    k_classify<<<grid_of(nact.yes ? nact.v : n / 2, 256, 1024), 256, 0, st>>>(w.act, nactp, w.skipv, C.SM, C.TL,
+                                                                             w.tiny, w.small, w.largeA, w.ctr);
+    SS_CHECK_LAUNCH();
+    return SS_OK;
+}
+
+// One radix level over the list LA (its length in ctr[C_LARGE] when the level
+// starts); its sub-lists go to LB and the round's lists.
+static int radix_level(RoundCtx &C, Seg *LA, Seg *LB, Known nlarge, Known ltiles, u64 lelem)
+{
+    SortWs &w = C.w;
+    const SortJob &J = C.J;
+    hipStream_t st = J.stream;
+    const u64 n = C.n;
+    k_level_begin<<<1, 64, 0, st>>>(w.ctr, w.hdr);
+    SS_CHECK_LAUNCH();
+    const u32 *nlp = w.hdr + H_LARGE;
+    k_level_tiles<<<grid_of(nlarge.yes ? nlarge.v : n / 128, 256, 1024), 256, 0, st>>>(LA, nlp, C.TL, w.tstart,
+                                                                                     w.smin, w.smax);
+    SS_CHECK_LAUNCH();
+    SS_TRY(scan_u32(C, w.tstart, nlp, nlarge));
+    const unsigned tg = grid_of(ltiles.yes ? ltiles.v : n, ltiles.yes ? 1 : C.TL, ltiles.yes ? 1u << 30 : 2048);
+    {
+        SS_PROF("k_hist", st, (double)lelem * 8.0);  // read the keys
+        k_hist<<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.keyA, w.keyB, w.hist, w.smin, w.smax);
+    }
+    SS_CHECK_LAUNCH();
+    if (ltiles.yes) SS_TRY(ss_scan_exclusive<u32>(w.hist, w.hist, (u64)ltiles.v * 256, (u32 *)w.scan_scratch, st));
+    else SS_TRY(ss_scan_exclusive_dev<u32>(w.hist, w.hist, w.hdr + H_HIST, 1, w.dscan, st));
+    EmitOut eo{w.tiny, w.small, LB, w.nxt, w.ident, w.bnd, w.ctr, w.scat, w.kinds, C.SM, C.TL};
+    k_emit<<<grid_of(nlarge.yes ? nlarge.v : n / 128, EPB, 4096), 256, 0, st>>>(LA, w.tstart, nlp, w.hist, w.smin,
+                                                                              w.smax, eo);
+    SS_CHECK_LAUNCH();
+    {
+        SS_PROF("k_scatter", st, (double)lelem * 24.0);  // key+payload in and out
+        k_scatter<<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.hist, w.scat, w.keyA, J.vals, w.keyB, w.valB);
+    }
+    SS_CHECK_LAUNCH();
+    {
+        SS_PROF("k_settle", st, (double)lelem * 8.0);  // at most the scattered keys read back
+        k_settle<<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.scat, w.kinds, w.keyB, w.valB, w.keyA, J.vals);
+    }
+    SS_CHECK_LAUNCH();
+    return SS_OK;
+}
+
+// The part of a round after the radix levels: small sorts, boundary LCPs,
+// equal strings.  h (when known) holds the counters after the last level.
+static int round_tail(RoundCtx &C, const u32 *h)
+{
+    SortWs &w = C.w;
+    const SortJob &J = C.J;
+    hipStream_t st = J.stream;
+    const u64 n = C.n;
+    u32 *lcp = J.lcp;
+    const bool known = h != nullptr;
+    if (!known || h[C_TINY] > 0) {
+        SS_PROF("k_wave_sort", st, known ? (double)h[C_TINYN] * 28.0 : 0.0);  // key+payload in/out, LCP out
+        k_wave_sort<<<grid_of(known ? h[C_TINY] : n / 2, WS_SPB, known ? 1u << 30 : 2048), 256, 0, st>>>(
+            w.tiny, w.ctr + C_TINY, w.keyA, J.vals, w.keyB, w.valB, lcp, w.nxt, w.ctr);
+        SS_CHECK_LAUNCH();
+    }
+    if (!known || h[C_SMALL] > 0) {
+        k_sizes<<<grid_of(known ? h[C_SMALL] : n / 2, 256, 1024), 256, 0, st>>>(w.small, w.ctr + C_SMALL, w.spref);
+        SS_CHECK_LAUNCH();
+        SS_TRY(scan_u32(C, w.spref, w.ctr + C_SMALL, Known{known, known ? h[C_SMALL] : 0u}));
+        SS_PROF("k_lds_sort", st, known ? (double)h[C_SMALLN] * 28.0 : 0.0);  // key+payload in/out, LCP out
+        k_lds_sort<<<grid_of(known ? h[C_SMALLN] : n, C.SM, known ? 1u << 30 : 2048), LDS_NT, 0, st>>>(
+            w.small, w.spref, w.ctr + C_SMALL, C.SM, w.keyA, J.vals, w.keyB, w.valB, lcp, w.nxt, w.ctr);
+        SS_CHECK_LAUNCH();
+    }
+    if (!known || h[C_BND] > 0) {
+        k_boundary<<<grid_of(known ? h[C_BND] : n, 256, 1024), 256, 0, st>>>(w.bnd, w.ctr + C_BND, w.keyA, lcp);
+        SS_CHECK_LAUNCH();
+    }
+    if (!known || h[C_IDENT] > 0) {
+        k_tile_counts<<<grid_of(known ? h[C_IDENT] : n / 2, 256, 1024), 256, 0, st>>>(w.ident, w.ctr + C_IDENT,
+                                                                                    ETILE, w.tstart);
+        SS_CHECK_LAUNCH();
+        SS_TRY(scan_u32(C, w.tstart, w.ctr + C_IDENT, Known{known, known ? h[C_IDENT] : 0u}));
+        k_ident<<<grid_of(known ? h[C_ITILES] : n, known ? 1 : ETILE, known ? 1u << 30 : 2048), NT, 0, st>>>(
+            w.ident, w.tstart, w.ctr + C_IDENT, lcp);
+        SS_CHECK_LAUNCH();
+    }
+    return SS_OK;
+}
+
+// Host-driven rounds: the host reads the counters once after the routing,
+// once per radix level and once at the end of a round, sizes every grid from
+// them and stops when no segment is unresolved.  The caller has put the first
+// round's segments in w.act and their count, tiles and strings in
+// ctr[C_NEXT], ctr[C_NTILES], ctr[C_NELEM].
 int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
 {
-    hipStream_t st = J.stream;
-    const u32 SM = (u32)g_small_max;
-    const u32 TL = (u32)g_tile;
-    u32 *lcp = J.lcp;
+    RoundCtx C{J, w, 0, (u32)g_small_max, (u32)g_tile};
+    C.n = J.n_total;
     u32 h[C_NCTR];
     u64 round_elems = J.n_first;
     while (nact > 0) {
-        {
-            const u32 nt = nact > C_NCTR ? nact : C_NCTR;
-            k_round_tiles<<<(unsigned)ceil_div(nt, 256), 256, 0, st>>>(w.act, nact, ETILE, w.tstart, w.skipv, w.ctr);
-            SS_CHECK_LAUNCH();
-            SS_TRY(ss_scan_exclusive<u32>(w.tstart, w.tstart, nact, (u32 *)w.scan_scratch, st));
-            {
-                // algorithmic bytes: perm + offsets + one word per string, its mismatch
-                // record out, plus the common prefix (added once the skips are known)
-                SS_PROF("k_skip", st, (double)round_elems * 44.0);
-                k_skip<<<atiles, NT, 0, st>>>(w.act, w.tstart, nact, J.bytes, J.N, J.off, J.vals, w.skipv,
-                                              w.mword, w.mpr);
-            }
-            SS_CHECK_LAUNCH();
-            {
-                SS_PROF("k_keys", st, (double)round_elems * 24.0);  // mismatch record in, key out
-                k_keys<<<atiles, NT, 0, st>>>(w.act, w.tstart, nact, J.bytes, J.N, J.off, J.vals, w.skipv,
-                                              w.mword, w.mpr, w.keyA);
-            }
-            SS_CHECK_LAUNCH();
-        }
-        k_classify<<<(unsigned)ceil_div(nact, 256), 256, 0, st>>>(w.act, nact, w.skipv, SM, TL, w.tiny, w.small,
-                                                                   w.largeA, w.ctr);
-        SS_CHECK_LAUNCH();
-        SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, st));
+        SS_TRY(round_head(C, Known{true, nact}, Known{true, atiles}, round_elems));
+        SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, J.stream));
         ss_prof_add_bytes("k_skip", (double)(h[10] | ((u64)h[11] << 32)));
         u32 nlarge = h[C_LARGE], ltiles = h[C_LTILES], lelem = h[C_LELEM];
         Seg *LA = w.largeA, *LB = w.largeB;
         while (nlarge > 0) {
-            k_level_tiles<<<(unsigned)ceil_div(nlarge, 256), 256, 0, st>>>(LA, nlarge, TL, w.tstart, w.smin, w.smax,
-                                                                           w.ctr);
-            SS_CHECK_LAUNCH();
-            SS_TRY(ss_scan_exclusive<u32>(w.tstart, w.tstart, nlarge, (u32 *)w.scan_scratch, st));
-            {
-                SS_PROF("k_hist", st, (double)lelem * 8.0);  // read the keys
-                k_hist<<<ltiles, NT, 0, st>>>(LA, w.tstart, nlarge, TL, w.keyA, w.keyB, w.hist, w.smin, w.smax);
-            }
-            SS_CHECK_LAUNCH();
-            SS_TRY(ss_scan_exclusive<u32>(w.hist, w.hist, (u64)ltiles * 256, (u32 *)w.scan_scratch, st));
-            EmitOut eo{w.tiny, w.small, LB, w.nxt, w.ident, w.bnd, w.ctr, w.scat, w.kinds, SM, TL};
-            k_emit<<<(unsigned)ceil_div(nlarge, EPB), 256, 0, st>>>(LA, w.tstart, nlarge, w.hist, w.smin, w.smax,
-                                                                     eo);
-            SS_CHECK_LAUNCH();
-            {
-                SS_PROF("k_scatter", st, (double)lelem * 24.0);  // key+payload in and out
-                k_scatter<<<ltiles, NT, 0, st>>>(LA, w.tstart, nlarge, TL, w.hist, w.scat, w.keyA, J.vals, w.keyB,
-                                                  w.valB);
-            }
-            SS_CHECK_LAUNCH();
-            {
-                SS_PROF("k_settle", st, (double)lelem * 8.0);  // at most the scattered keys read back
-                k_settle<<<ltiles, NT, 0, st>>>(LA, w.tstart, nlarge, TL, w.scat, w.kinds, w.keyB, w.valB, w.keyA,
-                                                J.vals);
-            }
-            SS_CHECK_LAUNCH();
-            SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, st));
+            SS_TRY(radix_level(C, LA, LB, Known{true, nlarge}, Known{true, ltiles}, lelem));
+            SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, J.stream));
             nlarge = h[C_LARGE];
             ltiles = h[C_LTILES];
             lelem = h[C_LELEM];
             Seg *tmp = LA; LA = LB; LB = tmp;
         }
-        const u32 ntiny = h[C_TINY];
-        if (ntiny > 0) {
-            {
-                SS_PROF("k_wave_sort", st, (double)h[C_TINYN] * 28.0);  // key+payload in/out, LCP out
-                k_wave_sort<<<(unsigned)ceil_div(ntiny, WS_SPB), 256, 0, st>>>(w.tiny, ntiny, w.keyA, J.vals, w.keyB,
-                                                                               w.valB, lcp, w.nxt, w.ctr);
-            }
-            SS_CHECK_LAUNCH();
-        }
-        const u32 nsmall = h[C_SMALL];
-        if (nsmall > 0) {
-            k_sizes<<<(unsigned)ceil_div(nsmall, 256), 256, 0, st>>>(w.small, nsmall, w.spref);
-            SS_CHECK_LAUNCH();
-            SS_TRY(ss_scan_exclusive<u32>(w.spref, w.spref, nsmall, (u32 *)w.scan_scratch, st));
-            const u32 ntile = (u32)ceil_div(h[C_SMALLN], SM);
-            {
-                SS_PROF("k_lds_sort", st, (double)h[C_SMALLN] * 28.0);  // key+payload in/out, LCP out
-                k_lds_sort<<<ntile, LDS_NT, 0, st>>>(w.small, w.spref, nsmall, SM, w.keyA, J.vals, w.keyB, w.valB,
-                                                      lcp, w.nxt, w.ctr);
-            }
-            SS_CHECK_LAUNCH();
-        }
-        if (h[C_BND] > 0) {
-            k_boundary<<<(unsigned)ceil_div(h[C_BND], 256), 256, 0, st>>>(w.bnd, h[C_BND], w.keyA, lcp);
-            SS_CHECK_LAUNCH();
-        }
-        if (h[C_IDENT] > 0) {
-            SS_TRY(build_tiles(w.ident, h[C_IDENT], ETILE, w.tstart, w.scan_scratch, st));
-            k_ident<<<h[C_ITILES], NT, 0, st>>>(w.ident, w.tstart, h[C_IDENT], lcp);
-            SS_CHECK_LAUNCH();
-        }
-        SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, st));
+        SS_TRY(round_tail(C, h));
+        SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, J.stream));
         nact = h[C_NEXT];
         atiles = h[C_NTILES];
         round_elems = h[C_NELEM];
         Seg *tmp = w.act; w.act = w.nxt; w.nxt = tmp;
     }
+    return SS_OK;
+}
+
+// Device-driven rounds: `rounds` rounds of RADIX_LEVELS levels each are
+// enqueued with fixed grids and nothing is read back (the launch sequence can
+// be captured in a graph); rounds and levels without work find empty lists.
+// hdr[H_REMAIN] receives the number of segments still unresolved afterwards
+// (0: the sort is complete).
+#define RADIX_LEVELS 8  // a radix level consumes one of the key's 8 bytes
+__global__ void k_remaining(const u32 *ctr, u32 *hdr, u32 *status)
+{
+    hdr[H_REMAIN] = ctr[C_NEXT];
+    if (status) *status = ctr[C_NEXT];
+}
+
+static int sort_rounds_device(const SortJob &J, SortWs &w, u32 rounds, u32 *status)
+{
+    RoundCtx C{J, w, J.n_total, (u32)g_small_max, (u32)g_tile};
+    const Known unknown{false, 0};
+    for (u32 r = 0; r < rounds; r++) {
+        SS_TRY(round_head(C, unknown, unknown, 0));
+        Seg *LA = w.largeA, *LB = w.largeB;
+        for (u32 l = 0; l < RADIX_LEVELS; l++) {
+            SS_TRY(radix_level(C, LA, LB, unknown, unknown, 0));
+            Seg *tmp = LA; LA = LB; LB = tmp;
+        }
+        SS_TRY(round_tail(C, nullptr));
+        Seg *tmp = w.act; w.act = w.nxt; w.nxt = tmp;
+    }
+    k_remaining<<<1, 1, 0, J.stream>>>(w.ctr, w.hdr, status);
+    SS_CHECK_LAUNCH();
     return SS_OK;
 }
 
@@ -1174,16 +1333,27 @@ __global__ void k_iota(u32 *p, u32 n)
     if (i < n) p[i] = i;
 }
 
-__global__ void k_init_single(Seg *act, u32 n, u32 *lcp)
+__global__ void k_zero_u32(u32 *p, u32 count)
+{
+    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
+// The whole array as the first round's one segment (n >= 2), with its counts.
+__global__ void k_init_single(Seg *act, u32 n, u32 *lcp, u32 *ctr)
 {
     act[0] = Seg{0, n, 0, SEG_SKIP};
     lcp[0] = 0;
+    for (u32 j = 0; j < C_NCTR; j++) ctr[j] = 0;
+    ctr[C_NEXT] = 1;
+    ctr[C_NTILES] = (n + ETILE - 1) / ETILE;
+    ctr[C_NELEM] = n;
 }
 
-// One segment per set of two or more strings.  A set whose bounds are not
-// well placed (set_off non-decreasing from 0 to n) raises ctr[C_BADSET] and
-// writes nothing, so a malformed set_off never leads outside the arrays; the
-// host reads the flag with the counters.
+// One segment per set of two or more strings (the counters are zero before).
+// A set whose bounds are not well placed (set_off non-decreasing from 0 to n)
+// raises ctr[C_BADSET] and writes nothing, so a malformed set_off never leads
+// outside the arrays.
 __global__ void k_init_sets(const u64 *set_off, u32 nsets, u64 n, Seg *act, u32 *ctr, u32 *lcp)
 {
     u32 j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1205,6 +1375,18 @@ __global__ void k_init_sets(const u64 *set_off, u32 nsets, u64 n, Seg *act, u32 
     if (two) act[a] = Seg{b, e, 0, SEG_SKIP};
     wave_add(two ? (e - b + ETILE - 1) / ETILE : 0u, &ctr[C_NTILES]);
     wave_add(two ? e - b : 0u, &ctr[C_NELEM]);
+}
+
+// A malformed set_off found by k_init_sets leaves no segment to sort: every
+// set's work is dropped (nothing is written beyond the initial identity).
+__global__ void k_drop_if_bad(u32 *ctr, u32 *status)
+{
+    if (ctr[C_BADSET]) {
+        ctr[C_NEXT] = 0;
+        ctr[C_NTILES] = 0;
+        ctr[C_NELEM] = 0;
+    }
+    if (status) status[1] = ctr[C_BADSET] ? 1u : 0u;
 }
 
 __global__ void k_localize(const u64 *set_off, u32 nsets, u32 n, u32 *perm)
@@ -1297,20 +1479,20 @@ extern "C" int ss_sort(const uint8_t *bytes, uint64_t N, const uint64_t *offsets
         SS_CHECK_LAUNCH();
         return SS_OK;
     }
-    SortJob J{bytes, N, offsets, perm, lcp ? lcp : w.lcp_scratch, st, n};
+    SortJob J{bytes, N, offsets, perm, lcp ? lcp : w.lcp_scratch, st, n, n};
     k_iota<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(perm, (u32)n);
     SS_CHECK_LAUNCH();
-    k_init_single<<<1, 1, 0, st>>>(w.act, (u32)n, J.lcp);
+    k_init_single<<<1, 1, 0, st>>>(w.act, (u32)n, J.lcp, w.ctr);
     SS_CHECK_LAUNCH();
-    return sort_rounds(J, w, n >= 2 ? 1 : 0, (u32)ceil_div(n, ETILE));
+    return sort_rounds(J, w, 1, (u32)ceil_div(n, ETILE));
 }
 
-extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
-                             const uint64_t *set_off, uint32_t num_sets, uint32_t *perm_local,
-                             uint32_t *lcp, uint32_t flags, void *ws, size_t ws_bytes, void *stream)
+// The checks and first-round set-up shared by both batch forms.
+static int batch_setup(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                       const uint64_t *set_off, uint32_t num_sets, uint32_t *perm, uint32_t *lcp, uint32_t flags,
+                       void *ws, size_t ws_bytes, hipStream_t st, SortWs &w, SortJob &J)
 {
-    ss_clear_error();
-    SS_TRY(sort_common_checks(bytes, offsets, n, perm_local));
+    SS_TRY(sort_common_checks(bytes, offsets, n, perm));
     if (num_sets == 0 || !set_off) {
         ss_set_error("batch needs num_sets >= 1 and set_off");
         return SS_ERR_INVALID_ARG;
@@ -1320,20 +1502,32 @@ extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *o
         return SS_ERR_INVALID_ARG;
     }
     if (n == 0) return SS_OK;
-    hipStream_t st = (hipStream_t)stream;
     WsArena a(ws, ws_bytes);
-    SortWs w;
     sort_ws_layout(n, &w, &a, nullptr);
     if (a.overflow || !ws) {
         ss_set_error("workspace too small: need %zu bytes", ss_sort_workspace(n));
         return SS_ERR_WORKSPACE;
     }
-    SortJob J{bytes, N, offsets, perm_local, lcp ? lcp : w.lcp_scratch, st, 0};
-    k_iota<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(perm_local, (u32)n);
+    J = SortJob{bytes, N, offsets, perm, lcp ? lcp : w.lcp_scratch, st, 0, n};
+    k_iota<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(perm, (u32)n);
     SS_CHECK_LAUNCH();
-    SS_HIP(hipMemsetAsync(w.ctr, 0, sizeof(u32) * C_NCTR, st));
+    k_zero_u32<<<1, 64, 0, st>>>(w.ctr, C_NCTR);
+    SS_CHECK_LAUNCH();
     k_init_sets<<<(unsigned)ceil_div(num_sets, 256), 256, 0, st>>>(set_off, num_sets, n, w.act, w.ctr, J.lcp);
     SS_CHECK_LAUNCH();
+    return SS_OK;
+}
+
+extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                             const uint64_t *set_off, uint32_t num_sets, uint32_t *perm_local,
+                             uint32_t *lcp, uint32_t flags, void *ws, size_t ws_bytes, void *stream)
+{
+    ss_clear_error();
+    hipStream_t st = (hipStream_t)stream;
+    SortWs w;
+    SortJob J{};
+    SS_TRY(batch_setup(bytes, N, offsets, n, set_off, num_sets, perm_local, lcp, flags, ws, ws_bytes, st, w, J));
+    if (n == 0) return SS_OK;
     u32 h[C_NCTR];
     SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, st));
     if (h[C_BADSET]) {
@@ -1342,6 +1536,45 @@ extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *o
     }
     J.n_first = h[C_NELEM];
     SS_TRY(sort_rounds(J, w, h[C_NEXT], h[C_NTILES]));
+    if (!(flags & SS_BATCH_GLOBAL_IDS)) {
+        k_localize<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(set_off, num_sets, (u32)n, perm_local);
+        SS_CHECK_LAUNCH();
+    }
+    return SS_OK;
+}
+
+extern "C" uint32_t ss_sort_batch_device_rounds(uint32_t max_len)
+{
+    // a round consumes at least 7 bytes of every string it keeps
+    return max_len / 7 + 2;
+}
+
+extern "C" int ss_sort_batch_device(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                                    const uint64_t *set_off, uint32_t num_sets, uint32_t *perm_local,
+                                    uint32_t *lcp, uint32_t flags, uint32_t rounds, uint32_t *status, void *ws,
+                                    size_t ws_bytes, void *stream)
+{
+    ss_clear_error();
+    if (!status) {
+        ss_set_error("status is required");
+        return SS_ERR_INVALID_ARG;
+    }
+    if (rounds == 0 || rounds > 1024) {
+        ss_set_error("rounds must be 1..1024");
+        return SS_ERR_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    SortWs w;
+    SortJob J{};
+    SS_TRY(batch_setup(bytes, N, offsets, n, set_off, num_sets, perm_local, lcp, flags, ws, ws_bytes, st, w, J));
+    if (n == 0) {
+        k_zero_u32<<<1, 64, 0, st>>>(status, 2);
+        SS_CHECK_LAUNCH();
+        return SS_OK;
+    }
+    k_drop_if_bad<<<1, 1, 0, st>>>(w.ctr, status);
+    SS_CHECK_LAUNCH();
+    SS_TRY(sort_rounds_device(J, w, rounds, status));
     if (!(flags & SS_BATCH_GLOBAL_IDS)) {
         k_localize<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(set_off, num_sets, (u32)n, perm_local);
         SS_CHECK_LAUNCH();

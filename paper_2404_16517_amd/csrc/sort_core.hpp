@@ -24,7 +24,9 @@ struct SortWs {
     u8 *kinds;  // per radix segment and digit: what the bucket became
     u32 *tstart, *spref, *hist;
     u64 *scan_scratch;
+    u32 *dscan;  // scratch of the device-length scans
     u32 *ctr;
+    u32 *hdr;    // list lengths of the current round and level (device)
 };
 
 struct SortJob {
@@ -35,8 +37,10 @@ struct SortJob {
     u32 *lcp;   // LCP output
     hipStream_t stream;
     u64 n_first;  // strings in the first round's segments (for byte accounting)
+    u64 n_total;  // strings of the whole sort (bounds every list)
 };
 
 void sort_ws_layout(u64 n, SortWs *w, WsArena *a, WsCounter *c);
-// nact segments in w.act covering `atiles` element tiles of 2048.
+// Host-driven rounds from nact segments in w.act covering `atiles` element
+// tiles of 2048 (their count, tiles and strings also in the counters).
 int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles);

@@ -335,6 +335,87 @@ template <class T> int ss_scan_exclusive(const T *in, T *out, u64 n, T *scratch,
     return SS_OK;
 }
 
+// Scans whose length is read on the device (n = *n_dev * mult), for launch
+// sequences that must not read counts back (captured graphs).  A fixed grid
+// of SCAN_DEV_G workgroups: workgroup b takes the contiguous range
+// [b*per, (b+1)*per) with per = ceil(n / SCAN_DEV_G), sums it (phase 1), one
+// workgroup scans the SCAN_DEV_G sums (phase 2), and every workgroup scans its
+// range from its offset in chunks of SCAN_ITEMS (phase 3).
+#define SCAN_DEV_G 1024
+
+__device__ __forceinline__ u64 scan_dev_n(const u32 *n_dev, u32 mult) { return (u64)(*n_dev) * mult; }
+
+template <class T>
+__global__ __launch_bounds__(SCAN_NT) void k_scand_reduce(const T *in, const u32 *n_dev, u32 mult, T *part)
+{
+    const u64 n = scan_dev_n(n_dev, mult);
+    const u64 per = (n + SCAN_DEV_G - 1) / SCAN_DEV_G;
+    const u64 c0 = blockIdx.x * per, c1 = (c0 + per < n) ? c0 + per : n;
+    T sacc = 0;
+    for (u64 i = c0 + threadIdx.x; i < c1; i += SCAN_NT) sacc += in[i];
+    T tot;
+    (void)block_excl_scan<T, SCAN_NT>(sacc, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+template <class T>
+__global__ __launch_bounds__(SCAN_DEV_G) void k_scand_top(T *part, const u32 *n_dev, u32 mult, T *out)
+{
+    const T v = part[threadIdx.x];
+    T tot;
+    const T x = block_excl_scan<T, SCAN_DEV_G>(v, &tot);
+    part[threadIdx.x] = x;
+    if (threadIdx.x == 0) out[scan_dev_n(n_dev, mult)] = tot;
+}
+
+template <class T>
+__global__ __launch_bounds__(SCAN_NT) void k_scand_apply(const T *in, T *out, const u32 *n_dev, u32 mult,
+                                                         const T *part)
+{
+    const u64 n = scan_dev_n(n_dev, mult);
+    const u64 per = (n + SCAN_DEV_G - 1) / SCAN_DEV_G;
+    const u64 c0 = blockIdx.x * per, c1 = (c0 + per < n) ? c0 + per : n;
+    T carry = part[blockIdx.x];
+    for (u64 b = c0; b < c1; b += SCAN_ITEMS) {
+        const u64 e = (b + SCAN_ITEMS < c1) ? b + SCAN_ITEMS : c1;
+        // blocked: thread t takes SCAN_PER consecutive items
+        const u64 t0 = b + (u64)threadIdx.x * SCAN_PER;
+        T v[SCAN_PER];
+        T sacc = 0;
+#pragma unroll
+        for (int q = 0; q < SCAN_PER; q++) {
+            v[q] = (t0 + q < e) ? in[t0 + q] : (T)0;
+            sacc += v[q];
+        }
+        T tot;
+        T pre = block_excl_scan<T, SCAN_NT>(sacc, &tot) + carry;
+#pragma unroll
+        for (int q = 0; q < SCAN_PER; q++) {
+            if (t0 + q < e) out[t0 + q] = pre;
+            pre += v[q];
+        }
+        carry += tot;
+        __syncthreads();  // (in may alias out: the next chunk's reads follow every write)
+    }
+}
+
+template <class T> u64 ss_scan_dev_scratch_elems() { return SCAN_DEV_G; }
+
+template <class T> int ss_scan_exclusive_dev(const T *in, T *out, const u32 *n_dev, u32 mult, T *scratch,
+                                             hipStream_t s)
+{
+    k_scand_reduce<T><<<SCAN_DEV_G, SCAN_NT, 0, s>>>(in, n_dev, mult, scratch);
+    SS_CHECK_LAUNCH();
+    k_scand_top<T><<<1, SCAN_DEV_G, 0, s>>>(scratch, n_dev, mult, out);
+    SS_CHECK_LAUNCH();
+    k_scand_apply<T><<<SCAN_DEV_G, SCAN_NT, 0, s>>>(in, out, n_dev, mult, scratch);
+    SS_CHECK_LAUNCH();
+    return SS_OK;
+}
+
+template u64 ss_scan_dev_scratch_elems<u32>();
+template int ss_scan_exclusive_dev<u32>(const u32 *, u32 *, const u32 *, u32, u32 *, hipStream_t);
+
 template u64 ss_scan_scratch_elems<u32>(u64);
 template u64 ss_scan_scratch_elems<u64>(u64);
 template int ss_scan_exclusive<u32>(const u32 *, u32 *, u64, u32 *, hipStream_t);
