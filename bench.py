@@ -45,6 +45,8 @@ class Pipeline:
         self.B, self.O, self.p, self.v, self.ss, self.torch = B, O, p, v, ss, torch
         dev = B.device
         self.overlap = overlap
+        self.ms_mode = False  # True: the paper's MS (full strings, no prefix doubling) instead of PDMS
+        self.literal_bytes = 0
         if overlap:
             self.side = torch.cuda.Stream(device=dev)
             self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=1)
@@ -64,7 +66,9 @@ class Pipeline:
         # 1. prefix doubling over all strings (on the side stream: it shares
         #    nothing with 2 and 3 but the input, and its host thread's waits
         #    for its own read-backs do not hold up the sort's launches)
-        if self.overlap:
+        if self.ms_mode:
+            dpx, rounds = None, 0
+        elif self.overlap:
             main = torch.cuda.current_stream()
             self.side.wait_stream(main)
             fut = self.pool.submit(self._dist_prefix, marks)
@@ -81,7 +85,7 @@ class Pipeline:
         fid = ss.select_splitters(sperm, p)
         fb, fo = ss.gather_strings(sb, so, fid)
         ev("splitters")
-        if self.overlap:
+        if self.overlap and not self.ms_mode:
             dpx, rounds = fut.result()
             main.wait_stream(self.side)
             dpx.record_stream(main)
@@ -89,6 +93,7 @@ class Pipeline:
         # 4. every PE splits its array into p buckets and front-codes the
         #    distinguishing prefixes (all PEs in one batched call)
         fc = ss.partition_encode_batch(B, O, self.set_off, perm, lcp, dpx, fb, fo, ws=self.ws_pe)
+        self.literal_bytes = fc["total"]
         ev("partition_encode")
         # 5. bucket j merges run (i, j) of every PE i: all p merges in one call
         ro = fc["run_off"].view(p, p + 1)                              # [PE, bucket bound], absolute
@@ -153,20 +158,56 @@ def verify_dn(s, order, mlcp, dist, dpx):
     return bool(ok)
 
 
-def batch_leg(ss, torch, synth, num_sets=1024, lo=1e3, hi=1e5, reps=3):
-    """Many independent sorts: one batched launch sequence vs one call per set."""
+def batch_leg(ss, torch, synth, num_sets=4096, lo=1e3, hi=1e6, len_lo=8, len_hi=256, reps=3, graph_rounds=3):
+    """Many independent sorts (+ LCP): the device-driven batch sort captured in
+    a graph and replayed, the host-driven batch sort, and one call per set, at
+    equal output; a few sets are also checked against the oracle."""
+    import numpy as np
+    import oracle
     dev = torch.device("cuda:0")
-    S, bounds = synth.random_sets(num_sets, lo, hi, seed=5, device=dev)
+    S, bounds = synth.random_sets(num_sets, lo, hi, len_lo, len_hi, seed=5, device=dev)
     bl = bounds.tolist()
     bd = bounds.to(dev)
-    ws = torch.empty(ss.lib().ss_sort_workspace(S.n), dtype=torch.uint8, device=dev)
+    n = S.n
+    ws = torch.empty(ss.lib().ss_sort_workspace(n), dtype=torch.uint8, device=dev)
+    # host-driven batch (reads counts back between levels)
     pb, lb = ss.sort_batch(S.bytes, S.offsets, bd, ws=ws)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
         pb, lb = ss.sort_batch(S.bytes, S.offsets, bd, ws=ws)
     torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / reps
+    t_host = (time.perf_counter() - t0) / reps
+    # device-driven batch captured once (a few rounds: enough for these
+    # strings unless 7-byte runs repeat), replayed; the status word is read
+    # after each replay and an incomplete sort would be finished host-driven
+    pg = torch.empty(n, dtype=torch.int32, device=dev)
+    lg = torch.empty(n, dtype=torch.int32, device=dev)
+    status = torch.full((2,), -1, dtype=torch.int32, device=dev)
+    st = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()
+    graph = ss.Graph.capture(lambda: ss.sort_batch_device(S.bytes, S.offsets, bd, pg, lg, status, ws,
+                                                           graph_rounds), st)
+    continued = 0
+
+    def replay():
+        nonlocal continued
+        graph.launch(st)
+        st.synchronize()
+        if status[0].item() != 0:
+            continued += 1
+            with torch.cuda.stream(st):
+                ss.sort_batch(S.bytes, S.offsets, bd, ws=ws, out=(pg, lg))
+            st.synchronize()
+    replay()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        replay()
+    t_graph = (time.perf_counter() - t0) / reps
+    nodes = graph.nodes()
+    graph.close()
+    complete = status[1].item() == 0
+    same_graph = torch.equal(pg, pb) and torch.equal(lg, lb)
 
     def per_job():
         outs = []
@@ -176,22 +217,47 @@ def batch_leg(ss, torch, synth, num_sets=1024, lo=1e3, hi=1e5, reps=3):
     per_job()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(reps):
-        outs = per_job()
+    outs = per_job()
     torch.cuda.synchronize()
-    tj = (time.perf_counter() - t0) / reps
-    same = torch.equal(torch.cat([o[0] for o in outs]), pb) and torch.equal(torch.cat([o[1] for o in outs]), lb)
-    return {"sets": num_sets, "set_sizes": f"log-uniform [{lo:.0f}, {hi:.0f}]", "strings": S.n, "bytes": S.N,
-            "batched_jobs_per_s": num_sets / tb, "per_job_jobs_per_s": num_sets / tj, "speedup": tj / tb,
-            "batched_GBps": S.N / tb / 1e9, "results_identical": bool(same)}
+    t_job = time.perf_counter() - t0
+    same_job = torch.equal(torch.cat([o[0] for o in outs]), pb) and torch.equal(torch.cat([o[1] for o in outs]), lb)
+    del outs
+    sizes = np.diff(np.array(bl))
+    checked = sorted({0, num_sets // 2, int(np.argmin(sizes)), int(np.argmax(sizes))})
+    oracle_ok = True
+    for j in checked:
+        a, c = bl[j], bl[j + 1]
+        b0, b1 = int(S.offsets[a]), int(S.offsets[c])
+        hb = S.bytes[b0:b1].cpu().numpy()
+        ho = (S.offsets[a:c + 1] - b0).cpu().numpy().view(np.uint64)
+        p_ref = oracle.sort(hb, ho)
+        oracle_ok &= bool(np.array_equal(pg[a:c].cpu().numpy().view(np.uint32), p_ref))
+        oracle_ok &= bool(np.array_equal(lg[a:c].cpu().numpy().view(np.uint32), oracle.lcp(hb, ho, p_ref)))
+    out = {"sets": num_sets, "set_sizes": f"log-uniform [{lo:.0f}, {hi:.0f}] strings",
+           "lengths": f"uniform [{len_lo}, {len_hi}] bytes, 'A'..'Z'", "strings": n, "bytes": S.N,
+           "graph_sets_per_s": num_sets / t_graph, "host_driven_sets_per_s": num_sets / t_host,
+           "per_set_call_sets_per_s": num_sets / t_job,
+           "graph_speedup_over_per_set_calls": t_job / t_graph, "graph_ms": t_graph * 1e3,
+           "host_driven_ms": t_host * 1e3, "per_set_calls_ms": t_job * 1e3,
+           "graph_GBps": S.N / t_graph / 1e9, "graph_strings_per_s": n / t_graph,
+           "graph_rounds": graph_rounds, "graph_nodes": nodes, "graph_status_ok": complete,
+           "graph_replays_continued_host_driven": continued,
+           "results_identical": bool(same_graph and same_job),
+           "oracle_checked_sets": checked, "oracle_agrees": oracle_ok}
+    del S, ws, pb, lb, pg, lg
+    torch.cuda.empty_cache()
+    return out
 
 
-def serve_leg(ss, torch, synth, count=48, lo=1e3, hi=1e6, budget_gb=200.0, slots=4, load=0.7):
-    """Sort requests served with continuous batching (`slots` concurrent
-    streams, HBM-budget admission) against one job at a time, at equal output:
-    throughput with every request queued at once, and latency of a Poisson
-    trace offered at `load` x the one-at-a-time capacity (both servers replay
-    the same trace).  Each served result must equal the job run alone."""
+def serve_leg(ss, torch, synth, count=200, lo=1e3, hi=1e7, budget_gb=200.0, tight_gb=4.0, slots=4, load=0.7):
+    """Sort requests (sort + LCP + exact and approximate distinguishing
+    prefixes) served with continuous batching (`slots` concurrent streams,
+    HBM-budget admission, results held on the device until the client takes
+    them) against one job at a time, at equal output: throughput with every
+    request queued at once (with the stated budget, and with a tight one that
+    makes admission wait), and latency of a Poisson trace offered at `load` x
+    the one-at-a-time capacity (both servers replay the same trace).  Every
+    served result must equal the job run alone."""
     from paper_2404_16517_amd import serve
     dev = torch.device("cuda:0")
     reqs = synth.poisson_requests(count, qps=1.0, size_lo=lo, size_hi=hi, seed=7)
@@ -201,33 +267,64 @@ def serve_leg(ss, torch, synth, count=48, lo=1e3, hi=1e6, budget_gb=200.0, slots
     serve.serve_sequential(reqs[:4], inputs)  # warm-up
     alone, t_seq = serve.serve_sequential(reqs, inputs)
     capacity = count / t_seq
+    mismatch = []
+
+    def check(job):
+        if not all(torch.equal(a, b) for a, b in zip(job.result, alone[job.rid])):
+            mismatch.append(job.rid)
     # saturation: all requests waiting at t = 0
-    jobs_sat, span_sat = serve.serve_trace(reqs, inputs, budget, slots=slots, time_scale=0.0)
+    jobs_sat, span_sat = serve.serve_trace(reqs, inputs, budget, slots=slots, time_scale=0.0, on_done=check)
     _, span_one = serve.serve_trace(reqs, inputs, budget, slots=1, time_scale=0.0)
+    largest = max(serve.job_bytes(x.n, x.N)[0] for x in inputs.values())
+    tight = max(int(tight_gb * 1e9), largest)
+    jobs_tight, span_tight = serve.serve_trace(reqs, inputs, tight, slots=slots, time_scale=0.0, on_done=check)
+    waited = sum(1 for j in jobs_tight if j.admitted_s > 1e-3)
     # latency at a fixed offered load
     scale = 1.0 / (capacity * load)
-    jobs, makespan = serve.serve_trace(reqs, inputs, budget, slots=slots, time_scale=scale)
+    jobs, makespan = serve.serve_trace(reqs, inputs, budget, slots=slots, time_scale=scale, on_done=check)
     jobs1, _ = serve.serve_trace(reqs, inputs, budget, slots=1, time_scale=scale)
     lat = [j.done_s - j.arrival_s for j in jobs]
     lat1 = [j.done_s - j.arrival_s for j in jobs1]
-    same = all(all(torch.equal(a, b) for a, b in zip(j.result, alone[j.rid])) for j in jobs + jobs_sat)
     total_bytes = sum(x.N for x in inputs.values())
-    return {"requests": count, "sizes": f"log-uniform [{lo:.0f}, {hi:.0f}] strings", "slots": slots,
-            "budget_GB": budget_gb,
-            "saturated_jobs_per_s": count / span_sat, "one_at_a_time_jobs_per_s": count / span_one,
-            "saturated_speedup": span_one / span_sat, "saturated_GBps": total_bytes / span_sat / 1e9,
-            "offered_qps": capacity * load,
-            "p50_ms": serve.percentile(lat, 0.5) * 1e3, "p99_ms": serve.percentile(lat, 0.99) * 1e3,
-            "one_at_a_time_p50_ms": serve.percentile(lat1, 0.5) * 1e3,
-            "one_at_a_time_p99_ms": serve.percentile(lat1, 0.99) * 1e3,
-            "results_identical": bool(same)}
+    total_strings = sum(x.n for x in inputs.values())
+    out = {"requests": count, "sizes": f"log-uniform [{lo:.0f}, {hi:.0f}] strings", "strings": total_strings,
+           "bytes": total_bytes, "slots": slots, "budget_GB": budget_gb,
+           "saturated_jobs_per_s": count / span_sat, "one_at_a_time_jobs_per_s": count / span_one,
+           "saturated_speedup": span_one / span_sat, "saturated_GBps": total_bytes / span_sat / 1e9,
+           "tight_budget_GB": tight / 1e9, "tight_jobs_per_s": count / span_tight,
+           "tight_requests_that_waited": waited,
+           "offered_qps": capacity * load,
+           "p50_ms": serve.percentile(lat, 0.5) * 1e3, "p99_ms": serve.percentile(lat, 0.99) * 1e3,
+           "one_at_a_time_p50_ms": serve.percentile(lat1, 0.5) * 1e3,
+           "one_at_a_time_p99_ms": serve.percentile(lat1, 0.99) * 1e3,
+           "results_identical": not mismatch}
+    del inputs, alone, jobs_sat, jobs_tight, jobs, jobs1
+    torch.cuda.empty_cache()
+    return out
 
 
-def cpu_baseline(s_host, p, v, target_s=15.0):
-    """The CPU oracle running the same step on a bounded prefix of the input."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(s_host, p, v, target_s=10.0, threads=1):
+    """The CPU oracle running the same step on a bounded prefix of the input.
+    With threads > 1 the independent parts run concurrently (the per-PE sorts,
+    bucket encodings and per-bucket merges; the oracle's C calls release the
+    GIL); prefix doubling and the final LCP pass stay single-threaded, as the
+    oracle has them."""
     import numpy as np
     import oracle
     b_all, o_all = oracle.strings_np(s_host)
+    pool = concurrent.futures.ThreadPoolExecutor(max_workers=threads) if threads > 1 else None
+    pmap = (lambda f, xs: list(pool.map(f, xs))) if pool else (lambda f, xs: [f(x) for x in xs])
 
     def run(ns):
         o = o_all[:ns + 1].copy()
@@ -235,13 +332,16 @@ def cpu_baseline(s_host, p, v, target_s=15.0):
         bounds = [ns * i // p for i in range(p + 1)]
         t0 = time.perf_counter()
         dpx, _, _ = oracle.dist_prefix(b, o, 8, 64)
-        perms, lcps = [], []
-        for a, e in zip(bounds[:-1], bounds[1:]):
+
+        def sort_pe(ae):
+            a, e = ae
             so = o[a:e + 1] - o[a]
             sb = b[int(o[a]):int(o[e])]
             pl = oracle.sort(sb, so)
-            perms.append(pl.astype(np.uint32) + np.uint32(a))
-            lcps.append(oracle.lcp(sb, so, pl))
+            return pl.astype(np.uint32) + np.uint32(a), oracle.lcp(sb, so, pl)
+        res = pmap(sort_pe, list(zip(bounds[:-1], bounds[1:])))
+        perms = [r[0] for r in res]
+        lcps = [r[1] for r in res]
         samp = np.concatenate([oracle.select_splitters(len(pm), pm, v + 2) for pm in perms])
         strs = [bytes(b[int(o[i]):int(o[i + 1])]) for i in samp]
         sl = np.cumsum([0] + [len(x) for x in strs]).astype(np.uint64)
@@ -251,12 +351,14 @@ def cpu_baseline(s_host, p, v, target_s=15.0):
         spl = [strs[i] for i in fid]
         fl = np.cumsum([0] + [len(x) for x in spl]).astype(np.uint64)
         fbytes = np.frombuffer(b"".join(spl) or b"\0", np.uint8)
-        encs = []
-        for pm, lc in zip(perms, lcps):
+
+        def encode_pe(pl):
+            pm, lc = pl
             bb = oracle.bucket_bounds(b, o, pm, fbytes, fl)
-            encs.append((bb, oracle.fc_encode(b, o, pm, lc, dpx, bb)))
-        out_ids = []
-        for j in range(p):
+            return bb, oracle.fc_encode(b, o, pm, lc, dpx, bb)
+        encs = pmap(encode_pe, list(zip(perms, lcps)))
+
+        def merge_bucket(j):
             ro, LC, LN, ID, SO, SUF, base = [0], [], [], [], [], [], 0
             for bb, enc in encs:
                 x, y = int(bb[j]), int(bb[j + 1])
@@ -265,24 +367,28 @@ def cpu_baseline(s_host, p, v, target_s=15.0):
                 SUF.append(enc["suf"][int(enc["suf_off"][x]):int(enc["suf_off"][y])])
                 base += int(enc["suf_off"][y] - enc["suf_off"][x])
                 ro.append(ro[-1] + y - x)
-            if ro[-1]:
-                _, ids, _ = oracle.merge(np.array(ro, np.uint64), np.concatenate(LC), np.concatenate(LN),
-                                         np.concatenate(ID), np.concatenate(SO + [np.array([base], np.uint64)]),
-                                         np.concatenate(SUF))
-                out_ids.append(ids)
-        order = np.concatenate(out_ids)
+            if not ro[-1]:
+                return np.zeros(0, np.uint32)
+            _, ids, _ = oracle.merge(np.array(ro, np.uint64), np.concatenate(LC), np.concatenate(LN),
+                                     np.concatenate(ID), np.concatenate(SO + [np.array([base], np.uint64)]),
+                                     np.concatenate(SUF))
+            return ids
+        order = np.concatenate(pmap(merge_bucket, list(range(p))))
         full_lcp = oracle.lcp(b, o, order)
         oracle.dist_exact(o, order, full_lcp)
         return time.perf_counter() - t0, int(o[-1])
 
     ns = 20_000
     dt, nbytes = run(ns)
-    while dt < target_s / 4 and ns < s_host.n // 2:
+    while dt < target_s / 4 and ns < s_host.n:
         ns = min(s_host.n, int(ns * min(8.0, max(1.5, target_s / max(dt, 1e-3) * 0.8))))
         dt, nbytes = run(ns)
-    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+    if pool:
+        pool.shutdown()
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
             "sample": f"first {ns} strings ({nbytes} bytes) of the same workload, same step with p={p}, "
-                      f"single-threaded C oracle, {dt:.1f} s"}
+                      f"C oracle on {threads} thread(s), {dt:.1f} s; host: {ncpu} CPUs available, {_cpu_model()}"}
 
 
 # Kernel -> the source files its code comes from (for the staleness check of
@@ -325,6 +431,44 @@ def committed_traffic(kernel, args):
     return per
 
 
+def pass_rooflines(stage_ms, n, D, D_approx, active_sum, literal):
+    """Per-pass achieved bandwidth with each pass's algorithmic bytes: what the
+    pass must move, independent of how the kernels do it --
+      sort+LCP          D + 16n (each distinguishing prefix read once, offsets
+                        8 B, perm and LCP written 4 + 4 B per string);
+      dist_prefix       D_approx + 16 sum_t |A_t| (every round's key written
+                        and read) + 12n (offsets, result);
+      partition_encode  32n + 2 sum(d - e) (metadata in and out, every
+                        literal byte read and written once);
+      lcp_merge         28n + sum(d - e) (front-coded metadata and literals
+                        in, order and LCP out)."""
+    def entry(ms, by):
+        gbs = by / (ms / 1e3) / 1e9 if ms and ms > 0 else None
+        return {"ms": ms, "algorithmic_bytes": by, "achieved_GBps": gbs,
+                "frac": gbs / HBM_PEAK_GBS if gbs else None}
+    return {"sort+lcp": entry(stage_ms.get("sort_batch+lcp"), D + 16 * n),
+            "dist_prefix": entry(stage_ms.get("dist_prefix"), D_approx + 16 * active_sum + 12 * n),
+            "partition_encode": entry(stage_ms.get("partition_encode"), 32 * n + 2 * literal),
+            "lcp_merge": entry(stage_ms.get("lcp_merge"), 28 * n + literal)}
+
+
+def doubling_active_sum(dpx, l0=8):
+    """sum over rounds of the active strings: a string with approximate
+    distinguishing prefix d took part in every round up to the first whose
+    length l0 * 2^(t-1) reaches d (Section 4's finish rule)."""
+    import numpy as np
+    d = dpx.cpu().numpy().view(np.uint32).astype(np.int64)
+    t = np.ones_like(d)
+    L = np.full_like(d, l0)
+    while True:
+        m = d > L
+        if not m.any():
+            break
+        t[m] += 1
+        L[m] *= 2
+    return int(t.sum())
+
+
 def roofline(prof, steps, args):
     """Roofline object of the kernel with the largest event time."""
     name = max(prof, key=lambda k: prof[k][0])
@@ -356,6 +500,7 @@ def main():
                          "stream beside the sort, and per-kernel times include the other stream's kernels)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-per-job leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-ms-mode", action="store_true", help="skip the full-string (MS) step")
     ap.add_argument("--no-profile", action="store_true",
                     help="time the steps without the per-launch events (no roofline)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GB",
@@ -435,7 +580,9 @@ def main():
     if prof:
         out["roofline"] = roofline(prof, args.steps, args)
         out["kernels_ms_per_step"] = {k: v[0] / args.steps for k, v in sorted(prof.items(), key=lambda x: -x[1][0])}
-        out["kernels_gbs"] = {k: (v[1] / (v[0] / 1e3) / 1e9 if v[0] > 0 else None) for k, v in prof.items()}
+        # each kernel's own bytes (its reads and writes as implemented, e.g.
+        # 40 B per element per merge level), not the pass formulas
+        out["kernels_impl_gbs"] = {k: (v[1] / (v[0] / 1e3) / 1e9 if v[0] > 0 else None) for k, v in prof.items()}
         if pipe.overlap and not args.no_one_stream:
             # The same kernels with the step on one stream (a few extra steps
             # after the timed ones): each kernel's time without the other
@@ -445,8 +592,13 @@ def main():
             torch.cuda.synchronize()
             ss.profile_enable(True)
             serial_steps = 3
+            sstages = {}
             for _ in range(serial_steps):
-                pipe.step(Marks(torch, False))
+                mk = Marks(torch, True)
+                res1 = pipe.step(mk)
+                torch.cuda.synchronize()
+                for k, v in mk.times().items():
+                    sstages.setdefault(k, []).append(v)
             torch.cuda.synchronize()
             sprof = ss.profile_report()
             ss.profile_enable(False)
@@ -454,8 +606,36 @@ def main():
             out["roofline_one_stream"] = roofline(sprof, serial_steps, args)
             out["kernels_ms_per_step_one_stream"] = {k: v[0] / serial_steps for k, v in
                                                      sorted(sprof.items(), key=lambda x: -x[1][0])}
+            stage_ms = {k: sorted(v)[len(v) // 2] for k, v in sstages.items()}
+            _, _, dist1, dpx1, _ = res1
+            D = int(dist1.to(torch.int64).sum())
+            Dx = int(dpx1.to(torch.int64).sum())
+            out["roofline"]["passes"] = pass_rooflines(stage_ms, s.n, D, Dx, doubling_active_sum(dpx1),
+                                                       pipe.literal_bytes)
+            out["roofline"]["passes_note"] = ("one-stream steps, median stage time (events on the stream), "
+                                              "algorithmic bytes per pass; D = %d, D_approx = %d" % (D, Dx))
+            out["stages_ms_one_stream"] = stage_ms
     if args.stages:
         out["stages_ms"] = {k: sum(v) / len(v) for k, v in stages.items()}
+    if not args.no_ms_mode:
+        # the paper's MS beside PDMS: the same step on full strings (no prefix
+        # doubling), and the front-coded bytes each mode moves per string
+        out["front_coded_bytes_per_string"] = {"pdms": pipe.literal_bytes / s.n + 12.0}
+        pipe.overlap, was = False, pipe.overlap
+        pipe.ms_mode = True
+        pipe.step(Marks(torch, False))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            pipe.step(Marks(torch, False))
+        torch.cuda.synchronize()
+        ms_dt = (time.perf_counter() - t0) / 3
+        out["front_coded_bytes_per_string"]["ms"] = pipe.literal_bytes / s.n + 12.0
+        out["front_coded_bytes_per_string"]["note"] = "literal bytes / n + 12 B of metadata (e, d, id)"
+        out["ms_mode"] = {"ms_per_step": ms_dt * 1e3, "GBps": s.N / ms_dt / 1e9,
+                          "note": "one stream, full strings front-coded and merged (no prefix doubling)"}
+        pipe.ms_mode = False
+        pipe.overlap = was
     if not args.no_batch:
         out["batch"] = batch_leg(ss, torch, synth)
         print(f"# batch leg: {out['batch']}", file=sys.stderr, flush=True)
@@ -463,9 +643,14 @@ def main():
         out["serve"] = serve_leg(ss, torch, synth)
         print(f"# serve leg: {out['serve']}", file=sys.stderr, flush=True)
     if not args.no_cpu:
-        host = synth.StringSet(s.bytes[: int(s.offsets[min(s.n, 2_000_000)])].cpu(),
-                               s.offsets[: min(s.n, 2_000_000) + 1].cpu(), dict(s.meta))
-        out["cpu_baseline"] = cpu_baseline(host, args.pes, args.sampling)
+        host = synth.StringSet(s.bytes[: int(s.offsets[min(s.n, 4_000_000)])].cpu(),
+                               s.offsets[: min(s.n, 4_000_000) + 1].cpu(), dict(s.meta))
+        ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        threads = max(1, min(args.pes, 16, ncpu))
+        out["cpu_baseline"] = cpu_baseline(host, args.pes, args.sampling, threads=threads)
+        out["cpu_baseline_single_thread"] = cpu_baseline(host, args.pes, args.sampling, threads=1)
+        print(f"# cpu baselines: {out['cpu_baseline']} / {out['cpu_baseline_single_thread']}", file=sys.stderr,
+              flush=True)
     print(json.dumps(out))
 
 

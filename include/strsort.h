@@ -86,6 +86,13 @@ int ss_sort(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t 
  * (checked on the device; the call reads one word back) or flags has an
  * unknown bit. */
 #define SS_BATCH_GLOBAL_IDS 1u
+/* Continue a device-driven batch sort that ended with unresolved segments
+ * (ss_sort_batch_device's status[0] > 0): same arguments and workspace as that
+ * call, whose state (the order so far and the segments left) the workspace
+ * holds; ss_sort_batch finishes it host-driven, ss_sort_batch_device runs
+ * `rounds` more rounds.  Indices become set-local (without
+ * SS_BATCH_GLOBAL_IDS) only once the sort is complete. */
+#define SS_BATCH_CONTINUE 2u
 int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
                   const uint64_t *set_off, uint32_t num_sets, uint32_t *perm, uint32_t *lcp,
                   uint32_t flags, void *ws, size_t ws_bytes, void *stream);
@@ -98,9 +105,9 @@ int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uin
  * more bytes of every string it keeps, so ss_sort_batch_device_rounds(L)
  * rounds finish any input whose strings are at most L bytes long.
  *   status (device, 2 words, out): status[0] = segments still unresolved
- *   after the last round (0: perm and lcp are complete; else the output is
- *   incomplete and the call must be repeated with more rounds), status[1] = 1
- *   if set_off is malformed (then nothing is sorted).
+ *   after the last round (0: perm and lcp are complete; else they are not,
+ *   and a call with SS_BATCH_CONTINUE finishes the sort from the workspace's
+ *   state), status[1] = 1 if set_off is malformed (then nothing is sorted).
  * Other arguments, outputs and workspace as in ss_sort_batch.  Rounds without
  * work cost only launches that find empty lists. */
 uint32_t ss_sort_batch_device_rounds(uint32_t max_len);

@@ -145,22 +145,31 @@ def sort(bytes_, offsets, with_lcp: bool = True, ws: torch.Tensor | None = None)
 
 
 SS_BATCH_GLOBAL_IDS = 1
+SS_BATCH_CONTINUE = 2
 
 
-def sort_batch(bytes_, offsets, set_off: torch.Tensor, with_lcp: bool = True, ws=None, global_ids: bool = False):
+def sort_batch(bytes_, offsets, set_off: torch.Tensor, with_lcp: bool = True, ws=None, global_ids: bool = False,
+               out=None):
     """Independent sorts of the sets [set_off[j], set_off[j+1]) in one launch sequence.
     Returns (perm int32[n], lcp int32[n] or None); perm holds indices within
-    each set, or indices of the whole array with ``global_ids``."""
+    each set, or indices of the whole array with ``global_ids``.  With
+    ``out=(perm, lcp)`` (and the same ``ws``) it finishes an incomplete
+    device-driven sort instead of starting over."""
     b, o, n = _dev_strings(bytes_, offsets)
     dev = b.device
     so = set_off.to(device=dev, dtype=torch.int64).contiguous()
-    perm = _u32(n, dev)
-    lcp = _u32(n, dev) if with_lcp else None
+    cont = out is not None
+    if cont:
+        perm, lcp = out
+    else:
+        perm = _u32(n, dev)
+        lcp = _u32(n, dev) if with_lcp else None
     need = lib().ss_sort_workspace(n)
     if ws is None or ws.numel() < need:
         ws = _ws(need, dev)
+    flags = (SS_BATCH_GLOBAL_IDS if global_ids else 0) | (SS_BATCH_CONTINUE if cont else 0)
     _check(lib().ss_sort_batch(_p(b), b.numel(), _p(o), n, _p(so), so.numel() - 1, _p(perm), _p(lcp),
-                               SS_BATCH_GLOBAL_IDS if global_ids else 0, _p(ws), ws.numel(), _stream(dev)))
+                               flags, _p(ws), ws.numel(), _stream(dev)))
     return perm, lcp
 
 
@@ -169,7 +178,8 @@ def sort_batch_device_rounds(max_len: int) -> int:
     return int(lib().ss_sort_batch_device_rounds(max_len))
 
 
-def sort_batch_device(bytes_, offsets, set_off, perm, lcp_, status, ws, rounds: int, global_ids: bool = False):
+def sort_batch_device(bytes_, offsets, set_off, perm, lcp_, status, ws, rounds: int, global_ids: bool = False,
+                      cont: bool = False):
     """Device-driven batch sort into caller-supplied buffers (nothing is read
     back or allocated, so it can be captured in a Graph).  ``status``: int32
     device tensor of 2 words (unresolved segments, malformed set_off)."""
@@ -177,7 +187,8 @@ def sort_batch_device(bytes_, offsets, set_off, perm, lcp_, status, ws, rounds: 
     if perm.numel() < n or (lcp_ is not None and lcp_.numel() < n) or status.numel() < 2:
         raise StrsortError("perm/lcp need n entries and status 2")
     _check(lib().ss_sort_batch_device(_p(b), b.numel(), _p(o), n, _p(set_off), set_off.numel() - 1, _p(perm),
-                                      _p(lcp_), SS_BATCH_GLOBAL_IDS if global_ids else 0, rounds, _p(status),
+                                      _p(lcp_), (SS_BATCH_GLOBAL_IDS if global_ids else 0) |
+                                      (SS_BATCH_CONTINUE if cont else 0), rounds, _p(status),
                                       _p(ws), ws.numel(), _stream(b.device)))
 
 

@@ -1221,7 +1221,9 @@ static int first_pass(const uint8_t *bytes, uint64_t N, const uint64_t *offsets,
     Fa.bp = bp;
     Fa.fw = first_weights();
     if (!deep) {
-        SS_PROF("k_hash_first", st, (double)n * (double)P.l[c0 - 1] + (double)n * (24.0 + 8.0 * c0));
+        // algorithmic bytes: each string's prefix read once, its offsets, one
+        // key written per precomputed round
+        SS_PROF("k_hash_first", st, (double)n * (double)P.l[c0 - 1] + (double)n * (8.0 + 8.0 * c0));
         k_hash_first<<<blocks, 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits, bp, Fa.fw, w.state, w.pre,
                                              fl_first);
         SS_CHECK_LAUNCH();
@@ -1233,7 +1235,7 @@ static int first_pass(const uint8_t *bytes, uint64_t N, const uint64_t *offsets,
         // more, shorter workgroups than the plain pass: beside the other
         // stream's kernels they give compute units back sooner
         const unsigned dblocks = (unsigned)(ceil_div(tiles, 4) < 8192 ? ceil_div(tiles, 4) : 8192);
-        SS_PROF("k_hash_first_deep", st, (double)n * (4.0 * PRE_MAX) + (double)n * (24.0 + 8.0 * (c0 + 2)));
+        SS_PROF("k_hash_first_deep", st, (double)n * (4.0 * PRE_MAX) + (double)n * (8.0 + 8.0 * (c0 + 2)));
         k_hash_first_deep<<<dblocks, 256, 0, st>>>(A, rwd, Fa);
         SS_CHECK_LAUNCH();
         P.l[c0] = 2 * PRE_MAX;

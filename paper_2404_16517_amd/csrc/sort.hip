@@ -126,6 +126,13 @@ __device__ __forceinline__ T block_max(T v)
 
 #define GSTRIDE(j, count) for (u32 j = blockIdx.x * blockDim.x + threadIdx.x; j < (count); j += gridDim.x * blockDim.x)
 
+// Tile loop of the heavier kernels: with LOOP, a grid-stride loop over `count`
+// tiles (fixed grids); without, exactly one tile per workgroup, t = blockIdx.x
+// (grids sized from counts read back) -- the loop then runs once and compiles
+// away, keeping the kernel's registers as they were.
+#define TILE_LOOP(t, count) \
+    for (u32 t = blockIdx.x; LOOP ? (t < (count)) : (t == blockIdx.x); t += LOOP ? gridDim.x : 1u)
+
 __global__ void k_tile_counts(const Seg *segs, const u32 *nsegp, u32 tile, u32 *out)
 {
     const u32 nseg = *nsegp;
@@ -276,6 +283,7 @@ __device__ __forceinline__ u32 skip_cmp(const u8 *bytes, u64 N, const u8 *R, con
 // position, its remaining length there (capped at 8) and its 8 bytes there
 // (mword, mpr), from which k_keys builds its key without reading the string
 // again.
+template <bool LOOP>
 __global__ __launch_bounds__(NT, 6) void k_skip(const Seg *segs, const u32 *tstart, const u32 *nsegp,
                                              const u8 *bytes, u64 N, const u64 *off,
                                              const u32 *perm, u32 *skipv, u64 *mword, uint2 *mpr)
@@ -285,8 +293,8 @@ __global__ __launch_bounds__(NT, 6) void k_skip(const Seg *segs, const u32 *tsta
     __shared__ u64 wwa[NT / 64][SKB];  // per wavefront: window start of each member
     __shared__ u32 wwn[NT / 64][SKB];  // ... and its chunk count
     const u32 nseg = *nsegp;
-    const u32 ntiles = tstart[nseg];
-    for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {  // (uniform over the workgroup)
+    const u32 ntiles = LOOP ? tstart[nseg] : 0u;
+    TILE_LOOP(t, ntiles) {  // (uniform over the workgroup)
     const u32 sg = seg_of_tile(tstart, nseg, t);
     const Seg g = segs[sg];
     if (!(g.aux & SEG_SKIP)) continue;  // uniform over the workgroup
@@ -385,6 +393,7 @@ __global__ __launch_bounds__(NT, 6) void k_skip(const Seg *segs, const u32 *tsta
     }
 }
 
+template <bool LOOP>
 __global__ __launch_bounds__(NT) void k_keys(const Seg *segs, const u32 *tstart, const u32 *nsegp,
                                              const u8 *bytes, u64 N, const u64 *off,
                                              const u32 *perm, const u32 *skipv, const u64 *mword,
@@ -392,8 +401,8 @@ __global__ __launch_bounds__(NT) void k_keys(const Seg *segs, const u32 *tstart,
 {
     __shared__ u64 fw;
     const u32 nseg = *nsegp;
-    const u32 ntiles = tstart[nseg];
-    for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const u32 ntiles = LOOP ? tstart[nseg] : 0u;
+    TILE_LOOP(t, ntiles) {
     const u32 s = seg_of_tile(tstart, nseg, t);
     const Seg g = segs[s];
     const u32 lt = t - tstart[s];
@@ -477,13 +486,14 @@ __device__ __forceinline__ u32 digit_of(u64 k, u32 level) { return (u32)(k >> (5
 
 // Per-tile histogram of the segment's current byte, digit-major per segment:
 // hist[256*tstart[s] + d*T_s + lt].  Also the segment's min and max key.
+template <bool LOOP>
 __global__ __launch_bounds__(NT) void k_hist(const Seg *segs, const u32 *tstart, const u32 *nsegp, u32 tile,
                                              const u64 *keyA, const u64 *keyB, u32 *hist, u64 *smin, u64 *smax)
 {
     __shared__ u32 h[256];
     const u32 nseg = *nsegp;
-    const u32 ntiles = tstart[nseg];
-    for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const u32 ntiles = LOOP ? tstart[nseg] : 0u;
+    TILE_LOOP(t, ntiles) {
     const u32 s = seg_of_tile(tstart, nseg, t);
     const Seg g = segs[s];
     const u64 *keys = (g.aux & SEG_INB) ? keyB : keyA;
@@ -601,13 +611,16 @@ __device__ __forceinline__ EmitItem emit_item(const Seg *segs, const u32 *tstart
 // A workgroup takes EPB segments (thread d = digit d): it counts its entries in
 // LDS, reserves room in every list with one global atomic per list, and then
 // writes the entries.
+template <bool LOOP>
 __global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart, const u32 *nsegp,
                                               const u32 *hist, const u64 *smin, const u64 *smax,
                                               EmitOut o)
 {
     __shared__ u32 lcount[K_KINDS], lslot[K_KINDS], lsum[7], gbase[K_KINDS];
     const u32 nseg = *nsegp;
-    for (u32 s0 = blockIdx.x * EPB; s0 < nseg; s0 += gridDim.x * EPB) {
+    const u32 ngrp = LOOP ? (nseg + EPB - 1) / EPB : 0u;
+    TILE_LOOP(grp, ngrp) {
+    const u32 s0 = grp * EPB;
     const u32 d = threadIdx.x;
     if (d < K_KINDS) { lcount[d] = 0; lslot[d] = 0; }
     if (d < 7) lsum[d] = 0;
@@ -667,6 +680,7 @@ __global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart
 
 // Stable scatter of (key, payload) by the current byte into the other pair
 // of arrays (A -> B or B -> A, by the segment's flag).
+template <bool LOOP>
 __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tstart, const u32 *nsegp, u32 tile,
                                                 const u32 *hist, const u8 *scat, u64 *keyA, u32 *valA,
                                                 u64 *keyB, u32 *valB)
@@ -674,8 +688,8 @@ __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tsta
     __shared__ u32 run[256];
     __shared__ u32 wcnt[NT / 64][256];
     const u32 nseg = *nsegp;
-    const u32 ntiles = tstart[nseg];
-    for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const u32 ntiles = LOOP ? tstart[nseg] : 0u;
+    TILE_LOOP(t, ntiles) {
     const u32 s = seg_of_tile(tstart, nseg, t);
     if (!scat[s]) continue;  // (uniform over the workgroup)
     const Seg g = segs[s];
@@ -736,13 +750,14 @@ __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tsta
 // the next round, equal strings) are copied to A when the level left them in
 // B.  Scattered segments read back their digits to find them; an unscattered
 // segment that became such a run is copied whole.
+template <bool LOOP>
 __global__ __launch_bounds__(NT) void k_settle(const Seg *segs, const u32 *tstart, const u32 *nsegp, u32 tile,
                                                const u8 *scat, const u8 *kinds, const u64 *keyB,
                                                const u32 *valB, u64 *keyA, u32 *valA)
 {
     const u32 nseg = *nsegp;
-    const u32 ntiles = tstart[nseg];
-    for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const u32 ntiles = LOOP ? tstart[nseg] : 0u;
+    TILE_LOOP(t, ntiles) {
     const u32 s = seg_of_tile(tstart, nseg, t);
     const Seg g = segs[s];
     const bool inb = g.aux & SEG_INB;
@@ -780,11 +795,12 @@ __global__ void k_boundary(const uint2 *bnd, const u32 *nbp, const u64 *keys, u3
 }
 
 // Equal strings: LCP = their length for every member after the first.
+template <bool LOOP>
 __global__ __launch_bounds__(NT) void k_ident(const Seg *segs, const u32 *tstart, const u32 *nsegp, u32 *lcp)
 {
     const u32 nseg = *nsegp;
-    const u32 ntiles = tstart[nseg];
-    for (u32 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const u32 ntiles = LOOP ? tstart[nseg] : 0u;
+    TILE_LOOP(t, ntiles) {
         const u32 s = seg_of_tile(tstart, nseg, t);
         const Seg g = segs[s];
         const u32 lt = t - tstart[s];
@@ -808,6 +824,7 @@ __device__ __forceinline__ bool lds_greater(u16 sa, u64 ka, u32 va, u16 sb, u64 
 // the concatenated small-segment space lies in [t*H, (t+1)*H); with segment
 // sizes <= H a tile holds < 2H elements.  Sorted by (segment, key, payload)
 // with a bitonic network in LDS.
+template <bool LOOP>
 __global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32 *pref, const u32 *nsmallp,
                                                      u32 H, u64 *keys, u32 *vals, const u64 *keyB,
                                                      const u32 *valB, u32 *lcp, Seg *next, u32 *ctr)
@@ -822,8 +839,8 @@ __global__ __launch_bounds__(LDS_NT) void k_lds_sort(const Seg *small, const u32
     __shared__ Seg nq[LDS_CAP / 2];  // next-round segments found in this tile
     __shared__ u32 nq_count, nq_tiles, nq_elems, nq_base;
     const u32 nsmall = *nsmallp;
-    const u32 ntile = (pref[nsmall] + H - 1) / H;  // pref[nsmall]: strings in all small segments
-    for (u32 t = blockIdx.x; t < ntile; t += gridDim.x) {
+    const u32 ntile = LOOP ? (pref[nsmall] + H - 1) / H : 0u;  // pref[nsmall]: strings in all small segments
+    TILE_LOOP(t, ntile) {
     const u32 lo = t * H, hi = lo + H;
     // j0 = first segment with pref >= lo, j1 = first with pref >= hi
     u32 j0, j1;
@@ -971,13 +988,15 @@ __device__ __forceinline__ u32 hibit(u64 m) { return 63u - (u32)__clzll(m); }
 // (key, payload) in registers (element e = lane + 64 r, r = 0, 1), then LCPs
 // and next-round runs as in the LDS sort.  Next-round segments are collected
 // per workgroup and published with one atomic per counter.
+template <bool LOOP>
 __global__ __launch_bounds__(256) void k_wave_sort(const Seg *tiny, const u32 *ntinyp, u64 *keys, u32 *vals,
                                                    const u64 *keyB, const u32 *valB, u32 *lcp, Seg *next, u32 *ctr)
 {
     __shared__ Seg nq[WS_SPB * (WS_MAX / 2)];
     __shared__ u32 nq_count, nq_tiles, nq_elems, nq_base;
     const u32 ntiny = *ntinyp;
-    for (u32 grp = blockIdx.x; grp * WS_SPB < ntiny; grp += gridDim.x) {
+    const u32 ngrp = LOOP ? (ntiny + WS_SPB - 1) / WS_SPB : 0u;
+    TILE_LOOP(grp, ngrp) {
     if (threadIdx.x == 0) { nq_count = 0; nq_tiles = 0; nq_elems = 0; }
     __syncthreads();
     const u32 lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1163,13 +1182,14 @@ static int round_head(RoundCtx &C, Known nact, Known atiles, u64 round_elems)
         // algorithmic bytes: perm + offsets + one word per string, its mismatch
         // record out, plus the common prefix (added once the skips are known)
         SS_PROF("k_skip", st, (double)round_elems * 44.0);
-        k_skip<<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr);
+        if (atiles.yes) k_skip<false><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr);
+        else k_skip<true><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr);
     }
     SS_CHECK_LAUNCH();
     {
         SS_PROF("k_keys", st, (double)round_elems * 24.0);  // mismatch record in, key out
-        k_keys<<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr,
-                                  w.keyA);
+        if (atiles.yes) k_keys<false><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr, w.keyA);
+        else k_keys<true><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr, w.keyA);
     }
     SS_CHECK_LAUNCH();
     k_classify<<<grid_of(nact.yes ? nact.v : n / 2, 256, 1024), 256, 0, st>>>(w.act, nactp, w.skipv, C.SM, C.TL,
@@ -1196,23 +1216,26 @@ static int radix_level(RoundCtx &C, Seg *LA, Seg *LB, Known nlarge, Known ltiles
     const unsigned tg = grid_of(ltiles.yes ? ltiles.v : n, ltiles.yes ? 1 : C.TL, ltiles.yes ? 1u << 30 : 2048);
     {
         SS_PROF("k_hist", st, (double)lelem * 8.0);  // read the keys
-        k_hist<<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.keyA, w.keyB, w.hist, w.smin, w.smax);
+        if (ltiles.yes) k_hist<false><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.keyA, w.keyB, w.hist, w.smin, w.smax);
+        else k_hist<true><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.keyA, w.keyB, w.hist, w.smin, w.smax);
     }
     SS_CHECK_LAUNCH();
     if (ltiles.yes) SS_TRY(ss_scan_exclusive<u32>(w.hist, w.hist, (u64)ltiles.v * 256, (u32 *)w.scan_scratch, st));
     else SS_TRY(ss_scan_exclusive_dev<u32>(w.hist, w.hist, w.hdr + H_HIST, 1, w.dscan, st));
     EmitOut eo{w.tiny, w.small, LB, w.nxt, w.ident, w.bnd, w.ctr, w.scat, w.kinds, C.SM, C.TL};
-    k_emit<<<grid_of(nlarge.yes ? nlarge.v : n / 128, EPB, 4096), 256, 0, st>>>(LA, w.tstart, nlp, w.hist, w.smin,
-                                                                              w.smax, eo);
+    if (nlarge.yes) k_emit<false><<<grid_of(nlarge.v, EPB, 1u << 30), 256, 0, st>>>(LA, w.tstart, nlp, w.hist, w.smin, w.smax, eo);
+    else k_emit<true><<<grid_of(n / 128, EPB, 4096), 256, 0, st>>>(LA, w.tstart, nlp, w.hist, w.smin, w.smax, eo);
     SS_CHECK_LAUNCH();
     {
         SS_PROF("k_scatter", st, (double)lelem * 24.0);  // key+payload in and out
-        k_scatter<<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.hist, w.scat, w.keyA, J.vals, w.keyB, w.valB);
+        if (ltiles.yes) k_scatter<false><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.hist, w.scat, w.keyA, J.vals, w.keyB, w.valB);
+        else k_scatter<true><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.hist, w.scat, w.keyA, J.vals, w.keyB, w.valB);
     }
     SS_CHECK_LAUNCH();
     {
         SS_PROF("k_settle", st, (double)lelem * 8.0);  // at most the scattered keys read back
-        k_settle<<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.scat, w.kinds, w.keyB, w.valB, w.keyA, J.vals);
+        if (ltiles.yes) k_settle<false><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.scat, w.kinds, w.keyB, w.valB, w.keyA, J.vals);
+        else k_settle<true><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.scat, w.kinds, w.keyB, w.valB, w.keyA, J.vals);
     }
     SS_CHECK_LAUNCH();
     return SS_OK;
@@ -1230,8 +1253,12 @@ static int round_tail(RoundCtx &C, const u32 *h)
     const bool known = h != nullptr;
     if (!known || h[C_TINY] > 0) {
         SS_PROF("k_wave_sort", st, known ? (double)h[C_TINYN] * 28.0 : 0.0);  // key+payload in/out, LCP out
-        k_wave_sort<<<grid_of(known ? h[C_TINY] : n / 2, WS_SPB, known ? 1u << 30 : 2048), 256, 0, st>>>(
-            w.tiny, w.ctr + C_TINY, w.keyA, J.vals, w.keyB, w.valB, lcp, w.nxt, w.ctr);
+        if (known)
+            k_wave_sort<false><<<grid_of(h[C_TINY], WS_SPB, 1u << 30), 256, 0, st>>>(
+                w.tiny, w.ctr + C_TINY, w.keyA, J.vals, w.keyB, w.valB, lcp, w.nxt, w.ctr);
+        else
+            k_wave_sort<true><<<grid_of(n / 2, WS_SPB, 2048), 256, 0, st>>>(
+                w.tiny, w.ctr + C_TINY, w.keyA, J.vals, w.keyB, w.valB, lcp, w.nxt, w.ctr);
         SS_CHECK_LAUNCH();
     }
     if (!known || h[C_SMALL] > 0) {
@@ -1239,8 +1266,12 @@ static int round_tail(RoundCtx &C, const u32 *h)
         SS_CHECK_LAUNCH();
         SS_TRY(scan_u32(C, w.spref, w.ctr + C_SMALL, Known{known, known ? h[C_SMALL] : 0u}));
         SS_PROF("k_lds_sort", st, known ? (double)h[C_SMALLN] * 28.0 : 0.0);  // key+payload in/out, LCP out
-        k_lds_sort<<<grid_of(known ? h[C_SMALLN] : n, C.SM, known ? 1u << 30 : 2048), LDS_NT, 0, st>>>(
-            w.small, w.spref, w.ctr + C_SMALL, C.SM, w.keyA, J.vals, w.keyB, w.valB, lcp, w.nxt, w.ctr);
+        if (known)
+            k_lds_sort<false><<<grid_of(h[C_SMALLN], C.SM, 1u << 30), LDS_NT, 0, st>>>(
+                w.small, w.spref, w.ctr + C_SMALL, C.SM, w.keyA, J.vals, w.keyB, w.valB, lcp, w.nxt, w.ctr);
+        else
+            k_lds_sort<true><<<grid_of(n, C.SM, 2048), LDS_NT, 0, st>>>(
+                w.small, w.spref, w.ctr + C_SMALL, C.SM, w.keyA, J.vals, w.keyB, w.valB, lcp, w.nxt, w.ctr);
         SS_CHECK_LAUNCH();
     }
     if (!known || h[C_BND] > 0) {
@@ -1252,8 +1283,10 @@ static int round_tail(RoundCtx &C, const u32 *h)
                                                                                     ETILE, w.tstart);
         SS_CHECK_LAUNCH();
         SS_TRY(scan_u32(C, w.tstart, w.ctr + C_IDENT, Known{known, known ? h[C_IDENT] : 0u}));
-        k_ident<<<grid_of(known ? h[C_ITILES] : n, known ? 1 : ETILE, known ? 1u << 30 : 2048), NT, 0, st>>>(
-            w.ident, w.tstart, w.ctr + C_IDENT, lcp);
+        if (known)
+            k_ident<false><<<grid_of(h[C_ITILES], 1, 1u << 30), NT, 0, st>>>(w.ident, w.tstart, w.ctr + C_IDENT, lcp);
+        else
+            k_ident<true><<<grid_of(n, ETILE, 2048), NT, 0, st>>>(w.ident, w.tstart, w.ctr + C_IDENT, lcp);
         SS_CHECK_LAUNCH();
     }
     return SS_OK;
@@ -1306,8 +1339,17 @@ __global__ void k_remaining(const u32 *ctr, u32 *hdr, u32 *status)
     if (status) *status = ctr[C_NEXT];
 }
 
+// The next round's segments back into the first list (after an odd number of
+// rounds they are in the second), so that a continuation finds them there.
+__global__ void k_copy_segs(const Seg *src, const u32 *cnt, Seg *dst)
+{
+    const u32 c = *cnt;
+    GSTRIDE(j, c) dst[j] = src[j];
+}
+
 static int sort_rounds_device(const SortJob &J, SortWs &w, u32 rounds, u32 *status)
 {
+    Seg *const act0 = w.act;
     RoundCtx C{J, w, J.n_total, (u32)g_small_max, (u32)g_tile};
     const Known unknown{false, 0};
     for (u32 r = 0; r < rounds; r++) {
@@ -1322,6 +1364,10 @@ static int sort_rounds_device(const SortJob &J, SortWs &w, u32 rounds, u32 *stat
     }
     k_remaining<<<1, 1, 0, J.stream>>>(w.ctr, w.hdr, status);
     SS_CHECK_LAUNCH();
+    if (w.act != act0) {
+        k_copy_segs<<<grid_of(J.n_total / 2, 256, 1024), 256, 0, J.stream>>>(w.act, w.ctr + C_NEXT, act0);
+        SS_CHECK_LAUNCH();
+    }
     return SS_OK;
 }
 
@@ -1389,10 +1435,13 @@ __global__ void k_drop_if_bad(u32 *ctr, u32 *status)
     if (status) status[1] = ctr[C_BADSET] ? 1u : 0u;
 }
 
-__global__ void k_localize(const u64 *set_off, u32 nsets, u32 n, u32 *perm)
+// Input indices within each set instead of the whole array, once the sort is
+// complete (*remaining == 0; a sort left incomplete keeps global indices, as
+// its continuation needs them).
+__global__ void k_localize(const u64 *set_off, u32 nsets, u32 n, u32 *perm, const u32 *remaining)
 {
     u32 i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || (remaining && *remaining)) return;
     // largest j with set_off[j] <= i
     u32 lo = 0, hi = nsets;
     while (hi - lo > 1) {
@@ -1497,7 +1546,7 @@ static int batch_setup(const uint8_t *bytes, uint64_t N, const uint64_t *offsets
         ss_set_error("batch needs num_sets >= 1 and set_off");
         return SS_ERR_INVALID_ARG;
     }
-    if (flags & ~SS_BATCH_GLOBAL_IDS) {
+    if (flags & ~(SS_BATCH_GLOBAL_IDS | SS_BATCH_CONTINUE)) {
         ss_set_error("unknown flags 0x%x", flags);
         return SS_ERR_INVALID_ARG;
     }
@@ -1509,6 +1558,7 @@ static int batch_setup(const uint8_t *bytes, uint64_t N, const uint64_t *offsets
         return SS_ERR_WORKSPACE;
     }
     J = SortJob{bytes, N, offsets, perm, lcp ? lcp : w.lcp_scratch, st, 0, n};
+    if (flags & SS_BATCH_CONTINUE) return SS_OK;  // the state of an incomplete device-driven sort
     k_iota<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(perm, (u32)n);
     SS_CHECK_LAUNCH();
     k_zero_u32<<<1, 64, 0, st>>>(w.ctr, C_NCTR);
@@ -1537,7 +1587,7 @@ extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *o
     J.n_first = h[C_NELEM];
     SS_TRY(sort_rounds(J, w, h[C_NEXT], h[C_NTILES]));
     if (!(flags & SS_BATCH_GLOBAL_IDS)) {
-        k_localize<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(set_off, num_sets, (u32)n, perm_local);
+        k_localize<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(set_off, num_sets, (u32)n, perm_local, nullptr);
         SS_CHECK_LAUNCH();
     }
     return SS_OK;
@@ -1572,11 +1622,14 @@ extern "C" int ss_sort_batch_device(const uint8_t *bytes, uint64_t N, const uint
         SS_CHECK_LAUNCH();
         return SS_OK;
     }
-    k_drop_if_bad<<<1, 1, 0, st>>>(w.ctr, status);
-    SS_CHECK_LAUNCH();
+    if (!(flags & SS_BATCH_CONTINUE)) {
+        k_drop_if_bad<<<1, 1, 0, st>>>(w.ctr, status);
+        SS_CHECK_LAUNCH();
+    }
     SS_TRY(sort_rounds_device(J, w, rounds, status));
     if (!(flags & SS_BATCH_GLOBAL_IDS)) {
-        k_localize<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(set_off, num_sets, (u32)n, perm_local);
+        k_localize<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(set_off, num_sets, (u32)n, perm_local,
+                                                               w.ctr + C_NEXT);
         SS_CHECK_LAUNCH();
     }
     return SS_OK;

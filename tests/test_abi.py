@@ -57,7 +57,7 @@ def test_argument_errors_without_device():
     # select_splitters needs r >= 1 and n >= 1
     assert L.ss_select_splitters(0, P(8), 4, P(8), None) == -1
     # unknown batch flag; join needs k >= 1
-    assert L.ss_sort_batch(P(8), 0, P(8), 10, P(8), 1, P(8), None, 2, P(8), 1 << 20, None) == -1
+    assert L.ss_sort_batch(P(8), 0, P(8), 10, P(8), 1, P(8), None, 4, P(8), 1 << 20, None) == -1
     assert L.ss_join_group_lcps(P(8), 0, P(8), P(8), 10, 0, P(8), P(8), 2, P(8), P(8), None) == -1
     assert L.ss_select_splitters_batch(P(8), 10, P(8), 0, 4, P(8), P(8), 256, None) == -1
     assert L.ss_select_splitters_batch(P(8), 10, P(8), 2, 4, P(8), P(8), 0, None) == -2
@@ -78,3 +78,19 @@ def test_tuning_validation():
         ss.set_tuning(ss.SS_TUNE_SMALL_MAX, 300)
     with pytest.raises(ss.StrsortError):
         ss.set_tuning(ss.SS_TUNE_TILE, 3000)
+
+
+def test_device_batch_sort_and_graph_arguments():
+    L = ss.lib()
+    P = ctypes.c_void_p
+    # status is required; rounds 1..1024; unknown flag bit
+    assert L.ss_sort_batch_device(P(8), 0, P(8), 10, P(8), 1, P(8), None, 0, 4, None, P(8), 1 << 20, None) == -1
+    assert L.ss_sort_batch_device(P(8), 0, P(8), 10, P(8), 1, P(8), None, 0, 0, P(8), P(8), 1 << 20, None) == -1
+    assert L.ss_sort_batch_device(P(8), 0, P(8), 10, P(8), 1, P(8), None, 8, 4, P(8), P(8), 1 << 20, None) == -1
+    # a round resolves at least 7 bytes: strings of L bytes need L // 7 + 2 rounds at most
+    assert L.ss_sort_batch_device_rounds(256) == 38 and L.ss_sort_batch_device_rounds(0) == 2
+    # capture needs a real stream; ending without a stream or output fails cleanly
+    assert L.ss_graph_begin(None) == -1
+    assert L.ss_graph_end(None, None) == -1
+    assert L.ss_graph_launch(None, None) == -1
+    L.ss_graph_destroy(None)

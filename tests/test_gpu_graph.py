@@ -82,8 +82,44 @@ def test_too_few_rounds_report_unresolved_segments():
     ss.sort_batch_device(g.bytes, g.offsets, so, perm, lcp, status, ws, ss.sort_batch_device_rounds(22))
     torch.cuda.synchronize()
     assert status.tolist() == [0, 0]
-    p_ref = oracle.sort(*oracle.strings_np(s))
+    b, o = oracle.strings_np(s)
+    p_ref = oracle.sort(b, o)
     np.testing.assert_array_equal(u32(perm), p_ref)
+    np.testing.assert_array_equal(u32(lcp), oracle.lcp(b, o, p_ref))
+
+
+@pytest.mark.parametrize("odd", [False, True])
+@pytest.mark.parametrize("finish", ["host", "device"])
+def test_incomplete_device_sort_continues_to_the_oracle_result(finish, odd):
+    """A device-driven sort stopped after one or two rounds (leaving
+    segments for later rounds, in either list) is finished by a continuation:
+    host-driven, or device-driven with more rounds."""
+    rng = np.random.default_rng(3)
+    strs = [bytes([65 + i % 4]) + b"Z" * int(rng.integers(10, 30)) + bytes([65 + int(x) for x in rng.integers(0, 3, 3)])
+            for i in range(3000)]
+    s1 = synth.from_list(strs[:1700])
+    s2 = synth.from_list(strs[1700:])
+    s, bounds = synth.concat([s1, s2])
+    g = s.to(DEV)
+    so = bounds.to(DEV)
+    perm, lcp, status, ws = _buffers(s.n)
+    ss.sort_batch_device(g.bytes, g.offsets, so, perm, lcp, status, ws, 2 if odd else 1)
+    torch.cuda.synchronize()
+    assert status[0].item() > 0
+    if finish == "host":
+        ss.sort_batch(g.bytes, g.offsets, so, ws=ws, out=(perm, lcp))
+    else:
+        ss.sort_batch_device(g.bytes, g.offsets, so, perm, lcp, status, ws, ss.sort_batch_device_rounds(40),
+                             cont=True)
+    torch.cuda.synchronize()
+    if finish == "device":
+        assert status.tolist() == [0, 0]
+    b, o = oracle.strings_np(s)
+    for a, c in ((0, 1700), (1700, 3000)):
+        sb, sob = b[o[a]:o[c]], o[a:c + 1] - o[a]
+        p_ref = oracle.sort(sb, sob)
+        np.testing.assert_array_equal(u32(perm[a:c]), p_ref)
+        np.testing.assert_array_equal(u32(lcp[a:c]), oracle.lcp(sb, sob, p_ref))
 
 
 def test_device_driven_flags_malformed_sets():
