@@ -43,6 +43,8 @@ def lib():
         L.or_kr_key.argtypes = [P, U64]; L.or_kr_key.restype = U64
         L.or_dist_prefix.argtypes = [P, P, U64, U32, U32, P, P, P]; L.or_dist_prefix.restype = I32
         L.or_select_splitters.argtypes = [U64, P, U32, P]; L.or_select_splitters.restype = I32
+        L.or_select_splitters_chars.argtypes = [U64, P, P, P, U32, P]
+        L.or_select_splitters_chars.restype = I32
         L.or_bucket_bounds.argtypes = [P, P, U64, P, P, P, U32, P]; L.or_bucket_bounds.restype = None
         L.or_fc_encode.argtypes = [P, P, U64, P, P, P, P, U32, P, P, P, P, P]
         L.or_fc_encode.restype = ctypes.c_int64
@@ -132,6 +134,17 @@ def select_splitters(n, perm, r) -> np.ndarray:
     ids = np.empty(max(r - 1, 1), dtype=np.uint32)
     if lib().or_select_splitters(n, _p(np.ascontiguousarray(perm, dtype=np.uint32)), r, _p(ids)) != 0:
         raise ValueError("select_splitters")
+    return ids[:r - 1]
+
+
+def select_splitters_chars(perm, offsets, r, weights=None) -> np.ndarray:
+    """Character-based regular sampling of one sorted array (r - 1 samples)."""
+    perm = np.ascontiguousarray(perm, dtype=np.uint32)
+    o = np.ascontiguousarray(offsets, dtype=np.uint64)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.uint32)
+    ids = np.empty(max(r - 1, 1), dtype=np.uint32)
+    if lib().or_select_splitters_chars(perm.size, _p(perm), _p(o), _p(w), r, _p(ids)) != 0:
+        raise ValueError("select_splitters_chars")
     return ids[:r - 1]
 
 

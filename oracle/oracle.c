@@ -72,6 +72,7 @@ static uint64_t str_lcp(const uint8_t *a, uint64_t la, const uint8_t *b, uint64_
 
 #define SP(i) (bytes + off[(i)])
 #define SL(i) (off[(i) + 1] - off[(i)])
+#define SLEN(i) (off[(i) + 1] - off[(i)])
 
 /* Order of (string, input index): the stable sorted order of R3. */
 static int idx_less(const uint8_t *bytes, const uint64_t *off, uint32_t x, uint32_t y)
@@ -261,6 +262,41 @@ int or_select_splitters(uint64_t n, const uint32_t *perm, uint32_t r, uint32_t *
     for (uint64_t j = 1; j < r; j++) {
         uint64_t c = (j * n + r - 1) / r;
         ids[j - 1] = perm[c - 1];
+    }
+    return 0;
+}
+
+/* Character-based regular sampling (Section 3.1, "Character-Based Sampling";
+ * Appendix A): samples are drawn at equally spaced positions of the sorted
+ * array's character array and each sampled position is shifted back to the
+ * beginning of the string that contains it.  One array's form with r - 1
+ * samples: with C_k = characters of the strings at sorted positions < k and
+ * N = C_n, sample j (j = 1..r-1) is at character position
+ * x_j = ceil(j N / r) - 1 (the character analogue of f_j = V[j|V|/r - 1]),
+ * and ids[j-1] = perm[k] for the string k with C_k <= x_j < C_{k+1}.
+ * Characters are the full lengths, or the given per-string counts `w`
+ * (indexed by input index; e.g. approximate distinguishing prefixes, the
+ * characters prefix doubling keeps).  N = 0 (no characters) samples the
+ * first string.  Returns 0, or -1 if n == 0 or r == 0. */
+int or_select_splitters_chars(uint64_t n, const uint32_t *perm, const uint64_t *off, const uint32_t *w,
+                              uint32_t r, uint32_t *ids)
+{
+    if (n == 0 || r == 0) return -1;
+    uint64_t N = 0;
+    for (uint64_t k = 0; k < n; k++) N += w ? w[perm[k]] : SLEN(perm[k]);
+    for (uint32_t j = 1; j < r; j++) {
+        if (N == 0) {
+            ids[j - 1] = perm[0];
+            continue;
+        }
+        uint64_t x = ((uint64_t)j * N + r - 1) / r - 1;
+        uint64_t C = 0, k = 0;
+        for (;; k++) {
+            uint64_t c = w ? w[perm[k]] : SLEN(perm[k]);
+            if (x < C + c) break;  /* (x < N, so some string contains it) */
+            C += c;
+        }
+        ids[j - 1] = perm[k];
     }
     return 0;
 }

@@ -473,3 +473,117 @@ def test_select_splitters_are_lower_quantiles_with_balanced_buckets(n, r):
     for v in (1, 2, 16):
         if v <= n:  # ceil(n/r) <= n/r + 1 <= n/r + n/v
             assert sizes.max() <= (1 + r / v) * n / r
+
+
+# ------------------------------------------------ character-based sampling
+
+def _sorted_by_len_strings(n, seed, max_len=300):
+    """Strings whose sorted order is also increasing length ('A' * k + tail):
+    the worst case for string-based splitters, whose last buckets take all
+    the long strings."""
+    rng = random.Random(seed)
+    strs = []
+    for i in range(n):
+        k = min(max_len - 2, int(rng.paretovariate(1.2))) if rng.random() < 0.9 else rng.randint(100, max_len - 2)
+        strs.append(b"A" * k + bytes([66 + rng.randrange(20), 65 + rng.randrange(26)]))
+    return strs
+
+
+@pytest.mark.parametrize("n,r,L", [(10, 4, 3), (250, 7, 1), (250, 64, 5), (1000, 3, 17), (97, 96, 2), (5, 9, 4),
+                                   (64, 64, 8), (3000, 128, 9)])
+def test_char_splitters_on_equal_lengths_are_the_string_splitters(n, r, L):
+    """With every string L characters long, the j-th character quantile lies
+    in the j-th string quantile (Section 3.1: character-based sampling
+    generalises string-based sampling), so both pick the same strings."""
+    rng = random.Random(n + r)
+    strs = [bytes(rng.randrange(65, 91) for _ in range(L)) for _ in range(n)]
+    b, o = _arrays(strs)
+    perm = oracle.sort(b, o)
+    np.testing.assert_array_equal(oracle.select_splitters_chars(perm, o, r), oracle.select_splitters(n, perm, r))
+    # equal per-string character counts (e.g. equal distinguishing prefixes) likewise
+    w = np.full(n, 3, np.uint32)
+    np.testing.assert_array_equal(oracle.select_splitters_chars(perm, o, r, w), oracle.select_splitters(n, perm, r))
+
+
+def test_char_splitters_count_the_given_characters():
+    """Counting given characters (e.g. approximate distinguishing prefixes)
+    samples exactly as counting the lengths of strings that long."""
+    rng = random.Random(8)
+    n = 2000
+    strs = [bytes(rng.randrange(65, 70) for _ in range(rng.randint(0, 40))) for _ in range(n)]
+    b, o = _arrays(strs)
+    perm = oracle.sort(b, o)
+    w = np.array([rng.randint(0, 90) for _ in range(n)], np.uint32)
+    o2 = np.concatenate([[0], np.cumsum(w.astype(np.uint64))]).astype(np.uint64)  # strings of length w_i
+    for r in (2, 5, 33, 256):
+        np.testing.assert_array_equal(oracle.select_splitters_chars(perm, o, r, w),
+                                      oracle.select_splitters_chars(perm, o2, r))
+
+
+@pytest.mark.parametrize("seed,r", [(0, 4), (1, 16), (2, 97), (3, 300)])
+def test_char_sample_density(seed, r):
+    """Appendix A, character sample density: a contiguous run of the sorted
+    array holding k sampled strings has at most (k + 1)(w + l_max)
+    characters, w the sampling distance (here ceil(N / r))."""
+    strs = _sorted_by_len_strings(3000, seed)
+    rng = random.Random(seed)
+    rng.shuffle(strs)
+    b, o = _arrays(strs)
+    perm = oracle.sort(b, o)
+    ids = oracle.select_splitters_chars(perm, o, r)
+    lens = (o[1:] - o[:-1]).astype(np.int64)
+    sl = lens[perm]
+    C = np.concatenate([[0], np.cumsum(sl)])
+    N, lmax = int(C[-1]), int(sl.max())
+    w = -(-N // r)
+    pos = {int(x): i for i, x in enumerate(perm)}
+    sampled = np.zeros(len(strs), bool)
+    for x in ids:
+        sampled[pos[int(x)]] = True
+    S = np.concatenate([[0], np.cumsum(sampled)])
+    for _ in range(3000):
+        a = rng.randrange(len(strs))
+        e = rng.randrange(a, len(strs)) + 1
+        k = int(S[e] - S[a])
+        assert C[e] - C[a] <= (k + 1) * (w + lmax)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_char_splitters_bound_bucket_characters(seed):
+    """Appendix A's bucket bound for character-based regular sampling: with p
+    arrays each sampled v + 1 times by characters, sorted samples V and
+    f_j = V[j|V|/p - 1], every bucket holds at most
+    (1 + p/v) N/p + (1 + (v+1)/p) p l_max characters.  On an input whose long
+    strings sort last, string-based samples overload the last bucket."""
+    p, v = 8, 4
+    strs = _sorted_by_len_strings(4000, 10 + seed)
+    random.Random(seed).shuffle(strs)
+    b, o = _arrays(strs)
+    n = len(strs)
+    lens = (o[1:] - o[:-1]).astype(np.int64)
+    bounds = [n * i // p for i in range(p + 1)]
+    perms = []
+    for a, e in zip(bounds[:-1], bounds[1:]):
+        sb, so = b[o[a]:o[e]], o[a:e + 1] - o[a]
+        perms.append(oracle.sort(sb, so).astype(np.int64) + a)
+
+    def bucket_chars(per_pe_samples):
+        V = sorted(set(int(x) for x in per_pe_samples), key=lambda i: (strs[i], i))
+        spl = [V[len(V) * j // p - 1] for j in range(1, p)]
+        spl_strs = [strs[i] for i in spl]
+        sb, so = _arrays(spl_strs)
+        tot = np.zeros(p, np.int64)
+        for pm in perms:
+            bb = oracle.bucket_bounds(b, o, pm.astype(np.uint32), sb, so)
+            for j in range(p):
+                tot[j] += lens[pm[int(bb[j]):int(bb[j + 1])]].sum()
+        return tot
+
+    chars = np.concatenate([oracle.select_splitters_chars(pm.astype(np.uint32), o, v + 2) for pm in perms])
+    strings = np.concatenate([oracle.select_splitters(len(pm), pm.astype(np.uint32), v + 2) for pm in perms])
+    N, lmax = int(lens.sum()), int(lens.max())
+    bound = (1 + p / v) * N / p + (1 + (v + 1) / p) * p * lmax
+    by_chars, by_strings = bucket_chars(chars), bucket_chars(strings)
+    assert by_chars.sum() == by_strings.sum() == N
+    assert by_chars.max() <= bound
+    assert by_strings.max() > 2 * by_chars.max()
