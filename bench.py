@@ -249,6 +249,59 @@ def batch_leg(ss, torch, synth, num_sets=4096, lo=1e3, hi=1e6, len_lo=8, len_hi=
     return out
 
 
+def splitters_leg(ss, torch, synth, n=50_000_000, p=16, v=2):
+    """Text strings (log-normal lengths, Zipf bytes, 20% duplicates), split
+    over p virtual PEs, each sorted: characters per bucket with string-based
+    and with character-based regular sampling (v + 1 samples per PE, sorted,
+    f_j = V[j|V|/p - 1]; Section 3.1), and with samples weighted by the
+    approximate distinguishing prefixes (the characters PDMS sends)."""
+    dev = torch.device("cuda:0")
+    s = synth.text_strings(n, seed=0, device=dev)
+    so = torch.tensor([n * i // p for i in range(p + 1)], dtype=torch.int64)
+    perm, _ = ss.sort_batch(s.bytes, s.offsets, so.to(dev), with_lcp=False, global_ids=True)
+    dpx, _ = ss.dist_prefix(s.bytes, s.offsets, 8, 64)
+    lens = (s.offsets[1:] - s.offsets[:-1])
+    pl = perm.to(torch.int64)
+    C = {"len": torch.zeros(n + 1, dtype=torch.int64, device=dev), "dist": torch.zeros(n + 1, dtype=torch.int64,
+                                                                                        device=dev)}
+    C["len"][1:] = torch.cumsum(lens[pl], 0)
+    C["dist"][1:] = torch.cumsum(dpx.to(torch.int64)[pl], 0)
+    bl = so.tolist()
+    out = {"workload": f"text strings n={n} (log-normal lengths median 40, Zipf 1.1 bytes, 20% duplicates)",
+           "virtual_pes": p, "N": int(C["len"][-1]), "D_approx": int(C["dist"][-1]),
+           "note": "largest bucket over the mean, in characters, in distinguishing-prefix characters and in "
+                   "strings, for v + 1 samples per PE"}
+    lmax = int(lens.max())
+    for vv in (v, 64):
+        res = {}
+        for kind in ("strings", "chars", "chars_by_dist"):
+            if kind == "strings":
+                samp = ss.select_splitters_batch(perm, so, vv + 2)
+            else:
+                samp = ss.select_splitters_chars_batch(perm, s.offsets, so, vv + 2,
+                                                       weights=dpx if kind == "chars_by_dist" else None)
+            sb, sof = ss.gather_strings(s.bytes, s.offsets, samp)
+            sperm, _ = ss.sort(sb, sof, with_lcp=False)
+            fid = ss.select_splitters(sperm, p)
+            fb, fo = ss.gather_strings(sb, sof, fid)
+            cnt = {"len": torch.zeros(p, dtype=torch.int64, device=dev),
+                   "dist": torch.zeros(p, dtype=torch.int64, device=dev)}
+            strs = torch.zeros(p, dtype=torch.int64, device=dev)
+            for a, e in zip(bl[:-1], bl[1:]):
+                bb = ss.bucket_bounds(s.bytes, s.offsets, perm[a:e], fb, fo) + a
+                strs += bb[1:] - bb[:-1]
+                for key in cnt:
+                    cnt[key] += C[key][bb[1:]] - C[key][bb[:-1]]
+            res[kind] = {"chars": float(cnt["len"].max()) / (out["N"] / p),
+                         "dist_chars": float(cnt["dist"].max()) / (out["D_approx"] / p),
+                         "strings": float(strs.max()) / (n / p)}
+        res["appendix_A_char_bound"] = ((1 + p / vv) * out["N"] / p + (1 + (vv + 1) / p) * p * lmax) / (out["N"] / p)
+        out[f"v={vv}"] = res
+    del s, perm, dpx, C
+    torch.cuda.empty_cache()
+    return out
+
+
 def serve_leg(ss, torch, synth, count=200, lo=1e3, hi=1e7, budget_gb=200.0, tight_gb=4.0, slots=4, load=0.7):
     """Sort requests (sort + LCP + exact and approximate distinguishing
     prefixes) served with continuous batching (`slots` concurrent streams,
@@ -501,6 +554,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-per-job leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-ms-mode", action="store_true", help="skip the full-string (MS) step")
+    ap.add_argument("--no-splitters", action="store_true",
+                    help="skip the string- vs character-based splitter comparison on text strings")
     ap.add_argument("--no-profile", action="store_true",
                     help="time the steps without the per-launch events (no roofline)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GB",
@@ -639,6 +694,9 @@ def main():
     if not args.no_batch:
         out["batch"] = batch_leg(ss, torch, synth)
         print(f"# batch leg: {out['batch']}", file=sys.stderr, flush=True)
+    if not args.no_splitters:
+        out["splitters_text"] = splitters_leg(ss, torch, synth)
+        print(f"# splitters leg: {out['splitters_text']}", file=sys.stderr, flush=True)
     if not args.no_serve:
         out["serve"] = serve_leg(ss, torch, synth)
         print(f"# serve leg: {out['serve']}", file=sys.stderr, flush=True)

@@ -223,6 +223,27 @@ size_t ss_select_splitters_batch_workspace(void);
 int ss_select_splitters_batch(const uint32_t *perm, uint64_t n, const uint64_t *set_off, uint32_t num_sets,
                               uint32_t r, uint32_t *splitter_ids, void *ws, size_t ws_bytes, void *stream);
 
+/* Workspace bytes for ss_select_splitters_chars_batch on n sorted positions. */
+size_t ss_select_splitters_chars_batch_workspace(uint64_t n);
+
+/* Character-based regular sampling (Section 3.1, "Character-Based Sampling";
+ * Appendix A) of every set of a batch: samples at equally spaced positions of
+ * each sorted set's character array, each shifted back to the start of the
+ * string that holds it, so that buckets between them hold balanced numbers of
+ * characters rather than of strings.  Set b is positions [set_off[b],
+ * set_off[b+1]) of perm (values index offsets); with C_k the characters of the
+ * set's first k strings and N_b = C_{n_b}, sample j (1..r-1) is at character
+ * position x_j = ceil(j N_b / r) - 1 and splitter_ids[b*(r-1) + j-1] =
+ * perm[set_off[b] + k] for the k with C_k <= x_j < C_{k+1} (a set without
+ * characters gives its first string).  Characters are string lengths, or
+ * weights[s] (device, by input index, nullable; e.g. the approximate
+ * distinguishing prefixes of ss_dist_prefix, the characters prefix-doubling
+ * merge sort sends).  Errors as ss_select_splitters_batch (reads one word
+ * back). */
+int ss_select_splitters_chars_batch(const uint32_t *perm, const uint64_t *offsets, const uint32_t *weights,
+                                    uint64_t n, const uint64_t *set_off, uint32_t num_sets, uint32_t r,
+                                    uint32_t *splitter_ids, void *ws, size_t ws_bytes, void *stream);
+
 /* Workspace bytes for ss_gather_strings of m strings. */
 size_t ss_gather_workspace(uint64_t m);
 

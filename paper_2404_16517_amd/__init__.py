@@ -61,6 +61,8 @@ def lib():
             "ss_select_splitters_batch_workspace": ([], SZ),
             "ss_select_splitters_batch": ([P, U64, P, U32, U32, P, P, SZ, P], I32),
             "ss_gather_workspace": ([U64], SZ),
+            "ss_select_splitters_chars_batch_workspace": ([U64], SZ),
+            "ss_select_splitters_chars_batch": ([P, P, P, U64, P, U32, U32, P, P, SZ, P], I32),
             "ss_gather_strings": ([P, U64, P, U64, P, U64, P, P, U64, P, P, SZ, P], I32),
             "ss_bucket_bounds": ([P, U64, P, U64, P, P, U64, P, U32, P, P], I32),
             "ss_partition_encode_workspace": ([U64], SZ),
@@ -324,6 +326,22 @@ def select_splitters_batch(perm: torch.Tensor, set_off: torch.Tensor, r: int):
     return ids
 
 
+def select_splitters_chars_batch(perm: torch.Tensor, offsets: torch.Tensor, set_off: torch.Tensor, r: int,
+                                 weights: torch.Tensor | None = None):
+    """Character-based regular samples of every set (r - 1 per set), by string
+    lengths or by ``weights`` (per input index); (num_sets * (r-1),) uint32."""
+    n = perm.numel()
+    dev = perm.device
+    so = set_off.to(device=dev, dtype=torch.int64).contiguous()
+    k = max(so.numel() - 1, 0)
+    ids = _u32(max(k * (r - 1), 0), dev)
+    ws = _ws(lib().ss_select_splitters_chars_batch_workspace(n), dev)
+    _check(lib().ss_select_splitters_chars_batch(_p(perm.contiguous()), _p(offsets),
+                                                 _p(weights.contiguous()) if weights is not None else None, n,
+                                                 _p(so), k, r, _p(ids), _p(ws), ws.numel(), _stream(dev)))
+    return ids
+
+
 def gather_strings(bytes_, offsets, ids: torch.Tensor, cap_hint: int | None = None):
     """Strings ids[0..m) as a new string array (bytes, offsets).  The byte
     buffer starts at ``cap_hint`` bytes (default 1 KiB per string) and is
@@ -348,7 +366,11 @@ def gather_strings(bytes_, offsets, ids: torch.Tensor, cap_hint: int | None = No
 
 
 def bucket_bounds(bytes_, offsets, perm, spl_bytes, spl_offsets):
-    b, o, n = _dev_strings(bytes_, offsets)
+    """Bucket bounds (r+1 entries) of the sorted order ``perm`` (its values
+    index ``offsets``; it may cover any part of the string array) for the
+    r-1 splitters (spl_bytes, spl_offsets)."""
+    b, o, _ = _dev_strings(bytes_, offsets)
+    n = perm.numel()
     r = spl_offsets.numel()  # r-1 splitters
     out = torch.empty(r + 1, dtype=torch.int64, device=b.device)
     _check(lib().ss_bucket_bounds(_p(b), b.numel(), _p(o), n, _p(perm.contiguous()), _p(spl_bytes),

@@ -92,6 +92,104 @@ extern "C" int ss_select_splitters_batch(const uint32_t *perm, uint64_t n, const
     return SS_OK;
 }
 
+// ----------------------------------------------- character-based splitters
+//
+// Character-based regular sampling (Section 3.1, Appendix A): equally spaced
+// positions of each sorted set's character array, each shifted back to the
+// start of the string holding it.  P[i] = characters of the strings at sorted
+// positions < i (all sets in one scan); in set b = [lo, hi) with N_b =
+// P[hi] - P[lo], sample j (1..r-1) is at x = P[lo] + ceil(j N_b / r) - 1 and
+// picks the largest position k in [lo, hi) with P[k] <= x (empty strings share
+// P with the next string, so the pick always holds x); N_b = 0 picks lo.
+
+__global__ void k_char_counts(const u32 *perm, const u64 *off, const u32 *w, u64 n, u64 *P)
+{
+    const u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const u32 s = perm[i];
+    P[i] = w ? (u64)w[s] : off[s + 1] - off[s];
+}
+
+__global__ void k_select_chars_batch(const u32 *perm, const u64 *P, u64 n, const u64 *set_off, u32 num_sets,
+                                     u32 r, u32 *ids, u32 *bad)
+{
+    const u64 t = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    const u32 per = r - 1;
+    if (t >= (u64)num_sets * per) return;
+    const u32 b = (u32)(t / per);
+    const u32 j = (u32)(t - (u64)b * per) + 1;
+    const u64 lo = set_off[b], hi = set_off[b + 1];
+    const bool ok = lo < hi && hi <= n;
+    if (j == 1 && (!ok || (b == 0 && lo != 0) || (b == num_sets - 1 && hi != n))) atomicOr(bad, 1u);
+    u32 v = 0xFFFFFFFFu;
+    if (ok) {
+        const u64 base = P[lo], Nb = P[hi] - base;
+        u64 k = lo;
+        if (Nb > 0) {
+            const u64 x = base + ((u64)j * Nb + r - 1) / r - 1;
+            u64 a = lo, e = hi;  // largest k in [a, e) with P[k] <= x (P[lo] <= x holds)
+            while (e - a > 1) {
+                const u64 m = (a + e) >> 1;
+                if (P[m] <= x) a = m;
+                else e = m;
+            }
+            k = a;
+        }
+        v = perm[k];
+    }
+    ids[t] = v;
+}
+
+extern "C" size_t ss_select_splitters_chars_batch_workspace(uint64_t n)
+{
+    WsCounter c;
+    c.take<u64>(n + 1);
+    c.take<u64>(ss_scan_scratch_elems<u64>(n + 1));
+    c.take<u32>(1);
+    return c.used;
+}
+
+extern "C" int ss_select_splitters_chars_batch(const uint32_t *perm, const uint64_t *offsets, const uint32_t *weights,
+                                               uint64_t n, const uint64_t *set_off, uint32_t num_sets, uint32_t r,
+                                               uint32_t *splitter_ids, void *ws, size_t ws_bytes, void *stream)
+{
+    ss_clear_error();
+    if (n == 0 || r == 0 || num_sets == 0 || !perm || !offsets || !set_off || (r > 1 && !splitter_ids)) {
+        ss_set_error("select_splitters_chars_batch needs n >= 1, r >= 1, num_sets >= 1 and non-null arrays");
+        return SS_ERR_INVALID_ARG;
+    }
+    if (n >= 0xFFFFFFFFull || (u64)num_sets * (r - 1) >= 0xFFFFFFFFull) {
+        ss_set_error("n or num_sets * (r - 1) too large");
+        return SS_ERR_TOO_LARGE;
+    }
+    if (r == 1) return SS_OK;
+    WsArena a(ws, ws_bytes);
+    u64 *P = a.take<u64>(n + 1);
+    u64 *scratch = a.take<u64>(ss_scan_scratch_elems<u64>(n + 1));
+    u32 *bad = a.take<u32>(1);
+    if (a.overflow || !ws) {
+        ss_set_error("workspace too small: need %zu bytes", ss_select_splitters_chars_batch_workspace(n));
+        return SS_ERR_WORKSPACE;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    k_char_counts<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(perm, offsets, weights, n, P);
+    SS_CHECK_LAUNCH();
+    SS_TRY(ss_scan_exclusive<u64>(P, P, n, scratch, st));
+    SS_HIP(hipMemsetAsync(bad, 0, sizeof(u32), st));
+    const u64 total = (u64)num_sets * (r - 1);
+    k_select_chars_batch<<<(unsigned)ceil_div(total, 256), 256, 0, st>>>(perm, P, n, set_off, num_sets, r,
+                                                                         splitter_ids, bad);
+    SS_CHECK_LAUNCH();
+    u32 h;
+    SS_TRY(ss_read_u32(bad, &h, 1, st));
+    if (h) {
+        ss_set_error("every set must be non-empty, with set_off[0] = 0, set_off[num_sets] = n and "
+                     "set_off increasing");
+        return SS_ERR_INVALID_ARG;
+    }
+    return SS_OK;
+}
+
 // ---------------------------------------------------------------- gather
 
 __global__ void k_gather_lens(const u64 *off, const u32 *ids, u32 m, u64 *out)
