@@ -185,6 +185,21 @@ int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, ui
 /* (Synchronises the stream: the number of active strings is read back every
  * round.) */
 
+/* ss_dist_prefix in two calls that share the workspace, so that a caller can
+ * order the first pass against other work: ss_dist_prefix_first hashes every
+ * string's first bytes (all rounds up to 64 bytes, or 256 bytes when a sample
+ * shows long shared prefixes; it reads the sample's count back), then
+ * ss_dist_prefix_rounds (same arguments, same workspace, on a stream ordered
+ * after the first call) runs the remaining rounds and the duplicate
+ * detection.  Together they compute exactly what ss_dist_prefix computes.
+ * INVALID_ARG from ss_dist_prefix_rounds if the workspace holds no first
+ * pass for init_len. */
+int ss_dist_prefix_first(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                         uint32_t init_len, uint32_t hash_bits, void *ws, size_t ws_bytes, void *stream);
+int ss_dist_prefix_rounds(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                          uint32_t init_len, uint32_t hash_bits, uint32_t *dist_approx,
+                          uint32_t *rounds_host, void *ws, size_t ws_bytes, void *stream);
+
 /* The keys of the first `rounds` prefix-doubling rounds of every string, as
  * ss_dist_prefix's rounds compute them (Section 4: round t hashes the
  * l_t-prefix, l_t = init_len * 2^t), with every string kept active:

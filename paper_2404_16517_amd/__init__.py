@@ -56,6 +56,8 @@ def lib():
             "ss_dist_exact": ([P, U64, P, P, P, P], I32),
             "ss_dist_prefix_workspace": ([U64], SZ),
             "ss_dist_prefix": ([P, U64, P, U64, U32, U32, P, P, P, SZ, P], I32),
+            "ss_dist_prefix_first": ([P, U64, P, U64, U32, U32, P, SZ, P], I32),
+            "ss_dist_prefix_rounds": ([P, U64, P, U64, U32, U32, P, P, P, SZ, P], I32),
             "ss_doubling_keys": ([P, U64, P, U64, U32, U32, U32, U32, P, P, SZ, P], I32),
             "ss_select_splitters": ([U64, P, U32, P, P], I32),
             "ss_select_splitters_batch_workspace": ([], SZ),
@@ -284,6 +286,29 @@ def dist_prefix(bytes_, offsets, init_len: int = 8, hash_bits: int = 64, ws=None
     rounds = ctypes.c_uint32(0)
     _check(lib().ss_dist_prefix(_p(b), b.numel(), _p(o), n, init_len, hash_bits, _p(out), ctypes.byref(rounds),
                                 _p(ws), ws.numel(), _stream(dev)))
+    return out, int(rounds.value)
+
+
+def dist_prefix_first(bytes_, offsets, init_len: int = 8, hash_bits: int = 64, ws=None):
+    """The first hash pass of prefix doubling; returns the workspace that
+    dist_prefix_rounds continues from."""
+    b, o, n = _dev_strings(bytes_, offsets)
+    need = lib().ss_dist_prefix_workspace(n)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, b.device)
+    _check(lib().ss_dist_prefix_first(_p(b), b.numel(), _p(o), n, init_len, hash_bits, _p(ws), ws.numel(),
+                                      _stream(b.device)))
+    return ws
+
+
+def dist_prefix_rounds(bytes_, offsets, ws, init_len: int = 8, hash_bits: int = 64):
+    """The remaining rounds after dist_prefix_first (same workspace).
+    Returns (dist_approx int32[n] by input index, rounds)."""
+    b, o, n = _dev_strings(bytes_, offsets)
+    out = _u32(n, b.device)
+    rounds = ctypes.c_uint32(0)
+    _check(lib().ss_dist_prefix_rounds(_p(b), b.numel(), _p(o), n, init_len, hash_bits, _p(out),
+                                       ctypes.byref(rounds), _p(ws), ws.numel(), _stream(b.device)))
     return out, int(rounds.value)
 
 

@@ -1087,6 +1087,7 @@ __global__ __launch_bounds__(256) void k_dedup(const u64 *keys, int kin, const u
 #define HDR_FIRST 8
 #define HDR_DEEP (HDR_FIRST + 3 * PRE_ALL)
 #define HDR_ROUND (HDR_DEEP + 1)
+#define HDR_PRECOUNT (HDR_ROUND + 6)  // rounds the first pass precomputed (for a later rounds call)
 struct PdWs {
     u32 *actA, *actB, *ctr;
     u64 *hdr, *keys, *keysB, *keysC, *state, *pre, *tab;
@@ -1245,9 +1246,16 @@ static int first_pass(const uint8_t *bytes, uint64_t N, const uint64_t *offsets,
     return SS_OK;
 }
 
-extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
-                              uint32_t init_len, uint32_t hash_bits, uint32_t *dist_approx,
-                              uint32_t *rounds_host, void *ws, size_t ws_bytes, void *stream)
+__global__ void k_store_u64(u64 *p, u64 v) { *p = v; }
+
+enum { PD_FIRST = 1, PD_ROUNDS = 2 };
+
+// Prefix doubling in two parts that share the workspace: PD_FIRST hashes the
+// first pass (and leaves its flags and round count in the header), PD_ROUNDS
+// runs the remaining rounds and the duplicate detection from there.
+static int pd_run(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n, uint32_t init_len,
+                  uint32_t hash_bits, uint32_t *dist_approx, uint32_t *rounds_host, void *ws, size_t ws_bytes,
+                  void *stream, int parts)
 {
     ss_clear_error();
     if (n >= 0xFFFFFFFFull) { ss_set_error("n too large"); return SS_ERR_TOO_LARGE; }
@@ -1258,7 +1266,7 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
     if (hash_bits < 8 || hash_bits > 64) { ss_set_error("hash_bits must be 8..64"); return SS_ERR_INVALID_ARG; }
     if (rounds_host) *rounds_host = 0;
     if (n == 0) return SS_OK;
-    if (!offsets || !dist_approx) { ss_set_error("null pointer"); return SS_ERR_INVALID_ARG; }
+    if (!offsets || (!dist_approx && (parts & PD_ROUNDS))) { ss_set_error("null pointer"); return SS_ERR_INVALID_ARG; }
     hipStream_t st = (hipStream_t)stream;
     WsArena a(ws, ws_bytes);
     PdWs w;
@@ -1273,16 +1281,37 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
     // counters: [0], [1] active-list lengths (current / next, swapped per
     // round), [2], [3] the round's flags, [4..] flags of the first-pass rounds
     u32 *ctr = w.ctr;
-    u64 *fl_first = w.hdr + HDR_FIRST, *fl_round = w.hdr + HDR_ROUND;
-    k_store_u32<<<1, 1, 0, st>>>(ctr, (u32)n);
-    SS_CHECK_LAUNCH();
+    u64 *fl_round = w.hdr + HDR_ROUND;
     // rounds whose prefix length is at most PRE_MAX are hashed in one first pass
     PreLens P{};
     u32 pf[2 * PRE_ALL] = {};
-    SS_TRY(first_pass(bytes, N, offsets, n, init_len, hash_bits, w, FP_PROBE, P, st));
-    if (P.count) {
-        u64 F[3 * PRE_ALL];  // the flags of every precomputed round
-        SS_TRY(ss_read_u64(w.hdr + HDR_FIRST, F, 3 * PRE_ALL, st));
+    if (parts & PD_FIRST) {
+        k_store_u32<<<1, 1, 0, st>>>(ctr, (u32)n);
+        SS_CHECK_LAUNCH();
+        SS_TRY(first_pass(bytes, N, offsets, n, init_len, hash_bits, w, FP_PROBE, P, st));
+        k_store_u64<<<1, 1, 0, st>>>(w.hdr + HDR_PRECOUNT, P.count);
+        SS_CHECK_LAUNCH();
+        if (!(parts & PD_ROUNDS)) return SS_OK;
+    }
+    {
+        // the flags of every precomputed round and (rounds call alone) their count
+        u64 F[HDR_PRECOUNT + 1 - HDR_FIRST];
+        SS_TRY(ss_read_u64(w.hdr + HDR_FIRST, F, HDR_PRECOUNT + 1 - HDR_FIRST, st));
+        if (!(parts & PD_FIRST)) {
+            // the lengths follow from init_len and the count (plain pass: the
+            // rounds up to 64 bytes; deep pass: and the two after)
+            const u64 cnt = F[HDR_PRECOUNT - HDR_FIRST];
+            P = PreLens{};
+            for (u64 L = init_len; L <= PRE_MAX && P.count < PRE_SLOTS; L *= 2) P.l[P.count++] = L;
+            if (cnt == (u64)P.count + 2) {
+                P.l[P.count] = 2 * PRE_MAX;
+                P.l[P.count + 1] = 4 * PRE_MAX;
+                P.count += 2;
+            } else if (cnt != P.count) {
+                ss_set_error("the workspace holds no first pass for init_len %u", init_len);
+                return SS_ERR_INVALID_ARG;
+            }
+        }
         for (u32 r = 0; r < P.count; r++) {
             pf[2 * r] = F[3 * r] != F[3 * r + 1];
             pf[2 * r + 1] = F[3 * r + 2] != 0;
@@ -1446,6 +1475,28 @@ extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *
     }
     if (rounds_host) *rounds_host = rounds;
     return SS_OK;
+}
+
+extern "C" int ss_dist_prefix(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                              uint32_t init_len, uint32_t hash_bits, uint32_t *dist_approx,
+                              uint32_t *rounds_host, void *ws, size_t ws_bytes, void *stream)
+{
+    return pd_run(bytes, N, offsets, n, init_len, hash_bits, dist_approx, rounds_host, ws, ws_bytes, stream,
+                  PD_FIRST | PD_ROUNDS);
+}
+
+extern "C" int ss_dist_prefix_first(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                                    uint32_t init_len, uint32_t hash_bits, void *ws, size_t ws_bytes, void *stream)
+{
+    return pd_run(bytes, N, offsets, n, init_len, hash_bits, nullptr, nullptr, ws, ws_bytes, stream, PD_FIRST);
+}
+
+extern "C" int ss_dist_prefix_rounds(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                                     uint32_t init_len, uint32_t hash_bits, uint32_t *dist_approx,
+                                     uint32_t *rounds_host, void *ws, size_t ws_bytes, void *stream)
+{
+    return pd_run(bytes, N, offsets, n, init_len, hash_bits, dist_approx, rounds_host, ws, ws_bytes, stream,
+                  PD_ROUNDS);
 }
 
 // The keys of the first `rounds` doubling rounds for every string, as the

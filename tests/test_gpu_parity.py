@@ -880,3 +880,33 @@ def test_join_group_lcps_leaves_other_positions():
     go = torch.tensor([0, 1, 2, 3, 4], dtype=torch.int32, device=DEV)  # group 1 is empty
     ss.join_group_lcps(g.bytes, g.offsets, order, lcp, rb, re_, go)
     assert list(u32(lcp)) == [77, 77, 1, 0, 77, 77]
+
+
+@pytest.mark.parametrize("case", ["c0", "text", "deep_mixed", "init64"])
+def test_dist_prefix_in_two_calls_equals_one(case):
+    """ss_dist_prefix_first then ss_dist_prefix_rounds (same workspace, the
+    rounds on another stream ordered after the first) = ss_dist_prefix."""
+    if case == "c0":
+        s, l0 = synth.dn_strings(100_000, 100, 0.5, seed=0), 8
+    elif case == "text":
+        s, l0 = synth.text_strings(200_000, seed=5), 8
+    elif case == "deep_mixed":
+        s, l0 = _deep_mixed(3), 8
+    else:
+        s, l0 = synth.text_strings(50_000, seed=6, median=90), 128
+    g = s.to(DEV)
+    ref, r_ref = ss.dist_prefix(g.bytes, g.offsets, l0, 64)
+    ws = ss.dist_prefix_first(g.bytes, g.offsets, l0, 64)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        got, rounds = ss.dist_prefix_rounds(g.bytes, g.offsets, ws, l0, 64)
+    torch.cuda.synchronize()
+    assert rounds == r_ref and torch.equal(got, ref)
+
+
+def test_dist_prefix_rounds_without_a_first_pass_is_refused():
+    s = synth.text_strings(1000, seed=1).to(DEV)
+    ws = torch.zeros(ss.lib().ss_dist_prefix_workspace(s.n), dtype=torch.uint8, device=DEV)
+    with pytest.raises(ss.StrsortError):
+        ss.dist_prefix_rounds(s.bytes, s.offsets, ws, 8, 64)
