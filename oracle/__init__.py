@@ -51,6 +51,7 @@ def lib():
         L.or_fc_decode.argtypes = [U32, P, P, P, P, P, U64, P, P]; L.or_fc_decode.restype = None
         L.or_merge.argtypes = [U32, P, P, P, P, P, P, U64, P, P, P]; L.or_merge.restype = I32
         L.or_check_sorted.argtypes = [P, P, U64, P, P]; L.or_check_sorted.restype = ctypes.c_int64
+        L.or_suffix_sort.argtypes = [P, U64, P, P]; L.or_suffix_sort.restype = I32
         _lib = L
     return _lib
 
@@ -220,3 +221,15 @@ def check_sorted(bytes_, offsets, perm, lcp_=None) -> int:
     perm = np.ascontiguousarray(perm, dtype=np.uint32)
     lc = None if lcp_ is None else np.ascontiguousarray(lcp_, dtype=np.uint32)
     return int(lib().or_check_sorted(_p(b), _p(o), n, _p(perm), _p(lc)))
+
+
+def suffix_sort(text) -> tuple[np.ndarray, np.ndarray]:
+    """Suffix array and LCP array of one text (numpy uint8)."""
+    t = np.ascontiguousarray(np.asarray(text, dtype=np.uint8))
+    N = t.size
+    if N == 0:
+        return np.zeros(0, np.uint32), np.zeros(0, np.uint32)
+    sa = np.empty(N, np.uint32)
+    lc = np.empty(N, np.uint32)
+    lib().or_suffix_sort(_p(t), N, _p(sa), _p(lc))
+    return sa, lc

@@ -443,6 +443,39 @@ int or_merge(uint32_t k, const uint64_t *run_off, const uint32_t *fc_lcp, const 
     return 0;
 }
 
+/* ------------------------------------------------------------ suffixes */
+
+/* Suffix sorting, the application of string sorting the paper names as
+ * future work (Section 6): the suffixes T[i, N) of one text, which overlap
+ * and are never stored as separate strings, in lexicographic order (a suffix
+ * that is a prefix of another sorts first; suffixes are distinct, so there
+ * are no ties).  Plain definition: sort the start positions with a
+ * suffix comparator.  sa (out, N) = start of the k-th smallest suffix;
+ * lcp (out, N, nullable) = lcp[0] = 0, lcp[k] = lcp(T[sa[k-1], N), T[sa[k], N)).
+ * Returns 0, or -1 on allocation failure. */
+static const uint8_t *g_sfx_text;
+static uint64_t g_sfx_n;
+
+static int sfx_cmp(const void *x, const void *y)
+{
+    uint32_t a = *(const uint32_t *)x, b = *(const uint32_t *)y;
+    return str_cmp(g_sfx_text + a, g_sfx_n - a, g_sfx_text + b, g_sfx_n - b);
+}
+
+int or_suffix_sort(const uint8_t *text, uint64_t N, uint32_t *sa, uint32_t *lcp)
+{
+    for (uint64_t i = 0; i < N; i++) sa[i] = (uint32_t)i;
+    g_sfx_text = text;  /* (single-threaded oracle) */
+    g_sfx_n = N;
+    qsort(sa, N, sizeof(uint32_t), sfx_cmp);
+    if (lcp && N > 0) {
+        lcp[0] = 0;
+        for (uint64_t k = 1; k < N; k++)
+            lcp[k] = (uint32_t)str_lcp(text + sa[k - 1], N - sa[k - 1], text + sa[k], N - sa[k]);
+    }
+    return 0;
+}
+
 /* ---------------------------------------------------------------- checking */
 
 /* Full check of a claimed sort + LCP result at any size, in linear time:

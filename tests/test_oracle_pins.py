@@ -587,3 +587,40 @@ def test_char_splitters_bound_bucket_characters(seed):
     assert by_chars.sum() == by_strings.sum() == N
     assert by_chars.max() <= bound
     assert by_strings.max() > 2 * by_chars.max()
+
+
+# ----------------------------------------------------------------- suffixes
+
+def _py_suffix_array(t: bytes):
+    sa = sorted(range(len(t)), key=lambda i: t[i:])
+    lcp = ([0] if t else []) + [_py_lcp(t[sa[k - 1]:], t[sa[k]:]) for k in range(1, len(t))]
+    return sa, lcp
+
+
+def test_suffix_sort_every_binary_text_up_to_10():
+    """All 2^N texts over {0x00, 0x01} (N <= 10) against Python's ordering of
+    the suffixes as bytes."""
+    for N in range(0, 11):
+        for bits in range(1 << N):
+            t = bytes((bits >> k) & 1 for k in range(N))
+            sa, lcp = oracle.suffix_sort(np.frombuffer(t, np.uint8))
+            esa, elcp = _py_suffix_array(t)
+            assert list(sa) == esa and list(lcp) == elcp, t
+
+
+@pytest.mark.parametrize("seed,N,alpha", [(0, 2000, b"AB"), (1, 3000, b"ACGT"), (2, 1500, bytes(range(256))),
+                                          (3, 2500, b"A")])
+def test_suffix_sort_random_texts(seed, N, alpha):
+    rng = random.Random(seed)
+    t = bytes(rng.choice(alpha) for _ in range(N))
+    sa, lcp = oracle.suffix_sort(np.frombuffer(t, np.uint8))
+    esa, elcp = _py_suffix_array(t)
+    assert list(sa) == esa and list(lcp) == elcp
+
+
+def test_suffix_sort_unary_text_closed_form():
+    """a^N: shorter suffixes first, lcp of a^(k-1) and a^k is k - 1."""
+    N = 5000
+    sa, lcp = oracle.suffix_sort(np.full(N, 97, np.uint8))
+    assert list(sa) == list(range(N - 1, -1, -1))
+    assert list(lcp) == [0] + list(range(1, N))
