@@ -402,6 +402,28 @@ int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_t *run_end,
                  uint32_t *out_len, uint64_t out_cap, uint64_t *n_out_host, void *ws, size_t ws_bytes,
                  void *stream);
 
+/* ------------------------------------------------------------- suffixes */
+
+/* Workspace bytes for ss_suffix_sort of a text of N bytes (about
+ * 26 B + the ss_sort workspace per suffix). */
+size_t ss_suffix_sort_workspace(uint64_t N);
+
+/* Suffix sorting by sorting strings of equal length (the application
+ * Section 6 names), space-efficiently: the N suffixes T[i, N) of one text
+ * are never stored.  Prefix doubling over ranks: each step sorts one
+ * equal-length string per suffix -- its pair (rank of its h-prefix, rank of
+ * the h-prefix h bytes later) as 7 big-endian bytes (8 when N >= 2^28) --
+ * with ss_sort and re-ranks, doubling h from 6 until every rank is distinct
+ * (about log2(max LCP / 6) + 1 steps; one read-back per step).
+ *   sa (out, N)  start of the k-th smallest suffix (a proper prefix sorts
+ *                first; suffixes are distinct).
+ *   lcp (out, N, nullable)  lcp[0] = 0, lcp[k] = LCP of the suffixes at k-1
+ *                and k, by comparison (cost: the sum of the LCPs).
+ *   steps_host (host, out, nullable)  sorting steps run.
+ * TOO_LARGE if N >= 2^32 - 1. */
+int ss_suffix_sort(const uint8_t *text, uint64_t N, uint32_t *sa, uint32_t *lcp, uint32_t *steps_host,
+                   void *ws, size_t ws_bytes, void *stream);
+
 /* ---------------------------------------------------------------- graphs */
 
 /* A launch sequence of library calls captured once from a stream and replayed

@@ -52,6 +52,7 @@ def lib():
         L.or_merge.argtypes = [U32, P, P, P, P, P, P, U64, P, P, P]; L.or_merge.restype = I32
         L.or_check_sorted.argtypes = [P, P, U64, P, P]; L.or_check_sorted.restype = ctypes.c_int64
         L.or_suffix_sort.argtypes = [P, U64, P, P]; L.or_suffix_sort.restype = I32
+        L.or_check_suffixes.argtypes = [P, U64, P, P]; L.or_check_suffixes.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -233,3 +234,11 @@ def suffix_sort(text) -> tuple[np.ndarray, np.ndarray]:
     lc = np.empty(N, np.uint32)
     lib().or_suffix_sort(_p(t), N, _p(sa), _p(lc))
     return sa, lc
+
+
+def check_suffixes(text, sa, lcp_=None) -> int:
+    """-1 if sa is the suffix array of text (and lcp, if given, exact)."""
+    t = np.ascontiguousarray(np.asarray(text, dtype=np.uint8))
+    sa = np.ascontiguousarray(sa, dtype=np.uint32)
+    lc = None if lcp_ is None else np.ascontiguousarray(lcp_, dtype=np.uint32)
+    return int(lib().or_check_suffixes(_p(t), t.size, _p(sa), _p(lc)))

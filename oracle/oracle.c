@@ -476,6 +476,28 @@ int or_suffix_sort(const uint8_t *text, uint64_t N, uint32_t *sa, uint32_t *lcp)
     return 0;
 }
 
+/* Check of a claimed suffix array at any size: sa must be a permutation of
+ * 0..N-1 with every adjacent pair of suffixes in order, and lcp (nullable)
+ * exact for every pair.  Time O(N + sum of the LCPs).  Returns -1 when all
+ * holds, -2 if sa is not a permutation, else the first bad position. */
+int64_t or_check_suffixes(const uint8_t *text, uint64_t N, const uint32_t *sa, const uint32_t *lcp)
+{
+    uint8_t *seen = (uint8_t *)calloc(N ? N : 1, 1);
+    if (!seen) return -3;
+    for (uint64_t k = 0; k < N; k++) {
+        if (sa[k] >= N || seen[sa[k]]) { free(seen); return -2; }
+        seen[sa[k]] = 1;
+    }
+    free(seen);
+    if (lcp && N > 0 && lcp[0] != 0) return 0;
+    for (uint64_t k = 1; k < N; k++) {
+        const uint64_t a = sa[k - 1], b = sa[k];
+        if (str_cmp(text + a, N - a, text + b, N - b) >= 0) return (int64_t)k;
+        if (lcp && lcp[k] != (uint32_t)str_lcp(text + a, N - a, text + b, N - b)) return (int64_t)k;
+    }
+    return -1;
+}
+
 /* ---------------------------------------------------------------- checking */
 
 /* Full check of a claimed sort + LCP result at any size, in linear time:

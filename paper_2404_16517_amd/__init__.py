@@ -83,6 +83,8 @@ def lib():
             "ss_dist_exact_bounded": ([P, P, P, U64, P, P], I32),
             "ss_join_group_lcps": ([P, U64, P, P, U64, U32, P, P, U32, P, P, P], I32),
             "ss_set_tuning": ([I32, I32], I32),
+            "ss_suffix_sort_workspace": ([U64], SZ),
+            "ss_suffix_sort": ([P, U64, P, P, P, P, SZ, P], I32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -567,3 +569,23 @@ def lcp_merge_runs(run_off, fc_lcp, fc_len, fc_id, suf_off, suf, ws=None):
     k = ro.numel() - 1
     go = torch.tensor([0, k], dtype=torch.int32, device=fc_lcp.device)
     return lcp_merge(ro[:-1], ro[1:], go, fc_lcp, fc_len, fc_id, suf_off, suf, ws=ws)
+
+
+# ---------------------------------------------------------------- suffixes
+
+def suffix_sort(text: torch.Tensor, with_lcp: bool = True, ws=None):
+    """Suffix array (and LCP array) of a uint8 device tensor.
+    Returns (sa int32[N], lcp int32[N] or None, steps)."""
+    if not text.is_cuda or text.dtype != torch.uint8 or not text.is_contiguous():
+        raise StrsortError("text must be a contiguous uint8 GPU tensor")
+    N = text.numel()
+    dev = text.device
+    sa = _u32(N, dev)
+    lc = _u32(N, dev) if with_lcp else None
+    need = lib().ss_suffix_sort_workspace(N)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, dev)
+    steps = ctypes.c_uint32(0)
+    _check(lib().ss_suffix_sort(_p(text), N, _p(sa), _p(lc), ctypes.byref(steps), _p(ws), ws.numel(),
+                                _stream(dev)))
+    return sa, lc, int(steps.value)

@@ -624,3 +624,14 @@ def test_suffix_sort_unary_text_closed_form():
     sa, lcp = oracle.suffix_sort(np.full(N, 97, np.uint8))
     assert list(sa) == list(range(N - 1, -1, -1))
     assert list(lcp) == [0] + list(range(1, N))
+
+
+def test_check_suffixes_accepts_exactly_the_suffix_array():
+    t = np.frombuffer(b"mississippi", np.uint8)
+    sa, lcp = oracle.suffix_sort(t)
+    assert oracle.check_suffixes(t, sa, lcp) == -1
+    bad = sa.copy(); bad[[3, 4]] = bad[[4, 3]]
+    assert oracle.check_suffixes(t, bad) == 4
+    assert oracle.check_suffixes(t, np.zeros(11, np.uint32)) == -2
+    wrong = lcp.copy(); wrong[5] += 1
+    assert oracle.check_suffixes(t, sa, wrong) == 5
