@@ -615,7 +615,7 @@ def main():
     import synth
 
     from paper_2404_16517_amd import autotune
-    tuned = autotune.apply()
+    tuned = autotune.apply("dn")
     dev = torch.device("cuda:0")
     if args.calibrate_copy > 0:
         nbytes = int(args.calibrate_copy * 1e9) // 16 * 16
@@ -740,10 +740,15 @@ def main():
         pipe.ms_mode = False
         pipe.overlap = was
     if not args.no_batch:
+        used = autotune.apply("sets")
         out["batch"] = batch_leg(ss, torch, synth)
+        out["batch"]["tuning"] = used or "library defaults"
+        autotune.apply("dn")
         print(f"# batch leg: {out['batch']}", file=sys.stderr, flush=True)
     if not args.no_splitters:
+        autotune.apply("text")
         out["splitters_text"] = splitters_leg(ss, torch, synth)
+        autotune.apply("dn")
         print(f"# splitters leg: {out['splitters_text']}", file=sys.stderr, flush=True)
     if not args.no_suffix:
         out["suffix_sort"] = suffix_leg(ss, torch, synth)

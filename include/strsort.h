@@ -469,9 +469,15 @@ size_t ss_profile_names(char *buf, size_t cap);
  *                      (128, 256, 512 or 1024; default 1024).
  *   SS_TUNE_TILE       elements per workgroup in radix passes (1024..16384,
  *                      power of two; default 4096).
- * Returns the previous value, or SS_ERR_INVALID_ARG. */
+ *   SS_TUNE_DIGIT_BITS radix digit width: 8 (a level per key byte, 256
+ *                      buckets) or 11 (six levels per 64-bit key, 2048
+ *                      buckets); 11 takes effect only with a tile >= 4096 and
+ *                      SMALL_MAX >= 512, else 8 is used (default 8).
+ * Results never depend on the tuning.  Returns the previous value, or
+ * SS_ERR_INVALID_ARG. */
 #define SS_TUNE_SMALL_MAX 1
 #define SS_TUNE_TILE 2
+#define SS_TUNE_DIGIT_BITS 3
 int ss_set_tuning(int param, int value);
 
 #ifdef __cplusplus

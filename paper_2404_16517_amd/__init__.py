@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libstrsort.so")
 
 SS_TUNE_SMALL_MAX = 1
 SS_TUNE_TILE = 2
+SS_TUNE_DIGIT_BITS = 3
 SS_ERR_CAPACITY = -5
 
 

@@ -96,6 +96,7 @@ void ss_prof_drop_last(const char *name);
 // Tunables (set by ss_set_tuning).
 extern int g_small_max;
 extern int g_tile;
+extern int g_digit_bits;  // radix digit width (8 or 11 bits)
 
 // ------------------------------------------------------ device-wide scans
 

@@ -51,18 +51,6 @@ enum { H_ACT = 0, H_LARGE = 1, H_HIST = 2, H_REMAIN = 3, H_NHDR = 4 };
 
 // ------------------------------------------------------------ wave helpers
 
-// Lanes of this wave holding the same 8-bit digit (restricted to `valid`).
-__device__ __forceinline__ u64 match_digit(u32 digit, bool valid)
-{
-    u64 m = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; b++) {
-        u64 bb = __ballot((digit >> b) & 1);
-        m &= ((digit >> b) & 1) ? bb : ~bb;
-    }
-    return m;
-}
-
 // Wave-aggregated atomic add of per-lane values.
 __device__ __forceinline__ void wave_add(u32 v, u32 *counter)
 {
@@ -161,11 +149,11 @@ __global__ void k_round_tiles(const Seg *segs, const u32 *nsegp, u32 tile, u32 *
 
 // Start of a radix level: the radix list's length and its histogram length
 // go to the header, the counters of the next level's radix list are reset.
-__global__ void k_level_begin(u32 *ctr, u32 *hdr)
+__global__ void k_level_begin(u32 *ctr, u32 *hdr, u32 nb)
 {
     if (threadIdx.x == 0) {
         hdr[H_LARGE] = ctr[C_LARGE];
-        hdr[H_HIST] = 256u * ctr[C_LTILES];
+        hdr[H_HIST] = nb * ctr[C_LTILES];
         ctr[C_LARGE] = 0;
         ctr[C_LTILES] = 0;
         ctr[C_LELEM] = 0;
@@ -481,16 +469,49 @@ __global__ void k_classify(const Seg *act, const u32 *nactp, const u32 *skipv, u
 }
 
 // ------------------------------------------------------------ radix passes
+//
+// A radix level sorts a segment by one digit of the 64-bit key.  The digit
+// width W is 8 bits (eight levels per key, one per byte) or 11 bits (six
+// levels: five of 11 bits and a last one of 9 that ends with the key's
+// length byte).  Level l covers key bits [lo, hi) with hi = 64 - W l and
+// lo = max(0, hi - W); its histograms have 2^W buckets.
 
-__device__ __forceinline__ u32 digit_of(u64 k, u32 level) { return (u32)(k >> (56 - 8 * level)) & 0xFFu; }
+template <u32 W>
+struct Digits {
+    static constexpr u32 NB = 1u << W;                 // buckets of a level
+    static constexpr u32 LEVELS = (64 + W - 1) / W;    // levels of one key
+    static constexpr u32 DPT = NB / 256;               // digits per thread of a 256-thread workgroup
+};
 
-// Per-tile histogram of the segment's current byte, digit-major per segment:
-// hist[256*tstart[s] + d*T_s + lt].  Also the segment's min and max key.
-template <bool LOOP>
+template <u32 W>
+__device__ __forceinline__ u32 digit_of(u64 k, u32 level)
+{
+    const u32 hi = 64 - W * level;
+    const u32 lo = hi > W ? hi - W : 0u;
+    return (u32)(k >> lo) & ((1u << (hi - lo)) - 1u);
+}
+
+// Lanes of this wave holding the same W-bit digit (restricted to `valid`).
+template <u32 W>
+__device__ __forceinline__ u64 match_digit_w(u32 digit, bool valid)
+{
+    u64 m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < (int)W; b++) {
+        u64 bb = __ballot((digit >> b) & 1);
+        m &= ((digit >> b) & 1) ? bb : ~bb;
+    }
+    return m;
+}
+
+// Per-tile histogram of the segment's current digit, digit-major per
+// segment: hist[NB*tstart[s] + d*T_s + lt].  Also the segment's min and max key.
+template <bool LOOP, u32 W>
 __global__ __launch_bounds__(NT) void k_hist(const Seg *segs, const u32 *tstart, const u32 *nsegp, u32 tile,
                                              const u64 *keyA, const u64 *keyB, u32 *hist, u64 *smin, u64 *smax)
 {
-    __shared__ u32 h[256];
+    constexpr u32 NB = Digits<W>::NB;
+    __shared__ u32 h[NB];
     const u32 nseg = *nsegp;
     const u32 ntiles = LOOP ? tstart[nseg] : 0u;
     TILE_LOOP(t, ntiles) {
@@ -502,15 +523,15 @@ __global__ __launch_bounds__(NT) void k_hist(const Seg *segs, const u32 *tstart,
     const u32 level = g.aux & 15;
     const u32 b0 = g.begin + lt * tile;
     const u32 b1 = min(g.end, b0 + tile);
-    h[threadIdx.x] = 0;
+    for (u32 d = threadIdx.x; d < NB; d += NT) h[d] = 0;
     __syncthreads();
     u64 mn = ~0ull, mx = 0;
     for (u32 c = b0; c < b1; c += NT) {
         const u32 i = c + threadIdx.x;
         const bool valid = i < b1;
         u64 k = valid ? keys[i] : 0;
-        u32 d = digit_of(k, level);
-        u64 peers = match_digit(d, valid);
+        u32 d = digit_of<W>(k, level);
+        u64 peers = match_digit_w<W>(d, valid);
         if (valid) {
             mn = k < mn ? k : mn;
             mx = k > mx ? k : mx;
@@ -518,7 +539,7 @@ __global__ __launch_bounds__(NT) void k_hist(const Seg *segs, const u32 *tstart,
         }
     }
     __syncthreads();
-    hist[256u * tstart[s] + threadIdx.x * T + lt] = h[threadIdx.x];
+    for (u32 d = threadIdx.x; d < NB; d += NT) hist[NB * tstart[s] + d * T + lt] = h[d];
     mn = block_min(mn);
     mx = block_max(mx);  // (ends with a barrier: h is free again)
     if (threadIdx.x == 0) {
@@ -549,9 +570,11 @@ struct EmitItem {
     uint2 bv;
 };
 
+template <u32 W>
 __device__ __forceinline__ EmitItem emit_item(const Seg *segs, const u32 *tstart, const u32 *hist, const u64 *smin,
                                               const u64 *smax, const EmitOut &o, u32 s, u32 d, bool *scat)
 {
+    constexpr u32 NB = Digits<W>::NB;
     EmitItem it{K_NONE, Seg{0, 0, 0, 0}, false, make_uint2(0, 0)};
     const Seg g = segs[s];
     const u32 level = g.aux & 15;
@@ -570,19 +593,19 @@ __device__ __forceinline__ EmitItem emit_item(const Seg *segs, const u32 *tstart
         }
         return it;
     }
-    const u32 fb = __clzll(mn ^ mx) >> 3;  // first byte where the keys differ
-    if (fb > level) {
-        // bytes level..fb-1 are common to the whole segment: no scatter needed
+    const u32 fd = (u32)__clzll(mn ^ mx) / W;  // first digit where the keys differ
+    if (fd > level) {
+        // digits level..fd-1 are common to the whole segment: no scatter needed
         *scat = false;
-        if (d == 0) { it.kind = K_LARGE; it.ns = Seg{g.begin, g.end, g.depth, fb | pf}; }
+        if (d == 0) { it.kind = K_LARGE; it.ns = Seg{g.begin, g.end, g.depth, fd | pf}; }
         return it;
     }
     *scat = true;
     const u32 cf = pf ? 0u : (u32)SEG_INB;  // the scatter writes the other arrays
     const u32 ts = tstart[s];
     const u32 T = tstart[s + 1] - ts;
-    const u32 e = 256u * ts + d * T;
-    const u32 base = hist[256u * ts];
+    const u32 e = NB * ts + d * T;
+    const u32 base = hist[NB * ts];
     const u32 start = hist[e] - base;
     const u32 cnt = hist[e + T] - hist[e];
     const u32 sb = g.begin + start, se = sb + cnt;
@@ -590,9 +613,12 @@ __device__ __forceinline__ EmitItem emit_item(const Seg *segs, const u32 *tstart
     it.bv = make_uint2(sb, g.depth);
     it.ns = Seg{sb, se, g.depth, cf};
     if (cnt >= 2) {
-        if (level == 7) {
-            if (d == 8) { it.kind = K_NEXT; it.ns = Seg{sb, se, g.depth + 7, SEG_SKIP}; }
-            else { it.kind = K_IDENT; it.ns = Seg{sb, se, g.depth + d, 0}; }
+        if (level == Digits<W>::LEVELS - 1) {
+            // the last digit ends with the key's length byte: the bucket's
+            // keys are equal in all 64 bits
+            const u32 c8 = d & 0xFFu;
+            if (c8 == 8) { it.kind = K_NEXT; it.ns = Seg{sb, se, g.depth + 7, SEG_SKIP}; }
+            else { it.kind = K_IDENT; it.ns = Seg{sb, se, g.depth + c8, 0}; }
         } else if (cnt <= WS_MAX) {
             it.kind = K_TINY;
         } else if (cnt <= o.small_max) {
@@ -605,37 +631,39 @@ __device__ __forceinline__ EmitItem emit_item(const Seg *segs, const u32 *tstart
     return it;
 }
 
-#define EPB 8  // radix segments per workgroup in k_emit
+#define EPB 8  // emit items per thread in k_emit: 8 segments of 256 digits, or 1 segment of 2048
 
 // Digit counts from the scanned histogram and emission of the sub-segments.
-// A workgroup takes EPB segments (thread d = digit d): it counts its entries in
-// LDS, reserves room in every list with one global atomic per list, and then
-// writes the entries.
-template <bool LOOP>
+// A workgroup takes 8 / DPT segments (thread x = digits x + 256 r, r < DPT):
+// it counts its entries in LDS, reserves room in every list with one global
+// atomic per list, and then writes the entries.
+template <bool LOOP, u32 W>
 __global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart, const u32 *nsegp,
                                               const u32 *hist, const u64 *smin, const u64 *smax,
                                               EmitOut o)
 {
+    constexpr u32 NB = Digits<W>::NB, DPT = Digits<W>::DPT, SPG = EPB / DPT;  // segments per group
     __shared__ u32 lcount[K_KINDS], lslot[K_KINDS], lsum[7], gbase[K_KINDS];
     const u32 nseg = *nsegp;
-    const u32 ngrp = LOOP ? (nseg + EPB - 1) / EPB : 0u;
+    const u32 ngrp = LOOP ? (nseg + SPG - 1) / SPG : 0u;
     TILE_LOOP(grp, ngrp) {
-    const u32 s0 = grp * EPB;
-    const u32 d = threadIdx.x;
-    if (d < K_KINDS) { lcount[d] = 0; lslot[d] = 0; }
-    if (d < 7) lsum[d] = 0;
+    const u32 s0 = grp * SPG;
+    const u32 tx = threadIdx.x;
+    if (tx < K_KINDS) { lcount[tx] = 0; lslot[tx] = 0; }
+    if (tx < 7) lsum[tx] = 0;
     __syncthreads();
     EmitItem it[EPB];
 #pragma unroll
     for (u32 q = 0; q < EPB; q++) {
-        const u32 s = s0 + q;
+        const u32 s = s0 + q / DPT;
+        const u32 d = tx + 256u * (q % DPT);
         it[q].kind = K_NONE;
         it[q].bnd = false;
         if (s >= nseg) continue;
         bool sc = false;
-        it[q] = emit_item(segs, tstart, hist, smin, smax, o, s, d, &sc);
+        it[q] = emit_item<W>(segs, tstart, hist, smin, smax, o, s, d, &sc);
         if (d == 0) o.scat[s] = sc ? 1 : 0;
-        o.kinds[256u * s + d] = (u8)it[q].kind;
+        o.kinds[NB * s + d] = (u8)it[q].kind;
         const EmitItem &x = it[q];
         const u32 cnt = x.ns.end - x.ns.begin;
         if (x.bnd) atomicAdd(&lcount[0], 1u);
@@ -647,7 +675,7 @@ __global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart
         if (x.kind == K_TINY) atomicAdd(&lsum[6], cnt);
     }
     __syncthreads();
-    if (d == 0) {
+    if (tx == 0) {
         gbase[0] = lcount[0] ? atomicAdd(&o.ctr[C_BND], lcount[0]) : 0u;
         gbase[K_SMALL] = lcount[K_SMALL] ? atomicAdd(&o.ctr[C_SMALL], lcount[K_SMALL]) : 0u;
         gbase[K_LARGE] = lcount[K_LARGE] ? atomicAdd(&o.ctr[C_LARGE], lcount[K_LARGE]) : 0u;
@@ -678,15 +706,16 @@ __global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart
     }
 }
 
-// Stable scatter of (key, payload) by the current byte into the other pair
+// Stable scatter of (key, payload) by the current digit into the other pair
 // of arrays (A -> B or B -> A, by the segment's flag).
-template <bool LOOP>
+template <bool LOOP, u32 W>
 __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tstart, const u32 *nsegp, u32 tile,
                                                 const u32 *hist, const u8 *scat, u64 *keyA, u32 *valA,
                                                 u64 *keyB, u32 *valB)
 {
-    __shared__ u32 run[256];
-    __shared__ u32 wcnt[NT / 64][256];
+    constexpr u32 NB = Digits<W>::NB;
+    __shared__ u32 run[NB];
+    __shared__ u32 wcnt[NT / 64][NB];
     const u32 nseg = *nsegp;
     const u32 ntiles = LOOP ? tstart[nseg] : 0u;
     TILE_LOOP(t, ntiles) {
@@ -704,8 +733,8 @@ __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tsta
     const u32 level = g.aux & 15;
     const u32 b0 = g.begin + lt * tile;
     const u32 b1 = min(g.end, b0 + tile);
-    const u32 base = hist[256u * ts];
-    run[threadIdx.x] = g.begin + hist[256u * ts + threadIdx.x * T + lt] - base;
+    const u32 base = hist[NB * ts];
+    for (u32 d = threadIdx.x; d < NB; d += NT) run[d] = g.begin + hist[NB * ts + d * T + lt] - base;
     const u32 wid = threadIdx.x >> 6;
     for (u32 c = b0; c < b1; c += NT) {
         const u32 i = c + threadIdx.x;
@@ -716,23 +745,25 @@ __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tsta
             k = ksrc[i];
             v = vsrc[i];
         }
-        const u32 d = digit_of(k, level);
+        const u32 d = digit_of<W>(k, level);
+        for (u32 e = threadIdx.x; e < NB; e += NT) {
 #pragma unroll
-        for (int w = 0; w < NT / 64; w++) wcnt[w][threadIdx.x] = 0;
+            for (int w = 0; w < NT / 64; w++) wcnt[w][e] = 0;
+        }
         __syncthreads();
-        const u64 peers = match_digit(d, valid);
+        const u64 peers = match_digit_w<W>(d, valid);
         const u32 rank = (u32)__popcll(peers & lanemask_lt());
         if (valid && rank == 0) wcnt[wid][d] = (u32)__popcll(peers);
         __syncthreads();
-        {
-            u32 acc = run[threadIdx.x];
+        for (u32 e = threadIdx.x; e < NB; e += NT) {
+            u32 acc = run[e];
 #pragma unroll
             for (int w = 0; w < NT / 64; w++) {
-                u32 x = wcnt[w][threadIdx.x];
-                wcnt[w][threadIdx.x] = acc;
+                u32 x = wcnt[w][e];
+                wcnt[w][e] = acc;
                 acc += x;
             }
-            run[threadIdx.x] = acc;
+            run[e] = acc;
         }
         __syncthreads();
         if (valid) {
@@ -750,7 +781,7 @@ __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tsta
 // the next round, equal strings) are copied to A when the level left them in
 // B.  Scattered segments read back their digits to find them; an unscattered
 // segment that became such a run is copied whole.
-template <bool LOOP>
+template <bool LOOP, u32 W>
 __global__ __launch_bounds__(NT) void k_settle(const Seg *segs, const u32 *tstart, const u32 *nsegp, u32 tile,
                                                const u8 *scat, const u8 *kinds, const u64 *keyB,
                                                const u32 *valB, u64 *keyA, u32 *valA)
@@ -765,12 +796,12 @@ __global__ __launch_bounds__(NT) void k_settle(const Seg *segs, const u32 *tstar
     const u32 lt = t - tstart[s];
     const u32 b0 = g.begin + lt * tile;
     const u32 b1 = min(g.end, b0 + tile);
-    const u8 *kd = kinds + 256u * s;
+    const u8 *kd = kinds + Digits<W>::NB * s;
     if (scat[s]) {
         if (inb) continue;  // scattered into A
         for (u32 i = b0 + threadIdx.x; i < b1; i += NT) {
             const u64 k = keyB[i];
-            const u32 c = kd[digit_of(k, level)];
+            const u32 c = kd[digit_of<W>(k, level)];
             if (c == K_NONE || c == K_NEXT || c == K_IDENT) {
                 keyA[i] = k;
                 valA[i] = valB[i];
@@ -1100,7 +1131,13 @@ void sort_ws_layout(u64 n, SortWs *w, WsArena *a, WsCounter *c)
     const u64 nseg = n / 2 + 2;
     const u64 nlarge = n / 128 + 2;
     const u64 ntiles = n / 1024 + nlarge + 2;
-    const u64 nscan = (256 * ntiles > nseg + 1 ? 256 * ntiles : nseg + 1) + 1;
+    // histograms and bucket kinds: 256 buckets per radix tile / segment with
+    // 8-bit digits; 2048 with 11-bit digits, which are used only with tiles
+    // of >= 4096 and radix segments of > 512 strings
+    const u64 nlarge11 = n / 512 + 2, ntiles11 = n / 4096 + nlarge11 + 2;
+    const u64 nhist = 256 * ntiles > 2048 * ntiles11 ? 256 * ntiles : 2048 * ntiles11;
+    const u64 nkinds = 256 * nlarge > 2048 * nlarge11 ? 256 * nlarge : 2048 * nlarge11;
+    const u64 nscan = (nhist > nseg + 1 ? nhist : nseg + 1) + 1;
 #define TAKE(field, T, cnt)                      \
     do {                                          \
         if (a) w->field = a->take<T>(cnt);        \
@@ -1124,7 +1161,7 @@ void sort_ws_layout(u64 n, SortWs *w, WsArena *a, WsCounter *c)
     TAKE(smin, u64, nlarge);
     TAKE(smax, u64, nlarge);
     TAKE(scat, u8, nlarge);
-    TAKE(kinds, u8, 256 * nlarge);
+    TAKE(kinds, u8, nkinds);
     TAKE(tstart, u32, nseg + 1);
     TAKE(spref, u32, nseg + 1);
     TAKE(hist, u32, nscan);
@@ -1155,7 +1192,10 @@ struct RoundCtx {
     SortWs &w;
     u64 n;  // strings of the whole sort (bounds every list)
     u32 SM, TL;
+    u32 W;  // radix digit bits (8, or 11 with tiles >= 4096 and a cutover >= 512)
 };
+
+static u32 digit_bits_for(u32 SM, u32 TL) { return (g_digit_bits == 11 && TL >= 4096 && SM >= 512) ? 11u : 8u; }
 
 static int scan_u32(RoundCtx &C, u32 *arr, const u32 *n_dev, Known k)
 {
@@ -1200,13 +1240,15 @@ static int round_head(RoundCtx &C, Known nact, Known atiles, u64 round_elems)
 
 // One radix level over the list LA (its length in ctr[C_LARGE] when the level
 // starts); its sub-lists go to LB and the round's lists.
-static int radix_level(RoundCtx &C, Seg *LA, Seg *LB, Known nlarge, Known ltiles, u64 lelem)
+template <u32 W>
+static int radix_level_w(RoundCtx &C, Seg *LA, Seg *LB, Known nlarge, Known ltiles, u64 lelem)
 {
+    constexpr u32 NB = Digits<W>::NB;
     SortWs &w = C.w;
     const SortJob &J = C.J;
     hipStream_t st = J.stream;
     const u64 n = C.n;
-    k_level_begin<<<1, 64, 0, st>>>(w.ctr, w.hdr);
+    k_level_begin<<<1, 64, 0, st>>>(w.ctr, w.hdr, NB);
     SS_CHECK_LAUNCH();
     const u32 *nlp = w.hdr + H_LARGE;
     k_level_tiles<<<grid_of(nlarge.yes ? nlarge.v : n / 128, 256, 1024), 256, 0, st>>>(LA, nlp, C.TL, w.tstart,
@@ -1216,29 +1258,36 @@ static int radix_level(RoundCtx &C, Seg *LA, Seg *LB, Known nlarge, Known ltiles
     const unsigned tg = grid_of(ltiles.yes ? ltiles.v : n, ltiles.yes ? 1 : C.TL, ltiles.yes ? 1u << 30 : 2048);
     {
         SS_PROF("k_hist", st, (double)lelem * 8.0);  // read the keys
-        if (ltiles.yes) k_hist<false><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.keyA, w.keyB, w.hist, w.smin, w.smax);
-        else k_hist<true><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.keyA, w.keyB, w.hist, w.smin, w.smax);
+        if (ltiles.yes) k_hist<false, W><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.keyA, w.keyB, w.hist, w.smin, w.smax);
+        else k_hist<true, W><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.keyA, w.keyB, w.hist, w.smin, w.smax);
     }
     SS_CHECK_LAUNCH();
-    if (ltiles.yes) SS_TRY(ss_scan_exclusive<u32>(w.hist, w.hist, (u64)ltiles.v * 256, (u32 *)w.scan_scratch, st));
+    if (ltiles.yes) SS_TRY(ss_scan_exclusive<u32>(w.hist, w.hist, (u64)ltiles.v * NB, (u32 *)w.scan_scratch, st));
     else SS_TRY(ss_scan_exclusive_dev<u32>(w.hist, w.hist, w.hdr + H_HIST, 1, w.dscan, st));
     EmitOut eo{w.tiny, w.small, LB, w.nxt, w.ident, w.bnd, w.ctr, w.scat, w.kinds, C.SM, C.TL};
-    if (nlarge.yes) k_emit<false><<<grid_of(nlarge.v, EPB, 1u << 30), 256, 0, st>>>(LA, w.tstart, nlp, w.hist, w.smin, w.smax, eo);
-    else k_emit<true><<<grid_of(n / 128, EPB, 4096), 256, 0, st>>>(LA, w.tstart, nlp, w.hist, w.smin, w.smax, eo);
+    constexpr u32 SPG = EPB / Digits<W>::DPT;
+    if (nlarge.yes) k_emit<false, W><<<grid_of(nlarge.v, SPG, 1u << 30), 256, 0, st>>>(LA, w.tstart, nlp, w.hist, w.smin, w.smax, eo);
+    else k_emit<true, W><<<grid_of(n / 128, SPG, 4096), 256, 0, st>>>(LA, w.tstart, nlp, w.hist, w.smin, w.smax, eo);
     SS_CHECK_LAUNCH();
     {
         SS_PROF("k_scatter", st, (double)lelem * 24.0);  // key+payload in and out
-        if (ltiles.yes) k_scatter<false><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.hist, w.scat, w.keyA, J.vals, w.keyB, w.valB);
-        else k_scatter<true><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.hist, w.scat, w.keyA, J.vals, w.keyB, w.valB);
+        if (ltiles.yes) k_scatter<false, W><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.hist, w.scat, w.keyA, J.vals, w.keyB, w.valB);
+        else k_scatter<true, W><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.hist, w.scat, w.keyA, J.vals, w.keyB, w.valB);
     }
     SS_CHECK_LAUNCH();
     {
         SS_PROF("k_settle", st, (double)lelem * 8.0);  // at most the scattered keys read back
-        if (ltiles.yes) k_settle<false><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.scat, w.kinds, w.keyB, w.valB, w.keyA, J.vals);
-        else k_settle<true><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.scat, w.kinds, w.keyB, w.valB, w.keyA, J.vals);
+        if (ltiles.yes) k_settle<false, W><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.scat, w.kinds, w.keyB, w.valB, w.keyA, J.vals);
+        else k_settle<true, W><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.scat, w.kinds, w.keyB, w.valB, w.keyA, J.vals);
     }
     SS_CHECK_LAUNCH();
     return SS_OK;
+}
+
+static int radix_level(RoundCtx &C, Seg *LA, Seg *LB, Known nlarge, Known ltiles, u64 lelem)
+{
+    return C.W == 11 ? radix_level_w<11>(C, LA, LB, nlarge, ltiles, lelem)
+                     : radix_level_w<8>(C, LA, LB, nlarge, ltiles, lelem);
 }
 
 // The part of a round after the radix levels: small sorts, boundary LCPs,
@@ -1299,8 +1348,9 @@ static int round_tail(RoundCtx &C, const u32 *h)
 // ctr[C_NEXT], ctr[C_NTILES], ctr[C_NELEM].
 int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
 {
-    RoundCtx C{J, w, 0, (u32)g_small_max, (u32)g_tile};
+    RoundCtx C{J, w, 0, (u32)g_small_max, (u32)g_tile, 8};
     C.n = J.n_total;
+    C.W = digit_bits_for(C.SM, C.TL);
     u32 h[C_NCTR];
     u64 round_elems = J.n_first;
     while (nact > 0) {
@@ -1327,12 +1377,11 @@ int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
     return SS_OK;
 }
 
-// Device-driven rounds: `rounds` rounds of RADIX_LEVELS levels each are
-// enqueued with fixed grids and nothing is read back (the launch sequence can
-// be captured in a graph); rounds and levels without work find empty lists.
-// hdr[H_REMAIN] receives the number of segments still unresolved afterwards
-// (0: the sort is complete).
-#define RADIX_LEVELS 8  // a radix level consumes one of the key's 8 bytes
+// Device-driven rounds: `rounds` rounds of as many levels as a key has digits
+// are enqueued with fixed grids and nothing is read back (the launch sequence
+// can be captured in a graph); rounds and levels without work find empty
+// lists.  hdr[H_REMAIN] receives the number of segments still unresolved
+// afterwards (0: the sort is complete).
 __global__ void k_remaining(const u32 *ctr, u32 *hdr, u32 *status)
 {
     hdr[H_REMAIN] = ctr[C_NEXT];
@@ -1350,12 +1399,14 @@ __global__ void k_copy_segs(const Seg *src, const u32 *cnt, Seg *dst)
 static int sort_rounds_device(const SortJob &J, SortWs &w, u32 rounds, u32 *status)
 {
     Seg *const act0 = w.act;
-    RoundCtx C{J, w, J.n_total, (u32)g_small_max, (u32)g_tile};
+    RoundCtx C{J, w, J.n_total, (u32)g_small_max, (u32)g_tile, 8};
+    C.W = digit_bits_for(C.SM, C.TL);
+    const u32 levels = C.W == 11 ? Digits<11>::LEVELS : Digits<8>::LEVELS;
     const Known unknown{false, 0};
     for (u32 r = 0; r < rounds; r++) {
         SS_TRY(round_head(C, unknown, unknown, 0));
         Seg *LA = w.largeA, *LB = w.largeB;
-        for (u32 l = 0; l < RADIX_LEVELS; l++) {
+        for (u32 l = 0; l < levels; l++) {
             SS_TRY(radix_level(C, LA, LB, unknown, unknown, 0));
             Seg *tmp = LA; LA = LB; LB = tmp;
         }

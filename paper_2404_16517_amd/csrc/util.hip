@@ -26,6 +26,7 @@ extern "C" int ss_version(void) { return 100; }
 
 int g_small_max = 1024;
 int g_tile = 4096;
+int g_digit_bits = 8;
 
 extern "C" int ss_set_tuning(int param, int value)
 {
@@ -45,6 +46,15 @@ extern "C" int ss_set_tuning(int param, int value)
         }
         int old = g_tile;
         g_tile = value;
+        return old;
+    }
+    if (param == SS_TUNE_DIGIT_BITS) {
+        if (value != 8 && value != 11) {
+            ss_set_error("SS_TUNE_DIGIT_BITS must be 8 or 11");
+            return SS_ERR_INVALID_ARG;
+        }
+        int old = g_digit_bits;
+        g_digit_bits = value;
         return old;
     }
     ss_set_error("unknown tuning parameter %d", param);

@@ -78,6 +78,10 @@ def test_tuning_validation():
         ss.set_tuning(ss.SS_TUNE_SMALL_MAX, 300)
     with pytest.raises(ss.StrsortError):
         ss.set_tuning(ss.SS_TUNE_TILE, 3000)
+    assert ss.set_tuning(ss.SS_TUNE_DIGIT_BITS, 11) == 8
+    assert ss.set_tuning(ss.SS_TUNE_DIGIT_BITS, 8) == 11
+    with pytest.raises(ss.StrsortError):
+        ss.set_tuning(ss.SS_TUNE_DIGIT_BITS, 16)
 
 
 def test_device_batch_sort_and_graph_arguments():

@@ -157,17 +157,70 @@ def test_sort_empty_input():
     assert perm.numel() == 0
 
 
-@pytest.mark.parametrize("tune", [(128, 1024), (256, 2048), (1024, 4096), (512, 16384)])
+@pytest.mark.parametrize("tune", [(128, 1024, 8), (256, 2048, 8), (1024, 4096, 8), (512, 16384, 8),
+                                  (1024, 4096, 11), (512, 8192, 11), (1024, 16384, 11), (256, 4096, 11)])
 def test_sort_tuning_variants_same_result(tune):
-    sm, tile = tune
+    sm, tile, bits = tune
     old_sm = ss.set_tuning(ss.SS_TUNE_SMALL_MAX, sm)
     old_t = ss.set_tuning(ss.SS_TUNE_TILE, tile)
+    old_b = ss.set_tuning(ss.SS_TUNE_DIGIT_BITS, bits)
     try:
         s = synth.text_strings(60_000, seed=4, median=12)
         _check_sort(s, f"tuning {tune}")
     finally:
         ss.set_tuning(ss.SS_TUNE_SMALL_MAX, old_sm)
         ss.set_tuning(ss.SS_TUNE_TILE, old_t)
+        ss.set_tuning(ss.SS_TUNE_DIGIT_BITS, old_b)
+
+
+@pytest.mark.parametrize("kind", ["dn_500", "text", "sets", "edge_deep", "zero_ff_runs"])
+@pytest.mark.parametrize("device_driven", [False, True])
+def test_sort_with_11_bit_digits(kind, device_driven):
+    """Six levels of 11 bits per key (the last ending with the length byte):
+    the same order and LCPs as the oracle, host- and device-driven."""
+    if kind == "dn_500":
+        s, bounds = synth.concat([synth.dn_strings(150_000, 500, 0.5, seed=s) for s in range(2)])
+    elif kind == "text":
+        s, bounds = synth.concat([synth.text_strings(120_000, seed=9, median=12), synth.text_strings(5_000, seed=8)])
+    elif kind == "sets":
+        s, bounds = synth.random_sets(40, 2_000, 60_000, 8, 64, seed=2)
+    elif kind == "edge_deep":
+        s, bounds = synth.concat([synth.from_list(EDGE_SETS["deep_shared"] * 4),
+                                  synth.from_list(EDGE_SETS["all_equal"] * 3)])
+    else:
+        rng = random.Random(5)
+        strs = [bytes(rng.choice(b"\x00\xff") for _ in range(rng.randint(0, 20))) for _ in range(30_000)]
+        s, bounds = synth.concat([synth.from_list(strs)])
+    old = [ss.set_tuning(ss.SS_TUNE_SMALL_MAX, 512), ss.set_tuning(ss.SS_TUNE_TILE, 4096),
+           ss.set_tuning(ss.SS_TUNE_DIGIT_BITS, 11)]
+    try:
+        g = s.to(DEV)
+        so = bounds.to(DEV)
+        if device_driven:
+            n = s.n
+            perm = torch.empty(n, dtype=torch.int32, device=DEV)
+            lcp = torch.empty(n, dtype=torch.int32, device=DEV)
+            status = torch.full((2,), -1, dtype=torch.int32, device=DEV)
+            ws = torch.empty(ss.lib().ss_sort_workspace(n), dtype=torch.uint8, device=DEV)
+            max_len = int((s.offsets[1:] - s.offsets[:-1]).max())
+            ss.sort_batch_device(g.bytes, g.offsets, so, perm, lcp, status, ws, ss.sort_batch_device_rounds(max_len))
+            torch.cuda.synchronize()
+            assert status.tolist() == [0, 0]
+        else:
+            perm, lcp = ss.sort_batch(g.bytes, g.offsets, so)
+            torch.cuda.synchronize()
+    finally:
+        ss.set_tuning(ss.SS_TUNE_SMALL_MAX, old[0])
+        ss.set_tuning(ss.SS_TUNE_TILE, old[1])
+        ss.set_tuning(ss.SS_TUNE_DIGIT_BITS, old[2])
+    b, o = oracle.strings_np(s)
+    bl = bounds.tolist()
+    for j in range(len(bl) - 1):
+        a, c = bl[j], bl[j + 1]
+        sb, sob = b[o[a]:o[c]], o[a:c + 1] - o[a]
+        p_ref = oracle.sort(sb, sob)
+        np.testing.assert_array_equal(u32(perm[a:c]), p_ref, err_msg=f"set {j}")
+        np.testing.assert_array_equal(u32(lcp[a:c]), oracle.lcp(sb, sob, p_ref), err_msg=f"set {j}")
 
 
 def test_sort_c0_closed_form_and_oracle():
