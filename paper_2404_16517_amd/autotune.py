@@ -50,21 +50,23 @@ def apply(workload: str = "dn", path: str | None = None) -> dict | None:
     return {"workload": workload, "small_max": e["small_max"], "tile": e["tile"], "digit_bits": e["digit_bits"]}
 
 
-def _samples(n, dev):
+def _samples(dev):
+    """Samples shaped like the benchmark's uses: per-PE sets of 10^6 D/N
+    strings (500 B, long shared prefixes) and of 10^6 text strings, and
+    independent sets of 10^3..10^6 strings."""
     import synth
     return {
-        # 16 PEs' worth of the D/N shape: long shared prefixes, 500 B strings
-        "dn": synth.concat([synth.dn_strings(n // 8, 500, 0.5, seed=s, device=dev) for s in range(8)]),
-        "text": synth.concat([synth.text_strings(n // 4, seed=s, device=dev) for s in range(4)]),
-        "sets": synth.random_sets(512, 1e3, 3e4, 8, 256, seed=1, device=dev),
+        "dn": synth.concat([synth.dn_strings(1_000_000, 500, 0.5, seed=s, device=dev) for s in range(4)]),
+        "text": synth.concat([synth.text_strings(1_000_000, seed=s, device=dev) for s in range(4)]),
+        "sets": synth.random_sets(96, 1e3, 1e6, 8, 256, seed=1, device=dev),
     }
 
 
-def autotune(n: int = 2_000_000, reps: int = 3, out: str | None = None) -> dict:
+def autotune(reps: int = 3, out: str | None = None) -> dict:
     import torch
     import paper_2404_16517_amd as ss
     dev = torch.device("cuda:0")
-    samples = _samples(n, dev)
+    samples = _samples(dev)
     old = (ss.set_tuning(ss.SS_TUNE_SMALL_MAX, 1024), ss.set_tuning(ss.SS_TUNE_TILE, 4096),
            ss.set_tuning(ss.SS_TUNE_DIGIT_BITS, 8))
     table = {"device": torch.cuda.get_device_name(0), "reps": reps, "workloads": {}}
@@ -106,8 +108,7 @@ def autotune(n: int = 2_000_000, reps: int = 3, out: str | None = None) -> dict:
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=DEFAULT_TABLE)
     a = ap.parse_args()
-    print(json.dumps(autotune(a.n, a.reps, a.out)))
+    print(json.dumps(autotune(a.reps, a.out)))

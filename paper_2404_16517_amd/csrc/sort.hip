@@ -707,7 +707,12 @@ __global__ __launch_bounds__(256) void k_emit(const Seg *segs, const u32 *tstart
 }
 
 // Stable scatter of (key, payload) by the current digit into the other pair
-// of arrays (A -> B or B -> A, by the segment's flag).
+// of arrays (A -> B or B -> A, by the segment's flag).  run[d] is the next
+// free position of digit d; in each chunk of NT elements the wavefronts take
+// turns (wave 0 first, so that equal digits keep the input order), and in a
+// wave the first lane of each digit reserves that digit's slots for all its
+// peers; the others take the base from it by a shuffle.  The work per chunk
+// does not grow with the number of buckets.
 template <bool LOOP, u32 W>
 __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tstart, const u32 *nsegp, u32 tile,
                                                 const u32 *hist, const u8 *scat, u64 *keyA, u32 *valA,
@@ -715,7 +720,6 @@ __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tsta
 {
     constexpr u32 NB = Digits<W>::NB;
     __shared__ u32 run[NB];
-    __shared__ u32 wcnt[NT / 64][NB];
     const u32 nseg = *nsegp;
     const u32 ntiles = LOOP ? tstart[nseg] : 0u;
     TILE_LOOP(t, ntiles) {
@@ -735,7 +739,8 @@ __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tsta
     const u32 b1 = min(g.end, b0 + tile);
     const u32 base = hist[NB * ts];
     for (u32 d = threadIdx.x; d < NB; d += NT) run[d] = g.begin + hist[NB * ts + d * T + lt] - base;
-    const u32 wid = threadIdx.x >> 6;
+    __syncthreads();
+    const u32 wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (u32 c = b0; c < b1; c += NT) {
         const u32 i = c + threadIdx.x;
         const bool valid = i < b1;
@@ -746,32 +751,23 @@ __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tsta
             v = vsrc[i];
         }
         const u32 d = digit_of<W>(k, level);
-        for (u32 e = threadIdx.x; e < NB; e += NT) {
-#pragma unroll
-            for (int w = 0; w < NT / 64; w++) wcnt[w][e] = 0;
-        }
-        __syncthreads();
         const u64 peers = match_digit_w<W>(d, valid);
         const u32 rank = (u32)__popcll(peers & lanemask_lt());
-        if (valid && rank == 0) wcnt[wid][d] = (u32)__popcll(peers);
-        __syncthreads();
-        for (u32 e = threadIdx.x; e < NB; e += NT) {
-            u32 acc = run[e];
+        u32 slot = 0;
 #pragma unroll
-            for (int w = 0; w < NT / 64; w++) {
-                u32 x = wcnt[w][e];
-                wcnt[w][e] = acc;
-                acc += x;
+        for (u32 w = 0; w < NT / 64; w++) {
+            if (wid == w && valid && rank == 0) {
+                slot = run[d];
+                run[d] = slot + (u32)__popcll(peers);
             }
-            run[e] = acc;
+            __syncthreads();
         }
-        __syncthreads();
+        const int leader = valid ? __ffsll((unsigned long long)peers) - 1 : (int)lane;
+        const u32 dst = __shfl(slot, leader, 64) + rank;
         if (valid) {
-            const u32 dst = wcnt[wid][d] + rank;
             kdst[dst] = k;
             vdst[dst] = v;
         }
-        __syncthreads();
     }
     __syncthreads();  // run is rewritten by the next tile
     }
