@@ -526,6 +526,34 @@ def committed_traffic(kernel, args):
     return per
 
 
+PASS_SOURCES = {"sort+lcp": ["paper_2404_16517_amd/csrc/sort.hip", "paper_2404_16517_amd/csrc/sort_core.hpp",
+                             "paper_2404_16517_amd/csrc/util.hip", "paper_2404_16517_amd/csrc/common.hpp"]}
+
+
+def committed_pass_traffic(name, args):
+    """Counter-measured HBM bytes of a whole pass (every dispatch of it) and
+    the pass's kernel-trace time, from its committed summary
+    (profiles/pass_sort_lcp_dn16M_traffic.txt), while its sources match."""
+    if any(getattr(args, k) != v for k, v in DEFAULT_WORKLOAD.items()) or name not in PASS_SOURCES:
+        return None
+    path = os.path.join(ROOT, "profiles", "pass_%s_dn16M_traffic.txt" % name.replace("+", "_"))
+    if not os.path.exists(path):
+        return None
+    digest = per = span = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("# sources sha256 "):
+                digest = line.split()[3]
+            elif line.startswith("pass_traffic_bytes "):
+                per = float(line.split()[1])
+            elif line.startswith("pass_span_ms "):
+                span = float(line.split()[1])
+    if digest is None or per is None or digest != sources_digest(PASS_SOURCES[name]):
+        return None
+    return {"bytes": per, "span_ms": span, "achieved_GBps": per / (span / 1e3) / 1e9 if span else None,
+            "frac": per / (span / 1e3) / 1e9 / HBM_PEAK_GBS if span else None}
+
+
 def pass_rooflines(stage_ms, n, D, D_approx, active_sum, literal):
     """Per-pass achieved bandwidth with each pass's algorithmic bytes: what the
     pass must move, independent of how the kernels do it --
@@ -715,6 +743,8 @@ def main():
             Dx = int(dpx1.to(torch.int64).sum())
             out["roofline"]["passes"] = pass_rooflines(stage_ms, s.n, D, Dx, doubling_active_sum(dpx1),
                                                        pipe.literal_bytes)
+            # what the counters saw the whole pass move (every dispatch), against its traced time
+            out["roofline"]["passes"]["sort+lcp"]["counter_traffic"] = committed_pass_traffic("sort+lcp", args)
             out["roofline"]["passes_note"] = ("one-stream steps, median stage time (events on the stream), "
                                               "algorithmic bytes per pass; D = %d, D_approx = %d" % (D, Dx))
             out["stages_ms_one_stream"] = stage_ms
