@@ -41,10 +41,14 @@ HBM_PEAK_GBS = 8000.0
 
 
 class Pipeline:
-    def __init__(self, B, O, p, v, ss, torch, overlap=True, first_alone=False):
+    def __init__(self, B, O, p, v, ss, torch, overlap=True, first_alone=False, seeded=True):
         self.B, self.O, self.p, self.v, self.ss, self.torch = B, O, p, v, ss, torch
         dev = B.device
         self.overlap = overlap
+        # seeded: prefix doubling's first pass reads every string's first 256
+        # bytes once for both passes (it leaves each PE's sort its first
+        # round's comparisons); the sort then runs beside the later rounds
+        self.seeded = seeded
         # first_alone: run prefix doubling's first pass (which reads the same
         # first bytes of every string as the sort's first round) alone, and
         # only its later rounds and duplicate detection beside the sort (on
@@ -64,6 +68,7 @@ class Pipeline:
         self.ws_pd = torch.empty(ss.lib().ss_dist_prefix_workspace(n), dtype=torch.uint8, device=dev)
         self.ws_merge = torch.empty(ss.lib().ss_lcp_merge_workspace(n, n, p * p), dtype=torch.uint8, device=dev)
         self.ws_pe = torch.empty(ss.lib().ss_partition_encode_workspace(n), dtype=torch.uint8, device=dev)
+        self.seed = torch.empty(ss.lib().ss_sort_seed_bytes(n), dtype=torch.uint8, device=dev)
         self.group_off = torch.arange(0, p * p + 1, p, dtype=torch.int32, device=dev)
 
     def step(self, marks):
@@ -74,6 +79,13 @@ class Pipeline:
         #    for its own read-backs do not hold up the sort's launches)
         if self.ms_mode:
             dpx, rounds = None, 0
+        elif self.seeded:
+            main = torch.cuda.current_stream()
+            ss.dist_prefix_first_seed(B, O, 8, 64, ws=self.ws_pd, seed=self.seed, set_off=self.set_off)
+            ev("dist_prefix first pass")
+            if self.overlap:
+                self.side.wait_stream(main)
+                fut = self.pool.submit(self._dist_prefix, marks)
         elif self.overlap:
             main = torch.cuda.current_stream()
             if self.first_alone:
@@ -85,8 +97,14 @@ class Pipeline:
             dpx, rounds = ss.dist_prefix(B, O, 8, 64, ws=self.ws_pd)
             ev("dist_prefix")
         # 2. every PE sorts its array (+ LCP), one batched launch sequence
-        perm, lcp = ss.sort_batch(B, O, self.set_off, ws=self.ws_sort, global_ids=True)
+        if self.seeded and not self.ms_mode:
+            perm, lcp = ss.sort_batch_seeded(B, O, self.set_off, self.seed, ws=self.ws_sort, global_ids=True)
+        else:
+            perm, lcp = ss.sort_batch(B, O, self.set_off, ws=self.ws_sort, global_ids=True)
         ev("sort_batch+lcp")
+        if self.seeded and not self.ms_mode and not self.overlap:
+            dpx, rounds = ss.dist_prefix_rounds(B, O, self.ws_pd, 8, 64)
+            ev("dist_prefix rounds")
         # 3. regular sampling (v+1 samples per PE) and splitters
         samp = ss.select_splitters_batch(perm, self.set_off, self.v + 2)
         sb, so = ss.gather_strings(B, O, samp)
@@ -122,7 +140,7 @@ class Pipeline:
     def _dist_prefix(self, marks):
         with self.torch.cuda.stream(self.side):
             marks.mark("side_start", side=True)
-            if self.first_alone:
+            if self.first_alone or self.seeded:
                 r = self.ss.dist_prefix_rounds(self.B, self.O, self.ws_pd, 8, 64)
             else:
                 r = self.ss.dist_prefix(self.B, self.O, 8, 64, ws=self.ws_pd)
@@ -554,7 +572,7 @@ def committed_pass_traffic(name, args):
             "frac": per / (span / 1e3) / 1e9 / HBM_PEAK_GBS if span else None}
 
 
-def pass_rooflines(stage_ms, n, D, D_approx, active_sum, literal):
+def pass_rooflines(stage_ms, n, D, D_approx, active_sum, literal, seeded=False, D_beyond=0):
     """Per-pass achieved bandwidth with each pass's algorithmic bytes: what the
     pass must move, independent of how the kernels do it --
       sort+LCP          D + 16n (each distinguishing prefix read once, offsets
@@ -564,11 +582,23 @@ def pass_rooflines(stage_ms, n, D, D_approx, active_sum, literal):
       partition_encode  32n + 2 sum(d - e) (metadata in and out, every
                         literal byte read and written once);
       lcp_merge         28n + sum(d - e) (front-coded metadata and literals
-                        in, order and LCP out)."""
+                        in, order and LCP out).
+    Seeded (the first hash pass reads every string's first 256 bytes for
+    both passes and writes the sort's 16-byte seed record): dist_prefix adds
+    16n and spans its first pass and its rounds; sort+LCP is D_beyond (the
+    distinguishing-prefix bytes past the first 256 of each string) + 24n
+    (seed records in, perm and LCP out)."""
     def entry(ms, by):
         gbs = by / (ms / 1e3) / 1e9 if ms and ms > 0 else None
         return {"ms": ms, "algorithmic_bytes": by, "achieved_GBps": gbs,
                 "frac": gbs / HBM_PEAK_GBS if gbs else None}
+    if seeded:
+        dp = [stage_ms.get("dist_prefix first pass"), stage_ms.get("dist_prefix rounds")]
+        dp_ms = sum(dp) if None not in dp else None
+        return {"sort+lcp": entry(stage_ms.get("sort_batch+lcp"), D_beyond + 24 * n),
+                "dist_prefix": entry(dp_ms, D_approx + 16 * active_sum + 28 * n),
+                "partition_encode": entry(stage_ms.get("partition_encode"), 32 * n + 2 * literal),
+                "lcp_merge": entry(stage_ms.get("lcp_merge"), 28 * n + literal)}
     return {"sort+lcp": entry(stage_ms.get("sort_batch+lcp"), D + 16 * n),
             "dist_prefix": entry(stage_ms.get("dist_prefix"), D_approx + 16 * active_sum + 12 * n),
             "partition_encode": entry(stage_ms.get("partition_encode"), 32 * n + 2 * literal),
@@ -621,6 +651,10 @@ def main():
     ap.add_argument("--serial", action="store_true",
                     help="run prefix doubling before the sort on one stream (by default it runs on a second "
                          "stream beside the sort, and per-kernel times include the other stream's kernels)")
+    ap.add_argument("--no-seed", action="store_true",
+                    help="the sort reads every string's first bytes itself, beside all of prefix doubling "
+                         "(by default prefix doubling's first pass reads them once for both and the sort "
+                         "runs beside the later rounds)")
     ap.add_argument("--first-pass-alone", action="store_true",
                     help="run prefix doubling's first pass before the sort, only its later rounds beside it")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-per-job leg")
@@ -659,7 +693,7 @@ def main():
     torch.cuda.synchronize()
     print(f"# generated n={s.n} N={s.N} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     pipe = Pipeline(s.bytes, s.offsets, args.pes, args.sampling, ss, torch, overlap=not args.serial,
-                    first_alone=args.first_pass_alone)
+                    first_alone=args.first_pass_alone, seeded=not args.no_seed)
 
     # (the warm-up steps also fill the library's pool of profiling events)
     ss.profile_enable(not args.no_profile)
@@ -703,6 +737,7 @@ def main():
                    "n": s.n, "N": s.N, "virtual_pes": args.pes, "sampling_factor": args.sampling,
                    "doubling_rounds": rounds, "streams": 1 if args.serial else 2,
                    "first_pass_alone": (not args.serial) and args.first_pass_alone,
+                   "seeded": not args.no_seed,
                    "tuning": tuned or "library defaults"},
         "strings_per_s": s.n / dt,
         "hbm_frac_of_N_per_step": s.N / dt / 1e9 / HBM_PEAK_GBS,
@@ -741,8 +776,9 @@ def main():
             _, _, dist1, dpx1, _ = res1
             D = int(dist1.to(torch.int64).sum())
             Dx = int(dpx1.to(torch.int64).sum())
+            Db = int((dist1.to(torch.int64) - 256).clamp_(min=0).sum())
             out["roofline"]["passes"] = pass_rooflines(stage_ms, s.n, D, Dx, doubling_active_sum(dpx1),
-                                                       pipe.literal_bytes)
+                                                       pipe.literal_bytes, seeded=pipe.seeded, D_beyond=Db)
             # what the counters saw the whole pass move (every dispatch), against its traced time
             out["roofline"]["passes"]["sort+lcp"]["counter_traffic"] = committed_pass_traffic("sort+lcp", args)
             out["roofline"]["passes_note"] = ("one-stream steps, median stage time (events on the stream), "

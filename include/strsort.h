@@ -73,6 +73,23 @@ size_t ss_sort_workspace(uint64_t n);
 int ss_sort(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
             uint32_t *perm, uint32_t *lcp, void *ws, size_t ws_bytes, void *stream);
 
+/* ss_sort with its first round's comparisons against the first string taken
+ * from sort_seed, written by ss_dist_prefix_first_seed on the same strings
+ * (on a stream ordered after that call).  Same results as ss_sort.  The sort
+ * overwrites the seed's records (they become its first round's).  A seed
+ * whose header says it was not written is ignored; a seed of other strings
+ * gives wrong results.  Errors as ss_sort, INVALID_ARG for a null
+ * sort_seed. */
+int ss_sort_seeded(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n, void *sort_seed,
+                   uint32_t *perm, uint32_t *lcp, void *ws, size_t ws_bytes, void *stream);
+/* ss_sort_batch with the first round taken from a seed that
+ * ss_dist_prefix_first_seed wrote for the same strings and the same set_off.
+ * Same results as ss_sort_batch; INVALID_ARG also for a null sort_seed or
+ * SS_BATCH_CONTINUE. */
+int ss_sort_batch_seeded(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                         const uint64_t *set_off, uint32_t num_sets, void *sort_seed, uint32_t *perm,
+                         uint32_t *lcp, uint32_t flags, void *ws, size_t ws_bytes, void *stream);
+
 /* Many independent sorts in one launch sequence (one sort per set, as each
  * processing element sorts its own array in Section 3).  set_off (device,
  * num_sets+1 entries, non-decreasing, set_off[0] = 0, set_off[num_sets] = n)
@@ -199,6 +216,37 @@ int ss_dist_prefix_first(const uint8_t *bytes, uint64_t N, const uint64_t *offse
 int ss_dist_prefix_rounds(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
                           uint32_t init_len, uint32_t hash_bits, uint32_t *dist_approx,
                           uint32_t *rounds_host, void *ws, size_t ws_bytes, void *stream);
+
+/* One read of every string's first bytes for both passes of Section 3's
+ * initialization (each processing element's local sort) and Section 4's
+ * prefix doubling.  The deep first pass (the one that reads 256 bytes) also
+ * compares each string with the first string of its set over those bytes and
+ * leaves, in sort_seed, what the sort's first round needs: the string's first
+ * mismatch with that string (their LCP) and its 8 bytes there, or, for a
+ * string that agrees with it over all 256 bytes, the position to go on from.
+ * ss_sort_seeded / ss_sort_batch_seeded then sort without reading those
+ * bytes again.
+ *   set_off   (device, num_sets+1, nullable) the sets of the batch sort that
+ *              will use the seed (as ss_sort_batch's); NULL: one set, for
+ *              ss_sort_seeded.  The pass keeps every set's first string in
+ *              LDS: with more than 16 sets it writes no seed (the seeded sort
+ *              then compares everything itself).  The strings of a 32-string
+ *              tile that crosses a set bound are left for the sort too.
+ *   sort_seed (device, out, ss_sort_seed_bytes(n) bytes, caller-owned): a
+ *              256-byte header (word 0 = 1 when the seed was written, 0 when
+ *              the plain first pass ran and wrote none), then n 8-byte words
+ *              and n 8-byte records.  Its contents are an implementation
+ *              detail; pass it only to a seeded sort of the same strings and
+ *              sets.
+ *   first_pass_mode 0 = as ss_dist_prefix_first (a sample decides between the
+ *              plain and the deep pass), 1 = plain, 2 = deep.
+ * Otherwise exactly ss_dist_prefix_first: ss_dist_prefix_rounds continues
+ * from the workspace.  Errors as ss_dist_prefix_first; INVALID_ARG for a null
+ * sort_seed, a mode above 2, or set_off with num_sets = 0. */
+size_t ss_sort_seed_bytes(uint64_t n);
+int ss_dist_prefix_first_seed(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                              const uint64_t *set_off, uint32_t num_sets, uint32_t init_len, uint32_t hash_bits,
+                              uint32_t first_pass_mode, void *sort_seed, void *ws, size_t ws_bytes, void *stream);
 
 /* The keys of the first `rounds` prefix-doubling rounds of every string, as
  * ss_dist_prefix's rounds compute them (Section 4: round t hashes the

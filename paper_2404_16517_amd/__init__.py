@@ -45,6 +45,10 @@ def lib():
             "ss_version": ([], I32),
             "ss_sort_workspace": ([U64], SZ),
             "ss_sort": ([P, U64, P, U64, P, P, P, SZ, P], I32),
+            "ss_sort_seeded": ([P, U64, P, U64, P, P, P, P, SZ, P], I32),
+            "ss_sort_seed_bytes": ([U64], SZ),
+            "ss_dist_prefix_first_seed": ([P, U64, P, U64, P, U32, U32, U32, U32, P, P, SZ, P], I32),
+            "ss_sort_batch_seeded": ([P, U64, P, U64, P, U32, P, P, P, U32, P, SZ, P], I32),
             "ss_sort_batch": ([P, U64, P, U64, P, U32, P, P, U32, P, SZ, P], I32),
             "ss_sort_batch_device_rounds": ([U32], U32),
             "ss_sort_batch_device": ([P, U64, P, U64, P, U32, P, P, U32, U32, P, P, SZ, P], I32),
@@ -302,6 +306,65 @@ def dist_prefix_first(bytes_, offsets, init_len: int = 8, hash_bits: int = 64, w
     _check(lib().ss_dist_prefix_first(_p(b), b.numel(), _p(o), n, init_len, hash_bits, _p(ws), ws.numel(),
                                       _stream(b.device)))
     return ws
+
+
+def dist_prefix_first_seed(bytes_, offsets, init_len: int = 8, hash_bits: int = 64, first_pass: str = "auto",
+                           ws=None, seed=None, set_off: torch.Tensor | None = None):
+    """dist_prefix_first that also leaves the sort's first-round seed (for
+    the sets of set_off, or one set).  Returns (ws, seed); pass ws to
+    dist_prefix_rounds and seed to sort_seeded / sort_batch_seeded."""
+    b, o, n = _dev_strings(bytes_, offsets)
+    nsets = 0
+    if set_off is not None:
+        set_off = set_off.to(device=b.device, dtype=torch.int64).contiguous()
+        nsets = set_off.numel() - 1
+    need = lib().ss_dist_prefix_workspace(n)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, b.device)
+    sneed = lib().ss_sort_seed_bytes(n)
+    if seed is None or seed.numel() < sneed:
+        seed = _ws(sneed, b.device)
+    _check(lib().ss_dist_prefix_first_seed(_p(b), b.numel(), _p(o), n, _p(set_off), nsets, init_len, hash_bits,
+                                           FIRST_PASS_MODES[first_pass], _p(seed), _p(ws), ws.numel(),
+                                           _stream(b.device)))
+    return ws, seed
+
+
+def sort_batch_seeded(bytes_, offsets, set_off: torch.Tensor, seed, with_lcp: bool = True, ws=None,
+                      global_ids: bool = False):
+    """sort_batch() whose first round uses the seed of dist_prefix_first_seed
+    on the same strings and set_off (the seed is overwritten)."""
+    b, o, n = _dev_strings(bytes_, offsets)
+    dev = b.device
+    if seed.numel() < lib().ss_sort_seed_bytes(n):
+        raise StrsortError("seed too small")
+    set_off = set_off.to(device=dev, dtype=torch.int64).contiguous()
+    perm = _u32(n, dev)
+    lcp = _u32(n, dev) if with_lcp else None
+    need = lib().ss_sort_workspace(n)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, dev)
+    flags = SS_BATCH_GLOBAL_IDS if global_ids else 0
+    _check(lib().ss_sort_batch_seeded(_p(b), b.numel(), _p(o), n, _p(set_off), set_off.numel() - 1, _p(seed),
+                                      _p(perm), _p(lcp), flags, _p(ws), ws.numel(), _stream(dev)))
+    return perm, lcp
+
+
+def sort_seeded(bytes_, offsets, seed, with_lcp: bool = True, ws: torch.Tensor | None = None):
+    """sort() whose first round uses the seed of dist_prefix_first_seed on the
+    same strings (the seed is overwritten)."""
+    b, o, n = _dev_strings(bytes_, offsets)
+    dev = b.device
+    if seed.numel() < lib().ss_sort_seed_bytes(n):
+        raise StrsortError("seed too small")
+    perm = _u32(n, dev)
+    lcp = _u32(n, dev) if with_lcp else None
+    need = lib().ss_sort_workspace(n)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, dev)
+    _check(lib().ss_sort_seeded(_p(b), b.numel(), _p(o), n, _p(seed), _p(perm), _p(lcp), _p(ws), ws.numel(),
+                                _stream(dev)))
+    return perm, lcp
 
 
 def dist_prefix_rounds(bytes_, offsets, ws, init_len: int = 8, hash_bits: int = 64):

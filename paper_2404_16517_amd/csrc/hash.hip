@@ -511,7 +511,18 @@ struct FirstArgs {
     PreLens P;  // rounds up to 64 bytes
     BPow bp;
     FirstW fw;
+    // Sort seed (deep pass; null: none): per string, its first mismatch with
+    // the first string of its set and its 8 bytes there (see
+    // ss_dist_prefix_first_seed).  set_off null: one set.
+    u64 *seed_word;
+    uint2 *seed_pos;
+    const u64 *set_off;
+    u32 nsets;
 };
+
+#define SEED_MAX_SETS 16  // sets whose first strings the pass keeps in LDS (more: no seed)
+
+#define SEED_OPEN 0xFFFFFFFFu  // seed_pos[i].y of a string not resolved inside the pass
 
 #define WT_ROUND (RW_STEPS * 2 * 2 * 9)  // round weights: [step of the chunk][32-byte block][16-byte half][digit]
 #define WT_FIRST (HF_ACC * 2 * 2 * 64)   // first-pass weights: [accumulator][32-byte block][low/high product][lane]
@@ -621,9 +632,32 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
         for (u32 e = threadIdx.x; e < WT_ROUND; e += blockDim.x) wtab[e] = wtab_entry(e, rw);
     }
     u32 c0 = 0;  // precomputed rounds up to 64 bytes (first pass)
+    // Sort seed: the set bounds and, per set, the first 4 * PRE_MAX bytes
+    // (zero past its end) and the length of its reference string -- the
+    // set's first string -- all in LDS.  (The strings of a tile across sets,
+    // at most 32 per set boundary, are left for the sort to compare from the
+    // start.)
+    __shared__ u64 s_set[FIRST ? SEED_MAX_SETS + 1 : 1];
+    __shared__ u64 s_ref[FIRST ? SEED_MAX_SETS : 1][FIRST ? PRE_MAX / 2 : 1];
+    __shared__ u32 s_refl[FIRST ? SEED_MAX_SETS : 1];
+    const bool seeding = FIRST && Fp->seed_pos != nullptr;  // uniform
+    const u32 nsets = (FIRST && seeding && Fp->set_off) ? Fp->nsets : 1u;  // (<= SEED_MAX_SETS)
     if (FIRST) {
         const FirstArgs &F = *Fp;
         c0 = F.P.count;
+        if (seeding) {
+            for (u32 e = threadIdx.x; e <= nsets; e += blockDim.x)
+                s_set[e] = F.set_off ? F.set_off[e] : (e ? (u64)A.n : 0ull);
+            for (u32 e = threadIdx.x; e < nsets * (PRE_MAX / 2); e += blockDim.x) {
+                const u32 sx = e / (PRE_MAX / 2), k = 8 * (e % (PRE_MAX / 2));
+                u64 f = F.set_off ? F.set_off[sx] : 0ull;
+                f = f < A.n ? f : A.n - 1;  // (bounds that are not well placed stay inside the arrays)
+                const u64 fo = A.off[f], fl64 = A.off[f + 1] - fo;
+                const u32 fl = fl64 < 0xFFFFFFFFull ? (u32)fl64 : 0xFFFFFFFFu;
+                s_ref[sx][k / 8] = k < fl ? load_le(A.bytes, A.N, fo + k, (fl - k) < 8 ? fl - k : 8u) : 0ull;
+                if (k == 0) s_refl[sx] = fl;
+            }
+        }
         // kernel-argument arrays are read with constant indices only
         if (threadIdx.x < PRE_SLOTS) {
             u64 v = 0;
@@ -772,6 +806,22 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
         u64 ibc = rw.ibc0;
         v16i S = {};
         u32 xp = x0;
+        u32 smis = 0xFFFFFFFFu;  // sort seed: first byte of this lane's pieces unlike the reference's
+        u32 runi = 1;            // the tile's strings share one set (uniform)
+        u32 rsel = 0;            // ... which one (uniform)
+        // the set of the tile's strings
+        auto seed_ref = [&](u32 t) {
+            const u32 jc = t * 32 + col < Acnt ? t * 32 + col : Acnt - 1;
+            u32 slo = 0, shi = nsets;  // the last set starting at or before jc
+            while (shi - slo > 1) {
+                const u32 mid = (slo + shi) >> 1;
+                if (s_set[mid] <= jc) slo = mid;
+                else shi = mid;
+            }
+            runi = __builtin_amdgcn_readfirstlane((u32)(__shfl(slo, 0, 64) == __shfl(slo, 31, 64)));
+            rsel = __builtin_amdgcn_readfirstlane(slo);
+        };
+        if (FIRST && seeding) seed_ref(tile);
         issue_copy(o_c, m, xp);
         for (;;) {  // passes; uniform over the wavefront
             // this pass's operand bytes: [u][kb], 16 each (zero past the string)
@@ -798,6 +848,23 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                             } else if (take < 16) {
                                 hi[u][kb] &= take == 8 ? 0ull : ((1ull << (8 * (take - 8))) - 1ull);
                             }
+                        }
+                    }
+            }
+            if (FIRST && seeding) {
+                // this lane's pieces against the reference's bytes at the same
+                // positions (both zero past their ends; a difference at or
+                // past the shorter end is discarded at the tile's end)
+#pragma unroll
+                for (int u = 0; u < RP_STEPS; u++)
+#pragma unroll
+                    for (int kb = 0; kb < 2; kb++) {
+                        const u32 pos = xp + 64 * u + 32 * kb + 16 * h;
+                        if (runi && pos < 4 * PRE_MAX) {
+                            const u64 d0 = lo[u][kb] ^ s_ref[rsel][pos / 8], d1 = hi[u][kb] ^ s_ref[rsel][pos / 8 + 1];
+                            const u32 mp = d0 ? pos + (u32)(__builtin_ctzll(d0) >> 3)
+                                              : (d1 ? pos + 8 + (u32)(__builtin_ctzll(d1) >> 3) : 0xFFFFFFFFu);
+                            smis = mp < smis ? mp : smis;
                         }
                     }
             }
@@ -889,6 +956,26 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                 xp += 64 * RP_STEPS;
                 continue;
             }
+            // sort seed: the string's first mismatch with its reference over
+            // both lane halves; the load of its 8 bytes there is issued here
+            // and stored after the keys below
+            u64 mw = 0;
+            uint2 sp = make_uint2(0u, SEED_OPEN);
+            if (FIRST && seeding) {
+                const u32 y = __shfl_xor(smis, 32, 64);
+                smis = y < smis ? y : smis;
+                const u32 rfl = s_refl[rsel];
+                const u32 E = len < rfl ? len : rfl;  // compared up to the shorter end
+                const u32 r = smis < E ? smis : E;
+                // equal over [0, lend): the sort goes on from lend (across sets: from 0)
+                sp = make_uint2(runi ? lend : 0u, SEED_OPEN);
+                if (valid && !h && runi && (r < lend || E <= lend)) {
+                    const u32 tk = len - r < 8 ? len - r : 8u;
+                    mw = tk ? load_be(bytes, N, o_c + r, tk) : 0ull;
+                    sp = make_uint2(r, tk);
+                }
+                smis = 0xFFFFFFFFu;
+            }
             // the tile's keys of the round machinery
             if (valid && (!h || two)) {
                 const u32 j = tile * 32 + col;
@@ -904,6 +991,11 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                     keys0[j] = key;
                 }
                 note(HF_ACC, key, len <= lmine);
+            }
+            if (FIRST && seeding && valid && !h) {
+                const u32 j = tile * 32 + col;
+                Fp->seed_word[j] = mw;
+                Fp->seed_pos[j] = sp;
             }
             if (!more) break;
             // advance: the next tile becomes current (its first pass is in flight)
@@ -925,6 +1017,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                 if (LP) G_n = A.state[i_n];
             }
             i_nn = entry(tile + 2 * nwaves < ntiles ? tile + 2 * nwaves : tile);
+            if (FIRST && seeding) seed_ref(tile);
         }
     }
     if constexpr (FIRST) {
@@ -1173,9 +1266,19 @@ enum { FP_PROBE = 0, FP_PLAIN = 1, FP_DEEP = 2 };
 // probe decides between the plain and the deep form (FP_PROBE; the probe's
 // count is read back), or the caller does.  P receives the precomputed
 // lengths (count 0: init_len > PRE_MAX, nothing launched).
+// Sort seed layout: a 256-byte header (word 0: 1 when the pass wrote the
+// seed, 0 when it did not), then the 8 bytes of every string at its mismatch
+// (u64, n), then its mismatch position and byte count there (uint2, n).
+#define SEED_HDR 256
+
 static int first_pass(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n, uint32_t init_len,
-                      uint32_t hash_bits, PdWs &w, int mode, PreLens &P, hipStream_t st)
+                      uint32_t hash_bits, PdWs &w, int mode, PreLens &P, hipStream_t st, void *seed = nullptr,
+                      const u64 *set_off = nullptr, u32 nsets = 1)
 {
+    if (seed) {  // not written unless the deep pass runs
+        k_store_u32<<<1, 1, 0, st>>>((u32 *)seed, 0u);
+        SS_CHECK_LAUNCH();
+    }
     P = PreLens{};
     for (u64 L = init_len; L <= PRE_MAX && P.count < PRE_SLOTS; L *= 2) P.l[P.count++] = L;
     if (!P.count) return SS_OK;
@@ -1221,6 +1324,15 @@ static int first_pass(const uint8_t *bytes, uint64_t N, const uint64_t *offsets,
     Fa.P = P;
     Fa.bp = bp;
     Fa.fw = first_weights();
+    // (the pass keeps every set's first string in LDS: with more sets it
+    // writes no seed, and the sort compares everything itself)
+    if (seed && set_off && nsets > SEED_MAX_SETS) seed = nullptr;
+    if (seed && deep) {
+        Fa.seed_word = (u64 *)((u8 *)seed + SEED_HDR);
+        Fa.seed_pos = (uint2 *)((u8 *)seed + SEED_HDR + 8 * n);
+        Fa.set_off = set_off;
+        Fa.nsets = set_off ? nsets : 1u;
+    }
     if (!deep) {
         // algorithmic bytes: each string's prefix read once, its offsets, one
         // key written per precomputed round
@@ -1236,9 +1348,14 @@ static int first_pass(const uint8_t *bytes, uint64_t N, const uint64_t *offsets,
         // more, shorter workgroups than the plain pass: beside the other
         // stream's kernels they give compute units back sooner
         const unsigned dblocks = (unsigned)(ceil_div(tiles, 4) < 8192 ? ceil_div(tiles, 4) : 8192);
-        SS_PROF("k_hash_first_deep", st, (double)n * (4.0 * PRE_MAX) + (double)n * (8.0 + 8.0 * (c0 + 2)));
+        SS_PROF("k_hash_first_deep", st,
+                (double)n * (4.0 * PRE_MAX) + (double)n * (8.0 + 8.0 * (c0 + 2) + (seed ? 16.0 : 0.0)));
         k_hash_first_deep<<<dblocks, 256, 0, st>>>(A, rwd, Fa);
         SS_CHECK_LAUNCH();
+        if (seed) {
+            k_store_u32<<<1, 1, 0, st>>>((u32 *)seed, 1u);
+            SS_CHECK_LAUNCH();
+        }
         P.l[c0] = 2 * PRE_MAX;
         P.l[c0 + 1] = 4 * PRE_MAX;
         P.count = c0 + 2;
@@ -1255,7 +1372,8 @@ enum { PD_FIRST = 1, PD_ROUNDS = 2 };
 // runs the remaining rounds and the duplicate detection from there.
 static int pd_run(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n, uint32_t init_len,
                   uint32_t hash_bits, uint32_t *dist_approx, uint32_t *rounds_host, void *ws, size_t ws_bytes,
-                  void *stream, int parts)
+                  void *stream, int parts, void *seed = nullptr, int fp_mode = FP_PROBE,
+                  const u64 *set_off = nullptr, u32 nsets = 1)
 {
     ss_clear_error();
     if (n >= 0xFFFFFFFFull) { ss_set_error("n too large"); return SS_ERR_TOO_LARGE; }
@@ -1288,7 +1406,7 @@ static int pd_run(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uin
     if (parts & PD_FIRST) {
         k_store_u32<<<1, 1, 0, st>>>(ctr, (u32)n);
         SS_CHECK_LAUNCH();
-        SS_TRY(first_pass(bytes, N, offsets, n, init_len, hash_bits, w, FP_PROBE, P, st));
+        SS_TRY(first_pass(bytes, N, offsets, n, init_len, hash_bits, w, fp_mode, P, st, seed, set_off, nsets));
         k_store_u64<<<1, 1, 0, st>>>(w.hdr + HDR_PRECOUNT, P.count);
         SS_CHECK_LAUNCH();
         if (!(parts & PD_ROUNDS)) return SS_OK;
@@ -1489,6 +1607,23 @@ extern "C" int ss_dist_prefix_first(const uint8_t *bytes, uint64_t N, const uint
                                     uint32_t init_len, uint32_t hash_bits, void *ws, size_t ws_bytes, void *stream)
 {
     return pd_run(bytes, N, offsets, n, init_len, hash_bits, nullptr, nullptr, ws, ws_bytes, stream, PD_FIRST);
+}
+
+extern "C" size_t ss_sort_seed_bytes(uint64_t n) { return SEED_HDR + 16 * (size_t)n; }
+
+extern "C" int ss_dist_prefix_first_seed(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                                         const uint64_t *set_off, uint32_t num_sets, uint32_t init_len,
+                                         uint32_t hash_bits, uint32_t first_pass_mode, void *sort_seed, void *ws,
+                                         size_t ws_bytes, void *stream)
+{
+    if (!sort_seed || first_pass_mode > FP_DEEP || (set_off && num_sets == 0)) {
+        ss_clear_error();
+        ss_set_error(!sort_seed ? "null sort_seed"
+                                : (first_pass_mode > FP_DEEP ? "first_pass_mode must be 0, 1 or 2" : "num_sets is 0"));
+        return SS_ERR_INVALID_ARG;
+    }
+    return pd_run(bytes, N, offsets, n, init_len, hash_bits, nullptr, nullptr, ws, ws_bytes, stream, PD_FIRST,
+                  sort_seed, (int)first_pass_mode, set_off, num_sets);
 }
 
 extern "C" int ss_dist_prefix_rounds(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,

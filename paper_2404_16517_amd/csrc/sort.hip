@@ -271,10 +271,18 @@ __device__ __forceinline__ u32 skip_cmp(const u8 *bytes, u64 N, const u8 *R, con
 // position, its remaining length there (capped at 8) and its 8 bytes there
 // (mword, mpr), from which k_keys builds its key without reading the string
 // again.
-template <bool LOOP>
+//
+// SEED (the first round of a seeded sort, one segment from depth 0 in input
+// order): when *seed_ok, mword and mpr arrive holding every member's record
+// as far as an earlier pass over the first bytes found it; a member whose
+// mpr.y is SEED_OPEN agreed with the first string up to mpr.x and is compared
+// from there, every other one is done without reading its string.
+#define SEED_OPEN 0xFFFFFFFFu
+template <bool LOOP, bool SEED = false>
 __global__ __launch_bounds__(NT, 6) void k_skip(const Seg *segs, const u32 *tstart, const u32 *nsegp,
                                              const u8 *bytes, u64 N, const u64 *off,
-                                             const u32 *perm, u32 *skipv, u64 *mword, uint2 *mpr)
+                                             const u32 *perm, u32 *skipv, u64 *mword, uint2 *mpr,
+                                             const u32 *seed_ok = nullptr)
 {
     __shared__ u64 fsw[SKFS];
     __shared__ __attribute__((aligned(16))) u8 rows[(NT / 64) * SKR];
@@ -282,6 +290,7 @@ __global__ __launch_bounds__(NT, 6) void k_skip(const Seg *segs, const u32 *tsta
     __shared__ u32 wwn[NT / 64][SKB];  // ... and its chunk count
     const u32 nseg = *nsegp;
     const u32 ntiles = LOOP ? tstart[nseg] : 0u;
+    const bool sok = SEED && *seed_ok != 0;  // uniform
     TILE_LOOP(t, ntiles) {  // (uniform over the workgroup)
     const u32 sg = seg_of_tile(tstart, nseg, t);
     const Seg g = segs[sg];
@@ -309,15 +318,26 @@ __global__ __launch_bounds__(NT, 6) void k_skip(const Seg *segs, const u32 *tsta
         const u32 i = i0 + sl;
         const bool valid = i < b1;
         u64 o = 0;
-        u32 len = 0, m = 0;
-        if (valid) {
+        u32 len = 0, m = 0, x = depth;
+        bool seeded = false;  // done by the seed
+        u32 sres = 0;
+        if (SEED && sok && valid) {
+            const uint2 sp = mpr[i];
+            if (sp.y != SEED_OPEN) {
+                seeded = true;
+                sres = sp.x;
+            } else {
+                x = sp.x;
+            }
+        }
+        if (valid && !seeded) {
             const u32 p = perm[i];
             o = off[p];
             len = (u32)(off[p + 1] - o);
             m = len < fl ? len : fl;
         }
-        u32 res = m, x = depth;
-        bool act = valid && depth < m;
+        u32 res = seeded ? sres : m;
+        bool act = valid && !seeded && x < m;
         while (__ballot(act)) {  // uniform over the wavefront
             const u32 CH = longw ? SKC_LONG : SKC_SHORT;
             const u64 A0 = (babs + o + x) & ~15ull;
@@ -368,7 +388,7 @@ __global__ __launch_bounds__(NT, 6) void k_skip(const Seg *segs, const u32 *tsta
         if (valid && q == 0) {
             const u32 c = res > depth ? res - depth : 0u;
             best = c < best ? c : best;
-            if (m <= depth) {  // nothing to compare: the member ends at or before depth
+            if (!seeded && m <= depth) {  // nothing to compare: the member ends at or before depth
                 const u32 rem = len - res;
                 const u32 tk = rem < 8 ? rem : 8u;
                 mword[i] = load_be(bytes, N, o + res, tk);
@@ -1200,7 +1220,7 @@ static int scan_u32(RoundCtx &C, u32 *arr, const u32 *n_dev, Known k)
 }
 
 // The part of a round before the radix levels: skip, keys, routing.
-static int round_head(RoundCtx &C, Known nact, Known atiles, u64 round_elems)
+static int round_head(RoundCtx &C, Known nact, Known atiles, u64 round_elems, bool first = false)
 {
     SortWs &w = C.w;
     const SortJob &J = C.J;
@@ -1217,15 +1237,22 @@ static int round_head(RoundCtx &C, Known nact, Known atiles, u64 round_elems)
     {
         // algorithmic bytes: perm + offsets + one word per string, its mismatch
         // record out, plus the common prefix (added once the skips are known)
-        SS_PROF("k_skip", st, (double)round_elems * 44.0);
-        if (atiles.yes) k_skip<false><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr);
+        // (seeded: the records in, the strings of members the seed left open)
+        const bool sd = first && atiles.yes && J.seed_pos;
+        SS_PROF("k_skip", st, (double)round_elems * (sd ? 8.0 : 44.0));
+        if (sd) k_skip<false, true><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, J.seed_word, J.seed_pos, J.seed_ok);
+        else if (atiles.yes) k_skip<false><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr);
         else k_skip<true><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr);
     }
     SS_CHECK_LAUNCH();
     {
+        // the first round of a seeded sort keeps its records in the seed
+        const bool sd = first && atiles.yes && J.seed_pos;
+        u64 *mw = sd ? J.seed_word : w.mword;
+        uint2 *mp = sd ? J.seed_pos : w.mpr;
         SS_PROF("k_keys", st, (double)round_elems * 24.0);  // mismatch record in, key out
-        if (atiles.yes) k_keys<false><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr, w.keyA);
-        else k_keys<true><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr, w.keyA);
+        if (atiles.yes) k_keys<false><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, mw, mp, w.keyA);
+        else k_keys<true><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, mw, mp, w.keyA);
     }
     SS_CHECK_LAUNCH();
     k_classify<<<grid_of(nact.yes ? nact.v : n / 2, 256, 1024), 256, 0, st>>>(w.act, nactp, w.skipv, C.SM, C.TL,
@@ -1349,10 +1376,13 @@ int sort_rounds(const SortJob &J, SortWs &w, u32 nact, u32 atiles)
     C.W = digit_bits_for(C.SM, C.TL);
     u32 h[C_NCTR];
     u64 round_elems = J.n_first;
+    bool first = true;
     while (nact > 0) {
-        SS_TRY(round_head(C, Known{true, nact}, Known{true, atiles}, round_elems));
+        SS_TRY(round_head(C, Known{true, nact}, Known{true, atiles}, round_elems, first));
         SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, J.stream));
-        ss_prof_add_bytes("k_skip", (double)(h[10] | ((u64)h[11] << 32)));
+        // (a seeded first round's common prefix was read by the pass that made the seed)
+        if (!(first && J.seed_pos)) ss_prof_add_bytes("k_skip", (double)(h[10] | ((u64)h[11] << 32)));
+        first = false;
         u32 nlarge = h[C_LARGE], ltiles = h[C_LTILES], lelem = h[C_LELEM];
         Seg *LA = w.largeA, *LB = w.largeB;
         while (nlarge > 0) {
@@ -1556,10 +1586,18 @@ __global__ __launch_bounds__(RANK_NT) void k_rank_sort(const u8 *bytes, u64 N, c
     }
 }
 
-extern "C" int ss_sort(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+// The first-round seed's arrays (layout: 256-byte header whose word 0 says
+// whether the seed was written, the mismatch words (n), the records (n)).
+static void attach_seed(SortJob &J, void *seed, u64 n)
+{
+    J.seed_ok = (const u32 *)seed;
+    J.seed_word = (u64 *)((u8 *)seed + 256);
+    J.seed_pos = (uint2 *)((u8 *)seed + 256 + 8 * n);
+}
+
+static int sort_single(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n, void *seed,
                        uint32_t *perm, uint32_t *lcp, void *ws, size_t ws_bytes, void *stream)
 {
-    ss_clear_error();
     SS_TRY(sort_common_checks(bytes, offsets, n, perm));
     if (n == 0) return SS_OK;
     hipStream_t st = (hipStream_t)stream;
@@ -1576,11 +1614,31 @@ extern "C" int ss_sort(const uint8_t *bytes, uint64_t N, const uint64_t *offsets
         return SS_OK;
     }
     SortJob J{bytes, N, offsets, perm, lcp ? lcp : w.lcp_scratch, st, n, n};
+    if (seed) attach_seed(J, seed, n);
     k_iota<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(perm, (u32)n);
     SS_CHECK_LAUNCH();
     k_init_single<<<1, 1, 0, st>>>(w.act, (u32)n, J.lcp, w.ctr);
     SS_CHECK_LAUNCH();
     return sort_rounds(J, w, 1, (u32)ceil_div(n, ETILE));
+}
+
+extern "C" int ss_sort(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                       uint32_t *perm, uint32_t *lcp, void *ws, size_t ws_bytes, void *stream)
+{
+    ss_clear_error();
+    return sort_single(bytes, N, offsets, n, nullptr, perm, lcp, ws, ws_bytes, stream);
+}
+
+extern "C" int ss_sort_seeded(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                              void *sort_seed, uint32_t *perm, uint32_t *lcp, void *ws, size_t ws_bytes,
+                              void *stream)
+{
+    ss_clear_error();
+    if (!sort_seed) {
+        ss_set_error("null sort_seed");
+        return SS_ERR_INVALID_ARG;
+    }
+    return sort_single(bytes, N, offsets, n, sort_seed, perm, lcp, ws, ws_bytes, stream);
 }
 
 // The checks and first-round set-up shared by both batch forms.
@@ -1615,16 +1673,16 @@ static int batch_setup(const uint8_t *bytes, uint64_t N, const uint64_t *offsets
     return SS_OK;
 }
 
-extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
-                             const uint64_t *set_off, uint32_t num_sets, uint32_t *perm_local,
-                             uint32_t *lcp, uint32_t flags, void *ws, size_t ws_bytes, void *stream)
+static int sort_batch_impl(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                           const uint64_t *set_off, uint32_t num_sets, void *seed, uint32_t *perm_local,
+                           uint32_t *lcp, uint32_t flags, void *ws, size_t ws_bytes, void *stream)
 {
-    ss_clear_error();
     hipStream_t st = (hipStream_t)stream;
     SortWs w;
     SortJob J{};
     SS_TRY(batch_setup(bytes, N, offsets, n, set_off, num_sets, perm_local, lcp, flags, ws, ws_bytes, st, w, J));
     if (n == 0) return SS_OK;
+    if (seed) attach_seed(J, seed, n);
     u32 h[C_NCTR];
     SS_TRY(ss_read_u32(w.ctr, h, C_NCTR, st));
     if (h[C_BADSET]) {
@@ -1638,6 +1696,29 @@ extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *o
         SS_CHECK_LAUNCH();
     }
     return SS_OK;
+}
+
+extern "C" int ss_sort_batch(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                             const uint64_t *set_off, uint32_t num_sets, uint32_t *perm_local,
+                             uint32_t *lcp, uint32_t flags, void *ws, size_t ws_bytes, void *stream)
+{
+    ss_clear_error();
+    return sort_batch_impl(bytes, N, offsets, n, set_off, num_sets, nullptr, perm_local, lcp, flags, ws, ws_bytes,
+                           stream);
+}
+
+extern "C" int ss_sort_batch_seeded(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
+                                    const uint64_t *set_off, uint32_t num_sets, void *sort_seed,
+                                    uint32_t *perm_local, uint32_t *lcp, uint32_t flags, void *ws,
+                                    size_t ws_bytes, void *stream)
+{
+    ss_clear_error();
+    if (!sort_seed || (flags & SS_BATCH_CONTINUE)) {
+        ss_set_error(!sort_seed ? "null sort_seed" : "a seeded sort cannot continue a device-driven one");
+        return SS_ERR_INVALID_ARG;
+    }
+    return sort_batch_impl(bytes, N, offsets, n, set_off, num_sets, sort_seed, perm_local, lcp, flags, ws,
+                           ws_bytes, stream);
 }
 
 extern "C" uint32_t ss_sort_batch_device_rounds(uint32_t max_len)

@@ -38,6 +38,11 @@ struct SortJob {
     hipStream_t stream;
     u64 n_first;  // strings in the first round's segments (for byte accounting)
     u64 n_total;  // strings of the whole sort (bounds every list)
+    // First-round seed (null: none): the mismatch records of the first
+    // round's one segment, used in place of the workspace's when *seed_ok.
+    u64 *seed_word;
+    uint2 *seed_pos;
+    const u32 *seed_ok;
 };
 
 void sort_ws_layout(u64 n, SortWs *w, WsArena *a, WsCounter *c);

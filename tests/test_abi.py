@@ -69,6 +69,15 @@ def test_argument_errors_without_device():
     # more groups than runs
     assert L.ss_lcp_merge(2, P(8), P(8), 3, P(8), 1, P(8), P(8), P(8), P(8), P(8), P(8), P(8), P(8), None, 1,
                           None, None, 0, None) == -1
+    # the shared first read: a seed is required, the mode is 0..2; the seed's size is 256 + 16 n
+    assert L.ss_dist_prefix_first_seed(P(8), 0, P(8), 10, None, 0, 8, 64, 0, None, P(8), 1 << 20, None) == -1
+    assert L.ss_dist_prefix_first_seed(P(8), 0, P(8), 10, None, 0, 8, 64, 3, P(8), P(8), 1 << 20, None) == -1
+    assert L.ss_dist_prefix_first_seed(P(8), 0, P(8), 10, P(8), 0, 8, 64, 0, P(8), P(8), 1 << 20, None) == -1
+    assert L.ss_sort_seeded(P(8), 0, P(8), 10, None, P(8), None, P(8), 1 << 20, None) == -1
+    assert L.ss_sort_batch_seeded(P(8), 0, P(8), 10, P(8), 1, None, P(8), None, 0, P(8), 1 << 20, None) == -1
+    assert L.ss_sort_batch_seeded(P(8), 0, P(8), 10, P(8), 1, P(8), P(8), None, 2, P(8), 1 << 20, None) == -1
+    assert L.ss_sort_seeded(P(8), 0, P(8), 1 << 33, P(8), P(8), None, P(8), 1 << 20, None) == -3
+    assert L.ss_sort_seed_bytes(1000) == 256 + 16 * 1000
 
 
 def test_tuning_validation():
