@@ -640,6 +640,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
     __shared__ u64 s_set[FIRST ? SEED_MAX_SETS + 1 : 1];
     __shared__ u64 s_ref[FIRST ? SEED_MAX_SETS : 1][FIRST ? PRE_MAX / 2 : 1];
     __shared__ u32 s_refl[FIRST ? SEED_MAX_SETS : 1];
+    __shared__ u64 s_mw[FIRST ? 4 : 1][32];  // per wavefront and string: the 8 bytes at its record
     const bool seeding = FIRST && Fp->seed_pos != nullptr;  // uniform
     const u32 nsets = (FIRST && seeding && Fp->set_off) ? Fp->nsets : 1u;  // (<= SEED_MAX_SETS)
     if (FIRST) {
@@ -807,6 +808,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
         v16i S = {};
         u32 xp = x0;
         u32 smis = 0xFFFFFFFFu;  // sort seed: first byte of this lane's pieces unlike the reference's
+        bool mwgot = false;      // ... the string's 8 bytes at its record are in s_mw
         u32 runi = 1;            // the tile's strings share one set (uniform)
         u32 rsel = 0;            // ... which one (uniform)
         // the set of the tile's strings
@@ -850,23 +852,46 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                             }
                         }
                     }
-            }
-            if (FIRST && seeding) {
-                // this lane's pieces against the reference's bytes at the same
-                // positions (both zero past their ends; a difference at or
-                // past the shorter end is discarded at the tile's end)
+                if (FIRST && seeding && runi) {
+                    // this lane's pieces against the reference's bytes at the same
+                    // positions (both zero past their ends; a difference at or
+                    // past the shorter end is discarded below)
 #pragma unroll
-                for (int u = 0; u < RP_STEPS; u++)
+                    for (int u = 0; u < RP_STEPS; u++)
 #pragma unroll
-                    for (int kb = 0; kb < 2; kb++) {
-                        const u32 pos = xp + 64 * u + 32 * kb + 16 * h;
-                        if (runi && pos < 4 * PRE_MAX) {
-                            const u64 d0 = lo[u][kb] ^ s_ref[rsel][pos / 8], d1 = hi[u][kb] ^ s_ref[rsel][pos / 8 + 1];
-                            const u32 mp = d0 ? pos + (u32)(__builtin_ctzll(d0) >> 3)
-                                              : (d1 ? pos + 8 + (u32)(__builtin_ctzll(d1) >> 3) : 0xFFFFFFFFu);
-                            smis = mp < smis ? mp : smis;
+                        for (int kb = 0; kb < 2; kb++) {
+                            const u32 pos = xp + 64 * u + 32 * kb + 16 * h;
+                            if (pos < 4 * PRE_MAX) {
+                                const u64 d0 = lo[u][kb] ^ s_ref[rsel][pos / 8];
+                                const u64 d1 = hi[u][kb] ^ s_ref[rsel][pos / 8 + 1];
+                                const u32 mp = d0 ? pos + (u32)(__builtin_ctzll(d0) >> 3)
+                                                  : (d1 ? pos + 8 + (u32)(__builtin_ctzll(d1) >> 3) : 0xFFFFFFFFu);
+                                smis = mp < smis ? mp : smis;
+                            }
+                        }
+                    // The string's record position so far (its first mismatch,
+                    // or the shorter end).  Passes go up in position, so once it
+                    // lies in this pass it is final: its 8 bytes are taken from
+                    // this pass's rows while they are still there (from global
+                    // memory at the tile's end when they reach past the copy).
+                    const u32 y = __shfl_xor(smis, 32, 64);
+                    const u32 sm = y < smis ? y : smis;
+                    const u32 rfl = s_refl[rsel];
+                    const u32 E = len < rfl ? len : rfl;
+                    const u32 rc = sm < E ? sm : E;
+                    if (!h && rc >= xp && rc < xp + 64 * RP_STEPS) {
+                        const u32 tk = len - rc < 8 ? len - rc : 8u;
+                        if (tk == 0) {
+                            s_mw[wv][col] = 0;
+                            mwgot = true;
+                        } else if (!edge && nch && rc + tk <= xp + 16 * nch - sh) {
+                            u64 w0, w1;
+                            lds_le16(R, RP_CH * 16 * col + sh + (rc - xp), w0, w1);
+                            s_mw[wv][col] = __builtin_bswap64(tk < 8 ? (w0 & ((1ull << (8 * tk)) - 1ull)) : w0);
+                            mwgot = true;
                         }
                     }
+                }
             }
             __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the rows are read before the next copy
             // the next pass: the rest of this tile, or the next tile's first
@@ -971,10 +996,11 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                 sp = make_uint2(runi ? lend : 0u, SEED_OPEN);
                 if (valid && !h && runi && (r < lend || E <= lend)) {
                     const u32 tk = len - r < 8 ? len - r : 8u;
-                    mw = tk ? load_be(bytes, N, o_c + r, tk) : 0ull;
+                    mw = mwgot ? s_mw[wv][col] : (tk ? load_be(bytes, N, o_c + r, tk) : 0ull);
                     sp = make_uint2(r, tk);
                 }
                 smis = 0xFFFFFFFFu;
+                mwgot = false;
             }
             // the tile's keys of the round machinery
             if (valid && (!h || two)) {
