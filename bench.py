@@ -64,6 +64,7 @@ class Pipeline:
         self.n = n
         self.bounds = [n * i // p for i in range(p + 1)]
         self.set_off = torch.tensor(self.bounds, dtype=torch.int64, device=dev)
+        self.max_len = max(int((O[1:] - O[:-1]).max()), 1) if n else 1
         self.ws_sort = torch.empty(ss.lib().ss_sort_workspace(n), dtype=torch.uint8, device=dev)
         self.ws_pd = torch.empty(ss.lib().ss_dist_prefix_workspace(n), dtype=torch.uint8, device=dev)
         self.ws_merge = torch.empty(ss.lib().ss_lcp_merge_workspace(n, n, p * p), dtype=torch.uint8, device=dev)
@@ -105,12 +106,14 @@ class Pipeline:
         if self.seeded and not self.ms_mode and not self.overlap:
             dpx, rounds = ss.dist_prefix_rounds(B, O, self.ws_pd, 8, 64)
             ev("dist_prefix rounds")
-        # 3. regular sampling (v+1 samples per PE) and splitters
-        samp = ss.select_splitters_batch(perm, self.set_off, self.v + 2)
-        sb, so = ss.gather_strings(B, O, samp)
+        # 3. regular sampling (v+1 samples per PE) and splitters (the sets are
+        #    well formed by construction and the sample strings' longest
+        #    length is known: nothing is read back)
+        samp = ss.select_splitters_batch(perm, self.set_off, self.v + 2, check=False)
+        sb, so = ss.gather_strings(B, O, samp, cap_hint=samp.numel() * self.max_len, sync=False)
         sperm, _ = ss.sort(sb, so, with_lcp=False)
         fid = ss.select_splitters(sperm, p)
-        fb, fo = ss.gather_strings(sb, so, fid)
+        fb, fo = ss.gather_strings(sb, so, fid, cap_hint=fid.numel() * self.max_len, sync=False)
         ev("splitters")
         if self.overlap and not self.ms_mode:
             dpx, rounds = fut.result()
@@ -651,6 +654,8 @@ def main():
     ap.add_argument("--serial", action="store_true",
                     help="run prefix doubling before the sort on one stream (by default it runs on a second "
                          "stream beside the sort, and per-kernel times include the other stream's kernels)")
+    ap.add_argument("--dedup", choices=["table", "buckets"], default="table",
+                    help="prefix doubling's duplicate detection (library tuning SS_TUNE_DEDUP)")
     ap.add_argument("--no-seed", action="store_true",
                     help="the sort reads every string's first bytes itself, beside all of prefix doubling "
                          "(by default prefix doubling's first pass reads them once for both and the sort "
@@ -678,6 +683,7 @@ def main():
 
     from paper_2404_16517_amd import autotune
     tuned = autotune.apply("dn")
+    ss.set_tuning(ss.SS_TUNE_DEDUP, {"table": 0, "buckets": 1}[args.dedup])
     dev = torch.device("cuda:0")
     if args.calibrate_copy > 0:
         nbytes = int(args.calibrate_copy * 1e9) // 16 * 16
@@ -738,6 +744,7 @@ def main():
                    "doubling_rounds": rounds, "streams": 1 if args.serial else 2,
                    "first_pass_alone": (not args.serial) and args.first_pass_alone,
                    "seeded": not args.no_seed,
+                   "dedup": args.dedup,
                    "tuning": tuned or "library defaults"},
         "strings_per_s": s.n / dt,
         "hbm_frac_of_N_per_step": s.N / dt / 1e9 / HBM_PEAK_GBS,

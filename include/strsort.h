@@ -282,7 +282,10 @@ size_t ss_select_splitters_batch_workspace(void);
  * j = 1..r-1.  perm (in, n), set_off (in, num_sets+1), splitter_ids (out,
  * num_sets*(r-1)).  INVALID_ARG if a set is empty or set_off is not increasing
  * from 0 to n (checked on the device, so the call synchronises the stream;
- * the samples of a bad set are 0xFFFFFFFF). */
+ * the samples of a bad set are 0xFFFFFFFF).  ws = NULL with ws_bytes = 0:
+ * no check and nothing read back (for a caller whose sets are well formed by
+ * construction; a bad set's samples are still 0xFFFFFFFF, which
+ * ss_gather_strings takes as empty strings). */
 int ss_select_splitters_batch(const uint32_t *perm, uint64_t n, const uint64_t *set_off, uint32_t num_sets,
                               uint32_t r, uint32_t *splitter_ids, void *ws, size_t ws_bytes, void *stream);
 
@@ -312,9 +315,12 @@ size_t ss_gather_workspace(uint64_t m);
 
 /* Copy strings ids[0..m) of a string array into a new string array
  * (out_offsets: m+1 entries, out_offsets[0] = 0; out_bytes capacity out_cap).
- * Used to materialise splitter strings.  *total_host (host, may be NULL)
- * receives the byte total (the call reads it back).  CAPACITY if out_cap is
- * too small: out_offsets and *total_host are then valid, no bytes are copied. */
+ * Used to materialise splitter strings.  An id >= n is an empty string.
+ * *total_host (host) receives the byte total (the call reads it back);
+ * CAPACITY if out_cap is too small: out_offsets and *total_host are then
+ * valid, no bytes are copied.  total_host = NULL: nothing is read back; the
+ * byte total is out_offsets[m] on the device, and a string that would end
+ * past out_cap is not copied (out_offsets[m] > out_cap tells the caller). */
 int ss_gather_strings(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n,
                       const uint32_t *ids, uint64_t m, uint64_t *out_offsets, uint8_t *out_bytes,
                       uint64_t out_cap, uint64_t *total_host, void *ws, size_t ws_bytes, void *stream);
@@ -521,11 +527,19 @@ size_t ss_profile_names(char *buf, size_t cap);
  *                      buckets) or 11 (six levels per 64-bit key, 2048
  *                      buckets); 11 takes effect only with a tile >= 4096 and
  *                      SMALL_MAX >= 512, else 8 is used (default 8).
+ *   SS_TUNE_DEDUP      prefix doubling's duplicate detection: 0 = a global
+ *                      hash table (default); 1 = buckets of keys counted in
+ *                      LDS for lists of 2^16..2^26 keys, the table otherwise;
+ *                      2 = buckets for every list up to 2^26 keys.
+ *   SS_TUNE_DEDUP_LOG_BUCKETS  log2 of the number of buckets (1..14; 0 = by
+ *                      the list length, about 2048 keys a bucket; default 0).
  * Results never depend on the tuning.  Returns the previous value, or
  * SS_ERR_INVALID_ARG. */
 #define SS_TUNE_SMALL_MAX 1
 #define SS_TUNE_TILE 2
 #define SS_TUNE_DIGIT_BITS 3
+#define SS_TUNE_DEDUP 4
+#define SS_TUNE_DEDUP_LOG_BUCKETS 5
 int ss_set_tuning(int param, int value);
 
 #ifdef __cplusplus

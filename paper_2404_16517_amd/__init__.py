@@ -22,6 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libstrsort.so")
 SS_TUNE_SMALL_MAX = 1
 SS_TUNE_TILE = 2
 SS_TUNE_DIGIT_BITS = 3
+SS_TUNE_DEDUP = 4
+SS_TUNE_DEDUP_LOG_BUCKETS = 5
 SS_ERR_CAPACITY = -5
 
 
@@ -405,15 +407,16 @@ def select_splitters(perm: torch.Tensor, r: int):
     return ids
 
 
-def select_splitters_batch(perm: torch.Tensor, set_off: torch.Tensor, r: int):
-    """Regular samples of every set of a batch; (num_sets * (r-1),) uint32."""
+def select_splitters_batch(perm: torch.Tensor, set_off: torch.Tensor, r: int, check: bool = True):
+    """Regular samples of every set of a batch; (num_sets * (r-1),) uint32.
+    check=False: set_off is not validated and nothing is read back."""
     n = perm.numel()
     so = set_off.to(device=perm.device, dtype=torch.int64).contiguous()
     k = max(so.numel() - 1, 0)
     ids = _u32(max(k * (r - 1), 0), perm.device)
-    ws = _ws(lib().ss_select_splitters_batch_workspace(), perm.device)
+    ws = _ws(lib().ss_select_splitters_batch_workspace(), perm.device) if check else None
     _check(lib().ss_select_splitters_batch(_p(perm.contiguous()), n, _p(so), k, r, _p(ids),
-                                           _p(ws), ws.numel(), _stream(perm.device)))
+                                           _p(ws), ws.numel() if check else 0, _stream(perm.device)))
     return ids
 
 
@@ -433,10 +436,12 @@ def select_splitters_chars_batch(perm: torch.Tensor, offsets: torch.Tensor, set_
     return ids
 
 
-def gather_strings(bytes_, offsets, ids: torch.Tensor, cap_hint: int | None = None):
+def gather_strings(bytes_, offsets, ids: torch.Tensor, cap_hint: int | None = None, sync: bool = True):
     """Strings ids[0..m) as a new string array (bytes, offsets).  The byte
     buffer starts at ``cap_hint`` bytes (default 1 KiB per string) and is
-    regrown once to the exact total if that is too small."""
+    regrown once to the exact total if that is too small.  sync=False:
+    nothing is read back; the whole buffer of cap_hint bytes is returned and
+    strings that would not fit are left out (offsets[m] > cap_hint says so)."""
     b, o, n = _dev_strings(bytes_, offsets)
     dev = b.device
     m = ids.numel()
@@ -444,6 +449,11 @@ def gather_strings(bytes_, offsets, ids: torch.Tensor, cap_hint: int | None = No
     ws = _ws(lib().ss_gather_workspace(m), dev)
     idc = ids.contiguous()
     cap = int(cap_hint) if cap_hint is not None else 1024 * m
+    if not sync:
+        out = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
+        _check(lib().ss_gather_strings(_p(b), b.numel(), _p(o), n, _p(idc), m, _p(out_off), _p(out), cap, None,
+                                       _p(ws), ws.numel(), _stream(dev)))
+        return out, out_off
     total = ctypes.c_uint64(0)
     for _ in range(2):
         out = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)

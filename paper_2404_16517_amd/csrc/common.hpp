@@ -97,6 +97,8 @@ void ss_prof_drop_last(const char *name);
 extern int g_small_max;
 extern int g_tile;
 extern int g_digit_bits;  // radix digit width (8 or 11 bits)
+extern int g_dedup_mode;  // duplicate detection: 0 global table, 1 buckets for long lists, 2 buckets
+extern int g_dedup_logb;  // log2 of the bucket count (0: by the list length)
 
 // ------------------------------------------------------ device-wide scans
 

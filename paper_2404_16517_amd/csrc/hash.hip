@@ -1148,13 +1148,154 @@ __global__ __launch_bounds__(256) void k_tab_insert(const u64 *keys, int kin, co
     }
 }
 
+// ---- duplicate detection by buckets (App. B finds multiplicities by sorting
+// (hash, index) pairs; here the pairs are only partitioned, by the top bits of
+// a mixed key, into buckets small enough to count in LDS).  Three launches and
+// one scan: each workgroup counts its contiguous chunk of the list per bucket
+// (a bucket-major matrix of counts, so that one scan gives every workgroup's
+// range in every bucket), writes its (key, list position) pairs there, and one
+// workgroup per bucket counts the keys in an LDS table and writes a duplicate
+// flag per list position.  The global table remains for very long lists.
+#define DD_NT 256
+#define DD_MAXLOG 14                 // at most 2^14 buckets (a workgroup's counts in LDS)
+#define DD_HM_CAP (1u << 22)         // counts matrix: buckets x workgroups
+#define DD_TSLOTS 8192               // LDS table slots of a bucket pass (64 KB)
+#define DD_CAP (DD_TSLOTS / 2 - DD_NT)  // new keys a pass takes before it starts over with more passes
+#define DD_MIN_ACT (1u << 16)        // shorter lists use the global table (it fits in L2)
+#define DD_MAX_ACT (1u << 26)        // ... and so do longer ones
+
+__device__ __forceinline__ u32 dd_bucket(u64 key, u32 logB)
+{
+    return logB ? (u32)((key * 0x9E3779B97F4A7C15ull) >> (64 - logB)) : 0u;
+}
+__device__ __forceinline__ u32 dd_sub(u64 key) { return (u32)((key * 0xC2B2AE3D27D4EB4Full) >> 40); }
+__device__ __forceinline__ u32 dd_slot(u64 key) { return (u32)((key * 0x165667B19E3779F9ull) >> 51); }  // 13 bits
+
+// Counts of this workgroup's chunk [w C, (w+1) C) of the list per bucket, into
+// hm[b G + w] (every entry of the column written).
+__global__ __launch_bounds__(DD_NT) void k_dd_count(const u64 *keys, int kin, const u32 *act, const u32 *cnt,
+                                                    u32 logB, u32 C, u32 G, u32 *hm)
+{
+    __shared__ u32 h[1u << DD_MAXLOG];
+    const u32 NB = 1u << logB;
+    for (u32 b = threadIdx.x; b < NB; b += DD_NT) h[b] = 0;
+    __syncthreads();
+    const u32 A = *cnt;
+    const u32 j0 = blockIdx.x * C, j1 = min(A, j0 + C);
+    for (u32 j = j0 + threadIdx.x; j < j1; j += DD_NT) {
+        const u32 i = act ? act[j] : j;
+        atomicAdd(&h[dd_bucket(key_of(keys, kin, i, j), logB)], 1u);
+    }
+    __syncthreads();
+    for (u32 b = threadIdx.x; b < NB; b += DD_NT) hm[(u64)b * G + blockIdx.x] = h[b];
+}
+
+// The same chunk's pairs into their buckets: hm now holds the exclusive scan
+// of the counts (bucket-major), i.e. where this workgroup's pairs of each
+// bucket start.
+__global__ __launch_bounds__(DD_NT) void k_dd_scatter(const u64 *keys, int kin, const u32 *act, const u32 *cnt,
+                                                      u32 logB, u32 C, u32 G, const u32 *hm, u64 *pk, u32 *pj)
+{
+    __shared__ u32 h[1u << DD_MAXLOG];
+    const u32 NB = 1u << logB;
+    for (u32 b = threadIdx.x; b < NB; b += DD_NT) h[b] = hm[(u64)b * G + blockIdx.x];
+    __syncthreads();
+    const u32 A = *cnt;
+    const u32 j0 = blockIdx.x * C, j1 = min(A, j0 + C);
+    for (u32 j = j0 + threadIdx.x; j < j1; j += DD_NT) {
+        const u32 i = act ? act[j] : j;
+        const u64 key = key_of(keys, kin, i, j);
+        const u32 slot = atomicAdd(&h[dd_bucket(key, logB)], 1u);
+        pk[slot] = key;
+        pj[slot] = j;
+    }
+}
+
+// One workgroup per bucket [hm[b G], hm[(b+1) G]): the keys go into an LDS
+// table (a repeated key sets the duplicate mark), then each pair reads its
+// key's mark into dupf[j].  A bucket with more distinct keys than a pass
+// takes is done again in Q = 2, 4, ... passes, pass q taking the keys whose
+// second hash is q mod Q (so a pass holds about 1/Q of them; copies of one
+// key always share a pass).
+__global__ __launch_bounds__(DD_NT) void k_dd_bucket(const u32 *hm, u32 G, u32 NB, const u64 *pk, const u32 *pj,
+                                                     u8 *dupf, u32 *err)
+{
+    __shared__ u64 tab[DD_TSLOTS];
+    __shared__ u32 s_new, s_over;
+    for (u32 b = blockIdx.x; b < NB; b += gridDim.x) {
+        const u32 e0 = hm[(u64)b * G], e1 = hm[(u64)(b + 1) * G];
+        if (e0 >= e1) continue;  // (uniform)
+        for (u32 Q = 1;; Q *= 2) {
+            if (Q > (1u << 24)) {  // (keys of one class share a 24-bit second hash: never in practice)
+                if (threadIdx.x == 0) atomicOr(err, 1u);
+                break;
+            }
+            bool over = false;
+            for (u32 q = 0; q < Q; q++) {
+                for (u32 t = threadIdx.x; t < DD_TSLOTS; t += DD_NT) tab[t] = TAB_EMPTY;
+                if (threadIdx.x == 0) {
+                    s_new = 0;
+                    s_over = 0;
+                }
+                __syncthreads();
+                for (u32 e = e0 + threadIdx.x; e < e1; e += DD_NT) {
+                    const u64 key = pk[e];
+                    if (Q > 1 && dd_sub(key) % Q != q) continue;
+                    u32 sl = dd_slot(key);
+                    for (;;) {  // (at most DD_CAP + DD_NT keys: the table never fills)
+                        u64 cur = tab[sl];
+                        if (cur == TAB_EMPTY) {
+                            if (__hip_atomic_load(&s_over, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+                            cur = atomicCAS((unsigned long long *)&tab[sl], TAB_EMPTY, key);
+                            if (cur == TAB_EMPTY) {
+                                if (atomicAdd(&s_new, 1u) >= DD_CAP) atomicOr(&s_over, 1u);
+                                break;
+                            }
+                        }
+                        if ((cur & ~TAB_DUP) == key) {
+                            if (!(cur & TAB_DUP)) atomicOr((unsigned long long *)&tab[sl], TAB_DUP);
+                            break;
+                        }
+                        sl = (sl + 1) & (DD_TSLOTS - 1);
+                    }
+                }
+                __syncthreads();
+                if (s_over) {  // (uniform) too many keys for one pass: more passes
+                    over = true;
+                    __syncthreads();
+                    break;
+                }
+                for (u32 e = e0 + threadIdx.x; e < e1; e += DD_NT) {
+                    const u64 key = pk[e];
+                    if (Q > 1 && dd_sub(key) % Q != q) continue;
+                    u32 sl = dd_slot(key);
+                    u8 d = 0;
+                    for (;;) {
+                        const u64 v = tab[sl];
+                        if ((v & ~TAB_DUP) == key) {
+                            d = (v & TAB_DUP) ? 1 : 0;
+                            break;
+                        }
+                        if (v == TAB_EMPTY) break;  // (cannot happen: every key of the pass was inserted)
+                        sl = (sl + 1) & (DD_TSLOTS - 1);
+                    }
+                    dupf[pj[e]] = d;
+                }
+                __syncthreads();
+            }
+            if (!over) break;
+        }
+    }
+}
+
 // Finish the active strings whose key is unique (or whose length is <= l):
 // dist = min(len, l).  The others are appended to the next active list
 // (one atomic per workgroup; lists keep input order within a workgroup),
 // with their key for the next round when a two-round pass computed it.
 __global__ __launch_bounds__(256) void k_dedup(const u64 *keys, int kin, const u32 *act, const u32 *cnt,
                                                const u64 *off, u64 l, int mode, const u64 *tab, u32 logT,
-                                               u32 *dist, u32 *next, u32 *ncnt, const u64 *carry, u64 *carry_out)
+                                               u32 *dist, u32 *next, u32 *ncnt, const u64 *carry, u64 *carry_out,
+                                               const u8 *dupf)
 {
     __shared__ u32 wcount[4], base;
     const u32 A = *cnt;
@@ -1165,7 +1306,9 @@ __global__ __launch_bounds__(256) void k_dedup(const u64 *keys, int kin, const u
         i = act ? act[j] : j;
         const u64 len = off[i + 1] - off[i];
         bool dup = mode == DM_ALLDUP;
-        if (mode == DM_TABLE) {
+        if (mode == DM_TABLE && dupf) {
+            dup = dupf[j] != 0;
+        } else if (mode == DM_TABLE) {
             const u64 key = key_of(keys, kin, i, j);
             const u64 mask = (1ull << logT) - 1ull;
             u64 s = tab_slot(key, logT);
@@ -1211,7 +1354,66 @@ struct PdWs {
     u32 *actA, *actB, *ctr;
     u64 *hdr, *keys, *keysB, *keysC, *state, *pre, *tab;
     v4i *wt;
+    u32 *ddh, *ddscr;  // bucketed duplicate detection: counts matrix and its scan scratch
 };
+#define CTR_DDERR 6  // ctr word: a bucket pass gave up (never in practice)
+
+// Entries of the counts matrix (buckets x workgroups) the workspace holds.
+static u64 dd_hm_cap(u64 n) { return (u64)DD_HM_CAP < 4 * n + 64 ? (u64)DD_HM_CAP : 4 * n + 64; }
+
+// Whether a table round over Ah keys takes the bucketed form (tuning: 0 the
+// global table, 1 buckets for lists of DD_MIN_ACT..DD_MAX_ACT keys, 2 buckets
+// for every list up to DD_MAX_ACT).  On the 16M-string D/N step the two forms
+// take the same time beside the sort, and the table alone is faster, so the
+// table is the default.
+static bool dd_use(u32 Ah)
+{
+    if (g_dedup_mode == 0) return false;
+    if (g_dedup_mode == 2) return Ah <= DD_MAX_ACT;
+    return Ah >= DD_MIN_ACT && Ah <= DD_MAX_ACT;
+}
+
+// Duplicate flags of the Ah active keys by buckets (see k_dd_count); the
+// pairs and flags live in the (unused) global table's memory: keys 8 B, list
+// positions 4 B and flags 1 B per entry within its >= 16 B per string.
+static int dd_run(const u64 *keys, int kin, const u32 *act, const u32 *cntp, u32 Ah, u64 n, PdWs &w,
+                  const u8 **dupf_out, hipStream_t st)
+{
+    const u64 cap = dd_hm_cap(n);
+    u32 logB = 0;  // buckets of about 2048 keys
+    if (g_dedup_logb > 0) logB = (u32)g_dedup_logb;
+    else
+        while (((u64)2048 << logB) < Ah && logB < DD_MAXLOG) logB++;
+    while (logB > 0 && ((u64)1 << logB) > cap) logB--;
+    const u32 NB = 1u << logB;
+    // workgroups over chunks of >= 8192 entries, the matrix within its cap
+    u64 G = ceil_div(Ah, 8192);
+    if (G > cap / NB) G = cap / NB;
+    if (G < 1) G = 1;
+    const u32 C = (u32)ceil_div(Ah, G);
+    G = ceil_div(Ah, C);
+    u64 *pk = w.tab;
+    u32 *pj = (u32 *)(w.tab + n);
+    u8 *dupf = (u8 *)(pj + n);
+    {
+        SS_PROF("k_dd_count", st, (double)Ah * (act ? 16.0 : 8.0));  // (list entry,) key
+        k_dd_count<<<(unsigned)G, DD_NT, 0, st>>>(keys, kin, act, cntp, logB, C, (u32)G, w.ddh);
+    }
+    SS_CHECK_LAUNCH();
+    SS_TRY(ss_scan_exclusive<u32>(w.ddh, w.ddh, (u64)NB * G, w.ddscr, st));
+    {
+        SS_PROF("k_dd_scatter", st, (double)Ah * (act ? 28.0 : 20.0));  // (list entry,) key in, pair out
+        k_dd_scatter<<<(unsigned)G, DD_NT, 0, st>>>(keys, kin, act, cntp, logB, C, (u32)G, w.ddh, pk, pj);
+    }
+    SS_CHECK_LAUNCH();
+    {
+        SS_PROF("k_dd_bucket", st, (double)Ah * 13.0);  // pair in, flag out
+        k_dd_bucket<<<NB < 2048 ? NB : 2048, DD_NT, 0, st>>>(w.ddh, (u32)G, NB, pk, pj, dupf, w.ctr + CTR_DDERR);
+    }
+    SS_CHECK_LAUNCH();
+    *dupf_out = dupf;
+    return SS_OK;
+}
 
 static u32 tab_log(u64 A)
 {
@@ -1230,6 +1432,8 @@ static void pd_layout(u64 n, PdWs *w, WsArena *a, WsCounter *c)
     PT(actA, u32, n); PT(actB, u32, n); PT(hdr, u64, HDR_WORDS); PT(keys, u64, n); PT(keysB, u64, n);
     PT(keysC, u64, n); PT(state, u64, n);
     PT(pre, u64, (u64)PRE_ALL * n); PT(tab, u64, 1ull << tab_log(n)); PT(wt, v4i, WT_ROUND + WT_FIRST);
+    const u64 hm = dd_hm_cap(n) + 1;
+    PT(ddh, u32, hm); PT(ddscr, u32, ss_scan_scratch_elems<u32>(hm));
 #undef PT
     if (a) w->ctr = (u32 *)w->hdr;
 }
@@ -1461,6 +1665,9 @@ static int pd_run(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uin
             pf[2 * r + 1] = F[3 * r + 2] != 0;
         }
     }
+    k_store_u32<<<1, 1, 0, st>>>(ctr + CTR_DDERR, 0u);
+    SS_CHECK_LAUNCH();
+    bool dd_used = false;
     u32 Ah = (u32)n;           // active count (exact after each flag read)
     const u32 *act = nullptr;  // the active strings (NULL = all, in input order)
     u32 *nxt = w.actA;
@@ -1585,7 +1792,11 @@ static int pd_run(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uin
         pend_flags = false;  // this round changes the list
         const int mode = Ah == 1 ? DM_UNIQUE : (differ ? DM_TABLE : DM_ALLDUP);
         u32 logT = 0;
-        if (mode == DM_TABLE) {
+        const u8 *dupf = nullptr;
+        if (mode == DM_TABLE && dd_use(Ah)) {
+            SS_TRY(dd_run(keys, kin, act, ctr + ci, Ah, n, w, &dupf, st));
+            dd_used = true;
+        } else if (mode == DM_TABLE) {
             logT = tab_log(Ah);
             SS_HIP(hipMemsetAsync(w.tab, 0xFF, sizeof(u64) << logT, st));
             {
@@ -1597,10 +1808,11 @@ static int pd_run(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uin
         SS_HIP(hipMemsetAsync(ctr + (ci ^ 1), 0, sizeof(u32), st));
         {
             // list entry, offsets, key, slot, dist or next entry (and a carried key)
-            SS_PROF("k_dedup", st, (double)Ah * ((mode == DM_TABLE ? 40.0 : 24.0) + (pend_next ? 16.0 : 0.0)));
+            SS_PROF("k_dedup", st,
+                    (double)Ah * ((mode == DM_TABLE ? (dupf ? 25.0 : 40.0) : 24.0) + (pend_next ? 16.0 : 0.0)));
             k_dedup<<<(unsigned)ceil_div(Ah, 256), 256, 0, st>>>(keys, kin, act, ctr + ci, offsets, l, mode, w.tab,
                                                                  logT, dist_approx, nxt, ctr + (ci ^ 1), pend_next,
-                                                                 w.keysC);
+                                                                 w.keysC, dupf);
         }
         SS_CHECK_LAUNCH();
         if (pend_next) pend = w.keysC;
@@ -1615,6 +1827,14 @@ static int pd_run(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uin
             // find the list empty costs about as much as this read-back)
             SS_TRY(ss_read_u32(ctr + ci, &Ah, 1, st));
             if (Ah == 0) break;
+        }
+    }
+    if (dd_used) {
+        u32 e = 0;
+        SS_TRY(ss_read_u32(ctr + CTR_DDERR, &e, 1, st));
+        if (e) {
+            ss_set_error("duplicate detection: a bucket's keys did not split into passes");
+            return SS_ERR_INVALID_ARG;
         }
     }
     if (rounds_host) *rounds_host = rounds;

@@ -46,7 +46,7 @@ __global__ void k_select_batch(const u32 *perm, u64 n, const u64 *set_off, u32 n
     const u32 j = (u32)(t - (u64)b * per) + 1;
     const u64 lo = set_off[b], hi = set_off[b + 1];
     const bool ok = lo < hi && hi <= n;
-    if (j == 1 && (!ok || (b == 0 && lo != 0) || (b == num_sets - 1 && hi != n))) atomicOr(bad, 1u);
+    if (bad && j == 1 && (!ok || (b == 0 && lo != 0) || (b == num_sets - 1 && hi != n))) atomicOr(bad, 1u);
     u32 v = 0xFFFFFFFFu;
     if (ok) {
         const u64 m = hi - lo;
@@ -71,14 +71,20 @@ extern "C" int ss_select_splitters_batch(const uint32_t *perm, uint64_t n, const
         return SS_ERR_TOO_LARGE;
     }
     if (r == 1) return SS_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const u64 total = (u64)num_sets * (r - 1);
+    if (!ws && ws_bytes == 0) {  // unchecked: nothing read back
+        k_select_batch<<<(unsigned)ceil_div(total, 256), 256, 0, st>>>(perm, n, set_off, num_sets, r, splitter_ids,
+                                                                       nullptr);
+        SS_CHECK_LAUNCH();
+        return SS_OK;
+    }
     if (!ws || ws_bytes < sizeof(u32)) {
         ss_set_error("workspace too small: need %zu bytes", ss_select_splitters_batch_workspace());
         return SS_ERR_WORKSPACE;
     }
-    hipStream_t st = (hipStream_t)stream;
     u32 *bad = (u32 *)ws;
     SS_HIP(hipMemsetAsync(bad, 0, sizeof(u32), st));
-    const u64 total = (u64)num_sets * (r - 1);
     k_select_batch<<<(unsigned)ceil_div(total, 256), 256, 0, st>>>(perm, n, set_off, num_sets, r, splitter_ids,
                                                                    bad);
     SS_CHECK_LAUNCH();
@@ -120,7 +126,7 @@ __global__ void k_select_chars_batch(const u32 *perm, const u64 *P, u64 n, const
     const u32 j = (u32)(t - (u64)b * per) + 1;
     const u64 lo = set_off[b], hi = set_off[b + 1];
     const bool ok = lo < hi && hi <= n;
-    if (j == 1 && (!ok || (b == 0 && lo != 0) || (b == num_sets - 1 && hi != n))) atomicOr(bad, 1u);
+    if (bad && j == 1 && (!ok || (b == 0 && lo != 0) || (b == num_sets - 1 && hi != n))) atomicOr(bad, 1u);
     u32 v = 0xFFFFFFFFu;
     if (ok) {
         const u64 base = P[lo], Nb = P[hi] - base;
@@ -192,20 +198,23 @@ extern "C" int ss_select_splitters_chars_batch(const uint32_t *perm, const uint6
 
 // ---------------------------------------------------------------- gather
 
-__global__ void k_gather_lens(const u64 *off, const u32 *ids, u32 m, u64 *out)
+// (an id >= n -- e.g. the UINT32_MAX sample of a malformed set -- is an empty string)
+__global__ void k_gather_lens(const u64 *off, u64 n, const u32 *ids, u32 m, u64 *out)
 {
     const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < m) out[j] = off[ids[j] + 1] - off[ids[j]];
+    if (j < m) out[j] = ids[j] < n ? off[ids[j] + 1] - off[ids[j]] : 0ull;
 }
 
-// one wave per string, lanes copy consecutive bytes
-__global__ __launch_bounds__(256) void k_gather_copy(const u8 *bytes, const u64 *off, const u32 *ids,
-                                                     u32 m, const u64 *out_off, u8 *out)
+// one wave per string, lanes copy consecutive bytes; a string ending past cap
+// is not copied (the caller that read nothing back sees out_off[m] > cap)
+__global__ __launch_bounds__(256) void k_gather_copy(const u8 *bytes, const u64 *off, u64 n, const u32 *ids,
+                                                     u32 m, const u64 *out_off, u8 *out, u64 cap)
 {
     const u32 j = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (j >= m) return;
+    if (j >= m || ids[j] >= n) return;
     const u32 lane = threadIdx.x & 63;
     const u64 so = off[ids[j]], len = off[ids[j] + 1] - so, oo = out_off[j];
+    if (oo + len > cap) return;
     for (u64 q = lane; q < len; q += 64) out[oo + q] = bytes[so + q];
 }
 
@@ -221,7 +230,7 @@ extern "C" int ss_gather_strings(const uint8_t *bytes, uint64_t N, const uint64_
                                  uint64_t out_cap, uint64_t *total_host, void *ws, size_t ws_bytes, void *stream)
 {
     ss_clear_error();
-    (void)N; (void)n;
+    (void)N;
     if (m >= 0xFFFFFFFFull) { ss_set_error("m too large"); return SS_ERR_TOO_LARGE; }
     if (!out_offsets || (m > 0 && (!offsets || !ids))) { ss_set_error("null pointer"); return SS_ERR_INVALID_ARG; }
     hipStream_t st = (hipStream_t)stream;
@@ -232,10 +241,18 @@ extern "C" int ss_gather_strings(const uint8_t *bytes, uint64_t N, const uint64_
         return SS_ERR_WORKSPACE;
     }
     if (m > 0) {
-        k_gather_lens<<<(unsigned)ceil_div(m, 256), 256, 0, st>>>(offsets, ids, (u32)m, out_offsets);
+        k_gather_lens<<<(unsigned)ceil_div(m, 256), 256, 0, st>>>(offsets, n, ids, (u32)m, out_offsets);
         SS_CHECK_LAUNCH();
     }
     SS_TRY(ss_scan_exclusive<u64>(out_offsets, out_offsets, m, scratch, st));
+    if (!total_host) {  // nothing read back: the copy checks the capacity per string
+        if (m > 0) {
+            k_gather_copy<<<(unsigned)ceil_div(m, 4), 256, 0, st>>>(bytes, offsets, n, ids, (u32)m, out_offsets,
+                                                                    out_bytes, out_cap);
+            SS_CHECK_LAUNCH();
+        }
+        return SS_OK;
+    }
     u64 total;
     SS_TRY(ss_read_u64(out_offsets + m, &total, 1, st));
     if (total_host) *total_host = total;
@@ -245,8 +262,8 @@ extern "C" int ss_gather_strings(const uint8_t *bytes, uint64_t N, const uint64_
         return SS_ERR_CAPACITY;
     }
     if (m > 0 && total > 0) {
-        k_gather_copy<<<(unsigned)ceil_div(m, 4), 256, 0, st>>>(bytes, offsets, ids, (u32)m, out_offsets,
-                                                                out_bytes);
+        k_gather_copy<<<(unsigned)ceil_div(m, 4), 256, 0, st>>>(bytes, offsets, n, ids, (u32)m, out_offsets,
+                                                                out_bytes, out_cap);
         SS_CHECK_LAUNCH();
     }
     return SS_OK;

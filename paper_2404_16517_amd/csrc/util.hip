@@ -27,6 +27,8 @@ extern "C" int ss_version(void) { return 100; }
 int g_small_max = 1024;
 int g_tile = 4096;
 int g_digit_bits = 8;
+int g_dedup_mode = 0;
+int g_dedup_logb = 0;
 
 extern "C" int ss_set_tuning(int param, int value)
 {
@@ -55,6 +57,24 @@ extern "C" int ss_set_tuning(int param, int value)
         }
         int old = g_digit_bits;
         g_digit_bits = value;
+        return old;
+    }
+    if (param == SS_TUNE_DEDUP) {
+        if (value < 0 || value > 2) {
+            ss_set_error("SS_TUNE_DEDUP must be 0, 1 or 2");
+            return SS_ERR_INVALID_ARG;
+        }
+        int old = g_dedup_mode;
+        g_dedup_mode = value;
+        return old;
+    }
+    if (param == SS_TUNE_DEDUP_LOG_BUCKETS) {
+        if (value < 0 || value > 14) {
+            ss_set_error("SS_TUNE_DEDUP_LOG_BUCKETS must be 0..14");
+            return SS_ERR_INVALID_ARG;
+        }
+        int old = g_dedup_logb;
+        g_dedup_logb = value;
         return old;
     }
     ss_set_error("unknown tuning parameter %d", param);

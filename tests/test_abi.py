@@ -91,6 +91,14 @@ def test_tuning_validation():
     assert ss.set_tuning(ss.SS_TUNE_DIGIT_BITS, 8) == 11
     with pytest.raises(ss.StrsortError):
         ss.set_tuning(ss.SS_TUNE_DIGIT_BITS, 16)
+    assert ss.set_tuning(ss.SS_TUNE_DEDUP, 1) == 0
+    assert ss.set_tuning(ss.SS_TUNE_DEDUP, 0) == 1
+    assert ss.set_tuning(ss.SS_TUNE_DEDUP_LOG_BUCKETS, 3) == 0
+    assert ss.set_tuning(ss.SS_TUNE_DEDUP_LOG_BUCKETS, 0) == 3
+    with pytest.raises(ss.StrsortError):
+        ss.set_tuning(ss.SS_TUNE_DEDUP, 3)
+    with pytest.raises(ss.StrsortError):
+        ss.set_tuning(ss.SS_TUNE_DEDUP_LOG_BUCKETS, 15)
 
 
 def test_device_batch_sort_and_graph_arguments():

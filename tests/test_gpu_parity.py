@@ -587,6 +587,42 @@ def test_gather_strings_capacity_hint(hint):
     np.testing.assert_array_equal(go.cpu().numpy(), np.cumsum([0] + [len(x) for x in want]))
 
 
+@pytest.mark.parametrize("r", [2, 17])
+def test_select_splitters_batch_unchecked(r):
+    """Without the check nothing is read back and well-formed sets give the
+    checked call's samples; a bad set's samples are 0xFFFFFFFF."""
+    rng = np.random.default_rng(40 + r)
+    sizes = rng.integers(1, 3000, 25)
+    set_off = torch.from_numpy(np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)).to(DEV)
+    perm = torch.from_numpy(rng.integers(0, 2**31 - 1, int(sizes.sum()), dtype=np.int64).astype(np.int32)).to(DEV)
+    a = ss.select_splitters_batch(perm, set_off, r)
+    b = ss.select_splitters_batch(perm, set_off, r, check=False)
+    assert torch.equal(a, b)
+    p6 = torch.arange(6, dtype=torch.int32, device=DEV)
+    bad = ss.select_splitters_batch(p6, torch.tensor([0, 3, 3, 6], device=DEV), 2, check=False)
+    assert list(u32(bad)) == [1, 0xFFFFFFFF, 4]
+
+
+@pytest.mark.parametrize("cap", [10**6, 120, 0])
+def test_gather_strings_without_read_back(cap):
+    """sync=False: offsets are complete on the device; strings that would end
+    past the capacity are not copied, the others are; an id past the last
+    string is an empty string."""
+    s = synth.text_strings(5000, seed=15, median=30)
+    g = s.to(DEV)
+    ids = torch.tensor([4999, 0, 17, 17, -1, 2500, 3], dtype=torch.int32, device=DEV)  # -1 = 0xFFFFFFFF
+    gb, go = ss.gather_strings(g.bytes, g.offsets, ids, cap_hint=cap, sync=False)
+    torch.cuda.synchronize()
+    strs = s.as_list()
+    want = [strs[i] if i >= 0 else b"" for i in ids.tolist()]
+    offs = np.cumsum([0] + [len(x) for x in want])
+    np.testing.assert_array_equal(go.cpu().numpy(), offs)
+    buf = bytes(gb.cpu().numpy())
+    for k, w in enumerate(want):
+        if offs[k + 1] <= cap:
+            assert buf[offs[k]:offs[k + 1]] == w
+
+
 @pytest.mark.parametrize("short_by", [1, 5000])
 def test_partition_encode_capacity(short_by):
     """A literal buffer shorter than the literals: CAPACITY, no literal byte
