@@ -298,6 +298,28 @@ __global__ __launch_bounds__(NT, 6) void k_skip(const Seg *segs, const u32 *tsta
     const u32 lt = t - tstart[sg];
     const u32 b0 = g.begin + lt * ETILE;
     const u32 b1 = min(g.end, b0 + ETILE);
+    if (SEED && sok) {
+        // the tile's records, one member per thread: when the seed resolved
+        // every member, their minimum is the tile's part of the skip and no
+        // string is read (a tile with an open member takes the loop below)
+        u32 sb = 0xFFFFFFFFu;
+        bool open = false;
+#pragma unroll 8
+        for (u32 k = 0; k < ETILE / NT; k++) {
+            const u32 i = b0 + k * NT + threadIdx.x;
+            if (i < b1) {
+                const uint2 sp = mpr[i];
+                open |= sp.y == SEED_OPEN;
+                const u32 c = sp.x > g.depth ? sp.x - g.depth : 0u;
+                sb = c < sb ? c : sb;
+            }
+        }
+        if (!__syncthreads_or(open)) {  // (uniform)
+            const u32 bm = block_min(sb);
+            if (threadIdx.x == 0) atomicMin(&skipv[sg], bm);
+            continue;
+        }
+    }
     const u32 f = perm[g.begin];
     const u64 fo = off[f];
     const u32 fl = (u32)(off[f + 1] - fo);
