@@ -305,7 +305,8 @@ __device__ __forceinline__ void lds_le16(const u8 *R, u32 a, u64 &lo, u64 &hi)
 // state later rounds continue from.  (When the deep first pass is chosen it
 // does this work and more, and this kernel is not launched.)
 __global__ __launch_bounds__(256, 4) void k_hash_first(u32 n, const u8 *bytes, u64 N, const u64 *off, PreLens P,
-                                                       u32 bits, BPow bp, FirstW fw, u64 *state, u64 *pre, u64 *fl)
+                                                       u32 bits, BPow bp, FirstW fw, u64 *state, u64 *pre, u64 *fl,
+                                                       u32 wstate)
 {
     __shared__ v4i wtab[HF_ACC][2][2][64];  // [accumulator][32-byte block][low/high product][lane]
     __shared__ __attribute__((aligned(16))) u8 rows[4 * HF_ROW];
@@ -465,7 +466,7 @@ __global__ __launch_bounds__(256, 4) void k_hash_first(u32 n, const u8 *bytes, u
                     const u32 mr = len_c < lr ? len_c : lr;
                     const u64 key = kr_key(G, bp.p[(mr + 3) / 4 + 1], mr, bits);
                     pre[(u64)r * n + i] = key;
-                    if (r == P.count - 1) state[i] = G;  // later rounds continue from G
+                    if (wstate && r == P.count - 1) state[i] = G;  // later rounds continue from G
                     fmn[a] = key < fmn[a] ? key : fmn[a];
                     fmx[a] = key > fmx[a] ? key : fmx[a];
                     if (len_c <= lr) fsh[a] = 1;
@@ -518,6 +519,12 @@ struct FirstArgs {
     uint2 *seed_pos;
     const u64 *set_off;
     u32 nsets;
+    // lazy: the rounds of at most 64 bytes are not hashed; instead cert gets
+    // a lower bound on every string's LCP with string 0 (over at most 256
+    // bytes) and minlen the shortest length, from which the caller tells
+    // whether those rounds can finish anything (if so it hashes them later)
+    u32 lazy;
+    u64 *cert, *minlen;
 };
 
 #define SEED_MAX_SETS 16  // sets whose first strings the pass keeps in LDS (more: no seed)
@@ -641,12 +648,14 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
     __shared__ u64 s_ref[FIRST ? SEED_MAX_SETS : 1][FIRST ? PRE_MAX / 2 : 1];
     __shared__ u32 s_refl[FIRST ? SEED_MAX_SETS : 1];
     __shared__ u64 s_mw[FIRST ? 4 : 1][32];  // per wavefront and string: the 8 bytes at its record
-    const bool seeding = FIRST && Fp->seed_pos != nullptr;  // uniform
-    const u32 nsets = (FIRST && seeding && Fp->set_off) ? Fp->nsets : 1u;  // (<= SEED_MAX_SETS)
+    const bool seeding = FIRST && Fp->seed_pos != nullptr;  // uniform: seed records are written
+    const bool lazy = FIRST && Fp->lazy != 0;                // the rounds up to 64 bytes are left out
+    const bool comparing = seeding || lazy;                  // the strings are compared with their references
+    const u32 nsets = (FIRST && comparing && Fp->set_off) ? Fp->nsets : 1u;  // (<= SEED_MAX_SETS)
     if (FIRST) {
         const FirstArgs &F = *Fp;
         c0 = F.P.count;
-        if (seeding) {
+        if (comparing) {
             for (u32 e = threadIdx.x; e <= nsets; e += blockDim.x)
                 s_set[e] = F.set_off ? F.set_off[e] : (e ? (u64)A.n : 0ull);
             for (u32 e = threadIdx.x; e < nsets * (PRE_MAX / 2); e += blockDim.x) {
@@ -808,6 +817,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
         v16i S = {};
         u32 xp = x0;
         u32 smis = 0xFFFFFFFFu;  // sort seed: first byte of this lane's pieces unlike the reference's
+        u32 cmin = 0xFFFFFFFFu, lmin = 0xFFFFFFFFu;  // lazy: this lane's certified LCP, shortest length
         bool mwgot = false;      // ... the string's 8 bytes at its record are in s_mw
         u32 runi = 1;            // the tile's strings share one set (uniform)
         u32 rsel = 0;            // ... which one (uniform)
@@ -823,7 +833,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
             runi = __builtin_amdgcn_readfirstlane((u32)(__shfl(slo, 0, 64) == __shfl(slo, 31, 64)));
             rsel = __builtin_amdgcn_readfirstlane(slo);
         };
-        if (FIRST && seeding) seed_ref(tile);
+        if (FIRST && comparing) seed_ref(tile);
         issue_copy(o_c, m, xp);
         for (;;) {  // passes; uniform over the wavefront
             // this pass's operand bytes: [u][kb], 16 each (zero past the string)
@@ -852,7 +862,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                             }
                         }
                     }
-                if (FIRST && seeding && runi) {
+                if (FIRST && comparing && runi) {
                     // this lane's pieces against the reference's bytes at the same
                     // positions (both zero past their ends; a difference at or
                     // past the shorter end is discarded below)
@@ -879,7 +889,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                     const u32 rfl = s_refl[rsel];
                     const u32 E = len < rfl ? len : rfl;
                     const u32 rc = sm < E ? sm : E;
-                    if (!h && rc >= xp && rc < xp + 64 * RP_STEPS) {
+                    if (seeding && !h && rc >= xp && rc < xp + 64 * RP_STEPS) {
                         const u32 tk = len - rc < 8 ? len - rc : 8u;
                         if (tk == 0) {
                             s_mw[wv][col] = 0;
@@ -911,7 +921,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
 #pragma unroll
             for (int u = 0; u < RP_STEPS; u++) {
                 const u32 x = xp + 64 * u;
-                const bool fstep = FIRST && x == 0;  // the first pass's rounds (taken even for empty strings)
+                const bool fstep = FIRST && x == 0 && !lazy;  // the first pass's rounds (taken even for empty strings)
                 if (x >= xmax && !fstep) break;      // uniform over the wavefront
                 const u32 sidx = (x & 1023) >> 6;
                 v4i xl[2], xh[2];
@@ -986,15 +996,22 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
             // and stored after the keys below
             u64 mw = 0;
             uint2 sp = make_uint2(0u, SEED_OPEN);
-            if (FIRST && seeding) {
+            if (FIRST && comparing) {
                 const u32 y = __shfl_xor(smis, 32, 64);
                 smis = y < smis ? y : smis;
                 const u32 rfl = s_refl[rsel];
                 const u32 E = len < rfl ? len : rfl;  // compared up to the shorter end
                 const u32 r = smis < E ? smis : E;
+                if (lazy && valid) {
+                    // LCP with the reference (capped at 256 or the shorter end; a
+                    // tile across sets certifies nothing), and the length
+                    const u32 c = runi ? r : 0u;
+                    cmin = c < cmin ? c : cmin;
+                    lmin = len < lmin ? len : lmin;
+                }
                 // equal over [0, lend): the sort goes on from lend (across sets: from 0)
                 sp = make_uint2(runi ? lend : 0u, SEED_OPEN);
-                if (valid && !h && runi && (r < lend || E <= lend)) {
+                if (seeding && valid && !h && runi && (r < lend || E <= lend)) {
                     const u32 tk = len - r < 8 ? len - r : 8u;
                     mw = mwgot ? s_mw[wv][col] : (tk ? load_be(bytes, N, o_c + r, tk) : 0ull);
                     sp = make_uint2(r, tk);
@@ -1043,8 +1060,36 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                 if (LP) G_n = A.state[i_n];
             }
             i_nn = entry(tile + 2 * nwaves < ntiles ? tile + 2 * nwaves : tile);
-            if (FIRST && seeding) seed_ref(tile);
+            if (FIRST && comparing) seed_ref(tile);
         }
+        if (FIRST && lazy) {
+            // one atomic per wavefront for the certificate and the length
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const u32 y = __shfl_xor(cmin, o, 64), z = __shfl_xor(lmin, o, 64);
+                cmin = y < cmin ? y : cmin;
+                lmin = z < lmin ? z : lmin;
+            }
+            if (lane == 0) {
+                atomicMin((unsigned long long *)Fp->cert, (unsigned long long)cmin);
+                atomicMin((unsigned long long *)Fp->minlen, (unsigned long long)lmin);
+            }
+        }
+    }
+    if (FIRST && lazy && blockIdx.x == 0 && threadIdx.x < nsets) {
+        // every reference's LCP with string 0 over the staged bytes
+        const u32 sx = threadIdx.x;
+        const u32 E = s_refl[sx] < s_refl[0] ? s_refl[sx] : s_refl[0];
+        u32 c = 4 * PRE_MAX;
+        for (u32 q = 0; q < PRE_MAX / 2; q++) {
+            const u64 d = s_ref[sx][q] ^ s_ref[0][q];
+            if (d) {
+                c = 8 * q + (u32)(__builtin_ctzll(d) >> 3);
+                break;
+            }
+        }
+        c = c < E ? c : E;
+        atomicMin((unsigned long long *)Fp->cert, (unsigned long long)c);
     }
     if constexpr (FIRST) {
         stage(HF_ACC);
@@ -1099,6 +1144,7 @@ __device__ __forceinline__ u64 tab_slot(u64 key, u32 logT)
 __device__ __forceinline__ u64 key_of(const u64 *keys, int kin, u32 i, u32 j) { return keys[kin ? i : j]; }
 
 __global__ void k_store_u32(u32 *p, u32 v) { *p = v; }
+__global__ void k_store_u64(u64 *p, u64 v) { *p = v; }
 
 // For one round over the active list: flags[0] = 1 if some key differs from
 // the first entry's, flags[1] = 1 if some string has length <= l.  A round
@@ -1350,6 +1396,9 @@ __global__ __launch_bounds__(256) void k_dedup(const u64 *keys, int kin, const u
 #define HDR_DEEP (HDR_FIRST + 3 * PRE_ALL)
 #define HDR_ROUND (HDR_DEEP + 1)
 #define HDR_PRECOUNT (HDR_ROUND + 6)  // rounds the first pass precomputed (for a later rounds call)
+#define HDR_CERT (HDR_PRECOUNT + 1)    // lazy deep pass: every string's certified LCP with string 0
+#define HDR_MINLEN (HDR_CERT + 1)      // ... the shortest length
+#define HDR_LAZY (HDR_MINLEN + 1)      // 1: the deep pass left its rounds of <= 64 bytes unhashed
 struct PdWs {
     u32 *actA, *actB, *ctr;
     u64 *hdr, *keys, *keysB, *keysC, *state, *pre, *tab;
@@ -1503,12 +1552,14 @@ enum { FP_PROBE = 0, FP_PLAIN = 1, FP_DEEP = 2 };
 
 static int first_pass(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uint64_t n, uint32_t init_len,
                       uint32_t hash_bits, PdWs &w, int mode, PreLens &P, hipStream_t st, void *seed = nullptr,
-                      const u64 *set_off = nullptr, u32 nsets = 1)
+                      const u64 *set_off = nullptr, u32 nsets = 1, bool lazy_ok = false)
 {
     if (seed) {  // not written unless the deep pass runs
         k_store_u32<<<1, 1, 0, st>>>((u32 *)seed, 0u);
         SS_CHECK_LAUNCH();
     }
+    k_store_u64<<<1, 1, 0, st>>>(w.hdr + HDR_LAZY, 0ull);
+    SS_CHECK_LAUNCH();
     P = PreLens{};
     for (u64 L = init_len; L <= PRE_MAX && P.count < PRE_SLOTS; L *= 2) P.l[P.count++] = L;
     if (!P.count) return SS_OK;
@@ -1556,19 +1607,40 @@ static int first_pass(const uint8_t *bytes, uint64_t N, const uint64_t *offsets,
     Fa.fw = first_weights();
     // (the pass keeps every set's first string in LDS: with more sets it
     // writes no seed, and the sort compares everything itself)
-    if (seed && set_off && nsets > SEED_MAX_SETS) seed = nullptr;
+    if (set_off && nsets > SEED_MAX_SETS) {
+        seed = nullptr;
+        set_off = nullptr;  // (a lazy certificate then compares with string 0)
+    }
     if (seed && deep) {
         Fa.seed_word = (u64 *)((u8 *)seed + SEED_HDR);
         Fa.seed_pos = (uint2 *)((u8 *)seed + SEED_HDR + 8 * n);
+    }
+    if (deep) {
         Fa.set_off = set_off;
         Fa.nsets = set_off ? nsets : 1u;
+    }
+    // Lazy: the deep pass leaves the rounds of <= 64 bytes out and certifies
+    // instead how long a prefix every string shares with string 0; the rounds
+    // call hashes them only if that does not show them unable to finish any
+    // string.
+    const bool lazy = deep && lazy_ok;
+    if (lazy) {
+        Fa.lazy = 1;
+        Fa.cert = w.hdr + HDR_CERT;
+        Fa.minlen = w.hdr + HDR_MINLEN;
+        k_store_u64<<<1, 1, 0, st>>>(w.hdr + HDR_CERT, ~0ull);
+        SS_CHECK_LAUNCH();
+        k_store_u64<<<1, 1, 0, st>>>(w.hdr + HDR_MINLEN, ~0ull);
+        SS_CHECK_LAUNCH();
+        k_store_u64<<<1, 1, 0, st>>>(w.hdr + HDR_LAZY, 1ull);
+        SS_CHECK_LAUNCH();
     }
     if (!deep) {
         // algorithmic bytes: each string's prefix read once, its offsets, one
         // key written per precomputed round
         SS_PROF("k_hash_first", st, (double)n * (double)P.l[c0 - 1] + (double)n * (8.0 + 8.0 * c0));
         k_hash_first<<<blocks, 256, 0, st>>>((u32)n, bytes, N, offsets, P, hash_bits, bp, Fa.fw, w.state, w.pre,
-                                             fl_first);
+                                             fl_first, 1u);
         SS_CHECK_LAUNCH();
     } else {
         const RoundW rwd = round_weights(0, 2 * PRE_MAX, 4 * PRE_MAX);
@@ -1579,7 +1651,7 @@ static int first_pass(const uint8_t *bytes, uint64_t N, const uint64_t *offsets,
         // stream's kernels they give compute units back sooner
         const unsigned dblocks = (unsigned)(ceil_div(tiles, 4) < 8192 ? ceil_div(tiles, 4) : 8192);
         SS_PROF("k_hash_first_deep", st,
-                (double)n * (4.0 * PRE_MAX) + (double)n * (8.0 + 8.0 * (c0 + 2) + (seed ? 16.0 : 0.0)));
+                (double)n * (4.0 * PRE_MAX) + (double)n * (8.0 + 8.0 * (lazy ? 2 : c0 + 2) + (seed ? 16.0 : 0.0)));
         k_hash_first_deep<<<dblocks, 256, 0, st>>>(A, rwd, Fa);
         SS_CHECK_LAUNCH();
         if (seed) {
@@ -1593,7 +1665,6 @@ static int first_pass(const uint8_t *bytes, uint64_t N, const uint64_t *offsets,
     return SS_OK;
 }
 
-__global__ void k_store_u64(u64 *p, u64 v) { *p = v; }
 
 enum { PD_FIRST = 1, PD_ROUNDS = 2 };
 
@@ -1636,15 +1707,16 @@ static int pd_run(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uin
     if (parts & PD_FIRST) {
         k_store_u32<<<1, 1, 0, st>>>(ctr, (u32)n);
         SS_CHECK_LAUNCH();
-        SS_TRY(first_pass(bytes, N, offsets, n, init_len, hash_bits, w, fp_mode, P, st, seed, set_off, nsets));
+        SS_TRY(first_pass(bytes, N, offsets, n, init_len, hash_bits, w, fp_mode, P, st, seed, set_off, nsets, true));
         k_store_u64<<<1, 1, 0, st>>>(w.hdr + HDR_PRECOUNT, P.count);
         SS_CHECK_LAUNCH();
         if (!(parts & PD_ROUNDS)) return SS_OK;
     }
     {
-        // the flags of every precomputed round and (rounds call alone) their count
-        u64 F[HDR_PRECOUNT + 1 - HDR_FIRST];
-        SS_TRY(ss_read_u64(w.hdr + HDR_FIRST, F, HDR_PRECOUNT + 1 - HDR_FIRST, st));
+        // the flags of every precomputed round, (rounds call alone) their
+        // count, and a lazy deep pass's certificate
+        u64 F[HDR_LAZY + 1 - HDR_FIRST];
+        SS_TRY(ss_read_u64(w.hdr + HDR_FIRST, F, HDR_LAZY + 1 - HDR_FIRST, st));
         if (!(parts & PD_FIRST)) {
             // the lengths follow from init_len and the count (plain pass: the
             // rounds up to 64 bytes; deep pass: and the two after)
@@ -1663,6 +1735,37 @@ static int pd_run(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uin
         for (u32 r = 0; r < P.count; r++) {
             pf[2 * r] = F[3 * r] != F[3 * r + 1];
             pf[2 * r + 1] = F[3 * r + 2] != 0;
+        }
+        if (F[HDR_LAZY - HDR_FIRST] && P.count >= 2) {
+            // The deep pass hashed only the rounds after 64 bytes.  Every
+            // string shares its first `cert` bytes with string 0 and is
+            // `mlen` bytes long or longer: when both reach past the longest
+            // of those rounds, each of them has one key for all and no short
+            // string -- it finishes nothing, the list stays whole, and its
+            // keys are never read.  Otherwise the plain pass hashes them now
+            // (without touching the running sums of the deep pass).
+            const u32 cs = P.count - 2;
+            const u64 cert = F[HDR_CERT - HDR_FIRST], mlen = F[HDR_MINLEN - HDR_FIRST];
+            const bool need = cs > 0 && (cert < P.l[cs - 1] || mlen <= P.l[cs - 1]);
+            if (!need) {
+                for (u32 r = 0; r < cs; r++) pf[2 * r] = pf[2 * r + 1] = 0;
+            } else {
+                PreLens Ps = P;
+                Ps.count = cs;
+                k_flag_init<<<1, 64, 0, st>>>(w.hdr + HDR_FIRST, 3 * cs, 3 * cs);
+                SS_CHECK_LAUNCH();
+                const u64 tiles = ceil_div(n, 32);
+                const unsigned blocks = (unsigned)(ceil_div(tiles, 4) < 2048 ? ceil_div(tiles, 4) : 2048);
+                SS_PROF("k_hash_first", st, (double)n * (double)Ps.l[cs - 1] + (double)n * (8.0 + 8.0 * cs));
+                k_hash_first<<<blocks, 256, 0, st>>>((u32)n, bytes, N, offsets, Ps, hash_bits, bp, first_weights(),
+                                                     w.state, w.pre, w.hdr + HDR_FIRST, 0u);
+                SS_CHECK_LAUNCH();
+                SS_TRY(ss_read_u64(w.hdr + HDR_FIRST, F, 3 * cs, st));
+                for (u32 r = 0; r < cs; r++) {
+                    pf[2 * r] = F[3 * r] != F[3 * r + 1];
+                    pf[2 * r + 1] = F[3 * r + 2] != 0;
+                }
+            }
         }
     }
     k_store_u32<<<1, 1, 0, st>>>(ctr + CTR_DDERR, 0u);
