@@ -507,6 +507,11 @@ void ss_graph_destroy(ss_graph g);
  * earlier records.  Records are process-wide; use from one thread. */
 void ss_profile_enable(int on);
 
+/* Record only the launches of kernel `name` (NULL or "": all).  Fewer event
+ * pairs in a timed region cost less host time.  Set it while no library call
+ * is running. */
+void ss_profile_only(const char *name);
+
 /* Totals for kernel `name` over the records so far: summed event time (ms),
  * summed algorithmic bytes and number of launches (synchronises the recorded
  * events).  Returns SS_OK, or SS_ERR_INVALID_ARG if nothing was recorded. */

@@ -81,6 +81,7 @@ def lib():
                                            P, P, SZ, P], I32),
             "ss_fc_decode_workspace": ([U64], SZ),
             "ss_profile_enable": ([I32], None),
+            "ss_profile_only": ([ctypes.c_char_p], None),
             "ss_profile_query": ([ctypes.c_char_p, P, P, P], I32),
             "ss_profile_names": ([ctypes.c_char_p, SZ], SZ),
             "ss_fc_decode": ([U32, P, P, P, P, P, U64, P, P, U64, P, SZ, P], I32),
@@ -545,6 +546,11 @@ def partition_encode_batch(bytes_, offsets, set_off, perm, lcp_, dist, spl_bytes
 def profile_enable(on: bool = True):
     """Record HIP events around the library's main kernels (clears old records)."""
     lib().ss_profile_enable(1 if on else 0)
+
+
+def profile_only(name: str | None = None):
+    """Record only the launches of kernel `name` (None: all)."""
+    lib().ss_profile_only(name.encode() if name else None)
 
 
 def profile_report() -> dict:

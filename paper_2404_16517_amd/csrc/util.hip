@@ -456,6 +456,7 @@ template int ss_scan_exclusive<u64>(const u64 *, u64 *, u64, u64 *, hipStream_t)
 bool g_prof_on = false;
 
 namespace {
+std::string g_prof_only;  // record only scopes of this name (empty: all)
 struct ProfRec {
     std::string name;
     hipEvent_t a, b;
@@ -503,6 +504,10 @@ void ev_give(hipEvent_t e)
 ProfScope::ProfScope(const char *n, hipStream_t s, double b) : name(n), st(s), bytes(b), a(nullptr), on(g_prof_on)
 {
     if (!on) return;
+    if (!g_prof_only.empty() && g_prof_only != n) {
+        on = false;
+        return;
+    }
     a = ev_take();
     if (!a || hipEventRecord(a, st) != hipSuccess) {
         ev_give(a);
@@ -552,6 +557,12 @@ extern "C" void ss_profile_enable(int on)
     std::lock_guard<std::mutex> lk(g_prof_mu);
     prof_clear();
     g_prof_on = on != 0;
+}
+
+extern "C" void ss_profile_only(const char *name)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_only = name ? name : "";
 }
 
 extern "C" int ss_profile_query(const char *name, double *ms, double *bytes, uint32_t *launches)
