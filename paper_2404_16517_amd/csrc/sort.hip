@@ -26,6 +26,9 @@
 #include <string.h>
 
 #include "common.hpp"
+#include <map>
+#include <mutex>
+
 #include "sort_core.hpp"
 
 #define NT 256
@@ -278,8 +281,10 @@ __device__ __forceinline__ u32 skip_cmp(const u8 *bytes, u64 N, const u8 *R, con
 // mpr.y is SEED_OPEN agreed with the first string up to mpr.x and is compared
 // from there, every other one is done without reading its string.
 #define SEED_OPEN 0xFFFFFFFFu
+// (the grid-stride form keeps its loop state live as well: five workgroups
+// per compute unit give it the registers to do so without spilling)
 template <bool LOOP, bool SEED = false>
-__global__ __launch_bounds__(NT, 6) void k_skip(const Seg *segs, const u32 *tstart, const u32 *nsegp,
+__global__ __launch_bounds__(NT, LOOP ? 5 : 6) void k_skip(const Seg *segs, const u32 *tstart, const u32 *nsegp,
                                              const u8 *bytes, u64 N, const u64 *off,
                                              const u32 *perm, u32 *skipv, u64 *mword, uint2 *mpr,
                                              const u32 *seed_ok = nullptr)
@@ -1219,6 +1224,32 @@ static unsigned grid_of(u64 items, u64 per, u64 cap)
     return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
+// Workgroups of `kernel` (nt threads) that the current device holds at once.
+// A grid-stride launch of at most this many runs as one wave of workgroups:
+// with more, the last workgroups -- each owning many tiles -- run while most
+// of the device waits for them.
+template <class K>
+static unsigned resident(K kernel, int nt)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, const void *>, unsigned> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    const auto key = std::make_pair(dev, (const void *)kernel);
+    const auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, nt, 0) != hipSuccess || per < 1 ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+        (void)hipGetLastError();
+        return 2048;  // (not cached: asked again next time)
+    }
+    const unsigned g = (unsigned)per * (unsigned)cus;
+    cache[key] = g;
+    return g;
+}
+
 // One round or level's lengths: known to the host (read back) or not.
 struct Known {
     bool yes;
@@ -1255,7 +1286,7 @@ static int round_head(RoundCtx &C, Known nact, Known atiles, u64 round_elems, bo
                                                                                w.skipv);
     SS_CHECK_LAUNCH();
     SS_TRY(scan_u32(C, w.tstart, nactp, nact));
-    const unsigned tg = grid_of(atiles.yes ? atiles.v : n, atiles.yes ? 1 : ETILE, atiles.yes ? 1u << 30 : 2048);
+    const unsigned tg = atiles.yes ? grid_of(atiles.v, 1, 1u << 30) : 0u;  // (one tile per workgroup)
     {
         // algorithmic bytes: perm + offsets + one word per string, its mismatch
         // record out, plus the common prefix (added once the skips are known)
@@ -1264,7 +1295,7 @@ static int round_head(RoundCtx &C, Known nact, Known atiles, u64 round_elems, bo
         SS_PROF("k_skip", st, (double)round_elems * (sd ? 8.0 : 44.0));
         if (sd) k_skip<false, true><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, J.seed_word, J.seed_pos, J.seed_ok);
         else if (atiles.yes) k_skip<false><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr);
-        else k_skip<true><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr);
+        else k_skip<true><<<grid_of(n, ETILE, resident(k_skip<true>, NT)), NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr);
     }
     SS_CHECK_LAUNCH();
     {
@@ -1274,7 +1305,7 @@ static int round_head(RoundCtx &C, Known nact, Known atiles, u64 round_elems, bo
         uint2 *mp = sd ? J.seed_pos : w.mpr;
         SS_PROF("k_keys", st, (double)round_elems * 24.0);  // mismatch record in, key out
         if (atiles.yes) k_keys<false><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, mw, mp, w.keyA);
-        else k_keys<true><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, mw, mp, w.keyA);
+        else k_keys<true><<<grid_of(n, ETILE, resident(k_keys<true>, NT)), NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, mw, mp, w.keyA);
     }
     SS_CHECK_LAUNCH();
     k_classify<<<grid_of(nact.yes ? nact.v : n / 2, 256, 1024), 256, 0, st>>>(w.act, nactp, w.skipv, C.SM, C.TL,
@@ -1300,11 +1331,11 @@ static int radix_level_w(RoundCtx &C, Seg *LA, Seg *LB, Known nlarge, Known ltil
                                                                                      w.smin, w.smax);
     SS_CHECK_LAUNCH();
     SS_TRY(scan_u32(C, w.tstart, nlp, nlarge));
-    const unsigned tg = grid_of(ltiles.yes ? ltiles.v : n, ltiles.yes ? 1 : C.TL, ltiles.yes ? 1u << 30 : 2048);
+    const unsigned tg = ltiles.yes ? grid_of(ltiles.v, 1, 1u << 30) : 0u;  // (one tile per workgroup)
     {
         SS_PROF("k_hist", st, (double)lelem * 8.0);  // read the keys
         if (ltiles.yes) k_hist<false, W><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.keyA, w.keyB, w.hist, w.smin, w.smax);
-        else k_hist<true, W><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.keyA, w.keyB, w.hist, w.smin, w.smax);
+        else k_hist<true, W><<<grid_of(n, C.TL, resident(k_hist<true, W>, NT)), NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.keyA, w.keyB, w.hist, w.smin, w.smax);
     }
     SS_CHECK_LAUNCH();
     if (ltiles.yes) SS_TRY(ss_scan_exclusive<u32>(w.hist, w.hist, (u64)ltiles.v * NB, (u32 *)w.scan_scratch, st));
@@ -1312,18 +1343,18 @@ static int radix_level_w(RoundCtx &C, Seg *LA, Seg *LB, Known nlarge, Known ltil
     EmitOut eo{w.tiny, w.small, LB, w.nxt, w.ident, w.bnd, w.ctr, w.scat, w.kinds, C.SM, C.TL};
     constexpr u32 SPG = EPB / Digits<W>::DPT;
     if (nlarge.yes) k_emit<false, W><<<grid_of(nlarge.v, SPG, 1u << 30), 256, 0, st>>>(LA, w.tstart, nlp, w.hist, w.smin, w.smax, eo);
-    else k_emit<true, W><<<grid_of(n / 128, SPG, 4096), 256, 0, st>>>(LA, w.tstart, nlp, w.hist, w.smin, w.smax, eo);
+    else k_emit<true, W><<<grid_of(n / 128, SPG, resident(k_emit<true, W>, 256)), 256, 0, st>>>(LA, w.tstart, nlp, w.hist, w.smin, w.smax, eo);
     SS_CHECK_LAUNCH();
     {
         SS_PROF("k_scatter", st, (double)lelem * 24.0);  // key+payload in and out
         if (ltiles.yes) k_scatter<false, W><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.hist, w.scat, w.keyA, J.vals, w.keyB, w.valB);
-        else k_scatter<true, W><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.hist, w.scat, w.keyA, J.vals, w.keyB, w.valB);
+        else k_scatter<true, W><<<grid_of(n, C.TL, resident(k_scatter<true, W>, NT)), NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.hist, w.scat, w.keyA, J.vals, w.keyB, w.valB);
     }
     SS_CHECK_LAUNCH();
     {
         SS_PROF("k_settle", st, (double)lelem * 8.0);  // at most the scattered keys read back
         if (ltiles.yes) k_settle<false, W><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.scat, w.kinds, w.keyB, w.valB, w.keyA, J.vals);
-        else k_settle<true, W><<<tg, NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.scat, w.kinds, w.keyB, w.valB, w.keyA, J.vals);
+        else k_settle<true, W><<<grid_of(n, C.TL, resident(k_settle<true, W>, NT)), NT, 0, st>>>(LA, w.tstart, nlp, C.TL, w.scat, w.kinds, w.keyB, w.valB, w.keyA, J.vals);
     }
     SS_CHECK_LAUNCH();
     return SS_OK;
@@ -1351,7 +1382,7 @@ static int round_tail(RoundCtx &C, const u32 *h)
             k_wave_sort<false><<<grid_of(h[C_TINY], WS_SPB, 1u << 30), 256, 0, st>>>(
                 w.tiny, w.ctr + C_TINY, w.keyA, J.vals, w.keyB, w.valB, lcp, w.nxt, w.ctr);
         else
-            k_wave_sort<true><<<grid_of(n / 2, WS_SPB, 2048), 256, 0, st>>>(
+            k_wave_sort<true><<<grid_of(n / 2, WS_SPB, resident(k_wave_sort<true>, 256)), 256, 0, st>>>(
                 w.tiny, w.ctr + C_TINY, w.keyA, J.vals, w.keyB, w.valB, lcp, w.nxt, w.ctr);
         SS_CHECK_LAUNCH();
     }
@@ -1364,7 +1395,7 @@ static int round_tail(RoundCtx &C, const u32 *h)
             k_lds_sort<false><<<grid_of(h[C_SMALLN], C.SM, 1u << 30), LDS_NT, 0, st>>>(
                 w.small, w.spref, w.ctr + C_SMALL, C.SM, w.keyA, J.vals, w.keyB, w.valB, lcp, w.nxt, w.ctr);
         else
-            k_lds_sort<true><<<grid_of(n, C.SM, 2048), LDS_NT, 0, st>>>(
+            k_lds_sort<true><<<grid_of(n, C.SM, resident(k_lds_sort<true>, LDS_NT)), LDS_NT, 0, st>>>(
                 w.small, w.spref, w.ctr + C_SMALL, C.SM, w.keyA, J.vals, w.keyB, w.valB, lcp, w.nxt, w.ctr);
         SS_CHECK_LAUNCH();
     }
@@ -1380,7 +1411,7 @@ static int round_tail(RoundCtx &C, const u32 *h)
         if (known)
             k_ident<false><<<grid_of(h[C_ITILES], 1, 1u << 30), NT, 0, st>>>(w.ident, w.tstart, w.ctr + C_IDENT, lcp);
         else
-            k_ident<true><<<grid_of(n, ETILE, 2048), NT, 0, st>>>(w.ident, w.tstart, w.ctr + C_IDENT, lcp);
+            k_ident<true><<<grid_of(n, ETILE, resident(k_ident<true>, NT)), NT, 0, st>>>(w.ident, w.tstart, w.ctr + C_IDENT, lcp);
         SS_CHECK_LAUNCH();
     }
     return SS_OK;
