@@ -513,6 +513,7 @@ KERNEL_SOURCES = {
     "k_hash_round": ["paper_2404_16517_amd/csrc/hash.hip", "paper_2404_16517_amd/csrc/common.hpp"],
     "k_hash_first": ["paper_2404_16517_amd/csrc/hash.hip", "paper_2404_16517_amd/csrc/common.hpp"],
     "k_hash_first_deep": ["paper_2404_16517_amd/csrc/hash.hip", "paper_2404_16517_amd/csrc/common.hpp"],
+    "k_hash_first_lazy": ["paper_2404_16517_amd/csrc/hash.hip", "paper_2404_16517_amd/csrc/common.hpp"],
     "k_skip": ["paper_2404_16517_amd/csrc/sort.hip", "paper_2404_16517_amd/csrc/common.hpp"],
 }
 DEFAULT_WORKLOAD = dict(n=16_000_000, length=500, ratio=0.5, pes=16, sampling=2)

@@ -285,7 +285,7 @@ __device__ __forceinline__ void lds_le16(const u8 *R, u32 a, u64 &lo, u64 &hi)
     for (int k = 0; k < 5; k++) d[k] = p[k];
     u32 q[4];
 #pragma unroll
-    for (int k = 0; k < 4; k++) q[k] = r ? __builtin_amdgcn_alignbyte(d[k + 1], d[k], r) : d[k];
+    for (int k = 0; k < 4; k++) q[k] = __builtin_amdgcn_alignbyte(d[k + 1], d[k], r);  // (r = 0: d[k])
     lo = (u64)q[0] | ((u64)q[1] << 32);
     hi = (u64)q[2] | ((u64)q[3] << 32);
 }
@@ -408,6 +408,10 @@ __global__ __launch_bounds__(256, 4) void k_hash_first(u32 n, const u8 *bytes, u
         for (;;) {  // tiles; uniform over the wavefront
             const u32 m = len_c < W ? len_c : W;
             u64 lo[2], hi[2];
+            // vmcnt(0): this tile's copy has landed in the rows (the compiler
+            // waits only for loads into registers)
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            __asm__ volatile("" ::: "memory");  // (no row read moves above the wait)
             {
                 const u32 sh = (u32)((babs + o_c) & 15);
                 const u32 nch = m ? (sh + m + 15) / 16 : 0u;
@@ -621,20 +625,31 @@ __global__ __launch_bounds__(256) void k_hash_weights(RoundW rw, FirstArgs F, v4
 // machinery, so data whose strings mostly share a long prefix are read once
 // instead of in two passes.  The host reads the probe's count back and
 // launches one of the two first-pass kernels.
-template <bool FIRST>
+//
+// LAZY (deep first pass only): the rounds up to 64 bytes are left out -- the
+// pass compares every string with its set's first string instead, and
+// certifies how long a prefix they all share (the rounds call hashes those
+// rounds afterwards only if that does not prove them unable to finish a
+// string).  Without the first step's products and their weight table the
+// kernel needs fewer registers and less LDS, and more workgroups fit on a
+// compute unit.
+template <bool FIRST, bool LAZY = false>
 __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, const FirstArgs *Fp)
 {
+    static_assert(FIRST || !LAZY, "only the deep first pass leaves rounds out");
     // round weights: [step of the chunk][32-byte block][16-byte half][digit]
-    __shared__ v4i wtab[WT_ROUND];
+    __shared__ v4i wtab[WT_ROUND + 1];  // (and a zero entry, for rows left out)
     // first-pass weights: [accumulator][32-byte block][low/high product][lane]
-    __shared__ v4i wfirst[FIRST ? WT_FIRST : 1];
+    __shared__ v4i wfirst[(FIRST && !LAZY) ? WT_FIRST : 1];
     __shared__ __attribute__((aligned(16))) u8 rows[4 * RP_ROW];
     __shared__ u64 pwa[4][32];  // per wavefront: pass start (16-aligned, relative) of each string
     __shared__ u32 pwn[4][32];  // ... and its chunk count (0: not copied)
     __shared__ u64 s_l[PRE_SLOTS];
+    if (threadIdx.x == 0) wtab[WT_ROUND] = v4i{0, 0, 0, 0};
     if (FIRST) {  // the same tables for every workgroup: made once per call
         for (u32 e = threadIdx.x; e < WT_ROUND; e += blockDim.x) wtab[e] = A.wt[e];
-        for (u32 e = threadIdx.x; e < WT_FIRST; e += blockDim.x) wfirst[e] = A.wt[WT_ROUND + e];
+        if (!LAZY)
+            for (u32 e = threadIdx.x; e < WT_FIRST; e += blockDim.x) wfirst[e] = A.wt[WT_ROUND + e];
     } else {
         for (u32 e = threadIdx.x; e < WT_ROUND; e += blockDim.x) wtab[e] = wtab_entry(e, rw);
     }
@@ -645,11 +660,11 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
     // at most 32 per set boundary, are left for the sort to compare from the
     // start.)
     __shared__ u64 s_set[FIRST ? SEED_MAX_SETS + 1 : 1];
-    __shared__ u64 s_ref[FIRST ? SEED_MAX_SETS : 1][FIRST ? PRE_MAX / 2 : 1];
+    __shared__ __attribute__((aligned(16))) u64 s_ref[FIRST ? SEED_MAX_SETS : 1][FIRST ? PRE_MAX / 2 : 1];
     __shared__ u32 s_refl[FIRST ? SEED_MAX_SETS : 1];
     __shared__ u64 s_mw[FIRST ? 4 : 1][32];  // per wavefront and string: the 8 bytes at its record
     const bool seeding = FIRST && Fp->seed_pos != nullptr;  // uniform: seed records are written
-    const bool lazy = FIRST && Fp->lazy != 0;                // the rounds up to 64 bytes are left out
+    constexpr bool lazy = LAZY;                              // the rounds up to 64 bytes are left out
     const bool comparing = seeding || lazy;                  // the strings are compared with their references
     const u32 nsets = (FIRST && comparing && Fp->set_off) ? Fp->nsets : 1u;  // (<= SEED_MAX_SETS)
     if (FIRST) {
@@ -838,47 +853,78 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
         for (;;) {  // passes; uniform over the wavefront
             // this pass's operand bytes: [u][kb], 16 each (zero past the string)
             u64 lo[RP_STEPS][2], hi[RP_STEPS][2];
+            bool top;  // (uniform) some byte of the pass is >= 128
+            // vmcnt(0): this pass's copy has landed in the rows (the compiler
+            // waits only for loads into registers)
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            __asm__ volatile("" ::: "memory");  // (no row read moves above the wait)
             {
                 const u32 sh = (u32)((babs + o_c + xp) & 15);
                 const u32 need = m > xp ? ((m - xp < 64 * RP_STEPS ? m : xp + 64 * RP_STEPS) - xp) : 0u;
                 const u32 nch = need ? (sh + need + 15) / 16 : 0u;
                 const u64 A0 = (babs + o_c + xp) & ~15ull;
                 const bool edge = nch && (A0 < babs || A0 + 16ull * nch > babs + N);
+                if (__all(!edge && need == 64 * RP_STEPS)) {
+                    // every lane's pass is whole and in its rows
 #pragma unroll
-                for (int u = 0; u < RP_STEPS; u++)
+                    for (int u = 0; u < RP_STEPS; u++)
 #pragma unroll
-                    for (int kb = 0; kb < 2; kb++) {
-                        const u32 rel = 64 * u + 32 * kb + 16 * h;
-                        const u32 take = need > rel ? ((need - rel) < 16 ? need - rel : 16u) : 0u;
-                        lo[u][kb] = hi[u][kb] = 0;
-                        if (take) {
-                            if (!edge) lds_le16(R, RP_CH * 16 * col + sh + rel, lo[u][kb], hi[u][kb]);
-                            else load16_le(bytes, N, o_c + xp + rel, take, lo[u][kb], hi[u][kb]);
-                            if (take < 8) {
-                                lo[u][kb] &= (1ull << (8 * take)) - 1ull;
-                                hi[u][kb] = 0;
-                            } else if (take < 16) {
-                                hi[u][kb] &= take == 8 ? 0ull : ((1ull << (8 * (take - 8))) - 1ull);
-                            }
-                        }
-                    }
-                if (FIRST && comparing && runi) {
-                    // this lane's pieces against the reference's bytes at the same
-                    // positions (both zero past their ends; a difference at or
-                    // past the shorter end is discarded below)
+                        for (int kb = 0; kb < 2; kb++)
+                            lds_le16(R, RP_CH * 16 * col + sh + 64 * u + 32 * kb + 16 * h, lo[u][kb], hi[u][kb]);
+                } else {
 #pragma unroll
                     for (int u = 0; u < RP_STEPS; u++)
 #pragma unroll
                         for (int kb = 0; kb < 2; kb++) {
-                            const u32 pos = xp + 64 * u + 32 * kb + 16 * h;
-                            if (pos < 4 * PRE_MAX) {
-                                const u64 d0 = lo[u][kb] ^ s_ref[rsel][pos / 8];
-                                const u64 d1 = hi[u][kb] ^ s_ref[rsel][pos / 8 + 1];
-                                const u32 mp = d0 ? pos + (u32)(__builtin_ctzll(d0) >> 3)
-                                                  : (d1 ? pos + 8 + (u32)(__builtin_ctzll(d1) >> 3) : 0xFFFFFFFFu);
-                                smis = mp < smis ? mp : smis;
+                            const u32 rel = 64 * u + 32 * kb + 16 * h;
+                            const u32 take = need > rel ? ((need - rel) < 16 ? need - rel : 16u) : 0u;
+                            lo[u][kb] = hi[u][kb] = 0;
+                            if (take) {
+                                if (!edge) lds_le16(R, RP_CH * 16 * col + sh + rel, lo[u][kb], hi[u][kb]);
+                                else load16_le(bytes, N, o_c + xp + rel, take, lo[u][kb], hi[u][kb]);
+                                if (take < 8) {
+                                    lo[u][kb] &= (1ull << (8 * take)) - 1ull;
+                                    hi[u][kb] = 0;
+                                } else if (take < 16) {
+                                    hi[u][kb] &= take == 8 ? 0ull : ((1ull << (8 * (take - 8))) - 1ull);
+                                }
                             }
                         }
+                }
+                // bytes of 128 or more anywhere in the wavefront's pass: the
+                // products then take the low 7 bits and the top bit apart
+                {
+                    u64 hb = 0;
+#pragma unroll
+                    for (int u = 0; u < RP_STEPS; u++)
+#pragma unroll
+                        for (int kb = 0; kb < 2; kb++) hb |= lo[u][kb] | hi[u][kb];
+                    top = __ballot((hb & 0x8080808080808080ull) != 0) != 0;
+                }
+                if (FIRST && comparing && runi) {
+                    // this lane's pieces against the reference's bytes at the same
+                    // positions (both zero past their ends; a difference at or
+                    // past the shorter end is discarded below): the first
+                    // differing word, from the pieces in decreasing position
+                    u64 fw = 0;
+                    u32 fp = 0;
+#pragma unroll
+                    for (int u = RP_STEPS - 1; u >= 0; u--)
+#pragma unroll
+                        for (int kb = 1; kb >= 0; kb--) {
+                            const u32 pos = xp + 64 * u + 32 * kb + 16 * h;
+                            if (pos < 4 * PRE_MAX) {
+                                typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+                                const u64x2 rv = *(const u64x2 *)&s_ref[rsel][pos / 8];
+                                const u64 d0 = lo[u][kb] ^ rv.x, d1 = hi[u][kb] ^ rv.y;
+                                if (d1) { fw = d1; fp = pos + 8; }
+                                if (d0) { fw = d0; fp = pos; }
+                            }
+                        }
+                    if (fw) {
+                        const u32 mp = fp + (u32)(__builtin_ctzll(fw) >> 3);
+                        smis = mp < smis ? mp : smis;
+                    }
                     // The string's record position so far (its first mismatch,
                     // or the shorter end).  Passes go up in position, so once it
                     // lies in this pass it is final: its 8 bytes are taken from
@@ -938,19 +984,22 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                             l0 &= ~((1ull << (8 * skip)) - 1ull);
                         }
                     }
-                    const u64 l7 = 0x7F7F7F7F7F7F7F7Full, h1 = 0x0101010101010101ull;
-                    const u64 lo7 = l0 & l7, hi7 = h0 & l7, loh = (l0 >> 7) & h1, hih = (h0 >> 7) & h1;
-                    xl[kb] = v4i{(int)(u32)lo7, (int)(u32)(lo7 >> 32), (int)(u32)hi7, (int)(u32)(hi7 >> 32)};
-                    xh[kb] = v4i{(int)(u32)loh, (int)(u32)(loh >> 32), (int)(u32)hih, (int)(u32)(hih >> 32)};
-                    {
-                        // this lane's weight row for the block's 16 positions (lane half = 16-byte
-                        // half); rows of the l1 set are zero from l1 on (a two-round l1 is a
-                        // multiple of 64, so no block straddles it; single rounds do not use it)
-                        const v4i *wrow = wtab + ((sidx * 2 + kb) * 2 + h) * 9;
-                        const bool zero = rowl1 && x + 32 * kb >= L1;
-                        v4i wl = wrow[rowlo ? dr : 0], wh = wrow[rowhi ? dr - 1 : 0];
-                        if (!rowlo || zero) wl = v4i{0, 0, 0, 0};
-                        if (!rowhi || zero) wh = v4i{0, 0, 0, 0};
+                    // this lane's weight row for the block's 16 positions (lane half = 16-byte
+                    // half); rows of the l1 set are zero from l1 on (a two-round l1 is a
+                    // multiple of 64, so no block straddles it; single rounds do not use it)
+                    const u32 wb = ((sidx * 2 + kb) * 2 + h) * 9;
+                    const bool zero = rowl1 && x + 32 * kb >= L1;
+                    const v4i wl = wtab[(rowlo && !zero) ? wb + dr : (u32)WT_ROUND];
+                    if (!top && !fstep) {
+                        // every byte < 128: the bytes are their own low 7 bits, no top-bit product
+                        xl[kb] = v4i{(int)(u32)l0, (int)(u32)(l0 >> 32), (int)(u32)h0, (int)(u32)(h0 >> 32)};
+                        S = __builtin_amdgcn_mfma_i32_32x32x32_i8(wl, xl[kb], S, 0, 0, 0);
+                    } else {
+                        const u64 l7 = 0x7F7F7F7F7F7F7F7Full, h1 = 0x0101010101010101ull;
+                        const u64 lo7 = l0 & l7, hi7 = h0 & l7, loh = (l0 >> 7) & h1, hih = (h0 >> 7) & h1;
+                        xl[kb] = v4i{(int)(u32)lo7, (int)(u32)(lo7 >> 32), (int)(u32)hi7, (int)(u32)(hi7 >> 32)};
+                        xh[kb] = v4i{(int)(u32)loh, (int)(u32)(loh >> 32), (int)(u32)hih, (int)(u32)(hih >> 32)};
+                        const v4i wh = wtab[(rowhi && !zero) ? wb + dr - 1 : (u32)WT_ROUND];
                         S = __builtin_amdgcn_mfma_i32_32x32x32_i8(wl, xl[kb], S, 0, 0, 0);
                         S = __builtin_amdgcn_mfma_i32_32x32x32_i8(wh, xh[kb], S, 0, 0, 0);
                     }
@@ -1093,15 +1142,19 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
     }
     if constexpr (FIRST) {
         stage(HF_ACC);
+        if (!LAZY) {
 #pragma unroll
-        for (int a = 0; a < HF_ACC; a++) stage(a);
+            for (int a = 0; a < HF_ACC; a++) stage(a);
+        }
         __syncthreads();
         // rounds l1 (lane half 1) and l2 (half 0) as precomputed rounds c0, c0 + 1
         commit(HF_ACC, A.fl + 3 * (c0 + (h ? 0u : 1u)), true);
+        if (!LAZY) {  // (lazy: nothing was hashed for them)
 #pragma unroll
-        for (int a = 0; a < HF_ACC; a++) {
-            const u32 r = 2 * a + h;
-            commit(a, A.fl + 3 * r, r < c0);
+            for (int a = 0; a < HF_ACC; a++) {
+                const u32 r = 2 * a + h;
+                commit(a, A.fl + 3 * r, r < c0);
+            }
         }
     } else {  // A.rf[0..2] round l1, A.rf[3..5] round l2, per wavefront half
         const u32 b = fb >> (3 * HF_ACC);
@@ -1123,10 +1176,18 @@ __global__ __launch_bounds__(256, 3) void k_hash_first_deep(PassArgs A, RoundW r
     hash_pass<true>(A, rw, &F);
 }
 
+__global__ __launch_bounds__(256, 4) void k_hash_first_lazy(PassArgs A, RoundW rw, FirstArgs F)
+{
+    hash_pass<true, true>(A, rw, &F);
+}
+
 // ------------------------------------------------------------ duplicates
 //
-// Keys are < 2^61 (residues mod 2^61-1, possibly masked to fewer bits), so the
-// all-ones word marks an empty slot and bit 62 marks a key seen twice or more.
+// The all-ones word marks an empty slot.  The global table's slots hold a
+// key's low 32 bits and a list position (< 2^32 - 1, so never all ones); the
+// LDS tables of the bucket form hold keys, which are < 2^61 (residues mod
+// 2^61-1, possibly masked to fewer bits), with bit 62 marking a key seen twice
+// or more.
 
 #define TAB_EMPTY 0xFFFFFFFFFFFFFFFFull
 #define TAB_DUP (1ull << 62)
@@ -1168,28 +1229,38 @@ __global__ __launch_bounds__(256) void k_flags(const u64 *keys, int kin, const u
     }
 }
 
-// Insert every active key into the table (linear probing); a key found
-// already present gets the duplicate mark.  The table has at least twice as
-// many slots as keys, so every probe sequence ends.
+// Insert every active key into the table (linear probing).  A slot holds the
+// low 32 bits of a key and the list position of the entry that brought it
+// first; an entry that finds its key there (the low bits equal, and the key
+// at that position equal) marks itself and that entry as duplicates in dupf,
+// so that the finishing pass reads one byte per entry, in list order, instead
+// of probing the table again.  dupf is zero on entry.  The table has at least
+// twice as many slots as keys, so every probe sequence ends.
 __global__ __launch_bounds__(256) void k_tab_insert(const u64 *keys, int kin, const u32 *act, const u32 *cnt,
-                                                    u64 *tab, u32 logT)
+                                                    u64 *tab, u32 logT, u8 *dupf)
 {
     const u32 A = *cnt;
     const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= A) return;
     const u32 i = act ? act[j] : j;
     const u64 key = key_of(keys, kin, i, j);
+    const u64 low = key & 0xFFFFFFFFull;
+    const u64 mine = (low << 32) | j;  // (j < 2^32 - 1: never the empty word)
     const u64 mask = (1ull << logT) - 1ull;
     u64 s = tab_slot(key, logT);
     for (u64 probe = 0; probe <= mask; probe++, s = (s + 1) & mask) {
         u64 cur = __hip_atomic_load(&tab[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (cur == TAB_EMPTY) {
-            cur = atomicCAS((unsigned long long *)&tab[s], TAB_EMPTY, key);
+            cur = atomicCAS((unsigned long long *)&tab[s], TAB_EMPTY, mine);
             if (cur == TAB_EMPTY) return;  // inserted
         }
-        if ((cur & ~TAB_DUP) == key) {
-            if (!(cur & TAB_DUP)) atomicOr((unsigned long long *)&tab[s], TAB_DUP);
-            return;
+        if ((cur >> 32) == low) {
+            const u32 jo = (u32)cur;
+            if (key_of(keys, kin, act ? act[jo] : jo, jo) == key) {
+                dupf[j] = 1;
+                dupf[jo] = 1;
+                return;
+            }
         }
     }
 }
@@ -1339,9 +1410,8 @@ __global__ __launch_bounds__(DD_NT) void k_dd_bucket(const u32 *hm, u32 G, u32 N
 // (one atomic per workgroup; lists keep input order within a workgroup),
 // with their key for the next round when a two-round pass computed it.
 __global__ __launch_bounds__(256) void k_dedup(const u64 *keys, int kin, const u32 *act, const u32 *cnt,
-                                               const u64 *off, u64 l, int mode, const u64 *tab, u32 logT,
-                                               u32 *dist, u32 *next, u32 *ncnt, const u64 *carry, u64 *carry_out,
-                                               const u8 *dupf)
+                                               const u64 *off, u64 l, int mode, u32 *dist, u32 *next, u32 *ncnt,
+                                               const u64 *carry, u64 *carry_out, const u8 *dupf)
 {
     __shared__ u32 wcount[4], base;
     const u32 A = *cnt;
@@ -1351,22 +1421,7 @@ __global__ __launch_bounds__(256) void k_dedup(const u64 *keys, int kin, const u
     if (j < A) {
         i = act ? act[j] : j;
         const u64 len = off[i + 1] - off[i];
-        bool dup = mode == DM_ALLDUP;
-        if (mode == DM_TABLE && dupf) {
-            dup = dupf[j] != 0;
-        } else if (mode == DM_TABLE) {
-            const u64 key = key_of(keys, kin, i, j);
-            const u64 mask = (1ull << logT) - 1ull;
-            u64 s = tab_slot(key, logT);
-            for (u64 probe = 0; probe <= mask; probe++, s = (s + 1) & mask) {
-                const u64 v = tab[s];
-                if (v == TAB_EMPTY) break;  // not in the table (cannot happen for an inserted key)
-                if ((v & ~TAB_DUP) == key) {
-                    dup = (v & TAB_DUP) != 0;
-                    break;
-                }
-            }
-        }
+        const bool dup = mode == DM_ALLDUP || (mode == DM_TABLE && dupf[j] != 0);
         stay = dup && len > l;
         if (!stay) dist[i] = (u32)(len < l ? len : l);
     }
@@ -1404,6 +1459,7 @@ struct PdWs {
     u64 *hdr, *keys, *keysB, *keysC, *state, *pre, *tab;
     v4i *wt;
     u32 *ddh, *ddscr;  // bucketed duplicate detection: counts matrix and its scan scratch
+    u8 *dupt;          // table form: a duplicate mark per list position
 };
 #define CTR_DDERR 6  // ctr word: a bucket pass gave up (never in practice)
 
@@ -1483,6 +1539,7 @@ static void pd_layout(u64 n, PdWs *w, WsArena *a, WsCounter *c)
     PT(pre, u64, (u64)PRE_ALL * n); PT(tab, u64, 1ull << tab_log(n)); PT(wt, v4i, WT_ROUND + WT_FIRST);
     const u64 hm = dd_hm_cap(n) + 1;
     PT(ddh, u32, hm); PT(ddscr, u32, ss_scan_scratch_elems<u32>(hm));
+    PT(dupt, u8, n);
 #undef PT
     if (a) w->ctr = (u32 *)w->hdr;
 }
@@ -1650,9 +1707,14 @@ static int first_pass(const uint8_t *bytes, uint64_t N, const uint64_t *offsets,
         // more, shorter workgroups than the plain pass: beside the other
         // stream's kernels they give compute units back sooner
         const unsigned dblocks = (unsigned)(ceil_div(tiles, 4) < 8192 ? ceil_div(tiles, 4) : 8192);
-        SS_PROF("k_hash_first_deep", st,
-                (double)n * (4.0 * PRE_MAX) + (double)n * (8.0 + 8.0 * (lazy ? 2 : c0 + 2) + (seed ? 16.0 : 0.0)));
-        k_hash_first_deep<<<dblocks, 256, 0, st>>>(A, rwd, Fa);
+        const double dbytes = (double)n * (4.0 * PRE_MAX) + (double)n * (8.0 + 8.0 * (lazy ? 2 : c0 + 2) + (seed ? 16.0 : 0.0));
+        if (lazy) {
+            SS_PROF("k_hash_first_lazy", st, dbytes);
+            k_hash_first_lazy<<<dblocks, 256, 0, st>>>(A, rwd, Fa);
+        } else {
+            SS_PROF("k_hash_first_deep", st, dbytes);
+            k_hash_first_deep<<<dblocks, 256, 0, st>>>(A, rwd, Fa);
+        }
         SS_CHECK_LAUNCH();
         if (seed) {
             k_store_u32<<<1, 1, 0, st>>>((u32 *)seed, 1u);
@@ -1902,19 +1964,21 @@ static int pd_run(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uin
         } else if (mode == DM_TABLE) {
             logT = tab_log(Ah);
             SS_HIP(hipMemsetAsync(w.tab, 0xFF, sizeof(u64) << logT, st));
+            SS_HIP(hipMemsetAsync(w.dupt, 0, Ah, st));
             {
                 SS_PROF("k_tab_insert", st, (double)Ah * 28.0);  // list entry, key, slot read + write
-                k_tab_insert<<<(unsigned)ceil_div(Ah, 256), 256, 0, st>>>(keys, kin, act, ctr + ci, w.tab, logT);
+                k_tab_insert<<<(unsigned)ceil_div(Ah, 256), 256, 0, st>>>(keys, kin, act, ctr + ci, w.tab, logT,
+                                                                          w.dupt);
             }
             SS_CHECK_LAUNCH();
+            dupf = w.dupt;
         }
         SS_HIP(hipMemsetAsync(ctr + (ci ^ 1), 0, sizeof(u32), st));
         {
             // list entry, offsets, key, slot, dist or next entry (and a carried key)
-            SS_PROF("k_dedup", st,
-                    (double)Ah * ((mode == DM_TABLE ? (dupf ? 25.0 : 40.0) : 24.0) + (pend_next ? 16.0 : 0.0)));
-            k_dedup<<<(unsigned)ceil_div(Ah, 256), 256, 0, st>>>(keys, kin, act, ctr + ci, offsets, l, mode, w.tab,
-                                                                 logT, dist_approx, nxt, ctr + (ci ^ 1), pend_next,
+            SS_PROF("k_dedup", st, (double)Ah * ((mode == DM_TABLE ? 25.0 : 24.0) + (pend_next ? 16.0 : 0.0)));
+            k_dedup<<<(unsigned)ceil_div(Ah, 256), 256, 0, st>>>(keys, kin, act, ctr + ci, offsets, l, mode,
+                                                                 dist_approx, nxt, ctr + (ci ^ 1), pend_next,
                                                                  w.keysC, dupf);
         }
         SS_CHECK_LAUNCH();
