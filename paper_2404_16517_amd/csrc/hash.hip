@@ -249,9 +249,6 @@ __device__ __forceinline__ u64 kr_pow(u64 L, const RoundW &rw)
 }
 
 #define RW_STEPS 16  // 64-byte steps per 1024-byte chunk
-#define RP_STEPS 2   // 64-byte steps per pass
-#define RP_CH 9      // 16-byte chunks per string and pass (128 bytes at any alignment)
-#define RP_ROW 5120  // LDS bytes per wavefront: five 1 KiB copy rows (32 x 9 chunks)
 
 typedef int v16i __attribute__((ext_vector_type(16)));
 typedef __attribute__((address_space(3))) void lds_void_h;
@@ -609,9 +606,9 @@ __global__ __launch_bounds__(256) void k_hash_weights(RoundW rw, FirstArgs F, v4
     else if (e < WT_ROUND + WT_FIRST) wt[e] = wfirst_entry(e - WT_ROUND, s_ib, s_l, c0);
 }
 
-// One pass = RP_STEPS steps of a tile's 32 strings.  Before its products are
+// One pass = PS steps of a tile's 32 strings.  Before its products are
 // taken, every string's bytes of the pass are copied into the wavefront's LDS
-// rows by the transfer unit (chunk c of string s at 16 (RP_CH s + c), from
+// rows by the transfer unit (chunk c of string s at 16 (CH s + c), from
 // the string's 16-aligned pass start), so that each copy instruction reads
 // long runs of one string; the lanes then read their MFMA operands from LDS.
 // The copy of the next pass is issued before the current pass's products.
@@ -633,17 +630,22 @@ __global__ __launch_bounds__(256) void k_hash_weights(RoundW rw, FirstArgs F, v4
 // string).  Without the first step's products and their weight table the
 // kernel needs fewer registers and less LDS, and more workgroups fit on a
 // compute unit.
-template <bool FIRST, bool LAZY = false>
+//
+// NW wavefronts per workgroup (they share the weight tables), PS 64-byte
+// steps per pass: CH 16-byte chunks per string cover a pass at any alignment.
+template <bool FIRST, bool LAZY = false, int NW = 4, int PS = 2>
 __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, const FirstArgs *Fp)
 {
     static_assert(FIRST || !LAZY, "only the deep first pass leaves rounds out");
+    constexpr int CH = 4 * PS + 1;
+    constexpr int ROW = 512 * CH + 64;  // LDS bytes of a wavefront's rows (32 strings; a read may run 4 past)
     // round weights: [step of the chunk][32-byte block][16-byte half][digit]
     __shared__ v4i wtab[WT_ROUND + 1];  // (and a zero entry, for rows left out)
     // first-pass weights: [accumulator][32-byte block][low/high product][lane]
     __shared__ v4i wfirst[(FIRST && !LAZY) ? WT_FIRST : 1];
-    __shared__ __attribute__((aligned(16))) u8 rows[4 * RP_ROW];
-    __shared__ u64 pwa[4][32];  // per wavefront: pass start (16-aligned, relative) of each string
-    __shared__ u32 pwn[4][32];  // ... and its chunk count (0: not copied)
+    __shared__ __attribute__((aligned(16))) u8 rows[NW * ROW];
+    __shared__ u64 pwa[NW][32];  // per wavefront: pass start (16-aligned, relative) of each string
+    __shared__ u32 pwn[NW][32];  // ... and its chunk count (0: not copied)
     __shared__ u64 s_l[PRE_SLOTS];
     if (threadIdx.x == 0) wtab[WT_ROUND] = v4i{0, 0, 0, 0};
     if (FIRST) {  // the same tables for every workgroup: made once per call
@@ -662,7 +664,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
     __shared__ u64 s_set[FIRST ? SEED_MAX_SETS + 1 : 1];
     __shared__ __attribute__((aligned(16))) u64 s_ref[FIRST ? SEED_MAX_SETS : 1][FIRST ? PRE_MAX / 2 : 1];
     __shared__ u32 s_refl[FIRST ? SEED_MAX_SETS : 1];
-    __shared__ u64 s_mw[FIRST ? 4 : 1][32];  // per wavefront and string: the 8 bytes at its record
+    __shared__ u64 s_mw[FIRST ? NW : 1][32];  // per wavefront and string: the 8 bytes at its record
     const bool seeding = FIRST && Fp->seed_pos != nullptr;  // uniform: seed records are written
     constexpr bool lazy = LAZY;                              // the rounds up to 64 bytes are left out
     const bool comparing = seeding || lazy;                  // the strings are compared with their references
@@ -694,7 +696,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
     }
     __syncthreads();
     const u32 lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5, wv = threadIdx.x >> 6;
-    u8 *R = rows + wv * RP_ROW;
+    u8 *R = rows + wv * ROW;
     const u64 babs = (u64)(uintptr_t)A.bytes;
     const u8 *bytes = A.bytes;
     const u64 N = A.N;
@@ -736,8 +738,8 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
     // deep first pass each wavefront half's go to LDS and the workgroup's are
     // committed once per lane half (the few global words take 4x fewer
     // atomics); round passes commit per wavefront half.
-    __shared__ u64 s_fmn[FIRST ? HF_ACC + 1 : 1][4][2], s_fmx[FIRST ? HF_ACC + 1 : 1][4][2];
-    __shared__ u32 s_fsh[FIRST ? HF_ACC + 1 : 1][4][2];
+    __shared__ u64 s_fmn[FIRST ? HF_ACC + 1 : 1][NW][2], s_fmx[FIRST ? HF_ACC + 1 : 1][NW][2];
+    __shared__ u32 s_fsh[FIRST ? HF_ACC + 1 : 1][NW][2];
     auto stage = [&](int slot) {
         const u32 b = fb >> (3 * slot);
         u64 mn = (b & 1) ? ((b & 2) ? 0ull : fk[slot]) : ~0ull;
@@ -754,7 +756,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
         if (wv == 0 && col == 0 && doit) {
             u64 mn = ~0ull, mx = 0, sh = 0;
 #pragma unroll
-            for (int w = 0; w < 4; w++) {
+            for (int w = 0; w < NW; w++) {
                 const u64 a = s_fmn[slot][w][h], b = s_fmx[slot][w][h];
                 mn = a < mn ? a : mn;
                 mx = b > mx ? b : mx;
@@ -786,21 +788,21 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
     auto issue_copy = [&](u64 o, u32 m, u32 xp) {
         const u64 A0 = (babs + o + xp) & ~15ull;
         const u32 sh = (u32)((babs + o + xp) & 15);
-        const u32 need = m > xp ? ((m - xp < 64 * RP_STEPS ? m : xp + 64 * RP_STEPS) - xp) : 0u;
+        const u32 need = m > xp ? ((m - xp < 64 * PS ? m : xp + 64 * PS) - xp) : 0u;
         const u32 nch = need ? (sh + need + 15) / 16 : 0u;
         const bool edge = nch && (A0 < babs || A0 + 16ull * nch > babs + N);
         if (h == 0) {  // (read back below by the same wavefront: LDS keeps its order)
             pwa[wv][col] = A0 - babs;
             pwn[wv][col] = edge ? 0u : nch;
         }
-        constexpr int T = (32 * RP_CH + 63) / 64;
+        constexpr int T = (32 * CH + 63) / 64;
         u64 ad[T];
         bool ok[T];
 #pragma unroll
         for (int t = 0; t < T; t++) {  // every address first: the copies then issue back to back
             u32 slot = 64 * t + lane;
             asm volatile("" : "+v"(slot));  // recomputed per pass rather than held in registers
-            const u32 sx = slot / RP_CH, c = slot % RP_CH;
+            const u32 sx = slot / CH, c = slot % CH;
             ad[t] = pwa[wv][sx & 31] + 16u * c;
             ok[t] = sx < 32 && c < pwn[wv][sx & 31];
         }
@@ -852,7 +854,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
         issue_copy(o_c, m, xp);
         for (;;) {  // passes; uniform over the wavefront
             // this pass's operand bytes: [u][kb], 16 each (zero past the string)
-            u64 lo[RP_STEPS][2], hi[RP_STEPS][2];
+            u64 lo[PS][2], hi[PS][2];
             bool top;  // (uniform) some byte of the pass is >= 128
             // vmcnt(0): this pass's copy has landed in the rows (the compiler
             // waits only for loads into registers)
@@ -860,27 +862,27 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
             __asm__ volatile("" ::: "memory");  // (no row read moves above the wait)
             {
                 const u32 sh = (u32)((babs + o_c + xp) & 15);
-                const u32 need = m > xp ? ((m - xp < 64 * RP_STEPS ? m : xp + 64 * RP_STEPS) - xp) : 0u;
+                const u32 need = m > xp ? ((m - xp < 64 * PS ? m : xp + 64 * PS) - xp) : 0u;
                 const u32 nch = need ? (sh + need + 15) / 16 : 0u;
                 const u64 A0 = (babs + o_c + xp) & ~15ull;
                 const bool edge = nch && (A0 < babs || A0 + 16ull * nch > babs + N);
-                if (__all(!edge && need == 64 * RP_STEPS)) {
+                if (__all(!edge && need == 64 * PS)) {
                     // every lane's pass is whole and in its rows
 #pragma unroll
-                    for (int u = 0; u < RP_STEPS; u++)
+                    for (int u = 0; u < PS; u++)
 #pragma unroll
                         for (int kb = 0; kb < 2; kb++)
-                            lds_le16(R, RP_CH * 16 * col + sh + 64 * u + 32 * kb + 16 * h, lo[u][kb], hi[u][kb]);
+                            lds_le16(R, CH * 16 * col + sh + 64 * u + 32 * kb + 16 * h, lo[u][kb], hi[u][kb]);
                 } else {
 #pragma unroll
-                    for (int u = 0; u < RP_STEPS; u++)
+                    for (int u = 0; u < PS; u++)
 #pragma unroll
                         for (int kb = 0; kb < 2; kb++) {
                             const u32 rel = 64 * u + 32 * kb + 16 * h;
                             const u32 take = need > rel ? ((need - rel) < 16 ? need - rel : 16u) : 0u;
                             lo[u][kb] = hi[u][kb] = 0;
                             if (take) {
-                                if (!edge) lds_le16(R, RP_CH * 16 * col + sh + rel, lo[u][kb], hi[u][kb]);
+                                if (!edge) lds_le16(R, CH * 16 * col + sh + rel, lo[u][kb], hi[u][kb]);
                                 else load16_le(bytes, N, o_c + xp + rel, take, lo[u][kb], hi[u][kb]);
                                 if (take < 8) {
                                     lo[u][kb] &= (1ull << (8 * take)) - 1ull;
@@ -896,7 +898,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                 {
                     u64 hb = 0;
 #pragma unroll
-                    for (int u = 0; u < RP_STEPS; u++)
+                    for (int u = 0; u < PS; u++)
 #pragma unroll
                         for (int kb = 0; kb < 2; kb++) hb |= lo[u][kb] | hi[u][kb];
                     top = __ballot((hb & 0x8080808080808080ull) != 0) != 0;
@@ -909,7 +911,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                     u64 fw = 0;
                     u32 fp = 0;
 #pragma unroll
-                    for (int u = RP_STEPS - 1; u >= 0; u--)
+                    for (int u = PS - 1; u >= 0; u--)
 #pragma unroll
                         for (int kb = 1; kb >= 0; kb--) {
                             const u32 pos = xp + 64 * u + 32 * kb + 16 * h;
@@ -935,14 +937,14 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                     const u32 rfl = s_refl[rsel];
                     const u32 E = len < rfl ? len : rfl;
                     const u32 rc = sm < E ? sm : E;
-                    if (seeding && !h && rc >= xp && rc < xp + 64 * RP_STEPS) {
+                    if (seeding && !h && rc >= xp && rc < xp + 64 * PS) {
                         const u32 tk = len - rc < 8 ? len - rc : 8u;
                         if (tk == 0) {
                             s_mw[wv][col] = 0;
                             mwgot = true;
                         } else if (!edge && nch && rc + tk <= xp + 16 * nch - sh) {
                             u64 w0, w1;
-                            lds_le16(R, RP_CH * 16 * col + sh + (rc - xp), w0, w1);
+                            lds_le16(R, CH * 16 * col + sh + (rc - xp), w0, w1);
                             s_mw[wv][col] = __builtin_bswap64(tk < 8 ? (w0 & ((1ull << (8 * tk)) - 1ull)) : w0);
                             mwgot = true;
                         }
@@ -951,11 +953,11 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
             }
             __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the rows are read before the next copy
             // the next pass: the rest of this tile, or the next tile's first
-            const bool tile_end = xp + 64 * RP_STEPS >= xmax;
+            const bool tile_end = xp + 64 * PS >= xmax;
             u32 m_n = 0, xmax_n = 0;
             bool valid_n = false;
             if (!tile_end) {
-                issue_copy(o_c, m, xp + 64 * RP_STEPS);
+                issue_copy(o_c, m, xp + 64 * PS);
             } else if (more) {
                 valid_n = (tile + nwaves) * 32 + col < Acnt;
                 if (!valid_n) len_n = 0;
@@ -965,7 +967,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
             }
             // this pass's products
 #pragma unroll
-            for (int u = 0; u < RP_STEPS; u++) {
+            for (int u = 0; u < PS; u++) {
                 const u32 x = xp + 64 * u;
                 const bool fstep = FIRST && x == 0 && !lazy;  // the first pass's rounds (taken even for empty strings)
                 if (x >= xmax && !fstep) break;      // uniform over the wavefront
@@ -1037,7 +1039,7 @@ __device__ __forceinline__ void hash_pass(const PassArgs &A, const RoundW &rw, c
                 }
             }
             if (!tile_end) {
-                xp += 64 * RP_STEPS;
+                xp += 64 * PS;
                 continue;
             }
             // sort seed: the string's first mismatch with its reference over

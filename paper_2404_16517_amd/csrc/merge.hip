@@ -941,6 +941,7 @@ __device__ __forceinline__ MOp mop_shfl(MOp a, u32 src)
 struct MScan {
     const u64 *run_begin, *P;
     const u32 *run_group, *Cg;
+    const u32 *bfirst;  // run of every scan block's first element
     u32 k, n_out;
     FcView V;
 };
@@ -970,31 +971,6 @@ __device__ __forceinline__ void run_seek(const MScan &S, RunCur &c, u64 x)
     }
 }
 
-// The operator of output position x (in run c); its low byte carries the
-// element's length count min(d_g - C, 8), so that the inclusive operator at x
-// is the element's cached key.  *g_out, *e_out: its entry and LCP.
-__device__ __forceinline__ MOp mop_of(const MScan &S, const RunCur &c, u64 x, u32 *g_out, u32 *e_out)
-{
-    const bool start = x == c.pr;
-    const u32 g = (u32)(c.rb + (x - c.pr));
-    const u32 e = start ? 0u : S.V.e[g];
-    const u32 d = S.V.d[g];
-    const u32 C = c.C;
-    *g_out = g;
-    *e_out = e;
-    const u32 cnt = d > C ? (d - C < 8 ? d - C : 8u) : 0u;
-    MOp o;
-    const u32 p = e > C ? (e - C < 7 ? e - C : 7u) : 0u;
-    o.rp = (start ? 8u : 0u) | p;
-    o.m = start ? 0xFFFFFFFFu : e;
-    o.v = cnt;
-    const u32 from = C + p;  // first window byte the entry's literal supplies (>= e)
-    const u32 to = d < C + 7 ? d : C + 7;
-    if (p < 7 && to > from)
-        o.v |= load_be(S.V.suf, S.V.sufN, S.V.suf_off[g] + (from - e), to - from) >> (8 * p);
-    return o;
-}
-
 __device__ __forceinline__ u32 run_of(const u64 *P, u32 k, u64 x)
 {
     u32 lo = 0, hi = k;  // largest j with P[j] <= x
@@ -1011,30 +987,72 @@ __device__ __forceinline__ u32 run_of(const u64 *P, u32 k, u64 x)
 #define MS_PER 7
 #define MS_ITEMS (256 * MS_PER)  // elements per workgroup
 
-// The workgroup's operators in LDS, read with consecutive lanes on consecutive
-// elements; returns this thread's composite of its MS_PER consecutive ones.
-__device__ __forceinline__ MOp mscan_stage(const MScan &S, u64 x0, MOp *ops)
+// This thread's elements x = x0 + 256 q + threadIdx.x (q < MS_PER; lanes on
+// consecutive elements): entry g, run depth C and the in-range / run-start
+// bits, from the block's first run and the cursor, which moves only at run
+// bounds -- before any load of the elements' data is issued.
+struct MElems {
+    u32 g[MS_PER], C[MS_PER];
+    u32 in, start;  // bit q
+};
+
+__device__ __forceinline__ void mscan_locate(const MScan &S, u64 x0, MElems &E)
 {
-    __shared__ u32 rfirst;
-    if (threadIdx.x == 0) rfirst = x0 < S.n_out ? run_of(S.P, S.k, x0) : 0u;
-    __syncthreads();
-    RunCur c = run_cur(S, rfirst);
+    RunCur c = run_cur(S, S.bfirst[blockIdx.x]);
+    E.in = E.start = 0;
+#pragma unroll
     for (u32 q = 0; q < MS_PER; q++) {
-        const u32 i = q * 256 + threadIdx.x;
-        const u64 x = x0 + i;
-        MOp o = mop_id();
+        const u64 x = x0 + q * 256 + threadIdx.x;
+        E.g[q] = 0;  // (a valid entry to load from: the workgroup has elements)
+        E.C[q] = 0;
         if (x < S.n_out) {
             run_seek(S, c, x);
-            u32 g, e;
-            o = mop_of(S, c, x, &g, &e);
+            E.g[q] = (u32)(c.rb + (x - c.pr));
+            E.C[q] = c.C;
+            E.in |= 1u << q;
+            if (x == c.pr) E.start |= 1u << q;
         }
-        ops[i] = o;
     }
-    __syncthreads();
-    MOp t = mop_id();
+}
+
+// The operators of this thread's elements (identity out of range) and their
+// LCPs e[q]: the entries' LCPs, lengths and literal offsets are loaded for all
+// elements first, then every element's window bytes, then combined.  An
+// operator's low byte carries the element's length count min(d - C, 8), so
+// that the inclusive operator at x is the element's cached key.
+__device__ __forceinline__ void mscan_ops(const MScan &S, const MElems &E, MOp *o, u32 *e)
+{
+    u32 d[MS_PER];
+    u64 so[MS_PER];
 #pragma unroll
-    for (u32 q = 0; q < MS_PER; q++) t = mop_cat(t, ops[threadIdx.x * MS_PER + q]);
-    return t;
+    for (u32 q = 0; q < MS_PER; q++) {
+        e[q] = S.V.e[E.g[q]];
+        d[q] = S.V.d[E.g[q]];
+        so[q] = S.V.suf_off[E.g[q]];
+    }
+    u32 p[MS_PER];
+    Raw8 lit[MS_PER];
+#pragma unroll
+    for (u32 q = 0; q < MS_PER; q++) {
+        if ((E.start >> q) & 1) e[q] = 0;
+        const u32 C = E.C[q];
+        p[q] = e[q] > C ? (e[q] - C < 7 ? e[q] - C : 7u) : 0u;
+        const u32 from = C + p[q];  // first window byte the entry's literal supplies (>= e)
+        const u32 to = d[q] < C + 7 ? d[q] : C + 7;
+        const bool want = ((E.in >> q) & 1) && p[q] < 7 && to > from;
+        lit[q] = raw8_issue(S.V.suf, S.V.sufN, want ? so[q] + (from - e[q]) : 0ull, want ? to - from : 0u);
+    }
+#pragma unroll
+    for (u32 q = 0; q < MS_PER; q++) {
+        const bool st = (E.start >> q) & 1;
+        const u32 C = E.C[q];
+        MOp r;
+        r.rp = (st ? 8u : 0u) | p[q];
+        r.m = st ? 0xFFFFFFFFu : e[q];
+        r.v = (d[q] > C ? (d[q] - C < 8 ? d[q] - C : 8u) : 0u) |
+              (__builtin_bswap64(raw8_le(S.V.suf, lit[q])) >> (8 * p[q]));
+        o[q] = ((E.in >> q) & 1) ? r : mop_id();
+    }
 }
 
 // Ordered reduction / exclusive scan of one operator per thread over a
@@ -1076,6 +1094,17 @@ __device__ __forceinline__ MOp block_mop_exclusive(MOp a, MOp carry)
     return mop_cat(pre, ex);
 }
 
+// The run of every scan block's first element (the run r with P[r] <= x <
+// P[r+1], x = j MS_ITEMS): each non-empty run writes it for the blocks that
+// start inside it.
+__global__ void k_block_runs(const u64 *P, u32 k, u32 nb, u32 *bfirst)
+{
+    const u32 r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= k) return;
+    const u64 a = P[r], b = P[r + 1];
+    for (u64 j = (a + MS_ITEMS - 1) / MS_ITEMS; j * MS_ITEMS < b && j < nb; j++) bfirst[j] = r;
+}
+
 // Phase 1: the operator of every MS_ITEMS-element block.  Its reset, p and m
 // parts need only each element's e and d.  Of its window, byte k (k < 7) is
 // the one written by the block's last element with p <= k (a later element
@@ -1083,59 +1112,70 @@ __device__ __forceinline__ MOp block_mop_exclusive(MOp a, MOp carry)
 // most eight literal bytes are read per block instead of every element's.
 __global__ __launch_bounds__(256) void k_mscan_reduce(MScan S, MOp *blk)
 {
-    __shared__ u32 rfirst;
     __shared__ u32 s_last[8];  // per window byte k < 7, and the count (7): last supplier + 1, block-relative
+    __shared__ u32 s_rp[MS_ITEMS], s_m[MS_ITEMS];
     const u64 x0 = (u64)blockIdx.x * MS_ITEMS;
-    if (threadIdx.x == 0) rfirst = x0 < S.n_out ? run_of(S.P, S.k, x0) : 0u;
     if (threadIdx.x < 8) s_last[threadIdx.x] = 0;
-    __syncthreads();
-    RunCur c = run_cur(S, rfirst);
-    MOp t = mop_id();
-    u32 lastk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const u64 xb = x0 + (u64)threadIdx.x * MS_PER;  // this thread's MS_PER consecutive elements
+    MElems E;
+    mscan_locate(S, x0, E);
+    u32 e[MS_PER];
+#pragma unroll
+    for (u32 q = 0; q < MS_PER; q++) e[q] = S.V.e[E.g[q]];
 #pragma unroll
     for (u32 q = 0; q < MS_PER; q++) {
-        const u64 x = xb + q;
-        if (x >= S.n_out) break;
-        run_seek(S, c, x);
-        const bool start = x == c.pr;
-        const u32 g = (u32)(c.rb + (x - c.pr));
-        const u32 e = start ? 0u : S.V.e[g];
-        const u32 p = e > c.C ? (e - c.C < 7 ? e - c.C : 7u) : 0u;
+        const u32 i = q * 256 + threadIdx.x;
+        const bool st = (E.start >> q) & 1;
+        const u32 ee = st ? 0u : e[q], C = E.C[q];
+        const u32 p = ee > C ? (ee - C < 7 ? ee - C : 7u) : 0u;
+        s_rp[i] = ((E.in >> q) & 1) ? ((st ? 8u : 0u) | p) : 0xFFu;  // (0xFF: out of range)
+        s_m[i] = st ? 0xFFFFFFFFu : ee;
+    }
+    __syncthreads();
+    // this thread's MS_PER consecutive elements, in order
+    MOp t = mop_id();
+    u32 lastk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (u32 q = 0; q < MS_PER; q++) {
+        const u32 i = threadIdx.x * MS_PER + q;
+        const u32 rp = s_rp[i];
+        if (rp == 0xFFu) break;  // (out of range from here on)
         MOp o;
-        o.rp = (start ? 8u : 0u) | p;
-        o.m = start ? 0xFFFFFFFFu : e;
+        o.rp = rp;
+        o.m = s_m[i];
         o.v = 0;
         t = mop_cat(t, o);
-        const u32 idx = threadIdx.x * MS_PER + q + 1;
+        const u32 p = rp & 7u;
 #pragma unroll
         for (u32 k = 0; k < 7; k++)
-            if (p <= k) lastk[k] = idx;
-        lastk[7] = idx;
+            if (p <= k) lastk[k] = i + 1;
+        lastk[7] = i + 1;
     }
 #pragma unroll
     for (u32 k = 0; k < 8; k++)
         if (lastk[k]) atomicMax(&s_last[k], lastk[k]);
-    t = block_mop_reduce(t);  // (reset, p, m); its window is filled below
+    t = block_mop_reduce(t);  // (reset, p, m); its window is filled below (its barriers complete s_last)
     __shared__ u64 s_v[8];
-    if (threadIdx.x < 8) {
-        const u32 k = threadIdx.x, j = s_last[k];
-        u64 b = 0;
-        if (j) {
-            const u64 x = x0 + j - 1;
-            const RunCur cj = run_cur(S, run_of(S.P, S.k, x));
-            const bool start = x == cj.pr;
-            const u32 g = (u32)(cj.rb + (x - cj.pr));
-            const u32 e = start ? 0u : S.V.e[g];
+    if (threadIdx.x < 8) s_v[threadIdx.x] = 0;
+    __syncthreads();
+    // byte k comes from element s_last[k] - 1; the thread holding that
+    // element's entry loads it
+#pragma unroll
+    for (u32 q = 0; q < MS_PER; q++) {
+        const u32 j = q * 256 + threadIdx.x + 1;
+        u32 ks = 0;
+#pragma unroll
+        for (u32 k = 0; k < 8; k++)
+            if (s_last[k] == j) ks |= 1u << k;
+        if (ks) {
+            const u32 g = E.g[q], C = E.C[q];
+            const u32 ee = ((E.start >> q) & 1) ? 0u : e[q];
             const u32 d = S.V.d[g];
-            const u32 C = cj.C;
-            if (k == 7) {
-                b = d > C ? (d - C < 8 ? d - C : 8u) : 0u;  // the count byte
-            } else if (C + k < d) {  // byte at position C + k of the string (its literal starts at e <= C + k)
-                b = (u64)S.V.suf[S.V.suf_off[g] + (C + k - e)] << (8 * (7 - k));
-            }
+            const u64 so = S.V.suf_off[g];
+            if (ks & 0x80u) s_v[7] = d > C ? (d - C < 8 ? d - C : 8u) : 0u;  // the count byte
+#pragma unroll
+            for (u32 k = 0; k < 7; k++)  // byte at position C + k of the string (its literal starts at e <= C + k)
+                if (((ks >> k) & 1) && C + k < d) s_v[k] = (u64)S.V.suf[so + (C + k - ee)] << (8 * (7 - k));
         }
-        s_v[k] = b;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1180,11 +1220,21 @@ __global__ __launch_bounds__(1024) void k_mscan_top(MOp *blk, u32 nb)
 
 // Phase 3: every element's inclusive operator -> G, L, F, K (written with
 // consecutive lanes on consecutive elements).
-__global__ __launch_bounds__(256) void k_mscan_apply(MScan S, const MOp *blk, u32 *G, u32 *L, u32 *F, u64 *K)
+__global__ __launch_bounds__(256, 5) void k_mscan_apply(MScan S, const MOp *blk, u32 *G, u32 *L, u32 *F, u64 *K)
 {
     __shared__ MOp ops[MS_ITEMS];
     const u64 x0 = (u64)blockIdx.x * MS_ITEMS;
-    const MOp t = mscan_stage(S, x0, ops);
+    MElems E;
+    mscan_locate(S, x0, E);
+    MOp o[MS_PER];
+    u32 e[MS_PER];
+    mscan_ops(S, E, o, e);
+#pragma unroll
+    for (u32 q = 0; q < MS_PER; q++) ops[q * 256 + threadIdx.x] = o[q];
+    __syncthreads();
+    MOp t = mop_id();
+#pragma unroll
+    for (u32 q = 0; q < MS_PER; q++) t = mop_cat(t, ops[threadIdx.x * MS_PER + q]);
     MOp st = block_mop_exclusive(t, blk[blockIdx.x]);
 #pragma unroll
     for (u32 q = 0; q < MS_PER; q++) {
@@ -1194,16 +1244,13 @@ __global__ __launch_bounds__(256) void k_mscan_apply(MScan S, const MOp *blk, u3
         ops[i].v = st.v;
     }
     __syncthreads();
-    RunCur c = run_cur(S, x0 < S.n_out ? run_of(S.P, S.k, x0) : 0u);
+#pragma unroll
     for (u32 q = 0; q < MS_PER; q++) {
         const u32 i = q * 256 + threadIdx.x;
         const u64 x = x0 + i;
-        if (x >= S.n_out) break;
-        run_seek(S, c, x);
-        const bool start = x == c.pr;
-        const u32 g = (u32)(c.rb + (x - c.pr));
-        G[x] = g;
-        L[x] = start ? 0u : S.V.e[g];
+        if (!((E.in >> q) & 1)) break;
+        G[x] = E.g[q];
+        L[x] = e[q];
         F[x] = ops[i].m;
         K[x] = ops[i].v;
     }
@@ -1264,7 +1311,7 @@ __global__ __launch_bounds__(256) void k_check_merge_runs(const u64 *rb, const u
 
 struct MergeWs {
     DecWs dec;
-    u32 *G0, *G1, *L0, *L1, *F0, *F1, *pc, *tstart, *sid, *pg, *Cg, *rgroup, *rep, *split, *runmin;
+    u32 *G0, *G1, *L0, *L1, *F0, *F1, *pc, *tstart, *sid, *pg, *Cg, *rgroup, *rep, *split, *runmin, *bfirst;
     MOp *mblk;
     u8 *pfirst;
     u64 *PA0, *PA1, *PB1, *P, *sb, *K0, *K1;
@@ -1291,7 +1338,7 @@ static void merge_layout(u64 n_out, u64 n_fc, u64 k, MergeWs *w, WsArena *a, WsC
     MT(pg, u32, MERGE_PCAP(k)); MT(tstart, u32, MERGE_PCAP(k) + 64);
     MT(Cg, u32, k + 2); MT(pc, u32, MERGE_PCAP(k)); MT(pfirst, u8, MERGE_PCAP(k));
     MT(split, u32, n_out / MW_TILE + MERGE_PCAP(k) + 64);  // tiles of one level
-    MT(runmin, u32, k + 2); MT(mblk, MOp, n_out / MS_ITEMS + 2);
+    MT(runmin, u32, k + 2); MT(mblk, MOp, n_out / MS_ITEMS + 2); MT(bfirst, u32, n_out / MS_ITEMS + 2);
 #undef MT
 }
 
@@ -1487,8 +1534,10 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
     {
         // front-coded LCP, length, literal offset and up to 7 literal bytes in (twice), state out
         SS_PROF("k_mscan", st, (double)n_out * (2.0 * 24.0 + 20.0));
-        const MScan S{run_begin, w.P, w.rgroup, w.Cg, k, (u32)n_out, V};
+        const MScan S{run_begin, w.P, w.rgroup, w.Cg, w.bfirst, k, (u32)n_out, V};
         const u32 nb = (u32)ceil_div(n_out, MS_ITEMS);
+        k_block_runs<<<(unsigned)ceil_div(k, 256), 256, 0, st>>>(w.P, k, nb, w.bfirst);
+        SS_CHECK_LAUNCH();
         k_mscan_reduce<<<nb, 256, 0, st>>>(S, w.mblk);
         SS_CHECK_LAUNCH();
         k_mscan_top<<<1, 1024, 0, st>>>(w.mblk, nb);
