@@ -546,45 +546,55 @@ struct FcView {
     u64 sufN;
 };
 
-__device__ __forceinline__ u64 fc_load_be(const FcView &V, u32 g, u64 k, u32 take)
+// The literal piece of front-coded string g that holds byte k (< d_g): the
+// offset in suf of byte k, and how many of the string's bytes from k on lie
+// in that literal (the chain element whose e is the first <= k, walking the
+// psv chain from g; its literal covers bytes [e_j, e of the element after it
+// toward g), or [e_g, d_g) for g itself).
+__device__ __forceinline__ void fc_piece(const FcView &V, u32 g, u64 k, u64 *pos, u64 *avail)
 {
-    u64 v = 0;
-    u32 got = 0;
-    while (got < take) {
-        const u64 kk = k + got;
-        u32 j = g;
-        u64 h = V.d[g];
-        u32 ej = V.e[j];
-        while (ej > kk) {
-            h = ej;
-            j = V.psv[j];
-            ej = V.e[j];
-        }
-        const u64 av = h - kk;
-        const u32 part = (u32)(av < (u64)(take - got) ? av : (u64)(take - got));
-        v |= load_be(V.suf, V.sufN, V.suf_off[j] + (kk - ej), part) >> (8 * got);
-        got += part;
+    u32 j = g;
+    u64 h = V.d[g];
+    u32 ej = V.e[j];
+    while (ej > k) {
+        h = ej;
+        j = V.psv[j];
+        ej = V.e[j];
     }
-    return v;
+    *pos = V.suf_off[j] + (k - ej);
+    *avail = h - k;
 }
 
 // Three-way comparison of front-coded strings x and y from byte `from`
-// (they agree on [0, from)); *lcp receives their LCP.
+// (they agree on [0, from)); *lcp receives their LCP.  Each string's bytes
+// are read piece by piece: one chain walk per literal piece, then the two
+// pieces' bytes compared directly, 8 at a time, until one of them ends.
 __device__ __forceinline__ int fc_cmp(const FcView &V, u32 x, u32 y, u64 from, u64 *lcp)
 {
     const u64 lx = V.d[x], ly = V.d[y];
     const u64 m = lx < ly ? lx : ly;
     u64 i = from < m ? from : m;
+    u64 px = 0, ax = 0, py = 0, ay = 0;
     while (i < m) {
-        const u64 r = m - i;
-        const u32 take = r < 8 ? (u32)r : 8u;
-        const u64 wa = fc_load_be(V, x, i, take);
-        const u64 wb = fc_load_be(V, y, i, take);
-        if (wa != wb) {
-            *lcp = i + (__clzll(wa ^ wb) >> 3);
-            return wa < wb ? -1 : 1;
+        if (ax == 0) fc_piece(V, x, i, &px, &ax);
+        if (ay == 0) fc_piece(V, y, i, &py, &ay);
+        u64 run = ax < ay ? ax : ay;
+        run = run < m - i ? run : m - i;
+        while (run > 0) {
+            const u32 take = run < 8 ? (u32)run : 8u;
+            const u64 wa = load_be(V.suf, V.sufN, px, take);
+            const u64 wb = load_be(V.suf, V.sufN, py, take);
+            if (wa != wb) {
+                *lcp = i + (__clzll(wa ^ wb) >> 3);
+                return wa < wb ? -1 : 1;
+            }
+            px += take;
+            py += take;
+            ax -= take;
+            ay -= take;
+            i += take;
+            run -= take;
         }
-        i += take;
     }
     *lcp = m;
     return lx < ly ? -1 : (lx > ly ? 1 : 0);
