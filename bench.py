@@ -335,6 +335,49 @@ def splitters_leg(ss, torch, synth, n=50_000_000, p=16, v=2):
     return out
 
 
+def text_step_leg(ss, torch, synth, n=50_000_000, p=16, v=2, steps=3, warmup=1):
+    """The same PDMS step on variable-length text strings (log-normal lengths,
+    median 40; Zipf 1.1 bytes over 96 printable codes; 20% exact duplicates),
+    p virtual PEs, prefix doubling from 8 bytes with 64-bit keys: time per
+    step (two streams, as the main step), string bytes and strings per
+    second, the stages on one stream, and whether every timed step gave the
+    same order, LCPs and distinguishing prefixes."""
+    import time as _time
+    dev = torch.device("cuda:0")
+    s = synth.text_strings(n, seed=0, device=dev)
+    N = int(s.offsets[-1])
+    pipe = Pipeline(s.bytes, s.offsets, p, v, ss, torch, overlap=True)
+    times, ref, same = [], None, True
+    for it in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = _time.perf_counter()
+        order, mlcp, dist, dpx, rounds = pipe.step(Marks(torch, False))
+        torch.cuda.synchronize()
+        dt = _time.perf_counter() - t0
+        if it >= warmup:
+            times.append(dt)
+        if ref is None:
+            ref = (order.clone(), mlcp.clone(), dist.clone())
+        else:
+            same = same and torch.equal(order, ref[0]) and torch.equal(mlcp, ref[1]) and torch.equal(dist, ref[2])
+        del order, mlcp, dist, dpx
+    pipe.overlap = False
+    m = Marks(torch, True)
+    pipe.step(m)
+    torch.cuda.synchronize()
+    stages = m.times()
+    stages.pop("start", None)
+    t = sorted(times)[len(times) // 2]
+    out = {"workload": f"text strings n={n} (log-normal lengths median 40 in [1, 4096], Zipf 1.1 bytes over 96 "
+                       f"codes, 20% duplicates), p={p}, v={v}, prefix doubling from 8 bytes, 64-bit keys",
+           "n": n, "N": N, "steps": steps, "ms_per_step": t * 1e3, "GBps": N / t / 1e9, "strings_per_s": n / t,
+           "hbm_frac_of_N_per_step": N / t / 1e9 / HBM_PEAK_GBS, "doubling_rounds": int(rounds),
+           "stages_ms_one_stream": stages, "results_identical": bool(same)}
+    del s, pipe, ref
+    torch.cuda.empty_cache()
+    return out
+
+
 def suffix_leg(ss, torch, synth, N=100_000_000, reps=3):
     """Suffix array + LCP array of one text (the bytes of text-like strings:
     Zipf-distributed printable characters with repeats), by prefix doubling
@@ -667,6 +710,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-ms-mode", action="store_true", help="skip the full-string (MS) step")
     ap.add_argument("--no-suffix", action="store_true", help="skip the suffix-sorting leg")
+    ap.add_argument("--no-text-step", action="store_true", help="skip the PDMS step on 50M text strings")
     ap.add_argument("--no-splitters", action="store_true",
                     help="skip the string- vs character-based splitter comparison on text strings")
     ap.add_argument("--no-profile", action="store_true",
@@ -835,6 +879,11 @@ def main():
         out["splitters_text"] = splitters_leg(ss, torch, synth)
         autotune.apply("dn")
         print(f"# splitters leg: {out['splitters_text']}", file=sys.stderr, flush=True)
+    if not args.no_text_step:
+        autotune.apply("text")
+        out["text_step"] = text_step_leg(ss, torch, synth)
+        autotune.apply("dn")
+        print(f"# text step leg: {out['text_step']}", file=sys.stderr, flush=True)
     if not args.no_suffix:
         out["suffix_sort"] = suffix_leg(ss, torch, synth)
         print(f"# suffix leg: {out['suffix_sort']}", file=sys.stderr, flush=True)
