@@ -566,27 +566,50 @@ __device__ __forceinline__ void fc_piece(const FcView &V, u32 g, u64 k, u64 *pos
 }
 
 // Three-way comparison of front-coded strings x and y from byte `from`
-// (they agree on [0, from)); *lcp receives their LCP.  Each string's bytes
-// are read piece by piece: one chain walk per literal piece, then the two
-// pieces' bytes compared directly, 8 at a time, until one of them ends.
+// (they agree on [0, from)); *lcp receives their LCP.  Merges call it where
+// cached keys tie, in lockstep wavefronts where one lane's comparison holds
+// up the others, so its chain of dependent loads is kept short: both
+// strings' lengths, LCPs and literal offsets are loaded together; a string
+// whose own literal holds byte `from` (the usual case) is read from there
+// without a chain walk, otherwise its piece is found along its psv chain;
+// the two pieces are then compared 32 bytes a round, every word of a round
+// loaded before any is compared, until one piece ends.
+#define FC_ROUND 4  // 8-byte words per comparison round
+
 __device__ __forceinline__ int fc_cmp(const FcView &V, u32 x, u32 y, u64 from, u64 *lcp)
 {
     const u64 lx = V.d[x], ly = V.d[y];
+    const u32 ex = V.e[x], ey = V.e[y];
+    const u64 sx = V.suf_off[x], sy = V.suf_off[y];
     const u64 m = lx < ly ? lx : ly;
     u64 i = from < m ? from : m;
     u64 px = 0, ax = 0, py = 0, ay = 0;
+    if (i < m) {
+        if (ex <= i) { px = sx + (i - ex); ax = lx - i; }
+        else fc_piece(V, x, i, &px, &ax);
+        if (ey <= i) { py = sy + (i - ey); ay = ly - i; }
+        else fc_piece(V, y, i, &py, &ay);
+    }
     while (i < m) {
         if (ax == 0) fc_piece(V, x, i, &px, &ax);
         if (ay == 0) fc_piece(V, y, i, &py, &ay);
         u64 run = ax < ay ? ax : ay;
         run = run < m - i ? run : m - i;
         while (run > 0) {
-            const u32 take = run < 8 ? (u32)run : 8u;
-            const u64 wa = load_be(V.suf, V.sufN, px, take);
-            const u64 wb = load_be(V.suf, V.sufN, py, take);
-            if (wa != wb) {
-                *lcp = i + (__clzll(wa ^ wb) >> 3);
-                return wa < wb ? -1 : 1;
+            const u32 take = run < 8 * FC_ROUND ? (u32)run : 8u * FC_ROUND;
+            u64 wa[FC_ROUND], wb[FC_ROUND];
+#pragma unroll
+            for (u32 q = 0; q < FC_ROUND; q++) {
+                const u32 tq = take > 8 * q ? (take - 8 * q < 8 ? take - 8 * q : 8u) : 0u;
+                wa[q] = tq ? load_be(V.suf, V.sufN, px + 8 * q, tq) : 0ull;
+                wb[q] = tq ? load_be(V.suf, V.sufN, py + 8 * q, tq) : 0ull;
+            }
+#pragma unroll
+            for (u32 q = 0; q < FC_ROUND; q++) {
+                if (wa[q] != wb[q]) {
+                    *lcp = i + 8 * q + (__clzll(wa[q] ^ wb[q]) >> 3);
+                    return wa[q] < wb[q] ? -1 : 1;
+                }
             }
             px += take;
             py += take;
