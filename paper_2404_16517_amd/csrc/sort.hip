@@ -33,6 +33,7 @@
 
 #define NT 256
 #define ETILE 2048  // elements per workgroup in element-wise round kernels
+#define RX_PF 8     // 256-element chunks a radix pass loads ahead
 #define LDS_NT 512
 #define LDS_CAP 2048  // elements per LDS tile (2 x the largest cutover)
 
@@ -573,16 +574,27 @@ __global__ __launch_bounds__(NT) void k_hist(const Seg *segs, const u32 *tstart,
     for (u32 d = threadIdx.x; d < NB; d += NT) h[d] = 0;
     __syncthreads();
     u64 mn = ~0ull, mx = 0;
-    for (u32 c = b0; c < b1; c += NT) {
-        const u32 i = c + threadIdx.x;
-        const bool valid = i < b1;
-        u64 k = valid ? keys[i] : 0;
-        u32 d = digit_of<W>(k, level);
-        u64 peers = match_digit_w<W>(d, valid);
-        if (valid) {
-            mn = k < mn ? k : mn;
-            mx = k > mx ? k : mx;
-            if ((peers & lanemask_lt()) == 0) atomicAdd(&h[d], (u32)__popcll(peers));
+    for (u32 c0 = b0; c0 < b1; c0 += RX_PF * NT) {
+        // RX_PF chunks' keys loaded before any is counted
+        u64 kq[RX_PF];
+#pragma unroll
+        for (u32 q = 0; q < RX_PF; q++) {
+            const u32 i = c0 + q * NT + threadIdx.x;
+            kq[q] = i < b1 ? keys[i] : 0;
+        }
+#pragma unroll
+        for (u32 q = 0; q < RX_PF; q++) {
+            const u32 c = c0 + q * NT;
+            if (c >= b1) break;  // (uniform)
+            const bool valid = c + threadIdx.x < b1;
+            const u64 k = kq[q];
+            u32 d = digit_of<W>(k, level);
+            u64 peers = match_digit_w<W>(d, valid);
+            if (valid) {
+                mn = k < mn ? k : mn;
+                mx = k > mx ? k : mx;
+                if ((peers & lanemask_lt()) == 0) atomicAdd(&h[d], (u32)__popcll(peers));
+            }
         }
     }
     __syncthreads();
@@ -788,15 +800,28 @@ __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tsta
     for (u32 d = threadIdx.x; d < NB; d += NT) run[d] = g.begin + hist[NB * ts + d * T + lt] - base;
     __syncthreads();
     const u32 wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (u32 c = b0; c < b1; c += NT) {
+    for (u32 c0 = b0; c0 < b1; c0 += RX_PF * NT) {
+    // RX_PF chunks' keys and payloads loaded before any is placed
+    u64 kq[RX_PF];
+    u32 vq[RX_PF];
+#pragma unroll
+    for (u32 q = 0; q < RX_PF; q++) {
+        const u32 i = c0 + q * NT + threadIdx.x;
+        kq[q] = 0;
+        vq[q] = 0;
+        if (i < b1) {
+            kq[q] = ksrc[i];
+            vq[q] = vsrc[i];
+        }
+    }
+#pragma unroll
+    for (u32 q = 0; q < RX_PF; q++) {
+        const u32 c = c0 + q * NT;
+        if (c >= b1) break;  // (uniform)
         const u32 i = c + threadIdx.x;
         const bool valid = i < b1;
-        u64 k = 0;
-        u32 v = 0;
-        if (valid) {
-            k = ksrc[i];
-            v = vsrc[i];
-        }
+        const u64 k = kq[q];
+        const u32 v = vq[q];
         const u32 d = digit_of<W>(k, level);
         const u64 peers = match_digit_w<W>(d, valid);
         const u32 rank = (u32)__popcll(peers & lanemask_lt());
@@ -815,6 +840,7 @@ __global__ __launch_bounds__(NT) void k_scatter(const Seg *segs, const u32 *tsta
             kdst[dst] = k;
             vdst[dst] = v;
         }
+    }
     }
     __syncthreads();  // run is rewritten by the next tile
     }
@@ -842,12 +868,25 @@ __global__ __launch_bounds__(NT) void k_settle(const Seg *segs, const u32 *tstar
     const u8 *kd = kinds + Digits<W>::NB * s;
     if (scat[s]) {
         if (inb) continue;  // scattered into A
-        for (u32 i = b0 + threadIdx.x; i < b1; i += NT) {
-            const u64 k = keyB[i];
-            const u32 c = kd[digit_of<W>(k, level)];
-            if (c == K_NONE || c == K_NEXT || c == K_IDENT) {
-                keyA[i] = k;
-                valA[i] = valB[i];
+        for (u32 c0 = b0; c0 < b1; c0 += RX_PF * NT) {
+            // RX_PF chunks' keys, then their buckets' kinds, loaded before any is used
+            u64 kq[RX_PF];
+            u32 cq[RX_PF];
+#pragma unroll
+            for (u32 q = 0; q < RX_PF; q++) {
+                const u32 i = c0 + q * NT + threadIdx.x;
+                kq[q] = i < b1 ? keyB[i] : 0ull;
+            }
+#pragma unroll
+            for (u32 q = 0; q < RX_PF; q++) cq[q] = kd[digit_of<W>(kq[q], level)];
+#pragma unroll
+            for (u32 q = 0; q < RX_PF; q++) {
+                const u32 i = c0 + q * NT + threadIdx.x;
+                const u32 c = cq[q];
+                if (i < b1 && (c == K_NONE || c == K_NEXT || c == K_IDENT)) {
+                    keyA[i] = kq[q];
+                    valA[i] = valB[i];
+                }
             }
         }
     } else if (inb && (kd[0] == K_NEXT || kd[0] == K_IDENT)) {
