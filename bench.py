@@ -282,6 +282,63 @@ def batch_leg(ss, torch, synth, num_sets=4096, lo=1e3, hi=1e6, len_lo=8, len_hi=
     return out
 
 
+def kway_leg(ss, torch, synth, n=64_000_000, k=256, length=64, ratio=0.3, reps=3):
+    """The k-way variant of the batched workload: k pre-sorted LCP-annotated
+    front-coded runs of D/N strings (dealt to the runs at random), merged
+    into one sequence by the LCP-aware merge, with full strings (d = length)
+    and with distinguishing prefixes only (the PDMS form).  Inputs are built
+    on the device from the D/N closed forms and resident before timing; the
+    merged order and LCPs are checked against the same closed forms."""
+    import numpy as np
+    from tests import closed_forms as cf
+    dev = torch.device("cuda:0")
+    s = synth.dn_strings(n, length, ratio, seed=3, device=dev)
+    run = synth.random_runs(n, k, 3, device=dev)
+    K, F = s.meta["k"], s.meta["filler"]
+    perm_ref = lcp_ref = None
+    out = {"workload": f"{k} sorted front-coded runs, {n} D/N strings of {length} B (ratio {ratio}) dealt at random",
+           "n": n, "k": k, "string_bytes": n * length}
+    for pdms in (False, True):
+        run_off, e, d, ids, suf_off, suf = cf.dn_front_coded_runs(s, run, k, pdms)
+        rb, re_ = run_off[:-1].contiguous(), run_off[1:].contiguous()
+        go = torch.tensor([0, k], dtype=torch.int32, device=dev)
+        ws = torch.empty(ss.lib().ss_lcp_merge_workspace(n, n, k), dtype=torch.uint8, device=dev)
+        lit = int(suf_off[-1])
+
+        def merge():
+            return ss.lcp_merge(rb, re_, go, e, d, ids, suf_off, suf, ws=ws, n_out=n, with_src=False)
+        _, gid, glcp = merge()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            _, gid2, glcp2 = merge()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b) / 1e3)
+        same = torch.equal(gid, gid2) and torch.equal(glcp, glcp2)
+        if perm_ref is None:
+            perm_ref = cf.dn_perm(s.meta["pi"].numpy())
+            lcp_ref = cf.dn_lcp(n, K, F)
+        ok = bool(np.array_equal(gid.cpu().numpy().view(np.uint32), perm_ref)
+                  and np.array_equal(glcp.cpu().numpy().view(np.uint32), lcp_ref))
+        t = sorted(ts)[len(ts) // 2]
+        # algorithmic bytes: e, d, id and suf_off (4+4+4+8 B) and the literal
+        # bytes read once, id and LCP (4+4 B) written once
+        alg = 28 * n + lit
+        out["pdms" if pdms else "full_strings"] = {
+            "ms": t * 1e3, "strings_per_s": n / t, "string_GBps": n * length / t / 1e9,
+            "literal_bytes": lit, "front_coded_bytes_per_string": lit / n + 12.0,
+            "algorithmic_GBps": alg / t / 1e9, "hbm_frac_algorithmic": alg / t / 1e9 / HBM_PEAK_GBS,
+            "results_identical": bool(same), "closed_forms_agree": ok}
+        del run_off, e, d, ids, suf_off, suf, ws, gid, glcp, gid2, glcp2
+        torch.cuda.empty_cache()
+    del s, run
+    torch.cuda.empty_cache()
+    return out
+
+
 def splitters_leg(ss, torch, synth, n=50_000_000, p=16, v=2):
     """Text strings (log-normal lengths, Zipf bytes, 20% duplicates), split
     over p virtual PEs, each sorted: characters per bucket with string-based
@@ -708,6 +765,7 @@ def main():
                     help="run prefix doubling's first pass before the sort, only its later rounds beside it")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-per-job leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-kway", action="store_true", help="skip the k-way merge of 256 front-coded runs")
     ap.add_argument("--no-ms-mode", action="store_true", help="skip the full-string (MS) step")
     ap.add_argument("--no-suffix", action="store_true", help="skip the suffix-sorting leg")
     ap.add_argument("--no-text-step", action="store_true", help="skip the PDMS step on 50M text strings")
@@ -874,6 +932,9 @@ def main():
         out["batch"]["tuning"] = used or "library defaults"
         autotune.apply("dn")
         print(f"# batch leg: {out['batch']}", file=sys.stderr, flush=True)
+    if not args.no_kway:
+        out["kway_merge"] = kway_leg(ss, torch, synth)
+        print(f"# k-way merge leg: {out['kway_merge']}", file=sys.stderr, flush=True)
     if not args.no_splitters:
         autotune.apply("text")
         out["splitters_text"] = splitters_leg(ss, torch, synth)

@@ -84,3 +84,52 @@ def doubling_rounds_closed_form(dist: np.ndarray, lengths: np.ndarray, l0: int) 
         t += 1
         L *= 2
     return t
+
+
+def dn_front_coded_runs(s, run, k: int, pdms: bool):
+    """k sorted front-coded runs of the D/N strings ``s`` (torch, on their
+    device), string i going to run ``run[i]``: order within a run by pi, the
+    LCP entry from the common base-26 digits above, 0 at each run's start;
+    d = the string length, or in the PDMS variant the smallest 8 * 2^t >= F + k
+    for every string (F + k is the distinguishing prefix wherever a neighbour
+    shares k - 1 digits, i.e. everywhere but possibly at the last position;
+    any d at least the distinguishing prefix gives the same merge).
+    Returns run_off (int64[k+1]), e, d, ids (int32[n]), suf_off (int64[n+1])
+    and suf (uint8), the arrays of the merge's input."""
+    import torch
+    dev = s.bytes.device
+    n, length = s.n, s.meta["length"]
+    K, F = s.meta["k"], s.meta["filler"]
+    pi = s.meta["pi"].to(dev)
+    ids = torch.sort(run.to(torch.int64) * (1 << 32) + pi).indices   # runs in order, each sorted by pi
+    run_off = torch.zeros(k + 1, dtype=torch.int64, device=dev)
+    run_off[1:] = torch.cumsum(torch.bincount(run.to(torch.int64), minlength=k), 0)
+    pv = pi[ids]
+    a, c = pv[:-1], pv[1:]
+    common = torch.zeros(max(n - 1, 0), dtype=torch.int64, device=dev)
+    alive = torch.ones(max(n - 1, 0), dtype=torch.bool, device=dev)
+    for dgt in range(K):
+        p = 26 ** (K - 1 - dgt)
+        alive &= (a // p) % 26 == (c // p) % 26
+        common += alive
+    del a, c, alive
+    e = torch.zeros(n, dtype=torch.int64, device=dev)
+    e[1:] = F + common
+    del common
+    e[run_off[:-1][run_off[:-1] < n]] = 0
+    dist = F + K
+    dlen = min(length, 8 * 2 ** int(np.ceil(np.log2(dist / 8)))) if pdms else length
+    d = torch.full((n,), dlen, dtype=torch.int64, device=dev)
+    lit = d - e
+    suf_off = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    suf_off[1:] = torch.cumsum(lit, 0)
+    suf = torch.empty(int(suf_off[-1]), dtype=torch.uint8, device=dev)
+    step = 1 << 22
+    for q0 in range(0, n, step):
+        q1 = min(n, q0 + step)
+        L = lit[q0:q1]
+        pos = torch.repeat_interleave(torch.arange(q0, q1, device=dev), L)
+        t = torch.arange(int(suf_off[q0]), int(suf_off[q1]), device=dev) - suf_off[pos]
+        suf[int(suf_off[q0]):int(suf_off[q1])] = s.bytes[ids[pos] * length + e[pos] + t]
+    i32 = lambda x: x.to(torch.int32)
+    return run_off, i32(e), i32(d), i32(ids), suf_off, suf

@@ -56,51 +56,13 @@ def test_text_50M_sort_lcp_and_prefix_doubling():
     assert rounds == cf.doubling_rounds_closed_form(dist, lens, 8)
 
 
-def _dn_runs_front_coded(n, length, ratio, k, seed, pdms):
-    """k sorted front-coded runs of D/N strings dealt at random, from the
-    closed forms (order by pi, LCP from common base-26 digits); d = len, or the
-    collision-free doubling result in the PDMS variant.  Torch on the device."""
-    s = synth.dn_strings(n, length, ratio, seed=seed, device=DEV)
-    K, F = s.meta["k"], s.meta["filler"]
-    pi = s.meta["pi"].to(DEV)
-    run = synth.random_runs(n, k, seed, device=DEV)
-    ids = torch.sort(run * (1 << 32) + pi).indices           # runs in order, each sorted by pi
-    run_off = torch.zeros(k + 1, dtype=torch.int64, device=DEV)
-    run_off[1:] = torch.cumsum(torch.bincount(run, minlength=k), 0)
-    pv = pi[ids]
-    a, c = pv[:-1], pv[1:]
-    common = torch.zeros(n - 1, dtype=torch.int64, device=DEV)
-    alive = torch.ones(n - 1, dtype=torch.bool, device=DEV)
-    for dgt in range(K):
-        p = 26 ** (K - 1 - dgt)
-        alive &= (a // p) % 26 == (c // p) % 26
-        common += alive
-    e = torch.zeros(n, dtype=torch.int64, device=DEV)
-    e[1:] = F + common
-    e[run_off[:-1][run_off[:-1] < n]] = 0
-    dist = F + K  # every string's distinguishing prefix
-    dlen = min(length, 8 * 2 ** int(np.ceil(np.log2(dist / 8)))) if pdms else length
-    d = torch.full((n,), dlen, dtype=torch.int64, device=DEV)
-    lit = d - e
-    suf_off = torch.zeros(n + 1, dtype=torch.int64, device=DEV)
-    suf_off[1:] = torch.cumsum(lit, 0)
-    suf = torch.empty(int(suf_off[-1]), dtype=torch.uint8, device=DEV)
-    step = 1 << 22
-    for q0 in range(0, n, step):
-        q1 = min(n, q0 + step)
-        L = lit[q0:q1]
-        pos = torch.repeat_interleave(torch.arange(q0, q1, device=DEV), L)
-        t = torch.arange(int(suf_off[q0]), int(suf_off[q1]), device=DEV) - suf_off[pos]
-        suf[int(suf_off[q0]):int(suf_off[q1])] = s.bytes[ids[pos] * length + e[pos] + t]
-    i32 = lambda x: x.to(torch.int32)
-    return s, run_off, i32(e), i32(d), i32(ids), suf_off, suf
-
-
 @pytest.mark.parametrize("pdms", [False, True])
 def test_merge_256_runs_of_64M_dn_strings(pdms):
     n, k = 64_000_000, 256
     _log(f"[full] merge 256 runs x 64M, pdms={pdms}: build runs")
-    s, run_off, e, d, ids, suf_off, suf = _dn_runs_front_coded(n, 64, 0.3, k, 3, pdms)
+    s = synth.dn_strings(n, 64, 0.3, seed=3, device=DEV)
+    run = synth.random_runs(n, k, 3, device=DEV)
+    run_off, e, d, ids, suf_off, suf = cf.dn_front_coded_runs(s, run, k, pdms)
     assert (s.meta["k"], s.meta["filler"]) == (6, 13)
     _log("[full] merge")
     _, gid, glcp = ss.lcp_merge_runs(run_off, e, d, ids, suf_off, suf)
