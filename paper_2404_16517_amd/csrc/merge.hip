@@ -643,25 +643,33 @@ struct MergeLevel {
 
 __device__ __forceinline__ u32 min3u(u32 a, u32 b, u32 c) { return min(a, min(b, c)); }
 
-// Compare two elements of one group whose strings agree on [0, bound): first by
-// their cached keys at the group depth C (bytes [C, C+7) and the remaining
-// length), then, on equal keys of continuing strings, on the strings from C+7.
+// Compare two elements of one group by their cached keys at the group depth C
+// (bytes [C, C+7) and the remaining length, capped at 8).  Different keys
+// decide alone: they order the two strings and give their LCP, whatever else
+// is known about them.  Equal keys of strings that end inside the key are
+// equal strings.  Otherwise the strings agree on [0, C+7), and `tie` compares
+// them from there (or from a larger known common prefix): only then are the
+// elements' ids and bounds needed, which lets callers read them lazily.
+template <class Tie>
+__device__ __forceinline__ int cmp_key(u64 kx, u64 ky, u32 C, u64 *lcp, Tie tie)
+{
+    if (kx != ky) {
+        *lcp = key_lcp(kx, ky, C);
+        return kx < ky ? -1 : 1;
+    }
+    const u32 cnt = (u32)(kx & 0xFF);
+    if (cnt < 8) {
+        *lcp = C + cnt;
+        return 0;
+    }
+    return tie(lcp);
+}
+
+// The same for elements whose strings are known to agree on [0, bound).
 __device__ __forceinline__ int cmp_elem(const FcView &V, u32 gx, u64 kx, u32 gy, u64 ky, u32 bound, u32 C,
                                         u64 *lcp)
 {
-    if (bound < C + 7) {
-        if (kx != ky) {
-            *lcp = key_lcp(kx, ky, C);
-            return kx < ky ? -1 : 1;
-        }
-        const u32 cnt = (u32)(kx & 0xFF);
-        if (cnt < 8) {
-            *lcp = C + cnt;
-            return 0;
-        }
-        bound = C + 7;
-    }
-    return fc_cmp(V, gx, gy, bound, lcp);
+    return cmp_key(kx, ky, C, lcp, [&](u64 *l) { return fc_cmp(V, gx, gy, bound > C + 7 ? bound : C + 7, l); });
 }
 
 #define MW_NT 256
@@ -680,7 +688,12 @@ __device__ u32 corank_global(const MergeLevel &M, u64 A0, u32 na, u64 B0, u32 nb
     while (xlo < xhi) {
         const u32 mid = (xlo + xhi) >> 1;
         const u32 y = d - mid - 1;
-        if (cmp_elem(M.V, GA[mid], KA[mid], GB[y], KB[y], min3u(FA[mid], c, FB[y]), C, &tmp) <= 0) xlo = mid + 1;
+        // keys first: the ids and bounds are read only when the keys tie
+        const int r = cmp_key(KA[mid], KB[y], C, &tmp, [&](u64 *l) {
+            const u32 bd = min3u(FA[mid], c, FB[y]);
+            return fc_cmp(M.V, GA[mid], GB[y], bd > C + 7 ? bd : C + 7, l);
+        });
+        if (r <= 0) xlo = mid + 1;
         else xhi = mid;
     }
     return xlo;
@@ -722,11 +735,42 @@ __global__ void k_merge_split(MergeLevel M, u32 nblocks, u32 *split)
     split[t] = d0 >= na + nb ? na : corank_global(M, A0, na, A1, nb, d0, c, C);
 }
 
+// The merge's results: per output, the source (run, position in run), the
+// string id, the LCP with the previous output and the string length (src and
+// len optional).  sb/sid: the non-empty runs' front-coded starts, ascending,
+// and their run numbers.
+struct MergeOut {
+    const u64 *sb;
+    const u32 *sid;
+    u32 kne;
+    const u32 *fc_id, *fc_len;
+    u64 *src;
+    u32 *id, *lcp, *len;
+};
+
+__device__ __forceinline__ void merge_emit(const MergeOut &O, u64 x, u32 g, u32 l)
+{
+    if (O.src) {
+        u32 lo = 0, hi = O.kne;  // largest j with sb[j] <= g
+        while (hi - lo > 1) {
+            u32 mid = (lo + hi) >> 1;
+            if (O.sb[mid] <= g) lo = mid;
+            else hi = mid;
+        }
+        O.src[x] = ((u64)O.sid[lo] << 32) | (u64)(g - O.sb[lo]);
+    }
+    O.id[x] = O.fc_id[g];
+    O.lcp[x] = l;
+    if (O.len) O.len[x] = O.fc_len[g];
+}
+
 // One merge level, merge-path style: each workgroup produces MW_TILE outputs of
 // one pair.  Its A and B windows (plus the element before each) are staged in
 // LDS; every thread co-ranks its MW_IPT outputs inside the window and merges them
-// with the LCP rule; outputs are written back through LDS.
-__global__ __launch_bounds__(MW_NT, 6) void k_merge_level(MergeLevel M, u32 nblocks, const u32 *split)
+// with the LCP rule; outputs are written back through LDS.  The last level
+// (LAST) writes the merge's results instead of the next level's elements.
+template <bool LAST>
+__global__ __launch_bounds__(MW_NT, 6) void k_merge_level(MergeLevel M, u32 nblocks, const u32 *split, MergeOut O)
 {
     __shared__ u32 sG[MW_TILE + 2], sL[MW_TILE + 2], sF[MW_TILE + 2];
     __shared__ u64 sK[MW_TILE + 2];
@@ -863,13 +907,15 @@ __global__ __launch_bounds__(MW_NT, 6) void k_merge_level(MergeLevel M, u32 nblo
 #pragma unroll
     for (u32 k = 0; k < MW_IPT; k++) {
         if (k < cnt) {
-            sG[dd + k] = oG[k]; sL[dd + k] = oL[k]; sF[dd + k] = oF[k]; sK[dd + k] = oK[k];
+            sG[dd + k] = oG[k]; sL[dd + k] = oL[k];
+            if (!LAST) { sF[dd + k] = oF[k]; sK[dd + k] = oK[k]; }
         }
     }
     __syncthreads();
     const u64 ob = A0 + d0;
     for (u32 i = threadIdx.x; i < dw; i += MW_NT) {
-        M.Go[ob + i] = sG[i]; M.Lo[ob + i] = sL[i]; M.Fo[ob + i] = sF[i]; M.Ko[ob + i] = sK[i];
+        if (LAST) merge_emit(O, ob + i, sG[i], sL[i]);
+        else { M.Go[ob + i] = sG[i]; M.Lo[ob + i] = sL[i]; M.Fo[ob + i] = sF[i]; M.Ko[ob + i] = sK[i]; }
     }
 }
 
@@ -1145,10 +1191,10 @@ __global__ void k_block_runs(const u64 *P, u32 k, u32 nb, u32 *bfirst)
 // most eight literal bytes are read per block instead of every element's.
 __global__ __launch_bounds__(256) void k_mscan_reduce(MScan S, MOp *blk)
 {
-    __shared__ u32 s_last[8];  // per window byte k < 7, and the count (7): last supplier + 1, block-relative
+    // per wavefront, per window byte k < 7 and the count (7): last supplier + 1, block-relative (0: none)
+    __shared__ u32 s_wl[4][8];
     __shared__ u32 s_rp[MS_ITEMS], s_m[MS_ITEMS];
     const u64 x0 = (u64)blockIdx.x * MS_ITEMS;
-    if (threadIdx.x < 8) s_last[threadIdx.x] = 0;
     MElems E;
     mscan_locate(S, x0, E);
     u32 e[MS_PER];
@@ -1183,14 +1229,22 @@ __global__ __launch_bounds__(256) void k_mscan_reduce(MScan S, MOp *blk)
             if (p <= k) lastk[k] = i + 1;
         lastk[7] = i + 1;
     }
+    // the last supplier of each byte is the highest lane that has one
+    // (a thread's elements follow those of the lanes below it)
 #pragma unroll
-    for (u32 k = 0; k < 8; k++)
-        if (lastk[k]) atomicMax(&s_last[k], lastk[k]);
-    t = block_mop_reduce(t);  // (reset, p, m); its window is filled below (its barriers complete s_last)
+    for (u32 k = 0; k < 8; k++) {
+        const u64 m = __ballot(lastk[k] != 0);
+        const u32 v = m ? (u32)__shfl((int)lastk[k], 63 - __clzll(m), 64) : 0u;
+        if ((threadIdx.x & 63) == 0) s_wl[threadIdx.x >> 6][k] = v;
+    }
+    t = block_mop_reduce(t);  // (reset, p, m); its window is filled below (its barriers complete s_wl)
+    u32 last[8];
+#pragma unroll
+    for (u32 k = 0; k < 8; k++) last[k] = max(max(s_wl[0][k], s_wl[1][k]), max(s_wl[2][k], s_wl[3][k]));
     __shared__ u64 s_v[8];
     if (threadIdx.x < 8) s_v[threadIdx.x] = 0;
     __syncthreads();
-    // byte k comes from element s_last[k] - 1; the thread holding that
+    // byte k comes from element last[k] - 1; the thread holding that
     // element's entry loads it
 #pragma unroll
     for (u32 q = 0; q < MS_PER; q++) {
@@ -1198,7 +1252,7 @@ __global__ __launch_bounds__(256) void k_mscan_reduce(MScan S, MOp *blk)
         u32 ks = 0;
 #pragma unroll
         for (u32 k = 0; k < 8; k++)
-            if (s_last[k] == j) ks |= 1u << k;
+            if (last[k] == j) ks |= 1u << k;
         if (ks) {
             const u32 g = E.g[q], C = E.C[q];
             const u32 ee = ((E.start >> q) & 1) ? 0u : e[q];
@@ -1228,8 +1282,15 @@ __global__ __launch_bounds__(1024) void k_mscan_top(MOp *blk, u32 nb)
     __shared__ MOp wtot[16];
     const u32 per = (nb + 1023) / 1024;
     const u32 c0 = threadIdx.x * per, c1 = (c0 + per < nb) ? c0 + per : nb;
+    // (operators loaded eight at a time, ahead of the chain that combines them)
     MOp t = mop_id();
-    for (u32 i = c0; i < c1; i++) t = mop_cat(t, blk[i]);
+    for (u32 i = c0; i < c1; i += 8) {
+        MOp v[8];
+#pragma unroll
+        for (u32 j = 0; j < 8; j++) v[j] = (i + j < c1) ? blk[i + j] : mop_id();
+#pragma unroll
+        for (u32 j = 0; j < 8; j++) t = mop_cat(t, v[j]);
+    }
     const u32 lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     MOp inc = t;
 #pragma unroll
@@ -1244,10 +1305,15 @@ __global__ __launch_bounds__(1024) void k_mscan_top(MOp *blk, u32 nb)
     MOp pre = mop_id();
     for (u32 w = 0; w < wv; w++) pre = mop_cat(pre, wtot[w]);
     pre = mop_cat(pre, ex);
-    for (u32 i = c0; i < c1; i++) {
-        const MOp v = blk[i];
-        blk[i] = pre;
-        pre = mop_cat(pre, v);
+    for (u32 i = c0; i < c1; i += 8) {
+        MOp v[8];
+#pragma unroll
+        for (u32 j = 0; j < 8; j++) v[j] = (i + j < c1) ? blk[i + j] : mop_id();
+#pragma unroll
+        for (u32 j = 0; j < 8; j++) {
+            if (i + j < c1) blk[i + j] = pre;
+            pre = mop_cat(pre, v[j]);
+        }
     }
 }
 
@@ -1289,26 +1355,13 @@ __global__ __launch_bounds__(256, 5) void k_mscan_apply(MScan S, const MOp *blk,
     }
 }
 
-// Source (run, position) of every output: runs sorted by their front-coded
-// start (sb, sid) locate the run of a front-coded position.
-__global__ void k_merge_out(const u32 *G, const u32 *L, u32 n_out, const u64 *sb, const u32 *sid, u32 k,
-                            const u32 *fc_id, const u32 *fc_len, u64 *src, u32 *id, u32 *lcp, u32 *len)
+// The results straight from the elements, where no merge level runs (every
+// group holds at most one non-empty run).
+__global__ void k_merge_out(const u32 *G, const u32 *L, u32 n_out, MergeOut O)
 {
     const u32 x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n_out) return;
-    const u32 g = G[x];
-    if (src) {
-        u32 lo = 0, hi = k;  // largest j with sb[j] <= g
-        while (hi - lo > 1) {
-            u32 mid = (lo + hi) >> 1;
-            if (sb[mid] <= g) lo = mid;
-            else hi = mid;
-        }
-        src[x] = ((u64)sid[lo] << 32) | (u64)(g - sb[lo]);
-    }
-    id[x] = fc_id[g];
-    lcp[x] = L[x];
-    if (len) len[x] = fc_len[g];
+    merge_emit(O, x, G[x], L[x]);
 }
 
 // Host-plan header: [0] check flag, [1] literal-buffer size, [2, 2+k) run
@@ -1628,16 +1681,25 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
                                 {w.tstart, tsv.data(), sizeof(u32) * tsv.size()}};
         SS_TRY(upload_parts(parts, 5, st));
     }
-    for (const LevelPlan &lp : plan) {
+    const MergeOut O{w.sb, w.sid, kne, fc_id, fc_len, out_src, out_id, out_lcp, out_len};
+    for (size_t li = 0; li < plan.size(); li++) {
+        const LevelPlan &lp = plan[li];
+        const bool last = li + 1 == plan.size();
         MergeLevel M{G, L, F, Go, Lo, Fo, K, Ko, w.pg + lp.off, w.Cg, w.PA0 + lp.off, w.PA1 + lp.off,
                      w.PB1 + lp.off, w.tstart + lp.ts_off, w.pc + lp.off, w.pfirst + lp.off, lp.npt, V};
         const u32 nblk = tsv[lp.ts_off + lp.npt];
         if (nblk > 0) {
             k_merge_split<<<(unsigned)ceil_div(nblk, 64), 64, 0, st>>>(M, nblk, w.split);
             SS_CHECK_LAUNCH();
-            // every element's id, LCP, bound and key read once and written once
-            SS_PROF("k_merge_level", st, (double)n_out * 40.0);
-            k_merge_level<<<nblk, MW_NT, 0, st>>>(M, nblk, w.split);
+            if (last) {
+                // id, LCP, bound and key in, the string id gathered; id and LCP out
+                SS_PROF("k_merge_level", st, (double)n_out * 32.0);
+                k_merge_level<true><<<nblk, MW_NT, 0, st>>>(M, nblk, w.split, O);
+            } else {
+                // every element's id, LCP, bound and key read once and written once
+                SS_PROF("k_merge_level", st, (double)n_out * 40.0);
+                k_merge_level<false><<<nblk, MW_NT, 0, st>>>(M, nblk, w.split, O);
+            }
         }
         SS_CHECK_LAUNCH();
         std::swap(G, Go);
@@ -1645,8 +1707,9 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
         std::swap(F, Fo);
         std::swap(K, Ko);
     }
-    k_merge_out<<<(unsigned)ceil_div(n_out, 256), 256, 0, st>>>(G, L, (u32)n_out, w.sb, w.sid, kne, fc_id, fc_len,
-                                                                out_src, out_id, out_lcp, out_len);
-    SS_CHECK_LAUNCH();
+    if (plan.empty()) {
+        k_merge_out<<<(unsigned)ceil_div(n_out, 256), 256, 0, st>>>(G, L, (u32)n_out, O);
+        SS_CHECK_LAUNCH();
+    }
     return SS_OK;
 }
