@@ -60,10 +60,12 @@ __global__ void k_fill_u32(u32 *p, u32 v, u32 count)
 
 // psv inside each block of PB entries (PSV_NONE if the answer lies before the
 // block).  The block minimum goes to leaf P + block of the tree T, the minima
-// of its PC-entry chunks to cm[block * PCB ..].
+// of its PC-entry chunks to cm[block * PCB ..].  This and the kernels below do
+// nothing when `need` is given and points to zero.
 __global__ __launch_bounds__(PB) void k_psv_block(const u32 *e, u32 n, u32 *psv, u32 *T, u32 P, u32 *cm,
-                                                 u32 *farl, u32 *fcnt)
+                                                 u32 *farl, u32 *fcnt, const u32 *need)
 {
+    if (need && *need == 0) return;
     __shared__ u32 t[2 * PB];  // heap: node x has children 2x, 2x+1; leaves PB..2PB-1
     const u32 b0 = blockIdx.x * PB;
     const u32 i = b0 + threadIdx.x;
@@ -123,8 +125,9 @@ __global__ __launch_bounds__(PB) void k_psv_block(const u32 *e, u32 n, u32 *psv,
 
 // Internal nodes of the tree T: each workgroup takes up to 512 nodes of one
 // level (m nodes, indices m..2m-1) and writes `lv` levels above them.
-__global__ __launch_bounds__(256) void k_tree_up(u32 *T, u32 m, u32 lv)
+__global__ __launch_bounds__(256) void k_tree_up(u32 *T, u32 m, u32 lv, const u32 *need)
 {
+    if (need && *need == 0) return;
     __shared__ u32 s[512];
     const u32 cnt = m < 512 ? m : 512;
     const u32 base = m + blockIdx.x * cnt;
@@ -200,8 +203,9 @@ __device__ __forceinline__ void psv_far_one(const u32 *e, const u32 *T, u32 P, c
 // farl[b*PB ..] (fcnt[b] of them); each walk is a chain of dependent loads,
 // so packing keeps the walks of a block in as few wavefronts as possible.
 __global__ __launch_bounds__(256) void k_psv_far(const u32 *e, const u32 *T, u32 P, const u32 *cm, const u32 *farl,
-                                                 const u32 *fcnt, u32 n, u32 *psv)
+                                                 const u32 *fcnt, u32 n, u32 *psv, const u32 *need)
 {
+    if (need && *need == 0) return;
     const u32 cnt = fcnt[blockIdx.x];
     const u32 *lst = farl + (u64)blockIdx.x * PB;
     for (u32 q = threadIdx.x; q < cnt; q += blockDim.x) psv_far_one(e, T, P, cm, lst[q], n, psv);
@@ -217,8 +221,10 @@ static u32 psv_leaves(u64 n)
 }
 
 // psv of every entry of e[0..n) (n >= 1).  T holds 2 * psv_leaves(n) words,
-// cm psv_leaves(n) * PCB words (256-byte aligned).
-static int psv_build(const u32 *e, u64 n, u32 *psv, u32 *T, u32 *cm, u32 *farl, u32 *fcnt, hipStream_t st)
+// cm psv_leaves(n) * PCB words (256-byte aligned).  Skipped on the device
+// when `need` is given and points to zero.
+static int psv_build(const u32 *e, u64 n, u32 *psv, u32 *T, u32 *cm, u32 *farl, u32 *fcnt, hipStream_t st,
+                     const u32 *need = nullptr)
 {
     if (n == 0) return SS_OK;
     const u32 nb = (u32)ceil_div(n, PB);
@@ -229,21 +235,21 @@ static int psv_build(const u32 *e, u64 n, u32 *psv, u32 *T, u32 *cm, u32 *farl, 
     }
     {
         SS_PROF("k_psv_block", st, (double)n * 8.0);  // e in, psv out
-        k_psv_block<<<nb, PB, 0, st>>>(e, (u32)n, psv, T, P, cm, farl, fcnt);
+        k_psv_block<<<nb, PB, 0, st>>>(e, (u32)n, psv, T, P, cm, farl, fcnt, need);
     }
     SS_CHECK_LAUNCH();
     for (u32 m = P; m > 1;) {
         u32 lv = 0;
         while (lv < 9 && (m >> lv) > 1) lv++;
         const u32 blocks = m > 512 ? m / 512 : 1;
-        k_tree_up<<<blocks, 256, 0, st>>>(T, m, lv);
+        k_tree_up<<<blocks, 256, 0, st>>>(T, m, lv, need);
         SS_CHECK_LAUNCH();
         m >>= lv;
     }
     {
         // (far entries only: their value, the tree path, one chunk)
         SS_PROF("k_psv_far", st, 0.0);
-        k_psv_far<<<nb, 256, 0, st>>>(e, T, P, cm, farl, fcnt, (u32)n, psv);
+        k_psv_far<<<nb, 256, 0, st>>>(e, T, P, cm, farl, fcnt, (u32)n, psv, need);
     }
     SS_CHECK_LAUNCH();
     return SS_OK;
@@ -1023,6 +1029,7 @@ struct MScan {
     const u32 *bfirst;  // run of every scan block's first element
     u32 k, n_out;
     FcView V;
+    u32 *ties;  // set to 1 if two adjacent strings of a run agree on [0, C+7)
 };
 
 // The run holding the positions being walked: its output range [pr, pr1),
@@ -1335,6 +1342,11 @@ __global__ __launch_bounds__(256, 5) void k_mscan_apply(MScan S, const MOp *blk,
 #pragma unroll
     for (u32 q = 0; q < MS_PER; q++) t = mop_cat(t, ops[threadIdx.x * MS_PER + q]);
     MOp st = block_mop_exclusive(t, blk[blockIdx.x]);
+    // adjacent strings of a run that agree on their whole cached key
+    bool tie = false;
+#pragma unroll
+    for (u32 q = 0; q < MS_PER; q++) tie |= ((E.in >> q) & 1) && e[q] >= E.C[q] + 7;
+    if (__ballot(tie) && (threadIdx.x & 63) == 0) *S.ties = 1u;
 #pragma unroll
     for (u32 q = 0; q < MS_PER; q++) {
         const u32 i = threadIdx.x * MS_PER + q;
@@ -1397,7 +1409,7 @@ __global__ __launch_bounds__(256) void k_check_merge_runs(const u64 *rb, const u
 
 struct MergeWs {
     DecWs dec;
-    u32 *G0, *G1, *L0, *L1, *F0, *F1, *pc, *tstart, *sid, *pg, *Cg, *rgroup, *rep, *split, *runmin, *bfirst;
+    u32 *G0, *G1, *L0, *L1, *F0, *F1, *pc, *tstart, *sid, *pg, *Cg, *rgroup, *rep, *split, *runmin, *bfirst, *ties;
     MOp *mblk;
     u8 *pfirst;
     u64 *PA0, *PA1, *PB1, *P, *sb, *K0, *K1;
@@ -1425,6 +1437,7 @@ static void merge_layout(u64 n_out, u64 n_fc, u64 k, MergeWs *w, WsArena *a, WsC
     MT(Cg, u32, k + 2); MT(pc, u32, MERGE_PCAP(k)); MT(pfirst, u8, MERGE_PCAP(k));
     MT(split, u32, n_out / MW_TILE + MERGE_PCAP(k) + 64);  // tiles of one level
     MT(runmin, u32, k + 2); MT(mblk, MOp, n_out / MS_ITEMS + 2); MT(bfirst, u32, n_out / MS_ITEMS + 2);
+    MT(ties, u32, 4);
 #undef MT
 }
 
@@ -1591,8 +1604,15 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
         return SS_ERR_WORKSPACE;
     }
 
-    // psv chains over the whole front-coded array (no decoding of the strings)
-    SS_TRY(psv_build(fc_lcp, n_fc, w.dec.psv, w.dec.tree, w.dec.cmin, w.dec.far, w.dec.fcnt, st));
+    // Strings are compared without decoding them, along psv chains over the
+    // whole front-coded array (built after the scan below).  Every comparison
+    // of two elements past their cached keys starts at byte C+7 or later of
+    // their group (the group depth compares run heads, whose e is 0), and a
+    // chain walk for byte i starts only at an entry with e > i: none takes
+    // place unless the scan finds adjacent strings of a run that share C+7
+    // bytes, and the chains are built only then.
+    k_fill_u32<<<1, 64, 0, st>>>(w.ties, 0u, 1);
+    SS_CHECK_LAUNCH();
     const FcView V{fc_lcp, fc_len, w.dec.psv, suf_off, suf, sufN};
     // group of every run, first non-empty run of every group, group depths, keys
     std::vector<u32> rg(k), rep(groups, 0);
@@ -1620,7 +1640,7 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
     {
         // front-coded LCP, length, literal offset and up to 7 literal bytes in (twice), state out
         SS_PROF("k_mscan", st, (double)n_out * (2.0 * 24.0 + 20.0));
-        const MScan S{run_begin, w.P, w.rgroup, w.Cg, w.bfirst, k, (u32)n_out, V};
+        const MScan S{run_begin, w.P, w.rgroup, w.Cg, w.bfirst, k, (u32)n_out, V, w.ties};
         const u32 nb = (u32)ceil_div(n_out, MS_ITEMS);
         k_block_runs<<<(unsigned)ceil_div(k, 256), 256, 0, st>>>(w.P, k, nb, w.bfirst);
         SS_CHECK_LAUNCH();
@@ -1631,6 +1651,7 @@ extern "C" int ss_lcp_merge(uint32_t k, const uint64_t *run_begin, const uint64_
         k_mscan_apply<<<nb, 256, 0, st>>>(S, w.mblk, w.G0, w.L0, w.F0, w.K0);
     }
     SS_CHECK_LAUNCH();
+    SS_TRY(psv_build(fc_lcp, n_fc, w.dec.psv, w.dec.tree, w.dec.cmin, w.dec.far, w.dec.fcnt, st, w.ties));
     u32 *G = w.G0, *L = w.L0, *F = w.F0, *Go = w.G1, *Lo = w.L1, *Fo = w.F1;
     u64 *K = w.K0, *Ko = w.K1;
     std::vector<u32> pgv;

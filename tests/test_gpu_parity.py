@@ -731,12 +731,14 @@ def test_bucket_bounds_with_external_splitters():
 
 # ----------------------------------------------------------------------- merge
 
-def _runs_from_oracle(s, k, seed, pdms=False):
-    """k sorted front-coded runs built by the oracle from a random split."""
+def _runs_from_oracle(s, k, seed, pdms=False, assign=None):
+    """k sorted front-coded runs built by the oracle from a random split
+    (or the given run of every string)."""
     rng = np.random.default_rng(seed)
     b, o = oracle.strings_np(s)
     strs = s.as_list()
-    assign = rng.integers(0, k, size=s.n)
+    if assign is None:
+        assign = rng.integers(0, k, size=s.n)
     parts = []
     for j in range(k):
         idx = np.nonzero(assign == j)[0]
@@ -780,6 +782,33 @@ def test_lcp_merge_matches_oracle(k, seed, pdms):
     np.testing.assert_array_equal(u64(src), rsrc)
     np.testing.assert_array_equal(u32(gid), rid)
     np.testing.assert_array_equal(u32(glcp), rlcp)
+
+
+def test_lcp_merge_ties_across_runs_only():
+    """Inside each run no two neighbours share 7 bytes, but strings of
+    different runs share 20 or more (and some are equal): every such pair is
+    compared past the cached keys, from the strings' own literals."""
+    rng = np.random.default_rng(12)
+    k = 6
+    strs, assign = [], []
+    for j in range(k):
+        for i in range(200):
+            head = bytes([33 + i % 90, 33 + i // 90])
+            tail = b"" if i % 7 == 0 else bytes(rng.integers(65, 70, size=int(rng.integers(0, 6))).tolist())
+            strs.append(head + b"Z" * 20 + (b"%d" % (j % 3)) + tail)
+            assign.append(j)
+    s = synth.from_list(strs)
+    ro, lc, ln, idv, so, suf = _runs_from_oracle(s, k, 0, assign=np.array(assign))
+    assert all(int(x) < 7 for x in lc)  # no neighbours in a run share 7 bytes
+    T = lambda a, dt: torch.from_numpy(a.view(dt).copy()).to(DEV)
+    src, gid, glcp = ss.lcp_merge_runs(T(ro, np.int64), T(lc, np.int32), T(ln, np.int32), T(idv, np.int32),
+                                       T(so, np.int64), torch.from_numpy(suf.copy()).to(DEV))
+    torch.cuda.synchronize()
+    rsrc, rid, rlcp = oracle.merge(ro, lc, ln, idv, so, suf)
+    np.testing.assert_array_equal(u64(src), rsrc)
+    np.testing.assert_array_equal(u32(gid), rid)
+    np.testing.assert_array_equal(u32(glcp), rlcp)
+    assert int(rlcp.max()) >= 22
 
 
 def test_lcp_merge_dn_closed_form():
