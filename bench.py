@@ -775,6 +775,8 @@ def main():
                     help="time the steps without the per-launch events (no roofline)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GB",
                     help="only run a plain device-to-device copy of this many GB (counter calibration)")
+    ap.add_argument("--kway-only", action="store_true",
+                    help="only run the k-way merge leg and print its results (for profiling it alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (use --gpus 1); the multi-GPU design is described, not built", file=sys.stderr)
@@ -796,6 +798,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 3}))
+        return
+    if args.kway_only:
+        print(json.dumps({"kway_merge": kway_leg(ss, torch, synth)}))
         return
     t0 = time.time()
     s = synth.dn_strings(args.n, args.length, args.ratio, seed=0, device=dev)
