@@ -433,11 +433,14 @@ __global__ void k_add_base(u64 *a, u64 n, u64 base)
 
 // Literal bytes of strings [i0, i0+256) (string i's bytes [e_i, d_i) go to
 // suf[suf_off[i] ..]; lit_src[i] = offset of byte e_i, written in sorted order
-// by k_fc_meta).  Each thread reads its string's literal with aligned
-// 8-byte words; when the workgroup's output span fits the LDS buffer the
-// literals are packed there and written out in aligned 16-byte words (bytes
-// at the two ends, which neighbouring workgroups share, one by one),
-// otherwise each thread writes its literal directly.
+// by k_fc_meta).  When the workgroup's output span fits the LDS buffer (short
+// literals, as distinguishing prefixes leave them) each thread reads its
+// string's literal with aligned 8-byte words, the literals are packed in LDS
+// and written out in aligned 16-byte words (bytes at the two ends, which
+// neighbouring workgroups share, one by one).  Otherwise (long literals) 16
+// lanes copy one string at a time: every lane an aligned 8-byte word of the
+// destination, read from the source at whatever alignment it has, and the
+// unaligned bytes at the two ends one by one.
 __global__ __launch_bounds__(CS_NT) void k_fc_copy(const u8 *bytes, u64 N, u32 n, const u64 *lit_src,
                                                    const u64 *suf_off, u8 *suf)
 {
@@ -449,6 +452,24 @@ __global__ __launch_bounds__(CS_NT) void k_fc_copy(const u8 *bytes, u64 N, u32 n
     const u64 span = S1 - S0;
     const u32 mis = (u32)(((uintptr_t)(suf + S0)) & 15);  // buf[mis] holds output byte S0
     const bool staged = span + mis <= CS_BUF;
+    if (!staged) {  // uniform over the workgroup
+        const u32 gl = threadIdx.x & 15;
+        for (u32 i = i0 + (threadIdx.x >> 4); i < i1; i += CS_NT / 16) {
+            const u64 so = suf_off[i], len = suf_off[i + 1] - so, src = lit_src[i];
+            const u32 mis8 = (u32)(((uintptr_t)(suf + so)) & 7);
+            const u64 head = mis8 ? (8u - mis8 < len ? 8u - mis8 : len) : 0u;  // bytes up to an aligned word
+            const u64 words = (len - head) / 8;
+            const u64 tail = (len - head) & 7;
+            if (gl < head) suf[so + gl] = bytes[src + gl];
+            for (u64 q = gl; q < words; q += 16)
+                *(u64 *)(suf + so + head + 8 * q) = load_le(bytes, N, src + head + 8 * q, 8u);
+            if (gl < tail) {
+                const u64 t = head + 8 * words + gl;
+                suf[so + t] = bytes[src + t];
+            }
+        }
+        return;
+    }
     const u32 i = i0 + threadIdx.x;
     if (i < i1) {
         const u64 so = suf_off[i], len = suf_off[i + 1] - so;
@@ -456,17 +477,10 @@ __global__ __launch_bounds__(CS_NT) void k_fc_copy(const u8 *bytes, u64 N, u32 n
         for (u64 k = 0; k < len; k += 8) {
             const u32 take = (len - k) < 8 ? (u32)(len - k) : 8u;
             const u64 w = load_le(bytes, N, src + k, take);
-            if (staged) {
-                const u64 b = so - S0 + mis + k;
-                for (u32 t = 0; t < take; t++) buf[b + t] = (u8)(w >> (8 * t));
-            } else if (take == 8 && (((uintptr_t)(suf + so + k)) & 7) == 0) {
-                *(u64 *)(suf + so + k) = w;
-            } else {
-                for (u32 t = 0; t < take; t++) suf[so + k + t] = (u8)(w >> (8 * t));
-            }
+            const u64 b = so - S0 + mis + k;
+            for (u32 t = 0; t < take; t++) buf[b + t] = (u8)(w >> (8 * t));
         }
     }
-    if (!staged) return;  // uniform over the workgroup
     __syncthreads();
     const u32 nchunk = (u32)((span + mis + 15) / 16);
     for (u32 c = threadIdx.x; c < nchunk; c += CS_NT) {

@@ -528,13 +528,15 @@ def test_partition_encode_long_literals(pdms):
     _check_partition(synth.dn_strings(20_000, 300, 0.3, seed=8), 5, pdms)
 
 
+@pytest.mark.parametrize("long_literals", [False, True])
 @pytest.mark.parametrize("base", [7, 4096 + 9])
-def test_partition_encode_unaligned_suf_base(base):
+def test_partition_encode_unaligned_suf_base(base, long_literals):
     """Literals written at an odd offset of a shared buffer: bytes outside
-    [base, base + total) stay untouched and suf_off is absolute."""
-    s = synth.text_strings(20_000, seed=9, median=24)
-    _log(f"[partition] suf_base={base}")
-    g, perm, lcp, dist, ids, sb, so, fc = _partition(s, 4, True)
+    [base, base + total) stay untouched and suf_off is absolute (short
+    literals staged in LDS; whole 300-byte strings copied word by word)."""
+    s = synth.dn_strings(8_000, 300, 0.3, seed=10) if long_literals else synth.text_strings(20_000, seed=9, median=24)
+    _log(f"[partition] suf_base={base} long={long_literals}")
+    g, perm, lcp, dist, ids, sb, so, fc = _partition(s, 4, not long_literals)
     t = fc["total"]
     cap = base + t + 64
     out = dict(run_off=torch.empty_like(fc["run_off"]), lcp=torch.empty_like(fc["lcp"]),
