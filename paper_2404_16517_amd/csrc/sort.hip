@@ -1097,13 +1097,46 @@ __device__ __forceinline__ bool ws_finish(u32 e, u32 cnt, u64 ka, u64 kb, u64 kn
 
 __device__ __forceinline__ u32 hibit(u64 m) { return 63u - (u32)__clzll(m); }
 
+#define WS_DEEP 8  // further 7-byte keys a wavefront reads for runs of equal continuing keys
+
+__device__ __forceinline__ bool rkv_greater(u32 ra, u64 ka, u32 va, u32 rb, u64 kb, u32 vb)
+{
+    return ra != rb ? ra > rb : (ka != kb ? ka > kb : va > vb);
+}
+
+// ws_step on (run start, key, payload)
+__device__ __forceinline__ void ws_step3(u32 &rs, u64 &key, u32 &val, u32 e, u32 j, u32 k)
+{
+    const u32 pr = __shfl_xor(rs, (int)j, 64);
+    const u64 pk = __shfl_xor(key, (int)j, 64);
+    const u32 pv = __shfl_xor(val, (int)j, 64);
+    const bool want_small = ((e & j) == 0) == ((e & k) == 0);
+    if (want_small == rkv_greater(rs, key, val, pr, pk, pv)) {
+        rs = pr;
+        key = pk;
+        val = pv;
+    }
+}
+
+__device__ __forceinline__ bool shfl_down_b(bool b, u32 lane, bool from_next)
+{
+    const int d = __shfl_down((int)b, 1, 64);
+    return lane < 63 ? d != 0 : from_next;
+}
+
 // Segments of 2..128 strings, one wavefront each: bitonic sort of
-// (key, payload) in registers (element e = lane + 64 r, r = 0, 1), then LCPs
-// and next-round runs as in the LDS sort.  Next-round segments are collected
-// per workgroup and published with one atomic per counter.
+// (key, payload) in registers (element e = lane + 64 r, r = 0, 1), then LCPs.
+// Runs of equal continuing keys are not sent to the next round at once: the
+// wavefront reads their strings' next 7-byte keys (up to WS_DEEP times) and
+// sorts every run again by (run, key, payload), writing the LCPs of the
+// pairs each key separates; runs still tied then become next-round segments,
+// collected per workgroup and published with one atomic per counter.  (Equal
+// strings, common in text, so end inside the wavefront instead of costing a
+// workgroup per run in the next round's skip and key passes.)
 template <bool LOOP>
 __global__ __launch_bounds__(256) void k_wave_sort(const Seg *tiny, const u32 *ntinyp, u64 *keys, u32 *vals,
-                                                   const u64 *keyB, const u32 *valB, u32 *lcp, Seg *next, u32 *ctr)
+                                                   const u64 *keyB, const u32 *valB, u32 *lcp, Seg *next, u32 *ctr,
+                                                   const u8 *bytes, u64 N, const u64 *off)
 {
     __shared__ Seg nq[WS_SPB * (WS_MAX / 2)];
     __shared__ u32 nq_count, nq_tiles, nq_elems, nq_base;
@@ -1158,8 +1191,8 @@ __global__ __launch_bounds__(256) void k_wave_sort(const Seg *tiny, const u32 *n
                 }
             }
         }
-        if (e0 < cnt) { keys[g.begin + e0] = k0; vals[g.begin + e0] = v0; }
-        if (e1 < cnt) { keys[g.begin + e1] = k1; vals[g.begin + e1] = v1; }
+        if (e0 < cnt) keys[g.begin + e0] = k0;
+        if (e1 < cnt) keys[g.begin + e1] = k1;
         // neighbours in sorted order
         const u64 k0_last = __shfl(k0, 63, 64), k1_first = __shfl(k1, 0, 64);
         const u64 up0 = __shfl_up(k0, 1, 64), up1 = __shfl_up(k1, 1, 64);
@@ -1167,30 +1200,87 @@ __global__ __launch_bounds__(256) void k_wave_sort(const Seg *tiny, const u32 *n
         const u64 pa0 = up0, pa1 = lane ? up1 : k0_last;
         const u64 nx0 = lane < 63 ? dn0 : k1_first, nx1 = dn1;
         u32 l0 = 0, l1 = 0;
-        const bool r0 = ws_finish(e0, cnt, pa0, k0, nx0, g.depth, &l0);
-        const bool r1 = ws_finish(e1, cnt, pa1, k1, nx1, g.depth, &l1);
+        ws_finish(e0, cnt, pa0, k0, nx0, g.depth, &l0);
+        ws_finish(e1, cnt, pa1, k1, nx1, g.depth, &l1);
         // LCP writes (skipped for the first element and for equal full keys)
         if (e0 >= 1 && e0 < cnt && !(pa0 == k0 && (k0 & 0xFF) == 8)) lcp[g.begin + e0] = l0;
         if (e1 < cnt && !(pa1 == k1 && (k1 & 0xFF) == 8)) lcp[g.begin + e1] = l1;
-        // run starts, to find where each run of equal full keys begins
-        const u64 m0 = __ballot(e0 < cnt && (e0 == 0 || pa0 != k0));
-        const u64 m1 = __ballot(e1 < cnt && pa1 != k1);
         const u64 le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-        if (r0) {
-            const u32 f = hibit(m0 & le);
-            const Seg ns{g.begin + f, g.begin + e0 + 1, g.depth + 7, SEG_SKIP};
+        // tied with the predecessor: equal keys, both strings continue
+        bool t0 = e0 >= 1 && e0 < cnt && pa0 == k0 && (k0 & 0xFF) == 8;
+        bool t1 = e1 < cnt && pa1 == k1 && (k1 & 0xFF) == 8;
+        u32 dep = g.depth;
+        if (__ballot(t0 || t1)) {  // (uniform: most segments have no run of equal keys)
+        for (u32 it = 0; it < WS_DEEP; it++) {
+            // in a run: tied with the predecessor or the successor (e0's successor
+            // is e0 + 1, lane 63's is e1 of lane 0); every lane shuffles first
+            const bool f1 = __shfl((int)t1, 0, 64) != 0;
+            const bool n0 = shfl_down_b(t0, lane, f1), n1 = shfl_down_b(t1, lane, false);
+            const bool in0 = t0 || n0, in1 = t1 || n1;
+            if (!__ballot(in0 || in1)) break;  // (uniform)
+            dep += 7;
+            // run of every element: its first position (padding sorts last)
+            const u64 s0 = __ballot(!t0), s1 = __ballot(!t1);
+            const u64 ms = s1 & le;
+            u32 rs0 = e0 < cnt ? hibit(s0 & le) : 0xFFFFFFFFu;
+            u32 rs1 = e1 < cnt ? (ms ? 64u + hibit(ms) : hibit(s0)) : 0xFFFFFFFFu;
+            u64 q0 = e0 < cnt ? 0ull : ~0ull, q1 = e1 < cnt ? 0ull : ~0ull;
+            if (in0) {
+                const u64 o = off[v0];
+                q0 = make_key(bytes, N, o, off[v0 + 1] - o, dep);
+            }
+            if (in1) {
+                const u64 o = off[v1];
+                q1 = make_key(bytes, N, o, off[v1 + 1] - o, dep);
+            }
+            for (u32 k = 2; k <= P; k <<= 1) {
+                for (u32 j = k >> 1; j > 0; j >>= 1) {
+                    if (j == 64) {
+                        if (rkv_greater(rs0, q0, v0, rs1, q1, v1)) {
+                            const u32 tr = rs0; rs0 = rs1; rs1 = tr;
+                            const u64 tq = q0; q0 = q1; q1 = tq;
+                            const u32 tv = v0; v0 = v1; v1 = tv;
+                        }
+                    } else {
+                        ws_step3(rs0, q0, v0, e0, j, k);
+                        if (P == 128) ws_step3(rs1, q1, v1, e1, j, k);
+                    }
+                }
+            }
+            const u32 rp0 = __shfl_up(rs0, 1, 64), rl0 = __shfl(rs0, 63, 64), ru1 = __shfl_up(rs1, 1, 64);
+            const u32 rp1 = lane ? ru1 : rl0;
+            const u64 qp0 = __shfl_up(q0, 1, 64), ql0 = __shfl(q0, 63, 64), qu1 = __shfl_up(q1, 1, 64);
+            const u64 qp1 = lane ? qu1 : ql0;
+            const bool same0 = e0 >= 1 && e0 < cnt && rp0 == rs0;  // same run as the predecessor
+            const bool same1 = e1 < cnt && rp1 == rs1;
+            t0 = same0 && qp0 == q0 && (q0 & 0xFF) == 8;
+            t1 = same1 && qp1 == q1 && (q1 & 0xFF) == 8;
+            if (same0 && !t0) lcp[g.begin + e0] = qp0 != q0 ? key_lcp(qp0, q0, dep) : dep + (u32)(q0 & 0xFF);
+            if (same1 && !t1) lcp[g.begin + e1] = qp1 != q1 ? key_lcp(qp1, q1, dep) : dep + (u32)(q1 & 0xFF);
+        }
+        // still tied: the last element of each run publishes it for the next round
+        const bool f1 = __shfl((int)t1, 0, 64) != 0;
+        const bool n0 = shfl_down_b(t0, lane, f1), n1 = shfl_down_b(t1, lane, false);
+        const bool end0 = t0 && !n0, end1 = t1 && !n1;
+        const u64 s0 = __ballot(!t0), s1 = __ballot(!t1);
+        if (end0) {
+            const u32 f = hibit(s0 & le);
+            const Seg ns{g.begin + f, g.begin + e0 + 1, dep + 7, SEG_SKIP};
             nq[atomicAdd(&nq_count, 1u)] = ns;
             atomicAdd(&nq_tiles, (ns.end - ns.begin + ETILE - 1) / ETILE);
             atomicAdd(&nq_elems, ns.end - ns.begin);
         }
-        if (r1) {
-            const u64 mm = m1 & le;
-            const u32 f = mm ? 64u + hibit(mm) : hibit(m0);
-            const Seg ns{g.begin + f, g.begin + e1 + 1, g.depth + 7, SEG_SKIP};
+        if (end1) {
+            const u64 mm = s1 & le;
+            const u32 f = mm ? 64u + hibit(mm) : hibit(s0);
+            const Seg ns{g.begin + f, g.begin + e1 + 1, dep + 7, SEG_SKIP};
             nq[atomicAdd(&nq_count, 1u)] = ns;
             atomicAdd(&nq_tiles, (ns.end - ns.begin + ETILE - 1) / ETILE);
             atomicAdd(&nq_elems, ns.end - ns.begin);
         }
+        }
+        if (e0 < cnt) vals[g.begin + e0] = v0;
+        if (e1 < cnt) vals[g.begin + e1] = v1;
     }
     __syncthreads();
     if (threadIdx.x == 0 && nq_count) {
@@ -1419,10 +1509,10 @@ static int round_tail(RoundCtx &C, const u32 *h)
         SS_PROF("k_wave_sort", st, known ? (double)h[C_TINYN] * 28.0 : 0.0);  // key+payload in/out, LCP out
         if (known)
             k_wave_sort<false><<<grid_of(h[C_TINY], WS_SPB, 1u << 30), 256, 0, st>>>(
-                w.tiny, w.ctr + C_TINY, w.keyA, J.vals, w.keyB, w.valB, lcp, w.nxt, w.ctr);
+                w.tiny, w.ctr + C_TINY, w.keyA, J.vals, w.keyB, w.valB, lcp, w.nxt, w.ctr, J.bytes, J.N, J.off);
         else
             k_wave_sort<true><<<grid_of(n / 2, WS_SPB, resident(k_wave_sort<true>, 256)), 256, 0, st>>>(
-                w.tiny, w.ctr + C_TINY, w.keyA, J.vals, w.keyB, w.valB, lcp, w.nxt, w.ctr);
+                w.tiny, w.ctr + C_TINY, w.keyA, J.vals, w.keyB, w.valB, lcp, w.nxt, w.ctr, J.bytes, J.N, J.off);
         SS_CHECK_LAUNCH();
     }
     if (!known || h[C_SMALL] > 0) {

@@ -239,6 +239,28 @@ def test_sort_text_with_duplicates():
     _check_sort(s, "text 200k")
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_sort_long_ties_in_small_segments(seed):
+    """Groups of 2..90 strings that share 10..300 bytes (past several 7-byte
+    keys and past the wavefront sort's own further keys), exact duplicates
+    of every length among them, strings that are prefixes of others: the
+    small-segment sorts resolve some ties themselves and hand the rest on."""
+    rng = random.Random(seed)
+    out = []
+    for _ in range(1500):
+        pre = bytes(rng.choice(b"ab") for _ in range(rng.randint(10, 300)))
+        for _ in range(rng.randint(2, 90)):
+            k = rng.random()
+            if k < 0.3:
+                out.append(pre)  # duplicates of the prefix itself
+            elif k < 0.5:
+                out.append(pre[: rng.randint(0, len(pre))])  # a prefix
+            else:
+                out.append(pre + bytes(rng.choice(b"xy") for _ in range(rng.randint(0, 12))))
+    rng.shuffle(out)
+    _check_sort(synth.from_list(out), f"long ties {seed}")
+
+
 def test_sort_batch_equals_single_sorts():
     sets, bounds = synth.random_sets(64, 10, 3000, seed=3)
     _log(f"[batch] n={sets.n}")
