@@ -1408,40 +1408,59 @@ __global__ __launch_bounds__(DD_NT) void k_dd_bucket(const u32 *hm, u32 G, u32 N
 }
 
 // Finish the active strings whose key is unique (or whose length is <= l):
-// dist = min(len, l).  The others are appended to the next active list
-// (one atomic per workgroup; lists keep input order within a workgroup),
-// with their key for the next round when a two-round pass computed it.
+// dist = min(len, l).  The others are appended to the next active list, with
+// their key for the next round when a two-round pass computed it.  Each
+// workgroup takes DD_PER x 256 list entries (lanes on consecutive entries)
+// and reserves its part of the next list with one atomic: every reservation
+// on that one counter is a round trip to the point where the chip's L2s meet,
+// and they queue, so fewer and larger reservations.  Lists keep input order
+// within a workgroup.
+#define DD_PER 8
+
 __global__ __launch_bounds__(256) void k_dedup(const u64 *keys, int kin, const u32 *act, const u32 *cnt,
                                                const u64 *off, u64 l, int mode, u32 *dist, u32 *next, u32 *ncnt,
                                                const u64 *carry, u64 *carry_out, const u8 *dupf)
 {
-    __shared__ u32 wcount[4], base;
+    __shared__ u32 wcount[DD_PER][4], base;
     const u32 A = *cnt;
-    const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-    bool stay = false;
-    u32 i = 0;
-    if (j < A) {
-        i = act ? act[j] : j;
-        const u64 len = off[i + 1] - off[i];
-        const bool dup = mode == DM_ALLDUP || (mode == DM_TABLE && dupf[j] != 0);
-        stay = dup && len > l;
-        if (!stay) dist[i] = (u32)(len < l ? len : l);
-    }
-    const u64 b = __ballot(stay);
     const u32 lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) wcount[w] = (u32)__popcll(b);
+    const u32 j0 = blockIdx.x * (256u * DD_PER);
+    u32 iq[DD_PER];
+    u64 bq[DD_PER];
+#pragma unroll
+    for (u32 q = 0; q < DD_PER; q++) {
+        const u32 j = j0 + q * 256 + threadIdx.x;
+        bool stay = false;
+        u32 i = 0;
+        if (j < A) {
+            i = act ? act[j] : j;
+            const u64 len = off[i + 1] - off[i];
+            const bool dup = mode == DM_ALLDUP || (mode == DM_TABLE && dupf[j] != 0);
+            stay = dup && len > l;
+            if (!stay) dist[i] = (u32)(len < l ? len : l);
+        }
+        iq[q] = i;
+        bq[q] = __ballot(stay);
+        if (lane == 0) wcount[q][w] = (u32)__popcll(bq[q]);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const u32 t = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+        u32 t = 0;
+        for (u32 q = 0; q < DD_PER; q++) t += wcount[q][0] + wcount[q][1] + wcount[q][2] + wcount[q][3];
         base = t ? atomicAdd(ncnt, t) : 0u;
     }
     __syncthreads();
-    u32 woff = base;
-    for (u32 k = 0; k < w; k++) woff += wcount[k];
-    if (stay) {
-        const u32 slot = woff + (u32)__popcll(b & lanemask_lt());
-        next[slot] = i;
-        if (carry) carry_out[slot] = carry[j];  // next round's key, already computed
+    u32 oq = base;  // first slot of row q (rows in list order, wavefronts in order within a row)
+#pragma unroll
+    for (u32 q = 0; q < DD_PER; q++) {
+        u32 o = oq;
+        for (u32 k = 0; k < w; k++) o += wcount[q][k];
+        if ((bq[q] >> lane) & 1) {
+            const u32 slot = o + (u32)__popcll(bq[q] & lanemask_lt());
+            next[slot] = iq[q];
+            if (carry) carry_out[slot] = carry[j0 + q * 256 + threadIdx.x];  // next round's key, already computed
+        }
+        oq += wcount[q][0] + wcount[q][1] + wcount[q][2] + wcount[q][3];
     }
 }
 
@@ -1979,7 +1998,7 @@ static int pd_run(const uint8_t *bytes, uint64_t N, const uint64_t *offsets, uin
         {
             // list entry, offsets, key, slot, dist or next entry (and a carried key)
             SS_PROF("k_dedup", st, (double)Ah * ((mode == DM_TABLE ? 25.0 : 24.0) + (pend_next ? 16.0 : 0.0)));
-            k_dedup<<<(unsigned)ceil_div(Ah, 256), 256, 0, st>>>(keys, kin, act, ctr + ci, offsets, l, mode,
+            k_dedup<<<(unsigned)ceil_div(Ah, 256 * DD_PER), 256, 0, st>>>(keys, kin, act, ctr + ci, offsets, l, mode,
                                                                  dist_approx, nxt, ctr + (ci ^ 1), pend_next,
                                                                  w.keysC, dupf);
         }
