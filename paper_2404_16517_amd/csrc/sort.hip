@@ -65,8 +65,13 @@ __device__ __forceinline__ void wave_add(u32 v, u32 *counter)
 
 __device__ __forceinline__ u32 seg_of_tile(const u32 *tstart, u32 nseg, u32 t)
 {
-    // largest s with tstart[s] <= t (tstart has nseg+1 entries, strictly increasing)
-    u32 lo = 0, hi = nseg;
+    // largest s with tstart[s] <= t (tstart has nseg+1 entries, strictly
+    // increasing).  Every segment has a tile, so s <= t, and all but
+    // extra = tstart[nseg] - nseg segments have one, so s >= t - extra: with
+    // many small segments (one tile each) the search is short.
+    const u32 extra = tstart[nseg] - nseg;
+    u32 lo = t > extra ? t - extra : 0u;
+    u32 hi = (t < nseg - 1 ? t : nseg - 1) + 1;
     while (hi - lo > 1) {
         u32 mid = (lo + hi) >> 1;
         if (tstart[mid] <= t) lo = mid;
