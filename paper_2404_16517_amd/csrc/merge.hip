@@ -833,8 +833,34 @@ __global__ __launch_bounds__(MW_NT, 6) void k_merge_level(MergeLevel M, u32 nblo
     if (dd < dw) {
         cnt = min((u32)MW_IPT, dw - dd);
         u64 tmp;
-        // co-rank inside the window (indices relative to a0 / b0)
+        // co-rank inside the window (indices relative to a0 / b0).  Along the
+        // diagonal the cached keys alone say "A first" up to some x1, "tie"
+        // (equal keys of continuing strings) up to x2, then "B first"; both
+        // bounds are found from the keys, and only [x1, x2) is searched with
+        // string comparisons, so a wavefront compares strings once per
+        // halving of its widest tie range instead of at every search step
+        // where some lane's keys tie.
         u32 xlo = dd > wb ? dd - wb : 0, xhi = dd < wa ? dd : wa;
+        auto key_side = [&](u32 x) -> int {  // -1: A first by the keys, 0: tie, 1: B first
+            const u64 ka = sK[baseA + x], kb = sK[baseB + (dd - x - 1)];
+            if (ka != kb) return ka < kb ? -1 : 1;
+            return (ka & 0xFF) < 8 ? -1 : 0;  // equal strings ending in the key: A first
+        };
+        u32 x1lo = xlo, x1hi = xhi;
+        while (x1lo < x1hi) {
+            const u32 mid = (x1lo + x1hi) >> 1;
+            if (key_side(mid) < 0) x1lo = mid + 1;
+            else x1hi = mid;
+        }
+        // (no tie at x1: the range is empty, as it is wherever keys decide)
+        u32 x2lo = x1lo, x2hi = (x1lo < xhi && key_side(x1lo) == 0) ? xhi : x1lo;
+        while (x2lo < x2hi) {
+            const u32 mid = (x2lo + x2hi) >> 1;
+            if (key_side(mid) <= 0) x2lo = mid + 1;
+            else x2hi = mid;
+        }
+        xlo = x1lo;
+        xhi = x2lo;
         while (xlo < xhi) {
             const u32 mid = (xlo + xhi) >> 1;
             const u32 ia = baseA + mid, ib = baseB + (dd - mid - 1);
