@@ -80,10 +80,10 @@ __device__ __forceinline__ u32 seg_of_tile(const u32 *tstart, u32 nseg, u32 t)
     return lo;
 }
 
-template <class T>
+template <class T, int NTB = NT>
 __device__ __forceinline__ T block_min(T v)
 {
-    __shared__ T red[NT / 64];
+    __shared__ T red[NTB / 64];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         T y = __shfl_xor(v, o, 64);
@@ -92,7 +92,7 @@ __device__ __forceinline__ T block_min(T v)
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     T r = red[0];
-    for (int w = 1; w < NT / 64; w++) r = red[w] < r ? red[w] : r;
+    for (int w = 1; w < NTB / 64; w++) r = red[w] < r ? red[w] : r;
     __syncthreads();
     return r;
 }
@@ -289,16 +289,16 @@ __device__ __forceinline__ u32 skip_cmp(const u8 *bytes, u64 N, const u8 *R, con
 #define SEED_OPEN 0xFFFFFFFFu
 // (the grid-stride form keeps its loop state live as well: five workgroups
 // per compute unit give it the registers to do so without spilling)
-template <bool LOOP, bool SEED = false>
-__global__ __launch_bounds__(NT, LOOP ? 5 : 6) void k_skip(const Seg *segs, const u32 *tstart, const u32 *nsegp,
+template <bool LOOP, bool SEED = false, int NTB = NT>
+__global__ __launch_bounds__(NTB, (LOOP ? 5 : 6) * (NT / NTB)) void k_skip(const Seg *segs, const u32 *tstart, const u32 *nsegp,
                                              const u8 *bytes, u64 N, const u64 *off,
                                              const u32 *perm, u32 *skipv, u64 *mword, uint2 *mpr,
                                              const u32 *seed_ok = nullptr)
 {
     __shared__ u64 fsw[SKFS];
-    __shared__ __attribute__((aligned(16))) u8 rows[(NT / 64) * SKR];
-    __shared__ u64 wwa[NT / 64][SKB];  // per wavefront: window start of each member
-    __shared__ u32 wwn[NT / 64][SKB];  // ... and its chunk count
+    __shared__ __attribute__((aligned(16))) u8 rows[(NTB / 64) * SKR];
+    __shared__ u64 wwa[NTB / 64][SKB];  // per wavefront: window start of each member
+    __shared__ u32 wwn[NTB / 64][SKB];  // ... and its chunk count
     const u32 nseg = *nsegp;
     const u32 ntiles = LOOP ? tstart[nseg] : 0u;
     const bool sok = SEED && *seed_ok != 0;  // uniform
@@ -316,8 +316,8 @@ __global__ __launch_bounds__(NT, LOOP ? 5 : 6) void k_skip(const Seg *segs, cons
         u32 sb = 0xFFFFFFFFu;
         bool open = false;
 #pragma unroll 8
-        for (u32 k = 0; k < ETILE / NT; k++) {
-            const u32 i = b0 + k * NT + threadIdx.x;
+        for (u32 k = 0; k < ETILE / NTB; k++) {
+            const u32 i = b0 + k * NTB + threadIdx.x;
             if (i < b1) {
                 const uint2 sp = mpr[i];
                 open |= sp.y == SEED_OPEN;
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(NT, LOOP ? 5 : 6) void k_skip(const Seg *segs, cons
             }
         }
         if (!__syncthreads_or(open)) {  // (uniform)
-            const u32 bm = block_min(sb);
+            const u32 bm = block_min<u32, NTB>(sb);
             if (threadIdx.x == 0) atomicMin(&skipv[sg], bm);
             continue;
         }
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(NT, LOOP ? 5 : 6) void k_skip(const Seg *segs, cons
     const u32 fl = (u32)(off[f + 1] - fo);
     const u32 depth = g.depth;
     const u32 fd = fl > depth ? fl - depth : 0;  // first-string bytes from depth
-    for (u32 q = threadIdx.x; q < SKFS; q += NT) {
+    for (u32 q = threadIdx.x; q < SKFS; q += NTB) {
         const u32 k = 8 * q;
         fsw[q] = k < fd ? load_le(bytes, N, fo + depth + k, (fd - k) < 8 ? fd - k : 8u) : 0ull;
     }
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(NT, LOOP ? 5 : 6) void k_skip(const Seg *segs, cons
     const u64 babs = (u64)(uintptr_t)bytes;
     bool longw = false;  // window size of the next batch (uniform over the wavefront)
     u32 best = 0xFFFFFFFFu;
-    for (u32 i0 = b0 + wv * SKB; i0 < b1; i0 += (NT / 64) * SKB) {
+    for (u32 i0 = b0 + wv * SKB; i0 < b1; i0 += (NTB / 64) * SKB) {
         const u32 i = i0 + sl;
         const bool valid = i < b1;
         u64 o = 0;
@@ -429,13 +429,13 @@ __global__ __launch_bounds__(NT, LOOP ? 5 : 6) void k_skip(const Seg *segs, cons
             }
         }
     }
-    const u32 bm = block_min(best);  // (ends with a barrier: fsw and the rows are free again)
+    const u32 bm = block_min<u32, NTB>(best);  // (ends with a barrier: fsw and the rows are free again)
     if (threadIdx.x == 0) atomicMin(&skipv[sg], bm);
     }
 }
 
-template <bool LOOP>
-__global__ __launch_bounds__(NT) void k_keys(const Seg *segs, const u32 *tstart, const u32 *nsegp,
+template <bool LOOP, int NTB = NT>
+__global__ __launch_bounds__(NTB) void k_keys(const Seg *segs, const u32 *tstart, const u32 *nsegp,
                                              const u8 *bytes, u64 N, const u64 *off,
                                              const u32 *perm, const u32 *skipv, const u64 *mword,
                                              const uint2 *mpr, u64 *keys)
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(NT) void k_keys(const Seg *segs, const u32 *tstart,
     const u32 b1 = min(g.end, b0 + ETILE);
     if (!(g.aux & SEG_SKIP)) {
         const u64 d = g.depth;
-        for (u32 i = b0 + threadIdx.x; i < b1; i += NT) {
+        for (u32 i = b0 + threadIdx.x; i < b1; i += NTB) {
             const u32 p = perm[i];
             const u64 o = off[p], l = off[p + 1] - o;
             keys[i] = make_key(bytes, N, o, l, d);
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(NT) void k_keys(const Seg *segs, const u32 *tstart,
         fw = load_be(bytes, N, fo + d, r < 7 ? (u32)r : 7u);
     }
     __syncthreads();
-    for (u32 i = b0 + threadIdx.x; i < b1; i += NT) {
+    for (u32 i = b0 + threadIdx.x; i < b1; i += NTB) {
         const uint2 pr = mpr[i];
         const u32 k = pr.x - (u32)d;  // bytes shared with the first string beyond d
         u64 data = fw;
@@ -1428,6 +1428,11 @@ static int round_head(RoundCtx &C, Known nact, Known atiles, u64 round_elems, bo
         const bool sd = first && atiles.yes && J.seed_pos;
         SS_PROF("k_skip", st, (double)round_elems * (sd ? 8.0 : 44.0));
         if (sd) k_skip<false, true><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, J.seed_word, J.seed_pos, J.seed_ok);
+        // (tiles of small segments, as later rounds leave them, hold few
+        // members: one wavefront per tile then keeps four times as many in
+        // flight)
+        else if (atiles.yes && round_elems < 64ull * atiles.v)
+            k_skip<false, false, 64><<<tg, 64, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr);
         else if (atiles.yes) k_skip<false><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr);
         else k_skip<true><<<grid_of(n, ETILE, resident(k_skip<true>, NT)), NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, w.mword, w.mpr);
     }
@@ -1438,7 +1443,9 @@ static int round_head(RoundCtx &C, Known nact, Known atiles, u64 round_elems, bo
         u64 *mw = sd ? J.seed_word : w.mword;
         uint2 *mp = sd ? J.seed_pos : w.mpr;
         SS_PROF("k_keys", st, (double)round_elems * 24.0);  // mismatch record in, key out
-        if (atiles.yes) k_keys<false><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, mw, mp, w.keyA);
+        if (atiles.yes && round_elems < 64ull * atiles.v)  // (small tiles: one wavefront each, as in the skip)
+            k_keys<false, 64><<<tg, 64, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, mw, mp, w.keyA);
+        else if (atiles.yes) k_keys<false><<<tg, NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, mw, mp, w.keyA);
         else k_keys<true><<<grid_of(n, ETILE, resident(k_keys<true>, NT)), NT, 0, st>>>(w.act, w.tstart, nactp, J.bytes, J.N, J.off, J.vals, w.skipv, mw, mp, w.keyA);
     }
     SS_CHECK_LAUNCH();
