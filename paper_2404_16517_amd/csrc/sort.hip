@@ -1102,7 +1102,7 @@ __device__ __forceinline__ bool ws_finish(u32 e, u32 cnt, u64 ka, u64 kb, u64 kn
 
 __device__ __forceinline__ u32 hibit(u64 m) { return 63u - (u32)__clzll(m); }
 
-#define WS_DEEP 8  // further 7-byte keys a wavefront reads for runs of equal continuing keys
+#define WS_DEEP 3  // further 7-byte keys a wavefront reads for runs of equal continuing keys
 
 __device__ __forceinline__ bool rkv_greater(u32 ra, u64 ka, u32 va, u32 rb, u64 kb, u32 vb)
 {
