@@ -429,15 +429,16 @@ __global__ void k_add_base(u64 *a, u64 n, u64 base)
 }
 
 #define CS_NT 256     // strings per workgroup in the literal copy (one thread each)
-#define CS_BUF 16384  // LDS staging bytes
+#define CS_BUF 4096   // LDS staging bytes (short literals: at most 16 B per string on average)
 
 // Literal bytes of strings [i0, i0+256) (string i's bytes [e_i, d_i) go to
 // suf[suf_off[i] ..]; lit_src[i] = offset of byte e_i, written in sorted order
 // by k_fc_meta).  When the workgroup's output span fits the LDS buffer (short
-// literals, as distinguishing prefixes leave them) each thread reads its
+// literals, as distinguishing prefixes of D/N strings leave them) each thread reads its
 // string's literal with aligned 8-byte words, the literals are packed in LDS
 // and written out in aligned 16-byte words (bytes at the two ends, which
-// neighbouring workgroups share, one by one).  Otherwise (long literals) 16
+// neighbouring workgroups share, one by one).  Otherwise (longer literals,
+// where one thread's word loop and byte stores cost more than idle lanes) 16
 // lanes copy one string at a time: every lane an aligned 8-byte word of the
 // destination, read from the source at whatever alignment it has, and the
 // unaligned bytes at the two ends one by one.
