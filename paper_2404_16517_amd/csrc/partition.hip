@@ -434,14 +434,15 @@ __global__ void k_add_base(u64 *a, u64 n, u64 base)
 // Literal bytes of strings [i0, i0+256) (string i's bytes [e_i, d_i) go to
 // suf[suf_off[i] ..]; lit_src[i] = offset of byte e_i, written in sorted order
 // by k_fc_meta).  When the workgroup's output span fits the LDS buffer (short
-// literals, as distinguishing prefixes of D/N strings leave them) each thread reads its
-// string's literal with aligned 8-byte words, the literals are packed in LDS
-// and written out in aligned 16-byte words (bytes at the two ends, which
-// neighbouring workgroups share, one by one).  Otherwise (longer literals,
-// where one thread's word loop and byte stores cost more than idle lanes) 16
-// lanes copy one string at a time: every lane an aligned 8-byte word of the
-// destination, read from the source at whatever alignment it has, and the
-// unaligned bytes at the two ends one by one.
+// literals, as distinguishing prefixes of D/N strings leave them) each
+// thread reads its string's literal with aligned 8-byte words, the literals
+// are packed in LDS and written out in aligned 16-byte words (bytes at the
+// two ends, which neighbouring workgroups share, one by one).  Otherwise
+// (longer literals, where one thread's word loop and byte stores cost more
+// than idle lanes) 4, 8 or 16 lanes, by the workgroup's average literal, copy
+// one string at a time: every lane an aligned 8-byte word of the destination,
+// read from the source at whatever alignment it has, and the unaligned bytes
+// at the two ends one by one.
 __global__ __launch_bounds__(CS_NT) void k_fc_copy(const u8 *bytes, u64 N, u32 n, const u64 *lit_src,
                                                    const u64 *suf_off, u8 *suf)
 {
@@ -454,20 +455,20 @@ __global__ __launch_bounds__(CS_NT) void k_fc_copy(const u8 *bytes, u64 N, u32 n
     const u32 mis = (u32)(((uintptr_t)(suf + S0)) & 15);  // buf[mis] holds output byte S0
     const bool staged = span + mis <= CS_BUF;
     if (!staged) {  // uniform over the workgroup
-        const u32 gl = threadIdx.x & 15;
-        for (u32 i = i0 + (threadIdx.x >> 4); i < i1; i += CS_NT / 16) {
+        // lanes per string by the workgroup's average literal: 4 up to 48
+        // bytes, 8 up to 128, else 16
+        const u64 avg = span / (i1 - i0);
+        const u32 lsh = avg <= 48 ? 2u : (avg <= 128 ? 3u : 4u), L = 1u << lsh;
+        const u32 gl = threadIdx.x & (L - 1);
+        for (u32 i = i0 + (threadIdx.x >> lsh); i < i1; i += CS_NT >> lsh) {
             const u64 so = suf_off[i], len = suf_off[i + 1] - so, src = lit_src[i];
             const u32 mis8 = (u32)(((uintptr_t)(suf + so)) & 7);
             const u64 head = mis8 ? (8u - mis8 < len ? 8u - mis8 : len) : 0u;  // bytes up to an aligned word
             const u64 words = (len - head) / 8;
-            const u64 tail = (len - head) & 7;
-            if (gl < head) suf[so + gl] = bytes[src + gl];
-            for (u64 q = gl; q < words; q += 16)
+            for (u64 t = gl; t < head; t += L) suf[so + t] = bytes[src + t];
+            for (u64 q = gl; q < words; q += L)
                 *(u64 *)(suf + so + head + 8 * q) = load_le(bytes, N, src + head + 8 * q, 8u);
-            if (gl < tail) {
-                const u64 t = head + 8 * words + gl;
-                suf[so + t] = bytes[src + t];
-            }
+            for (u64 t = head + 8 * words + gl; t < len; t += L) suf[so + t] = bytes[src + t];
         }
         return;
     }

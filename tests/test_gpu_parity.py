@@ -550,6 +550,13 @@ def test_partition_encode_long_literals(pdms):
     _check_partition(synth.dn_strings(20_000, 300, 0.3, seed=8), 5, pdms)
 
 
+@pytest.mark.parametrize("median", [30, 90])
+def test_partition_encode_medium_literals(median):
+    """Whole text strings of median 30 and 90 bytes as literals: workgroups
+    past the staging buffer copy them 4 or 8 lanes per string."""
+    _check_partition(synth.text_strings(20_000, seed=11 + median, median=median), 4, False)
+
+
 @pytest.mark.parametrize("long_literals", [False, True])
 @pytest.mark.parametrize("base", [7, 4096 + 9])
 def test_partition_encode_unaligned_suf_base(base, long_literals):
