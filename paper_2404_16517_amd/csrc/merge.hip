@@ -861,37 +861,67 @@ __global__ __launch_bounds__(MW_NT, 6) void k_merge_level(MergeLevel M, u32 nblo
         }
         xlo = x1lo;
         xhi = x2lo;
+        // (the LCPs of the last probes that moved each bound: the pairs on
+        // both sides of the co-rank, used below)
+        u64 lcp_lo = 0, lcp_hi = 0;
+        bool moved_lo = false, moved_hi = false;
         while (xlo < xhi) {
             const u32 mid = (xlo + xhi) >> 1;
             const u32 ia = baseA + mid, ib = baseB + (dd - mid - 1);
-            if (cmp_elem(V, sG[ia], sK[ia], sG[ib], sK[ib], min3u(sF[ia], c, sF[ib]), C, &tmp) <= 0) xlo = mid + 1;
-            else xhi = mid;
+            if (cmp_elem(V, sG[ia], sK[ia], sG[ib], sK[ib], min3u(sF[ia], c, sF[ib]), C, &tmp) <= 0) {
+                xlo = mid + 1;
+                lcp_lo = tmp;
+                moved_lo = true;
+            } else {
+                xhi = mid;
+                lcp_hi = tmp;
+                moved_hi = true;
+            }
         }
         u32 a = xlo, b = dd - xlo;  // relative to the window
         const u32 ga = a0 + a, gb = b0 + b;  // relative to the runs
         u32 ha = 0, hb = 0;
         if (d0 + dd > 0) {
-            // the previous output is A[ga-1] or B[gb-1] (LDS slots baseA+a-1 / baseB+b-1)
-            bool lastA;
+            // The previous output is A[ga-1] or B[gb-1] (LDS slots pa / pb).
+            // The LCPs across the co-rank, u = lcp(A[a-1], B[b]) and
+            // w = lcp(B[b-1], A[a]), are those of the search's last probes,
+            // or else the keys decide them (a pair outside the tie range);
+            // with p = lcp(A[a-1], A[a]) and q = lcp(B[b-1], B[b]) they say
+            // which predecessor is the larger: of two strings not above X,
+            // the one sharing more with X is the larger.  Only when both
+            // tests tie are the two predecessors compared.
             const u32 pa = baseA + a - 1, pb = baseB + b - 1;
-            if (ga == 0) lastA = false;
-            else if (gb == 0) lastA = true;
-            else lastA = cmp_elem(V, sG[pa], sK[pa], sG[pb], sK[pb], min3u(sF[pa], c, sF[pb]), C, &tmp) > 0;
-            if (lastA) {
-                if (a < wa) ha = sL[baseA + a];
-                if (b < wb) {
-                    cmp_elem(V, sG[pa], sK[pa], sG[baseB + b], sK[baseB + b], min3u(sF[pa], c, sF[baseB + b]), C,
-                             &tmp);
-                    hb = (u32)tmp;
-                }
+            const bool hasA = a < wa, hasB = b < wb;
+            auto pair_lcp = [&](u32 ix, u32 iy, bool rec, u64 l) -> u32 {
+                if (rec) return (u32)l;
+                u64 t;
+                cmp_key(sK[ix], sK[iy], C, &t, [&](u64 *ll) { return fc_cmp(V, sG[ix], sG[iy], C + 7, ll); });
+                return (u32)t;
+            };
+            const u32 w = (hasA && gb > 0) ? pair_lcp(baseA + a, pb, moved_hi && xhi == a, lcp_hi) : 0u;
+            const u32 u = (hasB && ga > 0) ? pair_lcp(pa, baseB + b, moved_lo && xlo == a, lcp_lo) : 0u;
+            const u32 p = hasA ? sL[baseA + a] : 0u, q = hasB ? sL[baseB + b] : 0u;
+            bool lastA;
+            if (ga == 0) {
+                lastA = false;
+            } else if (gb == 0) {
+                lastA = true;
             } else {
-                if (b < wb) hb = sL[baseB + b];
-                if (a < wa) {
-                    cmp_elem(V, sG[pb], sK[pb], sG[baseA + a], sK[baseA + a], min3u(sF[pb], c, sF[baseA + a]), C,
-                             &tmp);
-                    ha = (u32)tmp;
+                int dec = 0;
+                u32 bnd = 0;
+                if (hasA) {
+                    if (p != w) dec = p > w ? 1 : -1;
+                    bnd = p < w ? p : w;
                 }
+                if (dec == 0 && hasB) {
+                    if (u != q) dec = u > q ? 1 : -1;
+                    const u32 bq = u < q ? u : q;
+                    bnd = bq > bnd ? bq : bnd;
+                }
+                lastA = dec != 0 ? dec > 0 : cmp_elem(V, sG[pa], sK[pa], sG[pb], sK[pb], bnd, C, &tmp) > 0;
             }
+            ha = hasA ? (lastA ? p : w) : 0u;
+            hb = hasB ? (lastA ? u : q) : 0u;
         }
 #pragma unroll
         for (u32 k = 0; k < MW_IPT; k++) {
