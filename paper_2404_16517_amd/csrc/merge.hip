@@ -1124,8 +1124,9 @@ __device__ __forceinline__ u32 run_of(const u64 *P, u32 k, u64 x)
     return lo;
 }
 
-// 7 elements per thread: the apply kernel's LDS operators (28 KB) then fit
-// five workgroups per compute unit
+// 7 elements per thread: the apply kernel's LDS operators take 28 KB; it runs
+// four workgroups per compute unit, with the registers to keep its elements'
+// entries and LCPs for the output pass without spilling
 #define MS_PER 7
 #define MS_ITEMS (256 * MS_PER)  // elements per workgroup
 
@@ -1382,7 +1383,7 @@ __global__ __launch_bounds__(1024) void k_mscan_top(MOp *blk, u32 nb)
 
 // Phase 3: every element's inclusive operator -> G, L, F, K (written with
 // consecutive lanes on consecutive elements).
-__global__ __launch_bounds__(256, 5) void k_mscan_apply(MScan S, const MOp *blk, u32 *G, u32 *L, u32 *F, u64 *K)
+__global__ __launch_bounds__(256, 4) void k_mscan_apply(MScan S, const MOp *blk, u32 *G, u32 *L, u32 *F, u64 *K)
 {
     __shared__ MOp ops[MS_ITEMS];
     const u64 x0 = (u64)blockIdx.x * MS_ITEMS;
