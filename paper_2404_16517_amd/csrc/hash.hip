@@ -1178,7 +1178,8 @@ __global__ __launch_bounds__(256, 3) void k_hash_first_deep(PassArgs A, RoundW r
     hash_pass<true>(A, rw, &F);
 }
 
-__global__ __launch_bounds__(256, 4) void k_hash_first_lazy(PassArgs A, RoundW rw, FirstArgs F)
+// Three workgroups per CU: at four the pass spills 36 bytes per lane.
+__global__ __launch_bounds__(256, 3) void k_hash_first_lazy(PassArgs A, RoundW rw, FirstArgs F)
 {
     hash_pass<true, true>(A, rw, &F);
 }
