@@ -12,7 +12,13 @@ properties that hold at any size:
   (D/N 0.3), built from the D/N closed forms: the merged order and LCPs equal
   the closed forms, with full strings and with distinguishing prefixes only;
 * 4096 independent sets of 1e3..1e6 strings (lengths 8..256): every set with
-  index = 0 mod 64, the smallest and the largest against the oracle's sort.
+  index = 0 mod 64, the smallest and the largest against the oracle's sort;
+* the whole PDMS step on 16M D/N strings of 500 bytes (D/N 0.5, 16 virtual
+  PEs, sampling factor 2) in the benchmark's launch configuration (seeded
+  first hash pass, later doubling rounds on a second stream beside the sort),
+  twice on the same buffers: the merged order and LCPs by the oracle's check
+  of every adjacent pair, dist by the oracle from them, and every output
+  against the D/N closed forms.
 """
 import numpy as np
 import pytest
@@ -92,3 +98,35 @@ def test_4096_sets_of_1e3_to_1e6_strings_sampled_against_the_oracle():
         np.testing.assert_array_equal(u32(perm[a:c]), p_ref, err_msg=f"set {j}")
         np.testing.assert_array_equal(u32(lcp[a:c]), oracle.lcp(b, o, p_ref), err_msg=f"set {j}")
     _log(f"[full] 4096 sets: {len(pick)} sets checked")
+
+
+def test_dn_16M_pdms_step_in_the_benchmark_configuration():
+    import bench
+    n, length, ratio, pes, v = 16_000_000, 500, 0.5, 16, 2
+    _log("[full] D/N 16M step: generate")
+    s = synth.dn_strings(n, length, ratio, seed=0, device=DEV)
+    pipe = bench.Pipeline(s.bytes, s.offsets, pes, v, ss, torch, overlap=True)
+    assert pipe.seeded and pipe.overlap
+    marks = bench.Marks(torch, False)
+    outs = []
+    for rep in range(2):
+        _log(f"[full] D/N 16M step: run {rep}")
+        order, mlcp, dist, dpx, rounds = pipe.step(marks)
+        torch.cuda.synchronize()
+        outs.append([u32(t).copy() for t in (order, mlcp, dist, dpx)] + [rounds])
+    _log("[full] D/N 16M step: check")
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
+    order, mlcp, dist, dpx, rounds = outs[0]
+    k, F, pi = s.meta["k"], s.meta["filler"], s.meta["pi"].numpy()
+    b = s.bytes.cpu().numpy()
+    o = s.offsets.cpu().numpy().view(np.uint64)
+    del pipe, s
+    assert oracle.check_sorted(b, o, order, mlcp) == -1
+    del b
+    d_in = oracle.dist_exact(o, order, mlcp)  # by string, from the checked order and LCPs
+    np.testing.assert_array_equal(dist, d_in[order])  # the step's dist is by merged position
+    np.testing.assert_array_equal(dpx, cf.doubling_closed_form(d_in, np.full(n, length), 8))
+    np.testing.assert_array_equal(order, cf.dn_perm(pi))
+    np.testing.assert_array_equal(mlcp, cf.dn_lcp(n, k, F))
+    np.testing.assert_array_equal(dist, cf.dn_dist_sorted(n, k, F, length))
