@@ -1358,32 +1358,6 @@ static unsigned grid_of(u64 items, u64 per, u64 cap)
     return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
-// Workgroups of `kernel` (nt threads) that the current device holds at once.
-// A grid-stride launch of at most this many runs as one wave of workgroups:
-// with more, the last workgroups -- each owning many tiles -- run while most
-// of the device waits for them.
-template <class K>
-static unsigned resident(K kernel, int nt)
-{
-    static std::mutex mu;
-    static std::map<std::pair<int, const void *>, unsigned> cache;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-    std::lock_guard<std::mutex> lk(mu);
-    const auto key = std::make_pair(dev, (const void *)kernel);
-    const auto it = cache.find(key);
-    if (it != cache.end()) return it->second;
-    int per = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, nt, 0) != hipSuccess || per < 1 ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
-        (void)hipGetLastError();
-        return 2048;  // (not cached: asked again next time)
-    }
-    const unsigned g = (unsigned)per * (unsigned)cus;
-    cache[key] = g;
-    return g;
-}
-
 // One round or level's lengths: known to the host (read back) or not.
 struct Known {
     bool yes;
