@@ -1726,10 +1726,10 @@ static int first_pass(const uint8_t *bytes, uint64_t N, const uint64_t *offsets,
         k_hash_weights<<<(WT_ROUND + WT_FIRST + 255) / 256, 256, 0, st>>>(rwd, Fa, w.wt);
         SS_CHECK_LAUNCH();
         A.wt = w.wt;
-        // The lazy form runs alone (the sort starts from its seed): one wave
-        // of resident workgroups, each striding over many tiles, leaves no
-        // tail of late workgroups (1.55 -> 1.45 ms at 16M strings against
-        // 8192).  The deep form keeps more, shorter workgroups than the plain
+        // The lazy form usually runs alone (a seeded sort waits for its
+        // seed): one wave of resident workgroups, each striding over many
+        // tiles, leaves no tail of late workgroups (1.55 -> 1.45 ms at 16M
+        // strings against 8192).  The deep form keeps more, shorter workgroups than the plain
         // pass: beside the other stream's kernels they give compute units
         // back sooner.
         const u64 wg4 = ceil_div(tiles, 4);
